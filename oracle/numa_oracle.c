@@ -1,0 +1,624 @@
+/*
+ * numa_oracle.c -- plain FP64 CPU oracle of the HEVI (1D-IMEX) ARK2 step.
+ *
+ * TEST INFRASTRUCTURE ONLY (see numa_oracle.h).  Written for reading, not for
+ * speed: element-local loops, explicit gather/scatter direct stiffness
+ * summation, dense column matrices built by probing and solved with partial
+ * pivoting, and the ARK2 stages in their direct form.
+ *
+ * Readings of the paper that this file adopts (the paper is silent or garbled
+ * on them; each is listed with its reason in the design notes):
+ *  - continuity in divergence form, d rho'/dt = -div((rho0 + rho') u);
+ *  - DSS = mass-weighted average of element-local strong-form values;
+ *  - x, y periodic; w = 0 imposed strongly at the bottom and top nodes;
+ *  - isentropic background: theta0 constant, pi0 = 1 - g z/(cp theta0),
+ *    rho0 = p00 pi0^(cv/R)/(R theta0), P0 = EOS(rho0, theta0);
+ *  - ARK2 tableau with the signs restored by the order conditions.
+ */
+#include "numa_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+struct orc_ctx {
+    int N, nq, nex, ney, nez;
+    int nx, ny, nz;
+    long nelem, nq3, np;
+    double lx, ly, lz, hx, hy;
+    double *zf; /* nez+1 element faces */
+    double *hz; /* nez element heights */
+    double *xi, *wq, *D;
+    long *gmap;    /* element-local node -> unique node */
+    double *mloc;  /* element-local mass weight m_e */
+    double *mass;  /* assembled mass M_I */
+    double theta0, p00, cp, R, cv, gamma, g;
+    double *zk, *rho0, *P0, *G0, *H0; /* per level */
+    /* column factors of I - lambda L_V */
+    int factored;
+    double lambda;
+    double *A; /* per column (2M)^2, LU in place */
+    int *piv;  /* per column 2M */
+};
+
+/* ------------------------------------------------------------------------ */
+/* LGL basis (the sD operator of Alg. 1-2).                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Legendre P_N(x) and P_N'(x) by the three-term recurrence. */
+static void legendre(int N, double x, double *P, double *dP)
+{
+    double p0 = 1.0, p1 = x, d0 = 0.0, d1 = 1.0;
+    if (N == 0) { *P = 1.0; *dP = 0.0; return; }
+    for (int k = 1; k < N; ++k) {
+        double p2 = ((2.0 * k + 1.0) * x * p1 - k * p0) / (k + 1.0);
+        double d2 = d0 + (2.0 * k + 1.0) * p1; /* P'_{k+1} = P'_{k-1} + (2k+1) P_k */
+        p0 = p1; p1 = p2; d0 = d1; d1 = d2;
+    }
+    *P = p1; *dP = d1;
+}
+
+void orc_lgl(int N, double *xi, double *w)
+{
+    /* Interior nodes are the roots of P_N'; Newton from Chebyshev-Lobatto
+     * guesses, with P_N'' from Legendre's equation. */
+    xi[0] = -1.0; xi[N] = 1.0;
+    for (int i = 1; i < N; ++i) {
+        double x = -cos(3.14159265358979323846 * i / N);
+        for (int it = 0; it < 100; ++it) {
+            double P, dP;
+            legendre(N, x, &P, &dP);
+            double d2P = (2.0 * x * dP - N * (N + 1.0) * P) / (1.0 - x * x);
+            double dx = dP / d2P;
+            x -= dx;
+            if (fabs(dx) < 1e-16) break;
+        }
+        xi[i] = x;
+    }
+    for (int i = 0; i <= N; ++i) {
+        double P, dP;
+        legendre(N, xi[i], &P, &dP);
+        w[i] = 2.0 / (N * (N + 1.0) * P * P);
+    }
+}
+
+void orc_dmat(int N, const double *xi, double *D)
+{
+    int nq = N + 1;
+    for (int i = 0; i < nq; ++i) {
+        double Pi, dPi;
+        legendre(N, xi[i], &Pi, &dPi);
+        for (int j = 0; j < nq; ++j) {
+            if (i == j) {
+                double v = 0.0;
+                if (i == 0) v = -N * (N + 1.0) / 4.0;
+                if (i == N) v = N * (N + 1.0) / 4.0;
+                D[i * nq + j] = v;
+            } else {
+                double Pj, dPj;
+                legendre(N, xi[j], &Pj, &dPj);
+                D[i * nq + j] = Pi / (Pj * (xi[i] - xi[j]));
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Set-up: grid, mass, background (Sec. 3.1 background split).              */
+/* ------------------------------------------------------------------------ */
+
+static long lidx(const orc_ctx *c, int a, int b, int cc) { return a + c->nq * (b + (long)c->nq * cc); }
+
+orc_ctx *orc_setup(double lx, double ly, double lz, int nex, int ney, int nez,
+                   const double *zface, int N, double theta0, double p00,
+                   double cp, double rgas, double grav)
+{
+    if (N < 1 || N > 15 || nex < 1 || ney < 1 || nez < 1) return NULL;
+    if (!(lx > 0) || !(ly > 0) || !(lz > 0)) return NULL;
+    if (zface) {
+        if (zface[0] != 0.0 || zface[nez] != lz) return NULL;
+        for (int e = 0; e < nez; ++e) if (!(zface[e + 1] > zface[e])) return NULL;
+    }
+    orc_ctx *c = (orc_ctx *)calloc(1, sizeof(orc_ctx));
+    if (!c) return NULL;
+    c->N = N; c->nq = N + 1; c->nex = nex; c->ney = ney; c->nez = nez;
+    c->nx = nex * N; c->ny = ney * N; c->nz = nez * N + 1;
+    c->nelem = (long)nex * ney * nez;
+    c->nq3 = (long)c->nq * c->nq * c->nq;
+    c->np = (long)c->nx * c->ny * c->nz;
+    c->lx = lx; c->ly = ly; c->lz = lz;
+    c->hx = lx / nex; c->hy = ly / ney;
+    c->theta0 = theta0; c->p00 = p00; c->cp = cp; c->R = rgas;
+    c->cv = cp - rgas; c->gamma = cp / c->cv; c->g = grav;
+
+    c->zf = (double *)malloc(sizeof(double) * (nez + 1));
+    c->hz = (double *)malloc(sizeof(double) * nez);
+    for (int e = 0; e <= nez; ++e) c->zf[e] = zface ? zface[e] : lz * e / nez;
+    c->zf[nez] = lz;
+    for (int e = 0; e < nez; ++e) c->hz[e] = c->zf[e + 1] - c->zf[e];
+
+    c->xi = (double *)malloc(sizeof(double) * c->nq);
+    c->wq = (double *)malloc(sizeof(double) * c->nq);
+    c->D = (double *)malloc(sizeof(double) * c->nq * c->nq);
+    orc_lgl(N, c->xi, c->wq);
+    orc_dmat(N, c->xi, c->D);
+
+    long nl = c->nelem * c->nq3;
+    c->gmap = (long *)malloc(sizeof(long) * nl);
+    c->mloc = (double *)malloc(sizeof(double) * nl);
+    c->mass = (double *)calloc(c->np, sizeof(double));
+    if (!c->gmap || !c->mloc || !c->mass) { orc_free(c); return NULL; }
+    for (int ez = 0; ez < nez; ++ez)
+        for (int ey = 0; ey < ney; ++ey)
+            for (int ex = 0; ex < nex; ++ex) {
+                long e = ex + (long)nex * (ey + (long)ney * ez);
+                for (int cc = 0; cc <= N; ++cc)
+                    for (int b = 0; b <= N; ++b)
+                        for (int a = 0; a <= N; ++a) {
+                            long l = e * c->nq3 + lidx(c, a, b, cc);
+                            long i = (ex * N + a) % c->nx;
+                            long j = (ey * N + b) % c->ny;
+                            long k = ez * N + cc;
+                            c->gmap[l] = i + c->nx * (j + (long)c->ny * k);
+                            c->mloc[l] = c->wq[a] * c->wq[b] * c->wq[cc] * c->hx * c->hy * c->hz[ez] / 8.0;
+                        }
+            }
+    for (long l = 0; l < nl; ++l) c->mass[c->gmap[l]] += c->mloc[l];
+
+    c->zk = (double *)malloc(sizeof(double) * c->nz);
+    c->rho0 = (double *)malloc(sizeof(double) * c->nz);
+    c->P0 = (double *)malloc(sizeof(double) * c->nz);
+    c->G0 = (double *)malloc(sizeof(double) * c->nz);
+    c->H0 = (double *)malloc(sizeof(double) * c->nz);
+    for (int ez = 0; ez < nez; ++ez)
+        for (int cc = 0; cc <= N; ++cc)
+            c->zk[ez * N + cc] = c->zf[ez] + (c->xi[cc] + 1.0) * c->hz[ez] / 2.0;
+    for (int k = 0; k < c->nz; ++k) {
+        /* hydrostatic, neutral background with constant theta0 */
+        double pi0 = 1.0 - grav * c->zk[k] / (cp * theta0);
+        double rho0 = p00 * pow(pi0, c->cv / rgas) / (rgas * theta0);
+        double P0 = p00 * pow(rho0 * rgas * theta0 / p00, c->gamma); /* EOS, Eq. (10) */
+        c->rho0[k] = rho0;
+        c->P0[k] = P0;
+        c->G0[k] = c->gamma * P0 / rho0;   /* Eq. (13) */
+        c->H0[k] = c->gamma * P0 / theta0;
+    }
+    return c;
+}
+
+void orc_free(orc_ctx *c)
+{
+    if (!c) return;
+    free(c->zf); free(c->hz); free(c->xi); free(c->wq); free(c->D);
+    free(c->gmap); free(c->mloc); free(c->mass);
+    free(c->zk); free(c->rho0); free(c->P0); free(c->G0); free(c->H0);
+    free(c->A); free(c->piv);
+    free(c);
+}
+
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int orc_get_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_sizes(const orc_ctx *c, long *out)
+{
+    out[0] = c->nx; out[1] = c->ny; out[2] = c->nz; out[3] = c->nelem;
+}
+
+void orc_coords(const orc_ctx *c, double *x, double *y, double *z)
+{
+    for (int ex = 0; ex < c->nex; ++ex)
+        for (int a = 0; a < c->N; ++a) x[ex * c->N + a] = ex * c->hx + (c->xi[a] + 1.0) * c->hx / 2.0;
+    for (int ey = 0; ey < c->ney; ++ey)
+        for (int b = 0; b < c->N; ++b) y[ey * c->N + b] = ey * c->hy + (c->xi[b] + 1.0) * c->hy / 2.0;
+    for (int k = 0; k < c->nz; ++k) z[k] = c->zk[k];
+}
+
+void orc_mass(const orc_ctx *c, double *M) { memcpy(M, c->mass, sizeof(double) * c->np); }
+
+void orc_background(const orc_ctx *c, double *rho0, double *P0, double *G0, double *H0)
+{
+    for (int k = 0; k < c->nz; ++k) {
+        if (rho0) rho0[k] = c->rho0[k];
+        if (P0) P0[k] = c->P0[k];
+        if (G0) G0[k] = c->G0[k];
+        if (H0) H0[k] = c->H0[k];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Element-local derivative (Alg. 2 with the box metric 2/h).               */
+/* ------------------------------------------------------------------------ */
+
+/* d/dxi along direction dir (0: a, 1: b, 2: c) of an element-local field g at
+ * local node (a, b, cc), before the metric factor. */
+static double dref(const orc_ctx *c, const double *g, int a, int b, int cc, int dir)
+{
+    int nq = c->nq;
+    double s = 0.0;
+    for (int n = 0; n < nq; ++n) {
+        if (dir == 0) s += c->D[a * nq + n] * g[lidx(c, n, b, cc)];
+        else if (dir == 1) s += c->D[b * nq + n] * g[lidx(c, a, n, cc)];
+        else s += c->D[cc * nq + n] * g[lidx(c, a, b, n)];
+    }
+    return s;
+}
+
+/* DSS (Sec. 5.3): R_I = sum_e m_e r_e(I) / M_I over the elements containing I,
+ * then w = 0 on the bottom and top levels.  r is element-local [5][nelem*nq3]. */
+static void dss(const orc_ctx *c, const double *r, double *R)
+{
+    long nl = c->nelem * c->nq3;
+    memset(R, 0, sizeof(double) * 5 * c->np);
+    for (int f = 0; f < 5; ++f)
+        for (long l = 0; l < nl; ++l) R[f * c->np + c->gmap[l]] += c->mloc[l] * r[f * nl + l];
+    for (int f = 0; f < 5; ++f)
+        for (long I = 0; I < c->np; ++I) R[f * c->np + I] /= c->mass[I];
+    long plane = (long)c->nx * c->ny;
+    for (long I = 0; I < plane; ++I) {
+        R[3 * c->np + I] = 0.0;
+        R[3 * c->np + (long)(c->nz - 1) * plane + I] = 0.0;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Explicit RHS of Set2NC in perturbation form (Sec. 3.1), continuity in    */
+/* divergence form.                                                         */
+/* ------------------------------------------------------------------------ */
+
+int orc_rhs(orc_ctx *c, const double *q, double *R)
+{
+    if (!c || !q || !R) return -1;
+    long nl = c->nelem * c->nq3, nq3 = c->nq3, np = c->np;
+    double *r = (double *)malloc(sizeof(double) * 5 * nl);
+    if (!r) return -5;
+    int ok = 1;
+#pragma omp parallel
+    {
+        double *buf = (double *)malloc(sizeof(double) * 11 * nq3);
+        if (!buf) ok = 0;
+        if (buf) {
+            double *rp = buf, *u = buf + nq3, *v = buf + 2 * nq3, *w = buf + 3 * nq3;
+            double *th = buf + 4 * nq3, *rho = buf + 5 * nq3, *Pp = buf + 6 * nq3;
+            double *Fx = buf + 7 * nq3, *Fy = buf + 8 * nq3, *Fz = buf + 9 * nq3;
+#pragma omp for schedule(static)
+            for (long e = 0; e < c->nelem; ++e) {
+                int ez = (int)(e / ((long)c->nex * c->ney));
+                double sx = 2.0 / c->hx, sy = 2.0 / c->hy, sz = 2.0 / c->hz[ez];
+                for (long l = 0; l < nq3; ++l) {
+                    long I = c->gmap[e * nq3 + l];
+                    int k = (int)(I / ((long)c->nx * c->ny));
+                    rp[l] = q[0 * np + I]; u[l] = q[1 * np + I]; v[l] = q[2 * np + I];
+                    w[l] = q[3 * np + I]; th[l] = q[4 * np + I];
+                    rho[l] = c->rho0[k] + rp[l];
+                    double theta = c->theta0 + th[l];
+                    /* P' = EOS(rho, theta) - P0 (Eq. (10) and the background split) */
+                    Pp[l] = c->p00 * pow(rho[l] * c->R * theta / c->p00, c->gamma) - c->P0[k];
+                    Fx[l] = rho[l] * u[l]; Fy[l] = rho[l] * v[l]; Fz[l] = rho[l] * w[l];
+                }
+                for (int cc = 0; cc < c->nq; ++cc)
+                    for (int b = 0; b < c->nq; ++b)
+                        for (int a = 0; a < c->nq; ++a) {
+                            long l = lidx(c, a, b, cc);
+                            double dFx = sx * dref(c, Fx, a, b, cc, 0);
+                            double dFy = sy * dref(c, Fy, a, b, cc, 1);
+                            double dFz = sz * dref(c, Fz, a, b, cc, 2);
+                            double ux = sx * dref(c, u, a, b, cc, 0), uy = sy * dref(c, u, a, b, cc, 1), uz = sz * dref(c, u, a, b, cc, 2);
+                            double vx = sx * dref(c, v, a, b, cc, 0), vy = sy * dref(c, v, a, b, cc, 1), vz = sz * dref(c, v, a, b, cc, 2);
+                            double wx = sx * dref(c, w, a, b, cc, 0), wy = sy * dref(c, w, a, b, cc, 1), wz = sz * dref(c, w, a, b, cc, 2);
+                            double tx = sx * dref(c, th, a, b, cc, 0), ty = sy * dref(c, th, a, b, cc, 1), tz = sz * dref(c, th, a, b, cc, 2);
+                            double px = sx * dref(c, Pp, a, b, cc, 0), py = sy * dref(c, Pp, a, b, cc, 1), pz = sz * dref(c, Pp, a, b, cc, 2);
+                            double U = u[l], V = v[l], W = w[l], rh = rho[l];
+                            long o = e * nq3 + l;
+                            r[0 * nl + o] = -(dFx + dFy + dFz);
+                            r[1 * nl + o] = -(U * ux + V * uy + W * uz + px / rh);
+                            r[2 * nl + o] = -(U * vx + V * vy + W * vz + py / rh);
+                            r[3 * nl + o] = -(U * wx + V * wy + W * wz + pz / rh + c->g * rp[l] / rh);
+                            r[4 * nl + o] = -(U * tx + V * ty + W * tz); /* u . grad theta0 = 0 */
+                        }
+            }
+            free(buf);
+        }
+    }
+    if (!ok) { free(r); return -5; }
+    dss(c, r, R);
+    free(r);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Linear operators (Sec. 3.1): P'_lin = G0 rho' + H0 theta' (Eq. (13)).     */
+/* full = 0: vertical part L_V only (Eq. (4)); full = 1: the whole L.        */
+/* ------------------------------------------------------------------------ */
+
+static int linop(orc_ctx *c, const double *q, double *L, int full)
+{
+    if (!c || !q || !L) return -1;
+    long nl = c->nelem * c->nq3, nq3 = c->nq3, np = c->np;
+    double *r = (double *)malloc(sizeof(double) * 5 * nl);
+    if (!r) return -5;
+    int ok = 1;
+#pragma omp parallel
+    {
+        double *buf = (double *)malloc(sizeof(double) * 6 * nq3);
+        if (!buf) ok = 0;
+        if (buf) {
+            double *rp = buf, *mu = buf + nq3, *mv = buf + 2 * nq3, *mw = buf + 3 * nq3;
+            double *pl = buf + 4 * nq3, *r0 = buf + 5 * nq3;
+#pragma omp for schedule(static)
+            for (long e = 0; e < c->nelem; ++e) {
+                int ez = (int)(e / ((long)c->nex * c->ney));
+                double sx = 2.0 / c->hx, sy = 2.0 / c->hy, sz = 2.0 / c->hz[ez];
+                for (long l = 0; l < nq3; ++l) {
+                    long I = c->gmap[e * nq3 + l];
+                    int k = (int)(I / ((long)c->nx * c->ny));
+                    r0[l] = c->rho0[k];
+                    rp[l] = q[0 * np + I];
+                    mu[l] = c->rho0[k] * q[1 * np + I];
+                    mv[l] = c->rho0[k] * q[2 * np + I];
+                    mw[l] = c->rho0[k] * q[3 * np + I];
+                    pl[l] = c->G0[k] * q[0 * np + I] + c->H0[k] * q[4 * np + I];
+                }
+                for (int cc = 0; cc < c->nq; ++cc)
+                    for (int b = 0; b < c->nq; ++b)
+                        for (int a = 0; a < c->nq; ++a) {
+                            long l = lidx(c, a, b, cc), o = e * nq3 + l;
+                            double div = sz * dref(c, mw, a, b, cc, 2);
+                            if (full) div += sx * dref(c, mu, a, b, cc, 0) + sy * dref(c, mv, a, b, cc, 1);
+                            r[0 * nl + o] = -div;
+                            r[1 * nl + o] = full ? -(sx * dref(c, pl, a, b, cc, 0) / r0[l]) : 0.0;
+                            r[2 * nl + o] = full ? -(sy * dref(c, pl, a, b, cc, 1) / r0[l]) : 0.0;
+                            r[3 * nl + o] = -(sz * dref(c, pl, a, b, cc, 2) / r0[l] + c->g * rp[l] / r0[l]);
+                            r[4 * nl + o] = 0.0; /* -u . grad theta0 = 0 for constant theta0 */
+                        }
+            }
+            free(buf);
+        }
+    }
+    if (!ok) { free(r); return -5; }
+    dss(c, r, L);
+    free(r);
+    return 0;
+}
+
+int orc_lv(orc_ctx *c, const double *q, double *L) { return linop(c, q, L, 0); }
+int orc_lfull(orc_ctx *c, const double *q, double *L) { return linop(c, q, L, 1); }
+
+/* ------------------------------------------------------------------------ */
+/* Column matrices of I - lambda L_V (Sec. 5.4): built by probing (Alg. 7),  */
+/* unknowns (rho'_k, w_k) per column, solved by Gaussian elimination with    */
+/* partial pivoting.  u, v, theta' pass through unchanged because L_V has no */
+/* rows for them.                                                           */
+/* ------------------------------------------------------------------------ */
+
+static int build_columns(orc_ctx *c, double lambda, double *A)
+{
+    int M = c->nz, n2 = 2 * M;
+    long plane = (long)c->nx * c->ny, np = c->np;
+    double *P = (double *)calloc(5 * np, sizeof(double));
+    double *L = (double *)malloc(sizeof(double) * 5 * np);
+    if (!P || !L) { free(P); free(L); return -5; }
+    for (int gvar = 0; gvar < 2; ++gvar) {
+        int f = gvar == 0 ? 0 : 3; /* rho' or w */
+        for (int m = 0; m < M; ++m) {
+            /* unit value of dof (gvar, m) in every column at once */
+            for (long I = 0; I < plane; ++I) P[f * np + (long)m * plane + I] = 1.0;
+            int rc = orc_lv(c, P, L);
+            for (long I = 0; I < plane; ++I) P[f * np + (long)m * plane + I] = 0.0;
+            if (rc) { free(P); free(L); return rc; }
+            int col = gvar * M + m;
+            for (long I = 0; I < plane; ++I) {
+                double *Ac = A + I * (long)n2 * n2;
+                for (int k = 0; k < M; ++k) {
+                    Ac[(0 * M + k) * n2 + col] = (col == 0 * M + k ? 1.0 : 0.0) - lambda * L[0 * np + (long)k * plane + I];
+                    Ac[(1 * M + k) * n2 + col] = (col == 1 * M + k ? 1.0 : 0.0) - lambda * L[3 * np + (long)k * plane + I];
+                }
+            }
+        }
+    }
+    free(P); free(L);
+    /* w = 0 is imposed strongly on the bottom and top nodes: those two w
+     * values are not unknowns.  Their rows are already identity rows (L_V has
+     * no w tendency there); clearing their columns as well decouples them, so
+     * the solve returns them as exactly y_w = 0. */
+    for (long I = 0; I < plane; ++I) {
+        double *Ac = A + I * (long)n2 * n2;
+        int wall[2] = {M, 2 * M - 1};
+        for (int t = 0; t < 2; ++t)
+            for (int r = 0; r < n2; ++r)
+                if (r != wall[t]) Ac[(long)r * n2 + wall[t]] = 0.0;
+    }
+    return 0;
+}
+
+int orc_column_matrix(orc_ctx *c, double lambda, int i, int j, double *Aout)
+{
+    if (!c || !Aout || i < 0 || j < 0 || i >= c->nx || j >= c->ny) return -1;
+    int n2 = 2 * c->nz;
+    long plane = (long)c->nx * c->ny;
+    double *A = (double *)malloc(sizeof(double) * plane * n2 * n2);
+    if (!A) return -5;
+    int rc = build_columns(c, lambda, A);
+    if (!rc) memcpy(Aout, A + ((long)i + (long)c->nx * j) * n2 * n2, sizeof(double) * n2 * n2);
+    free(A);
+    return rc;
+}
+
+/* In-place LU with partial pivoting of an n x n row-major matrix. */
+static int lu_pp(double *A, int *piv, int n)
+{
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        double best = fabs(A[k * n + k]);
+        for (int i = k + 1; i < n; ++i)
+            if (fabs(A[i * n + k]) > best) { best = fabs(A[i * n + k]); p = i; }
+        piv[k] = p;
+        if (best == 0.0) return -4;
+        if (p != k)
+            for (int j = 0; j < n; ++j) { double t = A[k * n + j]; A[k * n + j] = A[p * n + j]; A[p * n + j] = t; }
+        for (int i = k + 1; i < n; ++i) {
+            A[i * n + k] /= A[k * n + k];
+            double m = A[i * n + k];
+            for (int j = k + 1; j < n; ++j) A[i * n + j] -= m * A[k * n + j];
+        }
+    }
+    return 0;
+}
+
+static void lu_solve(const double *A, const int *piv, int n, double *x)
+{
+    for (int k = 0; k < n; ++k)
+        if (piv[k] != k) { double t = x[k]; x[k] = x[piv[k]]; x[piv[k]] = t; }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < i; ++j) x[i] -= A[i * n + j] * x[j];
+    for (int i = n - 1; i >= 0; --i) {
+        for (int j = i + 1; j < n; ++j) x[i] -= A[i * n + j] * x[j];
+        x[i] /= A[i * n + i];
+    }
+}
+
+int orc_factor(orc_ctx *c, double lambda)
+{
+    if (!c) return -1;
+    int n2 = 2 * c->nz;
+    long plane = (long)c->nx * c->ny;
+    free(c->A); free(c->piv);
+    c->factored = 0;
+    c->A = (double *)malloc(sizeof(double) * plane * n2 * n2);
+    c->piv = (int *)malloc(sizeof(int) * plane * n2);
+    if (!c->A || !c->piv) return -5;
+    int rc = build_columns(c, lambda, c->A);
+    if (rc) return rc;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (long I = 0; I < plane; ++I)
+        if (lu_pp(c->A + I * (long)n2 * n2, c->piv + I * n2, n2)) bad = 1;
+    if (bad) return -4;
+    c->factored = 1;
+    c->lambda = lambda;
+    return 0;
+}
+
+int orc_solve(orc_ctx *c, const double *y, double *x)
+{
+    if (!c || !y || !x) return -1;
+    if (!c->factored) return -2;
+    int M = c->nz, n2 = 2 * M;
+    long plane = (long)c->nx * c->ny, np = c->np;
+    for (long I = 0; I < plane; ++I)
+        if (y[3 * np + I] != 0.0 || y[3 * np + (long)(M - 1) * plane + I] != 0.0) return -3;
+    /* theta' is known (x_theta = y_theta): move its L_V contribution to the
+     * right-hand side, then solve the (rho', w) system column by column. */
+    double *t = (double *)calloc(5 * np, sizeof(double));
+    double *Lt = (double *)malloc(sizeof(double) * 5 * np);
+    if (!t || !Lt) { free(t); free(Lt); return -5; }
+    memcpy(t + 4 * np, y + 4 * np, sizeof(double) * np);
+    int rc = orc_lv(c, t, Lt);
+    if (rc) { free(t); free(Lt); return rc; }
+    double lam = c->lambda;
+#pragma omp parallel
+    {
+        double *b = (double *)malloc(sizeof(double) * n2);
+#pragma omp for schedule(static)
+        for (long I = 0; I < plane; ++I) {
+            for (int k = 0; k < M; ++k) {
+                long o = (long)k * plane + I;
+                b[k] = y[0 * np + o] + lam * Lt[0 * np + o];
+                b[M + k] = y[3 * np + o] + lam * Lt[3 * np + o];
+            }
+            lu_solve(c->A + I * (long)n2 * n2, c->piv + I * n2, n2, b);
+            for (int k = 0; k < M; ++k) {
+                long o = (long)k * plane + I;
+                t[0 * np + o] = b[k];
+                t[3 * np + o] = b[M + k];
+            }
+        }
+        free(b);
+    }
+    for (long I = 0; I < np; ++I) {
+        x[0 * np + I] = t[0 * np + I];
+        x[1 * np + I] = y[1 * np + I];
+        x[2 * np + I] = y[2 * np + I];
+        x[3 * np + I] = t[3 * np + I];
+        x[4 * np + I] = y[4 * np + I];
+    }
+    free(t); free(Lt);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* ARK2 (Sec. 2.2, Table 1), direct stage form:                             */
+/*   Q_i = q^n + dt sum_{j<i} [a_ij R_j + (at_ij - a_ij) L_j] + at_ii dt L(Q_i) */
+/*   q^{n+1} = q^n + dt sum_i b_i R_i          (b = bt)                     */
+/* ------------------------------------------------------------------------ */
+
+void orc_ark2_tableau(double *a, double *at, double *b)
+{
+    double s2 = sqrt(2.0);
+    double alpha = (3.0 + 2.0 * s2) / 6.0;
+    double d = 1.0 - 1.0 / s2;
+    memset(a, 0, sizeof(double) * 9);
+    memset(at, 0, sizeof(double) * 9);
+    a[1 * 3 + 0] = 2.0 - s2;
+    a[2 * 3 + 0] = 1.0 - alpha;
+    a[2 * 3 + 1] = alpha;
+    at[1 * 3 + 0] = d; at[1 * 3 + 1] = d;
+    at[2 * 3 + 0] = 1.0 / (2.0 * s2); at[2 * 3 + 1] = 1.0 / (2.0 * s2); at[2 * 3 + 2] = d;
+    b[0] = 1.0 / (2.0 * s2); b[1] = 1.0 / (2.0 * s2); b[2] = d;
+}
+
+int orc_step(orc_ctx *c, double *q, double dt, int nsteps, int linear)
+{
+    if (!c || !q || nsteps < 0) return -1;
+    double a[9], at[9], b[3];
+    orc_ark2_tableau(a, at, b);
+    double lam = at[1 * 3 + 1] * dt;
+    if (!c->factored || c->lambda != lam) return -2;
+    long n5 = 5 * c->np;
+    double *Rs[3], *Ls[2], *Y = (double *)malloc(sizeof(double) * n5);
+    double *Q = (double *)malloc(sizeof(double) * n5);
+    for (int s = 0; s < 3; ++s) Rs[s] = (double *)malloc(sizeof(double) * n5);
+    for (int s = 0; s < 2; ++s) Ls[s] = (double *)malloc(sizeof(double) * n5);
+    int rc = (Y && Q && Rs[0] && Rs[1] && Rs[2] && Ls[0] && Ls[1]) ? 0 : -5;
+    for (int n = 0; n < nsteps && !rc; ++n) {
+        for (int i = 0; i < 3 && !rc; ++i) {
+            if (i == 0) {
+                memcpy(Q, q, sizeof(double) * n5);
+            } else {
+                for (long I = 0; I < n5; ++I) {
+                    double y = q[I];
+                    for (int j = 0; j < i; ++j)
+                        y += dt * (a[i * 3 + j] * Rs[j][I] + (at[i * 3 + j] - a[i * 3 + j]) * Ls[j][I]);
+                    Y[I] = y;
+                }
+                rc = orc_solve(c, Y, Q);
+                if (rc) break;
+            }
+            rc = linear ? orc_lfull(c, Q, Rs[i]) : orc_rhs(c, Q, Rs[i]);
+            if (!rc && i < 2) rc = orc_lv(c, Q, Ls[i]);
+        }
+        if (rc) break;
+        for (long I = 0; I < n5; ++I) q[I] += dt * (b[0] * Rs[0][I] + b[1] * Rs[1][I] + b[2] * Rs[2][I]);
+    }
+    free(Y); free(Q);
+    for (int s = 0; s < 3; ++s) free(Rs[s]);
+    for (int s = 0; s < 2; ++s) free(Ls[s]);
+    return rc;
+}

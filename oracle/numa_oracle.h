@@ -1,0 +1,81 @@
+/*
+ * numa_oracle.h -- plain FP64 CPU oracle for the 1D-IMEX (HEVI) ARK2 step of
+ * NUMA (Abdi, Giraldo, Constantinescu, Carr, Wilcox, Warburton, "Acceleration
+ * of the IMEX Non-hydrostatic Unified Model of the Atmosphere (NUMA) on
+ * manycore processors").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the GPU library
+ * against the paper.  Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load it; the product path never does.
+ * It shares no code, header, table or helper with the GPU library.
+ *
+ * Everything is FP64.  Loops follow the paper's statement of the method in
+ * its own order and notation: element-local strong-form derivatives on
+ * Legendre-Gauss-Lobatto (LGL) nodes (Sec. 5.1, Alg. 1-2), direct stiffness
+ * summation (Sec. 5.3), column Jacobians built by probing (Sec. 5.4, Alg. 7)
+ * and the ARK2 stages in their direct form (Sec. 2.2, Table 1).
+ *
+ * State layout (same contract as the GPU library, so the two can be compared
+ * element by element): 5 fields (rho', u, v, w, theta'), each a unique-node
+ * array [k][j][i], i fastest; nx = nex*N, ny = ney*N (x and y periodic),
+ * nz = nez*N + 1 (rigid bottom and top).
+ *
+ * Return codes: 0 ok, -1 bad argument, -2 not factored / lambda mismatch,
+ * -3 precondition violated (w != 0 on a wall), -4 singular column matrix,
+ * -5 out of memory.
+ */
+#ifndef NUMA_ORACLE_H
+#define NUMA_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orc_ctx orc_ctx;
+
+/* LGL nodes xi[0..N] (ascending, xi[0] = -1, xi[N] = 1) and weights w[0..N]. */
+void orc_lgl(int N, double *xi, double *w);
+/* LGL differentiation matrix D[i*(N+1)+j] = d l_j / d xi at xi_i. */
+void orc_dmat(int N, const double *xi, double *D);
+
+/* zface: NULL (uniform) or nez+1 increasing heights from 0 to lz. */
+orc_ctx *orc_setup(double lx, double ly, double lz, int nex, int ney, int nez,
+                   const double *zface, int N, double theta0, double p00,
+                   double cp, double rgas, double grav);
+void orc_free(orc_ctx *c);
+void orc_set_threads(int n);
+int orc_get_threads(void);
+
+/* Sizes: out[0..3] = nx, ny, nz, nelem. */
+void orc_sizes(const orc_ctx *c, long *out);
+/* Node coordinates: x[nx], y[ny], z[nz]. */
+void orc_coords(const orc_ctx *c, double *x, double *y, double *z);
+/* Assembled (lumped) mass M_I at every unique node, [k][j][i]. */
+void orc_mass(const orc_ctx *c, double *M);
+/* Background per level k: rho0, P0, G0 = gamma P0/rho0, H0 = gamma P0/theta0. */
+void orc_background(const orc_ctx *c, double *rho0, double *P0, double *G0, double *H0);
+
+/* Explicit right-hand side R(q) of Set2NC (Sec. 3.1) with DSS. */
+int orc_rhs(orc_ctx *c, const double *q, double *R);
+/* Vertical linear operator L_V(q) (Sec. 2, HEVI splitting; Sec. 3.1 operator L). */
+int orc_lv(orc_ctx *c, const double *q, double *L);
+/* Full 3D linear operator L(q) (Sec. 3.1). */
+int orc_lfull(orc_ctx *c, const double *q, double *L);
+/* Build (by probing, Alg. 7) and LU-factor the column matrices of I - lambda*L_V. */
+int orc_factor(orc_ctx *c, double lambda);
+/* x = (I - lambda L_V)^{-1} y using the stored factors.  y and x may alias. */
+int orc_solve(orc_ctx *c, const double *y, double *x);
+/* The dense column matrix (2M x 2M, row-major, unknowns (rho'_0..M-1, w_0..M-1))
+ * of I - lambda L_V for column (i, j), before factorisation. */
+int orc_column_matrix(orc_ctx *c, double lambda, int i, int j, double *A);
+/* nsteps ARK2 steps of size dt, in place.  linear != 0 replaces R by the full
+ * linear operator L (used by the time-order test).  The factors must have been
+ * built with lambda = (1 - 1/sqrt 2) dt. */
+int orc_step(orc_ctx *c, double *q, double dt, int nsteps, int linear);
+/* ARK2 tableau as used by orc_step: a[3][3], at[3][3], b[3] (Table 1). */
+void orc_ark2_tableau(double *a, double *at, double *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,177 @@
+"""ctypes binding of the plain FP64 CPU oracle (test infrastructure only).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark use
+this module.  It loads ``oracle/libnuma_oracle.so`` (built by
+``oracle/build.py``) and shares nothing with the GPU library.
+
+Arrays are numpy float64, C-contiguous.  The state is (5, nz, ny, nx) with
+fields (rho', u, v, w, theta').
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "libnuma_oracle.so")
+_lib = None
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        from . import build as _b
+        _b.build()
+    lib = C.CDLL(_LIB)
+    lib.orc_lgl.argtypes = [C.c_int, _dp, _dp]
+    lib.orc_dmat.argtypes = [C.c_int, _dp, _dp]
+    lib.orc_setup.restype = C.c_void_p
+    lib.orc_setup.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
+                              C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_double,
+                              C.c_double, C.c_double]
+    lib.orc_free.argtypes = [C.c_void_p]
+    lib.orc_set_threads.argtypes = [C.c_int]
+    lib.orc_get_threads.restype = C.c_int
+    lib.orc_sizes.argtypes = [C.c_void_p, np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")]
+    lib.orc_coords.argtypes = [C.c_void_p, _dp, _dp, _dp]
+    lib.orc_mass.argtypes = [C.c_void_p, _dp]
+    lib.orc_background.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
+    for name in ("orc_rhs", "orc_lv", "orc_lfull", "orc_solve"):
+        f = getattr(lib, name)
+        f.argtypes = [C.c_void_p, _dp, _dp]
+        f.restype = C.c_int
+    lib.orc_factor.argtypes = [C.c_void_p, C.c_double]
+    lib.orc_factor.restype = C.c_int
+    lib.orc_column_matrix.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_int, _dp]
+    lib.orc_column_matrix.restype = C.c_int
+    lib.orc_step.argtypes = [C.c_void_p, _dp, C.c_double, C.c_int, C.c_int]
+    lib.orc_step.restype = C.c_int
+    lib.orc_ark2_tableau.argtypes = [_dp, _dp, _dp]
+    _lib = lib
+    return lib
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise OracleError(f"{what} failed with code {rc}")
+
+
+def lgl(N):
+    lib = _load()
+    xi = np.zeros(N + 1)
+    w = np.zeros(N + 1)
+    lib.orc_lgl(N, xi, w)
+    return xi, w
+
+
+def dmat(N):
+    lib = _load()
+    xi, _ = lgl(N)
+    D = np.zeros((N + 1) * (N + 1))
+    lib.orc_dmat(N, xi, D)
+    return D.reshape(N + 1, N + 1)
+
+
+def ark2_tableau():
+    lib = _load()
+    a = np.zeros(9)
+    at = np.zeros(9)
+    b = np.zeros(3)
+    lib.orc_ark2_tableau(a, at, b)
+    return a.reshape(3, 3), at.reshape(3, 3), b
+
+
+def set_threads(n):
+    _load().orc_set_threads(int(n))
+
+
+def get_threads():
+    return int(_load().orc_get_threads())
+
+
+class Oracle:
+    """One grid + background; mirrors the GPU library's set-up contract."""
+
+    def __init__(self, lx, ly, lz, nex, ney, nez, N, theta0=300.0, p00=1.0e5,
+                 cp=1004.67, rgas=287.17, grav=9.80616, zface=None):
+        lib = _load()
+        self._zf = None if zface is None else np.ascontiguousarray(zface, dtype=np.float64)
+        zp = None if self._zf is None else self._zf.ctypes.data_as(C.c_void_p)
+        self.h = lib.orc_setup(lx, ly, lz, nex, ney, nez, zp, N, theta0, p00, cp, rgas, grav)
+        if not self.h:
+            raise OracleError("orc_setup rejected its arguments")
+        sz = np.zeros(4, dtype=np.int64)
+        lib.orc_sizes(self.h, sz)
+        self.nx, self.ny, self.nz, self.nelem = (int(v) for v in sz)
+        self.N = N
+        self.shape = (5, self.nz, self.ny, self.nx)
+        self.lam = None
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h and _lib is not None:
+            _lib.orc_free(h)
+            self.h = None
+
+    def coords(self):
+        x = np.zeros(self.nx)
+        y = np.zeros(self.ny)
+        z = np.zeros(self.nz)
+        _lib.orc_coords(self.h, x, y, z)
+        return x, y, z
+
+    def mass(self):
+        M = np.zeros(self.shape[1:])
+        _lib.orc_mass(self.h, M.reshape(-1))
+        return M
+
+    def background(self):
+        out = [np.zeros(self.nz) for _ in range(4)]
+        _lib.orc_background(self.h, *out)
+        return dict(zip(("rho0", "P0", "G0", "H0"), out))
+
+    def _op(self, name, q):
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        assert q.shape == self.shape, (q.shape, self.shape)
+        out = np.zeros(self.shape)
+        _check(getattr(_lib, name)(self.h, q.reshape(-1), out.reshape(-1)), name)
+        return out
+
+    def rhs(self, q):
+        return self._op("orc_rhs", q)
+
+    def lv(self, q):
+        return self._op("orc_lv", q)
+
+    def lfull(self, q):
+        return self._op("orc_lfull", q)
+
+    def factor(self, lam):
+        _check(_lib.orc_factor(self.h, float(lam)), "orc_factor")
+        self.lam = float(lam)
+
+    def factor_dt(self, dt):
+        self.factor((1.0 - 1.0 / np.sqrt(2.0)) * dt)
+
+    def solve(self, y):
+        return self._op("orc_solve", y)
+
+    def column_matrix(self, lam, i, j):
+        n2 = 2 * self.nz
+        A = np.zeros(n2 * n2)
+        _check(_lib.orc_column_matrix(self.h, float(lam), i, j, A), "orc_column_matrix")
+        return A.reshape(n2, n2)
+
+    def step(self, q, dt, nsteps=1, linear=False):
+        q = np.array(q, dtype=np.float64, order="C", copy=True)
+        assert q.shape == self.shape
+        _check(_lib.orc_step(self.h, q.reshape(-1), float(dt), int(nsteps), 1 if linear else 0), "orc_step")
+        return q

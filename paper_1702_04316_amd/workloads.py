@@ -1,0 +1,288 @@
+"""Seeded synthetic workloads for the HEVI step.
+
+This module only builds inputs: grids, time-step sizes and initial states.
+It holds none of the step's arithmetic; both the GPU library and the CPU
+oracle receive the same float64 arrays from it.
+
+The paper's own test cases (rising thermal bubbles, the acoustic wave on the
+cubed sphere) are not reproduced; seeded boxes with the same structure stand
+in for them: a hydrostatic, neutral background with theta0 = 300 K, smooth
+potential-temperature bumps in hydrostatic pressure balance, LGL order 4 and
+about ten vertical elements per column.
+
+Two readings of the Courant numbers are provided (the literal boxes make the
+explicit horizontal Courant number 15 or more, which no HEVI scheme can run):
+  R1 (primary): keep the element counts, N, the height and the vertical
+      Courant number; stretch the horizontal extent (and each bump's
+      horizontal radius) by s so that the horizontal Courant number is 0.4.
+  R2 (literal box): keep the box; dt from horizontal Courant number 0.4.
+"""
+from dataclasses import dataclass, field
+from typing import Optional, Tuple
+
+import numpy as np
+from numpy.polynomial import legendre as _leg
+
+# Physical constants of the synthetic atmosphere (passed to both sides).
+CP = 1004.67
+RGAS = 287.17
+P00 = 1.0e5
+GRAV = 9.80616
+THETA0 = 300.0
+
+
+@dataclass
+class Grid:
+    lx: float
+    ly: float
+    lz: float
+    nex: int
+    ney: int
+    nez: int
+    N: int
+    zface: Optional[np.ndarray] = None
+
+    @property
+    def nx(self):
+        return self.nex * self.N
+
+    @property
+    def ny(self):
+        return self.ney * self.N
+
+    @property
+    def nz(self):
+        return self.nez * self.N + 1
+
+    @property
+    def shape(self):
+        return (5, self.nz, self.ny, self.nx)
+
+    @property
+    def n_unique(self):
+        return self.nx * self.ny * self.nz
+
+    @property
+    def n_local(self):
+        return self.nex * self.ney * self.nez * (self.N + 1) ** 3
+
+    def faces(self):
+        if self.zface is not None:
+            return np.asarray(self.zface, dtype=np.float64)
+        return self.lz * np.arange(self.nez + 1) / self.nez
+
+
+@dataclass
+class Background:
+    theta0: float = THETA0
+    p00: float = P00
+    cp: float = CP
+    rgas: float = RGAS
+    grav: float = GRAV
+
+
+@dataclass
+class Workload:
+    name: str
+    grid: Grid
+    dt: float
+    nsteps: int
+    seed: int
+    nbumps: int
+    amp: Tuple[float, float]
+    radius: Tuple[float, float]
+    stretch: float = 1.0
+    background: Background = field(default_factory=Background)
+
+
+def sound_speed(bg=None):
+    bg = bg or Background()
+    gamma = bg.cp / (bg.cp - bg.rgas)
+    return float(np.sqrt(gamma * bg.rgas * bg.theta0))
+
+
+def lgl_nodes(N):
+    """LGL nodes on [-1, 1] from numpy's Legendre routines (input sampling only)."""
+    inner = _leg.Legendre.basis(N).deriv().roots()
+    return np.concatenate(([-1.0], np.sort(inner.real), [1.0]))
+
+
+def node_coords(grid):
+    """Unique-node coordinates x[nx], y[ny], z[nz] (x, y periodic: x = lx is node 0)."""
+    xi = lgl_nodes(grid.N)
+    hx = grid.lx / grid.nex
+    hy = grid.ly / grid.ney
+    x = np.array([ex * hx + (xi[a] + 1.0) * hx / 2.0 for ex in range(grid.nex) for a in range(grid.N)])
+    y = np.array([ey * hy + (xi[b] + 1.0) * hy / 2.0 for ey in range(grid.ney) for b in range(grid.N)])
+    zf = grid.faces()
+    z = np.empty(grid.nz)
+    for ez in range(grid.nez):
+        for c in range(grid.N + 1):
+            z[ez * grid.N + c] = zf[ez] + (xi[c] + 1.0) * (zf[ez + 1] - zf[ez]) / 2.0
+    return x, y, z
+
+
+def min_spacing_factor(N):
+    """Smallest LGL spacing on [-1, 1], as a fraction of the element width."""
+    xi = lgl_nodes(N)
+    return float(np.min(np.diff(xi))) / 2.0
+
+
+def dt_for_courant(grid, courant, axis, bg=None):
+    """dt with C = c0 dt / dx_min (the Courant number of the introduction)."""
+    c0 = sound_speed(bg)
+    f = min_spacing_factor(grid.N)
+    if axis == "z":
+        h = float(np.min(np.diff(grid.faces())))
+    elif axis == "x":
+        h = grid.lx / grid.nex
+    else:
+        h = grid.ly / grid.ney
+    return courant * f * h / c0
+
+
+def _bumps(rng, nb, lx, ly, lz, amp, radius):
+    out = []
+    for _ in range(nb):
+        fx, fy, fz = rng.uniform(0.0, 1.0), rng.uniform(0.0, 1.0), rng.uniform(0.0, 1.0)
+        A = rng.uniform(amp[0], amp[1])
+        r = rng.uniform(radius[0], radius[1])
+        out.append((fx * lx, fy * ly, fz * lz, A, r))
+    return out
+
+
+def _theta_bumps(grid, bumps, stretch):
+    x, y, z = node_coords(grid)
+    th = np.zeros((grid.nz, grid.ny, grid.nx))
+    X = x[None, None, :]
+    Y = y[None, :, None]
+    Z = z[:, None, None]
+    for (xm, ym, zm, A, r) in bumps:
+        rh = stretch * r
+        dz = Z - zm
+        # sum over periodic images so the field is smooth across x = 0 and y = 0
+        gx = sum(np.exp(-((X - xm + m * grid.lx) / rh) ** 2) for m in range(-2, 3))
+        gy = sum(np.exp(-((Y - ym + m * grid.ly) / rh) ** 2) for m in range(-2, 3))
+        th = th + A * gx * gy * np.exp(-dz * dz / (r * r))
+    return th
+
+
+def balanced_density(grid, theta_p, bg=None):
+    """rho' that keeps the hydrostatic pressure unperturbed for a given theta'.
+
+    Initial-condition recipe: with P held at its hydrostatic value, rho theta
+    is unchanged, so rho' = -rho_hyd theta'/(theta0 + theta').
+    """
+    bg = bg or Background()
+    _, _, z = node_coords(grid)
+    cv = bg.cp - bg.rgas
+    pi = 1.0 - bg.grav * z / (bg.cp * bg.theta0)
+    rho_h = bg.p00 * pi ** (cv / bg.rgas) / (bg.rgas * bg.theta0)
+    return -rho_h[:, None, None] * theta_p / (bg.theta0 + theta_p)
+
+
+def make_initial_state(wl: Workload):
+    """Seeded initial state (5, nz, ny, nx): theta' bumps, balanced rho', u = v = w = 0.
+
+    Bump m: A_m exp(-((x-x_m)^2 + (y-y_m)^2)/(s r_m)^2 - (z-z_m)^2/r_m^2), summed
+    over periodic images in x and y; centre drawn uniformly in the box, then
+    A_m and r_m uniformly in their ranges (numpy PCG64, in that order)."""
+    g = wl.grid
+    rng = np.random.default_rng(wl.seed)
+    bumps = _bumps(rng, wl.nbumps, g.lx, g.ly, g.lz, wl.amp, wl.radius)
+    q = np.zeros(g.shape)
+    q[4] = _theta_bumps(g, bumps, wl.stretch)
+    q[0] = balanced_density(g, q[4], wl.background)
+    return q
+
+
+def make_random_state(grid, seed, wind=10.0, theta_amp=1.0, smooth=True):
+    """A generic state for operator parity: theta' bumps, balanced-free rho',
+    random winds; w vanishes on the bottom and top levels.
+
+    smooth=False adds node-wise noise (parity of the discrete operators does
+    not need smooth data)."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = grid.nz, grid.ny, grid.nx
+    x, y, z = node_coords(grid)
+    X = x[None, None, :] / grid.lx
+    Y = y[None, :, None] / grid.ly
+    Z = z[:, None, None] / grid.lz
+    q = np.zeros(grid.shape)
+
+    def wave():
+        kx, ky = rng.integers(0, 3, size=2)
+        kz = rng.uniform(0.5, 2.0)
+        ph = rng.uniform(0, 2 * np.pi, size=3)
+        return (np.cos(2 * np.pi * kx * X + ph[0]) * np.cos(2 * np.pi * ky * Y + ph[1])
+                * np.cos(np.pi * kz * Z + ph[2]))
+
+    q[0] = 1e-3 * wave()
+    q[1] = wind * wave()
+    q[2] = wind * wave()
+    q[3] = 0.2 * wind * wave() * np.sin(np.pi * Z)
+    q[4] = theta_amp * wave()
+    if not smooth:
+        noise = rng.standard_normal(grid.shape)
+        q[0] += 1e-4 * noise[0]
+        q[1] += 0.5 * noise[1]
+        q[2] += 0.5 * noise[2]
+        q[3] += 0.1 * noise[3]
+        q[4] += 0.1 * noise[4]
+    q[3, 0] = 0.0
+    q[3, -1] = 0.0
+    return q
+
+
+def random_zface(nez, lz, seed):
+    """Non-uniform element faces (heights between 0.5 and 1.5 of uniform)."""
+    rng = np.random.default_rng(seed)
+    h = rng.uniform(0.5, 1.5, size=nez)
+    zf = np.concatenate(([0.0], np.cumsum(h)))
+    zf = zf * (lz / zf[-1])
+    zf[-1] = lz
+    return zf
+
+
+# --------------------------------------------------------------------------
+# Named workloads
+# --------------------------------------------------------------------------
+
+C_VERT = 15.0
+C_HORIZ = 0.4
+
+
+def _stretch(lx, nex, lz, nez):
+    # s * (lx/nex) = (C_VERT / C_HORIZ) * (lz/nez): horizontal Courant number 0.4
+    return (C_VERT / C_HORIZ) * (lz / nez) * nex / lx
+
+
+def box_small(reading="R1"):
+    """4x4x4 elements, N=4, 1 km cube (literal), one 0.5 K bump of radius 250 m, 10 steps."""
+    lx = ly = lz = 1000.0
+    nex = ney = nez = 4
+    s = _stretch(lx, nex, lz, nez) if reading == "R1" else 1.0
+    g = Grid(lx * s, ly * s, lz, nex, ney, nez, 4)
+    if reading == "R1":
+        dt = dt_for_courant(g, C_VERT, "z")
+    else:
+        dt = dt_for_courant(g, C_HORIZ, "x")
+    return Workload(f"box4x4x4_N4_{reading}", g, dt, 10, 1, 1, (0.5, 0.5), (250.0, 250.0), stretch=s)
+
+
+def box_large(reading="R1", nex=64, ney=64):
+    """64x64x10 elements, N=4, 20x20x10 km (literal), eight bumps 0.1-2 K,
+    radius 0.5-2 km, 100 steps.  nex/ney may be reduced for a sub-box with
+    the same element shape, order and dt."""
+    lx = ly = 20000.0
+    lz = 10000.0
+    nez = 10
+    s = _stretch(lx, 64, lz, nez) if reading == "R1" else 1.0
+    hx = lx * s / 64
+    g = Grid(hx * nex, hx * ney, lz, nex, ney, nez, 4)
+    if reading == "R1":
+        dt = dt_for_courant(g, C_VERT, "z")
+    else:
+        dt = dt_for_courant(g, C_HORIZ, "x")
+    return Workload(f"box{nex}x{ney}x10_N4_{reading}", g, dt, 100, 2, 8, (0.1, 2.0), (500.0, 2000.0),
+                    stretch=s)

@@ -1,0 +1,473 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: every check is a closed form,
+a textbook value, an invariant, a value the paper prints (tests/golden/), a
+library routine on a special case, or the defining equation's residual.
+Each check is chosen so that a plausible mistake in the oracle (a dropped
+term, a wrong sign or index, a transposed operand, a wrong DSS weight) fails.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from paper_1702_04316_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+def _oracle(O, grid, bg=None, grav=None):
+    bg = bg or W.Background()
+    g = bg.grav if grav is None else grav
+    return O.Oracle(grid.lx, grid.ly, grid.lz, grid.nex, grid.ney, grid.nez, grid.N,
+                    theta0=bg.theta0, p00=bg.p00, cp=bg.cp, rgas=bg.rgas, grav=g,
+                    zface=grid.zface)
+
+
+# ---------------------------------------------------------------------------
+# LGL basis (the sD operator of Alg. 1-2)
+# ---------------------------------------------------------------------------
+
+def test_lgl_N4_closed_form(oracle_mod):
+    xi, w = oracle_mod.lgl(4)
+    ref = np.array([[float(a), float(b)] for a, b in _golden("lgl_N4.txt")])
+    assert np.allclose(xi, ref[:, 0], atol=1e-15, rtol=0)
+    assert np.allclose(w, ref[:, 1], atol=1e-15, rtol=0)
+    assert abs(xi[3] - math.sqrt(3.0 / 7.0)) < 1e-15
+
+
+@pytest.mark.parametrize("N", range(1, 16))
+def test_lgl_nodes_match_legendre_roots(oracle_mod, N):
+    xi, w = oracle_mod.lgl(N)
+    inner = np.sort(np.polynomial.legendre.Legendre.basis(N).deriv().roots().real) if N > 1 else np.array([])
+    ref = np.concatenate(([-1.0], inner, [1.0]))
+    assert np.max(np.abs(xi - ref)) < 1e-14
+    assert abs(w.sum() - 2.0) < 1e-14
+    # Gauss-Lobatto quadrature is exact for polynomials of degree <= 2N-1
+    for k in range(2 * N):
+        exact = 0.0 if k % 2 else 2.0 / (k + 1)
+        assert abs(np.dot(w, xi ** k) - exact) < 1e-13
+
+
+@pytest.mark.parametrize("N", range(1, 16))
+def test_dmat_exact_on_polynomials(oracle_mod, N):
+    xi, _ = oracle_mod.lgl(N)
+    D = oracle_mod.dmat(N)
+    assert np.max(np.abs(D @ np.ones(N + 1))) < 1e-12 * (N + 1) ** 2
+    for k in range(1, N + 1):
+        err = np.max(np.abs(D @ xi ** k - k * xi ** (k - 1)))
+        assert err < 1e-12 * (N + 1) ** 2, (N, k, err)
+    # corner entries of the textbook LGL matrix
+    assert abs(D[0, 0] + N * (N + 1) / 4.0) < 1e-13
+    assert abs(D[N, N] - N * (N + 1) / 4.0) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Grid, mass, background
+# ---------------------------------------------------------------------------
+
+def test_mass_sums_to_volume(oracle_mod):
+    zf = W.random_zface(3, 900.0, seed=5)
+    g = W.Grid(1200.0, 700.0, 900.0, 3, 2, 3, 5, zface=zf)
+    o = _oracle(oracle_mod, g)
+    M = o.mass()
+    assert M.shape == (g.nz, g.ny, g.nx)
+    assert abs(M.sum() / (g.lx * g.ly * g.lz) - 1.0) < 1e-14
+    assert np.all(M > 0)
+
+
+def test_background_pins(oracle_mod):
+    g = W.box_small("R2").grid
+    o = _oracle(oracle_mod, g)
+    bg = o.background()
+    cp, R, th0, p00, grav = W.CP, W.RGAS, W.THETA0, W.P00, W.GRAV
+    # surface values: pi0 = 1, so rho0 = p00/(R theta0) and P0 = p00
+    assert abs(bg["rho0"][0] - p00 / (R * th0)) < 1e-15
+    assert abs(bg["P0"][0] / p00 - 1.0) < 1e-14
+    # G0 = gamma P0 / rho0 is c^2; at the surface it is gamma R theta0
+    gamma = cp / (cp - R)
+    assert abs(bg["G0"][0] / (gamma * R * th0) - 1.0) < 1e-14
+    # isentropic: EOS(rho0, theta0) equals the Exner form p00 pi0^(cp/R) in exact arithmetic
+    _, _, z = o.coords()
+    pi0 = 1.0 - grav * z / (cp * th0)
+    assert np.max(np.abs(bg["P0"] / (p00 * pi0 ** (cp / R)) - 1.0)) < 1e-13
+    # hydrostatic: the continuum d P0/dz = -rho0 g holds (central differences, interior)
+    dP = np.gradient(bg["P0"], z)
+    assert np.max(np.abs(dP[1:-1] / (-bg["rho0"][1:-1] * grav) - 1.0)) < 1e-4
+
+
+def test_sound_speed_printed_value():
+    """c0 = sqrt(gamma R theta0) reproduces the sound speed printed for the acoustic test."""
+    rows = {r[0]: (float(r[1]), float(r[2])) for r in _golden("sound_speed.txt")}
+    c, tol = rows["c0_m_per_s"]
+    assert abs(W.sound_speed() - c) < tol
+
+
+# ---------------------------------------------------------------------------
+# DSS derivative exactness (Sec. 5.3): exact on continuous global polynomials
+# of degree <= N for any element heights.  With g = 0 the background is
+# uniform and the linear operators reduce to pure derivatives.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N,nez,seed", [(2, 3, 0), (4, 4, 1), (5, 2, 2), (7, 3, 3)])
+def test_vertical_dss_derivative_exact(oracle_mod, N, nez, seed):
+    lz = 1000.0
+    zf = W.random_zface(nez, lz, seed)
+    g = W.Grid(800.0, 800.0, lz, 2, 1, nez, N, zface=zf)
+    o = _oracle(oracle_mod, g, grav=0.0)
+    bg = o.background()
+    rho0, G0 = bg["rho0"][0], bg["G0"][0]
+    _, _, z = o.coords()
+    s = z / lz
+    q = np.zeros(g.shape)
+    p = s ** N - 0.3 * s ** (N - 1) + 0.2            # rho' = p(z), degree N
+    dp = (N * s ** (N - 1) - 0.3 * (N - 1) * s ** (N - 2)) / lz
+    wz = s * (1.0 - s) * (0.5 + s ** (N - 2))        # w = 0 at both walls, degree N
+    dwz = ((1.0 - 2 * s) * (0.5 + s ** (N - 2)) + s * (1.0 - s) * (N - 2) * s ** max(N - 3, 0)) / lz
+    q[0] = 1e-3 * p[:, None, None]
+    q[3] = wz[:, None, None]
+    L = o.lv(q)
+    # l_rho = -d(rho0 w)/dz = -rho0 w'  ;  l_w = -(G0 d rho'/dz)/rho0 (interior)
+    assert np.max(np.abs(L[0] + rho0 * dwz[:, None, None])) < 1e-11 * rho0 / lz * lz
+    lw = -(G0 * 1e-3 * dp / rho0)
+    assert np.max(np.abs(L[3][1:-1] - lw[1:-1, None, None])) < 1e-9
+    assert np.all(L[3][0] == 0.0) and np.all(L[3][-1] == 0.0)
+
+
+@pytest.mark.parametrize("N,nex", [(3, 2), (4, 3), (6, 2)])
+def test_horizontal_dss_derivative_exact(oracle_mod, N, nex):
+    """Periodic x: f(x) = x (x - lx/2)(x - lx) is C1-periodic, so its DSS
+    derivative is exact at every node, including the periodic interface."""
+    lx = 3000.0
+    g = W.Grid(lx, 2000.0, 500.0, nex, 2, 1, N)
+    o = _oracle(oracle_mod, g, grav=0.0)
+    bg = o.background()
+    rho0, G0 = bg["rho0"][0], bg["G0"][0]
+    x, y, _ = o.coords()
+    f = x * (x - lx / 2) * (x - lx) / lx ** 3
+    df = (3 * x * x - 3 * lx * x + lx * lx / 2) / lx ** 3
+    q = np.zeros(g.shape)
+    q[1] = f[None, None, :]          # u = f(x)
+    q[0] = 1e-3 * f[None, None, :]   # rho' = 1e-3 f(x)
+    L = o.lfull(q)
+    assert np.max(np.abs(L[0] + rho0 * df[None, None, :])) < 1e-13
+    assert np.max(np.abs(L[1] + G0 * 1e-3 * df[None, None, :] / rho0)) < 1e-9
+    # y-direction with the same profile along y
+    ly = g.ly
+    fy = y * (y - ly / 2) * (y - ly) / ly ** 3
+    dfy = (3 * y * y - 3 * ly * y + ly * ly / 2) / ly ** 3
+    q = np.zeros(g.shape)
+    q[2] = fy[None, :, None]
+    L = o.lfull(q)
+    assert np.max(np.abs(L[0] + rho0 * dfy[None, :, None])) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Explicit RHS of Set2NC (Sec. 3.1)
+# ---------------------------------------------------------------------------
+
+def test_rest_state_is_exactly_at_rest(oracle_mod):
+    zf = W.random_zface(4, 1000.0, 7)
+    g = W.Grid(37500.0, 37500.0, 1000.0, 4, 4, 4, 4, zface=zf)
+    o = _oracle(oracle_mod, g)
+    q = np.zeros(g.shape)
+    R = o.rhs(q)
+    assert np.all(R == 0.0)
+    dt = W.dt_for_courant(g, 15.0, "z")
+    o.factor_dt(dt)
+    q1 = o.step(q, dt, 2)
+    assert np.all(q1 == 0.0)
+
+
+def test_mass_conservation_of_rhs(oracle_mod):
+    """Divergence-form continuity + periodic x, y + w = 0 on the walls:
+    the DSS-summed mass tendency vanishes to roundoff."""
+    g = W.Grid(5000.0, 4000.0, 2000.0, 3, 2, 3, 4, zface=W.random_zface(3, 2000.0, 3))
+    o = _oracle(oracle_mod, g)
+    q = W.make_random_state(g, seed=11, smooth=False)
+    R = o.rhs(q)
+    M = o.mass()
+    scale = np.sum(M * np.abs(R[0]))
+    assert abs(np.sum(M * R[0])) < 1e-13 * scale
+
+
+def test_rhs_linearisation_is_the_linear_operator(oracle_mod):
+    """About the rest state R(eps q) = eps L(q) + O(eps^2), with L the full
+    linear operator of Set2NC (Sec. 3.1); central differences cancel O(eps^2)."""
+    g = W.Grid(6000.0, 5000.0, 3000.0, 2, 2, 2, 4)
+    o = _oracle(oracle_mod, g)
+    q = W.make_random_state(g, seed=3)
+    L = o.lfull(q)
+    central, onesided = [], []
+    for eps in (0.5, 0.25):
+        dR = (o.rhs(eps * q) - o.rhs(-eps * q)) / (2 * eps)
+        central.append(np.max(np.abs(dR - L)) / np.max(np.abs(L)))
+        onesided.append(np.max(np.abs(o.rhs(eps * q) / eps - L)) / np.max(np.abs(L)))
+    assert central[0] < 1e-6
+    assert 3.8 < central[0] / central[1] < 4.2    # odd part: O(eps^2)
+    assert 1.9 < onesided[0] / onesided[1] < 2.1  # quadratic terms (advection): O(eps)
+
+
+def test_rhs_advection_and_buoyancy(oracle_mod):
+    """A balanced warm bump in a uniform wind U: P' = 0 up to roundoff, so
+    R_u = R_v = 0, R_theta = -U d theta'/dx (advection), and the buoyancy
+    R_w = -g rho'/rho is positive where theta' > 0 (warm air rises)."""
+    wl = W.box_small("R1")
+    g = W.Grid(wl.grid.lx, wl.grid.ly, wl.grid.lz, 8, 8, 4, 6)
+    wl = W.Workload("adv", g, wl.dt, 1, 1, 1, (0.5, 0.5), (250.0, 250.0), stretch=wl.stretch)
+    o = _oracle(oracle_mod, g)
+    q = W.make_initial_state(wl)
+    U = 12.0
+    q[1] = U
+    R = o.rhs(q)
+    rho0 = o.background()["rho0"]
+    assert np.max(np.abs(R[1])) < 1e-9 and np.max(np.abs(R[2])) < 1e-9
+    # analytic x-derivative of the Gaussian bump sum (spectrally accurate)
+    th = q[4]
+    x, y, z = W.node_coords(g)
+    rng = np.random.default_rng(wl.seed)
+    xm, ym, zm = (rng.uniform() * g.lx, rng.uniform() * g.ly, rng.uniform() * g.lz)
+    A = rng.uniform(0.5, 0.5)
+    r = rng.uniform(250.0, 250.0)
+    rh = wl.stretch * r
+    X, Y, Z = x[None, None, :], y[None, :, None], z[:, None, None]
+    gx = sum(np.exp(-((X - xm + m * g.lx) / rh) ** 2) for m in range(-2, 3))
+    dgx = sum(-2.0 * (X - xm + m * g.lx) / rh ** 2 * np.exp(-((X - xm + m * g.lx) / rh) ** 2) for m in range(-2, 3))
+    dthdx = th * dgx / gx
+    scale = np.max(np.abs(U * dthdx))
+    assert np.max(np.abs(R[4] + U * dthdx)) < 2e-3 * scale
+    rho = rho0[:, None, None] + q[0]
+    buoy = -W.GRAV * q[0] / rho
+    assert np.max(np.abs(R[3][1:-1] - buoy[1:-1])) < 1e-6 * np.max(np.abs(buoy))
+    assert R[3][1:-1][th[1:-1] > 0.1].min() > 0
+
+
+def test_acoustic_phase_speed(oracle_mod):
+    """With g = 0 the background is uniform and the full linear operator is
+    linear acoustics: the x-mode of wavenumber k has frequency c0 k, with c0
+    the sound speed printed for the acoustic test (347.32 m/s)."""
+    N, nex = 5, 4
+    lx = 40000.0
+    g = W.Grid(lx, 4000.0, 4000.0, nex, 1, 1, N)
+    o = _oracle(oracle_mod, g, grav=0.0)
+    # restrict to x-dependent fields (rho', u): probe L on that subspace
+    nx = g.nx
+    x, _, _ = o.coords()
+    cols = []
+    for f in (0, 1):
+        for i in range(nx):
+            q = np.zeros(g.shape)
+            q[f, :, :, i] = 1.0
+            L = o.lfull(q)
+            cols.append(np.concatenate((L[0, 1, 0, :], L[1, 1, 0, :])))
+    A = np.array(cols).T
+    ev = np.linalg.eigvals(A)
+    k = 2 * np.pi / lx
+    c_num = np.min(np.abs(np.abs(ev.imag) - W.sound_speed() * k)) / k
+    assert c_num < 1e-5 * W.sound_speed()
+    rows = {r[0]: (float(r[1]), float(r[2])) for r in _golden("sound_speed.txt")}
+    near = ev[np.argmin(np.abs(np.abs(ev.imag) - W.sound_speed() * k))]
+    assert abs(abs(near.imag) / k - rows["c0_m_per_s"][0]) < rows["c0_m_per_s"][1]
+    assert np.max(np.abs(ev.real)) < 1e-9 * np.max(np.abs(ev))  # non-dissipative
+
+
+# ---------------------------------------------------------------------------
+# Column solve (Sec. 5.4): x = (I - lambda L_V)^{-1} y
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N,nez,seed", [(1, 3, 0), (3, 2, 1), (4, 3, 2), (4, 10, 3), (7, 2, 4)])
+def test_column_solve_residual(oracle_mod, N, nez, seed):
+    """The solve satisfies its defining equation x - lambda L_V(x) = y, checked
+    with the operator L_V itself (not with the factors)."""
+    lz = 10000.0
+    g = W.Grid(3000.0, 2000.0, lz, 2, 1, nez, N, zface=W.random_zface(nez, lz, seed))
+    o = _oracle(oracle_mod, g)
+    dt = W.dt_for_courant(g, 15.0, "z")
+    o.factor_dt(dt)
+    y = W.make_random_state(g, seed, smooth=False)
+    x = o.solve(y)
+    res = x - o.lam * o.lv(x) - y
+    for f in range(5):
+        assert np.max(np.abs(res[f])) < 1e-11 * max(1.0, np.max(np.abs(y[f]))), f
+    assert np.array_equal(x[1], y[1]) and np.array_equal(x[2], y[2]) and np.array_equal(x[4], y[4])
+    assert np.all(x[3, 0] == 0.0) and np.all(x[3, -1] == 0.0)
+
+
+def test_column_matrix_vs_lapack(oracle_mod):
+    """The probed column matrix, solved by LAPACK gesv, gives the oracle's
+    solution; columns are independent (every column's matrix is the same in
+    a horizontally uniform box, Sec. 5.4)."""
+    lz = 3000.0
+    g = W.Grid(2000.0, 2000.0, lz, 2, 2, 3, 3, zface=W.random_zface(3, lz, 9))
+    o = _oracle(oracle_mod, g)
+    dt = W.dt_for_courant(g, 15.0, "z")
+    lam = (1 - 1 / np.sqrt(2)) * dt
+    o.factor(lam)
+    A = o.column_matrix(lam, 1, 2)
+    A2 = o.column_matrix(lam, 4, 0)
+    # identical up to the rounding of the DSS average over horizontal neighbours
+    assert np.max(np.abs(A - A2)) < 1e-14 * np.max(np.abs(A))
+    y = W.make_random_state(g, 2)
+    x = o.solve(y)
+    M = g.nz
+    # theta' enters through the right-hand side: b = y + lambda L_V(theta'-only)
+    t = np.zeros(g.shape)
+    t[4] = y[4]
+    Lt = o.lv(t)
+    b = np.concatenate((y[0, :, 2, 1] + lam * Lt[0, :, 2, 1], y[3, :, 2, 1] + lam * Lt[3, :, 2, 1]))
+    sol = scipy.linalg.solve(A, b)
+    assert np.max(np.abs(sol[:M] - x[0, :, 2, 1])) < 1e-13 * np.max(np.abs(x[0]))
+    assert np.max(np.abs(sol[M:] - x[3, :, 2, 1])) < 1e-13 * np.max(np.abs(x[3]))
+
+
+def test_schur_form_equals_standard_form(oracle_mod):
+    """Eliminating rho' and w (the Schur complement of Eqs. (14)-(17), 1D,
+    theta0 constant so A = I) gives the same column solution as the oracle's
+    standard-form solve.  The Schur operator is assembled here from the
+    oracle's vertical derivative matrix (probed through L_V with g = 0)."""
+    lz = 8000.0
+    nez, N = 3, 4
+    g = W.Grid(2000.0, 2000.0, lz, 1, 1, nez, N, zface=W.random_zface(nez, lz, 4))
+    o = _oracle(oracle_mod, g)
+    og = _oracle(oracle_mod, g, grav=0.0)
+    M = g.nz
+    rho0g = og.background()["rho0"][0]
+    # Dz: probe l_rho = -d(rho0 w)/dz with uniform rho0 (g = 0)
+    Dz = np.zeros((M, M))
+    for m in range(M):
+        q = np.zeros(g.shape)
+        q[3, m] = 1.0
+        Dz[:, m] = -og.lv(q)[0, :, 0, 0] / rho0g
+    bg = o.background()
+    rho0, G0, H0 = bg["rho0"], bg["G0"], bg["H0"]
+    grav = W.GRAV
+    dt = W.dt_for_courant(g, 15.0, "z")
+    lam = (1 - 1 / np.sqrt(2)) * dt
+    o.factor(lam)
+    B = np.ones(M)
+    B[0] = B[-1] = 0.0
+    S = np.eye(M) - lam * lam * np.diag(G0) @ Dz @ np.diag(rho0 * B) @ (np.diag(1 / rho0) @ Dz + np.diag(grav / (G0 * rho0)))
+    y = W.make_random_state(g, 8)
+    yr, yw, yt = y[0, :, 0, 0], y[3, :, 0, 0], y[4, :, 0, 0]
+    wa = B * (yw + lam * grav * H0 * yt / (G0 * rho0))
+    rhs = G0 * yr + H0 * yt - lam * G0 * (Dz @ (rho0 * wa))
+    P = np.linalg.solve(S, rhs)
+    wp = lam * (Dz @ P / rho0 + grav * P / (G0 * rho0))
+    xw = B * (wa - wp)
+    xr = yr - lam * (Dz @ (rho0 * xw))
+    x = o.solve(y)
+    assert np.max(np.abs(xw - x[3, :, 0, 0])) < 1e-12 * np.max(np.abs(xw))
+    assert np.max(np.abs(xr - x[0, :, 0, 0])) < 1e-12 * np.max(np.abs(xr))
+    # the pressure form of rho' agrees: rho' = (P - H0 theta')/G0
+    assert np.max(np.abs((P - H0 * yt) / G0 - xr)) < 1e-10 * np.max(np.abs(xr))
+    # half-bandwidth of S is 2N
+    band = max(abs(i - j) for i in range(M) for j in range(M) if abs(S[i, j]) > 1e-14)
+    assert band == 2 * N
+
+
+# ---------------------------------------------------------------------------
+# ARK2 (Sec. 2.2, Table 1)
+# ---------------------------------------------------------------------------
+
+def _tableau_from_golden():
+    env = {"sqrt": math.sqrt}
+    return {r[0]: eval(r[1], env) for r in _golden("ark2_tableau.txt")}
+
+
+def test_ark2_tableau_matches_table_and_order_conditions(oracle_mod):
+    a, at, b = oracle_mod.ark2_tableau()
+    t = _tableau_from_golden()
+    assert abs(a[1, 0] - t["a21"]) < 1e-15 and abs(a[2, 0] - t["a31"]) < 1e-15 and abs(a[2, 1] - t["a32"]) < 1e-15
+    assert abs(at[1, 0] - t["at21"]) < 1e-15 and abs(at[1, 1] - t["at22"]) < 1e-15
+    assert abs(at[2, 0] - t["at31"]) < 1e-15 and abs(at[2, 1] - t["at32"]) < 1e-15 and abs(at[2, 2] - t["at33"]) < 1e-15
+    assert np.allclose(b, [t["b1"], t["b2"], t["b3"]], atol=1e-15, rtol=0)
+    c = np.array([0.0, t["c2"], t["c3"]])
+    assert np.allclose(a.sum(1), c, atol=1e-15) and np.allclose(at.sum(1), c, atol=1e-15)
+    assert abs(b.sum() - 1) < 1e-15 and abs(b @ c - 0.5) < 1e-15
+    assert np.allclose(at[2], b, atol=1e-15)                      # stiffly accurate implicit part
+    assert abs(at[1, 1] - at[2, 2]) < 1e-16                         # SDIRK: equal diagonal
+    assert abs(b[2] * a[2, 1] * a[1, 0] - 1.0 / 6.0) < 1e-15        # explicit stability poly 1+z+z^2/2+z^3/6
+    assert abs(b @ (a @ c) - 1.0 / 6.0) < 1e-15
+
+
+def test_ark2_second_order_on_linear_acoustics(oracle_mod):
+    """R := full linear L, split L - L_V explicit and L_V implicit.  Compared with
+    the exact solution expm(T A) q0 (A probed from L), the error falls by ~4
+    each time dt halves."""
+    N = 3
+    g = W.Grid(6000.0, 3000.0, 3000.0, 2, 1, 2, N)
+    o = _oracle(oracle_mod, g)
+    n = int(np.prod(g.shape))
+    A = np.zeros((n, n))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        A[:, j] = o.lfull(e.reshape(g.shape)).reshape(-1)
+    q0 = W.make_random_state(g, 5)
+    T = 4.0
+    exact = (scipy.linalg.expm(T * A) @ q0.reshape(-1)).reshape(g.shape)
+    errs = []
+    for nsteps in (4, 8, 16, 32):
+        dt = T / nsteps
+        o.factor_dt(dt)
+        qT = o.step(q0, dt, nsteps, linear=True)
+        errs.append(np.linalg.norm(qT - exact) / np.linalg.norm(exact))
+    slopes = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert min(slopes[1:]) >= 1.9, (errs, slopes)
+
+
+def test_ark2_second_order_nonlinear(oracle_mod):
+    """Richardson ratio on the nonlinear step: |q(dt)-q(dt/2)| / |q(dt/2)-q(dt/4)| ~ 4."""
+    g = W.Grid(30000.0, 30000.0, 1000.0, 3, 3, 3, 4)
+    o = _oracle(oracle_mod, g)
+    q0 = W.make_random_state(g, 4)
+    T = 0.5  # asymptotic regime (vertical Courant number <= 1 at the coarsest dt)
+    sols = []
+    for nsteps in (4, 8, 16):
+        dt = T / nsteps
+        o.factor_dt(dt)
+        sols.append(o.step(q0, dt, nsteps))
+    r = np.linalg.norm(sols[0] - sols[1]) / np.linalg.norm(sols[1] - sols[2])
+    assert 3.7 < r < 4.3, r
+
+
+def test_step_conserves_mass(oracle_mod):
+    wl = W.box_small("R1")
+    o = _oracle(oracle_mod, wl.grid)
+    q = W.make_initial_state(wl)
+    M = o.mass()
+    m0 = np.sum(M * q[0])
+    o.factor_dt(wl.dt)
+    q = o.step(q, wl.dt, 5)
+    assert abs(np.sum(M * q[0]) - m0) < 1e-13 * np.sum(M * np.abs(q[0]))
+
+
+def test_hevi_needs_anisotropy(oracle_mod):
+    """HEVI gives no gain at aspect ratio 1 (Sec. 2): the literal 1 km cube at
+    vertical Courant number 15 is horizontally explicit at Courant 15 and blows
+    up, while the stretched box at the same dt stays bounded."""
+    lit = W.box_small("R2")
+    r1 = W.box_small("R1")
+    dt = r1.dt  # vertical Courant number 15 on both grids (same vertical grid)
+    out = {}
+    for name, wl in (("literal", lit), ("stretched", r1)):
+        o = _oracle(oracle_mod, wl.grid)
+        q = W.make_initial_state(wl)
+        o.factor_dt(dt)
+        with np.errstate(all="ignore"):
+            q1 = o.step(q, dt, 10)
+        out[name] = np.nanmax(np.abs(q1[3])) if np.all(np.isfinite(q1)) else np.inf
+    assert out["literal"] > 1e3
+    assert out["stretched"] < 1.0
