@@ -283,6 +283,37 @@ static void dss(const orc_ctx *c, const double *r, double *R)
 /* divergence form.                                                         */
 /* ------------------------------------------------------------------------ */
 
+/* P' = EOS(rho0 + rho', theta0 + theta') - P0(z), Eq. (10) with the
+ * background split of Sec. 3.1.  Since P0 = EOS(rho0, theta0), the same
+ * quantity is P0 [((rho theta)/(rho0 theta0))^gamma - 1]; it is evaluated in
+ * that form, with rho theta - rho0 theta0 = rho0 theta' + theta0 rho' +
+ * rho' theta', so that two ~1e5 Pa pressures are never subtracted (the
+ * subtraction would leave P' with an absolute rounding error of about 1e-11
+ * Pa, the whole of P' in a balanced state).  Accuracy: a few ulp of P'. */
+static double pressure_perturbation(const orc_ctx *c, int k, double rp, double th)
+{
+    double r0 = c->rho0[k], t0 = c->theta0;
+    /* rho0 theta', theta0 rho' and rho' theta' nearly cancel in a
+     * hydrostatically balanced state; the rounding error of each product is
+     * recovered exactly with fma, so that their small sum keeps its relative
+     * precision (the partial sums of nearly opposite terms are exact) */
+    double p1 = r0 * th, p2 = t0 * rp, p3 = rp * th;
+    double e1 = fma(r0, th, -p1), e2 = fma(t0, rp, -p2), e3 = fma(rp, th, -p3);
+    double d = ((p1 + p2) + p3) + ((e1 + e2) + e3);
+    return c->P0[k] * expm1(c->gamma * log1p(d / (r0 * t0)));
+}
+
+int orc_pressure_perturbation(orc_ctx *c, const double *q, double *Pp)
+{
+    if (!c || !q || !Pp) return -1;
+    long plane = (long)c->nx * c->ny;
+    for (long I = 0; I < c->np; ++I) {
+        int k = (int)(I / plane);
+        Pp[I] = pressure_perturbation(c, k, q[0 * c->np + I], q[4 * c->np + I]);
+    }
+    return 0;
+}
+
 int orc_rhs(orc_ctx *c, const double *q, double *R)
 {
     if (!c || !q || !R) return -1;
@@ -308,9 +339,7 @@ int orc_rhs(orc_ctx *c, const double *q, double *R)
                     rp[l] = q[0 * np + I]; u[l] = q[1 * np + I]; v[l] = q[2 * np + I];
                     w[l] = q[3 * np + I]; th[l] = q[4 * np + I];
                     rho[l] = c->rho0[k] + rp[l];
-                    double theta = c->theta0 + th[l];
-                    /* P' = EOS(rho, theta) - P0 (Eq. (10) and the background split) */
-                    Pp[l] = c->p00 * pow(rho[l] * c->R * theta / c->p00, c->gamma) - c->P0[k];
+                    Pp[l] = pressure_perturbation(c, k, rp[l], th[l]);
                     Fx[l] = rho[l] * u[l]; Fy[l] = rho[l] * v[l]; Fz[l] = rho[l] * w[l];
                 }
                 for (int cc = 0; cc < c->nq; ++cc)

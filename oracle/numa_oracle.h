@@ -55,6 +55,9 @@ void orc_mass(const orc_ctx *c, double *M);
 /* Background per level k: rho0, P0, G0 = gamma P0/rho0, H0 = gamma P0/theta0. */
 void orc_background(const orc_ctx *c, double *rho0, double *P0, double *G0, double *H0);
 
+/* Perturbation pressure P' = EOS(rho, theta) - P0 at every unique node
+ * (evaluated without cancelling the background pressure). */
+int orc_pressure_perturbation(orc_ctx *c, const double *q, double *Pp);
 /* Explicit right-hand side R(q) of Set2NC (Sec. 3.1) with DSS. */
 int orc_rhs(orc_ctx *c, const double *q, double *R);
 /* Vertical linear operator L_V(q) (Sec. 2, HEVI splitting; Sec. 3.1 operator L). */

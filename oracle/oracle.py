@@ -44,6 +44,8 @@ def _load():
         f = getattr(lib, name)
         f.argtypes = [C.c_void_p, _dp, _dp]
         f.restype = C.c_int
+    lib.orc_pressure_perturbation.argtypes = [C.c_void_p, _dp, _dp]
+    lib.orc_pressure_perturbation.restype = C.c_int
     lib.orc_factor.argtypes = [C.c_void_p, C.c_double]
     lib.orc_factor.restype = C.c_int
     lib.orc_column_matrix.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_int, _dp]
@@ -143,6 +145,12 @@ class Oracle:
         assert q.shape == self.shape, (q.shape, self.shape)
         out = np.zeros(self.shape)
         _check(getattr(_lib, name)(self.h, q.reshape(-1), out.reshape(-1)), name)
+        return out
+
+    def pressure_perturbation(self, q):
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        out = np.zeros(self.shape[1:])
+        _check(_lib.orc_pressure_perturbation(self.h, q.reshape(-1), out.reshape(-1)), "orc_pressure_perturbation")
         return out
 
     def rhs(self, q):

@@ -471,3 +471,58 @@ def test_hevi_needs_anisotropy(oracle_mod):
         out[name] = np.nanmax(np.abs(q1[3])) if np.all(np.isfinite(q1)) else np.inf
     assert out["literal"] > 1e3
     assert out["stretched"] < 1.0
+
+
+# ---------------------------------------------------------------------------
+# Perturbation pressure (Eq. (10) with the background split of Sec. 3.1)
+# ---------------------------------------------------------------------------
+
+def test_pressure_perturbation_high_precision(oracle_mod):
+    """P' = EOS(rho0 + rho', theta0 + theta') - P0 against a 50-digit decimal
+    evaluation of the same definition: relative error of a few ulp of P'
+    itself, down to balanced states where P' is 1e-12 of P0."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 50
+    g = W.Grid(3000.0, 3000.0, 8000.0, 2, 1, 2, 4)
+    o = _oracle(oracle_mod, g)
+    bg = o.background()
+    rng = np.random.default_rng(12)
+    q = np.zeros(g.shape)
+    th = rng.uniform(-2.0, 2.0, size=q[4].shape)
+    rho0 = bg["rho0"][:, None, None]
+    balanced = -rho0 * th / (W.THETA0 + th)
+    scale = 10.0 ** rng.uniform(-12, 0, size=th.shape)   # departures from balance, 1e-12 .. 1
+    q[4] = th
+    q[0] = balanced * (1.0 + scale * rng.choice([-1.0, 1.0], size=th.shape))
+    P = o.pressure_perturbation(q)
+    cp, R = Decimal(W.CP), Decimal(W.RGAS)
+    gamma = cp / (cp - R)
+    t0 = Decimal(W.THETA0)
+    worst = 0.0
+    for k in range(g.nz):
+        r0, P0 = Decimal(bg["rho0"][k]), Decimal(bg["P0"][k])
+        for j in range(g.ny):
+            for i in range(0, g.nx, 3):
+                rho = r0 + Decimal(q[0, k, j, i])
+                theta = t0 + Decimal(q[4, k, j, i])
+                ref = P0 * ((rho * theta) / (r0 * t0)) ** gamma - P0
+                err = abs(Decimal(P[k, j, i]) - ref) / abs(ref)
+                worst = max(worst, float(err))
+    assert worst < 1e-14, worst
+
+
+def test_pressure_perturbation_is_eos_minus_background(oracle_mod):
+    """The same P' equals the literal EOS(rho, theta) - P0 to within the
+    rounding of a 1e5 Pa pressure, and vanishes exactly at rest."""
+    g = W.box_small("R2").grid
+    o = _oracle(oracle_mod, g)
+    bg = o.background()
+    q = W.make_random_state(g, 3)
+    P = o.pressure_perturbation(q)
+    cv = W.CP - W.RGAS
+    gamma = W.CP / cv
+    rho = bg["rho0"][:, None, None] + q[0]
+    theta = W.THETA0 + q[4]
+    lit = W.P00 * (rho * W.RGAS * theta / W.P00) ** gamma - bg["P0"][:, None, None]
+    assert np.max(np.abs(P - lit)) < 8 * np.spacing(W.P00)
+    assert np.all(o.pressure_perturbation(np.zeros(g.shape)) == 0.0)
