@@ -1,0 +1,164 @@
+"""Benchmark of the HEVI (1D-IMEX) ARK2 step on one MI355X.
+
+Workload: 64 x 64 x 10 hexahedral elements at LGL order 4 (256 x 256 x 41 =
+2,686,976 unique nodes, 65,536 columns of 41 levels), x and y periodic,
+vertical Courant number 15 with the horizontal extent stretched to a
+horizontal Courant number of 0.4 (2400 x 2400 x 10 km), FP64, eight seeded
+potential-temperature bumps in hydrostatic pressure balance.
+
+Prints ONE JSON line.  value = DOF-steps/s = 5 * unique nodes * steps / s,
+with the state already resident in HBM.  The timed steps record a HIP event
+around every kernel on the library's stream; the roofline object uses the
+average duration of the dominant kernel and its algorithmic bytes.  The CPU
+baseline times the plain FP64 oracle on a bounded sub-box of the same
+workload (same element shape, order and dt).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_bytes(np_, ncol, nz, N):
+    """Algorithmic HBM bytes per launch of the five kernels of a step: whole
+    unique-node field passes (reads + writes) and the column factor reads."""
+    F = ncol * nz * (4 * N + 1) * 8
+    f = 8 * np_
+    return [
+        ("rhs_stage1", 10 * f),          # reads q^n (5), writes R1 (5)
+        ("colsolve_stage2", 7 * f + F),  # reads R1 rho/w/theta, q^n rho/w; writes Q2 rho/w; factors
+        ("rhs_stage2", 22 * f),          # reads Q2 rho/w, q^n (5), R1 (5); writes E3 (5), ACC (5)
+        ("colsolve_stage3", 11 * f + F), # reads E3, q^n (rho/w/theta), Q2 rho/w, R1 theta; writes Q3 rho/w; factors
+        ("rhs_stage3", 15 * f),          # reads Q3 rho/w, E3 u/v/theta, ACC (5); writes q^{n+1} (5)
+    ]
+
+
+def load_traffic():
+    """Measured HBM bytes per launch from the committed rocprofv3 counter summary, if any."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        return json.load(f)
+
+
+def cpu_baseline(sample_nex=32, steps=6):
+    import numpy as np
+    from oracle import oracle as O
+    from paper_1702_04316_amd import workloads as W
+    wl = W.box_large("R1", nex=sample_nex, ney=sample_nex)
+    g = wl.grid
+    o = O.Oracle(g.lx, g.ly, g.lz, g.nex, g.ney, g.nez, g.N)
+    q0 = W.make_initial_state(wl)
+    o.factor_dt(wl.dt)
+    t0 = time.perf_counter()
+    o.step(q0, wl.dt, steps)
+    t = time.perf_counter() - t0
+    return {"value": 5.0 * g.n_unique * steps / t, "unit": "DOF-steps/s", "cores": O.get_threads(),
+            "kind": "oracle",
+            "sample": f"{sample_nex}x{sample_nex}x10 elements N=4 sub-box of the benchmarked workload "
+                      f"(same element shape, order and dt), {steps} steps, factorisation not timed",
+            "seconds": t}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1702_04316_amd import numa
+    from paper_1702_04316_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    wl = W.box_large("R1")
+    g = wl.grid
+    ctx = numa.Context(g, wl.background)
+    t0 = time.perf_counter()
+    ctx.factor(wl.dt)
+    torch.cuda.synchronize()
+    t_factor = time.perf_counter() - t0
+    q = torch.from_numpy(W.make_initial_state(wl)).to("cuda")
+
+    ctx.step(q, args.warmup)
+    ctx.check()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = numa.profile_steps(ctx.ctx, q.data_ptr(), wl.dt, args.steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    ctx.check()
+
+    info = ctx.info()
+    dof = 5 * g.n_unique
+    value = dof * args.steps / t
+    kb = kernel_bytes(g.n_unique, info["ncol"], info["nz"], g.N)
+    per = [{"kernel": n, "ms": m, "GB/s": b / (m * 1e-3) / 1e9} for (n, b), m in zip(kb, ms)]
+    dom = max(range(5), key=lambda i: ms[i])
+    achieved = kb[dom][1] / (ms[dom] * 1e-3) / 1e9
+    traffic = load_traffic()
+    t_bytes = None
+    if traffic and traffic.get("kernel") == kb[dom][0]:
+        t_bytes = traffic.get("bytes_per_launch")
+    step_bytes = info["step_bytes"]
+    out = {
+        "metric": "HEVI DOF-steps/s on 1 GPU; speedup vs plain FP64 at fixed rel. L2 error",
+        "value": value,
+        "unit": "DOF-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "HEVI ARK2 step, box 64x64x10 elements, LGL N=4, 256x256x41 unique nodes, "
+                        "vertical Courant 15 (horizontal 0.4, 2400x2400x10 km), 8 seeded theta' bumps, FP64",
+            "unique_nodes": g.n_unique,
+            "element_local_nodes": g.n_local,
+            "dof_per_step": dof,
+            "dt_s": wl.dt,
+            "element_local_dof_steps_per_s": 5 * g.n_local * args.steps / t,
+            "factor_s": t_factor,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": kb[dom][0],
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": t_bytes,
+            "algorithmic_bytes_per_launch": kb[dom][1],
+            "avg_launch_ms": ms[dom],
+        },
+        "kernels": per,
+        "step_algorithmic_GBps": step_bytes * args.steps / t / 1e9,
+    }
+    if not args.no_cpu_baseline:
+        try:
+            out["cpu_baseline"] = cpu_baseline()
+        except Exception as e:  # the baseline must not hide the GPU line
+            out["cpu_baseline"] = {"error": str(e)}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,191 @@
+/*
+ * numa.h -- C ABI of the MI355X (gfx950) HEVI step for NUMA.
+ *
+ * The method is the horizontally-explicit, vertically-implicit ("1D-IMEX")
+ * ARK2 time step of Abdi, Giraldo, Constantinescu, Carr, Wilcox and
+ * Warburton, "Acceleration of the IMEX Non-hydrostatic Unified Model of the
+ * Atmosphere (NUMA) on manycore processors", for the compressible Euler
+ * equations in the non-conservative set Set2NC (Sec. 3.1) on hexahedral
+ * Legendre-Gauss-Lobatto (LGL) spectral elements with continuous Galerkin
+ * direct stiffness summation (Sec. 4, Sec. 5.3).
+ *
+ * Domain: an axis-aligned box, x and y periodic, rigid bottom and top
+ * (w = 0 imposed strongly on the bottom and top nodes).  Background:
+ * hydrostatic and neutral with constant theta0 (isentropic).
+ *
+ * State contract (every entry point that takes a state):
+ *   - a DEVICE pointer owned by the caller (e.g. a torch tensor on cuda:0),
+ *     5*nz*ny*nx contiguous doubles, structure of arrays [var][k][j][i],
+ *     i fastest, variables (rho', u, v, w, theta') in that order;
+ *   - nx = nex*N and ny = ney*N unique nodes (node i = nx is node 0, x and y
+ *     are periodic), nz = nez*N + 1 levels; node (i, j, k) sits at the LGL
+ *     point of its elements;
+ *   - w must be 0 on levels 0 and nz-1.
+ *
+ * All GPU work is enqueued on the stream given to numa_setup; calls are
+ * asynchronous except numa_check and numa_destroy, which synchronise.
+ * A context serves one host thread at a time; the library has no global state.
+ *
+ * Every function returns 0 (NUMA_OK) or a negative error code; the message of
+ * the last error on a context is returned by numa_last_error.
+ */
+#ifndef NUMA_H
+#define NUMA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NUMA_OK 0
+#define NUMA_E_ARG (-1)           /* null pointer, size <= 0, N outside 1..8, bad zface */
+#define NUMA_E_NOT_FACTORED (-2)  /* step or solve before numa_factor_columns           */
+#define NUMA_E_DT_MISMATCH (-3)   /* dt differs (bitwise) from the factored dt          */
+#define NUMA_E_HIP (-4)           /* HIP runtime error; text in numa_last_error         */
+#define NUMA_E_NOMEM (-5)         /* device allocation failed                           */
+#define NUMA_E_NONFINITE (-6)     /* a step produced NaN or Inf (reported by numa_check) */
+#define NUMA_E_NOT_CONVERGED (-7) /* reserved for an iterative 3D-IMEX solve            */
+#define NUMA_E_UNSUPPORTED (-8)   /* feature or size not supported by this build        */
+
+typedef struct numa_ctx numa_ctx; /* opaque; owns all device memory except states */
+
+typedef struct {
+    double lx, ly, lz;            /* box extents [m], > 0                              */
+    int32_t nex, ney, nez;        /* elements per axis, >= 1                           */
+    const double *zface;          /* optional HOST array of nez+1 strictly increasing
+                                     heights from 0 to lz; NULL = uniform             */
+} numa_grid;
+
+typedef struct {
+    double theta0;                /* background potential temperature [K] (constant)  */
+    double p00;                   /* reference pressure of the equation of state [Pa] */
+    double cp, rgas;              /* specific heat at constant pressure, gas constant */
+    double grav;                  /* gravitational acceleration [m/s^2]               */
+} numa_background;
+
+typedef struct {
+    int64_t nx, ny, nz;           /* unique-node grid                                 */
+    int64_t ncol;                 /* vertical columns (nx*ny)                         */
+    int64_t factor_bytes;         /* device bytes of the stored column factors        */
+    int64_t scratch_bytes;        /* device bytes of the stage buffers                */
+    int64_t step_bytes;           /* algorithmic HBM bytes moved per HEVI step        */
+    int32_t order;                /* LGL order N                                      */
+    int32_t factored;             /* 1 once numa_factor_columns succeeded             */
+    double dt_factored;           /* dt of the stored factors                         */
+} numa_info;
+
+/*
+ * Set up a context: LGL nodes and differentiation matrix of order N
+ * (the sD operator of Alg. 1-2), the direct-stiffness-summed 1D derivative
+ * operators along x, y and z (Sec. 5.3), and the background profiles rho0,
+ * P0 = EOS(rho0, theta0), G0 = gamma P0/rho0, H0 = gamma P0/theta0
+ * (Sec. 3.1, background split and linearised pressure, Eq. (13)); reference
+ * fields are computed once at start-up as in Sec. 5.1.
+ * g, bg: host pointers, read during the call only.  order: N in 1..8.
+ * hip_stream: a hipStream_t (NULL = the null stream).  *out receives the
+ * context.  Errors: NUMA_E_ARG, NUMA_E_UNSUPPORTED, NUMA_E_NOMEM, NUMA_E_HIP.
+ */
+int numa_setup(const numa_grid *g, int32_t order, const numa_background *bg,
+               void *hip_stream, numa_ctx **out);
+
+/* shape[4] (host) = {5, nz, ny, nx}.  Errors: NUMA_E_ARG. */
+int numa_state_shape(const numa_ctx *c, int64_t shape[4]);
+
+/* Sizes and byte counts of the context (host struct).  Errors: NUMA_E_ARG. */
+int numa_get_info(const numa_ctx *c, numa_info *info);
+
+/* Rebind the context to another stream (hipStream_t; NULL = null stream). */
+int numa_set_stream(numa_ctx *c, void *hip_stream);
+
+/*
+ * Build and LU-factor, once per time-step size, the matrix of every vertical
+ * column of the Schur-complement system of the implicit stages (Sec. 3.1,
+ * Eqs. (14)-(17), restricted to the vertical; Sec. 5.4: block-diagonal by
+ * column, factored once and stored), at lambda = (1 - 1/sqrt(2)) dt, the
+ * diagonal of the ARK2 implicit tableau (Table 1).  Banded LU without
+ * pivoting, half-bandwidth 2N (Alg. 9); the factors stay on the device, one
+ * set per column.  dt > 0.  Errors: NUMA_E_ARG, NUMA_E_HIP (a zero or
+ * non-finite pivot is reported by numa_check as NUMA_E_NONFINITE).
+ */
+int numa_factor_columns(numa_ctx *c, double dt);
+
+/*
+ * Advance state (device, see the state contract) in place by nsteps ARK2
+ * HEVI steps of size dt (Sec. 2: HEVI splitting Eq. (4) and the ARK stages
+ * of Sec. 2.2 in their q~ predictor-corrector form; Table 1).  Each step
+ * evaluates the explicit Set2NC right-hand side with DSS three times and
+ * solves the vertical Schur system column by column twice with the stored
+ * factors.  dt must equal the factored dt bitwise.  nsteps >= 0.
+ * Asynchronous; non-finite results are reported by numa_check.
+ * Errors: NUMA_E_ARG, NUMA_E_NOT_FACTORED, NUMA_E_DT_MISMATCH, NUMA_E_HIP.
+ */
+int numa_hevi_step(numa_ctx *c, double *state, double dt, int32_t nsteps);
+
+/*
+ * Same as numa_hevi_step, with a HIP event recorded around every kernel of
+ * the step on the context's stream; synchronises at the end.  ms_out (host,
+ * 5 doubles) receives the average duration in milliseconds of each of the
+ * five kernels of a step over the nsteps steps, in launch order: explicit
+ * right-hand side of stage 1, column solve of stage 2, right-hand side of
+ * stage 2, column solve of stage 3, right-hand side of stage 3 with the
+ * final ARK combination.  nsteps >= 1.  Errors: as numa_hevi_step.
+ */
+int numa_profile_steps(numa_ctx *c, double *state, double dt, int32_t nsteps, double *ms_out);
+
+/*
+ * rhs_out = R(state): the explicit right-hand side of Set2NC in perturbation
+ * form (Sec. 3.1) with the continuity equation in divergence form,
+ * element-local strong-form LGL derivatives (Alg. 2) and DSS (Sec. 5.3);
+ * R_w = 0 on the bottom and top levels.  state, rhs_out: device arrays of
+ * the state contract; they must not overlap.  Asynchronous.
+ * Errors: NUMA_E_ARG, NUMA_E_HIP.
+ */
+int numa_rhs(numa_ctx *c, const double *state, double *rhs_out);
+
+/*
+ * x = (I - lambda L_V)^{-1} y with the stored factors: the direct column
+ * solve of the implicit stage (Sec. 5.4) through the Schur complement for
+ * the pressure (Eqs. (16)-(17) in 1D) followed by the extraction of w and
+ * rho' (Sec. 5).  u, v and theta' pass through.  y, x: device arrays of the
+ * state contract (w = 0 on the walls of y); they must not overlap.
+ * Asynchronous.  Errors: NUMA_E_ARG, NUMA_E_NOT_FACTORED, NUMA_E_HIP.
+ */
+int numa_solve_columns(numa_ctx *c, const double *y, double *x);
+
+/*
+ * 3D-IMEX step with an iterative Schur solve (Sec. 5.5).  Not part of this
+ * build: always returns NUMA_E_UNSUPPORTED.
+ */
+int numa_imex3d_step(numa_ctx *c, double *state, double dt, double tol, int32_t *iters_out);
+
+/*
+ * Host-only helpers (no GPU needed): the operators numa_setup builds.
+ * numa_lgl_basis: LGL nodes xi[order+1] on [-1, 1] and the differentiation
+ * matrix D[(order+1)^2] (row-major, D[i*(order+1)+j] = l_j'(xi_i)), the sD
+ * operator of Alg. 1-2.  numa_line_operators: the direct-stiffness-summed
+ * 1D derivative operators (Sec. 5.3) on grid g: wxy[2*order*(2*order+1)]
+ * holds, for x then y and for each local index a in 0..order-1, the
+ * coefficients of the 2*order+1 nodes starting order nodes before the
+ * node's element; dzb[nz*(2*order+1)] holds, for each level k, the
+ * coefficients of levels k-order .. k+order.  Caller-owned host arrays.
+ * Errors: NUMA_E_ARG.
+ */
+int numa_lgl_basis(int32_t order, double *xi, double *D);
+int numa_line_operators(const numa_grid *g, int32_t order, double *wxy, double *dzb);
+
+/* Synchronise the stream; NUMA_E_NONFINITE if a step or factorisation
+ * produced NaN/Inf since the last check (the flag is then cleared). */
+int numa_check(numa_ctx *c);
+
+/* Synchronise and free every device allocation of the context.  NULL-safe. */
+int numa_destroy(numa_ctx *c);
+
+/* Text of the last error on c (per context; valid until the next call on c).
+ * numa_last_error(NULL) returns the last numa_setup failure of this thread. */
+const char *numa_last_error(const numa_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NUMA_H */

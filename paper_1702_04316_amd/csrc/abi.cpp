@@ -1,0 +1,348 @@
+// C ABI of the HEVI library: argument validation, context lifetime, device
+// memory, and the stage schedule (kernels in kernels.hip).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "numa_internal.h"
+
+namespace {
+
+thread_local std::string g_setup_error;
+
+int fail(numa_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    else g_setup_error = msg;
+    return code;
+}
+
+int hip_fail(numa_ctx *c, hipError_t e, const char *where)
+{
+    std::string m = std::string(where) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+    return fail(c, e == hipErrorOutOfMemory ? NUMA_E_NOMEM : NUMA_E_HIP, m);
+}
+
+void free_ctx(numa_ctx *c)
+{
+    if (!c) return;
+    if (c->lev_block) (void)hipFree(c->lev_block);
+    if (c->fac) (void)hipFree(c->fac);
+    if (c->work) (void)hipFree(c->work);
+    if (c->flag) (void)hipFree(c->flag);
+    delete c;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int64_t step_bytes_model(const numa_ctx *c)
+{
+    // Field passes per step of the fused schedule (reads + writes of whole
+    // unique-node fields): K1 5+5, K2 5+2, K3 12+10, K4 9+2, K5 10+5 = 65,
+    // plus two reads of the column factors.
+    const int64_t fields = 65;
+    const int64_t fac = c->ncol * c->nz * (4 * c->N + 1) * int64_t(sizeof(double));
+    return fields * c->np * int64_t(sizeof(double)) + 2 * fac;
+}
+
+}  // namespace
+
+extern "C" {
+
+int numa_setup(const numa_grid *g, int32_t order, const numa_background *bg, void *hip_stream, numa_ctx **out)
+{
+    g_setup_error.clear();
+    if (!out) return fail(nullptr, NUMA_E_ARG, "numa_setup: out is NULL");
+    *out = nullptr;
+    if (!g || !bg) return fail(nullptr, NUMA_E_ARG, "numa_setup: grid or background is NULL");
+    if (order < 1 || order > 15) return fail(nullptr, NUMA_E_ARG, "numa_setup: order must be in 1..15");
+    if (order > numa::kMaxOrder)
+        return fail(nullptr, NUMA_E_UNSUPPORTED, "numa_setup: orders above 8 are not built");
+    if (!finite_pos(g->lx) || !finite_pos(g->ly) || !finite_pos(g->lz))
+        return fail(nullptr, NUMA_E_ARG, "numa_setup: box extents must be finite and > 0");
+    if (g->nex < 1 || g->ney < 1 || g->nez < 1)
+        return fail(nullptr, NUMA_E_ARG, "numa_setup: element counts must be >= 1");
+    const int64_t nx = int64_t(g->nex) * order, ny = int64_t(g->ney) * order, nz = int64_t(g->nez) * order + 1;
+    if (nx > (1 << 30) || ny > (1 << 30) || nx * ny > (int64_t(1) << 40))
+        return fail(nullptr, NUMA_E_ARG, "numa_setup: grid too large");
+    if (g->zface) {
+        if (g->zface[0] != 0.0 || !(std::fabs(g->zface[g->nez] - g->lz) <= 1e-12 * g->lz))
+            return fail(nullptr, NUMA_E_ARG, "numa_setup: zface must run from 0 to lz");
+        for (int e = 0; e < g->nez; ++e)
+            if (!(g->zface[e + 1] > g->zface[e]) || !std::isfinite(g->zface[e + 1]))
+                return fail(nullptr, NUMA_E_ARG, "numa_setup: zface must be strictly increasing");
+    }
+    if (!finite_pos(bg->theta0) || !finite_pos(bg->p00) || !finite_pos(bg->rgas) || !finite_pos(bg->cp) ||
+        !(bg->cp > bg->rgas) || !std::isfinite(bg->grav) || bg->grav < 0.0)
+        return fail(nullptr, NUMA_E_ARG, "numa_setup: invalid background constants");
+    if (!(1.0 - bg->grav * g->lz / (bg->cp * bg->theta0) > 0.0))
+        return fail(nullptr, NUMA_E_ARG, "numa_setup: box top above the isentropic atmosphere's top");
+    if (nz > 64)
+        return fail(nullptr, NUMA_E_UNSUPPORTED, "numa_setup: columns longer than 64 levels are not built");
+    if (nx * ny * nz * int64_t(sizeof(double)) >= (int64_t(1) << 32))
+        return fail(nullptr, NUMA_E_UNSUPPORTED, "numa_setup: a field above 4 GiB is not supported");
+
+    numa_ctx *c = new (std::nothrow) numa_ctx();
+    if (!c) return fail(nullptr, NUMA_E_NOMEM, "numa_setup: host allocation failed");
+    c->N = order;
+    c->nex = g->nex;
+    c->ney = g->ney;
+    c->nez = g->nez;
+    c->nx = nx;
+    c->ny = ny;
+    c->nz = nz;
+    c->ncol = nx * ny;
+    c->plane = nx * ny;
+    c->np = nx * ny * nz;
+    c->lx = g->lx;
+    c->ly = g->ly;
+    c->lz = g->lz;
+    c->cp = bg->cp;
+    c->eos.theta0 = bg->theta0;
+    c->eos.p00 = bg->p00;
+    c->eos.rgas = bg->rgas;
+    c->eos.gamma = bg->cp / (bg->cp - bg->rgas);
+    c->eos.grav = bg->grav;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+
+    numa::build_ops(c, g->zface);
+
+    const int N = order, ns = 2 * N + 1;
+    const size_t n_lev = size_t(4 * nz + nz * ns + 3 * g->nez + 2 * N * ns + (N + 1) * (N + 1));
+    hipError_t e = hipMalloc(&c->lev_block, n_lev * sizeof(double));
+    if (e != hipSuccess) {
+        int rc = hip_fail(nullptr, e, "numa_setup: hipMalloc(levels)");
+        free_ctx(c);
+        return rc;
+    }
+    double *p = static_cast<double *>(c->lev_block);
+    c->lev.rho0 = p; p += nz;
+    c->lev.P0 = p; p += nz;
+    c->lev.G0 = p; p += nz;
+    c->lev.H0 = p; p += nz;
+    c->lev.dzb = p; p += nz * ns;
+    c->lev.zsc = p; p += 3 * g->nez;
+    c->lev.wxy = p; p += 2 * N * ns;
+    c->lev.D = p;
+
+    const size_t fac_n = size_t(c->ncol) * size_t(nz) * size_t(4 * N + 1);
+    const size_t work_n = size_t(19) * size_t(c->np);
+    e = hipMalloc(&c->fac, fac_n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&c->work, work_n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&c->flag, sizeof(int));
+    if (e != hipSuccess) {
+        int rc = hip_fail(nullptr, e, "numa_setup: hipMalloc(factors/work)");
+        free_ctx(c);
+        return rc;
+    }
+    struct Up { double *dst; const std::vector<double> *src; };
+    const Up ups[] = {{c->lev.rho0, &c->ops.rho0}, {c->lev.dzb, &c->ops.dzb}, {c->lev.zsc, &c->ops.zsc},
+                      {c->lev.wxy, &c->ops.wxy}, {c->lev.D, &c->ops.D}};
+    for (const Up &u : ups) {
+        e = hipMemcpyAsync(u.dst, u.src->data(), u.src->size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess) break;
+    }
+    if (e == hipSuccess) e = hipMemsetAsync(c->flag, 0, sizeof(int), c->stream);
+    if (e == hipSuccess) e = numa::launch_background(c);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        int rc = hip_fail(nullptr, e, "numa_setup: upload");
+        free_ctx(c);
+        return rc;
+    }
+    *out = c;
+    return NUMA_OK;
+}
+
+int numa_state_shape(const numa_ctx *c, int64_t shape[4])
+{
+    if (!c || !shape) return NUMA_E_ARG;
+    shape[0] = 5;
+    shape[1] = c->nz;
+    shape[2] = c->ny;
+    shape[3] = c->nx;
+    return NUMA_OK;
+}
+
+int numa_get_info(const numa_ctx *c, numa_info *info)
+{
+    if (!c || !info) return NUMA_E_ARG;
+    info->nx = c->nx;
+    info->ny = c->ny;
+    info->nz = c->nz;
+    info->ncol = c->ncol;
+    info->factor_bytes = c->ncol * c->nz * (4 * c->N + 1) * int64_t(sizeof(double));
+    info->scratch_bytes = 19 * c->np * int64_t(sizeof(double));
+    info->step_bytes = step_bytes_model(c);
+    info->order = c->N;
+    info->factored = c->factored;
+    info->dt_factored = c->dt_factored;
+    return NUMA_OK;
+}
+
+int numa_set_stream(numa_ctx *c, void *hip_stream)
+{
+    if (!c) return NUMA_E_ARG;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    return NUMA_OK;
+}
+
+int numa_factor_columns(numa_ctx *c, double dt)
+{
+    if (!c) return NUMA_E_ARG;
+    if (!finite_pos(dt)) return fail(c, NUMA_E_ARG, "numa_factor_columns: dt must be finite and > 0");
+    const double lambda = (1.0 - 1.0 / std::sqrt(2.0)) * dt;
+    c->factored = 0;
+    hipError_t e = numa::launch_factor(c, lambda);
+    if (e != hipSuccess) return hip_fail(c, e, "numa_factor_columns");
+    c->factored = 1;
+    c->dt_factored = dt;
+    c->lambda = lambda;
+    return NUMA_OK;
+}
+
+int numa_hevi_step(numa_ctx *c, double *state, double dt, int32_t nsteps)
+{
+    if (!c) return NUMA_E_ARG;
+    if (!state || nsteps < 0) return fail(c, NUMA_E_ARG, "numa_hevi_step: null state or nsteps < 0");
+    if (!c->factored) return fail(c, NUMA_E_NOT_FACTORED, "numa_hevi_step: call numa_factor_columns first");
+    if (std::memcmp(&dt, &c->dt_factored, sizeof(double)) != 0)
+        return fail(c, NUMA_E_DT_MISMATCH, "numa_hevi_step: dt differs from the factored dt");
+    for (int32_t s = 0; s < nsteps; ++s) {
+        hipError_t e = numa::launch_hevi_step(c, state, dt);
+        if (e != hipSuccess) return hip_fail(c, e, "numa_hevi_step");
+    }
+    return NUMA_OK;
+}
+
+int numa_profile_steps(numa_ctx *c, double *state, double dt, int32_t nsteps, double *ms_out)
+{
+    if (!c) return NUMA_E_ARG;
+    if (!state || nsteps < 1 || nsteps > 100000 || !ms_out)
+        return fail(c, NUMA_E_ARG, "numa_profile_steps: bad arguments");
+    if (!c->factored) return fail(c, NUMA_E_NOT_FACTORED, "numa_profile_steps: call numa_factor_columns first");
+    if (std::memcmp(&dt, &c->dt_factored, sizeof(double)) != 0)
+        return fail(c, NUMA_E_DT_MISMATCH, "numa_profile_steps: dt differs from the factored dt");
+    // 6 events per step around its 5 kernels
+    std::vector<hipEvent_t> ev(size_t(6) * nsteps, nullptr);
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+    for (int32_t s = 0; s < nsteps && e == hipSuccess; ++s) e = numa::launch_hevi_step(c, state, dt, &ev[size_t(6) * s]);
+    if (e == hipSuccess) e = hipEventSynchronize(ev.back());
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int32_t s = 0; s < nsteps && e == hipSuccess; ++s)
+        for (int i = 0; i < 5 && e == hipSuccess; ++i) {
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, ev[size_t(6) * s + i], ev[size_t(6) * s + i + 1]);
+            acc[i] += ms;
+        }
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (e != hipSuccess) return hip_fail(c, e, "numa_profile_steps");
+    for (int i = 0; i < 5; ++i) ms_out[i] = acc[i] / nsteps;
+    return NUMA_OK;
+}
+
+int numa_rhs(numa_ctx *c, const double *state, double *rhs_out)
+{
+    if (!c) return NUMA_E_ARG;
+    if (!state || !rhs_out) return fail(c, NUMA_E_ARG, "numa_rhs: null pointer");
+    hipError_t e = numa::launch_rhs_plain(c, state, rhs_out);
+    if (e != hipSuccess) return hip_fail(c, e, "numa_rhs");
+    return NUMA_OK;
+}
+
+int numa_solve_columns(numa_ctx *c, const double *y, double *x)
+{
+    if (!c) return NUMA_E_ARG;
+    if (!y || !x) return fail(c, NUMA_E_ARG, "numa_solve_columns: null pointer");
+    if (!c->factored) return fail(c, NUMA_E_NOT_FACTORED, "numa_solve_columns: call numa_factor_columns first");
+    hipError_t e = numa::launch_solve_plain(c, y, x);
+    if (e != hipSuccess) return hip_fail(c, e, "numa_solve_columns");
+    return NUMA_OK;
+}
+
+int numa_imex3d_step(numa_ctx *c, double *state, double dt, double tol, int32_t *iters_out)
+{
+    (void)state; (void)dt; (void)tol;
+    if (iters_out) *iters_out = 0;
+    if (!c) return NUMA_E_ARG;
+    return fail(c, NUMA_E_UNSUPPORTED, "numa_imex3d_step: 3D-IMEX is not part of this build");
+}
+
+int numa_lgl_basis(int32_t order, double *xi, double *D)
+{
+    if (order < 1 || order > 15 || !xi || !D) return NUMA_E_ARG;
+    std::vector<double> x, d;
+    numa::lgl_nodes(order, x);
+    numa::lgl_dmat(order, x, d);
+    std::memcpy(xi, x.data(), x.size() * sizeof(double));
+    std::memcpy(D, d.data(), d.size() * sizeof(double));
+    return NUMA_OK;
+}
+
+int numa_line_operators(const numa_grid *g, int32_t order, double *wxy, double *dzb)
+{
+    if (!g || !wxy || !dzb || order < 1 || order > 15) return NUMA_E_ARG;
+    if (!finite_pos(g->lx) || !finite_pos(g->ly) || !finite_pos(g->lz) || g->nex < 1 || g->ney < 1 || g->nez < 1)
+        return NUMA_E_ARG;
+    if (g->zface) {
+        if (g->zface[0] != 0.0 || !(std::fabs(g->zface[g->nez] - g->lz) <= 1e-12 * g->lz)) return NUMA_E_ARG;
+        for (int e = 0; e < g->nez; ++e)
+            if (!(g->zface[e + 1] > g->zface[e])) return NUMA_E_ARG;
+    }
+    numa_ctx c;
+    c.N = order;
+    c.nex = g->nex;
+    c.ney = g->ney;
+    c.nez = g->nez;
+    c.nx = int64_t(g->nex) * order;
+    c.ny = int64_t(g->ney) * order;
+    c.nz = int64_t(g->nez) * order + 1;
+    c.lx = g->lx;
+    c.ly = g->ly;
+    c.lz = g->lz;
+    c.cp = 1004.67;  // background is not used by the operators; any valid constants
+    c.eos = {300.0, 1.0e5, 287.17, 1.4, 0.0};
+    numa::build_ops(&c, g->zface);
+    std::memcpy(wxy, c.ops.wxy.data(), c.ops.wxy.size() * sizeof(double));
+    std::memcpy(dzb, c.ops.dzb.data(), c.ops.dzb.size() * sizeof(double));
+    return NUMA_OK;
+}
+
+int numa_check(numa_ctx *c)
+{
+    if (!c) return NUMA_E_ARG;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "numa_check: synchronize");
+    int flag = 0;
+    e = hipMemcpy(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(c, e, "numa_check: read flag");
+    if (flag) {
+        e = hipMemset(c->flag, 0, sizeof(int));
+        if (e != hipSuccess) return hip_fail(c, e, "numa_check: clear flag");
+        return fail(c, NUMA_E_NONFINITE, "numa_check: a step or factorisation produced NaN/Inf");
+    }
+    return NUMA_OK;
+}
+
+int numa_destroy(numa_ctx *c)
+{
+    if (!c) return NUMA_OK;
+    (void)hipStreamSynchronize(c->stream);
+    free_ctx(c);
+    return NUMA_OK;
+}
+
+const char *numa_last_error(const numa_ctx *c)
+{
+    if (!c) return g_setup_error.c_str();
+    return c->err.c_str();
+}
+
+}  // extern "C"

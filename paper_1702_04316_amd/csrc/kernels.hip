@@ -1,0 +1,788 @@
+// HIP kernels of the HEVI (1D-IMEX) ARK2 step for gfx950 (MI355X).
+//
+//  k_rhs      explicit Set2NC right-hand side with DSS, fused with the ARK
+//             stage combinations (one pass over the state per evaluation)
+//  k_colsolve Schur-complement column solve with the stored band LU factors,
+//             fused with the stage right-hand side and the extraction
+//  k_factor   assembly and unpivoted band LU of every column's Schur matrix
+//  k_background  P0, G0, H0 per level with the device equation of state
+//
+// Layout: fields are FP64 structure of arrays [var][k][j][i], i fastest, on
+// the unique nodes (x, y periodic).  Column factors are [k][m][col] with
+// col = j*nx + i fastest, so a wavefront of 64 columns loads 512 contiguous
+// bytes per factor entry.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <type_traits>
+
+#include "numa_internal.h"
+
+namespace numa {
+
+// ---------------------------------------------------------------------------
+// Right-hand-side kernel.  A workgroup owns a TX x TY tile of columns
+// (element aligned) and marches upwards through a chunk of vertical
+// elements.  For element ez its TX*TY*N threads compute the N owned levels
+// ez*N + c (c = 0..N-1, c slowest in the thread index, so a wavefront shares
+// c).  The N+1 levels of the element sit in an LDS ring of planes (level k in
+// slot k mod (N+1)); each plane holds the tile plus the halo the DSS line
+// operators need (N nodes below, 1 node above, in x and in y).
+// ---------------------------------------------------------------------------
+template <int N>
+struct Tile;
+//                     TX  TY      threads   LDS (ring of N+1 planes, 6 fields)
+template <> struct Tile<1> { static constexpr int TX = 32, TY = 16; };
+template <> struct Tile<2> { static constexpr int TX = 32, TY = 8; };
+template <> struct Tile<3> { static constexpr int TX = 24, TY = 6; };
+template <> struct Tile<4> { static constexpr int TX = 16, TY = 8; };
+template <> struct Tile<5> { static constexpr int TX = 15, TY = 5; };
+template <> struct Tile<6> { static constexpr int TX = 12, TY = 6; };
+template <> struct Tile<7> { static constexpr int TX = 14, TY = 7; };
+template <> struct Tile<8> { static constexpr int TX = 8, TY = 8; };
+
+template <int N>
+struct RhsGeom {
+    static constexpr int TX = Tile<N>::TX, TY = Tile<N>::TY;
+    static constexpr int NT = TX * TY * N;          // threads
+    static constexpr int LX = TX + N + 1;           // plane incl. halo
+    static constexpr int LY = TY + N + 1;
+    static constexpr int FS = LX * LY;              // one field of one plane
+    static constexpr int NF = 6;                    // rho', u, v, w, theta', P'
+    static constexpr int PS = NF * FS;              // one plane
+    static constexpr int NS = 2 * N + 1;            // x/y stencil width
+    // cross-shaped part of a plane that is loaded: tile rows with the x halo,
+    // plus the y-halo rows of the tile columns
+    static constexpr int NCROSS = TY * LX + TX * (N + 1);
+    static constexpr int NITEM = (N * NCROSS + NT - 1) / NT;  // plane loads per thread
+    static constexpr size_t LDS = size_t(N + 1) * PS * sizeof(double);
+};
+
+// device equation of state: P = p00 (rho R theta / p00)^gamma (Eq. (10))
+__device__ __forceinline__ double eos_pressure(double rho, double theta, const EOS &e)
+{
+    return e.p00 * pow(rho * e.rgas * theta / e.p00, e.gamma);
+}
+
+// P' = EOS(rho0 + rho', theta0 + theta') - P0 evaluated as
+// P0 [((rho theta)/(rho0 theta0))^gamma - 1]: with rho theta - rho0 theta0 =
+// rho0 theta' + theta0 rho' + rho' theta' no two ~1e5 Pa numbers are
+// subtracted, so P' keeps its own relative precision.
+// rho0 theta', theta0 rho' and rho' theta' nearly cancel in a balanced state:
+// each product is split into rounded value + exact error (fma), so their
+// small sum keeps its relative precision (no contraction may touch this).
+__device__ __forceinline__ double pressure_perturbation(double rp, double th, double r0, double P0, const EOS &e)
+{
+#pragma clang fp contract(off)
+    const double t0 = e.theta0;
+    const double p1 = r0 * th, p2 = t0 * rp, p3 = rp * th;
+    const double e1 = __builtin_fma(r0, th, -p1), e2 = __builtin_fma(t0, rp, -p2), e3 = __builtin_fma(rp, th, -p3);
+    const double d = ((p1 + p2) + p3) + ((e1 + e2) + e3);
+    return P0 * expm1(e.gamma * log1p(d / (r0 * t0)));
+}
+
+// Global access as (uniform 64-bit base) + (32-bit per-lane byte offset):
+// compiles to global_load/store with a scalar base address, so a field needs
+// two scalar registers whatever the number of lanes and levels.
+__device__ __forceinline__ double gload(const double *base, unsigned off)
+{
+    return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(base) + off);
+}
+__device__ __forceinline__ void gstore(double *base, unsigned off, double v)
+{
+    *reinterpret_cast<double *>(reinterpret_cast<char *>(base) + off) = v;
+}
+
+struct RhsParams {
+    const double *a[5];     // input fields (rho', u, v, w, theta')
+    const double *b[5];     // increments (HASB): input = a + cb * b; null entries = none
+    double cb;
+    double *out0[5];
+    double *out1[5];
+    const double *e0[5];
+    const double *e1[5];
+    double k01, k02, k11, k12;  // out0 = e0 + k01 e1 + k02 R ; out1 = e0 + k11 e1 + k12 R
+    const double *rho0, *P0, *zsc, *wxy, *D;
+    EOS eos;
+    int nx, ny, nz, nez, zchunk, nchunk, ntx, nty;
+    int *flag;
+};
+
+enum { EPI_R = 0, EPI_TWO = 1, EPI_FINAL = 2 };
+
+// Map the launch index to a tile so that each of the 8 XCDs (which receive
+// workgroups round-robin) works on a contiguous band of tiles and shares the
+// halo rows in its own L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    int q = nb >> 3, r = nb & 7;
+    int x = b & 7, s = b >> 3;
+    return x < r ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
+}
+
+// Stage input of field f at byte offset off (a + cb*b where b exists).
+template <bool HASB>
+__device__ __forceinline__ double stage_input(const RhsParams &p, int f, unsigned off)
+{
+    double v = gload(p.a[f], off);
+    if constexpr (HASB) {
+        if (f == 1 || f == 2 || f == 4) v += p.cb * gload(p.b[f], off);
+    }
+    return v;
+}
+
+template <int N, int EPI, bool HASB>
+__global__ __launch_bounds__(RhsGeom<N>::NT) void k_rhs(RhsParams p)
+{
+    using G = RhsGeom<N>;
+    constexpr int NQ = N + 1, NS = G::NS, TX = G::TX, TY = G::TY, LX = G::LX, FS = G::FS, PS = G::PS;
+    extern __shared__ double ring[];  // [N+1][6][LY][LX]
+    __shared__ double sw[2][N][NS];
+
+    const int tid = threadIdx.x;
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int ntile = p.ntx * p.nty;
+    const int chunk = lb / ntile;
+    const int tt = lb - chunk * ntile;
+    const int tyb = tt / p.ntx, txb = tt - tyb * p.ntx;
+    const int x0 = txb * TX, y0 = tyb * TY;
+    const int nx = p.nx, ny = p.ny;
+    const unsigned pbytes = unsigned(nx) * unsigned(ny) * 8u;
+
+    for (int s = tid; s < 2 * N * NS; s += G::NT) (&sw[0][0][0])[s] = p.wxy[s];
+
+    // plane loads of this thread: which of the N new planes (1..N, 0 = none),
+    // LDS offset in the plane, byte offset in a level plane
+    int it_p[G::NITEM], it_l[G::NITEM];
+    unsigned it_o[G::NITEM];
+#pragma unroll
+    for (int s = 0; s < G::NITEM; ++s) {
+        const int item = tid + s * G::NT;
+        const int pl = item / G::NCROSS, q = item - pl * G::NCROSS;
+        int lx, ly;
+        if (q < TY * LX) {
+            ly = N + q / LX;
+            lx = q % LX;
+        } else {
+            const int r = q - TY * LX, hy = r / TX;
+            lx = N + r % TX;
+            ly = hy < N ? hy : TY + N;
+        }
+        int gi = (x0 - N + lx) % nx;
+        if (gi < 0) gi += nx;
+        int gj = (y0 - N + ly) % ny;
+        if (gj < 0) gj += ny;
+        it_p[s] = item < N * G::NCROSS ? pl + 1 : 0;
+        it_l[s] = ly * LX + lx;
+        it_o[s] = unsigned(gj * nx + gi) * 8u;
+    }
+
+    const int c = tid / (TX * TY);
+    const int txy = tid - c * (TX * TY);
+    const int ty = txy / TX, tx = txy - ty * TX;
+    const int i = x0 + tx, j = y0 + ty;
+    const bool owner = (i < nx) && (j < ny);
+    const unsigned own = unsigned((j % ny) * nx + (i % nx)) * 8u;
+    const int ax = tx % N, ay = ty % N;
+    const int l_own = (ty + N) * LX + (tx + N);
+    const int l_x = (ty + N) * LX + (tx - ax);
+    const int l_y = (ty - ay) * LX + (tx + N);
+    const double *cwx = &sw[0][0][0] + ax * NS;
+    const double *cwy = &sw[1][0][0] + ay * NS;
+    const EOS eos = p.eos;
+
+    // one node of level k (with halo) into its ring slot
+    auto load_item = [&](int s, int k) {
+        const unsigned off = unsigned(k) * pbytes + it_o[s];
+        const double rp = stage_input<HASB>(p, 0, off), u = stage_input<HASB>(p, 1, off);
+        const double v = stage_input<HASB>(p, 2, off), w = stage_input<HASB>(p, 3, off);
+        const double th = stage_input<HASB>(p, 4, off);
+        const double Pp = pressure_perturbation(rp, th, p.rho0[k], p.P0[k], eos);
+        double *d = ring + (k % NQ) * PS + it_l[s];
+        d[0 * FS] = rp;
+        d[1 * FS] = u;
+        d[2 * FS] = v;
+        d[3 * FS] = w;
+        d[4 * FS] = th;
+        d[5 * FS] = Pp;
+    };
+
+    // sum_n D[r][n] g(level ez*N + n) over the own column for the six
+    // z-differentiated quantities rho w, u, v, w, theta', P'
+    auto zsum = [&](int ez, int r, double *out) {
+#pragma unroll
+        for (int f = 0; f < 6; ++f) out[f] = 0.0;
+#pragma unroll
+        for (int n = 0; n < NQ; ++n) {
+            const int k = ez * N + n;
+            const double *q = ring + (k % NQ) * PS + l_own;
+            const double d = p.D[r * NQ + n];
+            out[0] += d * ((p.rho0[k] + q[0]) * q[3 * FS]);
+            out[1] += d * q[1 * FS];
+            out[2] += d * q[2 * FS];
+            out[3] += d * q[3 * FS];
+            out[4] += d * q[4 * FS];
+            out[5] += d * q[5 * FS];
+        }
+    };
+
+    // tendencies at level k (Set2NC, Sec. 3.1) from the x/y line derivatives
+    // of the plane in the ring and the scaled vertical derivatives dz; then
+    // the stage epilogue
+    auto node = [&](int k, const double *dz) {
+        const double *q = ring + (k % NQ) * PS;
+        const double r0 = p.rho0[k];
+        const double rp = q[l_own], u = q[FS + l_own], v = q[2 * FS + l_own], w = q[3 * FS + l_own];
+        const double ir = 1.0 / (r0 + rp);
+        double dx[6] = {0, 0, 0, 0, 0, 0}, dy[6] = {0, 0, 0, 0, 0, 0};
+        // not unrolled: unrolled, the scheduler hoists all 12*NS LDS reads
+        // and runs out of registers
+#pragma unroll 1
+        for (int m = 0; m < NS; ++m) {
+            const double cx = cwx[m], cy = cwy[m];
+            const double *qx = q + l_x + m;
+            const double *qy = q + l_y + m * LX;
+            dx[0] += cx * ((r0 + qx[0]) * qx[FS]);
+            dy[0] += cy * ((r0 + qy[0]) * qy[2 * FS]);
+#pragma unroll
+            for (int f = 1; f < 6; ++f) {
+                dx[f] += cx * qx[f * FS];
+                dy[f] += cy * qy[f * FS];
+            }
+        }
+        double R[5];
+        R[0] = -(dx[0] + dy[0] + dz[0]);
+        R[1] = -(u * dx[1] + v * dy[1] + w * dz[1] + dx[5] * ir);
+        R[2] = -(u * dx[2] + v * dy[2] + w * dz[2] + dy[5] * ir);
+        R[3] = -(u * dx[3] + v * dy[3] + w * dz[3] + dz[5] * ir + eos.grav * rp * ir);
+        R[4] = -(u * dx[4] + v * dy[4] + w * dz[4]);
+        if (k == 0 || k == p.nz - 1) R[3] = 0.0;
+        if (!owner) return;
+        const unsigned off = unsigned(k) * pbytes + own;
+        if constexpr (EPI == EPI_R) {
+#pragma unroll
+            for (int f = 0; f < 5; ++f) gstore(p.out0[f], off, R[f]);
+        } else if constexpr (EPI == EPI_TWO) {
+#pragma unroll
+            for (int f = 0; f < 5; ++f) {
+                const double e0 = gload(p.e0[f], off), e1 = gload(p.e1[f], off);
+                gstore(p.out0[f], off, e0 + p.k01 * e1 + p.k02 * R[f]);
+                gstore(p.out1[f], off, e0 + p.k11 * e1 + p.k12 * R[f]);
+            }
+        } else {
+            bool bad = false;
+#pragma unroll
+            for (int f = 0; f < 5; ++f) {
+                const double v2 = gload(p.e0[f], off) + p.k02 * R[f];
+                bad |= !isfinite(v2);
+                gstore(p.out0[f], off, v2);
+            }
+            if (bad) *p.flag = 1;
+        }
+    };
+
+    const int ez0 = chunk * p.zchunk;
+    const int ez1 = min(p.nez, ez0 + p.zchunk);
+    const double *zs = p.zsc;  // [0,nez): 2/h ; [nez,2nez): bottom factor ; [2nez,3nez): top factor
+
+    // prologue: level ez0*N into the ring (the items of the first new plane
+    // cover one whole plane); the c = 0 threads take the contribution of the
+    // element below to the interface at ez0*N from their own column
+    double zpart[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < G::NITEM; ++s)
+        if (it_p[s] == 1) load_item(s, ez0 * N);
+    if (c == 0 && ez0 > 0) {
+        const int eb = ez0 - 1;
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+        for (int n = 0; n < NQ; ++n) {
+            const int k = eb * N + n;
+            const unsigned off = unsigned(k) * pbytes + own;
+            const double rp = stage_input<HASB>(p, 0, off), u = stage_input<HASB>(p, 1, off);
+            const double v = stage_input<HASB>(p, 2, off), w = stage_input<HASB>(p, 3, off);
+            const double th = stage_input<HASB>(p, 4, off);
+            const double rho = p.rho0[k] + rp;
+            const double Pp = pressure_perturbation(rp, th, p.rho0[k], p.P0[k], eos);
+            const double d = p.D[N * NQ + n];
+            acc[0] += d * (rho * w);
+            acc[1] += d * u;
+            acc[2] += d * v;
+            acc[3] += d * w;
+            acc[4] += d * th;
+            acc[5] += d * Pp;
+        }
+        const double st = zs[2 * p.nez + eb];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) zpart[f] = st * acc[f];
+    }
+
+    for (int ez = ez0; ez < ez1; ++ez) {
+        __syncthreads();  // the slots about to be overwritten are no longer read
+#pragma unroll
+        for (int s = 0; s < G::NITEM; ++s)
+            if (it_p[s] > 0) load_item(s, ez * N + it_p[s]);
+        __syncthreads();
+        double dz[6], sum[6];
+        zsum(ez, c, sum);
+        const double sc = (c == 0) ? zs[p.nez + ez] : zs[ez];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) dz[f] = (c == 0 ? zpart[f] : 0.0) + sc * sum[f];
+        node(ez * N + c, dz);
+        if (c == 0) {
+            // this element's share of the interface (or top node) above
+            zsum(ez, N, sum);
+            const double st = zs[2 * p.nez + ez];
+#pragma unroll
+            for (int f = 0; f < 6; ++f) zpart[f] = st * sum[f];
+        }
+    }
+    // top node of the column: one-sided from the top element
+    if (ez1 == p.nez && c == 0) node(p.nez * N, zpart);
+}
+
+// ---------------------------------------------------------------------------
+// Column solve.  One lane per column, 64 columns per workgroup; the column's
+// pressure and rho0*w live in LDS ([level][lane], conflict free).
+// ---------------------------------------------------------------------------
+struct SolveParams {
+    // q~_e for rho', w, theta': sum_t c_t * ptr_t (nt terms)
+    const double *er[3], *ew[3], *et[3];
+    double cr[3], cw[3], ct[3];
+    int nr, nw, nt;
+    // outputs: rho' = sum_t cbr_t br_t - lambda Dz(rho0 w~);  w = w~ + sum_t cbw_t bw_t
+    const double *br[2], *bw[2];
+    double cbr[2], cbw[2];
+    int nbr, nbw;
+    double *out_r, *out_w;
+    const double *fac;
+    const double *rho0, *G0, *H0, *dzb;
+    double lambda, grav;
+    int nz;
+    long ncol;
+};
+
+template <int N>
+__global__ __launch_bounds__(64) void k_colsolve(SolveParams p)
+{
+    extern __shared__ double smem[];
+    constexpr int NS = 2 * N + 1, NB = 4 * N + 1, HB = 2 * N;
+    const int lane = threadIdx.x;
+    const long col = (long)blockIdx.x * 64 + lane;
+    const bool act = col < p.ncol;
+    const long cc = act ? col : 0;
+    const int M = p.nz;
+    double *P = smem;            // [M][64]
+    double *RW = smem + M * 64;  // [M][64]
+    const long ncol = p.ncol;
+    const double lam = p.lambda, g = p.grav;
+
+    // A: explicit Schur right-hand-side pieces
+    for (int k = 0; k < M; ++k) {
+        const long n = (long)k * ncol + cc;
+        double re = 0.0, we = 0.0, te = 0.0;
+        for (int t = 0; t < p.nr; ++t) re += p.cr[t] * p.er[t][n];
+        for (int t = 0; t < p.nw; ++t) we += p.cw[t] * p.ew[t][n];
+        for (int t = 0; t < p.nt; ++t) te += p.ct[t] * p.et[t][n];
+        const double r0 = p.rho0[k], G0 = p.G0[k], H0 = p.H0[k];
+        const bool wall = (k == 0) || (k == M - 1);
+        double wa = wall ? 0.0 : we + lam * g * H0 * te / (G0 * r0);
+        P[k * 64 + lane] = G0 * re + H0 * te;
+        RW[k * 64 + lane] = r0 * wa;
+    }
+    __syncthreads();
+    // B: rhs = P_e - lambda G0 Dz(rho0 w_a); forward substitution (unit L)
+    for (int k = 0; k < M; ++k) {
+        const double *b = p.dzb + (long)k * NS;
+        double d = 0.0;
+#pragma unroll
+        for (int m = 0; m < NS; ++m) {
+            int kk = k - N + m;
+            if (kk >= 0 && kk < M) d += b[m] * RW[kk * 64 + lane];
+        }
+        double y = P[k * 64 + lane] - lam * p.G0[k] * d;
+        const double *f = p.fac + (long)k * NB * ncol + cc;
+#pragma unroll
+        for (int dd = 1; dd <= HB; ++dd) {
+            if (k - dd >= 0) y -= f[(long)(HB - dd) * ncol] * P[(k - dd) * 64 + lane];
+        }
+        P[k * 64 + lane] = y;
+    }
+    // C: backward substitution (U, reciprocal diagonal stored)
+    for (int k = M - 1; k >= 0; --k) {
+        const double *f = p.fac + (long)k * NB * ncol + cc;
+        double x = P[k * 64 + lane];
+#pragma unroll
+        for (int dd = 1; dd <= HB; ++dd) {
+            if (k + dd < M) x -= f[(long)(HB + dd) * ncol] * P[(k + dd) * 64 + lane];
+        }
+        P[k * 64 + lane] = x * f[(long)HB * ncol];
+    }
+    // D: w~ = B (w_a - lambda (Dz P / rho0 + g P /(G0 rho0)))
+    for (int k = 0; k < M; ++k) {
+        const double *b = p.dzb + (long)k * NS;
+        double d = 0.0;
+#pragma unroll
+        for (int m = 0; m < NS; ++m) {
+            int kk = k - N + m;
+            if (kk >= 0 && kk < M) d += b[m] * P[kk * 64 + lane];
+        }
+        const double r0 = p.rho0[k];
+        const bool wall = (k == 0) || (k == M - 1);
+        const double wa = RW[k * 64 + lane] / r0;
+        const double wt = wall ? 0.0 : wa - lam * (d / r0 + g * P[k * 64 + lane] / (p.G0[k] * r0));
+        RW[k * 64 + lane] = r0 * wt;
+        const long n = (long)k * ncol + cc;
+        double wout = wt;
+        for (int t = 0; t < p.nbw; ++t) wout += p.cbw[t] * p.bw[t][n];
+        if (act) p.out_w[n] = wout;
+    }
+    // E: rho' = q_e,rho - lambda Dz(rho0 w~)
+    for (int k = 0; k < M; ++k) {
+        const double *b = p.dzb + (long)k * NS;
+        double d = 0.0;
+#pragma unroll
+        for (int m = 0; m < NS; ++m) {
+            int kk = k - N + m;
+            if (kk >= 0 && kk < M) d += b[m] * RW[kk * 64 + lane];
+        }
+        const long n = (long)k * ncol + cc;
+        double r = 0.0;
+        for (int t = 0; t < p.nbr; ++t) r += p.cbr[t] * p.br[t][n];
+        if (act) p.out_r[n] = r - lam * d;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Column factorisation: S = I - lambda^2 G0 Dz rho0 B (Dz/rho0 + g/(G0 rho0))
+// = I - lambda^2 G0 Dz B (Dz + g/G0), assembled as a band of half-width 2N,
+// then Doolittle LU without pivoting (Alg. 9), one lane per column.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(64) void k_factor(const double *__restrict__ dzb, const double *__restrict__ G0,
+                                               double lambda, double grav, int M, long ncol, double *fac,
+                                               int *flag)
+{
+    constexpr int NS = 2 * N + 1, NB = 4 * N + 1, HB = 2 * N;
+    const long col = (long)blockIdx.x * 64 + threadIdx.x;
+    if (col >= ncol) return;
+    auto A = [&](int r, int cidx) -> double & { return fac[((long)r * NB + (cidx - r + HB)) * ncol + col]; };
+    const double l2 = lambda * lambda;
+    for (int r = 0; r < M; ++r) {
+        for (int cidx = r - HB; cidx <= r + HB; ++cidx) {
+            if (cidx < 0 || cidx >= M) {
+                fac[((long)r * NB + (cidx - r + HB)) * ncol + col] = 0.0;
+                continue;
+            }
+            double s = 0.0;
+            int mlo = max(max(r, cidx) - N, 1), mhi = min(min(r, cidx) + N, M - 2);
+            for (int m = mlo; m <= mhi; ++m) {
+                double drm = dzb[(long)r * NS + (m - r + N)];
+                double dmc = dzb[(long)m * NS + (cidx - m + N)];
+                s += drm * (dmc + (m == cidx ? grav / G0[m] : 0.0));
+            }
+            A(r, cidx) = (r == cidx ? 1.0 : 0.0) - l2 * G0[r] * s;
+        }
+    }
+    bool bad = false;
+    for (int k = 0; k < M; ++k) {
+        const double piv = A(k, k);
+        bad |= !(fabs(piv) > 0.0) || !isfinite(piv);
+        const double rp = 1.0 / piv;
+        const int e = min(k + HB, M - 1);
+        for (int i = k + 1; i <= e; ++i) {
+            double l = A(i, k) * rp;
+            A(i, k) = l;
+            for (int jj = k + 1; jj <= e; ++jj) A(i, jj) -= l * A(k, jj);
+        }
+        A(k, k) = rp;  // the solve multiplies by the reciprocal pivot
+    }
+    if (bad) *flag = 1;
+}
+
+// P0 = EOS(rho0, theta0), G0 = gamma P0 / rho0, H0 = gamma P0 / theta0
+__global__ void k_background(const double *rho0, double *P0, double *G0, double *H0, int nz, EOS e)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nz) return;
+    double P = eos_pressure(rho0[k], e.theta0, e);
+    P0[k] = P;
+    G0[k] = e.gamma * P / rho0[k];
+    H0[k] = e.gamma * P / e.theta0;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+namespace {
+
+template <int N>
+int rhs_zchunk_auto(const numa_ctx *c)
+{
+    if (c->rhs_zchunk > 0) return c->rhs_zchunk;
+    using G = RhsGeom<N>;
+    long tiles = ((c->nx + G::TX - 1) / G::TX) * ((c->ny + G::TY - 1) / G::TY);
+    // enough workgroups for every CU (256) to hold two
+    int zc = c->nez;
+    while (zc > 1 && tiles * ((c->nez + zc - 1) / zc) < 512) zc = (zc + 1) / 2;
+    return zc;
+}
+
+template <int N, int EPI, bool HASB>
+hipError_t rhs_launch(numa_ctx *c, RhsParams p)
+{
+    using G = RhsGeom<N>;
+    p.rho0 = c->lev.rho0;
+    p.P0 = c->lev.P0;
+    p.zsc = c->lev.zsc;
+    p.wxy = c->lev.wxy;
+    p.D = c->lev.D;
+    p.eos = c->eos;
+    p.nx = int(c->nx);
+    p.ny = int(c->ny);
+    p.nz = int(c->nz);
+    p.nez = c->nez;
+    p.zchunk = rhs_zchunk_auto<N>(c);
+    p.nchunk = (c->nez + p.zchunk - 1) / p.zchunk;
+    p.ntx = int((c->nx + G::TX - 1) / G::TX);
+    p.nty = int((c->ny + G::TY - 1) / G::TY);
+    p.flag = c->flag;
+    static bool attr_set = false;  // LDS above 64 KB must be opted into once
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rhs<N, EPI, HASB>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(G::LDS));
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    dim3 grid(unsigned(p.ntx * p.nty * p.nchunk));
+    hipLaunchKernelGGL((k_rhs<N, EPI, HASB>), grid, dim3(G::NT), G::LDS, c->stream, p);
+    return hipGetLastError();
+}
+
+template <int N>
+hipError_t solve_launch(numa_ctx *c, SolveParams p)
+{
+    p.fac = c->fac;
+    p.rho0 = c->lev.rho0;
+    p.G0 = c->lev.G0;
+    p.H0 = c->lev.H0;
+    p.dzb = c->lev.dzb;
+    p.lambda = c->lambda;
+    p.grav = c->eos.grav;
+    p.nz = int(c->nz);
+    p.ncol = c->ncol;
+    size_t shm = size_t(2) * c->nz * 64 * sizeof(double);
+    dim3 grid(unsigned((c->ncol + 63) / 64));
+    hipLaunchKernelGGL((k_colsolve<N>), grid, dim3(64), shm, c->stream, p);
+    return hipGetLastError();
+}
+
+template <int N>
+hipError_t factor_launch(numa_ctx *c, double lambda)
+{
+    dim3 grid(unsigned((c->ncol + 63) / 64));
+    hipLaunchKernelGGL((k_factor<N>), grid, dim3(64), 0, c->stream, c->lev.dzb, c->lev.G0, lambda, c->eos.grav,
+                       int(c->nz), c->ncol, c->fac, c->flag);
+    return hipGetLastError();
+}
+
+// Run f(std::integral_constant<int, N>) for the context's order N.
+template <typename F>
+hipError_t dispatch(int N, F &&f)
+{
+    switch (N) {
+    case 1: return f(std::integral_constant<int, 1>{});
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 3: return f(std::integral_constant<int, 3>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 5: return f(std::integral_constant<int, 5>{});
+    case 6: return f(std::integral_constant<int, 6>{});
+    case 7: return f(std::integral_constant<int, 7>{});
+    case 8: return f(std::integral_constant<int, 8>{});
+    default: return hipErrorInvalidValue;
+    }
+}
+
+void set_fields(const double *arr[5], const double *base, long np)
+{
+    for (int f = 0; f < 5; ++f) arr[f] = base ? base + f * np : nullptr;
+}
+void set_fields(double *arr[5], double *base, long np)
+{
+    for (int f = 0; f < 5; ++f) arr[f] = base ? base + f * np : nullptr;
+}
+
+// ARK2 tableau (Table 1, signs restored by the order conditions)
+struct Ark2 {
+    double a21, a31, a32, ad, b1, b2, b3, c31, c32;
+    Ark2()
+    {
+        const double s2 = std::sqrt(2.0);
+        const double al = (3.0 + 2.0 * s2) / 6.0;
+        a21 = 2.0 - s2;
+        a31 = 1.0 - al;
+        a32 = al;
+        ad = 1.0 - 1.0 / s2;                 // implicit diagonal
+        const double at31 = 1.0 / (2.0 * s2), at32 = 1.0 / (2.0 * s2);
+        b1 = b2 = 1.0 / (2.0 * s2);
+        b3 = ad;
+        c31 = (at31 - a31) / ad;             // q~ shifts (Sec. 2.2)
+        c32 = (at32 - a32) / ad;             // (c21 = -1 exactly)
+    }
+};
+
+}  // namespace
+
+StageBuffers stage_buffers(numa_ctx *c)
+{
+    const long np = c->np;
+    StageBuffers s;
+    s.R1 = c->work;
+    s.E3 = c->work + 5 * np;
+    s.ACC = c->work + 10 * np;
+    s.Q2r = c->work + 15 * np;
+    s.Q2w = c->work + 16 * np;
+    s.Q3r = c->work + 17 * np;
+    s.Q3w = c->work + 18 * np;
+    return s;
+}
+
+hipError_t launch_background(numa_ctx *c)
+{
+    hipLaunchKernelGGL(k_background, dim3(unsigned((c->nz + 63) / 64)), dim3(64), 0, c->stream, c->lev.rho0,
+                       c->lev.P0, c->lev.G0, c->lev.H0, int(c->nz), c->eos);
+    return hipGetLastError();
+}
+
+hipError_t launch_factor(numa_ctx *c, double lambda)
+{
+    return dispatch(c->N, [&](auto n) { return factor_launch<decltype(n)::value>(c, lambda); });
+}
+
+hipError_t launch_rhs_plain(numa_ctx *c, const double *q, double *R)
+{
+    RhsParams p{};
+    set_fields(p.a, q, c->np);
+    set_fields(p.out0, R, c->np);
+    return dispatch(c->N, [&](auto n) { return rhs_launch<decltype(n)::value, EPI_R, false>(c, p); });
+}
+
+hipError_t launch_solve_plain(numa_ctx *c, const double *y, double *x)
+{
+    const long np = c->np;
+    SolveParams p{};
+    p.er[0] = y + 0 * np; p.cr[0] = 1.0; p.nr = 1;
+    p.ew[0] = y + 3 * np; p.cw[0] = 1.0; p.nw = 1;
+    p.et[0] = y + 4 * np; p.ct[0] = 1.0; p.nt = 1;
+    p.br[0] = y + 0 * np; p.cbr[0] = 1.0; p.nbr = 1;
+    p.nbw = 0;
+    p.out_r = x + 0 * np;
+    p.out_w = x + 3 * np;
+    hipError_t e;
+    for (int f : {1, 2, 4}) {
+        e = hipMemcpyAsync(x + f * np, y + f * np, sizeof(double) * np, hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) return e;
+    }
+    return dispatch(c->N, [&](auto n) { return solve_launch<decltype(n)::value>(c, p); });
+}
+
+// One ARK2 step in the q~ form (Sec. 2.2):
+//   stage i:  q~ = q~_e + lambda L_V(q~),  q~_e = q_e^(i) + sum_j c_ij Q_j,
+//             Q_i = q~ - sum_j c_ij Q_j,   c_ij = (at_ij - a_ij)/at_ii,
+//   q^{n+1} = q^n + dt sum_i b_i R_i.
+// With c21 = -1 and Q1 = q^n, stage 2 needs q~_e = dt a21 R1 only.  Kernels:
+//   K1 rhs(q^n)            -> R1
+//   K2 colsolve(stage 2)   -> Q2 rho', w  (u, v, theta' of Q2 are q^n + dt a21 R1)
+//   K3 rhs(Q2)             -> E3 = q^n + dt(a31 R1 + a32 R2), ACC = q^n + dt b1 (R1 + R2)
+//   K4 colsolve(stage 3)   -> Q3 rho', w  (u, v, theta' of Q3 are E3's)
+//   K5 rhs(Q3)             -> q^{n+1} = ACC + dt b3 R3 (in place)
+hipError_t launch_hevi_step(numa_ctx *c, double *q, double dt, hipEvent_t *ev)
+{
+    static const Ark2 t;
+    const long np = c->np;
+    StageBuffers s = stage_buffers(c);
+    const double *qr = q + 0 * np, *qu = q + 1 * np, *qv = q + 2 * np, *qw = q + 3 * np, *qt = q + 4 * np;
+    const double *R1 = s.R1;
+    hipError_t e;
+
+    // ev (optional): events ev[0..5] recorded around the 5 kernels
+    auto mark = [&](int i) -> hipError_t { return ev ? hipEventRecord(ev[i], c->stream) : hipSuccess; };
+    if ((e = mark(0)) != hipSuccess) return e;
+
+    // K1
+    e = launch_rhs_plain(c, q, s.R1);
+    if (e != hipSuccess) return e;
+    if ((e = mark(1)) != hipSuccess) return e;
+
+    // K2: q~_e = dt a21 R1 ; Q2 rho' = q^n + dt a21 R1 - lambda Dz(rho0 w~) ; Q2 w = w~ + q^n w
+    {
+        SolveParams p{};
+        const double f = dt * t.a21;
+        p.er[0] = R1 + 0 * np; p.cr[0] = f; p.nr = 1;
+        p.ew[0] = R1 + 3 * np; p.cw[0] = f; p.nw = 1;
+        p.et[0] = R1 + 4 * np; p.ct[0] = f; p.nt = 1;
+        p.br[0] = qr; p.cbr[0] = 1.0; p.br[1] = R1 + 0 * np; p.cbr[1] = f; p.nbr = 2;
+        p.bw[0] = qw; p.cbw[0] = 1.0; p.nbw = 1;
+        p.out_r = s.Q2r;
+        p.out_w = s.Q2w;
+        e = dispatch(c->N, [&](auto n) { return solve_launch<decltype(n)::value>(c, p); });
+        if (e != hipSuccess) return e;
+        if ((e = mark(2)) != hipSuccess) return e;
+    }
+
+    // K3: rhs(Q2), Q2 = (Q2r, qu + f R1u, qv + f R1v, Q2w, qt + f R1t)
+    {
+        RhsParams p{};
+        const double f = dt * t.a21;
+        p.a[0] = s.Q2r; p.b[0] = nullptr;
+        p.a[1] = qu;    p.b[1] = R1 + 1 * np;
+        p.a[2] = qv;    p.b[2] = R1 + 2 * np;
+        p.a[3] = s.Q2w; p.b[3] = nullptr;
+        p.a[4] = qt;    p.b[4] = R1 + 4 * np;
+        p.cb = f;
+        set_fields(p.out0, s.E3, np);
+        set_fields(p.out1, s.ACC, np);
+        set_fields(p.e0, q, np);
+        set_fields(p.e1, R1, np);
+        p.k01 = dt * t.a31; p.k02 = dt * t.a32;
+        p.k11 = dt * t.b1;  p.k12 = dt * t.b2;
+        e = dispatch(c->N, [&](auto n) { return rhs_launch<decltype(n)::value, EPI_TWO, true>(c, p); });
+        if (e != hipSuccess) return e;
+        if ((e = mark(3)) != hipSuccess) return e;
+    }
+
+    // K4: q~_e = E3 + c31 q^n + c32 Q2 (rho', w, theta');  theta' of Q2 = qt + f R1t
+    {
+        SolveParams p{};
+        const double f = dt * t.a21;
+        p.er[0] = s.E3 + 0 * np; p.cr[0] = 1.0; p.er[1] = qr; p.cr[1] = t.c31; p.er[2] = s.Q2r; p.cr[2] = t.c32; p.nr = 3;
+        p.ew[0] = s.E3 + 3 * np; p.cw[0] = 1.0; p.ew[1] = qw; p.cw[1] = t.c31; p.ew[2] = s.Q2w; p.cw[2] = t.c32; p.nw = 3;
+        p.et[0] = s.E3 + 4 * np; p.ct[0] = 1.0; p.et[1] = qt; p.ct[1] = t.c31 + t.c32; p.et[2] = R1 + 4 * np;
+        p.ct[2] = t.c32 * f; p.nt = 3;
+        p.br[0] = s.E3 + 0 * np; p.cbr[0] = 1.0; p.nbr = 1;
+        p.bw[0] = qw; p.cbw[0] = -t.c31; p.bw[1] = s.Q2w; p.cbw[1] = -t.c32; p.nbw = 2;
+        p.out_r = s.Q3r;
+        p.out_w = s.Q3w;
+        e = dispatch(c->N, [&](auto n) { return solve_launch<decltype(n)::value>(c, p); });
+        if (e != hipSuccess) return e;
+        if ((e = mark(4)) != hipSuccess) return e;
+    }
+
+    // K5: rhs(Q3), Q3 = (Q3r, E3u, E3v, Q3w, E3t);  q^{n+1} = ACC + dt b3 R3
+    {
+        RhsParams p{};
+        p.a[0] = s.Q3r;
+        p.a[1] = s.E3 + 1 * np;
+        p.a[2] = s.E3 + 2 * np;
+        p.a[3] = s.Q3w;
+        p.a[4] = s.E3 + 4 * np;
+        set_fields(p.out0, q, np);
+        set_fields(p.e0, s.ACC, np);
+        p.k02 = dt * t.b3;
+        e = dispatch(c->N, [&](auto n) { return rhs_launch<decltype(n)::value, EPI_FINAL, false>(c, p); });
+        if (e != hipSuccess) return e;
+        if ((e = mark(5)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace numa

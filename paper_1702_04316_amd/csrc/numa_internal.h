@@ -1,0 +1,81 @@
+// Internal declarations of the HEVI library: the context, the host set-up
+// (LGL basis, DSS line operators, background) and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/numa.h"
+
+namespace numa {
+
+constexpr int kMaxOrder = 8;
+
+// Host-side operators of one context (built by setup.cpp).
+struct HostOps {
+    int N = 0;
+    std::vector<double> xi;     // LGL nodes, N+1
+    std::vector<double> D;      // differentiation matrix, (N+1)^2, D[i*(N+1)+j]
+    std::vector<double> wxy;    // [2][N][2N+1] x and y DSS stencils, metric included
+    std::vector<double> zsc;    // [3][nez]: 2/h_e, bottom-interface and top-interface factors
+    std::vector<double> dzb;    // [nz][2N+1] column DSS derivative band (offsets -N..N)
+    std::vector<double> zk;     // level heights, nz
+    std::vector<double> rho0;   // nz
+};
+
+// Per-level background on the device (P0, G0, H0 are evaluated on the device
+// with the same equation-of-state code as the right-hand side, so that the
+// rest state gives P' = 0 exactly).
+struct DevLevels {
+    double *rho0 = nullptr, *P0 = nullptr, *G0 = nullptr, *H0 = nullptr;
+    double *dzb = nullptr, *zsc = nullptr, *wxy = nullptr, *D = nullptr;
+};
+
+struct EOS {
+    double theta0, p00, rgas, gamma, grav;
+};
+
+}  // namespace numa
+
+struct numa_ctx {
+    int N = 0, nex = 0, ney = 0, nez = 0;
+    int64_t nx = 0, ny = 0, nz = 0, ncol = 0, plane = 0, np = 0;
+    double lx = 0, ly = 0, lz = 0;
+    numa::EOS eos{};
+    double cp = 0;
+    hipStream_t stream = nullptr;
+    numa::HostOps ops;
+    numa::DevLevels lev;
+    void *lev_block = nullptr;     // one allocation holding all of lev
+    double *fac = nullptr;         // [nz][4N+1][ncol] column LU factors
+    double *work = nullptr;        // stage buffers (19 fields)
+    int *flag = nullptr;           // device non-finite flag
+    int factored = 0;
+    double dt_factored = 0, lambda = 0;
+    int rhs_zchunk = 0;            // z elements per RHS workgroup (0 = auto)
+    std::string err;
+};
+
+namespace numa {
+
+// setup.cpp
+void lgl_nodes(int N, std::vector<double> &xi);
+void lgl_dmat(int N, const std::vector<double> &xi, std::vector<double> &D);
+void build_ops(numa_ctx *c, const double *zface);
+
+// kernels.hip: launchers return hipSuccess or the launch error.
+struct StageBuffers {
+    double *R1, *Q2r, *Q2w, *E3, *ACC, *Q3r, *Q3w;  // R1/E3/ACC: 5 fields each
+};
+StageBuffers stage_buffers(numa_ctx *c);
+
+hipError_t launch_background(numa_ctx *c);
+hipError_t launch_factor(numa_ctx *c, double lambda);
+hipError_t launch_rhs_plain(numa_ctx *c, const double *q, double *R);
+hipError_t launch_solve_plain(numa_ctx *c, const double *y, double *x);
+hipError_t launch_hevi_step(numa_ctx *c, double *q, double dt, hipEvent_t *ev = nullptr);
+
+}  // namespace numa

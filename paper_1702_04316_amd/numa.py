@@ -1,0 +1,273 @@
+"""Thin ctypes binding of the HEVI C ABI (include/numa.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of ``libnuma_hevi.so``.  PyTorch supplies device memory (the state tensor)
+and the stream.  If the library has not been built this module raises on
+first use; there is no fallback implementation.
+"""
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnuma_hevi.so")
+
+NUMA_OK = 0
+NUMA_E_ARG = -1
+NUMA_E_NOT_FACTORED = -2
+NUMA_E_DT_MISMATCH = -3
+NUMA_E_HIP = -4
+NUMA_E_NOMEM = -5
+NUMA_E_NONFINITE = -6
+NUMA_E_NOT_CONVERGED = -7
+NUMA_E_UNSUPPORTED = -8
+
+ERROR_NAMES = {
+    NUMA_E_ARG: "NUMA_E_ARG",
+    NUMA_E_NOT_FACTORED: "NUMA_E_NOT_FACTORED",
+    NUMA_E_DT_MISMATCH: "NUMA_E_DT_MISMATCH",
+    NUMA_E_HIP: "NUMA_E_HIP",
+    NUMA_E_NOMEM: "NUMA_E_NOMEM",
+    NUMA_E_NONFINITE: "NUMA_E_NONFINITE",
+    NUMA_E_NOT_CONVERGED: "NUMA_E_NOT_CONVERGED",
+    NUMA_E_UNSUPPORTED: "NUMA_E_UNSUPPORTED",
+}
+
+
+class numa_grid(C.Structure):
+    _fields_ = [("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double),
+                ("nex", C.c_int32), ("ney", C.c_int32), ("nez", C.c_int32),
+                ("zface", C.POINTER(C.c_double))]
+
+
+class numa_background(C.Structure):
+    _fields_ = [("theta0", C.c_double), ("p00", C.c_double), ("cp", C.c_double),
+                ("rgas", C.c_double), ("grav", C.c_double)]
+
+
+class numa_info(C.Structure):
+    _fields_ = [("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64), ("ncol", C.c_int64),
+                ("factor_bytes", C.c_int64), ("scratch_bytes", C.c_int64), ("step_bytes", C.c_int64),
+                ("order", C.c_int32), ("factored", C.c_int32), ("dt_factored", C.c_double)]
+
+
+class NumaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libnuma_hevi.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run `python __graft_entry__.py` or "
+                          f"`python paper_1702_04316_amd/build.py` to build the HIP library")
+    lib = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    lib.numa_setup.argtypes = [C.POINTER(numa_grid), C.c_int32, C.POINTER(numa_background), vp, C.POINTER(vp)]
+    lib.numa_state_shape.argtypes = [vp, C.POINTER(C.c_int64)]
+    lib.numa_get_info.argtypes = [vp, C.POINTER(numa_info)]
+    lib.numa_set_stream.argtypes = [vp, vp]
+    lib.numa_factor_columns.argtypes = [vp, C.c_double]
+    lib.numa_hevi_step.argtypes = [vp, vp, C.c_double, C.c_int32]
+    lib.numa_profile_steps.argtypes = [vp, vp, C.c_double, C.c_int32, C.POINTER(C.c_double)]
+    lib.numa_rhs.argtypes = [vp, vp, vp]
+    lib.numa_solve_columns.argtypes = [vp, vp, vp]
+    lib.numa_imex3d_step.argtypes = [vp, vp, C.c_double, C.c_double, C.POINTER(C.c_int32)]
+    lib.numa_check.argtypes = [vp]
+    lib.numa_destroy.argtypes = [vp]
+    lib.numa_last_error.argtypes = [vp]
+    lib.numa_last_error.restype = C.c_char_p
+    lib.numa_lgl_basis.argtypes = [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.numa_line_operators.argtypes = [C.POINTER(numa_grid), C.c_int32, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double)]
+    for name in ("numa_setup", "numa_state_shape", "numa_get_info", "numa_set_stream", "numa_factor_columns",
+                 "numa_hevi_step", "numa_profile_steps", "numa_rhs", "numa_solve_columns", "numa_imex3d_step", "numa_check",
+                 "numa_destroy", "numa_lgl_basis", "numa_line_operators"):
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def last_error(ctx=None):
+    return load().numa_last_error(ctx).decode()
+
+
+def _check(rc, ctx=None):
+    if rc != NUMA_OK:
+        raise NumaError(rc, last_error(ctx))
+    return rc
+
+
+def _dptr(arr):
+    import numpy as np
+    a = np.ascontiguousarray(arr, dtype=np.float64)
+    return a, a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def make_grid(lx, ly, lz, nex, ney, nez, zface=None):
+    """numa_grid plus the host array that keeps zface alive."""
+    g = numa_grid(lx, ly, lz, nex, ney, nez, None)
+    keep = None
+    if zface is not None:
+        keep, g.zface = _dptr(zface)
+    return g, keep
+
+
+# ---------------------------------------------------------------------------
+# Functions with the ABI's names (raw: return codes, pointers as integers)
+# ---------------------------------------------------------------------------
+
+def setup(grid, order, background, stream=None):
+    ctx = C.c_void_p()
+    rc = load().numa_setup(C.byref(grid), int(order), C.byref(background),
+                           C.c_void_p(stream) if stream else None, C.byref(ctx))
+    _check(rc, None)
+    return ctx.value
+
+
+def state_shape(ctx):
+    s = (C.c_int64 * 4)()
+    _check(load().numa_state_shape(ctx, s), ctx)
+    return tuple(int(v) for v in s)
+
+
+def get_info(ctx):
+    info = numa_info()
+    _check(load().numa_get_info(ctx, C.byref(info)), ctx)
+    return {f: getattr(info, f) for f, _ in numa_info._fields_}
+
+
+def set_stream(ctx, stream):
+    return _check(load().numa_set_stream(ctx, C.c_void_p(stream) if stream else None), ctx)
+
+
+def factor_columns(ctx, dt):
+    return _check(load().numa_factor_columns(ctx, float(dt)), ctx)
+
+
+def hevi_step(ctx, state_ptr, dt, nsteps):
+    return _check(load().numa_hevi_step(ctx, C.c_void_p(state_ptr), float(dt), int(nsteps)), ctx)
+
+
+def profile_steps(ctx, state_ptr, dt, nsteps):
+    """Average milliseconds of each of the 5 kernels of a step (launch order)."""
+    ms = (C.c_double * 5)()
+    _check(load().numa_profile_steps(ctx, C.c_void_p(state_ptr), float(dt), int(nsteps), ms), ctx)
+    return [float(v) for v in ms]
+
+
+def rhs(ctx, state_ptr, out_ptr):
+    return _check(load().numa_rhs(ctx, C.c_void_p(state_ptr), C.c_void_p(out_ptr)), ctx)
+
+
+def solve_columns(ctx, y_ptr, x_ptr):
+    return _check(load().numa_solve_columns(ctx, C.c_void_p(y_ptr), C.c_void_p(x_ptr)), ctx)
+
+
+def imex3d_step(ctx, state_ptr, dt, tol):
+    it = C.c_int32(0)
+    _check(load().numa_imex3d_step(ctx, C.c_void_p(state_ptr), float(dt), float(tol), C.byref(it)), ctx)
+    return it.value
+
+
+def check(ctx):
+    return _check(load().numa_check(ctx), ctx)
+
+
+def destroy(ctx):
+    return load().numa_destroy(ctx)
+
+
+def lgl_basis(order):
+    import numpy as np
+    xi = np.zeros(order + 1)
+    D = np.zeros((order + 1) ** 2)
+    _check(load().numa_lgl_basis(int(order), xi.ctypes.data_as(C.POINTER(C.c_double)),
+                                 D.ctypes.data_as(C.POINTER(C.c_double))))
+    return xi, D.reshape(order + 1, order + 1)
+
+
+def line_operators(grid, order):
+    import numpy as np
+    ns = 2 * order + 1
+    nz = grid.nez * order + 1
+    wxy = np.zeros(2 * order * ns)
+    dzb = np.zeros(nz * ns)
+    _check(load().numa_line_operators(C.byref(grid), int(order), wxy.ctypes.data_as(C.POINTER(C.c_double)),
+                                      dzb.ctypes.data_as(C.POINTER(C.c_double))))
+    return wxy.reshape(2, order, ns), dzb.reshape(nz, ns)
+
+
+# ---------------------------------------------------------------------------
+# Convenience wrapper around one context (torch tensors for the state)
+# ---------------------------------------------------------------------------
+
+class Context:
+    """One HEVI context on the current CUDA (HIP) device and stream."""
+
+    def __init__(self, grid, background=None, stream=None):
+        import torch
+        from . import workloads as W
+        bg = background or W.Background()
+        self.grid = grid
+        self._g, self._zkeep = make_grid(grid.lx, grid.ly, grid.lz, grid.nex, grid.ney, grid.nez,
+                                         grid.zface)
+        self._bg = numa_background(bg.theta0, bg.p00, bg.cp, bg.rgas, bg.grav)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.ctx = setup(self._g, grid.N, self._bg, stream)
+        self.shape = state_shape(self.ctx)
+        self.dt = None
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        return get_info(self.ctx)
+
+    def factor(self, dt):
+        factor_columns(self.ctx, dt)
+        self.dt = float(dt)
+
+    def _check_state(self, t):
+        import torch
+        assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous(), "state: contiguous float64 cuda"
+        assert tuple(t.shape) == self.shape, (tuple(t.shape), self.shape)
+
+    def step(self, state, nsteps=1, dt=None):
+        self._check_state(state)
+        hevi_step(self.ctx, state.data_ptr(), self.dt if dt is None else dt, nsteps)
+        return state
+
+    def rhs(self, state, out=None):
+        import torch
+        self._check_state(state)
+        out = torch.empty_like(state) if out is None else out
+        self._check_state(out)
+        rhs(self.ctx, state.data_ptr(), out.data_ptr())
+        return out
+
+    def solve(self, y, out=None):
+        import torch
+        self._check_state(y)
+        out = torch.empty_like(y) if out is None else out
+        self._check_state(out)
+        solve_columns(self.ctx, y.data_ptr(), out.data_ptr())
+        return out
+
+    def check(self):
+        return check(self.ctx)

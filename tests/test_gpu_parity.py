@@ -1,0 +1,256 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Per-variable relative L2 differences; floating-point bars:
+  - one explicit right-hand side or one column solve: 1e-12
+  - HEVI steps: 1e-11 after every step (the bar the method's FP64 form is held to)
+Operators are also compared on node-wise noise (their parity is algebraic and
+does not need smooth data) and on tiny, ragged and degenerate grids.
+"""
+import numpy as np
+import pytest
+
+from paper_1702_04316_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+STEP_TOL = 1e-11
+OP_TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def numa_mod():
+    from paper_1702_04316_amd import numa
+    numa.load()
+    return numa
+
+
+def _oracle(O, g, bg=None):
+    bg = bg or W.Background()
+    return O.Oracle(g.lx, g.ly, g.lz, g.nex, g.ney, g.nez, g.N, theta0=bg.theta0, p00=bg.p00, cp=bg.cp,
+                    rgas=bg.rgas, grav=bg.grav, zface=g.zface)
+
+
+def _rel(a, b):
+    """Per-variable relative L2 of a against the reference b."""
+    out = []
+    for f in range(5):
+        nb = np.linalg.norm(b[f])
+        d = np.linalg.norm(a[f] - b[f])
+        out.append(d / nb if nb > 0 else np.max(np.abs(a[f])))
+    return np.array(out)
+
+
+def _dev(torch, q):
+    return torch.from_numpy(np.ascontiguousarray(q)).to("cuda")
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
+
+
+GRIDS = [
+    # (N, nex, ney, nez, zface seed or None, state seed)
+    (1, 3, 2, 4, None, 0),
+    (1, 1, 1, 2, None, 1),          # degenerate: one element per horizontal axis
+    (2, 5, 3, 3, 1, 2),
+    (3, 4, 4, 2, 2, 3),
+    (4, 4, 4, 4, None, 4),
+    (4, 9, 5, 3, 3, 5),             # ragged tiles in x and y
+    (4, 1, 2, 1, None, 6),
+    (5, 3, 2, 2, 4, 7),
+    (6, 2, 3, 2, None, 8),
+    (7, 2, 2, 2, 5, 9),
+    (8, 2, 1, 2, 6, 10),
+]
+
+
+def _grid(N, nex, ney, nez, zseed):
+    lz = 6000.0
+    zf = None if zseed is None else W.random_zface(nez, lz, zseed)
+    return W.Grid(9000.0 * nex, 7000.0 * ney, lz, nex, ney, nez, N, zface=zf)
+
+
+@pytest.mark.parametrize("N,nex,ney,nez,zseed,seed", GRIDS)
+def test_rhs_parity(torch_cuda, numa_mod, oracle_mod, N, nex, ney, nez, zseed, seed):
+    g = _grid(N, nex, ney, nez, zseed)
+    q = W.make_random_state(g, seed, smooth=False)
+    ref = _oracle(oracle_mod, g).rhs(q)
+    ctx = numa_mod.Context(g)
+    out = _host(ctx.rhs(_dev(torch_cuda, q)))
+    ctx.check()
+    e = _rel(out, ref)
+    assert np.all(e < OP_TOL), e
+    assert np.all(out[3, 0] == 0.0) and np.all(out[3, -1] == 0.0)
+
+
+@pytest.mark.parametrize("N,nex,ney,nez,zseed,seed", GRIDS)
+def test_solve_parity(torch_cuda, numa_mod, oracle_mod, N, nex, ney, nez, zseed, seed):
+    g = _grid(N, nex, ney, nez, zseed)
+    dt = W.dt_for_courant(g, 15.0, "z")
+    y = W.make_random_state(g, seed + 100, smooth=False)
+    o = _oracle(oracle_mod, g)
+    o.factor_dt(dt)
+    ref = o.solve(y)
+    ctx = numa_mod.Context(g)
+    ctx.factor(dt)
+    out = _host(ctx.solve(_dev(torch_cuda, y)))
+    ctx.check()
+    e = _rel(out, ref)
+    assert np.all(e < OP_TOL), e
+    assert np.array_equal(out[1], y[1]) and np.array_equal(out[2], y[2]) and np.array_equal(out[4], y[4])
+
+
+def _run_steps(torch, numa, O, wl, q0, nsteps, tol=STEP_TOL):
+    g = wl.grid
+    o = _oracle(O, g, wl.background)
+    o.factor_dt(wl.dt)
+    ctx = numa.Context(g, wl.background)
+    ctx.factor(wl.dt)
+    qd = _dev(torch, q0)
+    qo = q0.copy()
+    table = []
+    for n in range(nsteps):
+        qo = o.step(qo, wl.dt, 1)
+        ctx.step(qd, 1)
+        qg = _host(qd)
+        table.append(_rel(qg, qo))
+    ctx.check()
+    table = np.array(table)
+    print(f"{wl.name}: per-step relative L2 (rho', u, v, w, theta'):")
+    for n, e in enumerate(table):
+        print(f"  step {n + 1:3d}: " + " ".join(f"{x:.2e}" for x in e))
+    assert np.all(table < tol), table
+    return table.max(axis=0)
+
+
+@pytest.mark.parametrize("reading", ["R1", "R2"])
+def test_step_parity_box_small(torch_cuda, numa_mod, oracle_mod, reading):
+    wl = W.box_small(reading)
+    q0 = W.make_initial_state(wl)
+    worst = _run_steps(torch_cuda, numa_mod, oracle_mod, wl, q0, wl.nsteps)
+    print(f"box_small {reading}: worst per-variable rel L2 over {wl.nsteps} steps {worst}")
+
+
+@pytest.mark.parametrize("N,nex,ney,nez,zseed,seed", [g for g in GRIDS if g[0] in (2, 4, 5, 7)])
+def test_step_parity_random(torch_cuda, numa_mod, oracle_mod, N, nex, ney, nez, zseed, seed):
+    g = _grid(N, nex, ney, nez, zseed)
+    # vertical Courant number 5, capped by a horizontal Courant number 0.4
+    # (the horizontal direction is explicit)
+    dt = min(W.dt_for_courant(g, 5.0, "z"), W.dt_for_courant(g, 0.4, "x"), W.dt_for_courant(g, 0.4, "y"))
+    wl = W.Workload("rand", g, dt, 3, seed, 1, (0.5, 0.5), (500.0, 500.0))
+    q0 = W.make_random_state(g, seed, wind=5.0)
+    _run_steps(torch_cuda, numa_mod, oracle_mod, wl, q0, 3)
+
+
+@pytest.mark.timeout(900)
+def test_step_parity_box_large_full_size(torch_cuda, numa_mod, oracle_mod):
+    """The benchmarked workload at full size (64x64x10 elements, N = 4, 2.7M
+    unique nodes), with the launch configuration the benchmark uses."""
+    wl = W.box_large("R1")
+    q0 = W.make_initial_state(wl)
+    worst = _run_steps(torch_cuda, numa_mod, oracle_mod, wl, q0, 2)
+    print(f"box_large R1 full size: worst per-variable rel L2 over 2 steps {worst}")
+
+
+def test_rest_state_stays_at_rest(torch_cuda, numa_mod):
+    g = _grid(4, 3, 2, 3, 7)
+    ctx = numa_mod.Context(g)
+    dt = W.dt_for_courant(g, 15.0, "z")
+    ctx.factor(dt)
+    q = torch_cuda.zeros(ctx.shape, dtype=torch_cuda.float64, device="cuda")
+    assert torch_cuda.count_nonzero(ctx.rhs(q)).item() == 0
+    ctx.step(q, 5)
+    ctx.check()
+    assert torch_cuda.count_nonzero(q).item() == 0
+
+
+def test_mass_conservation(torch_cuda, numa_mod, oracle_mod):
+    wl = W.box_small("R1")
+    g = wl.grid
+    M = _oracle(oracle_mod, g).mass()
+    q0 = W.make_initial_state(wl)
+    ctx = numa_mod.Context(g)
+    ctx.factor(wl.dt)
+    qd = _dev(torch_cuda, q0)
+    m0 = np.sum(M * q0[0])
+    for _ in range(5):
+        ctx.step(qd, 2)
+        q = _host(qd)
+        assert abs(np.sum(M * q[0]) - m0) < 1e-13 * np.sum(M * np.abs(q[0]))
+
+
+def test_deterministic_and_resumable(torch_cuda, numa_mod):
+    wl = W.box_small("R1")
+    q0 = W.make_initial_state(wl)
+    ctx = numa_mod.Context(wl.grid)
+    ctx.factor(wl.dt)
+    a = _dev(torch_cuda, q0)
+    ctx.step(a, 10)
+    b = _dev(torch_cuda, q0)
+    ctx.step(b, 10)
+    assert torch_cuda.equal(a, b)
+    # checkpoint after 5 steps, resume in a new context with re-built factors
+    c = _dev(torch_cuda, q0)
+    ctx.step(c, 5)
+    saved = _host(c).copy()
+    ctx2 = numa_mod.Context(wl.grid)
+    ctx2.factor(wl.dt)
+    d = _dev(torch_cuda, saved)
+    ctx2.step(d, 5)
+    assert torch_cuda.equal(a, d)
+
+
+def test_error_codes(torch_cuda, numa_mod):
+    numa = numa_mod
+    g = _grid(3, 2, 2, 2, None)
+    ctx = numa.Context(g)
+    q = torch_cuda.zeros(ctx.shape, dtype=torch_cuda.float64, device="cuda")
+    with pytest.raises(numa.NumaError) as ei:
+        numa.hevi_step(ctx.ctx, q.data_ptr(), 1.0, 1)
+    assert ei.value.code == numa.NUMA_E_NOT_FACTORED
+    x = torch_cuda.zeros_like(q)
+    with pytest.raises(numa.NumaError) as ei:
+        numa.solve_columns(ctx.ctx, q.data_ptr(), x.data_ptr())
+    assert ei.value.code == numa.NUMA_E_NOT_FACTORED
+    ctx.factor(1.0)
+    with pytest.raises(numa.NumaError) as ei:
+        numa.hevi_step(ctx.ctx, q.data_ptr(), 1.0 + 2e-16, 1)
+    assert ei.value.code == numa.NUMA_E_DT_MISMATCH
+    with pytest.raises(numa.NumaError) as ei:
+        numa.factor_columns(ctx.ctx, -1.0)
+    assert ei.value.code == numa.NUMA_E_ARG
+    with pytest.raises(numa.NumaError) as ei:
+        numa.imex3d_step(ctx.ctx, q.data_ptr(), 1.0, 1e-8)
+    assert ei.value.code == numa.NUMA_E_UNSUPPORTED
+    # a NaN in the state is reported by numa_check, and the flag is then cleared
+    q[4, 2, 1, 1] = float("nan")
+    ctx.step(q, 1)
+    with pytest.raises(numa.NumaError) as ei:
+        ctx.check()
+    assert ei.value.code == numa.NUMA_E_NONFINITE
+    ctx.check()
+    info = ctx.info()
+    assert info["factored"] == 1 and info["dt_factored"] == 1.0
+    assert info["nx"] == 6 and info["nz"] == 7
+    ctx.close()
+
+
+def test_many_contexts_no_leak(torch_cuda, numa_mod):
+    import gc
+    g = _grid(4, 4, 4, 2, None)
+    torch_cuda.cuda.synchronize()
+    free0, _ = torch_cuda.cuda.mem_get_info()
+    for _ in range(50):
+        ctx = numa_mod.Context(g)
+        ctx.factor(1.0)
+        ctx.close()
+    gc.collect()
+    free1, _ = torch_cuda.cuda.mem_get_info()
+    assert free0 - free1 < 64 << 20
