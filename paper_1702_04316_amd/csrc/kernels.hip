@@ -56,6 +56,8 @@ struct RhsGeom {
     static constexpr int NCROSS = TY * LX + TX * (N + 1);
     static constexpr int NITEM = (N * NCROSS + NT - 1) / NT;  // plane loads per thread
     static constexpr size_t LDS = size_t(N + 1) * PS * sizeof(double);
+    // waves per SIMD to compile for: two workgroups per CU where LDS allows
+    static constexpr int MINW = (NT <= 512 && 2 * LDS <= 150 * 1024) ? 2 * (NT / 256) : 1;
 };
 
 // device equation of state: P = p00 (rho R theta / p00)^gamma (Eq. (10))
@@ -132,12 +134,13 @@ __device__ __forceinline__ double stage_input(const RhsParams &p, int f, unsigne
 }
 
 template <int N, int EPI, bool HASB>
-__global__ __launch_bounds__(RhsGeom<N>::NT) void k_rhs(RhsParams p)
+__global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsParams p)
 {
     using G = RhsGeom<N>;
     constexpr int NQ = N + 1, NS = G::NS, TX = G::TX, TY = G::TY, LX = G::LX, FS = G::FS, PS = G::PS;
     extern __shared__ double ring[];  // [N+1][6][LY][LX]
     __shared__ double sw[2][N][NS];
+    __shared__ double sD[NQ * NQ];
 
     const int tid = threadIdx.x;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
@@ -150,6 +153,7 @@ __global__ __launch_bounds__(RhsGeom<N>::NT) void k_rhs(RhsParams p)
     const unsigned pbytes = unsigned(nx) * unsigned(ny) * 8u;
 
     for (int s = tid; s < 2 * N * NS; s += G::NT) (&sw[0][0][0])[s] = p.wxy[s];
+    for (int s = tid; s < NQ * NQ; s += G::NT) sD[s] = p.D[s];
 
     // plane loads of this thread: which of the N new planes (1..N, 0 = none),
     // LDS offset in the plane, byte offset in a level plane
@@ -209,20 +213,23 @@ __global__ __launch_bounds__(RhsGeom<N>::NT) void k_rhs(RhsParams p)
 
     // sum_n D[r][n] g(level ez*N + n) over the own column for the six
     // z-differentiated quantities rho w, u, v, w, theta', P'
+    // (not unrolled: unrolled, all 6*(N+1) LDS reads would be in flight at once)
     auto zsum = [&](int ez, int r, double *out) {
 #pragma unroll
         for (int f = 0; f < 6; ++f) out[f] = 0.0;
-#pragma unroll
+        int k = ez * N, slot = k % NQ;
+#pragma unroll 1
         for (int n = 0; n < NQ; ++n) {
-            const int k = ez * N + n;
-            const double *q = ring + (k % NQ) * PS + l_own;
-            const double d = p.D[r * NQ + n];
+            const double *q = ring + slot * PS + l_own;
+            const double d = sD[r * NQ + n];
             out[0] += d * ((p.rho0[k] + q[0]) * q[3 * FS]);
             out[1] += d * q[1 * FS];
             out[2] += d * q[2 * FS];
             out[3] += d * q[3 * FS];
             out[4] += d * q[4 * FS];
             out[5] += d * q[5 * FS];
+            ++k;
+            slot = (slot + 1 == NQ) ? 0 : slot + 1;
         }
     };
 
@@ -341,18 +348,21 @@ __global__ __launch_bounds__(RhsGeom<N>::NT) void k_rhs(RhsParams p)
 }
 
 // ---------------------------------------------------------------------------
-// Column solve.  One lane per column, 64 columns per workgroup; the column's
-// pressure and rho0*w live in LDS ([level][lane], conflict free).
+// Column solve.  One lane per column, 64 columns per workgroup (one
+// wavefront).  The column's pressure P and rho0*w live in LDS as
+// [level][lane] (conflict free), padded with HB zero levels below and above
+// so the band operators need no bounds tests.  The sequential band
+// substitutions run in blocks of CB levels whose factor loads are all issued
+// before the block's arithmetic: with one wavefront per SIMD that is what
+// keeps enough bytes in flight.
 // ---------------------------------------------------------------------------
 struct SolveParams {
-    // q~_e for rho', w, theta': sum_t c_t * ptr_t (nt terms)
+    // q~_e for rho', w, theta': sum_t c_t * ptr_t
     const double *er[3], *ew[3], *et[3];
     double cr[3], cw[3], ct[3];
-    int nr, nw, nt;
     // outputs: rho' = sum_t cbr_t br_t - lambda Dz(rho0 w~);  w = w~ + sum_t cbw_t bw_t
     const double *br[2], *bw[2];
     double cbr[2], cbw[2];
-    int nbr, nbw;
     double *out_r, *out_w;
     const double *fac;
     const double *rho0, *G0, *H0, *dzb;
@@ -361,94 +371,166 @@ struct SolveParams {
     long ncol;
 };
 
-template <int N>
+// term counts of the stage variants: (NR, NW, NT) explicit-estimate terms,
+// (NBR, NBW) output terms
+template <int NR_, int NW_, int NT_, int NBR_, int NBW_>
+struct SolveShape {
+    static constexpr int NR = NR_, NW = NW_, NT = NT_, NBR = NBR_, NBW = NBW_;
+};
+using ShapePlain = SolveShape<1, 1, 1, 1, 0>;
+using ShapeStage2 = SolveShape<1, 1, 1, 2, 1>;
+using ShapeStage3 = SolveShape<3, 3, 3, 1, 2>;
+
+template <int N, class SH>
 __global__ __launch_bounds__(64) void k_colsolve(SolveParams p)
 {
     extern __shared__ double smem[];
-    constexpr int NS = 2 * N + 1, NB = 4 * N + 1, HB = 2 * N;
+    constexpr int NS = 2 * N + 1, NB = 4 * N + 1, HB = 2 * N, CB = 8;
     const int lane = threadIdx.x;
     const long col = (long)blockIdx.x * 64 + lane;
     const bool act = col < p.ncol;
-    const long cc = act ? col : 0;
+    const unsigned cbyte = unsigned(act ? col : 0) * 8u;
     const int M = p.nz;
-    double *P = smem;            // [M][64]
-    double *RW = smem + M * 64;  // [M][64]
-    const long ncol = p.ncol;
+    const unsigned lbytes = unsigned(p.ncol) * 8u;  // one level of a field
+    double *P = smem + HB * 64 + lane;                     // P[k*64],  k in [-HB, M+HB)
+    double *RW = smem + (M + 2 * HB) * 64 + N * 64 + lane;  // RW[k*64], k in [-N, M+N)
     const double lam = p.lambda, g = p.grav;
 
-    // A: explicit Schur right-hand-side pieces
-    for (int k = 0; k < M; ++k) {
-        const long n = (long)k * ncol + cc;
-        double re = 0.0, we = 0.0, te = 0.0;
-        for (int t = 0; t < p.nr; ++t) re += p.cr[t] * p.er[t][n];
-        for (int t = 0; t < p.nw; ++t) we += p.cw[t] * p.ew[t][n];
-        for (int t = 0; t < p.nt; ++t) te += p.ct[t] * p.et[t][n];
-        const double r0 = p.rho0[k], G0 = p.G0[k], H0 = p.H0[k];
-        const bool wall = (k == 0) || (k == M - 1);
-        double wa = wall ? 0.0 : we + lam * g * H0 * te / (G0 * r0);
-        P[k * 64 + lane] = G0 * re + H0 * te;
-        RW[k * 64 + lane] = r0 * wa;
+    for (int k = 1; k <= HB; ++k) {
+        P[-k * 64] = 0.0;
+        P[(M - 1 + k) * 64] = 0.0;
     }
-    __syncthreads();
+    for (int k = 1; k <= N; ++k) {
+        RW[-k * 64] = 0.0;
+        RW[(M - 1 + k) * 64] = 0.0;
+    }
+
+    // A: explicit Schur right-hand-side pieces P_e = G0 rho_e + H0 theta_e and
+    //    rho0 w_a, w_a = B (w_e + lambda g H0 theta_e / (G0 rho0))
+    for (int k0 = 0; k0 < M; k0 += CB) {
+        double re[CB], we[CB], te[CB];
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+            const int k = min(k0 + b, M - 1);
+            const unsigned off = unsigned(k) * lbytes + cbyte;
+            re[b] = 0.0; we[b] = 0.0; te[b] = 0.0;
+#pragma unroll
+            for (int t = 0; t < SH::NR; ++t) re[b] += p.cr[t] * gload(p.er[t], off);
+#pragma unroll
+            for (int t = 0; t < SH::NW; ++t) we[b] += p.cw[t] * gload(p.ew[t], off);
+#pragma unroll
+            for (int t = 0; t < SH::NT; ++t) te[b] += p.ct[t] * gload(p.et[t], off);
+        }
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+            const int k = k0 + b;
+            if (k < M) {
+                const double r0 = p.rho0[k], G0 = p.G0[k], H0 = p.H0[k];
+                const bool wall = (k == 0) || (k == M - 1);
+                const double wa = wall ? 0.0 : we[b] + lam * g * H0 * te[b] / (G0 * r0);
+                P[k * 64] = G0 * re[b] + H0 * te[b];
+                RW[k * 64] = r0 * wa;
+            }
+        }
+    }
     // B: rhs = P_e - lambda G0 Dz(rho0 w_a); forward substitution (unit L)
-    for (int k = 0; k < M; ++k) {
-        const double *b = p.dzb + (long)k * NS;
-        double d = 0.0;
+    for (int k0 = 0; k0 < M; k0 += CB) {
+        double Lf[CB][HB];
 #pragma unroll
-        for (int m = 0; m < NS; ++m) {
-            int kk = k - N + m;
-            if (kk >= 0 && kk < M) d += b[m] * RW[kk * 64 + lane];
-        }
-        double y = P[k * 64 + lane] - lam * p.G0[k] * d;
-        const double *f = p.fac + (long)k * NB * ncol + cc;
+        for (int b = 0; b < CB; ++b) {
+            const int k = min(k0 + b, M - 1);
+            const double *f = reinterpret_cast<const double *>(reinterpret_cast<const char *>(p.fac) + cbyte) +
+                              (long)k * NB * p.ncol;
 #pragma unroll
-        for (int dd = 1; dd <= HB; ++dd) {
-            if (k - dd >= 0) y -= f[(long)(HB - dd) * ncol] * P[(k - dd) * 64 + lane];
+            for (int d = 0; d < HB; ++d) Lf[b][d] = f[(long)d * p.ncol];  // column k - HB + d
         }
-        P[k * 64 + lane] = y;
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+            const int k = k0 + b;
+            if (k < M) {
+                const double *bz = p.dzb + (long)k * NS;
+                double d = 0.0;
+#pragma unroll
+                for (int m = 0; m < NS; ++m) d += bz[m] * RW[(k - N + m) * 64];
+                double y = P[k * 64] - lam * p.G0[k] * d;
+#pragma unroll
+                for (int dd = 0; dd < HB; ++dd) y -= Lf[b][dd] * P[(k - HB + dd) * 64];
+                P[k * 64] = y;
+            }
+        }
     }
-    // C: backward substitution (U, reciprocal diagonal stored)
-    for (int k = M - 1; k >= 0; --k) {
-        const double *f = p.fac + (long)k * NB * ncol + cc;
-        double x = P[k * 64 + lane];
+    // C: backward substitution (U; the reciprocal pivot is stored)
+    for (int k1 = M - 1; k1 >= 0; k1 -= CB) {
+        double Uf[CB][HB + 1];
 #pragma unroll
-        for (int dd = 1; dd <= HB; ++dd) {
-            if (k + dd < M) x -= f[(long)(HB + dd) * ncol] * P[(k + dd) * 64 + lane];
+        for (int b = 0; b < CB; ++b) {
+            const int k = max(k1 - b, 0);
+            const double *f = reinterpret_cast<const double *>(reinterpret_cast<const char *>(p.fac) + cbyte) +
+                              ((long)k * NB + HB) * p.ncol;
+#pragma unroll
+            for (int d = 0; d <= HB; ++d) Uf[b][d] = f[(long)d * p.ncol];  // column k + d
         }
-        P[k * 64 + lane] = x * f[(long)HB * ncol];
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+            const int k = k1 - b;
+            if (k >= 0) {
+                double x = P[k * 64];
+#pragma unroll
+                for (int dd = 1; dd <= HB; ++dd) x -= Uf[b][dd] * P[(k + dd) * 64];
+                P[k * 64] = x * Uf[b][0];
+            }
+        }
     }
-    // D: w~ = B (w_a - lambda (Dz P / rho0 + g P /(G0 rho0)))
-    for (int k = 0; k < M; ++k) {
-        const double *b = p.dzb + (long)k * NS;
-        double d = 0.0;
+    // D: w~ = B (w_a - lambda (Dz P / rho0 + g P / (G0 rho0))); out_w = w~ + shifts
+    for (int k0 = 0; k0 < M; k0 += CB) {
+        double sh[CB];
 #pragma unroll
-        for (int m = 0; m < NS; ++m) {
-            int kk = k - N + m;
-            if (kk >= 0 && kk < M) d += b[m] * P[kk * 64 + lane];
+        for (int b = 0; b < CB; ++b) {
+            const int k = min(k0 + b, M - 1);
+            const unsigned off = unsigned(k) * lbytes + cbyte;
+            sh[b] = 0.0;
+#pragma unroll
+            for (int t = 0; t < SH::NBW; ++t) sh[b] += p.cbw[t] * gload(p.bw[t], off);
         }
-        const double r0 = p.rho0[k];
-        const bool wall = (k == 0) || (k == M - 1);
-        const double wa = RW[k * 64 + lane] / r0;
-        const double wt = wall ? 0.0 : wa - lam * (d / r0 + g * P[k * 64 + lane] / (p.G0[k] * r0));
-        RW[k * 64 + lane] = r0 * wt;
-        const long n = (long)k * ncol + cc;
-        double wout = wt;
-        for (int t = 0; t < p.nbw; ++t) wout += p.cbw[t] * p.bw[t][n];
-        if (act) p.out_w[n] = wout;
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+            const int k = k0 + b;
+            if (k < M) {
+                const double *bz = p.dzb + (long)k * NS;
+                double d = 0.0;
+#pragma unroll
+                for (int m = 0; m < NS; ++m) d += bz[m] * P[(k - N + m) * 64];
+                const double r0 = p.rho0[k];
+                const bool wall = (k == 0) || (k == M - 1);
+                const double wa = RW[k * 64] / r0;
+                const double wt = wall ? 0.0 : wa - lam * (d / r0 + g * P[k * 64] / (p.G0[k] * r0));
+                RW[k * 64] = r0 * wt;
+                if (act) gstore(p.out_w, unsigned(k) * lbytes + cbyte, wt + sh[b]);
+            }
+        }
     }
     // E: rho' = q_e,rho - lambda Dz(rho0 w~)
-    for (int k = 0; k < M; ++k) {
-        const double *b = p.dzb + (long)k * NS;
-        double d = 0.0;
+    for (int k0 = 0; k0 < M; k0 += CB) {
+        double qr[CB];
 #pragma unroll
-        for (int m = 0; m < NS; ++m) {
-            int kk = k - N + m;
-            if (kk >= 0 && kk < M) d += b[m] * RW[kk * 64 + lane];
+        for (int b = 0; b < CB; ++b) {
+            const int k = min(k0 + b, M - 1);
+            const unsigned off = unsigned(k) * lbytes + cbyte;
+            qr[b] = 0.0;
+#pragma unroll
+            for (int t = 0; t < SH::NBR; ++t) qr[b] += p.cbr[t] * gload(p.br[t], off);
         }
-        const long n = (long)k * ncol + cc;
-        double r = 0.0;
-        for (int t = 0; t < p.nbr; ++t) r += p.cbr[t] * p.br[t][n];
-        if (act) p.out_r[n] = r - lam * d;
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+            const int k = k0 + b;
+            if (k < M) {
+                const double *bz = p.dzb + (long)k * NS;
+                double d = 0.0;
+#pragma unroll
+                for (int m = 0; m < NS; ++m) d += bz[m] * RW[(k - N + m) * 64];
+                if (act) gstore(p.out_r, unsigned(k) * lbytes + cbyte, qr[b] - lam * d);
+            }
+        }
     }
 }
 
@@ -558,7 +640,7 @@ hipError_t rhs_launch(numa_ctx *c, RhsParams p)
     return hipGetLastError();
 }
 
-template <int N>
+template <int N, class SH>
 hipError_t solve_launch(numa_ctx *c, SolveParams p)
 {
     p.fac = c->fac;
@@ -570,9 +652,9 @@ hipError_t solve_launch(numa_ctx *c, SolveParams p)
     p.grav = c->eos.grav;
     p.nz = int(c->nz);
     p.ncol = c->ncol;
-    size_t shm = size_t(2) * c->nz * 64 * sizeof(double);
+    const size_t shm = size_t(2 * c->nz + 6 * N) * 64 * sizeof(double);
     dim3 grid(unsigned((c->ncol + 63) / 64));
-    hipLaunchKernelGGL((k_colsolve<N>), grid, dim3(64), shm, c->stream, p);
+    hipLaunchKernelGGL((k_colsolve<N, SH>), grid, dim3(64), shm, c->stream, p);
     return hipGetLastError();
 }
 
@@ -670,11 +752,10 @@ hipError_t launch_solve_plain(numa_ctx *c, const double *y, double *x)
 {
     const long np = c->np;
     SolveParams p{};
-    p.er[0] = y + 0 * np; p.cr[0] = 1.0; p.nr = 1;
-    p.ew[0] = y + 3 * np; p.cw[0] = 1.0; p.nw = 1;
-    p.et[0] = y + 4 * np; p.ct[0] = 1.0; p.nt = 1;
-    p.br[0] = y + 0 * np; p.cbr[0] = 1.0; p.nbr = 1;
-    p.nbw = 0;
+    p.er[0] = y + 0 * np; p.cr[0] = 1.0;
+    p.ew[0] = y + 3 * np; p.cw[0] = 1.0;
+    p.et[0] = y + 4 * np; p.ct[0] = 1.0;
+    p.br[0] = y + 0 * np; p.cbr[0] = 1.0;
     p.out_r = x + 0 * np;
     p.out_w = x + 3 * np;
     hipError_t e;
@@ -682,7 +763,7 @@ hipError_t launch_solve_plain(numa_ctx *c, const double *y, double *x)
         e = hipMemcpyAsync(x + f * np, y + f * np, sizeof(double) * np, hipMemcpyDeviceToDevice, c->stream);
         if (e != hipSuccess) return e;
     }
-    return dispatch(c->N, [&](auto n) { return solve_launch<decltype(n)::value>(c, p); });
+    return dispatch(c->N, [&](auto n) { return solve_launch<decltype(n)::value, ShapePlain>(c, p); });
 }
 
 // One ARK2 step in the q~ form (Sec. 2.2):
@@ -717,14 +798,14 @@ hipError_t launch_hevi_step(numa_ctx *c, double *q, double dt, hipEvent_t *ev)
     {
         SolveParams p{};
         const double f = dt * t.a21;
-        p.er[0] = R1 + 0 * np; p.cr[0] = f; p.nr = 1;
-        p.ew[0] = R1 + 3 * np; p.cw[0] = f; p.nw = 1;
-        p.et[0] = R1 + 4 * np; p.ct[0] = f; p.nt = 1;
-        p.br[0] = qr; p.cbr[0] = 1.0; p.br[1] = R1 + 0 * np; p.cbr[1] = f; p.nbr = 2;
-        p.bw[0] = qw; p.cbw[0] = 1.0; p.nbw = 1;
+        p.er[0] = R1 + 0 * np; p.cr[0] = f;
+        p.ew[0] = R1 + 3 * np; p.cw[0] = f;
+        p.et[0] = R1 + 4 * np; p.ct[0] = f;
+        p.br[0] = qr; p.cbr[0] = 1.0; p.br[1] = R1 + 0 * np; p.cbr[1] = f;
+        p.bw[0] = qw; p.cbw[0] = 1.0;
         p.out_r = s.Q2r;
         p.out_w = s.Q2w;
-        e = dispatch(c->N, [&](auto n) { return solve_launch<decltype(n)::value>(c, p); });
+        e = dispatch(c->N, [&](auto n) { return solve_launch<decltype(n)::value, ShapeStage2>(c, p); });
         if (e != hipSuccess) return e;
         if ((e = mark(2)) != hipSuccess) return e;
     }
@@ -754,15 +835,15 @@ hipError_t launch_hevi_step(numa_ctx *c, double *q, double dt, hipEvent_t *ev)
     {
         SolveParams p{};
         const double f = dt * t.a21;
-        p.er[0] = s.E3 + 0 * np; p.cr[0] = 1.0; p.er[1] = qr; p.cr[1] = t.c31; p.er[2] = s.Q2r; p.cr[2] = t.c32; p.nr = 3;
-        p.ew[0] = s.E3 + 3 * np; p.cw[0] = 1.0; p.ew[1] = qw; p.cw[1] = t.c31; p.ew[2] = s.Q2w; p.cw[2] = t.c32; p.nw = 3;
+        p.er[0] = s.E3 + 0 * np; p.cr[0] = 1.0; p.er[1] = qr; p.cr[1] = t.c31; p.er[2] = s.Q2r; p.cr[2] = t.c32;
+        p.ew[0] = s.E3 + 3 * np; p.cw[0] = 1.0; p.ew[1] = qw; p.cw[1] = t.c31; p.ew[2] = s.Q2w; p.cw[2] = t.c32;
         p.et[0] = s.E3 + 4 * np; p.ct[0] = 1.0; p.et[1] = qt; p.ct[1] = t.c31 + t.c32; p.et[2] = R1 + 4 * np;
-        p.ct[2] = t.c32 * f; p.nt = 3;
-        p.br[0] = s.E3 + 0 * np; p.cbr[0] = 1.0; p.nbr = 1;
-        p.bw[0] = qw; p.cbw[0] = -t.c31; p.bw[1] = s.Q2w; p.cbw[1] = -t.c32; p.nbw = 2;
+        p.ct[2] = t.c32 * f;
+        p.br[0] = s.E3 + 0 * np; p.cbr[0] = 1.0;
+        p.bw[0] = qw; p.cbw[0] = -t.c31; p.bw[1] = s.Q2w; p.cbw[1] = -t.c32;
         p.out_r = s.Q3r;
         p.out_w = s.Q3w;
-        e = dispatch(c->N, [&](auto n) { return solve_launch<decltype(n)::value>(c, p); });
+        e = dispatch(c->N, [&](auto n) { return solve_launch<decltype(n)::value, ShapeStage3>(c, p); });
         if (e != hipSuccess) return e;
         if ((e = mark(4)) != hipSuccess) return e;
     }
