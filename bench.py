@@ -39,16 +39,30 @@ def kernel_bytes(np_, ncol, nz, N):
     ]
 
 
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1702_04316_amd", "csrc", "kernels.hip")
+
+
+def kernel_source_hash():
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
 def load_traffic():
-    """Measured HBM bytes per launch from the committed rocprofv3 counter summary, if any."""
+    """Measured HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by the
+    copy calibration) from the committed rocprofv3 counter summary; None if
+    there is none or the kernels changed since the counters were taken."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
     with open(p) as f:
-        return json.load(f)
+        t = json.load(f)
+    if t.get("kernels_sha256") != kernel_source_hash():
+        return None
+    return t
 
 
-def cpu_baseline(sample_nex=32, steps=6):
+def cpu_baseline(sample_nex=32, steps=60):
     import numpy as np
     from oracle import oracle as O
     from paper_1702_04316_amd import workloads as W
@@ -67,16 +81,38 @@ def cpu_baseline(sample_nex=32, steps=6):
             "seconds": t}
 
 
+def copy_probe(nbytes=1 << 30, reps=10):
+    """A plain device-to-device copy of known size: the achievable HBM rate,
+    and the calibration program for the FETCH_SIZE/WRITE_SIZE counters."""
+    import torch
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    return {"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps,
+            "ms_per_copy": 1e3 * t, "copy_GBps": 2 * nbytes / t / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true", help="only time a plain 1 GiB device copy")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.copy_probe:
+        print(json.dumps(copy_probe()), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -111,8 +147,8 @@ def main():
     achieved = kb[dom][1] / (ms[dom] * 1e-3) / 1e9
     traffic = load_traffic()
     t_bytes = None
-    if traffic and traffic.get("kernel") == kb[dom][0]:
-        t_bytes = traffic.get("bytes_per_launch")
+    if traffic:
+        t_bytes = traffic.get("bytes_per_launch", {}).get(kb[dom][0])
     step_bytes = info["step_bytes"]
     out = {
         "metric": "HEVI DOF-steps/s on 1 GPU; speedup vs plain FP64 at fixed rel. L2 error",

@@ -381,60 +381,76 @@ using ShapePlain = SolveShape<1, 1, 1, 1, 0>;
 using ShapeStage2 = SolveShape<1, 1, 1, 2, 1>;
 using ShapeStage3 = SolveShape<3, 3, 3, 1, 2>;
 
+template <int N>
+struct SolveGeom {
+    static constexpr int HB = 2 * N;   // half-bandwidth of S
+    static constexpr int CB = 8;       // levels per block of the substitutions
+    // ring of rho0*w levels: holds the 2N+1 band window of a whole block
+    static constexpr int R = (2 * N + CB) <= 16 ? 16 : ((2 * N + CB) <= 32 ? 32 : 64);
+    static size_t lds_bytes(int M) { return size_t(R + M + HB) * 64 * sizeof(double); }
+};
+
 template <int N, class SH>
 __global__ __launch_bounds__(64) void k_colsolve(SolveParams p)
 {
+    using G = SolveGeom<N>;
     extern __shared__ double smem[];
-    constexpr int NS = 2 * N + 1, NB = 4 * N + 1, HB = 2 * N, CB = 8;
+    constexpr int NS = 2 * N + 1, NB = 4 * N + 1, HB = G::HB, CB = G::CB, R = G::R;
     const int lane = threadIdx.x;
     const long col = (long)blockIdx.x * 64 + lane;
     const bool act = col < p.ncol;
     const unsigned cbyte = unsigned(act ? col : 0) * 8u;
     const int M = p.nz;
     const unsigned lbytes = unsigned(p.ncol) * 8u;  // one level of a field
-    double *P = smem + HB * 64 + lane;                     // P[k*64],  k in [-HB, M+HB)
-    double *RW = smem + (M + 2 * HB) * 64 + N * 64 + lane;  // RW[k*64], k in [-N, M+N)
+    // LDS: [ring of rho0*w: R levels][P: M levels][HB zero levels].  The
+    // substitutions and band sums read up to HB levels outside [0, M); there
+    // the factor or band coefficient is exactly 0 and the LDS holds finite
+    // values (ring or zero levels), so those terms vanish.
+    double *W = smem + lane;                   // W[(k & (R-1)) * 64]
+    double *P = smem + R * 64 + lane;          // P[k * 64], k in [-R, M + HB)
     const double lam = p.lambda, g = p.grav;
+    for (int k = 0; k < R; ++k) W[k * 64] = 0.0;
+    for (int k = 0; k < HB; ++k) P[(M + k) * 64] = 0.0;
 
-    for (int k = 1; k <= HB; ++k) {
-        P[-k * 64] = 0.0;
-        P[(M - 1 + k) * 64] = 0.0;
-    }
-    for (int k = 1; k <= N; ++k) {
-        RW[-k * 64] = 0.0;
-        RW[(M - 1 + k) * 64] = 0.0;
-    }
+    // explicit-estimate values of level k: rho_e, w_e, theta_e
+    auto estimates = [&](int k, double &re, double &we, double &te) {
+        const unsigned off = unsigned(k) * lbytes + cbyte;
+        re = 0.0; we = 0.0; te = 0.0;
+#pragma unroll
+        for (int t = 0; t < SH::NR; ++t) re += p.cr[t] * gload(p.er[t], off);
+#pragma unroll
+        for (int t = 0; t < SH::NW; ++t) we += p.cw[t] * gload(p.ew[t], off);
+#pragma unroll
+        for (int t = 0; t < SH::NT; ++t) te += p.ct[t] * gload(p.et[t], off);
+    };
+    // w_a = B (w_e + lambda g H0 theta_e / (G0 rho0))  (Eq. (16), A = I)
+    auto w_a = [&](int k, double we, double te) -> double {
+        const bool wall = (k == 0) || (k == M - 1);
+        return wall ? 0.0 : we + lam * g * p.H0[k] * te / (p.G0[k] * p.rho0[k]);
+    };
 
-    // A: explicit Schur right-hand-side pieces P_e = G0 rho_e + H0 theta_e and
-    //    rho0 w_a, w_a = B (w_e + lambda g H0 theta_e / (G0 rho0))
+    // ---- forward: P_e and rho0 w_a run N levels ahead of the substitution
+    //      y_k = P_e,k - lambda G0 Dz(rho0 w_a)_k - sum_d L_kd y_{k-d}
+    int ahead = 0;  // levels whose P_e and rho0 w_a are in LDS
     for (int k0 = 0; k0 < M; k0 += CB) {
-        double re[CB], we[CB], te[CB];
+        const int kend = min(M, k0 + CB + N);
+        {
+            double re[CB + N], we[CB + N], te[CB + N];
 #pragma unroll
-        for (int b = 0; b < CB; ++b) {
-            const int k = min(k0 + b, M - 1);
-            const unsigned off = unsigned(k) * lbytes + cbyte;
-            re[b] = 0.0; we[b] = 0.0; te[b] = 0.0;
-#pragma unroll
-            for (int t = 0; t < SH::NR; ++t) re[b] += p.cr[t] * gload(p.er[t], off);
-#pragma unroll
-            for (int t = 0; t < SH::NW; ++t) we[b] += p.cw[t] * gload(p.ew[t], off);
-#pragma unroll
-            for (int t = 0; t < SH::NT; ++t) te[b] += p.ct[t] * gload(p.et[t], off);
-        }
-#pragma unroll
-        for (int b = 0; b < CB; ++b) {
-            const int k = k0 + b;
-            if (k < M) {
-                const double r0 = p.rho0[k], G0 = p.G0[k], H0 = p.H0[k];
-                const bool wall = (k == 0) || (k == M - 1);
-                const double wa = wall ? 0.0 : we[b] + lam * g * H0 * te[b] / (G0 * r0);
-                P[k * 64] = G0 * re[b] + H0 * te[b];
-                RW[k * 64] = r0 * wa;
+            for (int b = 0; b < CB + N; ++b) {
+                re[b] = we[b] = te[b] = 0.0;
+                if (ahead + b < kend) estimates(ahead + b, re[b], we[b], te[b]);
             }
+#pragma unroll
+            for (int b = 0; b < CB + N; ++b) {
+                const int k = ahead + b;
+                if (k < kend) {
+                    P[k * 64] = p.G0[k] * re[b] + p.H0[k] * te[b];
+                    W[(k & (R - 1)) * 64] = p.rho0[k] * w_a(k, we[b], te[b]);
+                }
+            }
+            ahead = kend;
         }
-    }
-    // B: rhs = P_e - lambda G0 Dz(rho0 w_a); forward substitution (unit L)
-    for (int k0 = 0; k0 < M; k0 += CB) {
         double Lf[CB][HB];
 #pragma unroll
         for (int b = 0; b < CB; ++b) {
@@ -451,7 +467,7 @@ __global__ __launch_bounds__(64) void k_colsolve(SolveParams p)
                 const double *bz = p.dzb + (long)k * NS;
                 double d = 0.0;
 #pragma unroll
-                for (int m = 0; m < NS; ++m) d += bz[m] * RW[(k - N + m) * 64];
+                for (int m = 0; m < NS; ++m) d += bz[m] * W[((k - N + m) & (R - 1)) * 64];
                 double y = P[k * 64] - lam * p.G0[k] * d;
 #pragma unroll
                 for (int dd = 0; dd < HB; ++dd) y -= Lf[b][dd] * P[(k - HB + dd) * 64];
@@ -459,7 +475,7 @@ __global__ __launch_bounds__(64) void k_colsolve(SolveParams p)
             }
         }
     }
-    // C: backward substitution (U; the reciprocal pivot is stored)
+    // ---- backward substitution (U; the reciprocal pivot is stored)
     for (int k1 = M - 1; k1 >= 0; k1 -= CB) {
         double Uf[CB][HB + 1];
 #pragma unroll
@@ -481,53 +497,48 @@ __global__ __launch_bounds__(64) void k_colsolve(SolveParams p)
             }
         }
     }
-    // D: w~ = B (w_a - lambda (Dz P / rho0 + g P / (G0 rho0))); out_w = w~ + shifts
-    for (int k0 = 0; k0 < M; k0 += CB) {
-        double sh[CB];
+    // ---- extraction: w~_k = B (w_a - lambda (Dz P / rho0 + g P / (G0 rho0))),
+    //      w out = w~ + shifts; then, N levels behind,
+    //      rho'_k = q_e,rho - lambda Dz(rho0 w~)  (rho0 w~ in the ring)
+    for (int k0 = 0; k0 < M + N; k0 += CB) {
+        double wt_out[CB], qr[CB];
 #pragma unroll
         for (int b = 0; b < CB; ++b) {
             const int k = min(k0 + b, M - 1);
+            double re, we, te;
+            estimates(k, re, we, te);
+            double sh = 0.0;
             const unsigned off = unsigned(k) * lbytes + cbyte;
-            sh[b] = 0.0;
 #pragma unroll
-            for (int t = 0; t < SH::NBW; ++t) sh[b] += p.cbw[t] * gload(p.bw[t], off);
-        }
+            for (int t = 0; t < SH::NBW; ++t) sh += p.cbw[t] * gload(p.bw[t], off);
+            const double *bz = p.dzb + (long)k * NS;
+            double d = 0.0;
 #pragma unroll
-        for (int b = 0; b < CB; ++b) {
-            const int k = k0 + b;
-            if (k < M) {
-                const double *bz = p.dzb + (long)k * NS;
-                double d = 0.0;
-#pragma unroll
-                for (int m = 0; m < NS; ++m) d += bz[m] * P[(k - N + m) * 64];
-                const double r0 = p.rho0[k];
-                const bool wall = (k == 0) || (k == M - 1);
-                const double wa = RW[k * 64] / r0;
-                const double wt = wall ? 0.0 : wa - lam * (d / r0 + g * P[k * 64] / (p.G0[k] * r0));
-                RW[k * 64] = r0 * wt;
-                if (act) gstore(p.out_w, unsigned(k) * lbytes + cbyte, wt + sh[b]);
-            }
-        }
-    }
-    // E: rho' = q_e,rho - lambda Dz(rho0 w~)
-    for (int k0 = 0; k0 < M; k0 += CB) {
-        double qr[CB];
-#pragma unroll
-        for (int b = 0; b < CB; ++b) {
-            const int k = min(k0 + b, M - 1);
-            const unsigned off = unsigned(k) * lbytes + cbyte;
+            for (int m = 0; m < NS; ++m) d += bz[m] * P[(k - N + m) * 64];
+            const double r0 = p.rho0[k];
+            const bool wall = (k == 0) || (k == M - 1);
+            const double wt = wall ? 0.0 : w_a(k, we, te) - lam * (d / r0 + g * P[k * 64] / (p.G0[k] * r0));
+            wt_out[b] = wt + sh;
+            if (k0 + b < M) W[(k & (R - 1)) * 64] = r0 * wt;
+            const int ke = max(k0 + b - N, 0);
+            const unsigned offe = unsigned(ke) * lbytes + cbyte;
             qr[b] = 0.0;
 #pragma unroll
-            for (int t = 0; t < SH::NBR; ++t) qr[b] += p.cbr[t] * gload(p.br[t], off);
+            for (int t = 0; t < SH::NBR; ++t) qr[b] += p.cbr[t] * gload(p.br[t], offe);
         }
 #pragma unroll
         for (int b = 0; b < CB; ++b) {
             const int k = k0 + b;
-            if (k < M) {
+            if (act && k < M) gstore(p.out_w, unsigned(k) * lbytes + cbyte, wt_out[b]);
+        }
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+            const int k = k0 + b - N;  // the rho0 w~ band of level k is complete
+            if (k >= 0 && k < M) {
                 const double *bz = p.dzb + (long)k * NS;
                 double d = 0.0;
 #pragma unroll
-                for (int m = 0; m < NS; ++m) d += bz[m] * RW[(k - N + m) * 64];
+                for (int m = 0; m < NS; ++m) d += bz[m] * W[((k - N + m) & (R - 1)) * 64];
                 if (act) gstore(p.out_r, unsigned(k) * lbytes + cbyte, qr[b] - lam * d);
             }
         }
@@ -652,7 +663,7 @@ hipError_t solve_launch(numa_ctx *c, SolveParams p)
     p.grav = c->eos.grav;
     p.nz = int(c->nz);
     p.ncol = c->ncol;
-    const size_t shm = size_t(2 * c->nz + 6 * N) * 64 * sizeof(double);
+    const size_t shm = SolveGeom<N>::lds_bytes(int(c->nz));
     dim3 grid(unsigned((c->ncol + 63) / 64));
     hipLaunchKernelGGL((k_colsolve<N, SH>), grid, dim3(64), shm, c->stream, p);
     return hipGetLastError();
