@@ -108,12 +108,13 @@ int numa_setup(const numa_grid *g, int32_t order, const numa_background *bg, voi
     c->eos.rgas = bg->rgas;
     c->eos.gamma = bg->cp / (bg->cp - bg->rgas);
     c->eos.grav = bg->grav;
+    numa::set_binomial(c->eos);
     c->stream = static_cast<hipStream_t>(hip_stream);
 
     numa::build_ops(c, g->zface);
 
     const int N = order, ns = 2 * N + 1;
-    const size_t n_lev = size_t(4 * nz + nz * ns + 3 * g->nez + 2 * N * ns + (N + 1) * (N + 1));
+    const size_t n_lev = size_t(4 * nz + nz * ns + 3 * g->nez + 2 * N * ns + (N + 1) * (N + 1) + 8 * nz);
     hipError_t e = hipMalloc(&c->lev_block, n_lev * sizeof(double));
     if (e != hipSuccess) {
         int rc = hip_fail(nullptr, e, "numa_setup: hipMalloc(levels)");
@@ -128,7 +129,8 @@ int numa_setup(const numa_grid *g, int32_t order, const numa_background *bg, voi
     c->lev.dzb = p; p += nz * ns;
     c->lev.zsc = p; p += 3 * g->nez;
     c->lev.wxy = p; p += 2 * N * ns;
-    c->lev.D = p;
+    c->lev.D = p; p += (N + 1) * (N + 1);
+    c->lev.scf = p;
 
     const size_t fac_n = size_t(c->ncol) * size_t(nz) * size_t(4 * N + 1);
     const size_t work_n = size_t(19) * size_t(c->np);
@@ -308,7 +310,7 @@ int numa_line_operators(const numa_grid *g, int32_t order, double *wxy, double *
     c.ly = g->ly;
     c.lz = g->lz;
     c.cp = 1004.67;  // background is not used by the operators; any valid constants
-    c.eos = {300.0, 1.0e5, 287.17, 1.4, 0.0};
+    c.eos = {300.0, 1.0e5, 287.17, 1.4, 0.0, {}};
     numa::build_ops(&c, g->zface);
     std::memcpy(wxy, c.ops.wxy.data(), c.ops.wxy.size() * sizeof(double));
     std::memcpy(dzb, c.ops.dzb.data(), c.ops.dzb.size() * sizeof(double));

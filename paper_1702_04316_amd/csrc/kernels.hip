@@ -73,14 +73,26 @@ __device__ __forceinline__ double eos_pressure(double rho, double theta, const E
 // rho0 theta', theta0 rho' and rho' theta' nearly cancel in a balanced state:
 // each product is split into rounded value + exact error (fma), so their
 // small sum keeps its relative precision (no contraction may touch this).
-__device__ __forceinline__ double pressure_perturbation(double rp, double th, double r0, double P0, const EOS &e)
+// With x = (rho theta - rho0 theta0)/(rho0 theta0), P' = P0 ((1 + x)^gamma - 1):
+// a 10-term binomial series for |x| <= 1/32 (every state of a weather
+// perturbation; the first omitted term is below 1e-18 relative), log1p/expm1
+// beyond.
+// irt = 1/(rho0 theta0) of the level.
+__device__ __forceinline__ double pressure_perturbation(double rp, double th, double r0, double P0, double irt,
+                                                        const EOS &e)
 {
 #pragma clang fp contract(off)
     const double t0 = e.theta0;
     const double p1 = r0 * th, p2 = t0 * rp, p3 = rp * th;
     const double e1 = __builtin_fma(r0, th, -p1), e2 = __builtin_fma(t0, rp, -p2), e3 = __builtin_fma(rp, th, -p3);
     const double d = ((p1 + p2) + p3) + ((e1 + e2) + e3);
-    return P0 * expm1(e.gamma * log1p(d / (r0 * t0)));
+    const double x = d * irt;
+    if (fabs(x) > kBinomMaxX) return P0 * expm1(e.gamma * log1p(x));
+    // (1 + x)^gamma - 1 by its binomial series, Horner form
+    double s = e.binom[kBinomTerms - 1];
+#pragma unroll
+    for (int k = kBinomTerms - 2; k >= 0; --k) s = __builtin_fma(s, x, e.binom[k]);
+    return P0 * (s * x);
 }
 
 // Global access as (uniform 64-bit base) + (32-bit per-lane byte offset):
@@ -96,8 +108,9 @@ __device__ __forceinline__ void gstore(double *base, unsigned off, double v)
 }
 
 struct RhsParams {
-    const double *a[5];     // input fields (rho', u, v, w, theta')
-    const double *b[5];     // increments (HASB): input = a + cb * b; null entries = none
+    // input fields (rho', u, v, w, theta'); with HASB, u, v, theta' of the
+    // input are e0 + cb * e1 (a[1], a[2], a[4] unused)
+    const double *a[5];
     double cb;
     double *out0[5];
     double *out1[5];
@@ -122,15 +135,14 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
     return x < r ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
 }
 
-// Stage input of field f at byte offset off (a + cb*b where b exists).
+// Stage input of field f at byte offset off.
 template <bool HASB>
 __device__ __forceinline__ double stage_input(const RhsParams &p, int f, unsigned off)
 {
-    double v = gload(p.a[f], off);
     if constexpr (HASB) {
-        if (f == 1 || f == 2 || f == 4) v += p.cb * gload(p.b[f], off);
+        if (f == 1 || f == 2 || f == 4) return gload(p.e0[f], off) + p.cb * gload(p.e1[f], off);
     }
-    return v;
+    return gload(p.a[f], off);
 }
 
 template <int N, int EPI, bool HASB>
@@ -138,7 +150,9 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
 {
     using G = RhsGeom<N>;
     constexpr int NQ = N + 1, NS = G::NS, TX = G::TX, TY = G::TY, LX = G::LX, FS = G::FS, PS = G::PS;
-    extern __shared__ double ring[];  // [N+1][6][LY][LX]
+    // dynamic LDS: ring [N+1][6][LY][LX], then per-level tables rho0, P0,
+    // 1/(rho0 theta0) for the levels this chunk touches, then zsc [3][nez]
+    extern __shared__ double ring[];
     __shared__ double sw[2][N][NS];
     __shared__ double sD[NQ * NQ];
 
@@ -151,9 +165,25 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
     const int x0 = txb * TX, y0 = tyb * TY;
     const int nx = p.nx, ny = p.ny;
     const unsigned pbytes = unsigned(nx) * unsigned(ny) * 8u;
+    const int ez0 = chunk * p.zchunk;
+    const int ez1 = min(p.nez, ez0 + p.zchunk);
+    const int kb = max(ez0 - 1, 0) * N;          // lowest level in the tables
+    const int nlev = ez1 * N + 1 - kb;
+    double *sR0 = ring + (N + 1) * PS;
+    double *sP0 = sR0 + nlev;
+    double *sIRT = sP0 + nlev;
+    double *zs = sIRT + nlev;  // [0,nez): 2/h ; [nez,2nez): bottom factor ; [2nez,3nez): top factor
+    const EOS eos = p.eos;
 
     for (int s = tid; s < 2 * N * NS; s += G::NT) (&sw[0][0][0])[s] = p.wxy[s];
     for (int s = tid; s < NQ * NQ; s += G::NT) sD[s] = p.D[s];
+    for (int s = tid; s < nlev; s += G::NT) {
+        const double r0 = p.rho0[kb + s];
+        sR0[s] = r0;
+        sP0[s] = p.P0[kb + s];
+        sIRT[s] = 1.0 / (r0 * eos.theta0);
+    }
+    for (int s = tid; s < 3 * p.nez; s += G::NT) zs[s] = p.zsc[s];
 
     // plane loads of this thread: which of the N new planes (1..N, 0 = none),
     // LDS offset in the plane, byte offset in a level plane
@@ -176,8 +206,11 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
         if (gi < 0) gi += nx;
         int gj = (y0 - N + ly) % ny;
         if (gj < 0) gj += ny;
-        it_p[s] = item < N * G::NCROSS ? pl + 1 : 0;
-        it_l[s] = ly * LX + lx;
+        // an item past the N planes reads level + 0 and writes a plane corner
+        // (lx, ly < N), which no stencil reads
+        const bool valid = item < N * G::NCROSS;
+        it_p[s] = valid ? pl + 1 : 0;
+        it_l[s] = valid ? ly * LX + lx : 0;
         it_o[s] = unsigned(gj * nx + gi) * 8u;
     }
 
@@ -193,22 +226,38 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
     const int l_y = (ty - ay) * LX + (tx + N);
     const double *cwx = &sw[0][0][0] + ax * NS;
     const double *cwy = &sw[1][0][0] + ay * NS;
-    const EOS eos = p.eos;
 
-    // one node of level k (with halo) into its ring slot
-    auto load_item = [&](int s, int k) {
-        const unsigned off = unsigned(k) * pbytes + it_o[s];
-        const double rp = stage_input<HASB>(p, 0, off), u = stage_input<HASB>(p, 1, off);
-        const double v = stage_input<HASB>(p, 2, off), w = stage_input<HASB>(p, 3, off);
-        const double th = stage_input<HASB>(p, 4, off);
-        const double Pp = pressure_perturbation(rp, th, p.rho0[k], p.P0[k], eos);
-        double *d = ring + (k % NQ) * PS + it_l[s];
-        d[0 * FS] = rp;
-        d[1 * FS] = u;
-        d[2 * FS] = v;
-        d[3 * FS] = w;
-        d[4 * FS] = th;
-        d[5 * FS] = Pp;
+    // the N new planes above level kbase into their ring slots: every load of
+    // every item is issued before the first is used (no item branches)
+    auto load_planes = [&](int kbase) {
+        double v[G::NITEM][5];
+#pragma unroll
+        for (int s = 0; s < G::NITEM; ++s) {
+            const unsigned off = unsigned(kbase + it_p[s]) * pbytes + it_o[s];
+#pragma unroll
+            for (int f = 0; f < 5; ++f) v[s][f] = gload(HASB && (f == 1 || f == 2 || f == 4) ? p.e0[f] : p.a[f], off);
+        }
+        if constexpr (HASB) {
+#pragma unroll
+            for (int s = 0; s < G::NITEM; ++s) {
+                const unsigned off = unsigned(kbase + it_p[s]) * pbytes + it_o[s];
+                v[s][1] += p.cb * gload(p.e1[1], off);
+                v[s][2] += p.cb * gload(p.e1[2], off);
+                v[s][4] += p.cb * gload(p.e1[4], off);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < G::NITEM; ++s) {
+            const int k = kbase + it_p[s], kl = k - kb;
+            const double Pp = pressure_perturbation(v[s][0], v[s][4], sR0[kl], sP0[kl], sIRT[kl], eos);
+            double *d = ring + (k % NQ) * PS + it_l[s];
+            d[0 * FS] = v[s][0];
+            d[1 * FS] = v[s][1];
+            d[2 * FS] = v[s][2];
+            d[3 * FS] = v[s][3];
+            d[4 * FS] = v[s][4];
+            d[5 * FS] = Pp;
+        }
     };
 
     // sum_n D[r][n] g(level ez*N + n) over the own column for the six
@@ -222,7 +271,7 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
         for (int n = 0; n < NQ; ++n) {
             const double *q = ring + slot * PS + l_own;
             const double d = sD[r * NQ + n];
-            out[0] += d * ((p.rho0[k] + q[0]) * q[3 * FS]);
+            out[0] += d * ((sR0[k - kb] + q[0]) * q[3 * FS]);
             out[1] += d * q[1 * FS];
             out[2] += d * q[2 * FS];
             out[3] += d * q[3 * FS];
@@ -238,7 +287,7 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
     // the stage epilogue
     auto node = [&](int k, const double *dz) {
         const double *q = ring + (k % NQ) * PS;
-        const double r0 = p.rho0[k];
+        const double r0 = sR0[k - kb];
         const double rp = q[l_own], u = q[FS + l_own], v = q[2 * FS + l_own], w = q[3 * FS + l_own];
         const double ir = 1.0 / (r0 + rp);
         double dx[6] = {0, 0, 0, 0, 0, 0}, dy[6] = {0, 0, 0, 0, 0, 0};
@@ -288,29 +337,41 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
         }
     };
 
-    const int ez0 = chunk * p.zchunk;
-    const int ez1 = min(p.nez, ez0 + p.zchunk);
-    const double *zs = p.zsc;  // [0,nez): 2/h ; [nez,2nez): bottom factor ; [2nez,3nez): top factor
+    __syncthreads();  // tables are in LDS
 
     // prologue: level ez0*N into the ring (the items of the first new plane
     // cover one whole plane); the c = 0 threads take the contribution of the
     // element below to the interface at ez0*N from their own column
     double zpart[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
-    for (int s = 0; s < G::NITEM; ++s)
-        if (it_p[s] == 1) load_item(s, ez0 * N);
+    for (int s = 0; s < G::NITEM; ++s) {
+        if (it_p[s] != 1) continue;
+        const int k = ez0 * N, kl = k - kb;
+        const unsigned off = unsigned(k) * pbytes + it_o[s];
+        const double rp = stage_input<HASB>(p, 0, off), u = stage_input<HASB>(p, 1, off);
+        const double v = stage_input<HASB>(p, 2, off), w = stage_input<HASB>(p, 3, off);
+        const double th = stage_input<HASB>(p, 4, off);
+        const double Pp = pressure_perturbation(rp, th, sR0[kl], sP0[kl], sIRT[kl], eos);
+        double *d = ring + (k % NQ) * PS + it_l[s];
+        d[0 * FS] = rp;
+        d[1 * FS] = u;
+        d[2 * FS] = v;
+        d[3 * FS] = w;
+        d[4 * FS] = th;
+        d[5 * FS] = Pp;
+    }
     if (c == 0 && ez0 > 0) {
         const int eb = ez0 - 1;
         double acc[6] = {0, 0, 0, 0, 0, 0};
         for (int n = 0; n < NQ; ++n) {
-            const int k = eb * N + n;
+            const int k = eb * N + n, kl = k - kb;
             const unsigned off = unsigned(k) * pbytes + own;
             const double rp = stage_input<HASB>(p, 0, off), u = stage_input<HASB>(p, 1, off);
             const double v = stage_input<HASB>(p, 2, off), w = stage_input<HASB>(p, 3, off);
             const double th = stage_input<HASB>(p, 4, off);
-            const double rho = p.rho0[k] + rp;
-            const double Pp = pressure_perturbation(rp, th, p.rho0[k], p.P0[k], eos);
-            const double d = p.D[N * NQ + n];
+            const double rho = sR0[kl] + rp;
+            const double Pp = pressure_perturbation(rp, th, sR0[kl], sP0[kl], sIRT[kl], eos);
+            const double d = sD[N * NQ + n];
             acc[0] += d * (rho * w);
             acc[1] += d * u;
             acc[2] += d * v;
@@ -325,9 +386,7 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
 
     for (int ez = ez0; ez < ez1; ++ez) {
         __syncthreads();  // the slots about to be overwritten are no longer read
-#pragma unroll
-        for (int s = 0; s < G::NITEM; ++s)
-            if (it_p[s] > 0) load_item(s, ez * N + it_p[s]);
+        load_planes(ez * N);
         __syncthreads();
         double dz[6], sum[6];
         zsum(ez, c, sum);
@@ -349,13 +408,22 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
 
 // ---------------------------------------------------------------------------
 // Column solve.  One lane per column, 64 columns per workgroup (one
-// wavefront).  The column's pressure P and rho0*w live in LDS as
-// [level][lane] (conflict free), padded with HB zero levels below and above
-// so the band operators need no bounds tests.  The sequential band
-// substitutions run in blocks of CB levels whose factor loads are all issued
-// before the block's arithmetic: with one wavefront per SIMD that is what
-// keeps enough bytes in flight.
+// wavefront, so one wavefront per SIMD on the benchmark grid).  The column's
+// pressure P and rho0*w live in LDS as [level][lane] (conflict free), padded
+// so the band operators need no bounds tests.  Every pass walks the levels
+// once and streams its per-level global loads a fixed number of levels ahead
+// of their use (slots in registers, rotated by unrolling), keeping up to ~56
+// loads in flight per wavefront: with one wavefront per SIMD there is no
+// other wavefront to hide the memory latency.
 // ---------------------------------------------------------------------------
+// Per-level tables are read through the constant address space: their loads
+// are uniform and become scalar loads.
+typedef const __attribute__((address_space(4))) double cdouble;
+__device__ __forceinline__ cdouble *as_const(const double *p) { return (cdouble *)(p); }
+
+// per-level coefficients of the column solve, [nz][8]
+enum { SC_G0 = 0, SC_H0, SC_RHO0, SC_WA, SC_LG, SC_X1, SC_X2, SC_N = 8 };
+
 struct SolveParams {
     // q~_e for rho', w, theta': sum_t c_t * ptr_t
     const double *er[3], *ew[3], *et[3];
@@ -365,8 +433,8 @@ struct SolveParams {
     double cbr[2], cbw[2];
     double *out_r, *out_w;
     const double *fac;
-    const double *rho0, *G0, *H0, *dzb;
-    double lambda, grav;
+    const double *scf, *dzb;
+    double lambda;
     int nz;
     long ncol;
 };
@@ -381,168 +449,194 @@ using ShapePlain = SolveShape<1, 1, 1, 1, 0>;
 using ShapeStage2 = SolveShape<1, 1, 1, 2, 1>;
 using ShapeStage3 = SolveShape<3, 3, 3, 1, 2>;
 
-template <int N>
+template <int N, class SH>
 struct SolveGeom {
     static constexpr int HB = 2 * N;   // half-bandwidth of S
-    static constexpr int CB = 8;       // levels per block of the substitutions
-    // ring of rho0*w levels: holds the 2N+1 band window of a whole block
-    static constexpr int R = (2 * N + CB) <= 16 ? 16 : ((2 * N + CB) <= 32 ? 32 : 64);
+    static constexpr int NE = SH::NR + SH::NW + SH::NT;
+    static constexpr int depth(int per_level) { return 56 / per_level < 1 ? 1 : (56 / per_level > 8 ? 8 : 56 / per_level); }
+    static constexpr int DF = depth(NE + HB);                   // forward: estimates + L row
+    static constexpr int DB = depth(HB + 1);                    // backward: U row
+    static constexpr int DX = depth(1 + SH::NBW + SH::NBR);     // extraction
+    // ring of rho0*w levels (>= 2N+1 for the band window, >= HB for the
+    // reads of P below level 0)
+    static constexpr int R = (2 * N + 1) <= 16 ? 16 : 32;
     static size_t lds_bytes(int M) { return size_t(R + M + HB) * 64 * sizeof(double); }
 };
 
 template <int N, class SH>
-__global__ __launch_bounds__(64) void k_colsolve(SolveParams p)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_colsolve(SolveParams p)
 {
-    using G = SolveGeom<N>;
+    using G = SolveGeom<N, SH>;
     extern __shared__ double smem[];
-    constexpr int NS = 2 * N + 1, NB = 4 * N + 1, HB = G::HB, CB = G::CB, R = G::R;
+    constexpr int NS = 2 * N + 1, NB = 4 * N + 1, HB = G::HB, R = G::R, NE = G::NE;
+    constexpr int DF = G::DF, DB = G::DB, DX = G::DX, NXL = 1 + SH::NBW + SH::NBR;
     const int lane = threadIdx.x;
     const long col = (long)blockIdx.x * 64 + lane;
     const bool act = col < p.ncol;
     const unsigned cbyte = unsigned(act ? col : 0) * 8u;
     const int M = p.nz;
     const unsigned lbytes = unsigned(p.ncol) * 8u;  // one level of a field
+    cdouble *scf = as_const(p.scf);
+    cdouble *dzb = as_const(p.dzb);
     // LDS: [ring of rho0*w: R levels][P: M levels][HB zero levels].  The
     // substitutions and band sums read up to HB levels outside [0, M); there
     // the factor or band coefficient is exactly 0 and the LDS holds finite
     // values (ring or zero levels), so those terms vanish.
     double *W = smem + lane;                   // W[(k & (R-1)) * 64]
     double *P = smem + R * 64 + lane;          // P[k * 64], k in [-R, M + HB)
-    const double lam = p.lambda, g = p.grav;
     for (int k = 0; k < R; ++k) W[k * 64] = 0.0;
     for (int k = 0; k < HB; ++k) P[(M + k) * 64] = 0.0;
+    // row d of the factor band of level k
+    auto frow = [&](int k, int d) { return p.fac + ((long)k * NB + d) * p.ncol; };
 
-    // explicit-estimate values of level k: rho_e, w_e, theta_e
-    auto estimates = [&](int k, double &re, double &we, double &te) {
-        const unsigned off = unsigned(k) * lbytes + cbyte;
-        re = 0.0; we = 0.0; te = 0.0;
-#pragma unroll
-        for (int t = 0; t < SH::NR; ++t) re += p.cr[t] * gload(p.er[t], off);
-#pragma unroll
-        for (int t = 0; t < SH::NW; ++t) we += p.cw[t] * gload(p.ew[t], off);
-#pragma unroll
-        for (int t = 0; t < SH::NT; ++t) te += p.ct[t] * gload(p.et[t], off);
-    };
-    // w_a = B (w_e + lambda g H0 theta_e / (G0 rho0))  (Eq. (16), A = I)
-    auto w_a = [&](int k, double we, double te) -> double {
-        const bool wall = (k == 0) || (k == M - 1);
-        return wall ? 0.0 : we + lam * g * p.H0[k] * te / (p.G0[k] * p.rho0[k]);
-    };
-
-    // ---- forward: P_e and rho0 w_a run N levels ahead of the substitution
+    // ---- forward.  Step s: P_e and rho0 w_a of level s into LDS (w_a also
+    //      parked in out_w for the extraction), then the substitution of
+    //      level s - N, whose Dz(rho0 w_a) band is complete:
     //      y_k = P_e,k - lambda G0 Dz(rho0 w_a)_k - sum_d L_kd y_{k-d}
-    int ahead = 0;  // levels whose P_e and rho0 w_a are in LDS
-    for (int k0 = 0; k0 < M; k0 += CB) {
-        const int kend = min(M, k0 + CB + N);
-        {
-            double re[CB + N], we[CB + N], te[CB + N];
+    {
+        double es[DF][NE], ls[DF][HB];
+        auto load = [&](double *e, double *l, int s) {
+            const unsigned off = unsigned(min(s, M - 1)) * lbytes + cbyte;
 #pragma unroll
-            for (int b = 0; b < CB + N; ++b) {
-                re[b] = we[b] = te[b] = 0.0;
-                if (ahead + b < kend) estimates(ahead + b, re[b], we[b], te[b]);
-            }
+            for (int t = 0; t < SH::NR; ++t) e[t] = gload(p.er[t], off);
 #pragma unroll
-            for (int b = 0; b < CB + N; ++b) {
-                const int k = ahead + b;
-                if (k < kend) {
-                    P[k * 64] = p.G0[k] * re[b] + p.H0[k] * te[b];
-                    W[(k & (R - 1)) * 64] = p.rho0[k] * w_a(k, we[b], te[b]);
+            for (int t = 0; t < SH::NW; ++t) e[SH::NR + t] = gload(p.ew[t], off);
+#pragma unroll
+            for (int t = 0; t < SH::NT; ++t) e[SH::NR + SH::NW + t] = gload(p.et[t], off);
+            const int kl = min(max(s - N, 0), M - 1);
+#pragma unroll
+            for (int d = 0; d < HB; ++d) l[d] = gload(frow(kl, d), cbyte);  // column kl - HB + d
+        };
+#pragma unroll
+        for (int b = 0; b < DF; ++b) load(es[b], ls[b], b);
+        for (int s0 = 0; s0 < M + N; s0 += DF) {
+#pragma unroll
+            for (int b = 0; b < DF; ++b) {
+                const int s = s0 + b;
+                if (s < M) {
+                    double re = 0.0, we = 0.0, te = 0.0;
+#pragma unroll
+                    for (int t = 0; t < SH::NR; ++t) re += p.cr[t] * es[b][t];
+#pragma unroll
+                    for (int t = 0; t < SH::NW; ++t) we += p.cw[t] * es[b][SH::NR + t];
+#pragma unroll
+                    for (int t = 0; t < SH::NT; ++t) te += p.ct[t] * es[b][SH::NR + SH::NW + t];
+                    cdouble *cf = scf + s * SC_N;
+                    // w_a = B (w_e + lambda g H0 theta_e / (G0 rho0))  (Eq. (16), A = I)
+                    const double wa = (s == 0 || s == M - 1) ? 0.0 : we + cf[SC_WA] * te;
+                    P[s * 64] = cf[SC_G0] * re + cf[SC_H0] * te;
+                    W[(s & (R - 1)) * 64] = cf[SC_RHO0] * wa;
+                    if (act) gstore(p.out_w, unsigned(s) * lbytes + cbyte, wa);
                 }
-            }
-            ahead = kend;
-        }
-        double Lf[CB][HB];
+                const int k = s - N;
+                if (k >= 0 && k < M) {
+                    cdouble *bz = dzb + k * NS;
+                    double d = 0.0;
 #pragma unroll
-        for (int b = 0; b < CB; ++b) {
-            const int k = min(k0 + b, M - 1);
-            const double *f = reinterpret_cast<const double *>(reinterpret_cast<const char *>(p.fac) + cbyte) +
-                              (long)k * NB * p.ncol;
+                    for (int m = 0; m < NS; ++m) d += bz[m] * W[((k - N + m) & (R - 1)) * 64];
+                    double y = P[k * 64] - scf[k * SC_N + SC_LG] * d;
 #pragma unroll
-            for (int d = 0; d < HB; ++d) Lf[b][d] = f[(long)d * p.ncol];  // column k - HB + d
-        }
-#pragma unroll
-        for (int b = 0; b < CB; ++b) {
-            const int k = k0 + b;
-            if (k < M) {
-                const double *bz = p.dzb + (long)k * NS;
-                double d = 0.0;
-#pragma unroll
-                for (int m = 0; m < NS; ++m) d += bz[m] * W[((k - N + m) & (R - 1)) * 64];
-                double y = P[k * 64] - lam * p.G0[k] * d;
-#pragma unroll
-                for (int dd = 0; dd < HB; ++dd) y -= Lf[b][dd] * P[(k - HB + dd) * 64];
-                P[k * 64] = y;
+                    for (int dd = 0; dd < HB; ++dd) y -= ls[b][dd] * P[(k - HB + dd) * 64];
+                    P[k * 64] = y;
+                }
+                load(es[b], ls[b], s + DF);
             }
         }
     }
     // ---- backward substitution (U; the reciprocal pivot is stored)
-    for (int k1 = M - 1; k1 >= 0; k1 -= CB) {
-        double Uf[CB][HB + 1];
+    {
+        double us[DB][HB + 1];
+        auto load = [&](double *u, int s) {
+            const int k = max(M - 1 - s, 0);
 #pragma unroll
-        for (int b = 0; b < CB; ++b) {
-            const int k = max(k1 - b, 0);
-            const double *f = reinterpret_cast<const double *>(reinterpret_cast<const char *>(p.fac) + cbyte) +
-                              ((long)k * NB + HB) * p.ncol;
+            for (int d = 0; d <= HB; ++d) u[d] = gload(frow(k, HB + d), cbyte);  // column k + d
+        };
 #pragma unroll
-            for (int d = 0; d <= HB; ++d) Uf[b][d] = f[(long)d * p.ncol];  // column k + d
-        }
+        for (int b = 0; b < DB; ++b) load(us[b], b);
+        for (int s0 = 0; s0 < M; s0 += DB) {
 #pragma unroll
-        for (int b = 0; b < CB; ++b) {
-            const int k = k1 - b;
-            if (k >= 0) {
-                double x = P[k * 64];
+            for (int b = 0; b < DB; ++b) {
+                const int k = M - 1 - (s0 + b);
+                if (k >= 0) {
+                    double x = P[k * 64];
 #pragma unroll
-                for (int dd = 1; dd <= HB; ++dd) x -= Uf[b][dd] * P[(k + dd) * 64];
-                P[k * 64] = x * Uf[b][0];
+                    for (int dd = 1; dd <= HB; ++dd) x -= us[b][dd] * P[(k + dd) * 64];
+                    P[k * 64] = x * us[b][0];
+                }
+                load(us[b], s0 + b + DB);
             }
         }
     }
-    // ---- extraction: w~_k = B (w_a - lambda (Dz P / rho0 + g P / (G0 rho0))),
-    //      w out = w~ + shifts; then, N levels behind,
-    //      rho'_k = q_e,rho - lambda Dz(rho0 w~)  (rho0 w~ in the ring)
-    for (int k0 = 0; k0 < M + N; k0 += CB) {
-        double wt_out[CB], qr[CB];
+    // ---- extraction.  Step s: w~_s = B (w_a - lambda (Dz P / rho0 + g P /
+    //      (G0 rho0))), w out = w~ + shifts, rho0 w~ into the ring; then
+    //      rho'_k = q_e,rho - lambda Dz(rho0 w~) of level k = s - N, whose
+    //      band is complete
+    {
+        double xs[DX][NXL];
+        auto load = [&](double *x, int s) {
+            const unsigned off = unsigned(min(s, M - 1)) * lbytes + cbyte;
+            x[0] = gload(p.out_w, off);  // w_a parked by the forward pass
 #pragma unroll
-        for (int b = 0; b < CB; ++b) {
-            const int k = min(k0 + b, M - 1);
-            double re, we, te;
-            estimates(k, re, we, te);
-            double sh = 0.0;
-            const unsigned off = unsigned(k) * lbytes + cbyte;
+            for (int t = 0; t < SH::NBW; ++t) x[1 + t] = gload(p.bw[t], off);
+            const unsigned offr = unsigned(min(max(s - N, 0), M - 1)) * lbytes + cbyte;
 #pragma unroll
-            for (int t = 0; t < SH::NBW; ++t) sh += p.cbw[t] * gload(p.bw[t], off);
-            const double *bz = p.dzb + (long)k * NS;
-            double d = 0.0;
+            for (int t = 0; t < SH::NBR; ++t) x[1 + SH::NBW + t] = gload(p.br[t], offr);
+        };
 #pragma unroll
-            for (int m = 0; m < NS; ++m) d += bz[m] * P[(k - N + m) * 64];
-            const double r0 = p.rho0[k];
-            const bool wall = (k == 0) || (k == M - 1);
-            const double wt = wall ? 0.0 : w_a(k, we, te) - lam * (d / r0 + g * P[k * 64] / (p.G0[k] * r0));
-            wt_out[b] = wt + sh;
-            if (k0 + b < M) W[(k & (R - 1)) * 64] = r0 * wt;
-            const int ke = max(k0 + b - N, 0);
-            const unsigned offe = unsigned(ke) * lbytes + cbyte;
-            qr[b] = 0.0;
+        for (int b = 0; b < DX; ++b) load(xs[b], b);
+        for (int s0 = 0; s0 < M + N; s0 += DX) {
 #pragma unroll
-            for (int t = 0; t < SH::NBR; ++t) qr[b] += p.cbr[t] * gload(p.br[t], offe);
-        }
+            for (int b = 0; b < DX; ++b) {
+                const int s = s0 + b;
+                if (s < M) {
+                    cdouble *cf = scf + s * SC_N;
+                    cdouble *bz = dzb + s * NS;
+                    double d = 0.0;
 #pragma unroll
-        for (int b = 0; b < CB; ++b) {
-            const int k = k0 + b;
-            if (act && k < M) gstore(p.out_w, unsigned(k) * lbytes + cbyte, wt_out[b]);
-        }
+                    for (int m = 0; m < NS; ++m) d += bz[m] * P[(s - N + m) * 64];
+                    const double wt =
+                        (s == 0 || s == M - 1) ? 0.0 : xs[b][0] - (cf[SC_X1] * d + cf[SC_X2] * P[s * 64]);
+                    double sh = 0.0;
 #pragma unroll
-        for (int b = 0; b < CB; ++b) {
-            const int k = k0 + b - N;  // the rho0 w~ band of level k is complete
-            if (k >= 0 && k < M) {
-                const double *bz = p.dzb + (long)k * NS;
-                double d = 0.0;
+                    for (int t = 0; t < SH::NBW; ++t) sh += p.cbw[t] * xs[b][1 + t];
+                    W[(s & (R - 1)) * 64] = cf[SC_RHO0] * wt;
+                    if (act) gstore(p.out_w, unsigned(s) * lbytes + cbyte, wt + sh);
+                }
+                const int k = s - N;
+                if (k >= 0 && k < M) {
+                    cdouble *bz = dzb + k * NS;
+                    double d = 0.0;
 #pragma unroll
-                for (int m = 0; m < NS; ++m) d += bz[m] * W[((k - N + m) & (R - 1)) * 64];
-                if (act) gstore(p.out_r, unsigned(k) * lbytes + cbyte, qr[b] - lam * d);
+                    for (int m = 0; m < NS; ++m) d += bz[m] * W[((k - N + m) & (R - 1)) * 64];
+                    double qr = 0.0;
+#pragma unroll
+                    for (int t = 0; t < SH::NBR; ++t) qr += p.cbr[t] * xs[b][1 + SH::NBW + t];
+                    if (act) gstore(p.out_r, unsigned(k) * lbytes + cbyte, qr - p.lambda * d);
+                }
+                load(xs[b], s + DX);
             }
         }
     }
+}
+
+// Per-level coefficients of the column solve at lambda (Eqs. (16)-(17) in
+// 1D with A = I): G0, H0, rho0, lambda g H0/(G0 rho0), lambda G0,
+// lambda/rho0, lambda g/(G0 rho0).
+__global__ void k_solve_coefs(const double *rho0, const double *G0, const double *H0, double lambda, double grav,
+                              int nz, double *scf)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nz) return;
+    const double r0 = rho0[k], g0 = G0[k], h0 = H0[k];
+    double *o = scf + SC_N * k;
+    o[SC_G0] = g0;
+    o[SC_H0] = h0;
+    o[SC_RHO0] = r0;
+    o[SC_WA] = lambda * grav * h0 / (g0 * r0);
+    o[SC_LG] = lambda * g0;
+    o[SC_X1] = lambda / r0;
+    o[SC_X2] = lambda * grav / (g0 * r0);
+    o[7] = 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -608,6 +702,14 @@ __global__ void k_background(const double *rho0, double *P0, double *G0, double 
 // ---------------------------------------------------------------------------
 namespace {
 
+// dynamic LDS of k_rhs: the ring, three per-level tables of the chunk's
+// levels (zchunk + 1 elements), the element factors
+template <int N>
+size_t rhs_lds_bytes(int zchunk, int nez)
+{
+    return RhsGeom<N>::LDS + sizeof(double) * (3 * ((zchunk + 1) * N + 1) + 3 * nez);
+}
+
 template <int N>
 int rhs_zchunk_auto(const numa_ctx *c)
 {
@@ -639,15 +741,16 @@ hipError_t rhs_launch(numa_ctx *c, RhsParams p)
     p.ntx = int((c->nx + G::TX - 1) / G::TX);
     p.nty = int((c->ny + G::TY - 1) / G::TY);
     p.flag = c->flag;
-    static bool attr_set = false;  // LDS above 64 KB must be opted into once
-    if (!attr_set) {
+    const size_t lds = rhs_lds_bytes<N>(p.zchunk, p.nez);
+    static size_t attr_set = 0;  // LDS above 64 KB must be opted into
+    if (attr_set < lds) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rhs<N, EPI, HASB>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(G::LDS));
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
         if (e != hipSuccess) return e;
-        attr_set = true;
+        attr_set = lds;
     }
     dim3 grid(unsigned(p.ntx * p.nty * p.nchunk));
-    hipLaunchKernelGGL((k_rhs<N, EPI, HASB>), grid, dim3(G::NT), G::LDS, c->stream, p);
+    hipLaunchKernelGGL((k_rhs<N, EPI, HASB>), grid, dim3(G::NT), lds, c->stream, p);
     return hipGetLastError();
 }
 
@@ -655,15 +758,12 @@ template <int N, class SH>
 hipError_t solve_launch(numa_ctx *c, SolveParams p)
 {
     p.fac = c->fac;
-    p.rho0 = c->lev.rho0;
-    p.G0 = c->lev.G0;
-    p.H0 = c->lev.H0;
+    p.scf = c->lev.scf;
     p.dzb = c->lev.dzb;
     p.lambda = c->lambda;
-    p.grav = c->eos.grav;
     p.nz = int(c->nz);
     p.ncol = c->ncol;
-    const size_t shm = SolveGeom<N>::lds_bytes(int(c->nz));
+    const size_t shm = SolveGeom<N, SH>::lds_bytes(int(c->nz));
     dim3 grid(unsigned((c->ncol + 63) / 64));
     hipLaunchKernelGGL((k_colsolve<N, SH>), grid, dim3(64), shm, c->stream, p);
     return hipGetLastError();
@@ -748,6 +848,10 @@ hipError_t launch_background(numa_ctx *c)
 
 hipError_t launch_factor(numa_ctx *c, double lambda)
 {
+    hipLaunchKernelGGL(k_solve_coefs, dim3(unsigned((c->nz + 63) / 64)), dim3(64), 0, c->stream, c->lev.rho0,
+                       c->lev.G0, c->lev.H0, lambda, c->eos.grav, int(c->nz), c->lev.scf);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     return dispatch(c->N, [&](auto n) { return factor_launch<decltype(n)::value>(c, lambda); });
 }
 
@@ -792,7 +896,7 @@ hipError_t launch_hevi_step(numa_ctx *c, double *q, double dt, hipEvent_t *ev)
     static const Ark2 t;
     const long np = c->np;
     StageBuffers s = stage_buffers(c);
-    const double *qr = q + 0 * np, *qu = q + 1 * np, *qv = q + 2 * np, *qw = q + 3 * np, *qt = q + 4 * np;
+    const double *qr = q + 0 * np, *qw = q + 3 * np, *qt = q + 4 * np;
     const double *R1 = s.R1;
     hipError_t e;
 
@@ -825,12 +929,9 @@ hipError_t launch_hevi_step(numa_ctx *c, double *q, double dt, hipEvent_t *ev)
     {
         RhsParams p{};
         const double f = dt * t.a21;
-        p.a[0] = s.Q2r; p.b[0] = nullptr;
-        p.a[1] = qu;    p.b[1] = R1 + 1 * np;
-        p.a[2] = qv;    p.b[2] = R1 + 2 * np;
-        p.a[3] = s.Q2w; p.b[3] = nullptr;
-        p.a[4] = qt;    p.b[4] = R1 + 4 * np;
-        p.cb = f;
+        p.a[0] = s.Q2r;
+        p.a[3] = s.Q2w;
+        p.cb = f;  // u, v, theta' = e0 + f e1 = q^n + f R1
         set_fields(p.out0, s.E3, np);
         set_fields(p.out1, s.ACC, np);
         set_fields(p.e0, q, np);

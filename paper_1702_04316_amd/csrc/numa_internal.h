@@ -32,11 +32,21 @@ struct HostOps {
 struct DevLevels {
     double *rho0 = nullptr, *P0 = nullptr, *G0 = nullptr, *H0 = nullptr;
     double *dzb = nullptr, *zsc = nullptr, *wxy = nullptr, *D = nullptr;
+    double *scf = nullptr;  // [nz][8] column-solve coefficients at the factored lambda
 };
+
+// Binomial series (1 + x)^gamma - 1 = sum_k C(gamma, k) x^k, used for the
+// perturbation pressure when |x| <= kBinomMaxX: for gamma of dry air the first
+// omitted term is below 1e-18 of the sum.
+constexpr int kBinomTerms = 10;
+constexpr double kBinomMaxX = 1.0 / 32.0;
 
 struct EOS {
     double theta0, p00, rgas, gamma, grav;
+    double binom[kBinomTerms];  // C(gamma, k), k = 1..kBinomTerms
 };
+
+void set_binomial(EOS &e);
 
 }  // namespace numa
 

@@ -93,6 +93,15 @@ void lgl_dmat(int N, const std::vector<double> &xi, std::vector<double> &D)
     }
 }
 
+void set_binomial(EOS &e)
+{
+    double ck = 1.0;
+    for (int k = 1; k <= kBinomTerms; ++k) {
+        ck *= (e.gamma - (k - 1)) / k;  // C(gamma, k) = C(gamma, k-1) (gamma - k + 1) / k
+        e.binom[k - 1] = ck;
+    }
+}
+
 void build_ops(numa_ctx *c, const double *zface)
 {
     HostOps &o = c->ops;

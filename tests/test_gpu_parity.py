@@ -90,6 +90,27 @@ def test_rhs_parity(torch_cuda, numa_mod, oracle_mod, N, nex, ney, nez, zseed, s
     assert np.all(out[3, 0] == 0.0) and np.all(out[3, -1] == 0.0)
 
 
+@pytest.mark.parametrize("theta_amp", [20.0, 60.0])
+def test_rhs_parity_large_perturbation(torch_cuda, numa_mod, oracle_mod, theta_amp):
+    """States far from the background: the relative perturbation of rho*theta
+    crosses 1/32 at some nodes and not at others, so the pressure takes both
+    of its evaluation forms within one launch."""
+    g = _grid(4, 5, 4, 3, 7)
+    q = W.make_random_state(g, 11, theta_amp=theta_amp, smooth=False)
+    o = _oracle(oracle_mod, g)
+    bg = o.background()
+    r0 = bg["rho0"][:, None, None]
+    t0 = W.THETA0
+    x = ((r0 + q[0]) * (t0 + q[4]) - r0 * t0) / (r0 * t0)
+    assert np.any(np.abs(x) > 1.0 / 32) and np.any(np.abs(x) < 1.0 / 32)
+    ref = o.rhs(q)
+    ctx = numa_mod.Context(g)
+    out = _host(ctx.rhs(_dev(torch_cuda, q)))
+    ctx.check()
+    e = _rel(out, ref)
+    assert np.all(e < OP_TOL), e
+
+
 @pytest.mark.parametrize("N,nex,ney,nez,zseed,seed", GRIDS)
 def test_solve_parity(torch_cuda, numa_mod, oracle_mod, N, nex, ney, nez, zseed, seed):
     g = _grid(N, nex, ney, nez, zseed)
