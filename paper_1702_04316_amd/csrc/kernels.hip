@@ -112,11 +112,12 @@ struct RhsParams {
     // input are e0 + cb * e1 (a[1], a[2], a[4] unused)
     const double *a[5];
     double cb;
-    double *out0[5];
-    double *out1[5];
-    const double *e0[5];
-    const double *e1[5];
-    double k01, k02, k11, k12;  // out0 = e0 + k01 e1 + k02 R ; out1 = e0 + k11 e1 + k12 R
+    // five-field buffers (field f at + f * fs): out0 = e0 + k01 e1 + k02 R,
+    // out1 = e0 + k11 e1 + k12 R
+    double *out0, *out1;
+    const double *e0, *e1;
+    long fs;
+    double k01, k02, k11, k12;
     const double *rho0, *P0, *zsc, *wxy, *D;
     EOS eos;
     int nx, ny, nz, nez, zchunk, nchunk, ntx, nty;
@@ -140,7 +141,7 @@ template <bool HASB>
 __device__ __forceinline__ double stage_input(const RhsParams &p, int f, unsigned off)
 {
     if constexpr (HASB) {
-        if (f == 1 || f == 2 || f == 4) return gload(p.e0[f], off) + p.cb * gload(p.e1[f], off);
+        if (f == 1 || f == 2 || f == 4) return gload(p.e0 + f * p.fs, off) + p.cb * gload(p.e1 + f * p.fs, off);
     }
     return gload(p.a[f], off);
 }
@@ -151,7 +152,8 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
     using G = RhsGeom<N>;
     constexpr int NQ = N + 1, NS = G::NS, TX = G::TX, TY = G::TY, LX = G::LX, FS = G::FS, PS = G::PS;
     // dynamic LDS: ring [N+1][6][LY][LX], then per-level tables rho0, P0,
-    // 1/(rho0 theta0) for the levels this chunk touches, then zsc [3][nez]
+    // 1/(rho0 theta0) for the levels this chunk touches, zsc [3][nez], and
+    // the interface shares [2][6][TX*TY]
     extern __shared__ double ring[];
     __shared__ double sw[2][N][NS];
     __shared__ double sD[NQ * NQ];
@@ -173,6 +175,9 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
     double *sP0 = sR0 + nlev;
     double *sIRT = sP0 + nlev;
     double *zs = sIRT + nlev;  // [0,nez): 2/h ; [nez,2nez): bottom factor ; [2nez,3nez): top factor
+    // the lower element's share of the six z-derivatives at the interface
+    // node of each column, double-buffered by element parity: [2][6][TX*TY]
+    double *zp = zs + 3 * p.nez;
     const EOS eos = p.eos;
 
     for (int s = tid; s < 2 * N * NS; s += G::NT) (&sw[0][0][0])[s] = p.wxy[s];
@@ -235,15 +240,15 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
         for (int s = 0; s < G::NITEM; ++s) {
             const unsigned off = unsigned(kbase + it_p[s]) * pbytes + it_o[s];
 #pragma unroll
-            for (int f = 0; f < 5; ++f) v[s][f] = gload(HASB && (f == 1 || f == 2 || f == 4) ? p.e0[f] : p.a[f], off);
+            for (int f = 0; f < 5; ++f) v[s][f] = gload(HASB && (f == 1 || f == 2 || f == 4) ? p.e0 + f * p.fs : p.a[f], off);
         }
         if constexpr (HASB) {
 #pragma unroll
             for (int s = 0; s < G::NITEM; ++s) {
                 const unsigned off = unsigned(kbase + it_p[s]) * pbytes + it_o[s];
-                v[s][1] += p.cb * gload(p.e1[1], off);
-                v[s][2] += p.cb * gload(p.e1[2], off);
-                v[s][4] += p.cb * gload(p.e1[4], off);
+                v[s][1] += p.cb * gload(p.e1 + 1 * p.fs, off);
+                v[s][2] += p.cb * gload(p.e1 + 2 * p.fs, off);
+                v[s][4] += p.cb * gload(p.e1 + 4 * p.fs, off);
             }
         }
 #pragma unroll
@@ -282,6 +287,21 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
         }
     };
 
+    // epilogue inputs of a node at byte offset off
+    constexpr int NEPI = EPI == EPI_TWO ? 10 : (EPI == EPI_FINAL ? 5 : 1);
+    auto epi_load = [&](unsigned off, double *ev) {
+        if constexpr (EPI == EPI_TWO) {
+#pragma unroll
+            for (int f = 0; f < 5; ++f) {
+                ev[f] = gload(p.e0 + f * p.fs, off);
+                ev[5 + f] = gload(p.e1 + f * p.fs, off);
+            }
+        } else if constexpr (EPI == EPI_FINAL) {
+#pragma unroll
+            for (int f = 0; f < 5; ++f) ev[f] = gload(p.e0 + f * p.fs, off);
+        }
+    };
+
     // tendencies at level k (Set2NC, Sec. 3.1) from the x/y line derivatives
     // of the plane in the ring and the scaled vertical derivatives dz; then
     // the stage epilogue
@@ -315,23 +335,25 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
         if (k == 0 || k == p.nz - 1) R[3] = 0.0;
         if (!owner) return;
         const unsigned off = unsigned(k) * pbytes + own;
+        double ev[NEPI];
+        epi_load(off, ev);
         if constexpr (EPI == EPI_R) {
 #pragma unroll
-            for (int f = 0; f < 5; ++f) gstore(p.out0[f], off, R[f]);
+            for (int f = 0; f < 5; ++f) gstore(p.out0 + f * p.fs, off, R[f]);
         } else if constexpr (EPI == EPI_TWO) {
 #pragma unroll
             for (int f = 0; f < 5; ++f) {
-                const double e0 = gload(p.e0[f], off), e1 = gload(p.e1[f], off);
-                gstore(p.out0[f], off, e0 + p.k01 * e1 + p.k02 * R[f]);
-                gstore(p.out1[f], off, e0 + p.k11 * e1 + p.k12 * R[f]);
+                const double e0 = ev[f], e1 = ev[5 + f];
+                gstore(p.out0 + f * p.fs, off, e0 + p.k01 * e1 + p.k02 * R[f]);
+                gstore(p.out1 + f * p.fs, off, e0 + p.k11 * e1 + p.k12 * R[f]);
             }
         } else {
             bool bad = false;
 #pragma unroll
             for (int f = 0; f < 5; ++f) {
-                const double v2 = gload(p.e0[f], off) + p.k02 * R[f];
+                const double v2 = ev[f] + p.k02 * R[f];
                 bad |= !isfinite(v2);
-                gstore(p.out0[f], off, v2);
+                gstore(p.out0 + f * p.fs, off, v2);
             }
             if (bad) *p.flag = 1;
         }
@@ -342,7 +364,6 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
     // prologue: level ez0*N into the ring (the items of the first new plane
     // cover one whole plane); the c = 0 threads take the contribution of the
     // element below to the interface at ez0*N from their own column
-    double zpart[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int s = 0; s < G::NITEM; ++s) {
         if (it_p[s] != 1) continue;
@@ -380,8 +401,9 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
             acc[5] += d * Pp;
         }
         const double st = zs[2 * p.nez + eb];
+        double *zb = zp + (ez0 & 1) * 6 * (TX * TY) + txy;
 #pragma unroll
-        for (int f = 0; f < 6; ++f) zpart[f] = st * acc[f];
+        for (int f = 0; f < 6; ++f) zb[f * (TX * TY)] = st * acc[f];
     }
 
     for (int ez = ez0; ez < ez1; ++ez) {
@@ -391,19 +413,31 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
         double dz[6], sum[6];
         zsum(ez, c, sum);
         const double sc = (c == 0) ? zs[p.nez + ez] : zs[ez];
+        const double *zb = zp + (ez & 1) * 6 * (TX * TY) + txy;
+        const bool below = c == 0 && ez > 0;  // a lower element shares the node
 #pragma unroll
-        for (int f = 0; f < 6; ++f) dz[f] = (c == 0 ? zpart[f] : 0.0) + sc * sum[f];
+        for (int f = 0; f < 6; ++f) dz[f] = (below ? zb[f * (TX * TY)] : 0.0) + sc * sum[f];
         node(ez * N + c, dz);
+        // this element's share of the interface (or top node) above, one
+        // field per level of the element in turn
+        const double st = zs[2 * p.nez + ez];
+        double *zn = zp + ((ez + 1) & 1) * 6 * (TX * TY) + txy;
         if (c == 0) {
-            // this element's share of the interface (or top node) above
-            zsum(ez, N, sum);
-            const double st = zs[2 * p.nez + ez];
+            double s6[6];
+            zsum(ez, N, s6);
 #pragma unroll
-            for (int f = 0; f < 6; ++f) zpart[f] = st * sum[f];
+            for (int f = 0; f < 6; ++f) zn[f * (TX * TY)] = st * s6[f];
         }
     }
     // top node of the column: one-sided from the top element
-    if (ez1 == p.nez && c == 0) node(p.nez * N, zpart);
+    __syncthreads();  // the shares of the top element are in LDS
+    if (ez1 == p.nez && c == 0) {
+        const double *zb = zp + (ez1 & 1) * 6 * (TX * TY) + txy;
+        double dz[6];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) dz[f] = zb[f * (TX * TY)];
+        node(p.nez * N, dz);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -703,11 +737,12 @@ __global__ void k_background(const double *rho0, double *P0, double *G0, double 
 namespace {
 
 // dynamic LDS of k_rhs: the ring, three per-level tables of the chunk's
-// levels (zchunk + 1 elements), the element factors
+// levels (zchunk + 1 elements), the element factors, the interface shares
 template <int N>
 size_t rhs_lds_bytes(int zchunk, int nez)
 {
-    return RhsGeom<N>::LDS + sizeof(double) * (3 * ((zchunk + 1) * N + 1) + 3 * nez);
+    return RhsGeom<N>::LDS +
+           sizeof(double) * (3 * ((zchunk + 1) * N + 1) + 3 * nez + 2 * 6 * RhsGeom<N>::TX * RhsGeom<N>::TY);
 }
 
 template <int N>
@@ -799,10 +834,6 @@ void set_fields(const double *arr[5], const double *base, long np)
 {
     for (int f = 0; f < 5; ++f) arr[f] = base ? base + f * np : nullptr;
 }
-void set_fields(double *arr[5], double *base, long np)
-{
-    for (int f = 0; f < 5; ++f) arr[f] = base ? base + f * np : nullptr;
-}
 
 // ARK2 tableau (Table 1, signs restored by the order conditions)
 struct Ark2 {
@@ -859,7 +890,8 @@ hipError_t launch_rhs_plain(numa_ctx *c, const double *q, double *R)
 {
     RhsParams p{};
     set_fields(p.a, q, c->np);
-    set_fields(p.out0, R, c->np);
+    p.out0 = R;
+    p.fs = c->np;
     return dispatch(c->N, [&](auto n) { return rhs_launch<decltype(n)::value, EPI_R, false>(c, p); });
 }
 
@@ -932,10 +964,11 @@ hipError_t launch_hevi_step(numa_ctx *c, double *q, double dt, hipEvent_t *ev)
         p.a[0] = s.Q2r;
         p.a[3] = s.Q2w;
         p.cb = f;  // u, v, theta' = e0 + f e1 = q^n + f R1
-        set_fields(p.out0, s.E3, np);
-        set_fields(p.out1, s.ACC, np);
-        set_fields(p.e0, q, np);
-        set_fields(p.e1, R1, np);
+        p.out0 = s.E3;
+        p.out1 = s.ACC;
+        p.e0 = q;
+        p.e1 = R1;
+        p.fs = np;
         p.k01 = dt * t.a31; p.k02 = dt * t.a32;
         p.k11 = dt * t.b1;  p.k12 = dt * t.b2;
         e = dispatch(c->N, [&](auto n) { return rhs_launch<decltype(n)::value, EPI_TWO, true>(c, p); });
@@ -968,8 +1001,9 @@ hipError_t launch_hevi_step(numa_ctx *c, double *q, double dt, hipEvent_t *ev)
         p.a[2] = s.E3 + 2 * np;
         p.a[3] = s.Q3w;
         p.a[4] = s.E3 + 4 * np;
-        set_fields(p.out0, q, np);
-        set_fields(p.e0, s.ACC, np);
+        p.out0 = q;
+        p.e0 = s.ACC;
+        p.fs = np;
         p.k02 = dt * t.b3;
         e = dispatch(c->N, [&](auto n) { return rhs_launch<decltype(n)::value, EPI_FINAL, false>(c, p); });
         if (e != hipSuccess) return e;
