@@ -77,6 +77,11 @@ __device__ __forceinline__ double eos_pressure(double rho, double theta, const E
 // a 10-term binomial series for |x| <= 1/32 (every state of a weather
 // perturbation; the first omitted term is below 1e-18 relative), log1p/expm1
 // beyond.
+// (1 + x)^gamma - 1 for |x| beyond the series range.  Out of line: inlined,
+// the compiler keeps the constants of log1p and expm1 in vector registers
+// across the stencil loops, for a path that weather states do not take.
+__device__ __noinline__ double binom_power_m1(double x, double gamma) { return expm1(gamma * log1p(x)); }
+
 // irt = 1/(rho0 theta0) of the level.
 __device__ __forceinline__ double pressure_perturbation(double rp, double th, double r0, double P0, double irt,
                                                         const EOS &e)
@@ -87,7 +92,7 @@ __device__ __forceinline__ double pressure_perturbation(double rp, double th, do
     const double e1 = __builtin_fma(r0, th, -p1), e2 = __builtin_fma(t0, rp, -p2), e3 = __builtin_fma(rp, th, -p3);
     const double d = ((p1 + p2) + p3) + ((e1 + e2) + e3);
     const double x = d * irt;
-    if (fabs(x) > kBinomMaxX) return P0 * expm1(e.gamma * log1p(x));
+    if (fabs(x) > kBinomMaxX) return P0 * binom_power_m1(x, e.gamma);
     // (1 + x)^gamma - 1 by its binomial series, Horner form
     double s = e.binom[kBinomTerms - 1];
 #pragma unroll
@@ -310,28 +315,45 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
         const double r0 = sR0[k - kb];
         const double rp = q[l_own], u = q[FS + l_own], v = q[2 * FS + l_own], w = q[3 * FS + l_own];
         const double ir = 1.0 / (r0 + rp);
-        double dx[6] = {0, 0, 0, 0, 0, 0}, dy[6] = {0, 0, 0, 0, 0, 0};
-        // not unrolled: unrolled, the scheduler hoists all 12*NS LDS reads
-        // and runs out of registers
-#pragma unroll 1
-        for (int m = 0; m < NS; ++m) {
-            const double cx = cwx[m], cy = cwy[m];
-            const double *qx = q + l_x + m;
-            const double *qy = q + l_y + m * LX;
-            dx[0] += cx * ((r0 + qx[0]) * qx[FS]);
-            dy[0] += cy * ((r0 + qy[0]) * qy[2 * FS]);
-#pragma unroll
-            for (int f = 1; f < 6; ++f) {
-                dx[f] += cx * qx[f * FS];
-                dy[f] += cy * qy[f * FS];
-            }
-        }
+        // the vertical terms first, so that only the tendencies stay live
+        // across the x and y stencils (with few live registers the stencil
+        // loads can be in flight together)
         double R[5];
-        R[0] = -(dx[0] + dy[0] + dz[0]);
-        R[1] = -(u * dx[1] + v * dy[1] + w * dz[1] + dx[5] * ir);
-        R[2] = -(u * dx[2] + v * dy[2] + w * dz[2] + dy[5] * ir);
-        R[3] = -(u * dx[3] + v * dy[3] + w * dz[3] + dz[5] * ir + eos.grav * rp * ir);
-        R[4] = -(u * dx[4] + v * dy[4] + w * dz[4]);
+        R[0] = dz[0];
+        R[1] = w * dz[1];
+        R[2] = w * dz[2];
+        R[3] = w * dz[3] + dz[5] * ir + eos.grav * rp * ir;
+        R[4] = w * dz[4];
+        // line derivative of the six quantities along x (dir 0) or y (dir 1)
+        // (not unrolled: unrolled, the scheduler hoists all its LDS reads)
+        auto line = [&](int dir, double *d6) {
+            const double *cw = dir == 0 ? cwx : cwy;
+            const int base = dir == 0 ? l_x : l_y, step = dir == 0 ? 1 : LX;
+            const int fv = dir == 0 ? FS : 2 * FS;  // the velocity in rho u or rho v
+#pragma unroll
+            for (int f = 0; f < 6; ++f) d6[f] = 0.0;
+#pragma unroll 1
+            for (int m = 0; m < NS; ++m) {
+                const double cm = cw[m];
+                const double *qm = q + base + m * step;
+                d6[0] += cm * ((r0 + qm[0]) * qm[fv]);
+#pragma unroll
+                for (int f = 1; f < 6; ++f) d6[f] += cm * qm[f * FS];
+            }
+        };
+        double d6[6];
+        line(0, d6);
+        R[0] += d6[0];
+        R[1] += u * d6[1] + d6[5] * ir;
+        R[2] += u * d6[2];
+        R[3] += u * d6[3];
+        R[4] += u * d6[4];
+        line(1, d6);
+        R[0] = -(R[0] + d6[0]);
+        R[1] = -(R[1] + v * d6[1]);
+        R[2] = -(R[2] + v * d6[2] + d6[5] * ir);
+        R[3] = -(R[3] + v * d6[3]);
+        R[4] = -(R[4] + v * d6[4]);
         if (k == 0 || k == p.nz - 1) R[3] = 0.0;
         if (!owner) return;
         const unsigned off = unsigned(k) * pbytes + own;
