@@ -292,7 +292,8 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
         }
     };
 
-    // epilogue inputs of a node at byte offset off
+    // epilogue inputs of a node at byte offset off (issued before the node's
+    // z sums and stencils, so that they arrive while those run)
     constexpr int NEPI = EPI == EPI_TWO ? 10 : (EPI == EPI_FINAL ? 5 : 1);
     auto epi_load = [&](unsigned off, double *ev) {
         if constexpr (EPI == EPI_TWO) {
@@ -309,8 +310,8 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
 
     // tendencies at level k (Set2NC, Sec. 3.1) from the x/y line derivatives
     // of the plane in the ring and the scaled vertical derivatives dz; then
-    // the stage epilogue
-    auto node = [&](int k, const double *dz) {
+    // the stage epilogue with its inputs ev
+    auto node = [&](int k, const double *dz, const double *ev) {
         const double *q = ring + (k % NQ) * PS;
         const double r0 = sR0[k - kb];
         const double rp = q[l_own], u = q[FS + l_own], v = q[2 * FS + l_own], w = q[3 * FS + l_own];
@@ -357,8 +358,6 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
         if (k == 0 || k == p.nz - 1) R[3] = 0.0;
         if (!owner) return;
         const unsigned off = unsigned(k) * pbytes + own;
-        double ev[NEPI];
-        epi_load(off, ev);
         if constexpr (EPI == EPI_R) {
 #pragma unroll
             for (int f = 0; f < 5; ++f) gstore(p.out0 + f * p.fs, off, R[f]);
@@ -432,6 +431,8 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
         __syncthreads();  // the slots about to be overwritten are no longer read
         load_planes(ez * N);
         __syncthreads();
+        double ev[NEPI];
+        epi_load(unsigned(ez * N + c) * pbytes + own, ev);
         double dz[6], sum[6];
         zsum(ez, c, sum);
         const double sc = (c == 0) ? zs[p.nez + ez] : zs[ez];
@@ -439,7 +440,7 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
         const bool below = c == 0 && ez > 0;  // a lower element shares the node
 #pragma unroll
         for (int f = 0; f < 6; ++f) dz[f] = (below ? zb[f * (TX * TY)] : 0.0) + sc * sum[f];
-        node(ez * N + c, dz);
+        node(ez * N + c, dz, ev);
         // this element's share of the interface (or top node) above, one
         // field per level of the element in turn
         const double st = zs[2 * p.nez + ez];
@@ -458,7 +459,9 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
         double dz[6];
 #pragma unroll
         for (int f = 0; f < 6; ++f) dz[f] = zb[f * (TX * TY)];
-        node(p.nez * N, dz);
+        double ev[NEPI];
+        epi_load(unsigned(p.nez * N) * pbytes + own, ev);
+        node(p.nez * N, dz, ev);
     }
 }
 
