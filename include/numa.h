@@ -84,7 +84,10 @@ typedef struct {
  * fields are computed once at start-up as in Sec. 5.1.
  * g, bg: host pointers, read during the call only.  order: N in 1..8.
  * hip_stream: a hipStream_t (NULL = the null stream).  *out receives the
- * context.  Errors: NUMA_E_ARG, NUMA_E_UNSUPPORTED, NUMA_E_NOMEM, NUMA_E_HIP.
+ * context.  Errors: NUMA_E_ARG, NUMA_E_UNSUPPORTED (order 9..15; columns
+ * whose solve or right-hand-side workgroup would not fit one CU's 160 KB of
+ * LDS, i.e. above about 290 levels; a field above 4 GiB), NUMA_E_NOMEM,
+ * NUMA_E_HIP.
  */
 int numa_setup(const numa_grid *g, int32_t order, const numa_background *bg,
                void *hip_stream, numa_ctx **out);

@@ -82,8 +82,8 @@ int numa_setup(const numa_grid *g, int32_t order, const numa_background *bg, voi
         return fail(nullptr, NUMA_E_ARG, "numa_setup: invalid background constants");
     if (!(1.0 - bg->grav * g->lz / (bg->cp * bg->theta0) > 0.0))
         return fail(nullptr, NUMA_E_ARG, "numa_setup: box top above the isentropic atmosphere's top");
-    if (nz > 64)
-        return fail(nullptr, NUMA_E_UNSUPPORTED, "numa_setup: columns longer than 64 levels are not built");
+    if (numa::lds_needed(order, g->nez, int(nz)) > numa::kLdsPerCU)
+        return fail(nullptr, NUMA_E_UNSUPPORTED, "numa_setup: columns too tall for one CU's LDS");
     if (nx * ny * nz * int64_t(sizeof(double)) >= (int64_t(1) << 32))
         return fail(nullptr, NUMA_E_UNSUPPORTED, "numa_setup: a field above 4 GiB is not supported");
 

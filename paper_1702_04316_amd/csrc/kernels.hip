@@ -13,6 +13,7 @@
 // bytes per factor entry.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -824,6 +825,13 @@ hipError_t solve_launch(numa_ctx *c, SolveParams p)
     p.nz = int(c->nz);
     p.ncol = c->ncol;
     const size_t shm = SolveGeom<N, SH>::lds_bytes(int(c->nz));
+    static size_t attr_set = 0;  // tall columns need LDS above 64 KB
+    if (shm > 65536 && attr_set < shm) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_colsolve<N, SH>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
+        if (e != hipSuccess) return e;
+        attr_set = shm;
+    }
     dim3 grid(unsigned((c->ncol + 63) / 64));
     hipLaunchKernelGGL((k_colsolve<N, SH>), grid, dim3(64), shm, c->stream, p);
     return hipGetLastError();
@@ -880,6 +888,21 @@ struct Ark2 {
 };
 
 }  // namespace
+
+// LDS one workgroup of each kernel needs on this grid (the right-hand side
+// at its largest vertical chunk), static arrays included.
+size_t lds_needed(int N, int nez, int nz)
+{
+    size_t need = 0;
+    auto f = [&](auto n) -> hipError_t {
+        constexpr int NN = decltype(n)::value;
+        const size_t stat = sizeof(double) * (2 * NN * (2 * NN + 1) + (NN + 1) * (NN + 1));
+        need = std::max(rhs_lds_bytes<NN>(nez, nez) + stat, SolveGeom<NN, ShapeStage3>::lds_bytes(nz));
+        return hipSuccess;
+    };
+    (void)dispatch(N, f);
+    return need;
+}
 
 StageBuffers stage_buffers(numa_ctx *c)
 {

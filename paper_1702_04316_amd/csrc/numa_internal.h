@@ -82,6 +82,10 @@ struct StageBuffers {
 };
 StageBuffers stage_buffers(numa_ctx *c);
 
+// LDS per CU on gfx950, and what one workgroup of the kernels needs
+constexpr size_t kLdsPerCU = 160 * 1024;
+size_t lds_needed(int N, int nez, int nz);
+
 hipError_t launch_background(numa_ctx *c);
 hipError_t launch_factor(numa_ctx *c, double lambda);
 hipError_t launch_rhs_plain(numa_ctx *c, const double *q, double *R);

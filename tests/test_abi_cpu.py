@@ -49,8 +49,11 @@ def test_setup_rejects_bad_arguments_before_any_gpu_call():
     assert "increasing" in numa.last_error()
     tall, _ = numa.make_grid(1000.0, 1000.0, 40000.0, 2, 2, 2)
     assert lib.numa_setup(C.byref(tall), 4, C.byref(bg), None, C.byref(out)) == numa.NUMA_E_ARG
-    long_col, _ = numa.make_grid(1000.0, 1000.0, 10000.0, 2, 2, 20)
+    # 321 levels: the column solve of one 64-column workgroup would need more
+    # than one CU's 160 KB of LDS
+    long_col, _ = numa.make_grid(1000.0, 1000.0, 10000.0, 2, 2, 80)
     assert lib.numa_setup(C.byref(long_col), 4, C.byref(bg), None, C.byref(out)) == numa.NUMA_E_UNSUPPORTED
+    assert "LDS" in numa.last_error()
     badbg = numa.numa_background(300.0, 1e5, 200.0, 287.17, 9.8)
     assert lib.numa_setup(C.byref(g), 4, C.byref(badbg), None, C.byref(out)) == numa.NUMA_E_ARG
     assert out.value is None

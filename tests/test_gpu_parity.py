@@ -128,6 +128,38 @@ def test_solve_parity(torch_cuda, numa_mod, oracle_mod, N, nex, ney, nez, zseed,
     assert np.array_equal(out[1], y[1]) and np.array_equal(out[2], y[2]) and np.array_equal(out[4], y[4])
 
 
+# Tall columns: the column solve's LDS exceeds 64 KB per wavefront, so fewer
+# wavefronts share a CU (161 and 197 levels).
+TALL = [(4, 2, 2, 40, None, 21), (7, 1, 2, 28, 8, 22)]
+
+
+@pytest.mark.parametrize("N,nex,ney,nez,zseed,seed", TALL)
+def test_tall_column_solve_and_step_parity(torch_cuda, numa_mod, oracle_mod, N, nex, ney, nez, zseed, seed):
+    lz = 20000.0
+    zf = None if zseed is None else W.random_zface(nez, lz, zseed)
+    g = W.Grid(9000.0 * nex, 7000.0 * ney, lz, nex, ney, nez, N, zface=zf)
+    dt = W.dt_for_courant(g, 15.0, "z")
+    o = _oracle(oracle_mod, g)
+    o.factor_dt(dt)
+    ctx = numa_mod.Context(g)
+    ctx.factor(dt)
+    y = W.make_random_state(g, seed, smooth=False)
+    e = _rel(_host(ctx.solve(_dev(torch_cuda, y))), o.solve(y))
+    ctx.check()
+    assert np.all(e < OP_TOL), e
+    q = W.make_random_state(g, seed + 1, wind=2.0)
+    dtx = min(dt, W.dt_for_courant(g, 0.4, "x"), W.dt_for_courant(g, 0.4, "y"))
+    if dtx < dt:
+        o.factor_dt(dtx)
+        ctx.factor(dtx)
+    qd = _dev(torch_cuda, q)
+    ctx.step(qd, 2)
+    ctx.check()
+    e = _rel(_host(qd), o.step(q, dtx, 2))
+    print(f"tall N={N} nz={g.nz}: step rel L2 {e}")
+    assert np.all(e < STEP_TOL), e
+
+
 def _run_steps(torch, numa, O, wl, q0, nsteps, tol=STEP_TOL):
     g = wl.grid
     o = _oracle(O, g, wl.background)
