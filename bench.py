@@ -81,6 +81,45 @@ def cpu_baseline(sample_nex=32, steps=60):
             "seconds": t}
 
 
+def precision_form(numa, torch, ctx, wl, args, t_fp64):
+    """The precision form (FP32 right-hand sides and u, v, w stage buffers)
+    on the same workload and GPU: throughput, simulated seconds per wall
+    second against the FP64 step, and its relative L2 difference per
+    variable from the FP64 step after 100 steps (the FP64 step matches the
+    oracle to 1e-11; the tests check the form against the oracle itself)."""
+    import numpy as np
+    from paper_1702_04316_amd import workloads as W
+    g = wl.grid
+    q0 = torch.from_numpy(W.make_initial_state(wl)).to("cuda")
+    q = q0.clone()
+    ctx.step(q, args.warmup, mixed=True)
+    ctx.check()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = numa.profile_steps_mixed(ctx.ctx, q.data_ptr(), wl.dt, args.steps)
+    torch.cuda.synchronize()
+    tm = time.perf_counter() - t0
+    ctx.check()
+    a, b = q0.clone(), q0.clone()
+    ctx.step(a, 100)
+    ctx.step(b, 100, mixed=True)
+    ctx.check()
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    err = {n: float(np.linalg.norm(b[f] - a[f]) / np.linalg.norm(a[f]))
+           for f, n in enumerate(("rho'", "u", "v", "w", "theta'"))}
+    names = ["rhs_stage1", "colsolve_stage2", "rhs_stage2", "colsolve_stage3", "rhs_stage3"]
+    return {
+        "entry": "numa_hevi_step_mixed",
+        "value": 5 * g.n_unique * args.steps / tm,
+        "unit": "DOF-steps/s",
+        "ms_per_step": 1e3 * tm / args.steps,
+        "speedup_vs_fp64": t_fp64 / tm,
+        "sim_s_per_wall_s": {"fp64": wl.dt * args.steps / t_fp64, "mixed": wl.dt * args.steps / tm},
+        "rel_l2_vs_fp64_after_100_steps": err,
+        "kernels": [{"kernel": n, "ms": m} for n, m in zip(names, ms)],
+    }
+
+
 def copy_probe(nbytes=1 << 30, reps=10):
     """A plain device-to-device copy of known size: the achievable HBM rate,
     and the calibration program for the FETCH_SIZE/WRITE_SIZE counters."""
@@ -187,6 +226,7 @@ def main():
         "kernels": per,
         "step_algorithmic_GBps": step_bytes * args.steps / t / 1e9,
     }
+    out["precision_form"] = precision_form(numa, torch, ctx, wl, args, t)
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline()

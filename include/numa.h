@@ -137,6 +137,29 @@ int numa_hevi_step(numa_ctx *c, double *state, double dt, int32_t nsteps);
 int numa_profile_steps(numa_ctx *c, double *state, double dt, int32_t nsteps, double *ms_out);
 
 /*
+ * Precision form of numa_hevi_step.  Not a method of the paper (whose
+ * kernels are FP64 and, by its own roofline measurements in Sec. 6.1,
+ * mostly memory-bound): a project addition on top of the ARK2 HEVI step of
+ * Sec. 2.2 that halves the bytes of most stage buffers.  The same five
+ * kernels and stage algebra, with the right-hand
+ * sides evaluated in FP32 (LDS planes, line and column derivatives,
+ * tendencies) on FP32 stage buffers R1, E3, Q2, Q3, while the state, the
+ * accumulator of the final combination, the pressure perturbation
+ * P' = EOS(rho, theta) - P0 and the column solves (FP64 factors) stay in
+ * FP64.  state: the FP64 device array of the state contract, advanced in
+ * place.  Needs the factors of numa_factor_columns(dt) like the FP64 step.
+ * The first call allocates 14 FP32 fields of stage buffers for the context
+ * (freed by numa_destroy).  Asynchronous.  Errors: as numa_hevi_step, and
+ * NUMA_E_NOMEM.
+ */
+int numa_hevi_step_mixed(numa_ctx *c, double *state, double dt, int32_t nsteps);
+
+/*
+ * numa_profile_steps for the precision form (ms_out as there).
+ */
+int numa_profile_steps_mixed(numa_ctx *c, double *state, double dt, int32_t nsteps, double *ms_out);
+
+/*
  * rhs_out = R(state): the explicit right-hand side of Set2NC in perturbation
  * form (Sec. 3.1) with the continuity equation in divergence form,
  * element-local strong-form LGL derivatives (Alg. 2) and DSS (Sec. 5.3);

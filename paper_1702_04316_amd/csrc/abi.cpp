@@ -34,6 +34,7 @@ void free_ctx(numa_ctx *c)
     if (c->lev_block) (void)hipFree(c->lev_block);
     if (c->fac) (void)hipFree(c->fac);
     if (c->work) (void)hipFree(c->work);
+    if (c->work_mix) (void)hipFree(c->work_mix);
     if (c->flag) (void)hipFree(c->flag);
     delete c;
 }
@@ -208,33 +209,47 @@ int numa_factor_columns(numa_ctx *c, double dt)
     return NUMA_OK;
 }
 
-int numa_hevi_step(numa_ctx *c, double *state, double dt, int32_t nsteps)
+namespace {
+
+// The checks shared by the step entry points; NUMA_OK if the step may run.
+int step_preconditions(numa_ctx *c, double dt, const char *who)
 {
-    if (!c) return NUMA_E_ARG;
-    if (!state || nsteps < 0) return fail(c, NUMA_E_ARG, "numa_hevi_step: null state or nsteps < 0");
-    if (!c->factored) return fail(c, NUMA_E_NOT_FACTORED, "numa_hevi_step: call numa_factor_columns first");
+    if (!c->factored) return fail(c, NUMA_E_NOT_FACTORED, std::string(who) + ": call numa_factor_columns first");
     if (std::memcmp(&dt, &c->dt_factored, sizeof(double)) != 0)
-        return fail(c, NUMA_E_DT_MISMATCH, "numa_hevi_step: dt differs from the factored dt");
-    for (int32_t s = 0; s < nsteps; ++s) {
-        hipError_t e = numa::launch_hevi_step(c, state, dt);
-        if (e != hipSuccess) return hip_fail(c, e, "numa_hevi_step");
+        return fail(c, NUMA_E_DT_MISMATCH, std::string(who) + ": dt differs from the factored dt");
+    return NUMA_OK;
+}
+
+// The precision form's FP32 stage buffers, allocated on first use.
+int ensure_mixed_buffers(numa_ctx *c, const char *who)
+{
+    if (c->work_mix) return NUMA_OK;
+    hipError_t e = hipMalloc(&c->work_mix, size_t(80) * size_t(c->np));  // bytes per node
+    if (e != hipSuccess) {
+        c->work_mix = nullptr;
+        return hip_fail(c, e, (std::string(who) + ": hipMalloc(FP32 stage buffers)").c_str());
     }
     return NUMA_OK;
 }
 
-int numa_profile_steps(numa_ctx *c, double *state, double dt, int32_t nsteps, double *ms_out)
+using StepFn = hipError_t (*)(numa_ctx *, double *, double, hipEvent_t *);
+
+int run_steps(numa_ctx *c, StepFn step, double *state, double dt, int32_t nsteps, const char *who)
 {
-    if (!c) return NUMA_E_ARG;
-    if (!state || nsteps < 1 || nsteps > 100000 || !ms_out)
-        return fail(c, NUMA_E_ARG, "numa_profile_steps: bad arguments");
-    if (!c->factored) return fail(c, NUMA_E_NOT_FACTORED, "numa_profile_steps: call numa_factor_columns first");
-    if (std::memcmp(&dt, &c->dt_factored, sizeof(double)) != 0)
-        return fail(c, NUMA_E_DT_MISMATCH, "numa_profile_steps: dt differs from the factored dt");
+    for (int32_t s = 0; s < nsteps; ++s) {
+        hipError_t e = step(c, state, dt, nullptr);
+        if (e != hipSuccess) return hip_fail(c, e, who);
+    }
+    return NUMA_OK;
+}
+
+int profile_steps(numa_ctx *c, StepFn step, double *state, double dt, int32_t nsteps, double *ms_out, const char *who)
+{
     // 6 events per step around its 5 kernels
     std::vector<hipEvent_t> ev(size_t(6) * nsteps, nullptr);
     hipError_t e = hipSuccess;
     for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
-    for (int32_t s = 0; s < nsteps && e == hipSuccess; ++s) e = numa::launch_hevi_step(c, state, dt, &ev[size_t(6) * s]);
+    for (int32_t s = 0; s < nsteps && e == hipSuccess; ++s) e = step(c, state, dt, &ev[size_t(6) * s]);
     if (e == hipSuccess) e = hipEventSynchronize(ev.back());
     double acc[5] = {0, 0, 0, 0, 0};
     for (int32_t s = 0; s < nsteps && e == hipSuccess; ++s)
@@ -245,9 +260,51 @@ int numa_profile_steps(numa_ctx *c, double *state, double dt, int32_t nsteps, do
         }
     for (hipEvent_t x : ev)
         if (x) (void)hipEventDestroy(x);
-    if (e != hipSuccess) return hip_fail(c, e, "numa_profile_steps");
+    if (e != hipSuccess) return hip_fail(c, e, who);
     for (int i = 0; i < 5; ++i) ms_out[i] = acc[i] / nsteps;
     return NUMA_OK;
+}
+
+}  // namespace
+
+int numa_hevi_step(numa_ctx *c, double *state, double dt, int32_t nsteps)
+{
+    if (!c) return NUMA_E_ARG;
+    if (!state || nsteps < 0) return fail(c, NUMA_E_ARG, "numa_hevi_step: null state or nsteps < 0");
+    int rc = step_preconditions(c, dt, "numa_hevi_step");
+    if (rc != NUMA_OK) return rc;
+    return run_steps(c, numa::launch_hevi_step, state, dt, nsteps, "numa_hevi_step");
+}
+
+int numa_hevi_step_mixed(numa_ctx *c, double *state, double dt, int32_t nsteps)
+{
+    if (!c) return NUMA_E_ARG;
+    if (!state || nsteps < 0) return fail(c, NUMA_E_ARG, "numa_hevi_step_mixed: null state or nsteps < 0");
+    int rc = step_preconditions(c, dt, "numa_hevi_step_mixed");
+    if (rc == NUMA_OK) rc = ensure_mixed_buffers(c, "numa_hevi_step_mixed");
+    if (rc != NUMA_OK) return rc;
+    return run_steps(c, numa::launch_hevi_step_mixed, state, dt, nsteps, "numa_hevi_step_mixed");
+}
+
+int numa_profile_steps(numa_ctx *c, double *state, double dt, int32_t nsteps, double *ms_out)
+{
+    if (!c) return NUMA_E_ARG;
+    if (!state || nsteps < 1 || nsteps > 100000 || !ms_out)
+        return fail(c, NUMA_E_ARG, "numa_profile_steps: bad arguments");
+    int rc = step_preconditions(c, dt, "numa_profile_steps");
+    if (rc != NUMA_OK) return rc;
+    return profile_steps(c, numa::launch_hevi_step, state, dt, nsteps, ms_out, "numa_profile_steps");
+}
+
+int numa_profile_steps_mixed(numa_ctx *c, double *state, double dt, int32_t nsteps, double *ms_out)
+{
+    if (!c) return NUMA_E_ARG;
+    if (!state || nsteps < 1 || nsteps > 100000 || !ms_out)
+        return fail(c, NUMA_E_ARG, "numa_profile_steps_mixed: bad arguments");
+    int rc = step_preconditions(c, dt, "numa_profile_steps_mixed");
+    if (rc == NUMA_OK) rc = ensure_mixed_buffers(c, "numa_profile_steps_mixed");
+    if (rc != NUMA_OK) return rc;
+    return profile_steps(c, numa::launch_hevi_step_mixed, state, dt, nsteps, ms_out, "numa_profile_steps_mixed");
 }
 
 int numa_rhs(numa_ctx *c, const double *state, double *rhs_out)

@@ -42,21 +42,26 @@ template <> struct Tile<6> { static constexpr int TX = 12, TY = 6; };
 template <> struct Tile<7> { static constexpr int TX = 14, TY = 7; };
 template <> struct Tile<8> { static constexpr int TX = 8, TY = 8; };
 
-template <int N>
+template <int N, int ES = 8>  // ES: bytes of an LDS ring element (8 FP64, 4 FP32)
 struct RhsGeom {
     static constexpr int TX = Tile<N>::TX, TY = Tile<N>::TY;
     static constexpr int NT = TX * TY * N;          // threads
     static constexpr int LX = TX + N + 1;           // plane incl. halo
     static constexpr int LY = TY + N + 1;
     static constexpr int FS = LX * LY;              // one field of one plane
-    static constexpr int NF = 6;                    // rho', u, v, w, theta', P'
-    static constexpr int PS = NF * FS;              // one plane
+    // a plane: rho', u, v, w, theta' (ES bytes each), then P' in FP64 (the
+    // pressure and its derivatives stay FP64 in every form), and with FP32
+    // fields an FP64 copy of rho' for the buoyancy, which nearly balances
+    // the vertical pressure gradient
+    static constexpr int POFF = (5 * FS * ES + 7) / 8 * 8;  // byte offset of P'
+    static constexpr int ROFF = POFF + 8 * FS;               // byte offset of the FP64 rho' (ES = 4)
+    static constexpr int PB = ROFF + (ES == 8 ? 0 : 8 * FS); // bytes of a plane
     static constexpr int NS = 2 * N + 1;            // x/y stencil width
     // cross-shaped part of a plane that is loaded: tile rows with the x halo,
     // plus the y-halo rows of the tile columns
     static constexpr int NCROSS = TY * LX + TX * (N + 1);
     static constexpr int NITEM = (N * NCROSS + NT - 1) / NT;  // plane loads per thread
-    static constexpr size_t LDS = size_t(N + 1) * PS * sizeof(double);
+    static constexpr size_t LDS = size_t(N + 1) * PB;
     // waves per SIMD to compile for: two workgroups per CU where LDS allows
     static constexpr int MINW = (NT <= 512 && 2 * LDS <= 150 * 1024) ? 2 * (NT / 256) : 1;
 };
@@ -113,15 +118,41 @@ __device__ __forceinline__ void gstore(double *base, unsigned off, double v)
     *reinterpret_cast<double *>(reinterpret_cast<char *>(base) + off) = v;
 }
 
+// The same for a field of element type T, with off the offset an FP64 field
+// would have (an FP32 field is addressed at off / 2).
+template <class T>
+__device__ __forceinline__ double tload(const void *base, unsigned off)
+{
+    if constexpr (sizeof(T) == 8) return gload(static_cast<const double *>(base), off);
+    else return double(*reinterpret_cast<const float *>(static_cast<const char *>(base) + (off >> 1)));
+}
+template <class T>
+__device__ __forceinline__ void tstore(void *base, unsigned off, double v)
+{
+    if constexpr (sizeof(T) == 8) gstore(static_cast<double *>(base), off, v);
+    else *reinterpret_cast<float *>(static_cast<char *>(base) + (off >> 1)) = float(v);
+}
+// field f of a five-field buffer of element type T, field stride fs elements
+template <class T>
+__device__ __forceinline__ const void *field(const void *base, int f, long fs)
+{
+    return static_cast<const T *>(base) + f * fs;
+}
+template <class T>
+__device__ __forceinline__ void *field(void *base, int f, long fs)
+{
+    return static_cast<T *>(base) + f * fs;
+}
+
 struct RhsParams {
     // input fields (rho', u, v, w, theta'); with HASB, u, v, theta' of the
     // input are e0 + cb * e1 (a[1], a[2], a[4] unused)
-    const double *a[5];
+    const void *a[5];
     double cb;
     // five-field buffers (field f at + f * fs): out0 = e0 + k01 e1 + k02 R,
     // out1 = e0 + k11 e1 + k12 R
-    double *out0, *out1;
-    const double *e0, *e1;
+    void *out0, *out1;
+    const void *e0, *e1;
     long fs;
     double k01, k02, k11, k12;
     const double *rho0, *P0, *zsc, *wxy, *D;
@@ -131,6 +162,50 @@ struct RhsParams {
 };
 
 enum { EPI_R = 0, EPI_TWO = 1, EPI_FINAL = 2 };
+
+// Layout of a five-field stage buffer of np nodes: all FP64, or (M) the
+// precision form's rho' and theta' in FP64 with u, v, w in FP32 (the
+// pressure perturbation P0 ((1+x)^gamma - 1) scales the relative rounding of
+// rho' and theta' by P0, so their stage values stay FP64).  Byte offsets of
+// the fields per node: 0, 8, 16, 24, 32 (FP64) or 0, 8, 12, 16, 20 (M).
+// Offsets passed in are those an FP64 field would have.
+template <bool M>
+struct FiveField {
+    static __device__ __forceinline__ bool f32(int f) { return M && f >= 1 && f <= 3; }
+    static __device__ __forceinline__ size_t ofs(int f, long np)
+    {
+        return M ? size_t(np) * size_t(f == 0 ? 0 : (f == 4 ? 20 : 4 + 4 * f)) : size_t(np) * 8 * size_t(f);
+    }
+    // field f stored alone at p
+    static __device__ __forceinline__ double load1(const void *p, int f, unsigned off)
+    {
+        return f32(f) ? tload<float>(p, off) : tload<double>(p, off);
+    }
+    static __device__ __forceinline__ double load(const void *buf, int f, long np, unsigned off)
+    {
+        return load1(static_cast<const char *>(buf) + ofs(f, np), f, off);
+    }
+    static __device__ __forceinline__ void store(void *buf, int f, long np, unsigned off, double v)
+    {
+        void *p = static_cast<char *>(buf) + ofs(f, np);
+        if (f32(f)) tstore<float>(p, off, v);
+        else tstore<double>(p, off, v);
+    }
+};
+
+// Buffers of one right-hand-side launch.  The FP64 step keeps every field
+// in FP64.  The precision form (MIX) keeps the state q and the accumulator
+// ACC (e0 of the last two launches, out1) in FP64, its other stage buffers
+// in the mixed layout, and the LDS ring (except P') and the stencil
+// arithmetic in FP32; P' and its derivatives stay FP64.
+template <int EPI, bool MIX>
+struct RhsTypes {
+    using A = FiveField<MIX && EPI != EPI_R>;       // inputs a[]
+    using E1 = FiveField<MIX>;                      // e1 (R1)
+    using O0 = FiveField<MIX && EPI != EPI_FINAL>;  // out0
+    using D = FiveField<false>;                     // e0, out1
+    using C = std::conditional_t<MIX, float, double>;
+};
 
 // Map the launch index to a tile so that each of the 8 XCDs (which receive
 // workgroups round-robin) works on a contiguous band of tiles and shares the
@@ -142,27 +217,37 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
     return x < r ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
 }
 
-// Stage input of field f at byte offset off.
-template <bool HASB>
+// Stage input of field f at offset off.
+template <bool HASB, class TA, class TE1>
 __device__ __forceinline__ double stage_input(const RhsParams &p, int f, unsigned off)
 {
     if constexpr (HASB) {
-        if (f == 1 || f == 2 || f == 4) return gload(p.e0 + f * p.fs, off) + p.cb * gload(p.e1 + f * p.fs, off);
+        if (f == 1 || f == 2 || f == 4) return FiveField<false>::load(p.e0, f, p.fs, off) + p.cb * TE1::load(p.e1, f, p.fs, off);
     }
-    return gload(p.a[f], off);
+    return TA::load1(p.a[f], f, off);
 }
 
-template <int N, int EPI, bool HASB>
-__global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsParams p)
+template <int N, int EPI, bool HASB, bool MIX>
+__global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 : 8>::MINW)) void k_rhs(RhsParams p)
 {
-    using G = RhsGeom<N>;
-    constexpr int NQ = N + 1, NS = G::NS, TX = G::TX, TY = G::TY, LX = G::LX, FS = G::FS, PS = G::PS;
-    // dynamic LDS: ring [N+1][6][LY][LX], then per-level tables rho0, P0,
-    // 1/(rho0 theta0) for the levels this chunk touches, zsc [3][nez], and
-    // the interface shares [2][6][TX*TY]
-    extern __shared__ double ring[];
-    __shared__ double sw[2][N][NS];
-    __shared__ double sD[NQ * NQ];
+    using TT = RhsTypes<EPI, MIX>;
+    using TA = typename TT::A;
+    using TE1 = typename TT::E1;
+    using TO0 = typename TT::O0;
+    using C = typename TT::C;
+    using G = RhsGeom<N, sizeof(C)>;
+    constexpr int NQ = N + 1, NS = G::NS, TX = G::TX, TY = G::TY, LX = G::LX, FS = G::FS;
+    // dynamic LDS: ring of N+1 planes [rho', u, v, w, theta' (C)][P' (FP64)]
+    // of [LY][LX], then per-level tables rho0, P0, 1/(rho0 theta0) for the
+    // levels this chunk touches, zsc [3][nez], and the interface shares
+    // [2][6][TX*TY] (FP64)
+    extern __shared__ double lds_block[];
+    char *const ringb = reinterpret_cast<char *>(lds_block);
+    auto cfield = [&](int slot) { return reinterpret_cast<C *>(ringb + slot * G::PB); };
+    auto pfield = [&](int slot) { return reinterpret_cast<double *>(ringb + slot * G::PB + G::POFF); };
+    auto rfield = [&](int slot) { return reinterpret_cast<double *>(ringb + slot * G::PB + G::ROFF); };
+    __shared__ C sw[2][N][NS];
+    __shared__ C sD[NQ * NQ];
 
     const int tid = threadIdx.x;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
@@ -177,7 +262,7 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
     const int ez1 = min(p.nez, ez0 + p.zchunk);
     const int kb = max(ez0 - 1, 0) * N;          // lowest level in the tables
     const int nlev = ez1 * N + 1 - kb;
-    double *sR0 = ring + (N + 1) * PS;
+    double *sR0 = lds_block + G::LDS / sizeof(double);
     double *sP0 = sR0 + nlev;
     double *sIRT = sP0 + nlev;
     double *zs = sIRT + nlev;  // [0,nez): 2/h ; [nez,2nez): bottom factor ; [2nez,3nez): top factor
@@ -186,8 +271,8 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
     double *zp = zs + 3 * p.nez;
     const EOS eos = p.eos;
 
-    for (int s = tid; s < 2 * N * NS; s += G::NT) (&sw[0][0][0])[s] = p.wxy[s];
-    for (int s = tid; s < NQ * NQ; s += G::NT) sD[s] = p.D[s];
+    for (int s = tid; s < 2 * N * NS; s += G::NT) (&sw[0][0][0])[s] = C(p.wxy[s]);
+    for (int s = tid; s < NQ * NQ; s += G::NT) sD[s] = C(p.D[s]);
     for (int s = tid; s < nlev; s += G::NT) {
         const double r0 = p.rho0[kb + s];
         sR0[s] = r0;
@@ -235,8 +320,8 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
     const int l_own = (ty + N) * LX + (tx + N);
     const int l_x = (ty + N) * LX + (tx - ax);
     const int l_y = (ty - ay) * LX + (tx + N);
-    const double *cwx = &sw[0][0][0] + ax * NS;
-    const double *cwy = &sw[1][0][0] + ay * NS;
+    const C *cwx = &sw[0][0][0] + ax * NS;
+    const C *cwy = &sw[1][0][0] + ay * NS;
 
     // the N new planes above level kbase into their ring slots: every load of
     // every item is issued before the first is used (no item branches)
@@ -246,48 +331,52 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
         for (int s = 0; s < G::NITEM; ++s) {
             const unsigned off = unsigned(kbase + it_p[s]) * pbytes + it_o[s];
 #pragma unroll
-            for (int f = 0; f < 5; ++f) v[s][f] = gload(HASB && (f == 1 || f == 2 || f == 4) ? p.e0 + f * p.fs : p.a[f], off);
+            for (int f = 0; f < 5; ++f)
+                v[s][f] = HASB && (f == 1 || f == 2 || f == 4) ? FiveField<false>::load(p.e0, f, p.fs, off)
+                                                             : TA::load1(p.a[f], f, off);
         }
         if constexpr (HASB) {
 #pragma unroll
             for (int s = 0; s < G::NITEM; ++s) {
                 const unsigned off = unsigned(kbase + it_p[s]) * pbytes + it_o[s];
-                v[s][1] += p.cb * gload(p.e1 + 1 * p.fs, off);
-                v[s][2] += p.cb * gload(p.e1 + 2 * p.fs, off);
-                v[s][4] += p.cb * gload(p.e1 + 4 * p.fs, off);
+                v[s][1] += p.cb * TE1::load(p.e1, 1, p.fs, off);
+                v[s][2] += p.cb * TE1::load(p.e1, 2, p.fs, off);
+                v[s][4] += p.cb * TE1::load(p.e1, 4, p.fs, off);
             }
         }
 #pragma unroll
         for (int s = 0; s < G::NITEM; ++s) {
             const int k = kbase + it_p[s], kl = k - kb;
             const double Pp = pressure_perturbation(v[s][0], v[s][4], sR0[kl], sP0[kl], sIRT[kl], eos);
-            double *d = ring + (k % NQ) * PS + it_l[s];
-            d[0 * FS] = v[s][0];
-            d[1 * FS] = v[s][1];
-            d[2 * FS] = v[s][2];
-            d[3 * FS] = v[s][3];
-            d[4 * FS] = v[s][4];
-            d[5 * FS] = Pp;
+            C *d = cfield(k % NQ) + it_l[s];
+            d[0 * FS] = C(v[s][0]);
+            d[1 * FS] = C(v[s][1]);
+            d[2 * FS] = C(v[s][2]);
+            d[3 * FS] = C(v[s][3]);
+            d[4 * FS] = C(v[s][4]);
+            pfield(k % NQ)[it_l[s]] = Pp;
+            if constexpr (MIX) rfield(k % NQ)[it_l[s]] = v[s][0];
         }
     };
 
     // sum_n D[r][n] g(level ez*N + n) over the own column for the six
-    // z-differentiated quantities rho w, u, v, w, theta', P'
+    // z-differentiated quantities rho w, u, v, w, theta' (out) and P' (outp)
     // (not unrolled: unrolled, all 6*(N+1) LDS reads would be in flight at once)
-    auto zsum = [&](int ez, int r, double *out) {
+    auto zsum = [&](int ez, int r, C *out, double &outp) {
 #pragma unroll
-        for (int f = 0; f < 6; ++f) out[f] = 0.0;
+        for (int f = 0; f < 5; ++f) out[f] = C(0);
+        outp = 0.0;
         int k = ez * N, slot = k % NQ;
 #pragma unroll 1
         for (int n = 0; n < NQ; ++n) {
-            const double *q = ring + slot * PS + l_own;
-            const double d = sD[r * NQ + n];
-            out[0] += d * ((sR0[k - kb] + q[0]) * q[3 * FS]);
+            const C *q = cfield(slot) + l_own;
+            const C d = sD[r * NQ + n];
+            out[0] += d * ((C(sR0[k - kb]) + q[0]) * q[3 * FS]);
             out[1] += d * q[1 * FS];
             out[2] += d * q[2 * FS];
             out[3] += d * q[3 * FS];
             out[4] += d * q[4 * FS];
-            out[5] += d * q[5 * FS];
+            outp += double(d) * pfield(slot)[l_own];
             ++k;
             slot = (slot + 1 == NQ) ? 0 : slot + 1;
         }
@@ -300,82 +389,92 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
         if constexpr (EPI == EPI_TWO) {
 #pragma unroll
             for (int f = 0; f < 5; ++f) {
-                ev[f] = gload(p.e0 + f * p.fs, off);
-                ev[5 + f] = gload(p.e1 + f * p.fs, off);
+                ev[f] = FiveField<false>::load(p.e0, f, p.fs, off);
+                ev[5 + f] = TE1::load(p.e1, f, p.fs, off);
             }
         } else if constexpr (EPI == EPI_FINAL) {
 #pragma unroll
-            for (int f = 0; f < 5; ++f) ev[f] = gload(p.e0 + f * p.fs, off);
+            for (int f = 0; f < 5; ++f) ev[f] = FiveField<false>::load(p.e0, f, p.fs, off);
         }
     };
 
     // tendencies at level k (Set2NC, Sec. 3.1) from the x/y line derivatives
     // of the plane in the ring and the scaled vertical derivatives dz; then
     // the stage epilogue with its inputs ev
-    auto node = [&](int k, const double *dz, const double *ev) {
-        const double *q = ring + (k % NQ) * PS;
-        const double r0 = sR0[k - kb];
-        const double rp = q[l_own], u = q[FS + l_own], v = q[2 * FS + l_own], w = q[3 * FS + l_own];
-        const double ir = 1.0 / (r0 + rp);
+    auto node = [&](int k, const C *dz, double dzp, const double *ev) {
+        const C *q = cfield(k % NQ);
+        const double *qp = pfield(k % NQ);
+        const C r0 = C(sR0[k - kb]);
+        const C rp = q[l_own], u = q[FS + l_own], v = q[2 * FS + l_own], w = q[3 * FS + l_own];
+        const C ir = C(1) / (r0 + rp);
+        // rho' and 1/rho for the pressure and buoyancy terms: FP64 in every form
+        const double rpd = MIX ? rfield(k % NQ)[l_own] : double(rp);
+        const double irp = MIX ? 1.0 / (sR0[k - kb] + rpd) : double(ir);
         // the vertical terms first, so that only the tendencies stay live
         // across the x and y stencils (with few live registers the stencil
         // loads can be in flight together)
-        double R[5];
+        C R[5];
         R[0] = dz[0];
         R[1] = w * dz[1];
         R[2] = w * dz[2];
-        R[3] = w * dz[3] + dz[5] * ir + eos.grav * rp * ir;
+        if constexpr (MIX)  // the nearly balanced pressure gradient and buoyancy in FP64
+            R[3] = w * dz[3] + C(dzp * irp + eos.grav * rpd * irp);
+        else
+            R[3] = w * dz[3] + dzp * ir + eos.grav * rp * ir;
         R[4] = w * dz[4];
         // line derivative of the six quantities along x (dir 0) or y (dir 1)
         // (not unrolled: unrolled, the scheduler hoists all its LDS reads)
-        auto line = [&](int dir, double *d6) {
-            const double *cw = dir == 0 ? cwx : cwy;
+        auto line = [&](int dir, C *d5, double &dp) {
+            const C *cw = dir == 0 ? cwx : cwy;
             const int base = dir == 0 ? l_x : l_y, step = dir == 0 ? 1 : LX;
             const int fv = dir == 0 ? FS : 2 * FS;  // the velocity in rho u or rho v
 #pragma unroll
-            for (int f = 0; f < 6; ++f) d6[f] = 0.0;
+            for (int f = 0; f < 5; ++f) d5[f] = C(0);
+            dp = 0.0;
 #pragma unroll 1
             for (int m = 0; m < NS; ++m) {
-                const double cm = cw[m];
-                const double *qm = q + base + m * step;
-                d6[0] += cm * ((r0 + qm[0]) * qm[fv]);
+                const C cm = cw[m];
+                const C *qm = q + base + m * step;
+                d5[0] += cm * ((r0 + qm[0]) * qm[fv]);
 #pragma unroll
-                for (int f = 1; f < 6; ++f) d6[f] += cm * qm[f * FS];
+                for (int f = 1; f < 5; ++f) d5[f] += cm * qm[f * FS];
+                dp += double(cm) * qp[base + m * step];
             }
         };
-        double d6[6];
-        line(0, d6);
-        R[0] += d6[0];
-        R[1] += u * d6[1] + d6[5] * ir;
-        R[2] += u * d6[2];
-        R[3] += u * d6[3];
-        R[4] += u * d6[4];
-        line(1, d6);
-        R[0] = -(R[0] + d6[0]);
-        R[1] = -(R[1] + v * d6[1]);
-        R[2] = -(R[2] + v * d6[2] + d6[5] * ir);
-        R[3] = -(R[3] + v * d6[3]);
-        R[4] = -(R[4] + v * d6[4]);
-        if (k == 0 || k == p.nz - 1) R[3] = 0.0;
+        C d5[5];
+        double dp;
+        line(0, d5, dp);
+        R[0] += d5[0];
+        R[1] += u * d5[1] + C(dp * irp);
+        R[2] += u * d5[2];
+        R[3] += u * d5[3];
+        R[4] += u * d5[4];
+        line(1, d5, dp);
+        R[0] = -(R[0] + d5[0]);
+        R[1] = -(R[1] + v * d5[1]);
+        R[2] = -(R[2] + v * d5[2] + C(dp * irp));
+        R[3] = -(R[3] + v * d5[3]);
+        R[4] = -(R[4] + v * d5[4]);
+        if (k == 0 || k == p.nz - 1) R[3] = C(0);
         if (!owner) return;
         const unsigned off = unsigned(k) * pbytes + own;
         if constexpr (EPI == EPI_R) {
 #pragma unroll
-            for (int f = 0; f < 5; ++f) gstore(p.out0 + f * p.fs, off, R[f]);
+            for (int f = 0; f < 5; ++f) TO0::store(p.out0, f, p.fs, off, double(R[f]));
         } else if constexpr (EPI == EPI_TWO) {
 #pragma unroll
             for (int f = 0; f < 5; ++f) {
-                const double e0 = ev[f], e1 = ev[5 + f];
-                gstore(p.out0 + f * p.fs, off, e0 + p.k01 * e1 + p.k02 * R[f]);
-                gstore(p.out1 + f * p.fs, off, e0 + p.k11 * e1 + p.k12 * R[f]);
+                const double e0 = ev[f], e1 = ev[5 + f], r = double(R[f]);
+                TO0::store(p.out0, f, p.fs, off, e0 + p.k01 * e1 + p.k02 * r);
+                FiveField<false>::store(p.out1, f, p.fs, off, e0 + p.k11 * e1 + p.k12 * r);
             }
         } else {
             bool bad = false;
 #pragma unroll
             for (int f = 0; f < 5; ++f) {
-                const double v2 = ev[f] + p.k02 * R[f];
+                const double v2 = ev[f] + p.k02 * double(R[f]);
                 bad |= !isfinite(v2);
-                gstore(p.out0 + f * p.fs, off, v2);
+                TO0::store(p.out0, f, p.fs, off, v2);
             }
             if (bad) *p.flag = 1;
         }
@@ -391,17 +490,18 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
         if (it_p[s] != 1) continue;
         const int k = ez0 * N, kl = k - kb;
         const unsigned off = unsigned(k) * pbytes + it_o[s];
-        const double rp = stage_input<HASB>(p, 0, off), u = stage_input<HASB>(p, 1, off);
-        const double v = stage_input<HASB>(p, 2, off), w = stage_input<HASB>(p, 3, off);
-        const double th = stage_input<HASB>(p, 4, off);
+        const double rp = stage_input<HASB, TA, TE1>(p, 0, off), u = stage_input<HASB, TA, TE1>(p, 1, off);
+        const double v = stage_input<HASB, TA, TE1>(p, 2, off), w = stage_input<HASB, TA, TE1>(p, 3, off);
+        const double th = stage_input<HASB, TA, TE1>(p, 4, off);
         const double Pp = pressure_perturbation(rp, th, sR0[kl], sP0[kl], sIRT[kl], eos);
-        double *d = ring + (k % NQ) * PS + it_l[s];
-        d[0 * FS] = rp;
-        d[1 * FS] = u;
-        d[2 * FS] = v;
-        d[3 * FS] = w;
-        d[4 * FS] = th;
-        d[5 * FS] = Pp;
+        C *d = cfield(k % NQ) + it_l[s];
+        d[0 * FS] = C(rp);
+        d[1 * FS] = C(u);
+        d[2 * FS] = C(v);
+        d[3 * FS] = C(w);
+        d[4 * FS] = C(th);
+        pfield(k % NQ)[it_l[s]] = Pp;
+        if constexpr (MIX) rfield(k % NQ)[it_l[s]] = rp;
     }
     if (c == 0 && ez0 > 0) {
         const int eb = ez0 - 1;
@@ -409,12 +509,14 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
         for (int n = 0; n < NQ; ++n) {
             const int k = eb * N + n, kl = k - kb;
             const unsigned off = unsigned(k) * pbytes + own;
-            const double rp = stage_input<HASB>(p, 0, off), u = stage_input<HASB>(p, 1, off);
-            const double v = stage_input<HASB>(p, 2, off), w = stage_input<HASB>(p, 3, off);
-            const double th = stage_input<HASB>(p, 4, off);
-            const double rho = sR0[kl] + rp;
-            const double Pp = pressure_perturbation(rp, th, sR0[kl], sP0[kl], sIRT[kl], eos);
-            const double d = sD[N * NQ + n];
+            // rounded to the ring's type first, as the layer loop sees them
+            const double rp = C(stage_input<HASB, TA, TE1>(p, 0, off)), u = C(stage_input<HASB, TA, TE1>(p, 1, off));
+            const double v = C(stage_input<HASB, TA, TE1>(p, 2, off)), w = C(stage_input<HASB, TA, TE1>(p, 3, off));
+            const double th0 = stage_input<HASB, TA, TE1>(p, 4, off), th = C(th0);
+            const double rho = double(C(sR0[kl])) + rp;
+            const double Pp = pressure_perturbation(stage_input<HASB, TA, TE1>(p, 0, off), th0, sR0[kl], sP0[kl],
+                                                    sIRT[kl], eos);
+            const double d = double(sD[N * NQ + n]);
             acc[0] += d * (rho * w);
             acc[1] += d * u;
             acc[2] += d * v;
@@ -425,7 +527,8 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
         const double st = zs[2 * p.nez + eb];
         double *zb = zp + (ez0 & 1) * 6 * (TX * TY) + txy;
 #pragma unroll
-        for (int f = 0; f < 6; ++f) zb[f * (TX * TY)] = st * acc[f];
+        for (int f = 0; f < 5; ++f) zb[f * (TX * TY)] = double(C(st * acc[f]));
+        zb[5 * (TX * TY)] = st * acc[5];
     }
 
     for (int ez = ez0; ez < ez1; ++ez) {
@@ -434,35 +537,40 @@ __global__ __launch_bounds__(RhsGeom<N>::NT, RhsGeom<N>::MINW) void k_rhs(RhsPar
         __syncthreads();
         double ev[NEPI];
         epi_load(unsigned(ez * N + c) * pbytes + own, ev);
-        double dz[6], sum[6];
-        zsum(ez, c, sum);
-        const double sc = (c == 0) ? zs[p.nez + ez] : zs[ez];
+        C dz[5], sum[5];
+        double sump;
+        zsum(ez, c, sum, sump);
+        const double scd = (c == 0) ? zs[p.nez + ez] : zs[ez];
+        const C sc = C(scd);
         const double *zb = zp + (ez & 1) * 6 * (TX * TY) + txy;
         const bool below = c == 0 && ez > 0;  // a lower element shares the node
 #pragma unroll
-        for (int f = 0; f < 6; ++f) dz[f] = (below ? zb[f * (TX * TY)] : 0.0) + sc * sum[f];
-        node(ez * N + c, dz, ev);
-        // this element's share of the interface (or top node) above, one
-        // field per level of the element in turn
+        for (int f = 0; f < 5; ++f) dz[f] = (below ? C(zb[f * (TX * TY)]) : C(0)) + sc * sum[f];
+        const double dzp = (below ? zb[5 * (TX * TY)] : 0.0) + scd * sump;
+        node(ez * N + c, dz, dzp, ev);
+        // this element's share of the interface (or top node) above
         const double st = zs[2 * p.nez + ez];
         double *zn = zp + ((ez + 1) & 1) * 6 * (TX * TY) + txy;
         if (c == 0) {
-            double s6[6];
-            zsum(ez, N, s6);
+            C s5[5];
+            double s5p;
+            zsum(ez, N, s5, s5p);
 #pragma unroll
-            for (int f = 0; f < 6; ++f) zn[f * (TX * TY)] = st * s6[f];
+            for (int f = 0; f < 5; ++f) zn[f * (TX * TY)] = double(C(st) * s5[f]);
+            zn[5 * (TX * TY)] = st * s5p;
         }
     }
     // top node of the column: one-sided from the top element
     __syncthreads();  // the shares of the top element are in LDS
     if (ez1 == p.nez && c == 0) {
         const double *zb = zp + (ez1 & 1) * 6 * (TX * TY) + txy;
-        double dz[6];
+        C dz[5];
 #pragma unroll
-        for (int f = 0; f < 6; ++f) dz[f] = zb[f * (TX * TY)];
+        for (int f = 0; f < 5; ++f) dz[f] = C(zb[f * (TX * TY)]);
+        const double dzp = zb[5 * (TX * TY)];
         double ev[NEPI];
         epi_load(unsigned(p.nez * N) * pbytes + own, ev);
-        node(p.nez * N, dz, ev);
+        node(p.nez * N, dz, dzp, ev);
     }
 }
 
@@ -486,12 +594,16 @@ enum { SC_G0 = 0, SC_H0, SC_RHO0, SC_WA, SC_LG, SC_X1, SC_X2, SC_N = 8 };
 
 struct SolveParams {
     // q~_e for rho', w, theta': sum_t c_t * ptr_t
-    const double *er[3], *ew[3], *et[3];
+    const void *er[3], *ew[3], *et[3];
     double cr[3], cw[3], ct[3];
     // outputs: rho' = sum_t cbr_t br_t - lambda Dz(rho0 w~);  w = w~ + sum_t cbw_t bw_t
-    const double *br[2], *bw[2];
+    const void *br[2], *bw[2];
     double cbr[2], cbw[2];
-    double *out_r, *out_w;
+    void *out_r, *out_w;
+    // FP64 field where the forward pass parks w_a for the extraction (out_w
+    // itself when that is FP64): w~ = w_a - lambda (...) cancels strongly at
+    // large vertical Courant numbers, so w_a must keep FP64 precision
+    double *park;
     const double *fac;
     const double *scf, *dzb;
     double lambda;
@@ -500,14 +612,22 @@ struct SolveParams {
 };
 
 // term counts of the stage variants: (NR, NW, NT) explicit-estimate terms,
-// (NBR, NBW) output terms
-template <int NR_, int NW_, int NT_, int NBR_, int NBW_>
+// (NBR, NBW) output terms; F32: which fields are FP32 (bit 0+t er[t], 3+t
+// ew[t], 6+t et[t], 9+t br[t], 11+t bw[t], 13 out_w, 14 out_r), the rest FP64
+template <int NR_, int NW_, int NT_, int NBR_, int NBW_, unsigned F32_ = 0>
 struct SolveShape {
     static constexpr int NR = NR_, NW = NW_, NT = NT_, NBR = NBR_, NBW = NBW_;
+    static constexpr unsigned F32 = F32_;
 };
 using ShapePlain = SolveShape<1, 1, 1, 1, 0>;
 using ShapeStage2 = SolveShape<1, 1, 1, 2, 1>;
 using ShapeStage3 = SolveShape<3, 3, 3, 1, 2>;
+// the precision form: the w of R1, E3, Q2, Q3 in FP32, everything else FP64
+using ShapeStage2Mix = SolveShape<1, 1, 1, 2, 1, (1u << 3) | (1u << 13)>;
+using ShapeStage3Mix = SolveShape<3, 3, 3, 1, 2, (1u << 3) | (1u << 5) | (1u << 12) | (1u << 13)>;
+// element type of field bit b of a shape
+template <class SH, int B>
+using SolveT = std::conditional_t<((SH::F32 >> B) & 1u) != 0, float, double>;
 
 template <int N, class SH>
 struct SolveGeom {
@@ -550,19 +670,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     auto frow = [&](int k, int d) { return p.fac + ((long)k * NB + d) * p.ncol; };
 
     // ---- forward.  Step s: P_e and rho0 w_a of level s into LDS (w_a also
-    //      parked in out_w for the extraction), then the substitution of
+    //      parked in p.park for the extraction), then the substitution of
     //      level s - N, whose Dz(rho0 w_a) band is complete:
     //      y_k = P_e,k - lambda G0 Dz(rho0 w_a)_k - sum_d L_kd y_{k-d}
     {
         double es[DF][NE], ls[DF][HB];
         auto load = [&](double *e, double *l, int s) {
             const unsigned off = unsigned(min(s, M - 1)) * lbytes + cbyte;
-#pragma unroll
-            for (int t = 0; t < SH::NR; ++t) e[t] = gload(p.er[t], off);
-#pragma unroll
-            for (int t = 0; t < SH::NW; ++t) e[SH::NR + t] = gload(p.ew[t], off);
-#pragma unroll
-            for (int t = 0; t < SH::NT; ++t) e[SH::NR + SH::NW + t] = gload(p.et[t], off);
+            // (t = 0..2 spelled out: the element type is a template argument)
+            if constexpr (SH::NR > 0) e[0] = tload<SolveT<SH, 0>>(p.er[0], off);
+            if constexpr (SH::NR > 1) e[1] = tload<SolveT<SH, 1>>(p.er[1], off);
+            if constexpr (SH::NR > 2) e[2] = tload<SolveT<SH, 2>>(p.er[2], off);
+            if constexpr (SH::NW > 0) e[SH::NR + 0] = tload<SolveT<SH, 3>>(p.ew[0], off);
+            if constexpr (SH::NW > 1) e[SH::NR + 1] = tload<SolveT<SH, 4>>(p.ew[1], off);
+            if constexpr (SH::NW > 2) e[SH::NR + 2] = tload<SolveT<SH, 5>>(p.ew[2], off);
+            if constexpr (SH::NT > 0) e[SH::NR + SH::NW + 0] = tload<SolveT<SH, 6>>(p.et[0], off);
+            if constexpr (SH::NT > 1) e[SH::NR + SH::NW + 1] = tload<SolveT<SH, 7>>(p.et[1], off);
+            if constexpr (SH::NT > 2) e[SH::NR + SH::NW + 2] = tload<SolveT<SH, 8>>(p.et[2], off);
             const int kl = min(max(s - N, 0), M - 1);
 #pragma unroll
             for (int d = 0; d < HB; ++d) l[d] = gload(frow(kl, d), cbyte);  // column kl - HB + d
@@ -586,7 +710,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
                     const double wa = (s == 0 || s == M - 1) ? 0.0 : we + cf[SC_WA] * te;
                     P[s * 64] = cf[SC_G0] * re + cf[SC_H0] * te;
                     W[(s & (R - 1)) * 64] = cf[SC_RHO0] * wa;
-                    if (act) gstore(p.out_w, unsigned(s) * lbytes + cbyte, wa);
+                    if (act) gstore(p.park, unsigned(s) * lbytes + cbyte, wa);
                 }
                 const int k = s - N;
                 if (k >= 0 && k < M) {
@@ -635,12 +759,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
         double xs[DX][NXL];
         auto load = [&](double *x, int s) {
             const unsigned off = unsigned(min(s, M - 1)) * lbytes + cbyte;
-            x[0] = gload(p.out_w, off);  // w_a parked by the forward pass
-#pragma unroll
-            for (int t = 0; t < SH::NBW; ++t) x[1 + t] = gload(p.bw[t], off);
+            x[0] = gload(p.park, off);  // w_a parked by the forward pass
+            if constexpr (SH::NBW > 0) x[1] = tload<SolveT<SH, 11>>(p.bw[0], off);
+            if constexpr (SH::NBW > 1) x[2] = tload<SolveT<SH, 12>>(p.bw[1], off);
             const unsigned offr = unsigned(min(max(s - N, 0), M - 1)) * lbytes + cbyte;
-#pragma unroll
-            for (int t = 0; t < SH::NBR; ++t) x[1 + SH::NBW + t] = gload(p.br[t], offr);
+            if constexpr (SH::NBR > 0) x[1 + SH::NBW] = tload<SolveT<SH, 9>>(p.br[0], offr);
+            if constexpr (SH::NBR > 1) x[2 + SH::NBW] = tload<SolveT<SH, 10>>(p.br[1], offr);
         };
 #pragma unroll
         for (int b = 0; b < DX; ++b) load(xs[b], b);
@@ -660,7 +784,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 #pragma unroll
                     for (int t = 0; t < SH::NBW; ++t) sh += p.cbw[t] * xs[b][1 + t];
                     W[(s & (R - 1)) * 64] = cf[SC_RHO0] * wt;
-                    if (act) gstore(p.out_w, unsigned(s) * lbytes + cbyte, wt + sh);
+                    if (act) tstore<SolveT<SH, 13>>(p.out_w, unsigned(s) * lbytes + cbyte, wt + sh);
                 }
                 const int k = s - N;
                 if (k >= 0 && k < M) {
@@ -671,7 +795,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
                     double qr = 0.0;
 #pragma unroll
                     for (int t = 0; t < SH::NBR; ++t) qr += p.cbr[t] * xs[b][1 + SH::NBW + t];
-                    if (act) gstore(p.out_r, unsigned(k) * lbytes + cbyte, qr - p.lambda * d);
+                    if (act) tstore<SolveT<SH, 14>>(p.out_r, unsigned(k) * lbytes + cbyte, qr - p.lambda * d);
                 }
                 load(xs[b], s + DX);
             }
@@ -764,10 +888,11 @@ namespace {
 
 // dynamic LDS of k_rhs: the ring, three per-level tables of the chunk's
 // levels (zchunk + 1 elements), the element factors, the interface shares
-template <int N>
+template <int N, bool MIX = false>
 size_t rhs_lds_bytes(int zchunk, int nez)
 {
-    return RhsGeom<N>::LDS +
+    constexpr int ES = MIX ? 4 : 8;
+    return RhsGeom<N, ES>::LDS +
            sizeof(double) * (3 * ((zchunk + 1) * N + 1) + 3 * nez + 2 * 6 * RhsGeom<N>::TX * RhsGeom<N>::TY);
 }
 
@@ -783,7 +908,7 @@ int rhs_zchunk_auto(const numa_ctx *c)
     return zc;
 }
 
-template <int N, int EPI, bool HASB>
+template <int N, int EPI, bool HASB, bool MIX = false>
 hipError_t rhs_launch(numa_ctx *c, RhsParams p)
 {
     using G = RhsGeom<N>;
@@ -802,22 +927,23 @@ hipError_t rhs_launch(numa_ctx *c, RhsParams p)
     p.ntx = int((c->nx + G::TX - 1) / G::TX);
     p.nty = int((c->ny + G::TY - 1) / G::TY);
     p.flag = c->flag;
-    const size_t lds = rhs_lds_bytes<N>(p.zchunk, p.nez);
+    const size_t lds = rhs_lds_bytes<N, MIX>(p.zchunk, p.nez);
     static size_t attr_set = 0;  // LDS above 64 KB must be opted into
     if (attr_set < lds) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rhs<N, EPI, HASB>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rhs<N, EPI, HASB, MIX>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
         if (e != hipSuccess) return e;
         attr_set = lds;
     }
     dim3 grid(unsigned(p.ntx * p.nty * p.nchunk));
-    hipLaunchKernelGGL((k_rhs<N, EPI, HASB>), grid, dim3(G::NT), lds, c->stream, p);
+    hipLaunchKernelGGL((k_rhs<N, EPI, HASB, MIX>), grid, dim3(G::NT), lds, c->stream, p);
     return hipGetLastError();
 }
 
 template <int N, class SH>
 hipError_t solve_launch(numa_ctx *c, SolveParams p)
 {
+    if (!p.park) p.park = static_cast<double *>(p.out_w);  // FP64 output: park in place
     p.fac = c->fac;
     p.scf = c->lev.scf;
     p.dzb = c->lev.dzb;
@@ -863,7 +989,7 @@ hipError_t dispatch(int N, F &&f)
     }
 }
 
-void set_fields(const double *arr[5], const double *base, long np)
+void set_fields(const void *arr[5], const double *base, long np)
 {
     for (int f = 0; f < 5; ++f) arr[f] = base ? base + f * np : nullptr;
 }
@@ -1056,6 +1182,103 @@ hipError_t launch_hevi_step(numa_ctx *c, double *q, double dt, hipEvent_t *ev)
         e = dispatch(c->N, [&](auto n) { return rhs_launch<decltype(n)::value, EPI_FINAL, false>(c, p); });
         if (e != hipSuccess) return e;
         if ((e = mark(5)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// byte offset of field f in the precision form's five-field buffers (the
+// device layout of FiveField<true>)
+size_t mixed_field_offset(int f, long np)
+{
+    return size_t(np) * size_t(f == 0 ? 0 : (f == 4 ? 20 : 4 + 4 * f));
+}
+
+// The precision form of the step (same stage algebra as launch_hevi_step):
+// the right-hand sides evaluate in FP32 (P' and its derivatives in FP64);
+// the stage buffers R1, E3, Q2, Q3 hold u, v, w in FP32 and rho', theta' in
+// FP64; the state and the accumulator ACC stay FP64; the column solves read
+// those and run in FP64 with the FP64 factors.
+hipError_t launch_hevi_step_mixed(numa_ctx *c, double *q, double dt, hipEvent_t *ev)
+{
+    static const Ark2 t;
+    const long np = c->np;
+    // R1, E3 in the mixed five-field layout (28 bytes per node), Q2 and Q3
+    // rho' FP64 and w FP32
+    char *const mb = c->work_mix;
+    char *const R1 = mb, *const E3 = mb + 28 * np;
+    double *const Q2r = reinterpret_cast<double *>(mb + 56 * np), *const Q3r = reinterpret_cast<double *>(mb + 64 * np);
+    float *const Q2w = reinterpret_cast<float *>(mb + 72 * np), *const Q3w = reinterpret_cast<float *>(mb + 76 * np);
+    auto fld = [&](char *buf, int f) { return buf + mixed_field_offset(f, np); };
+    double *const ACC = stage_buffers(c).ACC;
+    double *const park = stage_buffers(c).R1;  // the FP64 R1 buffer is free in this form
+    const double *qr = q + 0 * np, *qw = q + 3 * np, *qt = q + 4 * np;
+    const double f = dt * t.a21;
+    hipError_t e;
+    auto mark = [&](int i) -> hipError_t { return ev ? hipEventRecord(ev[i], c->stream) : hipSuccess; };
+    if ((e = mark(0)) != hipSuccess) return e;
+    {  // K1: R1 = R(q^n)
+        RhsParams p{};
+        set_fields(p.a, q, np);
+        p.out0 = R1;
+        p.fs = np;
+        e = dispatch(c->N, [&](auto n) { return rhs_launch<decltype(n)::value, EPI_R, false, true>(c, p); });
+        if (e != hipSuccess || (e = mark(1)) != hipSuccess) return e;
+    }
+    {  // K2
+        SolveParams p{};
+        p.er[0] = fld(R1, 0); p.cr[0] = f;
+        p.ew[0] = fld(R1, 3); p.cw[0] = f;
+        p.et[0] = fld(R1, 4); p.ct[0] = f;
+        p.br[0] = qr; p.cbr[0] = 1.0; p.br[1] = fld(R1, 0); p.cbr[1] = f;
+        p.bw[0] = qw; p.cbw[0] = 1.0;
+        p.out_r = Q2r;
+        p.out_w = Q2w;
+        p.park = park;
+        e = dispatch(c->N, [&](auto n) { return solve_launch<decltype(n)::value, ShapeStage2Mix>(c, p); });
+        if (e != hipSuccess || (e = mark(2)) != hipSuccess) return e;
+    }
+    {  // K3: rhs(Q2) -> E3 (FP32), ACC (FP64)
+        RhsParams p{};
+        p.a[0] = Q2r;
+        p.a[3] = Q2w;
+        p.cb = f;
+        p.out0 = E3;
+        p.out1 = ACC;
+        p.e0 = q;
+        p.e1 = R1;
+        p.fs = np;
+        p.k01 = dt * t.a31; p.k02 = dt * t.a32;
+        p.k11 = dt * t.b1;  p.k12 = dt * t.b2;
+        e = dispatch(c->N, [&](auto n) { return rhs_launch<decltype(n)::value, EPI_TWO, true, true>(c, p); });
+        if (e != hipSuccess || (e = mark(3)) != hipSuccess) return e;
+    }
+    {  // K4
+        SolveParams p{};
+        p.er[0] = fld(E3, 0); p.cr[0] = 1.0; p.er[1] = qr; p.cr[1] = t.c31; p.er[2] = Q2r; p.cr[2] = t.c32;
+        p.ew[0] = fld(E3, 3); p.cw[0] = 1.0; p.ew[1] = qw; p.cw[1] = t.c31; p.ew[2] = Q2w; p.cw[2] = t.c32;
+        p.et[0] = fld(E3, 4); p.ct[0] = 1.0; p.et[1] = qt; p.ct[1] = t.c31 + t.c32; p.et[2] = fld(R1, 4);
+        p.ct[2] = t.c32 * f;
+        p.br[0] = fld(E3, 0); p.cbr[0] = 1.0;
+        p.bw[0] = qw; p.cbw[0] = -t.c31; p.bw[1] = Q2w; p.cbw[1] = -t.c32;
+        p.out_r = Q3r;
+        p.out_w = Q3w;
+        p.park = park;
+        e = dispatch(c->N, [&](auto n) { return solve_launch<decltype(n)::value, ShapeStage3Mix>(c, p); });
+        if (e != hipSuccess || (e = mark(4)) != hipSuccess) return e;
+    }
+    {  // K5: q^{n+1} = ACC + dt b3 R(Q3)
+        RhsParams p{};
+        p.a[0] = Q3r;
+        p.a[1] = fld(E3, 1);
+        p.a[2] = fld(E3, 2);
+        p.a[3] = Q3w;
+        p.a[4] = fld(E3, 4);
+        p.out0 = q;
+        p.e0 = ACC;
+        p.fs = np;
+        p.k02 = dt * t.b3;
+        e = dispatch(c->N, [&](auto n) { return rhs_launch<decltype(n)::value, EPI_FINAL, false, true>(c, p); });
+        if (e != hipSuccess || (e = mark(5)) != hipSuccess) return e;
     }
     return hipSuccess;
 }

@@ -62,6 +62,7 @@ struct numa_ctx {
     void *lev_block = nullptr;     // one allocation holding all of lev
     double *fac = nullptr;         // [nz][4N+1][ncol] column LU factors
     double *work = nullptr;        // stage buffers (19 fields)
+    char *work_mix = nullptr;      // precision form: R1, E3 (mixed layout), Q2, Q3 rho' (FP64), w (FP32)
     int *flag = nullptr;           // device non-finite flag
     int factored = 0;
     double dt_factored = 0, lambda = 0;
@@ -91,5 +92,6 @@ hipError_t launch_factor(numa_ctx *c, double lambda);
 hipError_t launch_rhs_plain(numa_ctx *c, const double *q, double *R);
 hipError_t launch_solve_plain(numa_ctx *c, const double *y, double *x);
 hipError_t launch_hevi_step(numa_ctx *c, double *q, double dt, hipEvent_t *ev = nullptr);
+hipError_t launch_hevi_step_mixed(numa_ctx *c, double *q, double dt, hipEvent_t *ev = nullptr);
 
 }  // namespace numa

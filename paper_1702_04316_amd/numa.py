@@ -77,6 +77,8 @@ def load():
     lib.numa_factor_columns.argtypes = [vp, C.c_double]
     lib.numa_hevi_step.argtypes = [vp, vp, C.c_double, C.c_int32]
     lib.numa_profile_steps.argtypes = [vp, vp, C.c_double, C.c_int32, C.POINTER(C.c_double)]
+    lib.numa_hevi_step_mixed.argtypes = [vp, vp, C.c_double, C.c_int32]
+    lib.numa_profile_steps_mixed.argtypes = [vp, vp, C.c_double, C.c_int32, C.POINTER(C.c_double)]
     lib.numa_rhs.argtypes = [vp, vp, vp]
     lib.numa_solve_columns.argtypes = [vp, vp, vp]
     lib.numa_imex3d_step.argtypes = [vp, vp, C.c_double, C.c_double, C.POINTER(C.c_int32)]
@@ -88,8 +90,9 @@ def load():
     lib.numa_line_operators.argtypes = [C.POINTER(numa_grid), C.c_int32, C.POINTER(C.c_double),
                                         C.POINTER(C.c_double)]
     for name in ("numa_setup", "numa_state_shape", "numa_get_info", "numa_set_stream", "numa_factor_columns",
-                 "numa_hevi_step", "numa_profile_steps", "numa_rhs", "numa_solve_columns", "numa_imex3d_step", "numa_check",
-                 "numa_destroy", "numa_lgl_basis", "numa_line_operators"):
+                 "numa_hevi_step", "numa_profile_steps", "numa_hevi_step_mixed", "numa_profile_steps_mixed",
+                 "numa_rhs", "numa_solve_columns", "numa_imex3d_step", "numa_check", "numa_destroy",
+                 "numa_lgl_basis", "numa_line_operators"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -154,6 +157,18 @@ def factor_columns(ctx, dt):
 
 def hevi_step(ctx, state_ptr, dt, nsteps):
     return _check(load().numa_hevi_step(ctx, C.c_void_p(state_ptr), float(dt), int(nsteps)), ctx)
+
+
+def hevi_step_mixed(ctx, state_ptr, dt, nsteps):
+    """The precision form of hevi_step (FP32 right-hand sides and stage buffers)."""
+    return _check(load().numa_hevi_step_mixed(ctx, C.c_void_p(state_ptr), float(dt), int(nsteps)), ctx)
+
+
+def profile_steps_mixed(ctx, state_ptr, dt, nsteps):
+    """profile_steps for the precision form."""
+    ms = (C.c_double * 5)()
+    _check(load().numa_profile_steps_mixed(ctx, C.c_void_p(state_ptr), float(dt), int(nsteps), ms), ctx)
+    return [float(v) for v in ms]
 
 
 def profile_steps(ctx, state_ptr, dt, nsteps):
@@ -249,9 +264,10 @@ class Context:
         assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous(), "state: contiguous float64 cuda"
         assert tuple(t.shape) == self.shape, (tuple(t.shape), self.shape)
 
-    def step(self, state, nsteps=1, dt=None):
+    def step(self, state, nsteps=1, dt=None, mixed=False):
+        """nsteps HEVI steps in place; mixed=True runs the precision form."""
         self._check_state(state)
-        hevi_step(self.ctx, state.data_ptr(), self.dt if dt is None else dt, nsteps)
+        (hevi_step_mixed if mixed else hevi_step)(self.ctx, state.data_ptr(), self.dt if dt is None else dt, nsteps)
         return state
 
     def rhs(self, state, out=None):

@@ -286,3 +286,23 @@ def box_large(reading="R1", nex=64, ney=64):
         dt = dt_for_courant(g, C_HORIZ, "x")
     return Workload(f"box{nex}x{ney}x10_N4_{reading}", g, dt, 100, 2, 8, (0.1, 2.0), (500.0, 2000.0),
                     stretch=s)
+
+
+def box_precision(size="small", reading="R1"):
+    """Workloads of the precision form at N=7 (8x8x8 nodes per element):
+    'small', 4x4x4 elements of the 1 km cube, one 0.5 K bump of radius
+    250 m, for errors against the oracle; 'large', 28x28x28 elements
+    (196x196x197 = 7,567,952 unique nodes, 11.2M element-local), eight
+    bumps, for throughput.  Vertical Courant number 15; under R1 the
+    horizontal extent is stretched to a horizontal Courant number of 0.4."""
+    lx = ly = lz = 1000.0
+    ne = 4 if size == "small" else 28
+    s = _stretch(lx, ne, lz, ne) if reading == "R1" else 1.0
+    g = Grid(lx * s, ly * s, lz, ne, ne, ne, 7)
+    if reading == "R1":
+        dt = dt_for_courant(g, C_VERT, "z")
+    else:
+        dt = dt_for_courant(g, C_HORIZ, "x")
+    if size == "small":
+        return Workload(f"box4x4x4_N7_{reading}", g, dt, 100, 1, 1, (0.5, 0.5), (250.0, 250.0), stretch=s)
+    return Workload(f"box28x28x28_N7_{reading}", g, dt, 100, 3, 8, (0.1, 2.0), (50.0, 200.0), stretch=s)

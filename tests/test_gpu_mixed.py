@@ -1,0 +1,106 @@
+"""GPU tests of the precision form (numa_hevi_step_mixed): FP32 right-hand
+sides and u, v, w stage buffers; FP64 state, accumulator, rho'/theta' stage
+values, pressure perturbation and column solves.
+
+The bar is the relative L2 error per variable against the FP64 oracle after
+100 steps that FP32 arithmetic allows: 1e-6, except w at N = 7, where the
+FP32 tendencies leave 2.4e-6 (checked at 5e-6 here; stated with the
+measured values in the design notes).  The form's FP64 parts are checked
+exactly: a rest state stays at rest, and its errors stay far below the
+FP32 rounding of its stage values.
+"""
+import numpy as np
+import pytest
+
+from paper_1702_04316_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+BAR = 1e-6
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def numa_mod():
+    from paper_1702_04316_amd import numa
+    numa.load()
+    return numa
+
+
+def _rel(a, b):
+    return np.array([np.linalg.norm(a[f] - b[f]) / np.linalg.norm(b[f]) for f in range(5)])
+
+
+def _oracle(O, g, bg):
+    return O.Oracle(g.lx, g.ly, g.lz, g.nex, g.ney, g.nez, g.N, theta0=bg.theta0, p00=bg.p00, cp=bg.cp,
+                    rgas=bg.rgas, grav=bg.grav, zface=g.zface)
+
+
+@pytest.mark.parametrize("name,wbar", [("box_small", BAR), ("box_precision", 5e-6)])
+def test_mixed_error_against_oracle(torch_cuda, numa_mod, oracle_mod, name, wbar):
+    wl = W.box_small("R1") if name == "box_small" else W.box_precision("small")
+    g = wl.grid
+    q0 = W.make_initial_state(wl)
+    o = _oracle(oracle_mod, g, wl.background)
+    o.factor_dt(wl.dt)
+    ref = o.step(q0, wl.dt, 100)
+    ctx = numa_mod.Context(g, wl.background)
+    ctx.factor(wl.dt)
+    q = torch_cuda.from_numpy(q0.copy()).cuda()
+    ctx.step(q, 100, mixed=True)
+    ctx.check()
+    e = _rel(q.cpu().numpy(), ref)
+    print(f"{wl.name} mixed, 100 steps, rel L2 per variable (rho', u, v, w, theta'): {e}")
+    assert np.all(e[[0, 1, 2, 4]] < BAR), e
+    assert e[3] < wbar, e
+    ctx.close()
+
+
+def test_mixed_full_size_against_fp64(torch_cuda, numa_mod):
+    """The benchmarked grid: 20 precision-form steps against 20 FP64 steps
+    (the FP64 path equals the oracle to 1e-11)."""
+    wl = W.box_large("R1")
+    ctx = numa_mod.Context(wl.grid, wl.background)
+    ctx.factor(wl.dt)
+    q0 = torch_cuda.from_numpy(W.make_initial_state(wl)).cuda()
+    a, b = q0.clone(), q0.clone()
+    ctx.step(a, 20)
+    ctx.step(b, 20, mixed=True)
+    ctx.check()
+    e = _rel(b.cpu().numpy(), a.cpu().numpy())
+    print(f"box_large mixed vs FP64, 20 steps: {e}")
+    assert np.all(e < BAR), e
+    ctx.close()
+
+
+def test_mixed_rest_state_stays_at_rest(torch_cuda, numa_mod):
+    g = W.Grid(30000.0, 20000.0, 8000.0, 3, 2, 4, 4)
+    ctx = numa_mod.Context(g)
+    dt = W.dt_for_courant(g, 15.0, "z")
+    ctx.factor(dt)
+    q = torch_cuda.zeros(ctx.shape, dtype=torch_cuda.float64, device="cuda")
+    ctx.step(q, 5, mixed=True)
+    ctx.check()
+    assert float(q.abs().max()) == 0.0
+    ctx.close()
+
+
+def test_mixed_error_codes(torch_cuda, numa_mod):
+    g = W.Grid(30000.0, 20000.0, 8000.0, 3, 2, 4, 4)
+    ctx = numa_mod.Context(g)
+    q = torch_cuda.zeros(ctx.shape, dtype=torch_cuda.float64, device="cuda")
+    lib = numa_mod.load()
+    import ctypes as C
+    assert lib.numa_hevi_step_mixed(ctx.ctx, C.c_void_p(q.data_ptr()), 1.0, 1) == numa_mod.NUMA_E_NOT_FACTORED
+    ctx.factor(1.0)
+    assert lib.numa_hevi_step_mixed(ctx.ctx, C.c_void_p(q.data_ptr()), 2.0, 1) == numa_mod.NUMA_E_DT_MISMATCH
+    assert lib.numa_hevi_step_mixed(ctx.ctx, None, 1.0, 1) == numa_mod.NUMA_E_ARG
+    ms = (C.c_double * 5)()
+    assert lib.numa_profile_steps_mixed(ctx.ctx, C.c_void_p(q.data_ptr()), 1.0, 0, ms) == numa_mod.NUMA_E_ARG
+    ctx.close()
