@@ -120,6 +120,55 @@ def precision_form(numa, torch, ctx, wl, args, t_fp64):
     }
 
 
+def batched_ensemble(numa, torch, steps=50):
+    """Sixteen seeded domains of different sizes and orders (3..7), stepped
+    (a) one after another with the eager FP64 step (the baseline), (b)
+    together through the captured ensemble graph with tuned vertical
+    chunks, FP64, and (c) the same in the precision form.  Aggregate
+    DOF-steps/s over all domains; inputs resident in HBM."""
+    from paper_1702_04316_amd import workloads as W
+    doms = W.ensemble_domains()
+    ctxs, q0 = [], []
+    for wl in doms:
+        c = numa.Context(wl.grid, wl.background)
+        c.factor(wl.dt)
+        ctxs.append(c)
+        q0.append(torch.from_numpy(W.make_initial_state(wl)).to("cuda"))
+    dof = sum(5 * wl.grid.n_unique for wl in doms)
+
+    def timed(run):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    qs = [q.clone() for q in q0]
+    for c, q in zip(ctxs, qs):
+        c.step(q, 2)
+    t_seq = timed(lambda: [c.step(q, steps) for c, q in zip(ctxs, qs)])
+    for c in ctxs:
+        c.check()
+    out = {"domains": len(doms), "steps": steps, "dof_per_step": dof,
+           "orders": sorted({wl.grid.N for wl in doms}),
+           "unique_nodes_range": [min(wl.grid.n_unique for wl in doms), max(wl.grid.n_unique for wl in doms)],
+           "sequential_fp64": {"value": dof * steps / t_seq, "ms_per_step": 1e3 * t_seq / steps}}
+    for name, mixed in (("ensemble_fp64", False), ("ensemble_mixed", True)):
+        qs = [q.clone() for q in q0]
+        ens = numa.Ensemble(ctxs, qs, mixed=mixed, tune=True)
+        ens.step(2)
+        ens.sync()
+        t = timed(lambda: ens.step(steps))
+        ens.sync()
+        out[name] = {"value": dof * steps / t, "ms_per_step": 1e3 * t / steps, "speedup_vs_sequential": t_seq / t}
+        out["tuned_zchunks"] = ens.zchunks()
+        ens.close()
+    out["unit"] = "DOF-steps/s"
+    for c in ctxs:
+        c.close()
+    return out
+
+
 def copy_probe(nbytes=1 << 30, reps=10):
     """A plain device-to-device copy of known size: the achievable HBM rate,
     and the calibration program for the FETCH_SIZE/WRITE_SIZE counters."""
@@ -144,6 +193,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble measurement")
     ap.add_argument("--copy-probe", action="store_true", help="only time a plain 1 GiB device copy")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -227,6 +277,8 @@ def main():
         "step_algorithmic_GBps": step_bytes * args.steps / t / 1e9,
     }
     out["precision_form"] = precision_form(numa, torch, ctx, wl, args, t)
+    if not args.no_ensemble:
+        out["batched_ensemble"] = batched_ensemble(numa, torch)
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline()

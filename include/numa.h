@@ -160,6 +160,40 @@ int numa_hevi_step_mixed(numa_ctx *c, double *state, double dt, int32_t nsteps);
 int numa_profile_steps_mixed(numa_ctx *c, double *state, double dt, int32_t nsteps, double *ms_out);
 
 /*
+ * Batched ensemble (a project addition for many small domains; the paper
+ * steps one domain at a time).  n contexts, each already factored with its
+ * dt, with their FP64 device states, are stepped together: one step of every
+ * domain is captured into a single HIP graph, each domain's five kernels on
+ * its own branch, so that domains too small to fill the GPU run side by
+ * side and a step costs one graph launch.  mixed != 0 captures the
+ * precision form (numa_hevi_step_mixed) instead of the FP64 step.
+ * tune != 0 runs the autotuner first: for every domain it times the
+ * right-hand side for each vertical chunk (elements per workgroup in the z
+ * march: nez, nez/2, ..., 1) on the domain's state (read only) and keeps
+ * the fastest for that context.  States and dts are fixed at creation (the
+ * graph holds them); the contexts must not be destroyed or refactored while
+ * the ensemble lives.  hip_stream: the stream the graph is launched on
+ * (NULL: the ensemble creates one).  Creation synchronises the contexts'
+ * streams.  Errors: NUMA_E_ARG (null or repeated context or state, n outside
+ * 1..1024), NUMA_E_NOT_FACTORED, NUMA_E_DT_MISMATCH, NUMA_E_NOMEM,
+ * NUMA_E_HIP; message in numa_ensemble_last_error(NULL).
+ */
+typedef struct numa_ensemble numa_ensemble;
+int numa_ensemble_create(numa_ctx *const *ctxs, double *const *states, const double *dts, int32_t n,
+                         int32_t mixed, int32_t tune, void *hip_stream, numa_ensemble **out);
+/* nsteps steps of every domain (nsteps graph launches).  Asynchronous. */
+int numa_ensemble_step(numa_ensemble *e, int32_t nsteps);
+/* Synchronise, then numa_check every context (NUMA_E_NONFINITE if any step
+ * produced NaN/Inf). */
+int numa_ensemble_sync(numa_ensemble *e);
+/* The vertical chunk each domain's right-hand side uses (zchunk[n]). */
+int numa_ensemble_zchunks(const numa_ensemble *e, int32_t *zchunk);
+/* Synchronise and free the graph, streams and events (NULL-safe). */
+int numa_ensemble_destroy(numa_ensemble *e);
+/* Last error of e (of the last failed creation on this thread if e is NULL). */
+const char *numa_ensemble_last_error(const numa_ensemble *e);
+
+/*
  * rhs_out = R(state): the explicit right-hand side of Set2NC in perturbation
  * form (Sec. 3.1) with the continuity equation in divergence form,
  * element-local strong-form LGL derivatives (Alg. 2) and DSS (Sec. 5.3);

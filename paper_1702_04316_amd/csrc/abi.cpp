@@ -53,6 +53,34 @@ int64_t step_bytes_model(const numa_ctx *c)
 
 }  // namespace
 
+namespace numa {
+
+// The checks shared by the step entry points; NUMA_OK if the step may run.
+int step_preconditions(numa_ctx *c, double dt, const char *who)
+{
+    if (!c->factored) return fail(c, NUMA_E_NOT_FACTORED, std::string(who) + ": call numa_factor_columns first");
+    if (std::memcmp(&dt, &c->dt_factored, sizeof(double)) != 0)
+        return fail(c, NUMA_E_DT_MISMATCH, std::string(who) + ": dt differs from the factored dt");
+    return NUMA_OK;
+}
+
+// The precision form's FP32 stage buffers, allocated on first use.
+int ensure_mixed_buffers(numa_ctx *c, const char *who)
+{
+    if (c->work_mix) return NUMA_OK;
+    hipError_t e = hipMalloc(&c->work_mix, size_t(80) * size_t(c->np));  // bytes per node
+    if (e != hipSuccess) {
+        c->work_mix = nullptr;
+        return hip_fail(c, e, (std::string(who) + ": hipMalloc(FP32 stage buffers)").c_str());
+    }
+    return NUMA_OK;
+}
+
+}  // namespace numa
+
+using numa::ensure_mixed_buffers;
+using numa::step_preconditions;
+
 extern "C" {
 
 int numa_setup(const numa_grid *g, int32_t order, const numa_background *bg, void *hip_stream, numa_ctx **out)
@@ -210,27 +238,6 @@ int numa_factor_columns(numa_ctx *c, double dt)
 }
 
 namespace {
-
-// The checks shared by the step entry points; NUMA_OK if the step may run.
-int step_preconditions(numa_ctx *c, double dt, const char *who)
-{
-    if (!c->factored) return fail(c, NUMA_E_NOT_FACTORED, std::string(who) + ": call numa_factor_columns first");
-    if (std::memcmp(&dt, &c->dt_factored, sizeof(double)) != 0)
-        return fail(c, NUMA_E_DT_MISMATCH, std::string(who) + ": dt differs from the factored dt");
-    return NUMA_OK;
-}
-
-// The precision form's FP32 stage buffers, allocated on first use.
-int ensure_mixed_buffers(numa_ctx *c, const char *who)
-{
-    if (c->work_mix) return NUMA_OK;
-    hipError_t e = hipMalloc(&c->work_mix, size_t(80) * size_t(c->np));  // bytes per node
-    if (e != hipSuccess) {
-        c->work_mix = nullptr;
-        return hip_fail(c, e, (std::string(who) + ": hipMalloc(FP32 stage buffers)").c_str());
-    }
-    return NUMA_OK;
-}
 
 using StepFn = hipError_t (*)(numa_ctx *, double *, double, hipEvent_t *);
 

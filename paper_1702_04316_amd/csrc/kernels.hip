@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
+#include <vector>
 
 #include "numa_internal.h"
 
@@ -908,6 +909,34 @@ int rhs_zchunk_auto(const numa_ctx *c)
     return zc;
 }
 
+// Opt the kernel into lds bytes of dynamic LDS (needed above 64 KB); done
+// once per size, before the first launch (and before any stream capture).
+template <int N, int EPI, bool HASB, bool MIX>
+hipError_t rhs_prepare(size_t lds)
+{
+    static size_t attr_set = 0;
+    if (attr_set < lds) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rhs<N, EPI, HASB, MIX>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+        attr_set = lds;
+    }
+    return hipSuccess;
+}
+
+template <int N, class SH>
+hipError_t solve_prepare(size_t shm)
+{
+    static size_t attr_set = 0;  // tall columns need LDS above 64 KB
+    if (shm > 65536 && attr_set < shm) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_colsolve<N, SH>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
+        if (e != hipSuccess) return e;
+        attr_set = shm;
+    }
+    return hipSuccess;
+}
+
 template <int N, int EPI, bool HASB, bool MIX = false>
 hipError_t rhs_launch(numa_ctx *c, RhsParams p)
 {
@@ -928,13 +957,8 @@ hipError_t rhs_launch(numa_ctx *c, RhsParams p)
     p.nty = int((c->ny + G::TY - 1) / G::TY);
     p.flag = c->flag;
     const size_t lds = rhs_lds_bytes<N, MIX>(p.zchunk, p.nez);
-    static size_t attr_set = 0;  // LDS above 64 KB must be opted into
-    if (attr_set < lds) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rhs<N, EPI, HASB, MIX>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-        if (e != hipSuccess) return e;
-        attr_set = lds;
-    }
+    hipError_t e = rhs_prepare<N, EPI, HASB, MIX>(lds);
+    if (e != hipSuccess) return e;
     dim3 grid(unsigned(p.ntx * p.nty * p.nchunk));
     hipLaunchKernelGGL((k_rhs<N, EPI, HASB, MIX>), grid, dim3(G::NT), lds, c->stream, p);
     return hipGetLastError();
@@ -951,13 +975,8 @@ hipError_t solve_launch(numa_ctx *c, SolveParams p)
     p.nz = int(c->nz);
     p.ncol = c->ncol;
     const size_t shm = SolveGeom<N, SH>::lds_bytes(int(c->nz));
-    static size_t attr_set = 0;  // tall columns need LDS above 64 KB
-    if (shm > 65536 && attr_set < shm) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_colsolve<N, SH>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
-        if (e != hipSuccess) return e;
-        attr_set = shm;
-    }
+    hipError_t e = solve_prepare<N, SH>(shm);
+    if (e != hipSuccess) return e;
     dim3 grid(unsigned((c->ncol + 63) / 64));
     hipLaunchKernelGGL((k_colsolve<N, SH>), grid, dim3(64), shm, c->stream, p);
     return hipGetLastError();
@@ -1281,6 +1300,74 @@ hipError_t launch_hevi_step_mixed(numa_ctx *c, double *q, double dt, hipEvent_t 
         if (e != hipSuccess || (e = mark(5)) != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// Set the LDS attributes of every kernel one step of this context launches,
+// so that a step can be captured into a graph (no first-use set-up inside).
+hipError_t prepare_step(numa_ctx *c, bool mixed)
+{
+    return dispatch(c->N, [&](auto n) -> hipError_t {
+        constexpr int NN = decltype(n)::value;
+        const int zc = c->rhs_zchunk > 0 ? c->rhs_zchunk : rhs_zchunk_auto<NN>(c);
+        const int nez = c->nez, nz = int(c->nz);
+        hipError_t e = hipSuccess;
+        if (!mixed) {
+            const size_t lds = rhs_lds_bytes<NN, false>(zc, nez);
+            if (e == hipSuccess) e = rhs_prepare<NN, EPI_R, false, false>(lds);
+            if (e == hipSuccess) e = rhs_prepare<NN, EPI_TWO, true, false>(lds);
+            if (e == hipSuccess) e = rhs_prepare<NN, EPI_FINAL, false, false>(lds);
+            if (e == hipSuccess) e = solve_prepare<NN, ShapeStage2>(SolveGeom<NN, ShapeStage2>::lds_bytes(nz));
+            if (e == hipSuccess) e = solve_prepare<NN, ShapeStage3>(SolveGeom<NN, ShapeStage3>::lds_bytes(nz));
+        } else {
+            const size_t lds = rhs_lds_bytes<NN, true>(zc, nez);
+            if (e == hipSuccess) e = rhs_prepare<NN, EPI_R, false, true>(lds);
+            if (e == hipSuccess) e = rhs_prepare<NN, EPI_TWO, true, true>(lds);
+            if (e == hipSuccess) e = rhs_prepare<NN, EPI_FINAL, false, true>(lds);
+            if (e == hipSuccess) e = solve_prepare<NN, ShapeStage2Mix>(SolveGeom<NN, ShapeStage2Mix>::lds_bytes(nz));
+            if (e == hipSuccess) e = solve_prepare<NN, ShapeStage3Mix>(SolveGeom<NN, ShapeStage3Mix>::lds_bytes(nz));
+        }
+        return e;
+    });
+}
+
+// Autotuner of the right-hand side's vertical chunk (elements per workgroup,
+// i.e. the workgroup's height in the z march): times the plain right-hand
+// side of state (written to the context's stage buffer R1; state is only
+// read) for chunks nez, nez/2, nez/3, ... 1 and keeps the fastest in
+// c->rhs_zchunk.  Synchronises the context's stream.
+hipError_t autotune_rhs_zchunk(numa_ctx *c, const double *state, int reps, int *chosen)
+{
+    std::vector<int> cand;
+    for (int d = 1; d <= c->nez; ++d) {
+        const int zc = (c->nez + d - 1) / d;
+        if (cand.empty() || cand.back() != zc) cand.push_back(zc);
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    const int keep = c->rhs_zchunk;
+    float best = 0.f;
+    int best_zc = keep;
+    double *R = stage_buffers(c).R1;
+    for (size_t i = 0; i < cand.size() && e == hipSuccess; ++i) {
+        c->rhs_zchunk = cand[i];
+        e = launch_rhs_plain(c, state, R);  // warm-up (and LDS attribute)
+        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_rhs_plain(c, state, R);
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && (i == 0 || ms < best)) {
+            best = ms;
+            best_zc = cand[i];
+        }
+    }
+    c->rhs_zchunk = e == hipSuccess ? best_zc : keep;
+    if (chosen) *chosen = c->rhs_zchunk;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return e;
 }
 
 }  // namespace numa

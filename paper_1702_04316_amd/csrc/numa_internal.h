@@ -93,5 +93,10 @@ hipError_t launch_rhs_plain(numa_ctx *c, const double *q, double *R);
 hipError_t launch_solve_plain(numa_ctx *c, const double *y, double *x);
 hipError_t launch_hevi_step(numa_ctx *c, double *q, double dt, hipEvent_t *ev = nullptr);
 hipError_t launch_hevi_step_mixed(numa_ctx *c, double *q, double dt, hipEvent_t *ev = nullptr);
+hipError_t prepare_step(numa_ctx *c, bool mixed);
+hipError_t autotune_rhs_zchunk(numa_ctx *c, const double *state, int reps, int *chosen);
+// abi.cpp: NUMA_OK or the error code (message recorded in the context)
+int ensure_mixed_buffers(numa_ctx *c, const char *who);
+int step_preconditions(numa_ctx *c, double dt, const char *who);
 
 }  // namespace numa

@@ -78,6 +78,14 @@ def load():
     lib.numa_hevi_step.argtypes = [vp, vp, C.c_double, C.c_int32]
     lib.numa_profile_steps.argtypes = [vp, vp, C.c_double, C.c_int32, C.POINTER(C.c_double)]
     lib.numa_hevi_step_mixed.argtypes = [vp, vp, C.c_double, C.c_int32]
+    lib.numa_ensemble_create.argtypes = [C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_double), C.c_int32, C.c_int32,
+                                         C.c_int32, vp, C.POINTER(vp)]
+    lib.numa_ensemble_step.argtypes = [vp, C.c_int32]
+    lib.numa_ensemble_sync.argtypes = [vp]
+    lib.numa_ensemble_zchunks.argtypes = [vp, C.POINTER(C.c_int32)]
+    lib.numa_ensemble_destroy.argtypes = [vp]
+    lib.numa_ensemble_last_error.argtypes = [vp]
+    lib.numa_ensemble_last_error.restype = C.c_char_p
     lib.numa_profile_steps_mixed.argtypes = [vp, vp, C.c_double, C.c_int32, C.POINTER(C.c_double)]
     lib.numa_rhs.argtypes = [vp, vp, vp]
     lib.numa_solve_columns.argtypes = [vp, vp, vp]
@@ -92,7 +100,8 @@ def load():
     for name in ("numa_setup", "numa_state_shape", "numa_get_info", "numa_set_stream", "numa_factor_columns",
                  "numa_hevi_step", "numa_profile_steps", "numa_hevi_step_mixed", "numa_profile_steps_mixed",
                  "numa_rhs", "numa_solve_columns", "numa_imex3d_step", "numa_check", "numa_destroy",
-                 "numa_lgl_basis", "numa_line_operators"):
+                 "numa_lgl_basis", "numa_line_operators", "numa_ensemble_create", "numa_ensemble_step",
+                 "numa_ensemble_sync", "numa_ensemble_zchunks", "numa_ensemble_destroy"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -169,6 +178,79 @@ def profile_steps_mixed(ctx, state_ptr, dt, nsteps):
     ms = (C.c_double * 5)()
     _check(load().numa_profile_steps_mixed(ctx, C.c_void_p(state_ptr), float(dt), int(nsteps), ms), ctx)
     return [float(v) for v in ms]
+
+
+def ensemble_last_error(ens=None):
+    return (load().numa_ensemble_last_error(ens) or b"").decode()
+
+
+def _echeck(rc, ens=None):
+    if rc != NUMA_OK:
+        raise NumaError(rc, ensemble_last_error(ens))
+    return rc
+
+
+def ensemble_create(ctxs, state_ptrs, dts, mixed=False, tune=True, stream=None):
+    """numa_ensemble_create: one captured step over the n contexts."""
+    n = len(ctxs)
+    carr = (C.c_void_p * n)(*ctxs)
+    sarr = (C.c_void_p * n)(*state_ptrs)
+    darr = (C.c_double * n)(*[float(d) for d in dts])
+    out = C.c_void_p()
+    _echeck(load().numa_ensemble_create(carr, sarr, darr, n, 1 if mixed else 0, 1 if tune else 0,
+                                        C.c_void_p(stream) if stream else None, C.byref(out)))
+    return out.value
+
+
+def ensemble_step(ens, nsteps):
+    return _echeck(load().numa_ensemble_step(ens, int(nsteps)), ens)
+
+
+def ensemble_sync(ens):
+    return _echeck(load().numa_ensemble_sync(ens), ens)
+
+
+def ensemble_zchunks(ens, n):
+    z = (C.c_int32 * n)()
+    _echeck(load().numa_ensemble_zchunks(ens, z), ens)
+    return [int(v) for v in z]
+
+
+def ensemble_destroy(ens):
+    return load().numa_ensemble_destroy(ens)
+
+
+class Ensemble:
+    """Several contexts (each factored with its dt) and their device states
+    stepped together through one captured graph per step."""
+
+    def __init__(self, contexts, states, mixed=False, tune=True):
+        for c, st in zip(contexts, states):
+            c._check_state(st)
+        self.contexts = list(contexts)
+        self.states = list(states)  # keep the tensors alive
+        self.ens = ensemble_create([c.ctx for c in contexts], [st.data_ptr() for st in states],
+                                   [c.dt for c in contexts], mixed=mixed, tune=tune)
+
+    def step(self, nsteps=1):
+        ensemble_step(self.ens, nsteps)
+
+    def sync(self):
+        ensemble_sync(self.ens)
+
+    def zchunks(self):
+        return ensemble_zchunks(self.ens, len(self.contexts))
+
+    def close(self):
+        if getattr(self, "ens", None):
+            ensemble_destroy(self.ens)
+            self.ens = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def profile_steps(ctx, state_ptr, dt, nsteps):

@@ -93,6 +93,7 @@ class Workload:
     radius: Tuple[float, float]
     stretch: float = 1.0
     background: Background = field(default_factory=Background)
+    wind: Tuple[float, float] = (0.0, 0.0)  # uniform (u, v) of the initial state
 
 
 def sound_speed(bg=None):
@@ -182,7 +183,8 @@ def balanced_density(grid, theta_p, bg=None):
 
 
 def make_initial_state(wl: Workload):
-    """Seeded initial state (5, nz, ny, nx): theta' bumps, balanced rho', u = v = w = 0.
+    """Seeded initial state (5, nz, ny, nx): theta' bumps, balanced rho', the
+    workload's uniform wind (u, v), w = 0.
 
     Bump m: A_m exp(-((x-x_m)^2 + (y-y_m)^2)/(s r_m)^2 - (z-z_m)^2/r_m^2), summed
     over periodic images in x and y; centre drawn uniformly in the box, then
@@ -193,6 +195,8 @@ def make_initial_state(wl: Workload):
     q = np.zeros(g.shape)
     q[4] = _theta_bumps(g, bumps, wl.stretch)
     q[0] = balanced_density(g, q[4], wl.background)
+    q[1] = wl.wind[0]
+    q[2] = wl.wind[1]
     return q
 
 
@@ -306,3 +310,29 @@ def box_precision(size="small", reading="R1"):
     if size == "small":
         return Workload(f"box4x4x4_N7_{reading}", g, dt, 100, 1, 1, (0.5, 0.5), (250.0, 250.0), stretch=s)
     return Workload(f"box28x28x28_N7_{reading}", g, dt, 100, 3, 8, (0.1, 2.0), (50.0, 200.0), stretch=s)
+
+
+def ensemble_domains(seed=4, n=16):
+    """An ensemble of n domains drawn per seed: square horizontal grids of
+    16..64 elements per axis, 6..16 vertical elements, N in {3, 4, 5, 7},
+    1..8 theta' bumps (0.1..2 K, 0.5..2 km), a uniform wind of 0..20 m/s in
+    a random direction; the 20 x 20 x 10 km box of the 64x64x10 workload
+    with vertical Courant number 15 and, under R1, the horizontal extent
+    stretched so that the horizontal Courant number with c0 + |u| is 0.4."""
+    rng = np.random.default_rng(seed)
+    c0 = sound_speed()
+    out = []
+    for d in range(n):
+        ne = int(rng.integers(16, 65))
+        nez = int(rng.integers(6, 17))
+        N = int(rng.choice([3, 4, 5, 7]))
+        speed = float(rng.uniform(0.0, 20.0))
+        ang = float(rng.uniform(0.0, 2.0 * np.pi))
+        nb = int(rng.integers(1, 9))
+        lx, lz = 20000.0, 10000.0
+        s = _stretch(lx, ne, lz, nez) * (c0 + speed) / c0
+        g = Grid(lx * s, lx * s, lz, ne, ne, nez, N)
+        dt = dt_for_courant(g, C_VERT, "z")
+        out.append(Workload(f"ens{d}_{ne}x{ne}x{nez}_N{N}", g, dt, 50, 100 * seed + d, nb, (0.1, 2.0),
+                            (500.0, 2000.0), stretch=s, wind=(speed * np.cos(ang), speed * np.sin(ang))))
+    return out
