@@ -194,6 +194,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble measurement")
+    ap.add_argument("--no-precision", action="store_true", help="skip the precision-form measurement")
     ap.add_argument("--copy-probe", action="store_true", help="only time a plain 1 GiB device copy")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -276,7 +277,8 @@ def main():
         "kernels": per,
         "step_algorithmic_GBps": step_bytes * args.steps / t / 1e9,
     }
-    out["precision_form"] = precision_form(numa, torch, ctx, wl, args, t)
+    if not args.no_precision:
+        out["precision_form"] = precision_form(numa, torch, ctx, wl, args, t)
     if not args.no_ensemble:
         out["batched_ensemble"] = batched_ensemble(numa, torch)
     if not args.no_cpu_baseline:
