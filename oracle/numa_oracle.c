@@ -1,5 +1,6 @@
 /*
- * numa_oracle.c -- plain FP64 CPU oracle of the HEVI (1D-IMEX) ARK2 step.
+ * numa_oracle.c -- plain FP64 CPU oracle of the HEVI (1D-IMEX) ARK2 step, and
+ * of the 3D-IMEX step whose implicit systems are solved by GMRES.
  *
  * TEST INFRASTRUCTURE ONLY (see numa_oracle.h).  Written for reading, not for
  * speed: element-local loops, explicit gather/scatter direct stiffness
@@ -18,6 +19,7 @@
 #include "numa_oracle.h"
 
 #include <math.h>
+#include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -646,6 +648,382 @@ int orc_step(orc_ctx *c, double *q, double dt, int nsteps, int linear)
         if (rc) break;
         for (long I = 0; I < n5; ++I) q[I] += dt * (b[0] * Rs[0][I] + b[1] * Rs[1][I] + b[2] * Rs[2][I]);
     }
+    free(Y); free(Q);
+    for (int s = 0; s < 3; ++s) free(Rs[s]);
+    for (int s = 0; s < 2; ++s) free(Ls[s]);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 3D-IMEX (Sec. 2): the implicit part is the whole linear operator L of    */
+/* Sec. 3.1 instead of its vertical part L_V, and the implicit systems are  */
+/* solved iteratively (Sec. 5.5).                                           */
+/* ------------------------------------------------------------------------ */
+
+static double dot_n(const double *a, const double *b, long n)
+{
+    double s = 0.0;
+    for (long i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+}
+
+/* An operator on vectors of length n, and restarted right-preconditioned
+ * GMRES(m) for it: textbook Arnoldi with modified Gram-Schmidt, Givens
+ * rotations of the Hessenberg matrix, x0 = 0.  Inside a cycle the rotated
+ * right-hand side gives the residual norm; a cycle ends when that estimate
+ * reaches tol |b| or after m iterations, and the solve ends when the true
+ * residual |b - A x| reaches tol |b|.  *iters counts Arnoldi iterations. */
+typedef int (*orc_op_fn)(orc_ctx *c, const void *arg, const double *in, double *out);
+
+static int gmres(orc_ctx *c, long n, orc_op_fn A, const void *aarg, orc_op_fn M, const void *marg,
+                 const double *b, double *x, double tol, int m, int maxit, int *iters)
+{
+    int total = 0, rc = 0, converged = 0;
+    double *V = (double *)malloc(sizeof(double) * (size_t)(m + 1) * n);
+    double *w = (double *)malloc(sizeof(double) * n), *z = (double *)malloc(sizeof(double) * n);
+    double *H = (double *)calloc((size_t)(m + 1) * m, sizeof(double));
+    double *cs = (double *)malloc(sizeof(double) * m), *sn = (double *)malloc(sizeof(double) * m);
+    double *g = (double *)malloc(sizeof(double) * (m + 1)), *yv = (double *)malloc(sizeof(double) * m);
+    if (!V || !w || !z || !H || !cs || !sn || !g || !yv) rc = -5;
+    double bnorm = rc ? 0.0 : sqrt(dot_n(b, b, n));
+    if (!rc) memset(x, 0, sizeof(double) * n);
+    while (!rc) {
+        /* true residual r = b - A x */
+        rc = A(c, aarg, x, w);
+        if (rc) break;
+        for (long i = 0; i < n; ++i) w[i] = b[i] - w[i];
+        double beta = sqrt(dot_n(w, w, n));
+        if (beta <= tol * bnorm) { converged = 1; break; }
+        if (total >= maxit) break;
+        for (long i = 0; i < n; ++i) V[i] = w[i] / beta;
+        for (int i = 0; i <= m; ++i) g[i] = 0.0;
+        g[0] = beta;
+        int j = 0;
+        while (j < m && total < maxit) {
+            double *vj = V + (size_t)j * n, *vn = V + (size_t)(j + 1) * n;
+            if (M) { rc = M(c, marg, vj, z); if (rc) break; }
+            rc = A(c, aarg, M ? z : vj, w);
+            if (rc) break;
+            for (int i = 0; i <= j; ++i) {
+                double *vi = V + (size_t)i * n;
+                double h = dot_n(w, vi, n);
+                H[i * m + j] = h;
+                for (long l = 0; l < n; ++l) w[l] -= h * vi[l];
+            }
+            double hn = sqrt(dot_n(w, w, n));
+            H[(j + 1) * m + j] = hn;
+            for (long l = 0; l < n; ++l) vn[l] = hn > 0.0 ? w[l] / hn : 0.0;
+            for (int i = 0; i < j; ++i) {
+                double a = H[i * m + j], bb = H[(i + 1) * m + j];
+                H[i * m + j] = cs[i] * a + sn[i] * bb;
+                H[(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+            }
+            double a = H[j * m + j], bb = H[(j + 1) * m + j], r = hypot(a, bb);
+            cs[j] = r > 0.0 ? a / r : 1.0;
+            sn[j] = r > 0.0 ? bb / r : 0.0;
+            H[j * m + j] = r;
+            H[(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++total;
+            ++j;
+            if (fabs(g[j]) <= tol * bnorm) break;
+        }
+        if (rc) break;
+        /* x += M V y with H[0:j,0:j] y = g[0:j] */
+        for (int i = j - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int k = i + 1; k < j; ++k) t -= H[i * m + k] * yv[k];
+            yv[i] = t / H[i * m + i];
+        }
+        memset(w, 0, sizeof(double) * n);
+        for (int i = 0; i < j; ++i) {
+            double *vi = V + (size_t)i * n;
+            for (long l = 0; l < n; ++l) w[l] += yv[i] * vi[l];
+        }
+        if (M) { rc = M(c, marg, w, z); if (rc) break; }
+        const double *dx = M ? z : w;
+        for (long l = 0; l < n; ++l) x[l] += dx[l];
+    }
+    if (iters) *iters = total;
+    free(V); free(w); free(z); free(H); free(cs); free(sn); free(g); free(yv);
+    if (rc) return rc;
+    return converged ? 0 : -6;
+}
+
+/* Standard (unreduced) form: (I - lambda L) x = y on all five fields. */
+static int op_standard(orc_ctx *c, const void *arg, const double *v, double *w)
+{
+    double lambda = *(const double *)arg;
+    int rc = orc_lfull(c, v, w);
+    if (rc) return rc;
+    for (long i = 0; i < 5 * c->np; ++i) w[i] = v[i] - lambda * w[i];
+    return 0;
+}
+
+int orc_solve3d_standard(orc_ctx *c, const double *y, double *x, double lambda, double tol, int restart, int maxit,
+                         int *iters)
+{
+    if (!c || !y || !x || restart < 1 || maxit < 1 || !(tol > 0.0)) return -1;
+    return gmres(c, 5 * c->np, op_standard, &lambda, NULL, NULL, y, x, tol, restart, maxit, iters);
+}
+
+/* Schur-complement form (the Set2NC analogue of the pressure system of
+ * Algs. 4-5).  With theta' = y_theta fixed (L has no theta' tendency for a
+ * constant theta0) and the linear pressure P = G0 rho' + H0 theta', the
+ * velocity rows of (I - lambda L) x = y give
+ *     u = U_a - U_p(P),  U_a = (y_u, y_v, B (y_w + lambda g H0 y_theta/(G0 rho0))),
+ *     U_p(P) = lambda (Dx P/rho0, Dy P/rho0, B (Dz P/rho0 + g P/(G0 rho0))),
+ * B zeroing w on the bottom and top.  U_p is -lambda times the velocity
+ * tendencies of L applied to the state (rho' = P/G0, u = 0, theta' = 0).
+ * The continuity row times G0, plus H0 y_theta, then reads
+ *     S P = P - lambda G0 div(rho0 U_p(P)) = G0 y_rho + H0 y_theta - lambda G0 div(rho0 U_a),
+ * where -div(rho0 U) is the rho' tendency of L applied to (0, U, 0). */
+typedef struct {
+    double lambda;
+    double *s, *l; /* 5-field scratch states */
+} schur_arg;
+
+/* U_p(P) into the velocity fields of l (rho', theta' of l are cleared) */
+static int schur_up(orc_ctx *c, const schur_arg *a, const double *P, double *out_u)
+{
+    long np = c->np, plane = (long)c->nx * c->ny;
+    memset(a->s, 0, sizeof(double) * 5 * np);
+    for (long I = 0; I < np; ++I) a->s[I] = P[I] / c->G0[I / plane];
+    int rc = orc_lfull(c, a->s, a->l);
+    if (rc) return rc;
+    for (long I = 0; I < 3 * np; ++I) out_u[I] = -a->lambda * a->l[np + I];
+    return 0;
+}
+
+/* -div(rho0 U) for a velocity field U (3 fields) */
+static int schur_div(orc_ctx *c, const schur_arg *a, const double *U, double *out)
+{
+    long np = c->np;
+    memset(a->s, 0, sizeof(double) * 5 * np);
+    memcpy(a->s + np, U, sizeof(double) * 3 * np);
+    int rc = orc_lfull(c, a->s, a->l);
+    if (rc) return rc;
+    memcpy(out, a->l, sizeof(double) * np);
+    return 0;
+}
+
+static int op_schur(orc_ctx *c, const void *arg, const double *P, double *out)
+{
+    const schur_arg *a = (const schur_arg *)arg;
+    long np = c->np, plane = (long)c->nx * c->ny;
+    double *U = (double *)malloc(sizeof(double) * 3 * np);
+    if (!U) return -5;
+    int rc = schur_up(c, a, P, U);
+    if (!rc) rc = schur_div(c, a, U, out); /* out = -div(rho0 U_p) */
+    if (!rc)
+        for (long I = 0; I < np; ++I) out[I] = P[I] + a->lambda * c->G0[I / plane] * out[I];
+    free(U);
+    return rc;
+}
+
+/* U_a and the Schur right-hand side b */
+static int schur_rhs(orc_ctx *c, const schur_arg *a, const double *y, double *Ua, double *b)
+{
+    long np = c->np, plane = (long)c->nx * c->ny;
+    for (long I = 0; I < np; ++I) {
+        int k = (int)(I / plane);
+        Ua[I] = y[np + I];
+        Ua[np + I] = y[2 * np + I];
+        Ua[2 * np + I] = (k == 0 || k == c->nz - 1) ? 0.0
+                         : y[3 * np + I] + a->lambda * c->g * c->H0[k] * y[4 * np + I] / (c->G0[k] * c->rho0[k]);
+    }
+    int rc = schur_div(c, a, Ua, b);
+    if (rc) return rc;
+    for (long I = 0; I < np; ++I) {
+        int k = (int)(I / plane);
+        b[I] = c->G0[k] * y[I] + c->H0[k] * y[4 * np + I] + a->lambda * c->G0[k] * b[I];
+    }
+    return 0;
+}
+
+int orc_schur_apply(orc_ctx *c, const double *P, double *out, double lambda)
+{
+    if (!c || !P || !out) return -1;
+    schur_arg a = {lambda, (double *)malloc(sizeof(double) * 5 * c->np), (double *)malloc(sizeof(double) * 5 * c->np)};
+    int rc = (a.s && a.l) ? op_schur(c, &a, P, out) : -5;
+    free(a.s); free(a.l);
+    return rc;
+}
+
+int orc_schur_rhs(orc_ctx *c, const double *y, double *b, double lambda)
+{
+    if (!c || !y || !b) return -1;
+    long np = c->np;
+    schur_arg a = {lambda, (double *)malloc(sizeof(double) * 5 * np), (double *)malloc(sizeof(double) * 5 * np)};
+    double *Ua = (double *)malloc(sizeof(double) * 3 * np);
+    int rc = (a.s && a.l && Ua) ? schur_rhs(c, &a, y, Ua, b) : -5;
+    free(a.s); free(a.l); free(Ua);
+    return rc;
+}
+
+/* PBNO preconditioner (Sec. 5.5): a polynomial s(S) that approximates S^-1
+ * on the eigenvalue interval [lmin, lmax].  Its coefficients are those of
+ * Chebyshev acceleration (the polynomial of degree p for which 1 - x s(x) is
+ * the scaled and shifted Chebyshev polynomial T_{p+1}, minimax on the
+ * interval), applied by the three-term recurrence of the Chebyshev
+ * iteration for S z = r from z = 0: p applications of S.  For p = 0 it is
+ * the scaling 2/(lmin + lmax) alone. */
+typedef struct {
+    schur_arg *s;
+    int p;
+    double lmin, lmax;
+} pbno_arg;
+
+static int op_pbno(orc_ctx *c, const void *arg, const double *r, double *z)
+{
+    const pbno_arg *a = (const pbno_arg *)arg;
+    long n = c->np;
+    double theta = 0.5 * (a->lmax + a->lmin), delta = 0.5 * (a->lmax - a->lmin);
+    double sigma = theta / delta, rho = 1.0 / sigma;
+    double *res = (double *)malloc(sizeof(double) * n), *d = (double *)malloc(sizeof(double) * n);
+    double *Sd = (double *)malloc(sizeof(double) * n);
+    int rc = (res && d && Sd) ? 0 : -5;
+    if (!rc) {
+        for (long i = 0; i < n; ++i) {
+            res[i] = r[i];
+            d[i] = r[i] / theta;
+            z[i] = 0.0;
+        }
+        for (int k = 0; k <= a->p; ++k) {
+            for (long i = 0; i < n; ++i) z[i] += d[i];
+            if (k == a->p) break;
+            rc = op_schur(c, a->s, d, Sd);
+            if (rc) break;
+            double rho_n = 1.0 / (2.0 * sigma - rho);
+            for (long i = 0; i < n; ++i) {
+                res[i] -= Sd[i];
+                d[i] = rho_n * rho * d[i] + (2.0 * rho_n / delta) * res[i];
+            }
+            rho = rho_n;
+        }
+    }
+    free(res); free(d); free(Sd);
+    return rc;
+}
+
+int orc_pbno_apply(orc_ctx *c, const double *r, double *z, double lambda, int order, double lmin, double lmax)
+{
+    if (!c || !r || !z || order < 0 || !(lmax > lmin) || !(lmin > 0.0)) return -1;
+    schur_arg s = {lambda, (double *)malloc(sizeof(double) * 5 * c->np), (double *)malloc(sizeof(double) * 5 * c->np)};
+    pbno_arg a = {&s, order, lmin, lmax};
+    int rc = (s.s && s.l) ? op_pbno(c, &a, r, z) : -5;
+    free(s.s); free(s.l);
+    return rc;
+}
+
+/* Eigenvalue interval of S for the preconditioner: lmin = 1 (S is the
+ * identity plus lambda^2 times an operator with a non-negative spectrum up
+ * to the small buoyancy coupling), lmax = 1.1 |S^k v| / |S^(k-1) v| after k
+ * power-method steps from v_I = frac(I phi) - 1/2, phi the golden-ratio
+ * fraction taken as 2654435769 / 2^32 (integer arithmetic, so both
+ * implementations start from the same vector). */
+int orc_schur_bounds(orc_ctx *c, double lambda, int k, double *out)
+{
+    if (!c || !out || k < 1) return -1;
+    long n = c->np;
+    double *v = (double *)malloc(sizeof(double) * n), *w = (double *)malloc(sizeof(double) * n);
+    schur_arg a = {lambda, (double *)malloc(sizeof(double) * 5 * n), (double *)malloc(sizeof(double) * 5 * n)};
+    int rc = (v && w && a.s && a.l) ? 0 : -5;
+    double est = 0.0;
+    if (!rc) {
+        for (long i = 0; i < n; ++i) {
+            uint32_t h = (uint32_t)((uint64_t)i * 2654435769u);
+            v[i] = (double)h / 4294967296.0 - 0.5;
+        }
+        double nv = sqrt(dot_n(v, v, n));
+        for (long i = 0; i < n; ++i) v[i] /= nv;
+        for (int it = 0; it < k && !rc; ++it) {
+            rc = op_schur(c, &a, v, w);
+            if (rc) break;
+            est = sqrt(dot_n(w, w, n));
+            for (long i = 0; i < n; ++i) v[i] = w[i] / est;
+        }
+    }
+    out[0] = 1.0;
+    out[1] = 1.1 * est;
+    free(v); free(w); free(a.s); free(a.l);
+    return rc;
+}
+
+/* x = (I - lambda L)^-1 y through the Schur form: b, GMRES on S P = b with
+ * PBNO of the given order (order < 0: none) on the interval bounds, then
+ * u = U_a - U_p(P), rho' = y_rho - lambda div(rho0 u), theta' = y_theta. */
+int orc_solve3d(orc_ctx *c, const double *y, double *x, double lambda, double tol, int restart, int maxit,
+                int order, const double *bounds, int *iters)
+{
+    if (!c || !y || !x || restart < 1 || maxit < 1 || !(tol > 0.0)) return -1;
+    if (order >= 0 && (!bounds || !(bounds[1] > bounds[0]) || !(bounds[0] > 0.0))) return -1;
+    long np = c->np;
+    schur_arg a = {lambda, (double *)malloc(sizeof(double) * 5 * np), (double *)malloc(sizeof(double) * 5 * np)};
+    double *Ua = (double *)malloc(sizeof(double) * 3 * np), *Up = (double *)malloc(sizeof(double) * 3 * np);
+    double *b = (double *)malloc(sizeof(double) * np), *P = (double *)malloc(sizeof(double) * np);
+    int rc = (a.s && a.l && Ua && Up && b && P) ? 0 : -5, it = 0, grc = 0;
+    pbno_arg pa = {&a, order, bounds ? bounds[0] : 0.0, bounds ? bounds[1] : 0.0};
+    if (!rc) rc = schur_rhs(c, &a, y, Ua, b);
+    if (!rc) {
+        grc = gmres(c, np, op_schur, &a, order >= 0 ? op_pbno : NULL, &pa, b, P, tol, restart, maxit, &it);
+        if (grc && grc != -6) rc = grc;
+    }
+    if (!rc) rc = schur_up(c, &a, P, Up);
+    if (!rc) {
+        for (long I = 0; I < 3 * np; ++I) x[np + I] = Ua[I] - Up[I];
+        rc = schur_div(c, &a, x + np, x); /* x_rho = -div(rho0 u) */
+    }
+    if (!rc)
+        for (long I = 0; I < np; ++I) {
+            x[I] = y[I] + lambda * x[I];
+            x[4 * np + I] = y[4 * np + I];
+        }
+    if (iters) *iters = it;
+    free(a.s); free(a.l); free(Ua); free(Up); free(b); free(P);
+    return rc ? rc : grc;
+}
+
+/* nsteps 3D-IMEX ARK2 steps: orc_step with L in place of L_V and the Schur
+ * GMRES solve (PBNO order and interval as orc_solve3d; restart 30); linear
+ * != 0: R := L.  *iters: GMRES iterations of all solves. */
+int orc_step3d(orc_ctx *c, double *q, double dt, int nsteps, int linear, double tol, int order,
+               const double *bounds, int *iters)
+{
+    if (!c || !q || nsteps < 0 || !(dt > 0.0)) return -1;
+    double a[9], at[9], b[3];
+    orc_ark2_tableau(a, at, b);
+    double lam = at[1 * 3 + 1] * dt;
+    long n5 = 5 * c->np;
+    double *Rs[3], *Ls[2], *Y = (double *)malloc(sizeof(double) * n5);
+    double *Q = (double *)malloc(sizeof(double) * n5);
+    for (int s = 0; s < 3; ++s) Rs[s] = (double *)malloc(sizeof(double) * n5);
+    for (int s = 0; s < 2; ++s) Ls[s] = (double *)malloc(sizeof(double) * n5);
+    int rc = (Y && Q && Rs[0] && Rs[1] && Rs[2] && Ls[0] && Ls[1]) ? 0 : -5, total = 0;
+    for (int n = 0; n < nsteps && !rc; ++n) {
+        for (int i = 0; i < 3 && !rc; ++i) {
+            if (i == 0) {
+                memcpy(Q, q, sizeof(double) * n5);
+            } else {
+                for (long I = 0; I < n5; ++I) {
+                    double y = q[I];
+                    for (int j = 0; j < i; ++j)
+                        y += dt * (a[i * 3 + j] * Rs[j][I] + (at[i * 3 + j] - a[i * 3 + j]) * Ls[j][I]);
+                    Y[I] = y;
+                }
+                int it = 0;
+                rc = orc_solve3d(c, Y, Q, lam, tol, 30, 100000, order, bounds, &it);
+                total += it;
+                if (rc) break;
+            }
+            rc = linear ? orc_lfull(c, Q, Rs[i]) : orc_rhs(c, Q, Rs[i]);
+            if (!rc && i < 2) rc = orc_lfull(c, Q, Ls[i]);
+        }
+        if (rc) break;
+        for (long I = 0; I < n5; ++I) q[I] += dt * (b[0] * Rs[0][I] + b[1] * Rs[1][I] + b[2] * Rs[2][I]);
+    }
+    if (iters) *iters = total;
     free(Y); free(Q);
     for (int s = 0; s < 3; ++s) free(Rs[s]);
     for (int s = 0; s < 2; ++s) free(Ls[s]);

@@ -22,7 +22,7 @@
  *
  * Return codes: 0 ok, -1 bad argument, -2 not factored / lambda mismatch,
  * -3 precondition violated (w != 0 on a wall), -4 singular column matrix,
- * -5 out of memory.
+ * -5 out of memory, -6 iterative solve did not converge.
  */
 #ifndef NUMA_ORACLE_H
 #define NUMA_ORACLE_H
@@ -77,6 +77,29 @@ int orc_column_matrix(orc_ctx *c, double lambda, int i, int j, double *A);
 int orc_step(orc_ctx *c, double *q, double dt, int nsteps, int linear);
 /* ARK2 tableau as used by orc_step: a[3][3], at[3][3], b[3] (Table 1). */
 void orc_ark2_tableau(double *a, double *at, double *b);
+/* 3D-IMEX (Sec. 2, Sec. 5.5).  Schur-complement pressure operator
+ * S P = P - lambda G0 div(rho0 U_p(P)) and its right-hand side b from a
+ * 5-field y (Set2NC analogue of Algs. 4-5). */
+int orc_schur_apply(orc_ctx *c, const double *P, double *out, double lambda);
+int orc_schur_rhs(orc_ctx *c, const double *y, double *b, double lambda);
+/* PBNO preconditioner z = s(S) r of the given order (Chebyshev polynomial on
+ * [lmin, lmax]) and the interval estimate out = {1, 1.1 x k-step power method}. */
+int orc_pbno_apply(orc_ctx *c, const double *r, double *z, double lambda, int order, double lmin, double lmax);
+int orc_schur_bounds(orc_ctx *c, double lambda, int k, double *out);
+/* x = (I - lambda L)^{-1} y: Schur form, restarted GMRES(restart) from P = 0
+ * until |b - S P| <= tol |b|, PBNO of the given order on bounds[0..1]
+ * (order < 0: unpreconditioned, bounds unused).  *iters: Arnoldi iterations.
+ * Returns -6 (x still written) if maxit iterations did not reach tol. */
+int orc_solve3d(orc_ctx *c, const double *y, double *x, double lambda, double tol, int restart, int maxit,
+                int order, const double *bounds, int *iters);
+/* The same system in its unreduced 5-field form, unpreconditioned GMRES. */
+int orc_solve3d_standard(orc_ctx *c, const double *y, double *x, double lambda, double tol, int restart, int maxit,
+                         int *iters);
+/* nsteps 3D-IMEX ARK2 steps (orc_step with L in place of L_V and the Schur
+ * GMRES solve to tol; linear as in orc_step).  *iters: GMRES iterations in
+ * total. */
+int orc_step3d(orc_ctx *c, double *q, double dt, int nsteps, int linear, double tol, int order,
+               const double *bounds, int *iters);
 
 #ifdef __cplusplus
 }

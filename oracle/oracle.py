@@ -53,6 +53,19 @@ def _load():
     lib.orc_step.argtypes = [C.c_void_p, _dp, C.c_double, C.c_int, C.c_int]
     lib.orc_step.restype = C.c_int
     lib.orc_ark2_tableau.argtypes = [_dp, _dp, _dp]
+    lib.orc_schur_apply.argtypes = [C.c_void_p, _dp, _dp, C.c_double]
+    lib.orc_schur_rhs.argtypes = [C.c_void_p, _dp, _dp, C.c_double]
+    lib.orc_pbno_apply.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_int, C.c_double, C.c_double]
+    lib.orc_schur_bounds.argtypes = [C.c_void_p, C.c_double, C.c_int, _dp]
+    lib.orc_solve3d.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, _dp,
+                                C.POINTER(C.c_int)]
+    lib.orc_solve3d_standard.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_double, C.c_int, C.c_int,
+                                         C.POINTER(C.c_int)]
+    lib.orc_step3d.argtypes = [C.c_void_p, _dp, C.c_double, C.c_int, C.c_int, C.c_double, C.c_int, _dp,
+                               C.POINTER(C.c_int)]
+    for name in ("orc_schur_apply", "orc_schur_rhs", "orc_pbno_apply", "orc_schur_bounds", "orc_solve3d",
+                 "orc_solve3d_standard", "orc_step3d"):
+        getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
 
@@ -183,3 +196,61 @@ class Oracle:
         assert q.shape == self.shape
         _check(_lib.orc_step(self.h, q.reshape(-1), float(dt), int(nsteps), 1 if linear else 0), "orc_step")
         return q
+
+    # --- 3D-IMEX (Schur form, GMRES, PBNO) ---------------------------------
+    def schur_apply(self, P, lam):
+        P = np.ascontiguousarray(P, dtype=np.float64)
+        assert P.shape == self.shape[1:]
+        out = np.zeros(self.shape[1:])
+        _check(_lib.orc_schur_apply(self.h, P.reshape(-1), out.reshape(-1), float(lam)), "orc_schur_apply")
+        return out
+
+    def schur_rhs(self, y, lam):
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        assert y.shape == self.shape
+        out = np.zeros(self.shape[1:])
+        _check(_lib.orc_schur_rhs(self.h, y.reshape(-1), out.reshape(-1), float(lam)), "orc_schur_rhs")
+        return out
+
+    def pbno_apply(self, r, lam, order, bounds):
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        out = np.zeros(self.shape[1:])
+        _check(_lib.orc_pbno_apply(self.h, r.reshape(-1), out.reshape(-1), float(lam), int(order),
+                                   float(bounds[0]), float(bounds[1])), "orc_pbno_apply")
+        return out
+
+    def schur_bounds(self, lam, k=30):
+        out = np.zeros(2)
+        _check(_lib.orc_schur_bounds(self.h, float(lam), int(k), out), "orc_schur_bounds")
+        return out
+
+    def solve3d(self, y, lam, tol=1e-12, restart=30, maxit=100000, order=-1, bounds=None, allow_unconverged=False):
+        """(I - lam L)^{-1} y through the Schur form; returns (x, iterations)."""
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        assert y.shape == self.shape
+        x = np.zeros(self.shape)
+        it = C.c_int(0)
+        bd = np.ascontiguousarray(bounds if bounds is not None else (1.0, 2.0), dtype=np.float64)
+        rc = _lib.orc_solve3d(self.h, y.reshape(-1), x.reshape(-1), float(lam), float(tol), int(restart), int(maxit),
+                              int(order), bd, C.byref(it))
+        if not (allow_unconverged and rc == -6):
+            _check(rc, "orc_solve3d")
+        return x, it.value
+
+    def solve3d_standard(self, y, lam, tol=1e-12, restart=40, maxit=100000):
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        x = np.zeros(self.shape)
+        it = C.c_int(0)
+        _check(_lib.orc_solve3d_standard(self.h, y.reshape(-1), x.reshape(-1), float(lam), float(tol), int(restart),
+                                         int(maxit), C.byref(it)), "orc_solve3d_standard")
+        return x, it.value
+
+    def step3d(self, q, dt, nsteps=1, tol=1e-12, linear=False, order=-1, bounds=None):
+        """nsteps 3D-IMEX ARK2 steps; returns (state, GMRES iterations)."""
+        q = np.array(q, dtype=np.float64, order="C", copy=True)
+        assert q.shape == self.shape
+        it = C.c_int(0)
+        bd = np.ascontiguousarray(bounds if bounds is not None else (1.0, 2.0), dtype=np.float64)
+        _check(_lib.orc_step3d(self.h, q.reshape(-1), float(dt), int(nsteps), 1 if linear else 0, float(tol),
+                               int(order), bd, C.byref(it)), "orc_step3d")
+        return q, it.value

@@ -526,3 +526,183 @@ def test_pressure_perturbation_is_eos_minus_background(oracle_mod):
     lit = W.P00 * (rho * W.RGAS * theta / W.P00) ** gamma - bg["P0"][:, None, None]
     assert np.max(np.abs(P - lit)) < 8 * np.spacing(W.P00)
     assert np.all(o.pressure_perturbation(np.zeros(g.shape)) == 0.0)
+
+
+# ---------------------------------------------------------------------------
+# 3D-IMEX: implicit full linear operator, Schur form, GMRES, PBNO (Sec. 2,
+# Sec. 5.5, Algs. 4-5 and 8)
+# ---------------------------------------------------------------------------
+
+def _dense_operator(o, shape):
+    n = int(np.prod(shape))
+    A = np.zeros((n, n))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        A[:, j] = o.lfull(e.reshape(shape)).reshape(-1)
+    return A
+
+
+def _dense_schur(o, lam):
+    shp = o.shape[1:]
+    n = int(np.prod(shp))
+    S = np.zeros((n, n))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        S[:, j] = o.schur_apply(e.reshape(shp), lam).reshape(-1)
+    return S
+
+
+_G3 = W.Grid(3000.0, 2500.0, 2000.0, 2, 2, 2, 3)
+
+
+def test_solve3d_matches_dense_lapack(oracle_mod):
+    """The Schur-form GMRES solve and the unreduced 5-field GMRES solve of
+    (I - lambda L) x = y both agree with LAPACK on the matrix probed column by
+    column from L (pinned separately as the linearisation of R)."""
+    g = _G3
+    o = _oracle(oracle_mod, g)
+    dt = W.dt_for_courant(g, 15.0, "x")
+    lam = (1.0 - 1.0 / math.sqrt(2.0)) * dt
+    A = _dense_operator(o, g.shape)
+    y = W.make_random_state(g, 3, smooth=False)
+    xd = scipy.linalg.solve(np.eye(A.shape[0]) - lam * A, y.reshape(-1)).reshape(g.shape)
+    x, it = o.solve3d(y, lam, tol=1e-14)
+    xs, its = o.solve3d_standard(y, lam, tol=1e-13)
+    assert 1 < it < its
+    for f in range(5):
+        scale = np.max(np.abs(xd[f]))
+        assert np.max(np.abs(x[f] - xd[f])) < 1e-11 * scale, f
+        assert np.max(np.abs(xs[f] - xd[f])) < 1e-11 * scale, f
+    assert np.array_equal(x[4], y[4])  # no theta' tendency in L (theta0 constant)
+
+
+def test_schur_operator_is_the_elimination(oracle_mod):
+    """S P = b is what remains of (I - lambda L) x = y after eliminating the
+    velocities: with P = G0 x_rho + H0 x_theta of the LAPACK solution,
+    S P = b holds to rounding."""
+    g = _G3
+    o = _oracle(oracle_mod, g)
+    lam = (1.0 - 1.0 / math.sqrt(2.0)) * W.dt_for_courant(g, 15.0, "x")
+    A = _dense_operator(o, g.shape)
+    y = W.make_random_state(g, 9, smooth=False)
+    xd = scipy.linalg.solve(np.eye(A.shape[0]) - lam * A, y.reshape(-1)).reshape(g.shape)
+    bg = o.background()
+    G0 = bg["G0"][:, None, None]
+    H0 = bg["H0"][:, None, None]
+    P = G0 * xd[0] + H0 * xd[4]
+    b = o.schur_rhs(y, lam)
+    assert np.max(np.abs(o.schur_apply(P, lam) - b)) < 1e-12 * np.max(np.abs(b))
+
+
+def test_schur_spectrum_real_and_bounds(oracle_mod):
+    """The Schur operator has a real spectrum starting at 1 (Sec. 5.5 notes
+    the real eigenvalues of the Schur form); the PBNO interval covers it."""
+    g = _G3
+    o = _oracle(oracle_mod, g)
+    lam = (1.0 - 1.0 / math.sqrt(2.0)) * W.dt_for_courant(g, 15.0, "x")
+    ev = np.linalg.eigvals(_dense_schur(o, lam))
+    assert np.max(np.abs(ev.imag)) < 1e-8 * np.max(ev.real)
+    assert abs(np.min(ev.real) - 1.0) < 1e-8
+    bd = o.schur_bounds(lam, 30)
+    assert bd[0] == 1.0
+    assert np.max(ev.real) <= bd[1] <= 1.2 * np.max(ev.real)
+
+
+@pytest.mark.parametrize("order", [0, 1, 2])
+def test_pbno_is_the_chebyshev_polynomial(oracle_mod, order):
+    """On an eigenvector v of S (eigenvalue mu), s(S) v = s(mu) v with
+    1 - mu s(mu) = T_{p+1}((theta - mu)/delta) / T_{p+1}(theta/delta)."""
+    g = W.Grid(3000.0, 2500.0, 2000.0, 1, 1, 2, 3)
+    o = _oracle(oracle_mod, g)
+    lam = (1.0 - 1.0 / math.sqrt(2.0)) * W.dt_for_courant(g, 15.0, "x")
+    S = _dense_schur(o, lam)
+    ev, vecs = np.linalg.eig(S)
+    lmin, lmax = 1.0, 1.1 * np.max(ev.real)
+    th, de = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+    cheb = np.polynomial.chebyshev.Chebyshev.basis(order + 1)
+    for idx in np.argsort(ev.real)[:: max(1, len(ev) // 6)]:
+        mu, v = ev[idx].real, vecs[:, idx].real
+        z = o.pbno_apply(v.reshape(o.shape[1:]), lam, order, (lmin, lmax)).reshape(-1)
+        s_mu = (1.0 - cheb((th - mu) / de) / cheb(th / de)) / mu
+        assert np.max(np.abs(z - s_mu * v)) < 1e-10 * np.max(np.abs(v)) * max(1.0, abs(s_mu) * lmax), (mu, order)
+
+
+def test_pbno_order1_reduces_iterations(oracle_mod):
+    g = _G3
+    o = _oracle(oracle_mod, g)
+    lam = (1.0 - 1.0 / math.sqrt(2.0)) * W.dt_for_courant(g, 15.0, "x")
+    bd = o.schur_bounds(lam, 30)
+    y = W.make_random_state(g, 3, smooth=False)
+    x0, it0 = o.solve3d(y, lam, tol=1e-10)
+    x1, it1 = o.solve3d(y, lam, tol=1e-10, order=1, bounds=bd)
+    assert it1 < 0.7 * it0
+    assert np.max(np.abs(x1 - x0)) < 1e-8 * np.max(np.abs(x0))
+
+
+def _horizontally_uniform(grid, seed):
+    q = W.make_random_state(grid, seed, smooth=False)
+    return np.repeat(np.repeat(q[:, :, :1, :1], grid.ny, axis=2), grid.nx, axis=3)
+
+
+def test_solve3d_reduces_to_column_solve(oracle_mod):
+    """With no horizontal variation the horizontal derivatives vanish, L = L_V
+    and the 3D system is the column system: GMRES equals the direct column
+    solve (dense partial-pivot matrices per column)."""
+    g = W.Grid(4000.0, 4000.0, 3000.0, 2, 2, 3, 3, zface=W.random_zface(3, 3000.0, 2))
+    o = _oracle(oracle_mod, g)
+    dt = W.dt_for_courant(g, 15.0, "z")
+    o.factor_dt(dt)
+    y = _horizontally_uniform(g, 6)
+    x3, it = o.solve3d(y, o.lam, tol=1e-14)
+    x1 = o.solve(y)
+    for f in range(5):
+        assert np.max(np.abs(x3[f] - x1[f])) <= 1e-11 * np.max(np.abs(x1[f])) + 1e-300, f
+
+
+def test_step3d_reduces_to_hevi_step(oracle_mod):
+    """Horizontally uniform state: 3D-IMEX and HEVI give the same steps.  The
+    box is wide (horizontal acoustic Courant number ~0.5) so that HEVI's
+    explicit horizontal acoustics do not amplify the rounding differences."""
+    g = W.Grid(40000.0, 40000.0, 3000.0, 2, 2, 3, 3)
+    o = _oracle(oracle_mod, g)
+    dt = W.dt_for_courant(g, 10.0, "z")
+    o.factor_dt(dt)
+    q0 = _horizontally_uniform(g, 8)
+    q1 = o.step(q0, dt, 3)
+    q3, it = o.step3d(q0, dt, 3, tol=1e-14)
+    assert it > 0
+    for f in range(5):
+        assert np.max(np.abs(q3[f] - q1[f])) < 1e-10 * np.max(np.abs(q1[f] - q0[f])), f
+
+
+def test_imex3d_second_order_on_linear_acoustics(oracle_mod):
+    """R := L, all of it implicit: the step is the SDIRK part of the tableau
+    on linear acoustics; error against expm(T A) q0 falls by ~4 per halving."""
+    N = 3
+    g = W.Grid(6000.0, 3000.0, 3000.0, 2, 1, 2, N)
+    o = _oracle(oracle_mod, g)
+    A = _dense_operator(o, g.shape)
+    q0 = W.make_random_state(g, 5)
+    T = 4.0
+    exact = (scipy.linalg.expm(T * A) @ q0.reshape(-1)).reshape(g.shape)
+    errs = []
+    for nsteps in (4, 8, 16, 32):
+        qT, _ = o.step3d(q0, T / nsteps, nsteps, tol=1e-14, linear=True)
+        errs.append(np.linalg.norm(qT - exact) / np.linalg.norm(exact))
+    slopes = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert min(slopes[1:]) >= 1.9, (errs, slopes)
+
+
+def test_imex3d_stable_at_aspect_ratio_one(oracle_mod):
+    """The 1 km cube at acoustic Courant number 15 in every direction: HEVI
+    blows up (its horizontal acoustics are explicit), 3D-IMEX stays bounded
+    because all acoustic terms are implicit (Sec. 2)."""
+    lit = W.box_small("R2")
+    o = _oracle(oracle_mod, lit.grid)
+    q = W.make_initial_state(lit)
+    dt = W.box_small("R1").dt
+    q1, it = o.step3d(q, dt, 10, tol=1e-10)
+    assert np.all(np.isfinite(q1))
+    assert np.nanmax(np.abs(q1[3])) < 1.0
