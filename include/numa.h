@@ -45,7 +45,7 @@ extern "C" {
 #define NUMA_E_HIP (-4)           /* HIP runtime error; text in numa_last_error         */
 #define NUMA_E_NOMEM (-5)         /* device allocation failed                           */
 #define NUMA_E_NONFINITE (-6)     /* a step produced NaN or Inf (reported by numa_check) */
-#define NUMA_E_NOT_CONVERGED (-7) /* reserved for an iterative 3D-IMEX solve            */
+#define NUMA_E_NOT_CONVERGED (-7) /* 3D-IMEX GMRES reached maxit before tol             */
 #define NUMA_E_UNSUPPORTED (-8)   /* feature or size not supported by this build        */
 
 typedef struct numa_ctx numa_ctx; /* opaque; owns all device memory except states */
@@ -214,9 +214,55 @@ int numa_rhs(numa_ctx *c, const double *state, double *rhs_out);
 int numa_solve_columns(numa_ctx *c, const double *y, double *x);
 
 /*
- * 3D-IMEX step with an iterative Schur solve (Sec. 5.5).  Not part of this
- * build: always returns NUMA_E_UNSUPPORTED.
+ * 3D-IMEX (Sec. 2): the implicit part of the ARK2 step is the whole linear
+ * operator L (horizontal acoustics included) instead of L_V, and each
+ * implicit system (I - lambda L) x = y is solved iteratively (Sec. 5.5) in
+ * its Schur-complement form for the linear pressure P = G0 rho' + H0 theta'
+ * (the Set2NC analogue of Algs. 4-5):
+ *   S P = P - lambda G0 div(rho0 U_p(P)) = b,
+ *   U_p(P) = lambda (Dx P/rho0, Dy P/rho0, B (Dz P/rho0 + g P/(G0 rho0))),
+ *   b = G0 y_rho + H0 y_theta - lambda G0 div(rho0 U_a),
+ *   U_a = (y_u, y_v, B (y_w + lambda g H0 y_theta/(G0 rho0))),
+ * B zeroing w on the bottom and top levels, followed by u = U_a - U_p(P),
+ * rho' from the continuity row and theta' = y_theta.  S P = b is solved by
+ * restarted GMRES from P = 0, right-preconditioned by PBNO (Sec. 5.5,
+ * Alg. 8): the Chebyshev minimax polynomial of the given order on the
+ * eigenvalue interval [lmin, lmax] of S (order 0 is the scaling
+ * 2/(lmin+lmax) alone, -1 no preconditioner).  lambda = (1 - 1/sqrt(2)) dt.
+ *
+ * numa_imex3d_setup: allocates the solver state of the context (Krylov
+ * basis of restart+1 fields, 9 scalar and 4 five-field work fields) and
+ * estimates the interval: lmin = 1, lmax = 1.1 |S^k v|/|S^(k-1) v| after
+ * k = power_steps power steps from v_I = frac(I * 2654435769 / 2^32) - 1/2
+ * (power_steps = 0 keeps [1, 2]; set it with numa_imex3d_set_bounds).
+ * restart 1..200, pbno_order -1..16, maxit >= 1 (Arnoldi iterations per
+ * solve).  Calling it again replaces the previous state.  Synchronous.
+ * Errors: NUMA_E_ARG, NUMA_E_NOMEM, NUMA_E_HIP.
+ * numa_imex3d_bounds: out[2] (host) = {lmin, lmax}.  numa_imex3d_set_bounds:
+ * overrides them (0 < lmin < lmax).
+ *
+ * numa_schur_apply (out = S P), numa_schur_rhs (b from y) and
+ * numa_pbno_apply (z = s(S) r): single device fields of nz*ny*nx doubles
+ * (y: a state-contract array; P/out and r/z distinct).  Asynchronous.
+ *
+ * numa_imex3d_solve: x = (I - lambda L)^-1 y to |b - S P| <= tol |b|;
+ * y, x state-contract device arrays (x == y allowed, no partial overlap);
+ * *iters_out (host, nullable) = Arnoldi iterations.  Synchronous.
+ * numa_imex3d_step: one ARK2 step of state (dt equal, bitwise, to the set-up
+ * dt), both stage solves to tol; *iters_out = their iterations.
+ * Synchronous; NaN or Inf is reported by numa_check.
+ * Errors of these: NUMA_E_ARG, NUMA_E_NOT_FACTORED (no numa_imex3d_setup),
+ * NUMA_E_DT_MISMATCH, NUMA_E_NOT_CONVERGED (maxit reached; the result is
+ * still written), NUMA_E_HIP.
  */
+int numa_imex3d_setup(numa_ctx *c, double dt, int32_t restart, int32_t pbno_order, int32_t power_steps,
+                      int32_t maxit);
+int numa_imex3d_bounds(const numa_ctx *c, double *out);
+int numa_imex3d_set_bounds(numa_ctx *c, double lmin, double lmax);
+int numa_schur_apply(numa_ctx *c, const double *P, double *out);
+int numa_schur_rhs(numa_ctx *c, const double *y, double *b);
+int numa_pbno_apply(numa_ctx *c, const double *r, double *z);
+int numa_imex3d_solve(numa_ctx *c, const double *y, double *x, double tol, int32_t *iters_out);
 int numa_imex3d_step(numa_ctx *c, double *state, double dt, double tol, int32_t *iters_out);
 
 /*

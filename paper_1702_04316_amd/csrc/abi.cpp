@@ -36,6 +36,7 @@ void free_ctx(numa_ctx *c)
     if (c->work) (void)hipFree(c->work);
     if (c->work_mix) (void)hipFree(c->work_mix);
     if (c->flag) (void)hipFree(c->flag);
+    numa::imex3d_free(c);
     delete c;
 }
 
@@ -333,12 +334,113 @@ int numa_solve_columns(numa_ctx *c, const double *y, double *x)
     return NUMA_OK;
 }
 
-int numa_imex3d_step(numa_ctx *c, double *state, double dt, double tol, int32_t *iters_out)
+int numa_imex3d_setup(numa_ctx *c, double dt, int32_t restart, int32_t pbno_order, int32_t power_steps,
+                      int32_t maxit)
 {
-    (void)state; (void)dt; (void)tol;
+    if (!c) return NUMA_E_ARG;
+    if (!finite_pos(dt) || restart < 1 || restart > 200 || pbno_order < -1 || pbno_order > 16 || power_steps < 0 ||
+        power_steps > 1000 || maxit < 1)
+        return fail(c, NUMA_E_ARG, "numa_imex3d_setup: bad arguments");
+    hipError_t e = numa::imex3d_setup(c, dt, restart, pbno_order, power_steps, maxit);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        numa::imex3d_free(c);
+        return hip_fail(c, e, "numa_imex3d_setup");
+    }
+    return NUMA_OK;
+}
+
+int numa_imex3d_bounds(const numa_ctx *c, double *out)
+{
+    if (!c || !out || !c->imex) return NUMA_E_ARG;
+    double dt;
+    numa::imex3d_info(c, &dt, &out[0], &out[1]);
+    return NUMA_OK;
+}
+
+int numa_imex3d_set_bounds(numa_ctx *c, double lmin, double lmax)
+{
+    if (!c) return NUMA_E_ARG;
+    if (!c->imex) return fail(c, NUMA_E_NOT_FACTORED, "numa_imex3d_set_bounds: call numa_imex3d_setup first");
+    if (!finite_pos(lmin) || !std::isfinite(lmax) || !(lmax > lmin))
+        return fail(c, NUMA_E_ARG, "numa_imex3d_set_bounds: need 0 < lmin < lmax");
+    numa::imex3d_set_bounds(c, lmin, lmax);
+    return NUMA_OK;
+}
+
+namespace {
+
+int imex3d_ready(numa_ctx *c, const char *who)
+{
+    if (!c->imex) return fail(c, NUMA_E_NOT_FACTORED, std::string(who) + ": call numa_imex3d_setup first");
+    return NUMA_OK;
+}
+
+}  // namespace
+
+int numa_schur_apply(numa_ctx *c, const double *P, double *out)
+{
+    if (!c) return NUMA_E_ARG;
+    if (!P || !out || P == out) return fail(c, NUMA_E_ARG, "numa_schur_apply: null or identical pointers");
+    int rc = imex3d_ready(c, "numa_schur_apply");
+    if (rc != NUMA_OK) return rc;
+    hipError_t e = numa::schur_apply(c, P, out);
+    return e == hipSuccess ? NUMA_OK : hip_fail(c, e, "numa_schur_apply");
+}
+
+int numa_schur_rhs(numa_ctx *c, const double *y, double *b)
+{
+    if (!c) return NUMA_E_ARG;
+    if (!y || !b) return fail(c, NUMA_E_ARG, "numa_schur_rhs: null pointer");
+    int rc = imex3d_ready(c, "numa_schur_rhs");
+    if (rc != NUMA_OK) return rc;
+    hipError_t e = numa::schur_rhs(c, y, b);
+    return e == hipSuccess ? NUMA_OK : hip_fail(c, e, "numa_schur_rhs");
+}
+
+int numa_pbno_apply(numa_ctx *c, const double *r, double *z)
+{
+    if (!c) return NUMA_E_ARG;
+    if (!r || !z || r == z) return fail(c, NUMA_E_ARG, "numa_pbno_apply: null or identical pointers");
+    int rc = imex3d_ready(c, "numa_pbno_apply");
+    if (rc != NUMA_OK) return rc;
+    hipError_t e = numa::pbno_apply(c, r, z);
+    return e == hipSuccess ? NUMA_OK : hip_fail(c, e, "numa_pbno_apply");
+}
+
+int numa_imex3d_solve(numa_ctx *c, const double *y, double *x, double tol, int32_t *iters_out)
+{
     if (iters_out) *iters_out = 0;
     if (!c) return NUMA_E_ARG;
-    return fail(c, NUMA_E_UNSUPPORTED, "numa_imex3d_step: 3D-IMEX is not part of this build");
+    if (!y || !x || !(tol > 0.0) || !std::isfinite(tol)) return fail(c, NUMA_E_ARG, "numa_imex3d_solve: bad arguments");
+    int rc = imex3d_ready(c, "numa_imex3d_solve");
+    if (rc != NUMA_OK) return rc;
+    int it = 0, conv = 0;
+    hipError_t e = numa::imex3d_solve(c, y, x, nullptr, 0.0, nullptr, 0.0, tol, &it, &conv);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (iters_out) *iters_out = it;
+    if (e != hipSuccess) return hip_fail(c, e, "numa_imex3d_solve");
+    if (!conv) return fail(c, NUMA_E_NOT_CONVERGED, "numa_imex3d_solve: GMRES did not reach tol within maxit");
+    return NUMA_OK;
+}
+
+int numa_imex3d_step(numa_ctx *c, double *state, double dt, double tol, int32_t *iters_out)
+{
+    if (iters_out) *iters_out = 0;
+    if (!c) return NUMA_E_ARG;
+    if (!state || !(tol > 0.0) || !std::isfinite(tol)) return fail(c, NUMA_E_ARG, "numa_imex3d_step: bad arguments");
+    int rc = imex3d_ready(c, "numa_imex3d_step");
+    if (rc != NUMA_OK) return rc;
+    double dts, lmin, lmax;
+    numa::imex3d_info(c, &dts, &lmin, &lmax);
+    if (dt != dts) return fail(c, NUMA_E_DT_MISMATCH, "numa_imex3d_step: dt differs from the numa_imex3d_setup dt");
+    int it = 0, conv = 0;
+    hipError_t e = numa::imex3d_step(c, state, dt, tol, &it, &conv);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (iters_out) *iters_out = it;
+    if (e != hipSuccess) return hip_fail(c, e, "numa_imex3d_step");
+    if (!conv) return fail(c, NUMA_E_NOT_CONVERGED, "numa_imex3d_step: GMRES did not reach tol within maxit");
+    return NUMA_OK;
 }
 
 int numa_lgl_basis(int32_t order, double *xi, double *D)

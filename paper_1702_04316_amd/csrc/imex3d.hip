@@ -1,0 +1,886 @@
+// 3D-IMEX step (Sec. 2): the implicit part is the whole linear operator L,
+// and the implicit systems (I - lambda L) x = y are solved iteratively
+// (Sec. 5.5) in their Schur-complement form (the Set2NC analogue of the
+// pressure system of Algs. 4-5).
+//
+// With theta' = y_theta (L has no theta' tendency for a constant theta0) and
+// the linear pressure P = G0 rho' + H0 theta', eliminating the velocities
+// leaves one scalar field per node:
+//     S P = P - lambda^2 (V P + G0 (Dxx P + Dyy P)) = b,
+//     b   = G0 y_rho + H0 y_theta - lambda G0 (rho0 (Dx y_u + Dy y_v) + Dz(rho0 w_a)),
+//     w_a = B (y_w + lambda g H0 y_theta / (G0 rho0)),
+// where Dx, Dy, Dz are the direct-stiffness-summed line derivatives, B zeroes
+// w on the bottom and top, Dxx = Dx Dx and Dyy = Dy Dy (rho0 depends on z
+// only, so it cancels in the horizontal terms), and
+//     V = G0 Dz B (Dz + g / G0)
+// is the vertical part (rho0 cancels there too), a band of half-width 2N per
+// column.  The solution is
+// then u = y_u - lambda Dx P / rho0, v = y_v - lambda Dy P / rho0,
+// w = w_a - lambda B (Dz P / rho0 + g P / (G0 rho0)), and, with r = b - S P,
+// rho' = (P - H0 y_theta + r) / G0 (the continuity row written through S).
+//
+// Kernels (one thread per node; node I = i + nx (j + ny k), i fastest):
+//   k_schur_apply   S applied to a field in one pass (composed x and y line
+//                   stencils of width 4N+1, the vertical band), with an
+//                   epilogue for residuals, the Chebyshev (PBNO) recurrence
+//                   and fused partial dot products against Krylov vectors
+//   k_schur_rhs     b from the 5-field y
+//   k_schur_extract the 5-field solution (plus optional stage shifts)
+//   k_dots, k_finish, k_cgs_update, k_normalize, k_givens, k_combine:
+//                   the GMRES vector work; every reduction is two-pass with
+//                   a fixed order, so results do not depend on timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+#include <vector>
+
+#include "numa_internal.h"
+
+namespace numa {
+
+namespace {
+
+constexpr int kTB = 256;  // threads per block of every kernel here
+
+inline long nblocks(long n) { return (n + kTB - 1) / kTB; }
+
+__device__ inline int wrap(int i, int n)
+{
+    while (i < 0) i += n;
+    while (i >= n) i -= n;
+    return i;
+}
+
+// Sum over the 256 threads of a block in a fixed order (wave shuffles, then
+// the four wave sums); every thread must call it.
+__device__ inline double block_sum(double v, double *sh)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    const double t = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    __syncthreads();
+    return t;
+}
+
+struct OpTables {
+    const double *wxx, *wyy;  // [N][4N+1] composed x, y stencils by local index
+    const double *vb;         // [nz][4N+1] vertical band, offsets -2N..2N
+    const double *wxy;        // [2][N][2N+1] first-derivative x, y stencils
+    const double *dzb;        // [nz][2N+1] first-derivative column band
+    const double *rho0, *G0, *H0;
+    int nx, ny, nz;
+    long np;
+};
+
+enum { AP_AXPY = 0, AP_CHEB = 1 };
+
+struct ApplyArgs {
+    const double *in;
+    double scale;  // the operand is scale * in
+    int mode;
+    // AP_AXPY: out = alpha * x + beta * S x + gamma * aux   (x = scale * in)
+    double *out;
+    double alpha, beta, gamma;
+    const double *aux;
+    // AP_CHEB (one step of the Chebyshev recurrence, d = scale * in):
+    // res = res_in - S d; d' = c1 d + c2 res; z = z_in + d'.  Null res_in
+    // means res_in = in (unscaled), null z_in means z_in = d.
+    const double *res_in, *z_in;
+    double *res_out, *d_out, *z_out;
+    double c1, c2;
+    // fused partial dots of the AP_AXPY output with V_0..V_{nv-1}
+    const double *V;
+    int nv;
+    double *part;
+    long nblk;
+    const int *stop;
+    double lam2;
+};
+
+template <int N>
+__device__ inline double schur_at(const OpTables &t, const double *in, double lam2, long I)
+{
+    constexpr int W = 4 * N + 1;
+    const int nx = t.nx, ny = t.ny, nz = t.nz;
+    const long plane = long(nx) * ny;
+    const int i = int(I % nx);
+    const long tt = I / nx;
+    const int j = int(tt % ny), k = int(tt / ny);
+    const long kb = long(k) * plane;
+    const double *wx = t.wxx + (i % N) * W, *wy = t.wyy + (j % N) * W, *vk = t.vb + long(k) * W;
+    const double *row = in + kb + long(j) * nx;
+    double sx = 0.0, sy = 0.0, sv = 0.0;
+#pragma unroll
+    for (int m = 0; m < W; ++m) sx += wx[m] * row[wrap(i - 2 * N + m, nx)];
+#pragma unroll
+    for (int m = 0; m < W; ++m) sy += wy[m] * in[kb + long(wrap(j - 2 * N + m, ny)) * nx + i];
+    const double *col = in + long(j) * nx + i;
+#pragma unroll
+    for (int m = 0; m < W; ++m) {
+        const int kk = k - 2 * N + m;
+        if (kk >= 0 && kk < nz) sv += vk[m] * col[long(kk) * plane];
+    }
+    return in[I] - lam2 * (sv + t.G0[k] * (sx + sy));
+}
+
+template <int N>
+__global__ __launch_bounds__(kTB) void k_schur_apply(OpTables t, ApplyArgs a)
+{
+    __shared__ double sh[4];
+    if (a.stop && *a.stop) return;
+    const long I = long(blockIdx.x) * kTB + threadIdx.x;
+    const bool ok = I < t.np;
+    double val = 0.0;
+    if (ok) {
+        const double Sx = a.scale * schur_at<N>(t, a.in, a.lam2, I);
+        const double x = a.scale * a.in[I];
+        if (a.mode == AP_AXPY) {
+            val = a.beta * Sx;
+            if (a.alpha != 0.0) val += a.alpha * x;
+            if (a.aux) val += a.gamma * a.aux[I];
+            a.out[I] = val;
+        } else {
+            const double res = (a.res_in ? a.res_in[I] : a.in[I]) - Sx;
+            const double dn = a.c1 * x + a.c2 * res;
+            a.z_out[I] = (a.z_in ? a.z_in[I] : x) + dn;
+            if (a.res_out) a.res_out[I] = res;
+            if (a.d_out) a.d_out[I] = dn;
+        }
+    }
+    for (int v = 0; v < a.nv; ++v) {
+        const double s = block_sum(ok ? val * a.V[long(v) * t.np + I] : 0.0, sh);
+        if (threadIdx.x == 0) a.part[long(v) * a.nblk + blockIdx.x] = s;
+    }
+}
+
+// first derivatives along x, y (line stencils) and z (column band) of f at I
+template <int N>
+__device__ inline double dline(const double *w, const double *f, int i, int n, long base, long stride)
+{
+    const int a = i % N, e0 = i - a;
+    const double *c = w + a * (2 * N + 1);
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m <= 2 * N; ++m) s += c[m] * f[base + long(wrap(e0 - N + m, n)) * stride];
+    return s;
+}
+
+template <int N>
+__global__ __launch_bounds__(kTB) void k_schur_rhs(OpTables t, const double *y, double *b, double lam, double g)
+{
+    const long I = long(blockIdx.x) * kTB + threadIdx.x;
+    if (I >= t.np) return;
+    const long np = t.np, plane = long(t.nx) * t.ny;
+    const int i = int(I % t.nx);
+    const long tt = I / t.nx;
+    const int j = int(tt % t.ny), k = int(tt / t.ny);
+    const double *yr = y, *yu = y + np, *yv = y + 2 * np, *yw = y + 3 * np, *yt = y + 4 * np;
+    const double dxu = dline<N>(t.wxy, yu, i, t.nx, long(k) * plane + long(j) * t.nx, 1);
+    const double dyv = dline<N>(t.wxy + N * (2 * N + 1), yv, j, t.ny, long(k) * plane + i, t.nx);
+    // Dz(rho0 w_a)
+    const double *dz = t.dzb + long(k) * (2 * N + 1);
+    const long col = long(j) * t.nx + i;
+    double dzw = 0.0;
+#pragma unroll
+    for (int m = 0; m <= 2 * N; ++m) {
+        const int kk = k - N + m;
+        if (kk <= 0 || kk >= t.nz - 1) continue;  // outside, or a wall level (w_a = 0)
+        const long J = long(kk) * plane + col;
+        const double wa = yw[J] + lam * g * t.H0[kk] * yt[J] / (t.G0[kk] * t.rho0[kk]);
+        dzw += dz[m] * (t.rho0[kk] * wa);
+    }
+    const double G0 = t.G0[k];
+    b[I] = G0 * yr[I] + t.H0[k] * yt[I] - lam * G0 * (t.rho0[k] * (dxu + dyv) + dzw);
+}
+
+struct ExtractArgs {
+    const double *y, *P, *r;
+    double *out;
+    const double *in0, *in1;  // out = X + d0 in0 + d1 in1 (nullable)
+    double d0, d1;
+    double lam, g;
+};
+
+template <int N>
+__global__ __launch_bounds__(kTB) void k_schur_extract(OpTables t, ExtractArgs a)
+{
+    const long I = long(blockIdx.x) * kTB + threadIdx.x;
+    if (I >= t.np) return;
+    const long np = t.np, plane = long(t.nx) * t.ny;
+    const int i = int(I % t.nx);
+    const long tt = I / t.nx;
+    const int j = int(tt % t.ny), k = int(tt / t.ny);
+    const double *P = a.P;
+    const double dxp = dline<N>(t.wxy, P, i, t.nx, long(k) * plane + long(j) * t.nx, 1);
+    const double dyp = dline<N>(t.wxy + N * (2 * N + 1), P, j, t.ny, long(k) * plane + i, t.nx);
+    const double *dz = t.dzb + long(k) * (2 * N + 1);
+    const double *pc = P + long(j) * t.nx + i;
+    double dzp = 0.0;
+#pragma unroll
+    for (int m = 0; m <= 2 * N; ++m) {
+        const int kk = k - N + m;
+        if (kk >= 0 && kk < t.nz) dzp += dz[m] * pc[long(kk) * plane];
+    }
+    const double r0 = t.rho0[k], G0 = t.G0[k], H0 = t.H0[k];
+    const double yr = a.y[I], yu = a.y[np + I], yv = a.y[2 * np + I], yw = a.y[3 * np + I], yt = a.y[4 * np + I];
+    double X[5];
+    X[0] = (P[I] - H0 * yt + a.r[I]) / G0;
+    X[1] = yu - a.lam * dxp / r0;
+    X[2] = yv - a.lam * dyp / r0;
+    const bool wall = k == 0 || k == t.nz - 1;
+    X[3] = wall ? 0.0 : yw + a.lam * a.g * H0 * yt / (G0 * r0) - a.lam * (dzp / r0 + a.g * P[I] / (G0 * r0));
+    X[4] = yt;
+    (void)yr;
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+        double v = X[f];
+        if (a.in0) v += a.d0 * a.in0[f * np + I];
+        if (a.in1) v += a.d1 * a.in1[f * np + I];
+        a.out[f * np + I] = v;
+    }
+}
+
+// out = c0 in0 + c1 in1 + c2 in2 over n elements (null inputs skipped)
+__global__ __launch_bounds__(kTB) void k_lincomb(double *out, const double *in0, double c0, const double *in1, double c1,
+                                                 const double *in2, double c2, long n)
+{
+    const long I = long(blockIdx.x) * kTB + threadIdx.x;
+    if (I >= n) return;
+    double v = c0 * in0[I];
+    if (in1) v += c1 * in1[I];
+    if (in2) v += c2 * in2[I];
+    out[I] = v;
+}
+
+// partial dots of w with V_0..V_{nv-1} (V == null: of w with itself)
+__global__ __launch_bounds__(kTB) void k_dots(const double *w, const double *V, int nv, long n, double *part,
+                                              long nblk, const int *stop)
+{
+    __shared__ double sh[4];
+    if (stop && *stop) return;
+    const long I = long(blockIdx.x) * kTB + threadIdx.x;
+    const bool ok = I < n;
+    const double wv = ok ? w[I] : 0.0;
+    for (int v = 0; v < nv; ++v) {
+        const double o = ok ? (V ? V[long(v) * n + I] : wv) : 0.0;
+        const double s = block_sum(wv * o, sh);
+        if (threadIdx.x == 0) part[long(v) * nblk + blockIdx.x] = s;
+    }
+}
+
+// Second pass: block v sums the nblk partials of dot v (fixed order) into
+// h[v] (sqrt of it if root); with H, also H[v*m + col] = h[v] (add: +=).
+__global__ __launch_bounds__(kTB) void k_finish(const double *part, long nblk, double *h, int root, double *H, int m,
+                                                int col, int add, const int *stop)
+{
+    __shared__ double sh[4];
+    if (stop && *stop) return;
+    const int v = blockIdx.x;
+    double s = 0.0;
+    for (long b = threadIdx.x; b < nblk; b += kTB) s += part[long(v) * nblk + b];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) {
+        if (root) s = std::sqrt(s);
+        h[v] = s;
+        if (H) {
+            double *e = H + long(v) * m + col;
+            *e = add ? *e + s : s;
+        }
+    }
+}
+
+// w -= sum_v h[v] V_v; then partial dots of the new w with V_0..V_{nvd-1}
+// (nvd < 0: the partial of |w|^2 alone)
+__global__ __launch_bounds__(kTB) void k_cgs_update(double *w, const double *V, int nv, const double *h, long n,
+                                                    int nvd, double *part, long nblk, const int *stop)
+{
+    __shared__ double sh[4];
+    if (stop && *stop) return;
+    const long I = long(blockIdx.x) * kTB + threadIdx.x;
+    const bool ok = I < n;
+    double wv = 0.0;
+    if (ok) {
+        wv = w[I];
+        for (int v = 0; v < nv; ++v) wv -= h[v] * V[long(v) * n + I];
+        w[I] = wv;
+    }
+    if (nvd < 0) {
+        const double s = block_sum(wv * wv, sh);
+        if (threadIdx.x == 0) part[blockIdx.x] = s;
+    } else {
+        for (int v = 0; v < nvd; ++v) {
+            const double s = block_sum(ok ? wv * V[long(v) * n + I] : 0.0, sh);
+            if (threadIdx.x == 0) part[long(v) * nblk + blockIdx.x] = s;
+        }
+    }
+}
+
+// out = in / s (s on the device; 0 where s is not positive)
+__global__ __launch_bounds__(kTB) void k_normalize(double *out, const double *in, const double *s, long n,
+                                                   const int *stop)
+{
+    if (stop && *stop) return;
+    const long I = long(blockIdx.x) * kTB + threadIdx.x;
+    if (I >= n) return;
+    const double d = *s;
+    out[I] = d > 0.0 ? in[I] / d : 0.0;
+}
+
+// out = c in (host scalar)
+__global__ __launch_bounds__(kTB) void k_scale(double *out, const double *in, double c, long n)
+{
+    const long I = long(blockIdx.x) * kTB + threadIdx.x;
+    if (I < n) out[I] = c * in[I];
+}
+
+// Givens step of column j of the Hessenberg matrix (row stride m): the
+// earlier rotations, a new one that zeroes H[j+1][j], the rotated residual
+// vector g; stop[0] = 1 once |g[j+1]| <= tolb; stop[1] counts iterations.
+__global__ void k_givens(double *H, double *cs, double *sn, double *g, int j, int m, double tolb, int *stop)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0 || stop[0]) return;
+    for (int i = 0; i < j; ++i) {
+        const double a = H[i * m + j], b = H[(i + 1) * m + j];
+        H[i * m + j] = cs[i] * a + sn[i] * b;
+        H[(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = H[j * m + j], b = H[(j + 1) * m + j], r = std::hypot(a, b);
+    cs[j] = r > 0.0 ? a / r : 1.0;
+    sn[j] = r > 0.0 ? b / r : 0.0;
+    H[j * m + j] = r;
+    H[(j + 1) * m + j] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    stop[1] += 1;
+    if (std::fabs(g[j + 1]) <= tolb) stop[0] = 1;
+}
+
+// start of a cycle: g = (beta, 0, ...), flags cleared
+__global__ void k_cycle_init(double *g, int m, double beta, int *stop)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    g[0] = beta;
+    for (int i = 1; i <= m; ++i) g[i] = 0.0;
+    stop[0] = 0;
+    stop[1] = 0;
+}
+
+// out (+)= sum_v c[v] V_v
+__global__ __launch_bounds__(kTB) void k_combine(double *out, const double *V, const double *c, int nv, long n,
+                                                 int add)
+{
+    const long I = long(blockIdx.x) * kTB + threadIdx.x;
+    if (I >= n) return;
+    double s = add ? out[I] : 0.0;
+    for (int v = 0; v < nv; ++v) s += c[v] * V[long(v) * n + I];
+    out[I] = s;
+}
+
+// power-method start vector: frac(I * 2654435769 / 2^32) - 1/2
+__global__ __launch_bounds__(kTB) void k_start_vector(double *v, long n)
+{
+    const long I = long(blockIdx.x) * kTB + threadIdx.x;
+    if (I >= n) return;
+    const uint32_t h = uint32_t(uint64_t(I) * 2654435769u);
+    v[I] = double(h) / 4294967296.0 - 0.5;
+}
+
+template <typename F>
+hipError_t dispatch3(int N, F &&f)
+{
+    switch (N) {
+    case 1: return f(std::integral_constant<int, 1>{});
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 3: return f(std::integral_constant<int, 3>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 5: return f(std::integral_constant<int, 5>{});
+    case 6: return f(std::integral_constant<int, 6>{});
+    case 7: return f(std::integral_constant<int, 7>{});
+    case 8: return f(std::integral_constant<int, 8>{});
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+// Device state of the 3D-IMEX solver of one context.
+struct Imex3d {
+    int restart = 0, order = -1, maxit = 0, power_steps = 0;
+    double dt = 0, lambda = 0, lmin = 1, lmax = 2;
+    long np = 0, nblk = 0;
+    void *block = nullptr;  // one allocation for everything below
+    double *wxx = nullptr, *wyy = nullptr, *vb = nullptr;
+    double *V = nullptr;                                   // (restart+1) np
+    double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *w = nullptr;
+    double *cres = nullptr, *d0 = nullptr, *d1 = nullptr;  // Chebyshev recurrence
+    double *part = nullptr;                                // (restart+1) nblk
+    double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *hb = nullptr, *yc = nullptr;
+    double *R1 = nullptr, *Q2 = nullptr, *E3 = nullptr, *ACC = nullptr;  // 5 np each
+    int *stop = nullptr;
+    std::vector<double> hH, hg, hy;
+};
+
+namespace {
+
+OpTables op_tables(const numa_ctx *c)
+{
+    OpTables t{};
+    t.wxx = c->imex->wxx;
+    t.wyy = c->imex->wyy;
+    t.vb = c->imex->vb;
+    t.wxy = c->lev.wxy;
+    t.dzb = c->lev.dzb;
+    t.rho0 = c->lev.rho0;
+    t.G0 = c->lev.G0;
+    t.H0 = c->lev.H0;
+    t.nx = int(c->nx);
+    t.ny = int(c->ny);
+    t.nz = int(c->nz);
+    t.np = c->np;
+    return t;
+}
+
+// Composed stencil Dxx = Dx Dx of a periodic line of n nodes from the
+// first-derivative stencils w [N][2N+1] (node e0 - N + m for local index a,
+// e0 the element start): rows a = 0..N-1, offsets -2N..2N; where offsets
+// alias on a short line the coefficient is kept at the first of them.
+void composed_line(const double *w, int N, int n, std::vector<double> &out)
+{
+    const int ns = 2 * N + 1, W = 4 * N + 1;
+    auto row = [&](int i, std::vector<double> &r) {
+        r.assign(n, 0.0);
+        const int a = i % N, e0 = i - a;
+        for (int m = 0; m < ns; ++m) r[((e0 - N + m) % n + n) % n] += w[a * ns + m];
+    };
+    out.assign(size_t(N) * W, 0.0);
+    std::vector<double> ra, rl, acc;
+    for (int a = 0; a < N; ++a) {
+        row(a, ra);
+        acc.assign(n, 0.0);
+        for (int l = 0; l < n; ++l) {
+            if (ra[l] == 0.0) continue;
+            row(l, rl);
+            for (int q = 0; q < n; ++q) acc[q] += ra[l] * rl[q];
+        }
+        std::vector<char> used(n, 0);
+        for (int m = 0; m < W; ++m) {
+            const int col = ((a - 2 * N + m) % n + n) % n;
+            if (used[col]) continue;
+            used[col] = 1;
+            out[a * W + m] = acc[col];
+        }
+    }
+}
+
+// Vertical band V = G0 Dz B (Dz + g/G0), [nz][4N+1] (rho0 of the vertical
+// momentum flux cancels against the 1/rho0 of the pressure gradient)
+void vertical_band(const std::vector<double> &dzb, const std::vector<double> &G0, double grav, int N, int nz,
+                   std::vector<double> &out)
+{
+    const int ns = 2 * N + 1, W = 4 * N + 1;
+    auto dz = [&](int k, int l) -> double {
+        const int m = l - k + N;
+        return (m >= 0 && m < ns) ? dzb[size_t(k) * ns + m] : 0.0;
+    };
+    out.assign(size_t(nz) * W, 0.0);
+    for (int k = 0; k < nz; ++k)
+        for (int m = 0; m < W; ++m) {
+            const int l = k - 2 * N + m;
+            if (l < 0 || l >= nz) continue;
+            double s = 0.0;
+            for (int q = std::max(1, k - N); q <= std::min(nz - 2, k + N); ++q) {  // B: interior levels only
+                double inner = dz(q, l);
+                if (q == l) inner += grav / G0[l];
+                s += dz(k, q) * inner;
+            }
+            out[size_t(k) * W + m] = G0[k] * s;
+        }
+}
+
+template <int N>
+hipError_t apply_launch(numa_ctx *c, const ApplyArgs &a)
+{
+    hipLaunchKernelGGL((k_schur_apply<N>), dim3(unsigned(nblocks(c->np))), dim3(kTB), 0, c->stream, op_tables(c), a);
+    return hipGetLastError();
+}
+
+hipError_t apply(numa_ctx *c, ApplyArgs a)
+{
+    a.lam2 = c->imex->lambda * c->imex->lambda;
+    a.nblk = c->imex->nblk;
+    return dispatch3(c->N, [&](auto n) { return apply_launch<decltype(n)::value>(c, a); });
+}
+
+ApplyArgs axpy_args(const double *in, double *out, double alpha, double beta, double gamma, const double *aux)
+{
+    ApplyArgs a{};
+    a.in = in;
+    a.scale = 1.0;
+    a.mode = AP_AXPY;
+    a.out = out;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.gamma = gamma;
+    a.aux = aux;
+    return a;
+}
+
+hipError_t lincomb(numa_ctx *c, double *out, const double *in0, double c0, const double *in1, double c1,
+                   const double *in2, double c2, long n)
+{
+    hipLaunchKernelGGL(k_lincomb, dim3(unsigned(nblocks(n))), dim3(kTB), 0, c->stream, out, in0, c0, in1, c1, in2, c2,
+                       n);
+    return hipGetLastError();
+}
+
+// |v| into h[0] on the device
+hipError_t norm_dev(numa_ctx *c, const double *v, double *h)
+{
+    Imex3d &s = *c->imex;
+    hipLaunchKernelGGL(k_dots, dim3(unsigned(s.nblk)), dim3(kTB), 0, c->stream, v, nullptr, 1, s.np, s.part, s.nblk,
+                       nullptr);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kTB), 0, c->stream, s.part, s.nblk, h, 1, nullptr, 0, 0, 0, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t norm_host(numa_ctx *c, const double *v, double *out)
+{
+    hipError_t e = norm_dev(c, v, c->imex->hb);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, c->imex->hb, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return e;
+}
+
+// dst = s(S) src, the PBNO polynomial (order < 0: dst = src)
+hipError_t precondition(numa_ctx *c, const double *src, double *dst)
+{
+    Imex3d &s = *c->imex;
+    if (s.order < 0) return hipMemcpyAsync(dst, src, sizeof(double) * s.np, hipMemcpyDeviceToDevice, c->stream);
+    const double theta = 0.5 * (s.lmax + s.lmin), delta = 0.5 * (s.lmax - s.lmin);
+    const double sigma = theta / delta;
+    if (s.order == 0) {
+        hipLaunchKernelGGL(k_scale, dim3(unsigned(nblocks(s.np))), dim3(kTB), 0, c->stream, dst, src, 1.0 / theta,
+                           s.np);
+        return hipGetLastError();
+    }
+    double rho = 1.0 / sigma;
+    const double *din = src;
+    double *dbuf[2] = {s.d0, s.d1};
+    for (int k = 1; k <= s.order; ++k) {
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        ApplyArgs a{};
+        a.mode = AP_CHEB;
+        a.in = din;
+        a.scale = k == 1 ? 1.0 / theta : 1.0;
+        a.res_in = k == 1 ? nullptr : s.cres;
+        a.z_in = k == 1 ? nullptr : dst;
+        a.z_out = dst;
+        a.res_out = k < s.order ? s.cres : nullptr;
+        a.d_out = k < s.order ? dbuf[k & 1] : nullptr;
+        a.c1 = rn * rho;
+        a.c2 = 2.0 * rn / delta;
+        hipError_t e = apply(c, a);
+        if (e != hipSuccess) return e;
+        din = dbuf[k & 1];
+        rho = rn;
+    }
+    return hipSuccess;
+}
+
+template <int N>
+hipError_t rhs_kernel_launch(numa_ctx *c, const double *y, double *b)
+{
+    hipLaunchKernelGGL((k_schur_rhs<N>), dim3(unsigned(nblocks(c->np))), dim3(kTB), 0, c->stream, op_tables(c), y, b,
+                       c->imex->lambda, c->eos.grav);
+    return hipGetLastError();
+}
+
+template <int N>
+hipError_t extract_launch(numa_ctx *c, const ExtractArgs &a)
+{
+    hipLaunchKernelGGL((k_schur_extract<N>), dim3(unsigned(nblocks(c->np))), dim3(kTB), 0, c->stream, op_tables(c), a);
+    return hipGetLastError();
+}
+
+// Back substitution of the rotated Hessenberg system of j columns.
+void upper_solve(const std::vector<double> &H, const std::vector<double> &g, int m, int j, std::vector<double> &y)
+{
+    y.assign(size_t(std::max(j, 1)), 0.0);
+    for (int i = j - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int k = i + 1; k < j; ++k) t -= H[size_t(i) * m + k] * y[k];
+        y[i] = t / H[size_t(i) * m + i];
+    }
+}
+
+}  // namespace
+
+void imex3d_free(numa_ctx *c)
+{
+    if (!c || !c->imex) return;
+    if (c->imex->block) (void)hipFree(c->imex->block);
+    delete c->imex;
+    c->imex = nullptr;
+}
+
+hipError_t imex3d_setup(numa_ctx *c, double dt, int restart, int order, int power_steps, int maxit)
+{
+    imex3d_free(c);
+    Imex3d *s = new Imex3d();
+    c->imex = s;
+    const int N = c->N, W = 4 * N + 1;
+    const long np = c->np, nz = c->nz;
+    s->restart = restart;
+    s->order = order;
+    s->maxit = maxit;
+    s->power_steps = power_steps;
+    s->dt = dt;
+    s->lambda = (1.0 - 1.0 / std::sqrt(2.0)) * dt;
+    s->np = np;
+    s->nblk = nblocks(np);
+    const int m = restart;
+    // sizes in doubles
+    const size_t n_tab = size_t(2 * N * W + nz * W);
+    const size_t n_vec = size_t(m + 1) * np + 8 * size_t(np) + 20 * size_t(np);
+    const size_t n_small = size_t(m + 1) * s->nblk + size_t(m + 1) * m + 4 * size_t(m + 2) + size_t(m + 2);
+    const size_t total = n_tab + n_vec + n_small + 64;
+    hipError_t e = hipMalloc(&s->block, total * sizeof(double) + 64);
+    if (e != hipSuccess) {
+        s->block = nullptr;
+        return e;
+    }
+    double *p = static_cast<double *>(s->block);
+    s->wxx = p; p += N * W;
+    s->wyy = p; p += N * W;
+    s->vb = p; p += nz * W;
+    s->V = p; p += size_t(m + 1) * np;
+    s->b = p; p += np;
+    s->x = p; p += np;
+    s->r = p; p += np;
+    s->z = p; p += np;
+    s->w = p; p += np;
+    s->cres = p; p += np;
+    s->d0 = p; p += np;
+    s->d1 = p; p += np;
+    s->R1 = p; p += 5 * np;
+    s->Q2 = p; p += 5 * np;
+    s->E3 = p; p += 5 * np;
+    s->ACC = p; p += 5 * np;
+    s->part = p; p += size_t(m + 1) * s->nblk;
+    s->H = p; p += size_t(m + 1) * m;
+    s->cs = p; p += m + 2;
+    s->sn = p; p += m + 2;
+    s->g = p; p += m + 2;
+    s->hb = p; p += m + 2;
+    s->yc = p; p += m + 2;
+    s->stop = reinterpret_cast<int *>(p);
+
+    // host tables: composed line stencils and the vertical band
+    std::vector<double> G0(nz), wxx, wyy, vb;
+    e = hipMemcpy(G0.data(), c->lev.G0, sizeof(double) * nz, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+    const int ns = 2 * N + 1;
+    composed_line(c->ops.wxy.data(), N, int(c->nx), wxx);
+    composed_line(c->ops.wxy.data() + N * ns, N, int(c->ny), wyy);
+    vertical_band(c->ops.dzb, G0, c->eos.grav, N, int(nz), vb);
+    if ((e = hipMemcpy(s->wxx, wxx.data(), sizeof(double) * N * W, hipMemcpyHostToDevice)) != hipSuccess) return e;
+    if ((e = hipMemcpy(s->wyy, wyy.data(), sizeof(double) * N * W, hipMemcpyHostToDevice)) != hipSuccess) return e;
+    if ((e = hipMemcpy(s->vb, vb.data(), sizeof(double) * nz * W, hipMemcpyHostToDevice)) != hipSuccess) return e;
+    if ((e = hipMemset(s->stop, 0, 2 * sizeof(int))) != hipSuccess) return e;
+    s->hH.assign(size_t(m + 1) * m, 0.0);
+    s->hg.assign(size_t(m + 1), 0.0);
+
+    // eigenvalue interval of S: power method from the fixed start vector
+    if (power_steps > 0) {
+        hipLaunchKernelGGL(k_start_vector, dim3(unsigned(s->nblk)), dim3(kTB), 0, c->stream, s->z, np);
+        if ((e = norm_dev(c, s->z, s->hb)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_normalize, dim3(unsigned(s->nblk)), dim3(kTB), 0, c->stream, s->z, s->z, s->hb, np,
+                           nullptr);
+        for (int it = 0; it < power_steps; ++it) {
+            if ((e = apply(c, axpy_args(s->z, s->w, 0.0, 1.0, 0.0, nullptr))) != hipSuccess) return e;
+            if ((e = norm_dev(c, s->w, s->hb)) != hipSuccess) return e;
+            hipLaunchKernelGGL(k_normalize, dim3(unsigned(s->nblk)), dim3(kTB), 0, c->stream, s->z, s->w, s->hb, np,
+                               nullptr);
+        }
+        double est = 0.0;
+        if ((e = hipMemcpyAsync(&est, s->hb, sizeof(double), hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+            return e;
+        if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+        s->lmin = 1.0;
+        s->lmax = 1.1 * est;
+    }
+    return hipGetLastError();
+}
+
+void imex3d_set_bounds(numa_ctx *c, double lmin, double lmax)
+{
+    c->imex->lmin = lmin;
+    c->imex->lmax = lmax;
+}
+
+hipError_t schur_apply(numa_ctx *c, const double *P, double *out)
+{
+    return apply(c, axpy_args(P, out, 0.0, 1.0, 0.0, nullptr));
+}
+
+hipError_t schur_rhs(numa_ctx *c, const double *y, double *b)
+{
+    return dispatch3(c->N, [&](auto n) { return rhs_kernel_launch<decltype(n)::value>(c, y, b); });
+}
+
+hipError_t pbno_apply(numa_ctx *c, const double *r, double *z) { return precondition(c, r, z); }
+
+// x = (I - lambda L)^-1 y (5 fields), out = x + d0 in0 + d1 in1.  out may be
+// y itself.  *iters: Arnoldi iterations; *converged: 0 if maxit was reached.
+hipError_t imex3d_solve(numa_ctx *c, const double *y, double *out, const double *in0, double d0, const double *in1,
+                        double d1, double tol, int *iters, int *converged)
+{
+    Imex3d &s = *c->imex;
+    const long np = s.np;
+    const int m = s.restart;
+    hipError_t e;
+    *iters = 0;
+    *converged = 0;
+    if ((e = schur_rhs(c, y, s.b)) != hipSuccess) return e;
+    double bnorm = 0.0;
+    if ((e = norm_host(c, s.b, &bnorm)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(s.x, 0, sizeof(double) * np, c->stream)) != hipSuccess) return e;
+    const double tolb = tol * bnorm;
+    double beta = bnorm;
+    const double *rvec = s.b;  // residual of x = 0
+    int total = 0;
+    const int chunk = 4;
+    while (true) {
+        if (beta <= tolb) {
+            *converged = 1;
+            break;
+        }
+        if (total >= s.maxit) break;
+        hipLaunchKernelGGL(k_scale, dim3(unsigned(s.nblk)), dim3(kTB), 0, c->stream, s.V, rvec, 1.0 / beta, np);
+        hipLaunchKernelGGL(k_cycle_init, dim3(1), dim3(1), 0, c->stream, s.g, m, beta, s.stop);
+        const int jmax = std::min(m, s.maxit - total);
+        int jdone = 0;
+        for (int j0 = 0; j0 < jmax; j0 += chunk) {
+            for (int j = j0; j < std::min(jmax, j0 + chunk); ++j) {
+                const double *vj = s.V + size_t(j) * np;
+                double *vn = s.V + size_t(j + 1) * np;
+                const double *zin = vj;
+                if (s.order >= 0) {
+                    if ((e = precondition(c, vj, s.z)) != hipSuccess) return e;
+                    zin = s.z;
+                }
+                // w = S z and the first Gram-Schmidt dots
+                ApplyArgs a = axpy_args(zin, s.w, 0.0, 1.0, 0.0, nullptr);
+                a.V = s.V;
+                a.nv = j + 1;
+                a.part = s.part;
+                a.stop = s.stop;
+                if ((e = apply(c, a)) != hipSuccess) return e;
+                hipLaunchKernelGGL(k_finish, dim3(unsigned(j + 1)), dim3(kTB), 0, c->stream, s.part, s.nblk, s.hb, 0,
+                                   s.H, m, j, 0, s.stop);
+                // first update with the second pass dots fused; second update with |w|^2
+                hipLaunchKernelGGL(k_cgs_update, dim3(unsigned(s.nblk)), dim3(kTB), 0, c->stream, s.w, s.V, j + 1,
+                                   s.hb, np, j + 1, s.part, s.nblk, s.stop);
+                hipLaunchKernelGGL(k_finish, dim3(unsigned(j + 1)), dim3(kTB), 0, c->stream, s.part, s.nblk, s.hb, 0,
+                                   s.H, m, j, 1, s.stop);
+                hipLaunchKernelGGL(k_cgs_update, dim3(unsigned(s.nblk)), dim3(kTB), 0, c->stream, s.w, s.V, j + 1,
+                                   s.hb, np, -1, s.part, s.nblk, s.stop);
+                hipLaunchKernelGGL(k_finish, dim3(1), dim3(kTB), 0, c->stream, s.part, s.nblk, s.hb, 1,
+                                   s.H + size_t(j + 1) * m, m, j, 0, s.stop);
+                hipLaunchKernelGGL(k_normalize, dim3(unsigned(s.nblk)), dim3(kTB), 0, c->stream, vn, s.w,
+                                   s.H + size_t(j + 1) * m + j, np, s.stop);
+                hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, c->stream, s.H, s.cs, s.sn, s.g, j, m, tolb, s.stop);
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+            }
+            int flags[2] = {0, 0};
+            if ((e = hipMemcpyAsync(flags, s.stop, sizeof(flags), hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+                return e;
+            if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+            jdone = flags[1];
+            if (flags[0]) break;
+        }
+        // x += M V y
+        if ((e = hipMemcpyAsync(s.hH.data(), s.H, sizeof(double) * s.hH.size(), hipMemcpyDeviceToHost, c->stream)) !=
+            hipSuccess)
+            return e;
+        if ((e = hipMemcpyAsync(s.hg.data(), s.g, sizeof(double) * s.hg.size(), hipMemcpyDeviceToHost, c->stream)) !=
+            hipSuccess)
+            return e;
+        if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+        upper_solve(s.hH, s.hg, m, jdone, s.hy);
+        if ((e = hipMemcpyAsync(s.yc, s.hy.data(), sizeof(double) * jdone, hipMemcpyHostToDevice, c->stream)) !=
+            hipSuccess)
+            return e;
+        if (s.order < 0) {
+            hipLaunchKernelGGL(k_combine, dim3(unsigned(s.nblk)), dim3(kTB), 0, c->stream, s.x, s.V, s.yc, jdone, np, 1);
+        } else {
+            hipLaunchKernelGGL(k_combine, dim3(unsigned(s.nblk)), dim3(kTB), 0, c->stream, s.w, s.V, s.yc, jdone, np, 0);
+            if ((e = precondition(c, s.w, s.z)) != hipSuccess) return e;
+            if ((e = lincomb(c, s.x, s.x, 1.0, s.z, 1.0, nullptr, 0.0, np)) != hipSuccess) return e;
+        }
+        total += jdone;
+        // true residual
+        if ((e = apply(c, axpy_args(s.x, s.r, 0.0, -1.0, 1.0, s.b))) != hipSuccess) return e;
+        if ((e = norm_host(c, s.r, &beta)) != hipSuccess) return e;
+        rvec = s.r;
+    }
+    *iters = total;
+    if (rvec == s.b) {  // x = 0: r = b
+        if ((e = hipMemcpyAsync(s.r, s.b, sizeof(double) * np, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
+            return e;
+    }
+    ExtractArgs a{};
+    a.y = y;
+    a.P = s.x;
+    a.r = s.r;
+    a.out = out;
+    a.in0 = in0;
+    a.d0 = d0;
+    a.in1 = in1;
+    a.d1 = d1;
+    a.lam = s.lambda;
+    a.g = c->eos.grav;
+    return dispatch3(c->N, [&](auto n) { return extract_launch<decltype(n)::value>(c, a); });
+}
+
+// One 3D-IMEX ARK2 step in the shifted-stage form of the HEVI step with L in
+// place of L_V: Q2 = q + solve(dt a21 R1); Q3 = solve(E3 + c31 q + c32 Q2)
+// - c31 q - c32 Q2; q' = ACC + dt b3 R(Q3).
+hipError_t imex3d_step(numa_ctx *c, double *q, double dt, double tol, int *iters, int *converged)
+{
+    Imex3d &s = *c->imex;
+    const long n5 = 5 * s.np;
+    const double s2 = std::sqrt(2.0), al = (3.0 + 2.0 * s2) / 6.0, ad = 1.0 - 1.0 / s2;
+    const double a21 = 2.0 - s2, a31 = 1.0 - al, a32 = al, b1 = 1.0 / (2.0 * s2), b2 = b1, b3 = ad;
+    const double c31 = (1.0 / (2.0 * s2) - a31) / ad, c32 = (1.0 / (2.0 * s2) - a32) / ad;
+    hipError_t e;
+    int it2 = 0, it3 = 0, cv2 = 0, cv3 = 0;
+    *iters = 0;
+    *converged = 0;
+    if ((e = launch_rhs_plain(c, q, s.R1)) != hipSuccess) return e;
+    if ((e = lincomb(c, s.Q2, s.R1, dt * a21, nullptr, 0.0, nullptr, 0.0, n5)) != hipSuccess) return e;
+    if ((e = imex3d_solve(c, s.Q2, s.Q2, q, 1.0, nullptr, 0.0, tol, &it2, &cv2)) != hipSuccess) return e;
+    if ((e = launch_rhs_two(c, s.Q2, q, s.R1, s.E3, s.ACC, dt * a31, dt * a32, dt * b1, dt * b2)) != hipSuccess)
+        return e;
+    if ((e = lincomb(c, s.E3, s.E3, 1.0, q, c31, s.Q2, c32, n5)) != hipSuccess) return e;
+    if ((e = imex3d_solve(c, s.E3, s.E3, q, -c31, s.Q2, -c32, tol, &it3, &cv3)) != hipSuccess) return e;
+    if ((e = launch_rhs_final(c, s.E3, s.ACC, q, dt * b3)) != hipSuccess) return e;
+    *iters = it2 + it3;
+    *converged = cv2 && cv3;
+    return hipSuccess;
+}
+
+void imex3d_info(const numa_ctx *c, double *dt, double *lmin, double *lmax)
+{
+    *dt = c->imex->dt;
+    *lmin = c->imex->lmin;
+    *lmax = c->imex->lmax;
+}
+
+}  // namespace numa

@@ -1088,6 +1088,35 @@ hipError_t launch_rhs_plain(numa_ctx *c, const double *q, double *R)
     return dispatch(c->N, [&](auto n) { return rhs_launch<decltype(n)::value, EPI_R, false>(c, p); });
 }
 
+// R(Q) with the stage epilogue out0 = e0 + k01 e1 + k02 R, out1 = e0 + k11 e1 + k12 R
+// (all five fields of Q given)
+hipError_t launch_rhs_two(numa_ctx *c, const double *Q, const double *e0, const double *e1, double *out0,
+                          double *out1, double k01, double k02, double k11, double k12)
+{
+    RhsParams p{};
+    set_fields(p.a, Q, c->np);
+    p.out0 = out0;
+    p.out1 = out1;
+    p.e0 = e0;
+    p.e1 = e1;
+    p.fs = c->np;
+    p.k01 = k01; p.k02 = k02;
+    p.k11 = k11; p.k12 = k12;
+    return dispatch(c->N, [&](auto n) { return rhs_launch<decltype(n)::value, EPI_TWO, false>(c, p); });
+}
+
+// out = e0 + k R(Q), non-finite values flagged
+hipError_t launch_rhs_final(numa_ctx *c, const double *Q, const double *e0, double *out, double k)
+{
+    RhsParams p{};
+    set_fields(p.a, Q, c->np);
+    p.out0 = out;
+    p.e0 = e0;
+    p.fs = c->np;
+    p.k02 = k;
+    return dispatch(c->N, [&](auto n) { return rhs_launch<decltype(n)::value, EPI_FINAL, false>(c, p); });
+}
+
 hipError_t launch_solve_plain(numa_ctx *c, const double *y, double *x)
 {
     const long np = c->np;

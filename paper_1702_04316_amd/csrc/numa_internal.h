@@ -41,6 +41,8 @@ struct DevLevels {
 constexpr int kBinomTerms = 10;
 constexpr double kBinomMaxX = 1.0 / 32.0;
 
+struct Imex3d;  // 3D-IMEX solver state (imex3d.hip)
+
 struct EOS {
     double theta0, p00, rgas, gamma, grav;
     double binom[kBinomTerms];  // C(gamma, k), k = 1..kBinomTerms
@@ -67,6 +69,7 @@ struct numa_ctx {
     int factored = 0;
     double dt_factored = 0, lambda = 0;
     int rhs_zchunk = 0;            // z elements per RHS workgroup (0 = auto)
+    numa::Imex3d *imex = nullptr;  // 3D-IMEX solver (numa_imex3d_setup)
     std::string err;
 };
 
@@ -91,6 +94,9 @@ hipError_t launch_background(numa_ctx *c);
 hipError_t launch_factor(numa_ctx *c, double lambda);
 hipError_t launch_rhs_plain(numa_ctx *c, const double *q, double *R);
 hipError_t launch_solve_plain(numa_ctx *c, const double *y, double *x);
+hipError_t launch_rhs_two(numa_ctx *c, const double *Q, const double *e0, const double *e1, double *out0,
+                          double *out1, double k01, double k02, double k11, double k12);
+hipError_t launch_rhs_final(numa_ctx *c, const double *Q, const double *e0, double *out, double k);
 hipError_t launch_hevi_step(numa_ctx *c, double *q, double dt, hipEvent_t *ev = nullptr);
 hipError_t launch_hevi_step_mixed(numa_ctx *c, double *q, double dt, hipEvent_t *ev = nullptr);
 hipError_t prepare_step(numa_ctx *c, bool mixed);
@@ -98,5 +104,17 @@ hipError_t autotune_rhs_zchunk(numa_ctx *c, const double *state, int reps, int *
 // abi.cpp: NUMA_OK or the error code (message recorded in the context)
 int ensure_mixed_buffers(numa_ctx *c, const char *who);
 int step_preconditions(numa_ctx *c, double dt, const char *who);
+
+// imex3d.hip: the 3D-IMEX Schur-complement GMRES solver
+hipError_t imex3d_setup(numa_ctx *c, double dt, int restart, int order, int power_steps, int maxit);
+void imex3d_free(numa_ctx *c);
+void imex3d_set_bounds(numa_ctx *c, double lmin, double lmax);
+void imex3d_info(const numa_ctx *c, double *dt, double *lmin, double *lmax);
+hipError_t schur_apply(numa_ctx *c, const double *P, double *out);
+hipError_t schur_rhs(numa_ctx *c, const double *y, double *b);
+hipError_t pbno_apply(numa_ctx *c, const double *r, double *z);
+hipError_t imex3d_solve(numa_ctx *c, const double *y, double *out, const double *in0, double d0, const double *in1,
+                        double d1, double tol, int *iters, int *converged);
+hipError_t imex3d_step(numa_ctx *c, double *q, double dt, double tol, int *iters, int *converged);
 
 }  // namespace numa

@@ -89,6 +89,13 @@ def load():
     lib.numa_profile_steps_mixed.argtypes = [vp, vp, C.c_double, C.c_int32, C.POINTER(C.c_double)]
     lib.numa_rhs.argtypes = [vp, vp, vp]
     lib.numa_solve_columns.argtypes = [vp, vp, vp]
+    lib.numa_imex3d_setup.argtypes = [vp, C.c_double, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+    lib.numa_imex3d_bounds.argtypes = [vp, C.POINTER(C.c_double)]
+    lib.numa_imex3d_set_bounds.argtypes = [vp, C.c_double, C.c_double]
+    lib.numa_schur_apply.argtypes = [vp, vp, vp]
+    lib.numa_schur_rhs.argtypes = [vp, vp, vp]
+    lib.numa_pbno_apply.argtypes = [vp, vp, vp]
+    lib.numa_imex3d_solve.argtypes = [vp, vp, vp, C.c_double, C.POINTER(C.c_int32)]
     lib.numa_imex3d_step.argtypes = [vp, vp, C.c_double, C.c_double, C.POINTER(C.c_int32)]
     lib.numa_check.argtypes = [vp]
     lib.numa_destroy.argtypes = [vp]
@@ -101,7 +108,9 @@ def load():
                  "numa_hevi_step", "numa_profile_steps", "numa_hevi_step_mixed", "numa_profile_steps_mixed",
                  "numa_rhs", "numa_solve_columns", "numa_imex3d_step", "numa_check", "numa_destroy",
                  "numa_lgl_basis", "numa_line_operators", "numa_ensemble_create", "numa_ensemble_step",
-                 "numa_ensemble_sync", "numa_ensemble_zchunks", "numa_ensemble_destroy"):
+                 "numa_ensemble_sync", "numa_ensemble_zchunks", "numa_ensemble_destroy", "numa_imex3d_setup",
+                 "numa_imex3d_bounds", "numa_imex3d_set_bounds", "numa_schur_apply", "numa_schur_rhs",
+                 "numa_pbno_apply", "numa_imex3d_solve"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -268,6 +277,39 @@ def solve_columns(ctx, y_ptr, x_ptr):
     return _check(load().numa_solve_columns(ctx, C.c_void_p(y_ptr), C.c_void_p(x_ptr)), ctx)
 
 
+def imex3d_setup(ctx, dt, restart=30, pbno_order=1, power_steps=30, maxit=5000):
+    return _check(load().numa_imex3d_setup(ctx, float(dt), int(restart), int(pbno_order), int(power_steps),
+                                           int(maxit)), ctx)
+
+
+def imex3d_bounds(ctx):
+    out = (C.c_double * 2)()
+    _check(load().numa_imex3d_bounds(ctx, out), ctx)
+    return float(out[0]), float(out[1])
+
+
+def imex3d_set_bounds(ctx, lmin, lmax):
+    return _check(load().numa_imex3d_set_bounds(ctx, float(lmin), float(lmax)), ctx)
+
+
+def schur_apply(ctx, p_ptr, out_ptr):
+    return _check(load().numa_schur_apply(ctx, C.c_void_p(p_ptr), C.c_void_p(out_ptr)), ctx)
+
+
+def schur_rhs(ctx, y_ptr, b_ptr):
+    return _check(load().numa_schur_rhs(ctx, C.c_void_p(y_ptr), C.c_void_p(b_ptr)), ctx)
+
+
+def pbno_apply(ctx, r_ptr, z_ptr):
+    return _check(load().numa_pbno_apply(ctx, C.c_void_p(r_ptr), C.c_void_p(z_ptr)), ctx)
+
+
+def imex3d_solve(ctx, y_ptr, x_ptr, tol):
+    it = C.c_int32(0)
+    _check(load().numa_imex3d_solve(ctx, C.c_void_p(y_ptr), C.c_void_p(x_ptr), float(tol), C.byref(it)), ctx)
+    return it.value
+
+
 def imex3d_step(ctx, state_ptr, dt, tol):
     it = C.c_int32(0)
     _check(load().numa_imex3d_step(ctx, C.c_void_p(state_ptr), float(dt), float(tol), C.byref(it)), ctx)
@@ -366,6 +408,51 @@ class Context:
         out = torch.empty_like(y) if out is None else out
         self._check_state(out)
         solve_columns(self.ctx, y.data_ptr(), out.data_ptr())
+        return out
+
+    # --- 3D-IMEX -------------------------------------------------------------
+    def imex3d_setup(self, dt, restart=30, pbno_order=1, power_steps=30, maxit=5000):
+        imex3d_setup(self.ctx, dt, restart, pbno_order, power_steps, maxit)
+        self.dt3d = float(dt)
+        return imex3d_bounds(self.ctx)
+
+    def imex3d_step(self, state, tol, nsteps=1):
+        """nsteps 3D-IMEX steps in place; returns the GMRES iterations."""
+        self._check_state(state)
+        return sum(imex3d_step(self.ctx, state.data_ptr(), self.dt3d, tol) for _ in range(nsteps))
+
+    def imex3d_solve(self, y, tol, out=None):
+        import torch
+        self._check_state(y)
+        out = torch.empty_like(y) if out is None else out
+        self._check_state(out)
+        it = imex3d_solve(self.ctx, y.data_ptr(), out.data_ptr(), tol)
+        return out, it
+
+    def _scalar(self, t):
+        import torch
+        assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
+        assert tuple(t.shape) == self.shape[1:], (tuple(t.shape), self.shape)
+
+    def schur_apply(self, P):
+        import torch
+        self._scalar(P)
+        out = torch.empty_like(P)
+        schur_apply(self.ctx, P.data_ptr(), out.data_ptr())
+        return out
+
+    def schur_rhs(self, y):
+        import torch
+        self._check_state(y)
+        out = torch.empty(self.shape[1:], dtype=torch.float64, device=y.device)
+        schur_rhs(self.ctx, y.data_ptr(), out.data_ptr())
+        return out
+
+    def pbno_apply(self, r):
+        import torch
+        self._scalar(r)
+        out = torch.empty_like(r)
+        pbno_apply(self.ctx, r.data_ptr(), out.data_ptr())
         return out
 
     def check(self):

@@ -336,3 +336,25 @@ def ensemble_domains(seed=4, n=16):
         out.append(Workload(f"ens{d}_{ne}x{ne}x{nez}_N{N}", g, dt, 50, 100 * seed + d, nb, (0.1, 2.0),
                             (500.0, 2000.0), stretch=s, wind=(speed * np.cos(ang), speed * np.sin(ang))))
     return out
+
+
+IMEX3D_COURANT = 15.0
+IMEX3D_TOL = 1e-8
+
+
+def box_imex3d(size="full"):
+    """Workloads of the 3D-IMEX step: N=5, elements of 625 x 625 x 1250 m
+    (the 20 x 20 x 10 km box in 32 x 32 x 8 elements, literal, no
+    stretching); dt at acoustic Courant number 15 on the smallest node
+    spacing of any direction (here horizontal, so the horizontal acoustics
+    are stiff as well, which HEVI cannot step).  'full': 32x32x8 elements
+    (160x160x41 = 1,049,600 unique nodes), eight theta' bumps 0.1-2 K of
+    radius 0.5-2 km; 'small': 4x4x2 elements (20x20x11 nodes), one 0.5 K
+    bump of radius 500 m, for parity with the oracle."""
+    ne, nez = (32, 8) if size == "full" else (4, 2)
+    hx, hz = 20000.0 / 32, 10000.0 / 8
+    g = Grid(hx * ne, hx * ne, hz * nez, ne, ne, nez, 5)
+    dt = min(dt_for_courant(g, IMEX3D_COURANT, "x"), dt_for_courant(g, IMEX3D_COURANT, "z"))
+    if size == "full":
+        return Workload("box32x32x8_N5_3d", g, dt, 10, 5, 8, (0.1, 2.0), (500.0, 2000.0))
+    return Workload("box4x4x2_N5_3d", g, dt, 10, 5, 1, (0.5, 0.5), (500.0, 500.0))
