@@ -169,6 +169,62 @@ def batched_ensemble(numa, torch, steps=50):
     return out
 
 
+def imex3d(numa, torch, steps=10, order=6, restart=30):
+    """The 3D-IMEX step (all acoustics implicit, Schur-complement GMRES with
+    PBNO) on 32x32x8 elements, N=5, at acoustic Courant number 15 in every
+    direction, tol 1e-8: throughput, simulated seconds per wall second,
+    GMRES iterations per step, the same with PBNO order 1 and without a
+    preconditioner, and the Schur operator kernel against the HBM roofline
+    (HIP events on the context's stream around 50 launches)."""
+    from paper_1702_04316_amd import workloads as W
+    wl = W.box_imex3d("full")
+    g = wl.grid
+    ctx = numa.Context(g, wl.background)
+    q0 = torch.from_numpy(W.make_initial_state(wl)).to("cuda")
+    out = {"entry": "numa_imex3d_step", "workload": f"{wl.name}: 32x32x8 elements, LGL N=5, "
+           f"{g.nx}x{g.ny}x{g.nz} unique nodes, acoustic Courant 15 on the finest spacing, tol {W.IMEX3D_TOL}",
+           "dt_s": wl.dt, "unique_nodes": g.n_unique}
+    runs = {}
+    for name, p, n in (("pbno%d" % order, order, steps), ("pbno1", 1, 3), ("none", -1, 3)):
+        t0 = time.perf_counter()
+        bd = ctx.imex3d_setup(wl.dt, restart=restart, pbno_order=p, power_steps=30, maxit=5000)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        q = q0.clone()
+        ctx.imex3d_step(q, W.IMEX3D_TOL)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = [ctx.imex3d_step(q, W.IMEX3D_TOL) for _ in range(n)]
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / n
+        ctx.check()
+        runs[name] = {"pbno_order": p, "restart": restart, "ms_per_step": 1e3 * t,
+                      "value": 5 * g.n_unique / t, "sim_s_per_wall_s": wl.dt / t,
+                      "gmres_iters_per_step": sum(its) / n, "setup_s": t_setup, "interval": list(bd)}
+    out["runs"] = runs
+    best = runs["pbno%d" % order]
+    out.update({"value": best["value"], "unit": "DOF-steps/s", "ms_per_step": best["ms_per_step"],
+                "sim_s_per_wall_s": best["sim_s_per_wall_s"],
+                "pbno_speedup_vs_none": runs["none"]["ms_per_step"] / best["ms_per_step"]})
+    # Schur operator: 16 algorithmic bytes per node (read P, write S P)
+    P = torch.randn(g.shape[1:], dtype=torch.float64, device="cuda")
+    ctx.schur_apply(P)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(50):
+        ctx.schur_apply(P)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 50
+    achieved = 16 * g.n_unique / (ms * 1e-3) / 1e9
+    out["roofline"] = {"bound": "hbm", "kernel": "k_schur_apply", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                       "algorithmic_bytes_per_launch": 16 * g.n_unique, "avg_launch_ms": ms}
+    ctx.close()
+    return out
+
+
 def copy_probe(nbytes=1 << 30, reps=10):
     """A plain device-to-device copy of known size: the achievable HBM rate,
     and the calibration program for the FETCH_SIZE/WRITE_SIZE counters."""
@@ -196,6 +252,8 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble measurement")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision-form measurement")
     ap.add_argument("--copy-probe", action="store_true", help="only time a plain 1 GiB device copy")
+    ap.add_argument("--no-imex3d", action="store_true", help="skip the 3D-IMEX measurement")
+    ap.add_argument("--imex3d-only", action="store_true", help="only run the 3D-IMEX measurement (printed alone)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -210,6 +268,9 @@ def main():
     from paper_1702_04316_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.imex3d_only:
+        print(json.dumps(imex3d(numa, torch)), flush=True)
+        return
     wl = W.box_large("R1")
     g = wl.grid
     ctx = numa.Context(g, wl.background)
@@ -281,6 +342,8 @@ def main():
         out["precision_form"] = precision_form(numa, torch, ctx, wl, args, t)
     if not args.no_ensemble:
         out["batched_ensemble"] = batched_ensemble(numa, torch)
+    if not args.no_imex3d:
+        out["imex3d"] = imex3d(numa, torch)
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline()

@@ -235,7 +235,7 @@ int numa_solve_columns(numa_ctx *c, const double *y, double *x);
  * estimates the interval: lmin = 1, lmax = 1.1 |S^k v|/|S^(k-1) v| after
  * k = power_steps power steps from v_I = frac(I * 2654435769 / 2^32) - 1/2
  * (power_steps = 0 keeps [1, 2]; set it with numa_imex3d_set_bounds).
- * restart 1..200, pbno_order -1..16, maxit >= 1 (Arnoldi iterations per
+ * restart 1..63, pbno_order -1..16, maxit >= 1 (Arnoldi iterations per
  * solve).  Calling it again replaces the previous state.  Synchronous.
  * Errors: NUMA_E_ARG, NUMA_E_NOMEM, NUMA_E_HIP.
  * numa_imex3d_bounds: out[2] (host) = {lmin, lmax}.  numa_imex3d_set_bounds:

@@ -338,7 +338,7 @@ int numa_imex3d_setup(numa_ctx *c, double dt, int32_t restart, int32_t pbno_orde
                       int32_t maxit)
 {
     if (!c) return NUMA_E_ARG;
-    if (!finite_pos(dt) || restart < 1 || restart > 200 || pbno_order < -1 || pbno_order > 16 || power_steps < 0 ||
+    if (!finite_pos(dt) || restart < 1 || restart > 63 || pbno_order < -1 || pbno_order > 16 || power_steps < 0 ||
         power_steps > 1000 || maxit < 1)
         return fail(c, NUMA_E_ARG, "numa_imex3d_setup: bad arguments");
     hipError_t e = numa::imex3d_setup(c, dt, restart, pbno_order, power_steps, maxit);

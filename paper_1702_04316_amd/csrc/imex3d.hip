@@ -21,7 +21,8 @@
 //
 // Kernels (one thread per node; node I = i + nx (j + ny k), i fastest):
 //   k_schur_apply   S applied to a field in one pass (composed x and y line
-//                   stencils of width 4N+1, the vertical band), with an
+//                   stencils of width 4N+1, the vertical band; x-z slabs
+//                   staged in LDS), with an
 //                   epilogue for residuals, the Chebyshev (PBNO) recurrence
 //                   and fused partial dot products against Krylov vectors
 //   k_schur_rhs     b from the 5-field y
@@ -47,6 +48,10 @@ constexpr int kTB = 256;  // threads per block of every kernel here
 
 inline long nblocks(long n) { return (n + kTB - 1) / kTB; }
 
+// The node kernels run on a 3D grid: blocks of 32 (i) x 8 (j) threads, one
+// plane k per blockIdx.z, so no thread divides to find its node.
+constexpr int kBX = 32, kBY = 8;
+
 __device__ inline int wrap(int i, int n)
 {
     while (i < 0) i += n;
@@ -54,18 +59,71 @@ __device__ inline int wrap(int i, int n)
     return i;
 }
 
+// one wrap is enough when the stencil reach is at most the line length
+template <bool ONE>
+__device__ inline int wrapx(int i, int n)
+{
+    if constexpr (ONE) {
+        i += i < 0 ? n : 0;
+        return i - (i >= n ? n : 0);
+    } else {
+        return wrap(i, n);
+    }
+}
+
+struct Node {
+    int i, j, k;
+    long I;
+    bool ok;
+};
+
+__device__ inline Node node_of(int nx, int ny)
+{
+    Node n;
+    n.i = blockIdx.x * kBX + threadIdx.x;
+    n.j = blockIdx.y * kBY + threadIdx.y;
+    n.k = blockIdx.z;
+    n.ok = n.i < nx && n.j < ny;
+    n.I = (long(n.k) * ny + n.j) * nx + n.i;
+    return n;
+}
+
+__device__ inline int tid_flat() { return threadIdx.y * kBX + threadIdx.x; }
+
 // Sum over the 256 threads of a block in a fixed order (wave shuffles, then
 // the four wave sums); every thread must call it.
 __device__ inline double block_sum(double v, double *sh)
 {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int ft = threadIdx.y * blockDim.x + threadIdx.x;
+    const int lane = ft & 63, wid = ft >> 6;
     if (lane == 0) sh[wid] = v;
     __syncthreads();
     const double t = (sh[0] + sh[1]) + (sh[2] + sh[3]);
     __syncthreads();
     return t;
+}
+
+// Block sums of nv values per thread (nv <= M) in one barrier: wave
+// shuffles, then thread v adds the four wave sums of value v in a fixed
+// order and stores it at out[v * stride].  Every thread must call it.
+template <int M>
+__device__ inline void block_sums(const double (&val)[M], int nv, double *sh /* [4][M] */, double *out, long stride)
+{
+    const int ft = threadIdx.y * blockDim.x + threadIdx.x;
+    const int lane = ft & 63, wid = ft >> 6;
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+        if (v < nv) {
+            double x = val[v];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+            if (lane == 0) sh[wid * M + v] = x;
+        }
+    }
+    __syncthreads();
+    if (ft < nv) out[long(ft) * stride] = (sh[ft] + sh[M + ft]) + (sh[2 * M + ft] + sh[3 * M + ft]);
 }
 
 struct OpTables {
@@ -103,86 +161,119 @@ struct ApplyArgs {
     double lam2;
 };
 
-template <int N>
-__device__ inline double schur_at(const OpTables &t, const double *in, double lam2, long I)
-{
-    constexpr int W = 4 * N + 1;
-    const int nx = t.nx, ny = t.ny, nz = t.nz;
-    const long plane = long(nx) * ny;
-    const int i = int(I % nx);
-    const long tt = I / nx;
-    const int j = int(tt % ny), k = int(tt / ny);
-    const long kb = long(k) * plane;
-    const double *wx = t.wxx + (i % N) * W, *wy = t.wyy + (j % N) * W, *vk = t.vb + long(k) * W;
-    const double *row = in + kb + long(j) * nx;
-    double sx = 0.0, sy = 0.0, sv = 0.0;
-#pragma unroll
-    for (int m = 0; m < W; ++m) sx += wx[m] * row[wrap(i - 2 * N + m, nx)];
-#pragma unroll
-    for (int m = 0; m < W; ++m) sy += wy[m] * in[kb + long(wrap(j - 2 * N + m, ny)) * nx + i];
-    const double *col = in + long(j) * nx + i;
-#pragma unroll
-    for (int m = 0; m < W; ++m) {
-        const int kk = k - 2 * N + m;
-        if (kk >= 0 && kk < nz) sv += vk[m] * col[long(kk) * plane];
-    }
-    return in[I] - lam2 * (sv + t.G0[k] * (sx + sy));
-}
+// k_schur_apply: a block owns 32 nodes along x by 8 levels of one y line.
+// The x-z slab it needs (the 32 x 8 nodes plus 2N on every side, zero
+// below the bottom and above the top) is staged in LDS with the x and
+// vertical coefficient rows, so the x and z taps of a node are LDS reads;
+// its y taps are coalesced global reads of neighbouring lines of the plane.
+constexpr int kAX = 32, kAK = 8;
 
 template <int N>
+struct ApplyTile {
+    static constexpr int W = 4 * N + 1;
+    static constexpr int R = kAK + 4 * N;  // slab rows (levels)
+    static constexpr int C = kAX + 4 * N;  // slab columns (x)
+};
+
+template <int N, bool ONE>
 __global__ __launch_bounds__(kTB) void k_schur_apply(OpTables t, ApplyArgs a)
 {
-    __shared__ double sh[4];
+    using G = ApplyTile<N>;
+    constexpr int W = G::W;
+    __shared__ double slab[G::R * G::C];
+    __shared__ double cx[N * W], cz[kAK * W];
+    __shared__ double sh[4 * 64];
     if (a.stop && *a.stop) return;
-    const long I = long(blockIdx.x) * kTB + threadIdx.x;
-    const bool ok = I < t.np;
+    const int nx = t.nx, ny = t.ny, nz = t.nz;
+    const int tx = threadIdx.x, tk = threadIdx.y, tid = tk * kAX + tx;
+    // XCD-aware order: workgroup w runs on XCD w mod 8; XCD x takes one
+    // contiguous range of logical blocks, ordered x tile, then level tile,
+    // then y line, so that the y neighbours and the slab halos a block
+    // reads were mostly fetched into the same XCD's L2 by its neighbours.
+    const int gx = (nx + kAX - 1) / kAX, gk = (nz + kAK - 1) / kAK;
+    const long nb = long(gx) * gk * ny, w = blockIdx.x;
+    const long per = nb / 8, rem = nb % 8, xcd = w % 8;
+    const long L = xcd * per + min(xcd, rem) + w / 8;
+    const int bx = int(L % gx), bk = int((L / gx) % gk), j = int(L / (long(gx) * gk));
+    const int i0 = bx * kAX, k0 = bk * kAK;
+    const long plane = long(nx) * ny;
+    const double *in = a.in;
+    for (int e = tid; e < G::R * G::C; e += kTB) {
+        const int r = e / G::C, cc = e - r * G::C;
+        // the slab is 32 + 4N wide whatever nx is: wrap as often as needed
+        const int k = k0 - 2 * N + r, i = wrap(i0 - 2 * N + cc, nx);
+        slab[e] = (k >= 0 && k < nz) ? in[long(k) * plane + long(j) * nx + i] : 0.0;
+    }
+    for (int e = tid; e < N * W; e += kTB) cx[e] = t.wxx[e];
+    for (int e = tid; e < kAK * W; e += kTB) {
+        const int k = k0 + e / W;
+        cz[e] = k < nz ? t.vb[long(k) * W + e % W] : 0.0;
+    }
+    __syncthreads();
+    const int i = i0 + tx, k = k0 + tk;
+    const bool ok = i < nx && k < nz;
+    const long I = long(k) * plane + long(j) * nx + i;
     double val = 0.0;
     if (ok) {
-        const double Sx = a.scale * schur_at<N>(t, a.in, a.lam2, I);
-        const double x = a.scale * a.in[I];
+        const double *wx = cx + (i % N) * W, *wz = cz + tk * W, *wy = t.wyy + (j % N) * W;
+        double sx = 0.0, sy = 0.0, sv = 0.0;
+#pragma unroll
+        for (int m = 0; m < W; ++m) sx += wx[m] * slab[(tk + 2 * N) * G::C + tx + m];
+#pragma unroll
+        for (int m = 0; m < W; ++m) sv += wz[m] * slab[(tk + m) * G::C + tx + 2 * N];
+        const double *rowk = in + long(k) * plane + i;
+#pragma unroll
+        for (int m = 0; m < W; ++m) sy += wy[m] * rowk[long(wrapx<ONE>(j - 2 * N + m, ny)) * nx];
+        const double center = slab[(tk + 2 * N) * G::C + tx + 2 * N];
+        const double Sx = a.scale * (center - a.lam2 * (sv + t.G0[k] * (sx + sy)));
+        const double x = a.scale * center;
         if (a.mode == AP_AXPY) {
             val = a.beta * Sx;
             if (a.alpha != 0.0) val += a.alpha * x;
             if (a.aux) val += a.gamma * a.aux[I];
             a.out[I] = val;
         } else {
-            const double res = (a.res_in ? a.res_in[I] : a.in[I]) - Sx;
+            const double res = (a.res_in ? a.res_in[I] : center) - Sx;
             const double dn = a.c1 * x + a.c2 * res;
             a.z_out[I] = (a.z_in ? a.z_in[I] : x) + dn;
             if (a.res_out) a.res_out[I] = res;
             if (a.d_out) a.d_out[I] = dn;
         }
     }
-    for (int v = 0; v < a.nv; ++v) {
-        const double s = block_sum(ok ? val * a.V[long(v) * t.np + I] : 0.0, sh);
-        if (threadIdx.x == 0) a.part[long(v) * a.nblk + blockIdx.x] = s;
+    // partial dots with the Krylov vectors, 8 per barrier (each group of 8
+    // has its own LDS area, so no barrier is needed between groups)
+    const long blk = L;
+    for (int v0 = 0; v0 < a.nv; v0 += 8) {
+        double q[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) q[u] = (ok && v0 + u < a.nv) ? val * a.V[long(v0 + u) * t.np + I] : 0.0;
+        block_sums<8>(q, min(8, a.nv - v0), sh + 4 * 8 * ((v0 / 8) & 7), a.part + long(v0) * a.nblk + blk, a.nblk);
     }
 }
 
 // first derivatives along x, y (line stencils) and z (column band) of f at I
-template <int N>
+template <int N, bool ONE>
 __device__ inline double dline(const double *w, const double *f, int i, int n, long base, long stride)
 {
     const int a = i % N, e0 = i - a;
     const double *c = w + a * (2 * N + 1);
     double s = 0.0;
 #pragma unroll
-    for (int m = 0; m <= 2 * N; ++m) s += c[m] * f[base + long(wrap(e0 - N + m, n)) * stride];
+    for (int m = 0; m <= 2 * N; ++m) s += c[m] * f[base + long(wrapx<ONE>(e0 - N + m, n)) * stride];
     return s;
 }
 
-template <int N>
+template <int N, bool ONE>
 __global__ __launch_bounds__(kTB) void k_schur_rhs(OpTables t, const double *y, double *b, double lam, double g)
 {
-    const long I = long(blockIdx.x) * kTB + threadIdx.x;
-    if (I >= t.np) return;
+    const Node n = node_of(t.nx, t.ny);
+    if (!n.ok) return;
+    const long I = n.I;
+    const int i = n.i, j = n.j, k = n.k;
     const long np = t.np, plane = long(t.nx) * t.ny;
-    const int i = int(I % t.nx);
-    const long tt = I / t.nx;
-    const int j = int(tt % t.ny), k = int(tt / t.ny);
     const double *yr = y, *yu = y + np, *yv = y + 2 * np, *yw = y + 3 * np, *yt = y + 4 * np;
-    const double dxu = dline<N>(t.wxy, yu, i, t.nx, long(k) * plane + long(j) * t.nx, 1);
-    const double dyv = dline<N>(t.wxy + N * (2 * N + 1), yv, j, t.ny, long(k) * plane + i, t.nx);
+    const double dxu = dline<N, ONE>(t.wxy, yu, i, t.nx, long(k) * plane + long(j) * t.nx, 1);
+    const double dyv = dline<N, ONE>(t.wxy + N * (2 * N + 1), yv, j, t.ny, long(k) * plane + i, t.nx);
     // Dz(rho0 w_a)
     const double *dz = t.dzb + long(k) * (2 * N + 1);
     const long col = long(j) * t.nx + i;
@@ -207,18 +298,17 @@ struct ExtractArgs {
     double lam, g;
 };
 
-template <int N>
+template <int N, bool ONE>
 __global__ __launch_bounds__(kTB) void k_schur_extract(OpTables t, ExtractArgs a)
 {
-    const long I = long(blockIdx.x) * kTB + threadIdx.x;
-    if (I >= t.np) return;
+    const Node n = node_of(t.nx, t.ny);
+    if (!n.ok) return;
+    const long I = n.I;
+    const int i = n.i, j = n.j, k = n.k;
     const long np = t.np, plane = long(t.nx) * t.ny;
-    const int i = int(I % t.nx);
-    const long tt = I / t.nx;
-    const int j = int(tt % t.ny), k = int(tt / t.ny);
     const double *P = a.P;
-    const double dxp = dline<N>(t.wxy, P, i, t.nx, long(k) * plane + long(j) * t.nx, 1);
-    const double dyp = dline<N>(t.wxy + N * (2 * N + 1), P, j, t.ny, long(k) * plane + i, t.nx);
+    const double dxp = dline<N, ONE>(t.wxy, P, i, t.nx, long(k) * plane + long(j) * t.nx, 1);
+    const double dyp = dline<N, ONE>(t.wxy + N * (2 * N + 1), P, j, t.ny, long(k) * plane + i, t.nx);
     const double *dz = t.dzb + long(k) * (2 * N + 1);
     const double *pc = P + long(j) * t.nx + i;
     double dzp = 0.0;
@@ -296,28 +386,37 @@ __global__ __launch_bounds__(kTB) void k_finish(const double *part, long nblk, d
 }
 
 // w -= sum_v h[v] V_v; then partial dots of the new w with V_0..V_{nvd-1}
-// (nvd < 0: the partial of |w|^2 alone)
+// (nvd < 0: the partial of |w|^2 alone).  The nv <= M vectors are read once
+// into registers for both.
+template <int M>
 __global__ __launch_bounds__(kTB) void k_cgs_update(double *w, const double *V, int nv, const double *h, long n,
                                                     int nvd, double *part, long nblk, const int *stop)
 {
-    __shared__ double sh[4];
+    __shared__ double sh[4 * M];
     if (stop && *stop) return;
     const long I = long(blockIdx.x) * kTB + threadIdx.x;
     const bool ok = I < n;
+    double vv[M];
     double wv = 0.0;
     if (ok) {
         wv = w[I];
-        for (int v = 0; v < nv; ++v) wv -= h[v] * V[long(v) * n + I];
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            vv[v] = v < nv ? V[long(v) * n + I] : 0.0;
+            if (v < nv) wv -= h[v] * vv[v];
+        }
         w[I] = wv;
+    } else {
+#pragma unroll
+        for (int v = 0; v < M; ++v) vv[v] = 0.0;
     }
     if (nvd < 0) {
-        const double s = block_sum(wv * wv, sh);
-        if (threadIdx.x == 0) part[blockIdx.x] = s;
+        double q[1] = {wv * wv};
+        block_sums<1>(q, 1, sh, part + blockIdx.x, nblk);
     } else {
-        for (int v = 0; v < nvd; ++v) {
-            const double s = block_sum(ok ? wv * V[long(v) * n + I] : 0.0, sh);
-            if (threadIdx.x == 0) part[long(v) * nblk + blockIdx.x] = s;
-        }
+#pragma unroll
+        for (int v = 0; v < M; ++v) vv[v] *= wv;
+        block_sums<M>(vv, nvd, sh, part + blockIdx.x, nblk);
     }
 }
 
@@ -413,7 +512,7 @@ hipError_t dispatch3(int N, F &&f)
 struct Imex3d {
     int restart = 0, order = -1, maxit = 0, power_steps = 0;
     double dt = 0, lambda = 0, lmin = 1, lmax = 2;
-    long np = 0, nblk = 0;
+    long np = 0, nblk = 0, nblk3 = 0;  // blocks of the 1D vector kernels and of the apply grid
     void *block = nullptr;  // one allocation for everything below
     double *wxx = nullptr, *wyy = nullptr, *vb = nullptr;
     double *V = nullptr;                                   // (restart+1) np
@@ -503,17 +602,45 @@ void vertical_band(const std::vector<double> &dzb, const std::vector<double> &G0
         }
 }
 
+dim3 node_grid(const numa_ctx *c)
+{
+    return dim3(unsigned((c->nx + kBX - 1) / kBX), unsigned((c->ny + kBY - 1) / kBY), unsigned(c->nz));
+}
+
+long node_grid_blocks(const numa_ctx *c)
+{
+    const dim3 g = node_grid(c);
+    return long(g.x) * g.y * g.z;
+}
+
+// the single-wrap form needs the widest stencil (2N each side) within a line
+bool one_wrap(const numa_ctx *c) { return c->nx >= 2 * c->N && c->ny >= 2 * c->N; }
+
+dim3 apply_grid(const numa_ctx *c)
+{
+    return dim3(unsigned(((c->nx + kAX - 1) / kAX) * c->ny * ((c->nz + kAK - 1) / kAK)));
+}
+
+long apply_grid_blocks(const numa_ctx *c)
+{
+    const dim3 g = apply_grid(c);
+    return long(g.x) * g.y * g.z;
+}
+
 template <int N>
 hipError_t apply_launch(numa_ctx *c, const ApplyArgs &a)
 {
-    hipLaunchKernelGGL((k_schur_apply<N>), dim3(unsigned(nblocks(c->np))), dim3(kTB), 0, c->stream, op_tables(c), a);
+    if (one_wrap(c))
+        hipLaunchKernelGGL((k_schur_apply<N, true>), apply_grid(c), dim3(kAX, kAK), 0, c->stream, op_tables(c), a);
+    else
+        hipLaunchKernelGGL((k_schur_apply<N, false>), apply_grid(c), dim3(kAX, kAK), 0, c->stream, op_tables(c), a);
     return hipGetLastError();
 }
 
 hipError_t apply(numa_ctx *c, ApplyArgs a)
 {
     a.lam2 = c->imex->lambda * c->imex->lambda;
-    a.nblk = c->imex->nblk;
+    a.nblk = c->imex->nblk3;
     return dispatch3(c->N, [&](auto n) { return apply_launch<decltype(n)::value>(c, a); });
 }
 
@@ -596,15 +723,38 @@ hipError_t precondition(numa_ctx *c, const double *src, double *dst)
 template <int N>
 hipError_t rhs_kernel_launch(numa_ctx *c, const double *y, double *b)
 {
-    hipLaunchKernelGGL((k_schur_rhs<N>), dim3(unsigned(nblocks(c->np))), dim3(kTB), 0, c->stream, op_tables(c), y, b,
-                       c->imex->lambda, c->eos.grav);
+    const double lam = c->imex->lambda, g = c->eos.grav;
+    if (one_wrap(c))
+        hipLaunchKernelGGL((k_schur_rhs<N, true>), node_grid(c), dim3(kBX, kBY), 0, c->stream, op_tables(c), y, b, lam, g);
+    else
+        hipLaunchKernelGGL((k_schur_rhs<N, false>), node_grid(c), dim3(kBX, kBY), 0, c->stream, op_tables(c), y, b, lam,
+                           g);
     return hipGetLastError();
 }
 
 template <int N>
 hipError_t extract_launch(numa_ctx *c, const ExtractArgs &a)
 {
-    hipLaunchKernelGGL((k_schur_extract<N>), dim3(unsigned(nblocks(c->np))), dim3(kTB), 0, c->stream, op_tables(c), a);
+    if (one_wrap(c))
+        hipLaunchKernelGGL((k_schur_extract<N, true>), node_grid(c), dim3(kBX, kBY), 0, c->stream, op_tables(c), a);
+    else
+        hipLaunchKernelGGL((k_schur_extract<N, false>), node_grid(c), dim3(kBX, kBY), 0, c->stream, op_tables(c), a);
+    return hipGetLastError();
+}
+
+// w -= sum of the nv vectors times hb, with the fused partial dots (nvd)
+hipError_t cgs_update(numa_ctx *c, int nv, int nvd)
+{
+    Imex3d &s = *c->imex;
+    const dim3 g(unsigned(s.nblk)), b(kTB);
+    if (nv <= 8)
+        hipLaunchKernelGGL(k_cgs_update<8>, g, b, 0, c->stream, s.w, s.V, nv, s.hb, s.np, nvd, s.part, s.nblk, s.stop);
+    else if (nv <= 16)
+        hipLaunchKernelGGL(k_cgs_update<16>, g, b, 0, c->stream, s.w, s.V, nv, s.hb, s.np, nvd, s.part, s.nblk, s.stop);
+    else if (nv <= 32)
+        hipLaunchKernelGGL(k_cgs_update<32>, g, b, 0, c->stream, s.w, s.V, nv, s.hb, s.np, nvd, s.part, s.nblk, s.stop);
+    else
+        hipLaunchKernelGGL(k_cgs_update<64>, g, b, 0, c->stream, s.w, s.V, nv, s.hb, s.np, nvd, s.part, s.nblk, s.stop);
     return hipGetLastError();
 }
 
@@ -644,11 +794,13 @@ hipError_t imex3d_setup(numa_ctx *c, double dt, int restart, int order, int powe
     s->lambda = (1.0 - 1.0 / std::sqrt(2.0)) * dt;
     s->np = np;
     s->nblk = nblocks(np);
+    s->nblk3 = apply_grid_blocks(c);
+    const long npart = std::max(s->nblk, s->nblk3);
     const int m = restart;
     // sizes in doubles
     const size_t n_tab = size_t(2 * N * W + nz * W);
     const size_t n_vec = size_t(m + 1) * np + 8 * size_t(np) + 20 * size_t(np);
-    const size_t n_small = size_t(m + 1) * s->nblk + size_t(m + 1) * m + 4 * size_t(m + 2) + size_t(m + 2);
+    const size_t n_small = size_t(m + 1) * npart + size_t(m + 1) * m + 4 * size_t(m + 2) + size_t(m + 2);
     const size_t total = n_tab + n_vec + n_small + 64;
     hipError_t e = hipMalloc(&s->block, total * sizeof(double) + 64);
     if (e != hipSuccess) {
@@ -672,7 +824,7 @@ hipError_t imex3d_setup(numa_ctx *c, double dt, int restart, int order, int powe
     s->Q2 = p; p += 5 * np;
     s->E3 = p; p += 5 * np;
     s->ACC = p; p += 5 * np;
-    s->part = p; p += size_t(m + 1) * s->nblk;
+    s->part = p; p += size_t(m + 1) * npart;
     s->H = p; p += size_t(m + 1) * m;
     s->cs = p; p += m + 2;
     s->sn = p; p += m + 2;
@@ -782,15 +934,13 @@ hipError_t imex3d_solve(numa_ctx *c, const double *y, double *out, const double 
                 a.part = s.part;
                 a.stop = s.stop;
                 if ((e = apply(c, a)) != hipSuccess) return e;
-                hipLaunchKernelGGL(k_finish, dim3(unsigned(j + 1)), dim3(kTB), 0, c->stream, s.part, s.nblk, s.hb, 0,
+                hipLaunchKernelGGL(k_finish, dim3(unsigned(j + 1)), dim3(kTB), 0, c->stream, s.part, s.nblk3, s.hb, 0,
                                    s.H, m, j, 0, s.stop);
                 // first update with the second pass dots fused; second update with |w|^2
-                hipLaunchKernelGGL(k_cgs_update, dim3(unsigned(s.nblk)), dim3(kTB), 0, c->stream, s.w, s.V, j + 1,
-                                   s.hb, np, j + 1, s.part, s.nblk, s.stop);
+                if ((e = cgs_update(c, j + 1, j + 1)) != hipSuccess) return e;
                 hipLaunchKernelGGL(k_finish, dim3(unsigned(j + 1)), dim3(kTB), 0, c->stream, s.part, s.nblk, s.hb, 0,
                                    s.H, m, j, 1, s.stop);
-                hipLaunchKernelGGL(k_cgs_update, dim3(unsigned(s.nblk)), dim3(kTB), 0, c->stream, s.w, s.V, j + 1,
-                                   s.hb, np, -1, s.part, s.nblk, s.stop);
+                if ((e = cgs_update(c, j + 1, -1)) != hipSuccess) return e;
                 hipLaunchKernelGGL(k_finish, dim3(1), dim3(kTB), 0, c->stream, s.part, s.nblk, s.hb, 1,
                                    s.H + size_t(j + 1) * m, m, j, 0, s.stop);
                 hipLaunchKernelGGL(k_normalize, dim3(unsigned(s.nblk)), dim3(kTB), 0, c->stream, vn, s.w,
