@@ -675,16 +675,19 @@ static double dot_n(const double *a, const double *b, long n)
  * residual |b - A x| reaches tol |b|.  *iters counts Arnoldi iterations. */
 typedef int (*orc_op_fn)(orc_ctx *c, const void *arg, const double *in, double *out);
 
-static int gmres(orc_ctx *c, long n, orc_op_fn A, const void *aarg, orc_op_fn M, const void *marg,
-                 const double *b, double *x, double tol, int m, int maxit, int *iters)
+static int gmres_impl(orc_ctx *c, long n, orc_op_fn A, const void *aarg, orc_op_fn M, const void *marg,
+                      const double *b, double *x, double tol, int m, int maxit, int flexible, int *iters)
 {
     int total = 0, rc = 0, converged = 0;
+    /* flexible: keep z_j = M v_j and update x with them (M may change with
+     * its argument, as a nonlinear preconditioner does) */
+    double *Z = flexible ? (double *)malloc(sizeof(double) * (size_t)m * n) : NULL;
     double *V = (double *)malloc(sizeof(double) * (size_t)(m + 1) * n);
     double *w = (double *)malloc(sizeof(double) * n), *z = (double *)malloc(sizeof(double) * n);
     double *H = (double *)calloc((size_t)(m + 1) * m, sizeof(double));
     double *cs = (double *)malloc(sizeof(double) * m), *sn = (double *)malloc(sizeof(double) * m);
     double *g = (double *)malloc(sizeof(double) * (m + 1)), *yv = (double *)malloc(sizeof(double) * m);
-    if (!V || !w || !z || !H || !cs || !sn || !g || !yv) rc = -5;
+    if (!V || !w || !z || !H || !cs || !sn || !g || !yv || (flexible && !Z)) rc = -5;
     double bnorm = rc ? 0.0 : sqrt(dot_n(b, b, n));
     if (!rc) memset(x, 0, sizeof(double) * n);
     while (!rc) {
@@ -701,8 +704,9 @@ static int gmres(orc_ctx *c, long n, orc_op_fn A, const void *aarg, orc_op_fn M,
         int j = 0;
         while (j < m && total < maxit) {
             double *vj = V + (size_t)j * n, *vn = V + (size_t)(j + 1) * n;
-            if (M) { rc = M(c, marg, vj, z); if (rc) break; }
-            rc = A(c, aarg, M ? z : vj, w);
+            double *zj = flexible ? Z + (size_t)j * n : z;
+            if (M) { rc = M(c, marg, vj, zj); if (rc) break; }
+            rc = A(c, aarg, M ? zj : vj, w);
             if (rc) break;
             for (int i = 0; i <= j; ++i) {
                 double *vi = V + (size_t)i * n;
@@ -736,6 +740,13 @@ static int gmres(orc_ctx *c, long n, orc_op_fn A, const void *aarg, orc_op_fn M,
             for (int k = i + 1; k < j; ++k) t -= H[i * m + k] * yv[k];
             yv[i] = t / H[i * m + i];
         }
+        if (flexible) { /* x += Z y */
+            for (int i = 0; i < j; ++i) {
+                double *zi = Z + (size_t)i * n;
+                for (long l = 0; l < n; ++l) x[l] += yv[i] * zi[l];
+            }
+            continue;
+        }
         memset(w, 0, sizeof(double) * n);
         for (int i = 0; i < j; ++i) {
             double *vi = V + (size_t)i * n;
@@ -746,9 +757,15 @@ static int gmres(orc_ctx *c, long n, orc_op_fn A, const void *aarg, orc_op_fn M,
         for (long l = 0; l < n; ++l) x[l] += dx[l];
     }
     if (iters) *iters = total;
-    free(V); free(w); free(z); free(H); free(cs); free(sn); free(g); free(yv);
+    free(Z); free(V); free(w); free(z); free(H); free(cs); free(sn); free(g); free(yv);
     if (rc) return rc;
     return converged ? 0 : -6;
+}
+
+static int gmres(orc_ctx *c, long n, orc_op_fn A, const void *aarg, orc_op_fn M, const void *marg,
+                 const double *b, double *x, double tol, int m, int maxit, int *iters)
+{
+    return gmres_impl(c, n, A, aarg, M, marg, b, x, tol, m, maxit, 0, iters);
 }
 
 /* Standard (unreduced) form: (I - lambda L) x = y on all five fields. */
@@ -974,6 +991,176 @@ int orc_solve3d(orc_ctx *c, const double *y, double *x, double lambda, double to
     if (!rc) {
         for (long I = 0; I < 3 * np; ++I) x[np + I] = Ua[I] - Up[I];
         rc = schur_div(c, &a, x + np, x); /* x_rho = -div(rho0 u) */
+    }
+    if (!rc)
+        for (long I = 0; I < np; ++I) {
+            x[I] = y[I] + lambda * x[I];
+            x[4 * np + I] = y[4 * np + I];
+        }
+    if (iters) *iters = it;
+    free(a.s); free(a.l); free(Ua); free(Up); free(b); free(P);
+    return rc ? rc : grc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Learned correction to the PBNO preconditioner (a project addition; the   */
+/* paper's preconditioners are polynomial).  A two-layer perceptron acts on */
+/* each element's residual: x = r_e / s_e with s_e the RMS of r_e over the  */
+/* element's (N+1)^3 nodes (local order a + nq (b + nq c)), h = tanh(W1 x + */
+/* b1), y = W2 h + b2, correction s_e y; the corrections of the elements    */
+/* sharing a node are averaged.  The preconditioner is z = s(S) r + that    */
+/* average, nonlinear in r, hence flexible GMRES.                           */
+/* ------------------------------------------------------------------------ */
+
+void orc_mlp_forward(const orc_mlp *m, const double *x, double *h, double *y)
+{
+    for (int k = 0; k < m->nh; ++k) {
+        double t = m->b1[k];
+        for (int i = 0; i < m->nin; ++i) t += m->W1[(long)k * m->nin + i] * x[i];
+        h[k] = tanh(t);
+    }
+    for (int o = 0; o < m->nin; ++o) {
+        double t = m->b2[o];
+        for (int k = 0; k < m->nh; ++k) t += m->W2[(long)o * m->nh + k] * h[k];
+        y[o] = t;
+    }
+}
+
+/* Loss = mean over the B samples and nin outputs of (y - t)^2, and its
+ * gradient with respect to W1, b1, W2, b2 by the chain rule. */
+double orc_mlp_loss_grad(const orc_mlp *m, int B, const double *X, const double *T, double *gW1, double *gb1,
+                         double *gW2, double *gb2)
+{
+    int ni = m->nin, nh = m->nh;
+    memset(gW1, 0, sizeof(double) * nh * ni);
+    memset(gb1, 0, sizeof(double) * nh);
+    memset(gW2, 0, sizeof(double) * ni * nh);
+    memset(gb2, 0, sizeof(double) * ni);
+    double *h = (double *)malloc(sizeof(double) * nh), *y = (double *)malloc(sizeof(double) * ni);
+    double *dy = (double *)malloc(sizeof(double) * ni), *dh = (double *)malloc(sizeof(double) * nh);
+    double loss = 0.0, scale = 1.0 / ((double)B * ni);
+    for (int s = 0; s < B; ++s) {
+        const double *x = X + (long)s * ni, *t = T + (long)s * ni;
+        orc_mlp_forward(m, x, h, y);
+        for (int o = 0; o < ni; ++o) {
+            double d = y[o] - t[o];
+            loss += d * d * scale;
+            dy[o] = 2.0 * d * scale;
+            gb2[o] += dy[o];
+            for (int k = 0; k < nh; ++k) gW2[(long)o * nh + k] += dy[o] * h[k];
+        }
+        for (int k = 0; k < nh; ++k) {
+            double t2 = 0.0;
+            for (int o = 0; o < ni; ++o) t2 += m->W2[(long)o * nh + k] * dy[o];
+            dh[k] = t2 * (1.0 - h[k] * h[k]);
+            gb1[k] += dh[k];
+            for (int i = 0; i < ni; ++i) gW1[(long)k * ni + i] += dh[k] * x[i];
+        }
+    }
+    free(h); free(y); free(dy); free(dh);
+    return loss;
+}
+
+/* element features of a field: X[e][nq3] = r_e / s_e, scale[e] = s_e */
+int orc_element_features(orc_ctx *c, const double *r, double *X, double *scale)
+{
+    if (!c || !r || !X || !scale) return -1;
+    long nq3 = c->nq3;
+    for (long e = 0; e < c->nelem; ++e) {
+        double ss = 0.0;
+        for (long l = 0; l < nq3; ++l) {
+            double v = r[c->gmap[e * nq3 + l]];
+            ss += v * v;
+        }
+        double s_e = sqrt(ss / (double)nq3);
+        scale[e] = s_e;
+        for (long l = 0; l < nq3; ++l) X[e * nq3 + l] = s_e > 0.0 ? r[c->gmap[e * nq3 + l]] / s_e : 0.0;
+    }
+    return 0;
+}
+
+/* corr = node average of the element corrections s_e MLP(r_e / s_e) */
+int orc_mlp_correction(orc_ctx *c, const orc_mlp *m, const double *r, double *corr)
+{
+    if (!c || !m || !r || !corr || m->nin != c->nq3) return -1;
+    long nq3 = c->nq3, np = c->np;
+    double *X = (double *)malloc(sizeof(double) * c->nelem * nq3), *sc = (double *)malloc(sizeof(double) * c->nelem);
+    double *h = (double *)malloc(sizeof(double) * m->nh), *y = (double *)malloc(sizeof(double) * nq3);
+    double *cnt = (double *)calloc(np, sizeof(double));
+    if (!X || !sc || !h || !y || !cnt) { free(X); free(sc); free(h); free(y); free(cnt); return -5; }
+    orc_element_features(c, r, X, sc);
+    memset(corr, 0, sizeof(double) * np);
+    for (long e = 0; e < c->nelem; ++e) {
+        orc_mlp_forward(m, X + e * nq3, h, y);
+        for (long l = 0; l < nq3; ++l) {
+            long I = c->gmap[e * nq3 + l];
+            corr[I] += sc[e] * y[l];
+            cnt[I] += 1.0;
+        }
+    }
+    for (long I = 0; I < np; ++I) corr[I] /= cnt[I];
+    free(X); free(sc); free(h); free(y); free(cnt);
+    return 0;
+}
+
+typedef struct {
+    pbno_arg *p;
+    const orc_mlp *mlp;
+} learned_arg;
+
+static int op_learned(orc_ctx *c, const void *arg, const double *r, double *z)
+{
+    const learned_arg *a = (const learned_arg *)arg;
+    long n = c->np;
+    int rc = 0;
+    if (a->p->p >= 0) rc = op_pbno(c, a->p, r, z);
+    else memcpy(z, r, sizeof(double) * n);
+    if (rc || !a->mlp) return rc;
+    double *corr = (double *)malloc(sizeof(double) * n);
+    if (!corr) return -5;
+    rc = orc_mlp_correction(c, a->mlp, r, corr);
+    if (!rc)
+        for (long i = 0; i < n; ++i) z[i] += corr[i];
+    free(corr);
+    return rc;
+}
+
+int orc_learned_apply(orc_ctx *c, const double *r, double *z, double lambda, int order, const double *bounds,
+                      const orc_mlp *mlp)
+{
+    if (!c || !r || !z || (order >= 0 && !bounds)) return -1;
+    schur_arg s = {lambda, (double *)malloc(sizeof(double) * 5 * c->np), (double *)malloc(sizeof(double) * 5 * c->np)};
+    pbno_arg pa = {&s, order, bounds ? bounds[0] : 0.0, bounds ? bounds[1] : 0.0};
+    learned_arg la = {&pa, mlp};
+    int rc = (s.s && s.l) ? op_learned(c, &la, r, z) : -5;
+    free(s.s); free(s.l);
+    return rc;
+}
+
+/* orc_solve3d with flexible GMRES and the learned preconditioner (PBNO of
+ * the given order, order < 0 none, plus the MLP correction; mlp NULL: the
+ * polynomial alone, still through flexible GMRES). */
+int orc_solve3d_learned(orc_ctx *c, const double *y, double *x, double lambda, double tol, int restart, int maxit,
+                        int order, const double *bounds, const orc_mlp *mlp, int *iters)
+{
+    if (!c || !y || !x || restart < 1 || maxit < 1 || !(tol > 0.0)) return -1;
+    if (order >= 0 && (!bounds || !(bounds[1] > bounds[0]) || !(bounds[0] > 0.0))) return -1;
+    long np = c->np;
+    schur_arg a = {lambda, (double *)malloc(sizeof(double) * 5 * np), (double *)malloc(sizeof(double) * 5 * np)};
+    double *Ua = (double *)malloc(sizeof(double) * 3 * np), *Up = (double *)malloc(sizeof(double) * 3 * np);
+    double *b = (double *)malloc(sizeof(double) * np), *P = (double *)malloc(sizeof(double) * np);
+    int rc = (a.s && a.l && Ua && Up && b && P) ? 0 : -5, it = 0, grc = 0;
+    pbno_arg pa = {&a, order, bounds ? bounds[0] : 0.0, bounds ? bounds[1] : 0.0};
+    learned_arg la = {&pa, mlp};
+    if (!rc) rc = schur_rhs(c, &a, y, Ua, b);
+    if (!rc) {
+        grc = gmres_impl(c, np, op_schur, &a, op_learned, &la, b, P, tol, restart, maxit, 1, &it);
+        if (grc && grc != -6) rc = grc;
+    }
+    if (!rc) rc = schur_up(c, &a, P, Up);
+    if (!rc) {
+        for (long I = 0; I < 3 * np; ++I) x[np + I] = Ua[I] - Up[I];
+        rc = schur_div(c, &a, x + np, x);
     }
     if (!rc)
         for (long I = 0; I < np; ++I) {

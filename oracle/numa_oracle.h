@@ -95,6 +95,27 @@ int orc_solve3d(orc_ctx *c, const double *y, double *x, double lambda, double to
 /* The same system in its unreduced 5-field form, unpreconditioned GMRES. */
 int orc_solve3d_standard(orc_ctx *c, const double *y, double *x, double lambda, double tol, int restart, int maxit,
                          int *iters);
+/* Learned correction of the preconditioner (project addition): a two-layer
+ * perceptron per element, h = tanh(W1 x + b1), y = W2 h + b2, with
+ * W1[nh][nin], W2[nin][nh], nin = (N+1)^3 (the element's local nodes).
+ * orc_mlp_loss_grad: mean squared error over B samples X[B][nin] against
+ * T[B][nin] and its gradient.  orc_element_features: X[nelem][nin] = r_e/s_e,
+ * s_e the RMS of r over element e.  orc_mlp_correction: node average of
+ * s_e MLP(r_e/s_e).  orc_learned_apply: z = PBNO(r) + that correction.
+ * orc_solve3d_learned: orc_solve3d through flexible GMRES with it. */
+typedef struct {
+    int nin, nh;
+    const double *W1, *b1, *W2, *b2;
+} orc_mlp;
+void orc_mlp_forward(const orc_mlp *m, const double *x, double *h, double *y);
+double orc_mlp_loss_grad(const orc_mlp *m, int B, const double *X, const double *T, double *gW1, double *gb1,
+                         double *gW2, double *gb2);
+int orc_element_features(orc_ctx *c, const double *r, double *X, double *scale);
+int orc_mlp_correction(orc_ctx *c, const orc_mlp *m, const double *r, double *corr);
+int orc_learned_apply(orc_ctx *c, const double *r, double *z, double lambda, int order, const double *bounds,
+                      const orc_mlp *mlp);
+int orc_solve3d_learned(orc_ctx *c, const double *y, double *x, double lambda, double tol, int restart, int maxit,
+                        int order, const double *bounds, const orc_mlp *mlp, int *iters);
 /* nsteps 3D-IMEX ARK2 steps (orc_step with L in place of L_V and the Schur
  * GMRES solve to tol; linear as in orc_step).  *iters: GMRES iterations in
  * total. */

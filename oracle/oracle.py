@@ -63,8 +63,16 @@ def _load():
                                          C.POINTER(C.c_int)]
     lib.orc_step3d.argtypes = [C.c_void_p, _dp, C.c_double, C.c_int, C.c_int, C.c_double, C.c_int, _dp,
                                C.POINTER(C.c_int)]
+    lib.orc_mlp_loss_grad.argtypes = [C.POINTER(OrcMlp), C.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
+    lib.orc_mlp_loss_grad.restype = C.c_double
+    lib.orc_element_features.argtypes = [C.c_void_p, _dp, _dp, _dp]
+    lib.orc_mlp_correction.argtypes = [C.c_void_p, C.POINTER(OrcMlp), _dp, _dp]
+    lib.orc_learned_apply.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_int, _dp, C.POINTER(OrcMlp)]
+    lib.orc_solve3d_learned.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
+                                        _dp, C.POINTER(OrcMlp), C.POINTER(C.c_int)]
     for name in ("orc_schur_apply", "orc_schur_rhs", "orc_pbno_apply", "orc_schur_bounds", "orc_solve3d",
-                 "orc_solve3d_standard", "orc_step3d"):
+                 "orc_solve3d_standard", "orc_step3d", "orc_element_features", "orc_mlp_correction",
+                 "orc_learned_apply", "orc_solve3d_learned"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -72,6 +80,34 @@ def _load():
 
 class OracleError(RuntimeError):
     pass
+
+
+class OrcMlp(C.Structure):
+    _fields_ = [("nin", C.c_int), ("nh", C.c_int), ("W1", C.POINTER(C.c_double)), ("b1", C.POINTER(C.c_double)),
+                ("W2", C.POINTER(C.c_double)), ("b2", C.POINTER(C.c_double))]
+
+
+class Mlp:
+    """Weights of the per-element perceptron (float64 copies): W1[nh][nin],
+    b1[nh], W2[nin][nh], b2[nin]."""
+
+    def __init__(self, W1, b1, W2, b2):
+        self.W1 = np.ascontiguousarray(W1, dtype=np.float64)
+        self.b1 = np.ascontiguousarray(b1, dtype=np.float64)
+        self.W2 = np.ascontiguousarray(W2, dtype=np.float64)
+        self.b2 = np.ascontiguousarray(b2, dtype=np.float64)
+        nh, nin = self.W1.shape
+        assert self.W2.shape == (nin, nh) and self.b1.shape == (nh,) and self.b2.shape == (nin,)
+        p = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+        self.s = OrcMlp(nin, nh, p(self.W1), p(self.b1), p(self.W2), p(self.b2))
+
+    def loss_grad(self, X, T):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        g = [np.zeros_like(self.W1), np.zeros_like(self.b1), np.zeros_like(self.W2), np.zeros_like(self.b2)]
+        loss = _load().orc_mlp_loss_grad(C.byref(self.s), X.shape[0], X.reshape(-1), T.reshape(-1),
+                                         *[a.reshape(-1) for a in g])
+        return loss, g
 
 
 def _check(rc, what):
@@ -254,3 +290,37 @@ class Oracle:
         _check(_lib.orc_step3d(self.h, q.reshape(-1), float(dt), int(nsteps), 1 if linear else 0, float(tol),
                                int(order), bd, C.byref(it)), "orc_step3d")
         return q, it.value
+
+    # --- learned preconditioner (project addition) --------------------------
+    def element_features(self, r):
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        nq3 = (self.N + 1) ** 3
+        ne = self.nelem
+        X = np.zeros((ne, nq3))
+        sc = np.zeros(ne)
+        _check(_lib.orc_element_features(self.h, r.reshape(-1), X.reshape(-1), sc), "orc_element_features")
+        return X, sc
+
+    def mlp_correction(self, mlp, r):
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        out = np.zeros(self.shape[1:])
+        _check(_lib.orc_mlp_correction(self.h, C.byref(mlp.s), r.reshape(-1), out.reshape(-1)), "orc_mlp_correction")
+        return out
+
+    def learned_apply(self, r, lam, order, bounds, mlp):
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        out = np.zeros(self.shape[1:])
+        bd = np.ascontiguousarray(bounds if bounds is not None else (1.0, 2.0), dtype=np.float64)
+        _check(_lib.orc_learned_apply(self.h, r.reshape(-1), out.reshape(-1), float(lam), int(order), bd,
+                                      C.byref(mlp.s) if mlp is not None else None), "orc_learned_apply")
+        return out
+
+    def solve3d_learned(self, y, lam, mlp, tol=1e-12, restart=30, maxit=100000, order=-1, bounds=None):
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        x = np.zeros(self.shape)
+        it = C.c_int(0)
+        bd = np.ascontiguousarray(bounds if bounds is not None else (1.0, 2.0), dtype=np.float64)
+        _check(_lib.orc_solve3d_learned(self.h, y.reshape(-1), x.reshape(-1), float(lam), float(tol), int(restart),
+                                        int(maxit), int(order), bd, C.byref(mlp.s) if mlp is not None else None,
+                                        C.byref(it)), "orc_solve3d_learned")
+        return x, it.value

@@ -706,3 +706,97 @@ def test_imex3d_stable_at_aspect_ratio_one(oracle_mod):
     q1, it = o.step3d(q, dt, 10, tol=1e-10)
     assert np.all(np.isfinite(q1))
     assert np.nanmax(np.abs(q1[3])) < 1.0
+
+
+# ---------------------------------------------------------------------------
+# Learned correction of the preconditioner (project addition)
+# ---------------------------------------------------------------------------
+
+def _random_mlp(oracle_mod, nin, nh, seed, scale=0.3):
+    rng = np.random.default_rng(seed)
+    return oracle_mod.Mlp(scale * rng.standard_normal((nh, nin)), scale * rng.standard_normal(nh),
+                          scale * rng.standard_normal((nin, nh)), scale * rng.standard_normal(nin))
+
+
+def test_mlp_gradient_matches_finite_differences(oracle_mod):
+    nin, nh, B = 27, 8, 5
+    m = _random_mlp(oracle_mod, nin, nh, 1)
+    rng = np.random.default_rng(2)
+    X, T = rng.standard_normal((B, nin)), rng.standard_normal((B, nin))
+    loss, grads = m.loss_grad(X, T)
+    params = [m.W1, m.b1, m.W2, m.b2]
+    for p, g in zip(params, grads):
+        flat, gflat = p.reshape(-1), g.reshape(-1)
+        for idx in rng.choice(flat.size, size=min(6, flat.size), replace=False):
+            keep = flat[idx]
+            h = 1e-5
+            flat[idx] = keep + h
+            lp, _ = m.loss_grad(X, T)
+            flat[idx] = keep - h
+            lm, _ = m.loss_grad(X, T)
+            flat[idx] = keep
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - gflat[idx]) <= 1e-7 * max(1.0, abs(fd)), (p.shape, idx, fd, gflat[idx])
+    assert loss > 0
+
+
+def test_mlp_small_weights_are_the_linear_map(oracle_mod):
+    """tanh(t) = t + O(t^3): with tiny first-layer weights the network is the
+    affine map W2 (W1 x + b1) + b2 (pins the layer order and orientation)."""
+    nin, nh = 27, 8
+    rng = np.random.default_rng(3)
+    W1, b1 = 1e-5 * rng.standard_normal((nh, nin)), 1e-5 * rng.standard_normal(nh)
+    W2, b2 = rng.standard_normal((nin, nh)), rng.standard_normal(nin)
+    m = oracle_mod.Mlp(W1, b1, W2, b2)
+    X = rng.standard_normal((3, nin))
+    # loss against T = 0 is the mean of y^2; its gradient w.r.t. b2 is 2 y / (B nin)
+    _, g = m.loss_grad(X, np.zeros((3, nin)))
+    y_sum = g[3] * (3 * nin) / 2.0
+    lin = sum(W2 @ (W1 @ x + b1) + b2 for x in X)
+    assert np.max(np.abs(y_sum - lin)) < 1e-9 * np.max(np.abs(lin))
+
+
+def test_element_features_gather_by_coordinates(oracle_mod):
+    g = W.Grid(3000.0, 2000.0, 1500.0, 3, 2, 2, 3)
+    o = _oracle(oracle_mod, g)
+    x, y, z = W.node_coords(g)
+    r = x[None, None, :] + 10.0 * y[None, :, None] + 100.0 * z[:, None, None] + 5.0
+    X, sc = o.element_features(r)
+    N, nq = g.N, g.N + 1
+    for e in (0, 4, g.nex * g.ney * g.nez - 1):
+        ex, ey, ez = e % g.nex, (e // g.nex) % g.ney, e // (g.nex * g.ney)
+        vals = np.array([r[ez * N + c, (ey * N + b) % g.ny, (ex * N + a) % g.nx]
+                         for c in range(nq) for b in range(nq) for a in range(nq)])
+        assert abs(sc[e] - np.sqrt(np.mean(vals ** 2))) < 1e-12 * sc[e]
+        assert np.max(np.abs(X[e] * sc[e] - vals)) < 1e-12 * np.max(np.abs(vals))
+
+
+def test_mlp_correction_averages_element_outputs(oracle_mod):
+    """W2 = 0, b2 = 1: every element proposes its own RMS s_e at each of its
+    nodes; for a constant field that is |c| everywhere after averaging."""
+    g = W.Grid(3000.0, 2000.0, 1500.0, 3, 2, 2, 2)
+    o = _oracle(oracle_mod, g)
+    nin = (g.N + 1) ** 3
+    m = oracle_mod.Mlp(np.zeros((4, nin)), np.zeros(4), np.zeros((nin, 4)), np.ones(nin))
+    corr = o.mlp_correction(m, np.full(g.shape[1:], -2.5))
+    assert np.max(np.abs(corr - 2.5)) < 1e-14
+
+
+def test_flexible_gmres_with_and_without_network(oracle_mod):
+    """Without a network, flexible GMRES is right-preconditioned GMRES (same
+    iterations, same solution); with an untrained network it is a nonlinear
+    preconditioner and still solves the system."""
+    g = _G3
+    o = _oracle(oracle_mod, g)
+    lam = (1.0 - 1.0 / math.sqrt(2.0)) * W.dt_for_courant(g, 15.0, "x")
+    bd = o.schur_bounds(lam, 30)
+    y = W.make_random_state(g, 3, smooth=False)
+    x0, it0 = o.solve3d(y, lam, tol=1e-12, order=2, bounds=bd)
+    x1, it1 = o.solve3d_learned(y, lam, None, tol=1e-12, order=2, bounds=bd)
+    assert it0 == it1
+    assert np.max(np.abs(x1 - x0)) < 1e-10 * np.max(np.abs(x0))
+    m = _random_mlp(oracle_mod, (g.N + 1) ** 3, 8, 4, scale=0.001)
+    x2, it2 = o.solve3d_learned(y, lam, m, tol=1e-12, order=2, bounds=bd, maxit=2000)
+    assert it2 < 2 * it0
+    res = x2 - lam * o.lfull(x2) - y
+    assert np.linalg.norm(res) < 1e-9 * np.linalg.norm(y)
