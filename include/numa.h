@@ -266,6 +266,54 @@ int numa_imex3d_solve(numa_ctx *c, const double *y, double *x, double tol, int32
 int numa_imex3d_step(numa_ctx *c, double *state, double dt, double tol, int32_t *iters_out);
 
 /*
+ * Learned correction of the 3D-IMEX preconditioner (a project addition; the
+ * paper's preconditioners are polynomial, Sec. 5.5).  A two-layer FP32
+ * perceptron per element, h = tanh(W1 x + b1), y = W2 h + b2, nin = (N+1)^3
+ * inputs (the element's local nodes, a + (N+1) (b + (N+1) c), a along x),
+ * `hidden` units, acts on x = r_e / s_e (s_e the RMS of r over the element);
+ * the node average of s_e y over the elements sharing a node is added to
+ * the PBNO polynomial: z = s(S) r + corr(r).  While enabled, the 3D-IMEX
+ * solves run flexible GMRES (the correction is nonlinear); PBNO alone is
+ * the fallback: a restart cycle with the network that does not reduce the
+ * residual norm tenfold switches it off for the rest of that solve, and
+ * numa_learned_enable(c, 0) switches it off altogether.
+ *
+ * numa_learned_setup: allocates the network (parameters W1[hidden][nin],
+ * b1[hidden], W2[nin][hidden], b2[nin] in that order, FP32; W uniform in
+ * +-sqrt(6/(nin+hidden)) from `seed`, b = 0), Adam state and room for
+ * max_samples element samples.  Needs numa_imex3d_setup.  Synchronous.
+ * numa_learned_info: info[6] (host) = {nparam, nin, hidden, samples,
+ * max_samples, enabled}.
+ * numa_learned_add_samples: r (device field) -> solves S e = r with the
+ * polynomial preconditioner to |r - S e| <= tol |r| and appends the nelem
+ * samples (x = r_e/s_e, t = (e - s(S) r)_e / s_e).  Synchronous.
+ * numa_learned_samples: copies samples first..first+n-1 to X, T (device,
+ * n*nin floats each).
+ * numa_learned_params: theta_in (host, nparam floats, nullable) replaces the
+ * parameters, then theta_out (host, nullable) receives them.
+ * numa_learned_loss_grad: mean squared error of the network on X, T (device,
+ * n*nin floats; n <= max(max_samples, elements)) and its gradient into
+ * grad_out (device, nparam floats).  Synchronous.
+ * numa_learned_train: `steps` Adam steps (lr; betas 0.9, 0.999) on batches of
+ * `batch` consecutive samples at seeded offsets; losses of the first and
+ * last batch to the host pointers (nullable).  Synchronous.
+ * numa_learned_enable: on != 0 uses the correction in the 3D-IMEX solves.
+ * numa_learned_apply: z = s(S) r + corr(r) (device fields, distinct).
+ * Errors: NUMA_E_ARG, NUMA_E_NOT_FACTORED (no numa_imex3d_setup /
+ * numa_learned_setup), NUMA_E_NOT_CONVERGED (a sample solve), NUMA_E_HIP.
+ */
+int numa_learned_setup(numa_ctx *c, int32_t hidden, int64_t max_samples, uint64_t seed);
+int numa_learned_info(const numa_ctx *c, int64_t *info);
+int numa_learned_add_samples(numa_ctx *c, const double *r, double tol, int32_t *iters_out);
+int numa_learned_samples(numa_ctx *c, int64_t first, int64_t n, float *X, float *T);
+int numa_learned_params(numa_ctx *c, float *theta_out, const float *theta_in);
+int numa_learned_loss_grad(numa_ctx *c, const float *X, const float *T, int64_t n, float *grad_out, double *loss_out);
+int numa_learned_train(numa_ctx *c, int32_t steps, int32_t batch, double lr, uint64_t seed, double *loss_first,
+                       double *loss_last);
+int numa_learned_enable(numa_ctx *c, int32_t on);
+int numa_learned_apply(numa_ctx *c, const double *r, double *z);
+
+/*
  * Host-only helpers (no GPU needed): the operators numa_setup builds.
  * numa_lgl_basis: LGL nodes xi[order+1] on [-1, 1] and the differentiation
  * matrix D[(order+1)^2] (row-major, D[i*(order+1)+j] = l_j'(xi_i)), the sD

@@ -675,9 +675,15 @@ static double dot_n(const double *a, const double *b, long n)
  * residual |b - A x| reaches tol |b|.  *iters counts Arnoldi iterations. */
 typedef int (*orc_op_fn)(orc_ctx *c, const void *arg, const double *in, double *out);
 
+/* guard (flexible only, may be NULL): called with the residual norms before
+ * and after each restart cycle; it may change what M does from then on */
+typedef void (*orc_guard_fn)(const void *marg, double before, double after);
+
 static int gmres_impl(orc_ctx *c, long n, orc_op_fn A, const void *aarg, orc_op_fn M, const void *marg,
-                      const double *b, double *x, double tol, int m, int maxit, int flexible, int *iters)
+                      const double *b, double *x, double tol, int m, int maxit, int flexible, orc_guard_fn guard,
+                      int *iters)
 {
+    double prev = -1.0;
     int total = 0, rc = 0, converged = 0;
     /* flexible: keep z_j = M v_j and update x with them (M may change with
      * its argument, as a nonlinear preconditioner does) */
@@ -696,6 +702,8 @@ static int gmres_impl(orc_ctx *c, long n, orc_op_fn A, const void *aarg, orc_op_
         if (rc) break;
         for (long i = 0; i < n; ++i) w[i] = b[i] - w[i];
         double beta = sqrt(dot_n(w, w, n));
+        if (guard && prev >= 0.0) guard(marg, prev, beta);
+        prev = beta;
         if (beta <= tol * bnorm) { converged = 1; break; }
         if (total >= maxit) break;
         for (long i = 0; i < n; ++i) V[i] = w[i] / beta;
@@ -765,7 +773,7 @@ static int gmres_impl(orc_ctx *c, long n, orc_op_fn A, const void *aarg, orc_op_
 static int gmres(orc_ctx *c, long n, orc_op_fn A, const void *aarg, orc_op_fn M, const void *marg,
                  const double *b, double *x, double tol, int m, int maxit, int *iters)
 {
-    return gmres_impl(c, n, A, aarg, M, marg, b, x, tol, m, maxit, 0, iters);
+    return gmres_impl(c, n, A, aarg, M, marg, b, x, tol, m, maxit, 0, NULL, iters);
 }
 
 /* Standard (unreduced) form: (I - lambda L) x = y on all five fields. */
@@ -1108,6 +1116,15 @@ typedef struct {
     const orc_mlp *mlp;
 } learned_arg;
 
+/* The polynomial is the fallback: a restart cycle with the network that
+ * does not reduce the residual norm tenfold switches the network off for
+ * the rest of the solve. */
+static void learned_guard(const void *marg, double before, double after)
+{
+    learned_arg *a = (learned_arg *)marg;
+    if (a->mlp && after > 0.1 * before) a->mlp = NULL;
+}
+
 static int op_learned(orc_ctx *c, const void *arg, const double *r, double *z)
 {
     const learned_arg *a = (const learned_arg *)arg;
@@ -1139,7 +1156,8 @@ int orc_learned_apply(orc_ctx *c, const double *r, double *z, double lambda, int
 
 /* orc_solve3d with flexible GMRES and the learned preconditioner (PBNO of
  * the given order, order < 0 none, plus the MLP correction; mlp NULL: the
- * polynomial alone, still through flexible GMRES). */
+ * polynomial alone, still through flexible GMRES), with the fallback of
+ * learned_guard. */
 int orc_solve3d_learned(orc_ctx *c, const double *y, double *x, double lambda, double tol, int restart, int maxit,
                         int order, const double *bounds, const orc_mlp *mlp, int *iters)
 {
@@ -1154,7 +1172,7 @@ int orc_solve3d_learned(orc_ctx *c, const double *y, double *x, double lambda, d
     learned_arg la = {&pa, mlp};
     if (!rc) rc = schur_rhs(c, &a, y, Ua, b);
     if (!rc) {
-        grc = gmres_impl(c, np, op_schur, &a, op_learned, &la, b, P, tol, restart, maxit, 1, &it);
+        grc = gmres_impl(c, np, op_schur, &a, op_learned, &la, b, P, tol, restart, maxit, 1, learned_guard, &it);
         if (grc && grc != -6) rc = grc;
     }
     if (!rc) rc = schur_up(c, &a, P, Up);

@@ -102,7 +102,9 @@ int orc_solve3d_standard(orc_ctx *c, const double *y, double *x, double lambda, 
  * T[B][nin] and its gradient.  orc_element_features: X[nelem][nin] = r_e/s_e,
  * s_e the RMS of r over element e.  orc_mlp_correction: node average of
  * s_e MLP(r_e/s_e).  orc_learned_apply: z = PBNO(r) + that correction.
- * orc_solve3d_learned: orc_solve3d through flexible GMRES with it. */
+ * orc_solve3d_learned: orc_solve3d through flexible GMRES with it; a
+ * restart cycle that does not reduce the residual norm tenfold switches the
+ * network off for the rest of the solve (the polynomial is the fallback). */
 typedef struct {
     int nin, nh;
     const double *W1, *b1, *W2, *b2;

@@ -36,6 +36,7 @@ void free_ctx(numa_ctx *c)
     if (c->work) (void)hipFree(c->work);
     if (c->work_mix) (void)hipFree(c->work_mix);
     if (c->flag) (void)hipFree(c->flag);
+    numa::learned_free(c);
     numa::imex3d_free(c);
     delete c;
 }
@@ -441,6 +442,142 @@ int numa_imex3d_step(numa_ctx *c, double *state, double dt, double tol, int32_t 
     if (e != hipSuccess) return hip_fail(c, e, "numa_imex3d_step");
     if (!conv) return fail(c, NUMA_E_NOT_CONVERGED, "numa_imex3d_step: GMRES did not reach tol within maxit");
     return NUMA_OK;
+}
+
+namespace {
+
+int learned_ready(numa_ctx *c, const char *who)
+{
+    if (!c->learned) return fail(c, NUMA_E_NOT_FACTORED, std::string(who) + ": call numa_learned_setup first");
+    return NUMA_OK;
+}
+
+}  // namespace
+
+int numa_learned_setup(numa_ctx *c, int32_t hidden, int64_t max_samples, uint64_t seed)
+{
+    if (!c) return NUMA_E_ARG;
+    if (hidden < 1 || hidden > 1024 || max_samples < 1) return fail(c, NUMA_E_ARG, "numa_learned_setup: bad arguments");
+    int rc = imex3d_ready(c, "numa_learned_setup");
+    if (rc != NUMA_OK) return rc;
+    hipError_t e = numa::learned_setup(c, hidden, long(max_samples), seed);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        numa::learned_free(c);
+        return hip_fail(c, e, "numa_learned_setup");
+    }
+    return NUMA_OK;
+}
+
+int numa_learned_info(const numa_ctx *c, int64_t *info)
+{
+    if (!c || !info || !c->learned) return NUMA_E_ARG;
+    const numa::LearnedInfo L = numa::learned_info(c);
+    info[0] = L.nparam;
+    info[1] = L.nin;
+    info[2] = L.nh;
+    info[3] = L.nsamp;
+    info[4] = L.cap;
+    info[5] = L.enabled;
+    return NUMA_OK;
+}
+
+int numa_learned_add_samples(numa_ctx *c, const double *r, double tol, int32_t *iters_out)
+{
+    if (iters_out) *iters_out = 0;
+    if (!c) return NUMA_E_ARG;
+    if (!r || !(tol > 0.0)) return fail(c, NUMA_E_ARG, "numa_learned_add_samples: bad arguments");
+    int rc = learned_ready(c, "numa_learned_add_samples");
+    if (rc != NUMA_OK) return rc;
+    const numa::LearnedInfo L = numa::learned_info(c);
+    if (L.nsamp + L.nelem > L.cap) return fail(c, NUMA_E_ARG, "numa_learned_add_samples: sample capacity reached");
+    int it = 0, conv = 0;
+    hipError_t e = numa::learned_add_samples(c, r, tol, &it, &conv);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (iters_out) *iters_out = it;
+    if (e != hipSuccess) return hip_fail(c, e, "numa_learned_add_samples");
+    if (!conv) return fail(c, NUMA_E_NOT_CONVERGED, "numa_learned_add_samples: the sample solve did not converge");
+    return NUMA_OK;
+}
+
+int numa_learned_samples(numa_ctx *c, int64_t first, int64_t n, float *X, float *T)
+{
+    if (!c) return NUMA_E_ARG;
+    int rc = learned_ready(c, "numa_learned_samples");
+    if (rc != NUMA_OK) return rc;
+    const numa::LearnedInfo L = numa::learned_info(c);
+    if (first < 0 || n < 1 || first + n > L.nsamp || !X || !T)
+        return fail(c, NUMA_E_ARG, "numa_learned_samples: bad range or null pointer");
+    const size_t bytes = sizeof(float) * size_t(n) * L.nin;
+    hipError_t e = hipMemcpyAsync(X, L.X + first * L.nin, bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(T, L.T + first * L.nin, bytes, hipMemcpyDeviceToDevice, c->stream);
+    return e == hipSuccess ? NUMA_OK : hip_fail(c, e, "numa_learned_samples");
+}
+
+int numa_learned_params(numa_ctx *c, float *theta_out, const float *theta_in)
+{
+    if (!c) return NUMA_E_ARG;
+    int rc = learned_ready(c, "numa_learned_params");
+    if (rc != NUMA_OK) return rc;
+    const numa::LearnedInfo L = numa::learned_info(c);
+    const size_t bytes = sizeof(float) * size_t(L.nparam);
+    hipError_t e = hipSuccess;
+    if (theta_in) e = hipMemcpyAsync(L.theta, theta_in, bytes, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && theta_out) e = hipMemcpyAsync(theta_out, L.theta, bytes, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return e == hipSuccess ? NUMA_OK : hip_fail(c, e, "numa_learned_params");
+}
+
+int numa_learned_loss_grad(numa_ctx *c, const float *X, const float *T, int64_t n, float *grad_out, double *loss_out)
+{
+    if (!c) return NUMA_E_ARG;
+    int rc = learned_ready(c, "numa_learned_loss_grad");
+    if (rc != NUMA_OK) return rc;
+    const numa::LearnedInfo L = numa::learned_info(c);
+    if (!X || !T || !grad_out || !loss_out || n < 1 || n > std::max(L.cap, L.nelem))
+        return fail(c, NUMA_E_ARG, "numa_learned_loss_grad: bad arguments");
+    hipError_t e = numa::learned_loss_grad(c, X, T, long(n), loss_out);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(grad_out, L.grad, sizeof(float) * size_t(L.nparam), hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return e == hipSuccess ? NUMA_OK : hip_fail(c, e, "numa_learned_loss_grad");
+}
+
+int numa_learned_train(numa_ctx *c, int32_t steps, int32_t batch, double lr, uint64_t seed, double *loss_first,
+                       double *loss_last)
+{
+    if (!c) return NUMA_E_ARG;
+    if (steps < 1 || batch < 1 || !(lr > 0.0)) return fail(c, NUMA_E_ARG, "numa_learned_train: bad arguments");
+    int rc = learned_ready(c, "numa_learned_train");
+    if (rc != NUMA_OK) return rc;
+    const numa::LearnedInfo L = numa::learned_info(c);
+    if (L.nsamp < 1) return fail(c, NUMA_E_ARG, "numa_learned_train: no samples");
+    if (batch > std::max(L.cap, L.nelem)) return fail(c, NUMA_E_ARG, "numa_learned_train: batch too large");
+    double lf = 0.0, ll = 0.0;
+    hipError_t e = numa::learned_train(c, steps, batch, lr, seed, &lf, &ll);
+    if (loss_first) *loss_first = lf;
+    if (loss_last) *loss_last = steps == 1 ? lf : ll;
+    return e == hipSuccess ? NUMA_OK : hip_fail(c, e, "numa_learned_train");
+}
+
+int numa_learned_enable(numa_ctx *c, int32_t on)
+{
+    if (!c) return NUMA_E_ARG;
+    int rc = learned_ready(c, "numa_learned_enable");
+    if (rc != NUMA_OK) return rc;
+    numa::learned_set_enabled(c, on);
+    return NUMA_OK;
+}
+
+int numa_learned_apply(numa_ctx *c, const double *r, double *z)
+{
+    if (!c) return NUMA_E_ARG;
+    if (!r || !z || r == z) return fail(c, NUMA_E_ARG, "numa_learned_apply: null or identical pointers");
+    int rc = learned_ready(c, "numa_learned_apply");
+    if (rc != NUMA_OK) return rc;
+    hipError_t e = numa::pbno_apply(c, r, z);
+    if (e == hipSuccess) e = numa::learned_correction_add(c, r, z, nullptr);
+    return e == hipSuccess ? NUMA_OK : hip_fail(c, e, "numa_learned_apply");
 }
 
 int numa_lgl_basis(int32_t order, double *xi, double *D)

@@ -516,6 +516,7 @@ struct Imex3d {
     void *block = nullptr;  // one allocation for everything below
     double *wxx = nullptr, *wyy = nullptr, *vb = nullptr;
     double *V = nullptr;                                   // (restart+1) np
+    double *Z = nullptr;                                   // restart np (flexible GMRES)
     double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *w = nullptr;
     double *cres = nullptr, *d0 = nullptr, *d1 = nullptr;  // Chebyshev recurrence
     double *part = nullptr;                                // (restart+1) nblk
@@ -799,7 +800,7 @@ hipError_t imex3d_setup(numa_ctx *c, double dt, int restart, int order, int powe
     const int m = restart;
     // sizes in doubles
     const size_t n_tab = size_t(2 * N * W + nz * W);
-    const size_t n_vec = size_t(m + 1) * np + 8 * size_t(np) + 20 * size_t(np);
+    const size_t n_vec = size_t(2 * m + 1) * np + 8 * size_t(np) + 20 * size_t(np);
     const size_t n_small = size_t(m + 1) * npart + size_t(m + 1) * m + 4 * size_t(m + 2) + size_t(m + 2);
     const size_t total = n_tab + n_vec + n_small + 64;
     hipError_t e = hipMalloc(&s->block, total * sizeof(double) + 64);
@@ -812,6 +813,7 @@ hipError_t imex3d_setup(numa_ctx *c, double dt, int restart, int order, int powe
     s->wyy = p; p += N * W;
     s->vb = p; p += nz * W;
     s->V = p; p += size_t(m + 1) * np;
+    s->Z = p; p += size_t(m) * np;
     s->b = p; p += np;
     s->x = p; p += np;
     s->r = p; p += np;
@@ -888,24 +890,26 @@ hipError_t schur_rhs(numa_ctx *c, const double *y, double *b)
 
 hipError_t pbno_apply(numa_ctx *c, const double *r, double *z) { return precondition(c, r, z); }
 
-// x = (I - lambda L)^-1 y (5 fields), out = x + d0 in0 + d1 in1.  out may be
-// y itself.  *iters: Arnoldi iterations; *converged: 0 if maxit was reached.
-hipError_t imex3d_solve(numa_ctx *c, const double *y, double *out, const double *in0, double d0, const double *in1,
-                        double d1, double tol, int *iters, int *converged)
+// S x = b by restarted GMRES from x = 0 (flexible, with the Z basis, when
+// the learned correction is on): the solution in s.x, its residual b - S x
+// in s.r.  *iters: Arnoldi iterations; *converged: 0 if maxit was reached.
+hipError_t schur_gmres(numa_ctx *c, const double *bvec, int *iters, int *converged, double tol)
 {
     Imex3d &s = *c->imex;
     const long np = s.np;
     const int m = s.restart;
+    // the learned correction (flexible GMRES) until a restart cycle with it
+    // fails to reduce the residual norm tenfold; then the polynomial alone
+    bool flex = learned_enabled(c);
     hipError_t e;
     *iters = 0;
     *converged = 0;
-    if ((e = schur_rhs(c, y, s.b)) != hipSuccess) return e;
     double bnorm = 0.0;
-    if ((e = norm_host(c, s.b, &bnorm)) != hipSuccess) return e;
+    if ((e = norm_host(c, bvec, &bnorm)) != hipSuccess) return e;
     if ((e = hipMemsetAsync(s.x, 0, sizeof(double) * np, c->stream)) != hipSuccess) return e;
     const double tolb = tol * bnorm;
     double beta = bnorm;
-    const double *rvec = s.b;  // residual of x = 0
+    const double *rvec = bvec;  // residual of x = 0
     int total = 0;
     const int chunk = 4;
     while (true) {
@@ -923,7 +927,12 @@ hipError_t imex3d_solve(numa_ctx *c, const double *y, double *out, const double 
                 const double *vj = s.V + size_t(j) * np;
                 double *vn = s.V + size_t(j + 1) * np;
                 const double *zin = vj;
-                if (s.order >= 0) {
+                if (flex) {
+                    double *zj = s.Z + size_t(j) * np;
+                    if ((e = precondition(c, vj, zj)) != hipSuccess) return e;
+                    if ((e = learned_correction_add(c, vj, zj, s.stop)) != hipSuccess) return e;
+                    zin = zj;
+                } else if (s.order >= 0) {
                     if ((e = precondition(c, vj, s.z)) != hipSuccess) return e;
                     zin = s.z;
                 }
@@ -967,7 +976,9 @@ hipError_t imex3d_solve(numa_ctx *c, const double *y, double *out, const double 
         if ((e = hipMemcpyAsync(s.yc, s.hy.data(), sizeof(double) * jdone, hipMemcpyHostToDevice, c->stream)) !=
             hipSuccess)
             return e;
-        if (s.order < 0) {
+        if (flex) {
+            hipLaunchKernelGGL(k_combine, dim3(unsigned(s.nblk)), dim3(kTB), 0, c->stream, s.x, s.Z, s.yc, jdone, np, 1);
+        } else if (s.order < 0) {
             hipLaunchKernelGGL(k_combine, dim3(unsigned(s.nblk)), dim3(kTB), 0, c->stream, s.x, s.V, s.yc, jdone, np, 1);
         } else {
             hipLaunchKernelGGL(k_combine, dim3(unsigned(s.nblk)), dim3(kTB), 0, c->stream, s.w, s.V, s.yc, jdone, np, 0);
@@ -976,15 +987,35 @@ hipError_t imex3d_solve(numa_ctx *c, const double *y, double *out, const double 
         }
         total += jdone;
         // true residual
-        if ((e = apply(c, axpy_args(s.x, s.r, 0.0, -1.0, 1.0, s.b))) != hipSuccess) return e;
+        if ((e = apply(c, axpy_args(s.x, s.r, 0.0, -1.0, 1.0, bvec))) != hipSuccess) return e;
+        const double before = beta;
         if ((e = norm_host(c, s.r, &beta)) != hipSuccess) return e;
+        if (flex && beta > 0.1 * before) flex = false;
         rvec = s.r;
     }
     *iters = total;
-    if (rvec == s.b) {  // x = 0: r = b
-        if ((e = hipMemcpyAsync(s.r, s.b, sizeof(double) * np, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
-            return e;
-    }
+    if (rvec == bvec)  // x = 0: r = b
+        return hipMemcpyAsync(s.r, bvec, sizeof(double) * np, hipMemcpyDeviceToDevice, c->stream);
+    return hipSuccess;
+}
+
+// S e = r for a field r (device), solution copied to e_out
+hipError_t schur_solve_field(numa_ctx *c, const double *r, double *e_out, double tol, int *iters, int *converged)
+{
+    hipError_t e = schur_gmres(c, r, iters, converged, tol);
+    if (e != hipSuccess) return e;
+    return hipMemcpyAsync(e_out, c->imex->x, sizeof(double) * c->np, hipMemcpyDeviceToDevice, c->stream);
+}
+
+// x = (I - lambda L)^-1 y (5 fields), out = x + d0 in0 + d1 in1.  out may be
+// y itself.  *iters: Arnoldi iterations; *converged: 0 if maxit was reached.
+hipError_t imex3d_solve(numa_ctx *c, const double *y, double *out, const double *in0, double d0, const double *in1,
+                        double d1, double tol, int *iters, int *converged)
+{
+    Imex3d &s = *c->imex;
+    hipError_t e;
+    if ((e = schur_rhs(c, y, s.b)) != hipSuccess) return e;
+    if ((e = schur_gmres(c, s.b, iters, converged, tol)) != hipSuccess) return e;
     ExtractArgs a{};
     a.y = y;
     a.P = s.x;

@@ -41,7 +41,8 @@ struct DevLevels {
 constexpr int kBinomTerms = 10;
 constexpr double kBinomMaxX = 1.0 / 32.0;
 
-struct Imex3d;  // 3D-IMEX solver state (imex3d.hip)
+struct Imex3d;   // 3D-IMEX solver state (imex3d.hip)
+struct Learned;  // learned preconditioner correction (learned.hip)
 
 struct EOS {
     double theta0, p00, rgas, gamma, grav;
@@ -70,6 +71,7 @@ struct numa_ctx {
     double dt_factored = 0, lambda = 0;
     int rhs_zchunk = 0;            // z elements per RHS workgroup (0 = auto)
     numa::Imex3d *imex = nullptr;  // 3D-IMEX solver (numa_imex3d_setup)
+    numa::Learned *learned = nullptr;  // learned correction (numa_learned_setup)
     std::string err;
 };
 
@@ -116,5 +118,23 @@ hipError_t pbno_apply(numa_ctx *c, const double *r, double *z);
 hipError_t imex3d_solve(numa_ctx *c, const double *y, double *out, const double *in0, double d0, const double *in1,
                         double d1, double tol, int *iters, int *converged);
 hipError_t imex3d_step(numa_ctx *c, double *q, double dt, double tol, int *iters, int *converged);
+hipError_t schur_solve_field(numa_ctx *c, const double *r, double *e_out, double tol, int *iters, int *converged);
+
+// learned.hip: the learned correction of the preconditioner
+bool learned_enabled(const numa_ctx *c);
+void learned_free(numa_ctx *c);
+hipError_t learned_setup(numa_ctx *c, int nh, long cap, uint64_t seed);
+hipError_t learned_correction_add(numa_ctx *c, const double *r, double *z, const int *stop);
+hipError_t learned_add_samples(numa_ctx *c, const double *r, double tol, int *iters, int *converged);
+hipError_t learned_loss_grad(numa_ctx *c, const float *X, const float *T, long n, double *loss);
+hipError_t learned_train(numa_ctx *c, int steps, int batch, double lr, uint64_t seed, double *loss_first,
+                         double *loss_last);
+struct LearnedInfo {
+    long nparam, nsamp, cap, nelem;
+    int nin, nh, enabled;
+    float *theta, *grad, *X, *T;
+};
+LearnedInfo learned_info(const numa_ctx *c);
+void learned_set_enabled(numa_ctx *c, int on);
 
 }  // namespace numa

@@ -97,6 +97,16 @@ def load():
     lib.numa_pbno_apply.argtypes = [vp, vp, vp]
     lib.numa_imex3d_solve.argtypes = [vp, vp, vp, C.c_double, C.POINTER(C.c_int32)]
     lib.numa_imex3d_step.argtypes = [vp, vp, C.c_double, C.c_double, C.POINTER(C.c_int32)]
+    lib.numa_learned_setup.argtypes = [vp, C.c_int32, C.c_int64, C.c_uint64]
+    lib.numa_learned_info.argtypes = [vp, C.POINTER(C.c_int64)]
+    lib.numa_learned_add_samples.argtypes = [vp, vp, C.c_double, C.POINTER(C.c_int32)]
+    lib.numa_learned_samples.argtypes = [vp, C.c_int64, C.c_int64, vp, vp]
+    lib.numa_learned_params.argtypes = [vp, vp, vp]
+    lib.numa_learned_loss_grad.argtypes = [vp, vp, vp, C.c_int64, vp, C.POINTER(C.c_double)]
+    lib.numa_learned_train.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, C.c_uint64, C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double)]
+    lib.numa_learned_enable.argtypes = [vp, C.c_int32]
+    lib.numa_learned_apply.argtypes = [vp, vp, vp]
     lib.numa_check.argtypes = [vp]
     lib.numa_destroy.argtypes = [vp]
     lib.numa_last_error.argtypes = [vp]
@@ -110,7 +120,9 @@ def load():
                  "numa_lgl_basis", "numa_line_operators", "numa_ensemble_create", "numa_ensemble_step",
                  "numa_ensemble_sync", "numa_ensemble_zchunks", "numa_ensemble_destroy", "numa_imex3d_setup",
                  "numa_imex3d_bounds", "numa_imex3d_set_bounds", "numa_schur_apply", "numa_schur_rhs",
-                 "numa_pbno_apply", "numa_imex3d_solve"):
+                 "numa_pbno_apply", "numa_imex3d_solve", "numa_learned_setup", "numa_learned_info",
+                 "numa_learned_add_samples", "numa_learned_samples", "numa_learned_params", "numa_learned_loss_grad",
+                 "numa_learned_train", "numa_learned_enable", "numa_learned_apply"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -308,6 +320,55 @@ def imex3d_solve(ctx, y_ptr, x_ptr, tol):
     it = C.c_int32(0)
     _check(load().numa_imex3d_solve(ctx, C.c_void_p(y_ptr), C.c_void_p(x_ptr), float(tol), C.byref(it)), ctx)
     return it.value
+
+
+def learned_setup(ctx, hidden=64, max_samples=24576, seed=1):
+    return _check(load().numa_learned_setup(ctx, int(hidden), int(max_samples), int(seed)), ctx)
+
+
+def learned_info(ctx):
+    info = (C.c_int64 * 6)()
+    _check(load().numa_learned_info(ctx, info), ctx)
+    return dict(zip(("nparam", "nin", "hidden", "samples", "max_samples", "enabled"), (int(v) for v in info)))
+
+
+def learned_add_samples(ctx, r_ptr, tol):
+    it = C.c_int32(0)
+    _check(load().numa_learned_add_samples(ctx, C.c_void_p(r_ptr), float(tol), C.byref(it)), ctx)
+    return it.value
+
+
+def learned_samples(ctx, first, n, x_ptr, t_ptr):
+    return _check(load().numa_learned_samples(ctx, int(first), int(n), C.c_void_p(x_ptr), C.c_void_p(t_ptr)), ctx)
+
+
+def learned_params(ctx, theta_out=None, theta_in=None):
+    """theta_out / theta_in: host float32 numpy arrays (nparam) or None."""
+    po = theta_out.ctypes.data_as(C.c_void_p) if theta_out is not None else None
+    pi = theta_in.ctypes.data_as(C.c_void_p) if theta_in is not None else None
+    return _check(load().numa_learned_params(ctx, po, pi), ctx)
+
+
+def learned_loss_grad(ctx, x_ptr, t_ptr, n, grad_ptr):
+    loss = C.c_double(0.0)
+    _check(load().numa_learned_loss_grad(ctx, C.c_void_p(x_ptr), C.c_void_p(t_ptr), int(n), C.c_void_p(grad_ptr),
+                                         C.byref(loss)), ctx)
+    return loss.value
+
+
+def learned_train(ctx, steps, batch=1024, lr=1e-3, seed=7):
+    lf, ll = C.c_double(0.0), C.c_double(0.0)
+    _check(load().numa_learned_train(ctx, int(steps), int(batch), float(lr), int(seed), C.byref(lf), C.byref(ll)),
+           ctx)
+    return lf.value, ll.value
+
+
+def learned_enable(ctx, on):
+    return _check(load().numa_learned_enable(ctx, 1 if on else 0), ctx)
+
+
+def learned_apply(ctx, r_ptr, z_ptr):
+    return _check(load().numa_learned_apply(ctx, C.c_void_p(r_ptr), C.c_void_p(z_ptr)), ctx)
 
 
 def imex3d_step(ctx, state_ptr, dt, tol):
