@@ -14,6 +14,7 @@ baseline times the plain FP64 oracle on a bounded sub-box of the same
 workload (same element shape, order and dt).
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -169,7 +170,7 @@ def batched_ensemble(numa, torch, steps=50):
     return out
 
 
-def imex3d(numa, torch, steps=10, order=6, restart=30):
+def imex3d(numa, torch, steps=10, order=6, restart=30, learned=True):
     """The 3D-IMEX step (all acoustics implicit, Schur-complement GMRES with
     PBNO) on 32x32x8 elements, N=5, at acoustic Courant number 15 in every
     direction, tol 1e-8: throughput, simulated seconds per wall second,
@@ -201,11 +202,70 @@ def imex3d(numa, torch, steps=10, order=6, restart=30):
         runs[name] = {"pbno_order": p, "restart": restart, "ms_per_step": 1e3 * t,
                       "value": 5 * g.n_unique / t, "sim_s_per_wall_s": wl.dt / t,
                       "gmres_iters_per_step": sum(its) / n, "setup_s": t_setup, "interval": list(bd)}
+    if learned:
+        runs["pbno%d_learned" % order] = imex3d_learned(numa, torch, ctx, wl, q0, order, restart, runs)
     out["runs"] = runs
     best = runs["pbno%d" % order]
     out.update({"value": best["value"], "unit": "DOF-steps/s", "ms_per_step": best["ms_per_step"],
                 "sim_s_per_wall_s": best["sim_s_per_wall_s"],
                 "pbno_speedup_vs_none": runs["none"]["ms_per_step"] / best["ms_per_step"]})
+    return imex3d_roofline(numa, torch, ctx, g, out)
+
+
+def imex3d_learned(numa, torch, ctx, wl, q0, order, restart, runs):
+    """The learned correction: trained on 3 fields' element patches (24,576
+    samples: one Schur right-hand side of a stage-like state, two seeded
+    random fields), then the same steps with it enabled."""
+    from paper_1702_04316_amd import workloads as W
+    g = wl.grid
+    # learned correction: trained on 3 fields' element patches (24,576
+    # samples: one Schur right-hand side of a stage-like state, two seeded
+    # random fields), then the same steps with it enabled
+    ctx.imex3d_setup(wl.dt, restart=restart, pbno_order=order, power_steps=30, maxit=5000)
+    ne = g.nex * g.ney * g.nez
+    t0 = time.perf_counter()
+    numa.learned_setup(ctx.ctx, hidden=16, max_samples=3 * ne, seed=1)
+    R1 = ctx.rhs(q0)
+    lam = (1.0 - 1.0 / 2 ** 0.5) * wl.dt
+    fields = [ctx.schur_rhs(q0 + 0.5 * wl.dt * R1)]
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    fields += [torch.randn(g.shape[1:], dtype=torch.float64, device="cuda", generator=gen) for _ in range(2)]
+    sample_iters = [numa.learned_add_samples(ctx.ctx, f.data_ptr(), 1e-10) for f in fields]
+    torch.cuda.synchronize()
+    t_samples = time.perf_counter() - t0
+    nin = (g.N + 1) ** 3
+    nparam = numa.learned_info(ctx.ctx)["nparam"]
+    Xs = torch.empty(3 * ne * nin, dtype=torch.float32, device="cuda")
+    Ts = torch.empty_like(Xs)
+    gr = torch.empty(nparam, dtype=torch.float32, device="cuda")
+    numa.learned_samples(ctx.ctx, 0, 3 * ne, Xs.data_ptr(), Ts.data_ptr())
+    loss_before = numa.learned_loss_grad(ctx.ctx, Xs.data_ptr(), Ts.data_ptr(), 3 * ne, gr.data_ptr())
+    t0 = time.perf_counter()
+    lf, ll = numa.learned_train(ctx.ctx, 2000, batch=1024, lr=1e-3)
+    t_train = time.perf_counter() - t0
+    loss_after = numa.learned_loss_grad(ctx.ctx, Xs.data_ptr(), Ts.data_ptr(), 3 * ne, gr.data_ptr())
+    del Xs, Ts, gr
+    numa.learned_enable(ctx.ctx, True)
+    q = q0.clone()
+    ctx.imex3d_step(q, W.IMEX3D_TOL)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = [ctx.imex3d_step(q, W.IMEX3D_TOL) for _ in range(3)]
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / 3
+    ctx.check()
+    numa.learned_enable(ctx.ctx, False)
+    return {
+        "pbno_order": order, "restart": restart, "ms_per_step": 1e3 * t, "value": 5 * g.n_unique / t,
+        "sim_s_per_wall_s": wl.dt / t, "gmres_iters_per_step": sum(its) / 3,
+        "network": "per-element perceptron %d-16-%d, tanh, FP32" % ((g.N + 1) ** 3, (g.N + 1) ** 3),
+        "samples": 3 * ne, "sample_solve_iters": sample_iters, "sample_s": t_samples,
+        "train_steps": 2000, "batch": 1024, "train_s": t_train, "loss_all_samples_before": loss_before,
+        "loss_all_samples_after": loss_after,
+        "gain_vs_polynomial": runs["pbno%d" % order]["ms_per_step"] / (1e3 * t)}
+
+
+def imex3d_roofline(numa, torch, ctx, g, out):
     # Schur operator: 16 algorithmic bytes per node (read P, write S P)
     P = torch.randn(g.shape[1:], dtype=torch.float64, device="cuda")
     ctx.schur_apply(P)
@@ -218,8 +278,16 @@ def imex3d(numa, torch, steps=10, order=6, restart=30):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / 50
     achieved = 16 * g.n_unique / (ms * 1e-3) / 1e9
+    traffic = None
+    try:  # counter-measured bytes of the same kernel source, if profiled
+        t = json.load(open(os.path.join(ROOT, "profiles", "traffic_imex3d.json")))
+        src = os.path.join(ROOT, "paper_1702_04316_amd", "csrc", "imex3d.hip")
+        if t.get("kernels_sha256") == hashlib.sha256(open(src, "rb").read()).hexdigest():
+            traffic = t["bytes_per_launch"]["k_schur_apply"]
+    except (OSError, ValueError, KeyError):
+        traffic = None
     out["roofline"] = {"bound": "hbm", "kernel": "k_schur_apply", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                       "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                       "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                        "algorithmic_bytes_per_launch": 16 * g.n_unique, "avg_launch_ms": ms}
     ctx.close()
     return out
@@ -254,6 +322,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="only time a plain 1 GiB device copy")
     ap.add_argument("--no-imex3d", action="store_true", help="skip the 3D-IMEX measurement")
     ap.add_argument("--imex3d-only", action="store_true", help="only run the 3D-IMEX measurement (printed alone)")
+    ap.add_argument("--no-learned", action="store_true", help="3D-IMEX without the learned-correction run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -269,7 +338,7 @@ def main():
 
     torch.cuda.set_device(0)
     if args.imex3d_only:
-        print(json.dumps(imex3d(numa, torch)), flush=True)
+        print(json.dumps(imex3d(numa, torch, learned=not args.no_learned)), flush=True)
         return
     wl = W.box_large("R1")
     g = wl.grid
@@ -343,7 +412,7 @@ def main():
     if not args.no_ensemble:
         out["batched_ensemble"] = batched_ensemble(numa, torch)
     if not args.no_imex3d:
-        out["imex3d"] = imex3d(numa, torch)
+        out["imex3d"] = imex3d(numa, torch, learned=not args.no_learned)
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline()

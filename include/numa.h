@@ -286,7 +286,8 @@ int numa_imex3d_step(numa_ctx *c, double *state, double dt, double tol, int32_t 
  * max_samples, enabled}.
  * numa_learned_add_samples: r (device field) -> solves S e = r with the
  * polynomial preconditioner to |r - S e| <= tol |r| and appends the nelem
- * samples (x = r_e/s_e, t = (e - s(S) r)_e / s_e).  Synchronous.
+ * samples (x = r_e/s_e, t = (e - s(S) r)_e / s_e; elements with s_e below
+ * 1e-3 of the field's RMS give empty samples, x = t = 0).  Synchronous.
  * numa_learned_samples: copies samples first..first+n-1 to X, T (device,
  * n*nin floats each).
  * numa_learned_params: theta_in (host, nparam floats, nullable) replaces the

@@ -104,16 +104,20 @@ __global__ __launch_bounds__(kLB) void k_features(const double *r, float *X, dou
     }
 }
 
-// targets of a sample field: T[e][l] = (e_field - pb)_e / s_e
-__global__ __launch_bounds__(kLB) void k_targets(const double *ef, const double *pb, const double *se, float *T, int N,
-                                                 int nex, int ney, int nx, int ny)
+// targets of a sample field: T[e][l] = (e_field - pb)_e / s_e.  Elements
+// whose s_e is below `floor` (where the field is nearly zero, the
+// normalised target would be huge) become empty samples (X = T = 0).
+__global__ __launch_bounds__(kLB) void k_targets(const double *ef, const double *pb, const double *se, float *X,
+                                                 float *T, double floor, int N, int nex, int ney, int nx, int ny)
 {
     const int e = blockIdx.x, nq = N + 1, nin = nq * nq * nq;
     const double s = se[e];
+    const bool keep = s > floor && s > 0.0;
     for (int l = threadIdx.x; l < nin; l += kLB) {
         const int a = l % nq, b = (l / nq) % nq, cc = l / (nq * nq);
         const long I = elem_node(e, a, b, cc, N, nex, ney, nx, ny);
-        T[long(e) * nin + l] = s > 0.0 ? float((ef[I] - pb[I]) / s) : 0.0f;
+        T[long(e) * nin + l] = keep ? float((ef[I] - pb[I]) / s) : 0.0f;
+        if (!keep) X[long(e) * nin + l] = 0.0f;
     }
 }
 
@@ -332,7 +336,8 @@ hipError_t learned_correction_add(numa_ctx *c, const double *r, double *z, const
 }
 
 // one sample field r: solve S e = r (polynomial preconditioner, the network
-// off), append its element patches (r_e / s_e, (e - s(S) r)_e / s_e)
+// off), append its element patches (r_e / s_e, (e - s(S) r)_e / s_e); the
+// patches of elements with s_e below 1e-3 of the field's RMS stay empty
 hipError_t learned_add_samples(numa_ctx *c, const double *r, double tol, int *iters, int *converged)
 {
     Learned &L = *c->learned;
@@ -345,8 +350,18 @@ hipError_t learned_add_samples(numa_ctx *c, const double *r, double tol, int *it
     if ((e = pbno_apply(c, r, L.pb)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_features, dim3(unsigned(L.nelem)), dim3(kLB), 0, c->stream, r, L.X + L.nsamp * L.nin, L.se,
                        c->N, c->nex, c->ney, int(c->nx), int(c->ny));
+    // the field's RMS scale from the element scales (host, nelem values)
+    std::vector<double> se(size_t(L.nelem));
+    if ((e = hipMemcpyAsync(se.data(), L.se, sizeof(double) * se.size(), hipMemcpyDeviceToHost, c->stream)) !=
+        hipSuccess)
+        return e;
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+    double ms = 0.0;
+    for (double v : se) ms += v * v;
+    const double floor = 1e-3 * std::sqrt(ms / double(se.size()));
     hipLaunchKernelGGL(k_targets, dim3(unsigned(L.nelem)), dim3(kLB), 0, c->stream, L.e, L.pb, L.se,
-                       L.T + L.nsamp * L.nin, c->N, c->nex, c->ney, int(c->nx), int(c->ny));
+                       L.X + L.nsamp * L.nin, L.T + L.nsamp * L.nin, floor, c->N, c->nex, c->ney, int(c->nx),
+                       int(c->ny));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     L.nsamp += L.nelem;
     return hipSuccess;
