@@ -121,6 +121,42 @@ def precision_form(numa, torch, ctx, wl, args, t_fp64):
     }
 
 
+def standard_form_columns(numa, torch, ctx, wl, q, reps=20):
+    """The column solve in its standard (rho', w) form against the Schur
+    form on the benchmark grid: factor bytes, milliseconds per solve (HIP
+    events around `reps` solves of the same right-hand side) and the
+    relative L2 difference of the two solutions per variable."""
+    import numpy as np
+    y = q.clone()
+    xs, xk = torch.empty_like(y), torch.empty_like(y)
+    t0 = time.perf_counter()
+    nbytes = numa.factor_columns_standard(ctx.ctx, wl.dt)
+    torch.cuda.synchronize()
+    t_factor = time.perf_counter() - t0
+
+    def timed(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_std = timed(lambda: numa.solve_columns_standard(ctx.ctx, y.data_ptr(), xs.data_ptr()))
+    ms_schur = timed(lambda: numa.solve_columns(ctx.ctx, y.data_ptr(), xk.data_ptr()))
+    ctx.check()
+    a, b = xs.cpu().numpy(), xk.cpu().numpy()
+    diff = {n: float(np.linalg.norm(a[f] - b[f]) / np.linalg.norm(b[f])) for f, n in ((0, "rho'"), (3, "w"))}
+    info = ctx.info()
+    schur_bytes = info["nz"] * (4 * wl.grid.N + 1) * info["ncol"] * 8
+    return {"entry": "numa_solve_columns_standard", "factor_bytes": nbytes, "schur_factor_bytes": schur_bytes,
+            "factor_s": t_factor, "ms_per_solve": ms_std, "schur_ms_per_solve": ms_schur,
+            "schur_speedup": ms_std / ms_schur, "rel_l2_vs_schur": diff}
+
+
 def batched_ensemble(numa, torch, steps=50):
     """Sixteen seeded domains of different sizes and orders (3..7), stepped
     (a) one after another with the eager FP64 step (the baseline), (b)
@@ -407,6 +443,7 @@ def main():
         "kernels": per,
         "step_algorithmic_GBps": step_bytes * args.steps / t / 1e9,
     }
+    out["standard_form_columns"] = standard_form_columns(numa, torch, ctx, wl, q)
     if not args.no_precision:
         out["precision_form"] = precision_form(numa, torch, ctx, wl, args, t)
     if not args.no_ensemble:

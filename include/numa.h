@@ -214,6 +214,23 @@ int numa_rhs(numa_ctx *c, const double *state, double *rhs_out);
 int numa_solve_columns(numa_ctx *c, const double *y, double *x);
 
 /*
+ * Standard-form column solve, a comparison point for the Schur form (Sec. 5,
+ * Sec. 5.4): the same x = (I - lambda L_V)^{-1} y as numa_solve_columns, but
+ * solving for (rho', w) together, unknowns interleaved per level, a band of
+ * half-width 2N+1 factored without pivoting.  Its matrix is far worse
+ * conditioned than the Schur matrix (about 1e6 against 1e2 at vertical
+ * Courant number 15), so it agrees with the Schur solve to about 1e-9, not to
+ * rounding.  numa_factor_columns_standard: factors at lambda(dt) (allocated
+ * on first use; *bytes_out, nullable host, = their size).  Asynchronous.
+ * numa_solve_columns_standard: as numa_solve_columns (y, x state-contract
+ * device arrays, not overlapping; u, v, theta' copied through).
+ * Asynchronous.  Errors: NUMA_E_ARG, NUMA_E_NOT_FACTORED, NUMA_E_NOMEM,
+ * NUMA_E_HIP (a zero or non-finite pivot is reported by numa_check).
+ */
+int numa_factor_columns_standard(numa_ctx *c, double dt, int64_t *bytes_out);
+int numa_solve_columns_standard(numa_ctx *c, const double *y, double *x);
+
+/*
  * 3D-IMEX (Sec. 2): the implicit part of the ARK2 step is the whole linear
  * operator L (horizontal acoustics included) instead of L_V, and each
  * implicit system (I - lambda L) x = y is solved iteratively (Sec. 5.5) in

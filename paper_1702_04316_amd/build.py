@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnuma_hevi.so")
-SOURCES = ["abi.cpp", "setup.cpp", "ensemble.cpp", "kernels.hip", "imex3d.hip", "learned.hip"]
+SOURCES = ["abi.cpp", "setup.cpp", "ensemble.cpp", "kernels.hip", "imex3d.hip", "learned.hip", "colstd.hip"]
 ARCH = "gfx950"
 
 

@@ -36,6 +36,7 @@ void free_ctx(numa_ctx *c)
     if (c->work) (void)hipFree(c->work);
     if (c->work_mix) (void)hipFree(c->work_mix);
     if (c->flag) (void)hipFree(c->flag);
+    if (c->fac_std) (void)hipFree(c->fac_std);
     numa::learned_free(c);
     numa::imex3d_free(c);
     delete c;
@@ -332,6 +333,32 @@ int numa_solve_columns(numa_ctx *c, const double *y, double *x)
     if (!c->factored) return fail(c, NUMA_E_NOT_FACTORED, "numa_solve_columns: call numa_factor_columns first");
     hipError_t e = numa::launch_solve_plain(c, y, x);
     if (e != hipSuccess) return hip_fail(c, e, "numa_solve_columns");
+    return NUMA_OK;
+}
+
+int numa_factor_columns_standard(numa_ctx *c, double dt, int64_t *bytes_out)
+{
+    if (!c) return NUMA_E_ARG;
+    if (!finite_pos(dt)) return fail(c, NUMA_E_ARG, "numa_factor_columns_standard: dt must be finite and > 0");
+    const double lambda = (1.0 - 1.0 / std::sqrt(2.0)) * dt;
+    c->std_factored = 0;
+    hipError_t e = numa::launch_factor_std(c, lambda);
+    if (e != hipSuccess) return hip_fail(c, e, "numa_factor_columns_standard");
+    c->std_factored = 1;
+    c->dt_std = dt;
+    c->lambda_std = lambda;
+    if (bytes_out) *bytes_out = int64_t(numa::std_factor_bytes(c));
+    return NUMA_OK;
+}
+
+int numa_solve_columns_standard(numa_ctx *c, const double *y, double *x)
+{
+    if (!c) return NUMA_E_ARG;
+    if (!y || !x) return fail(c, NUMA_E_ARG, "numa_solve_columns_standard: null pointer");
+    if (!c->std_factored)
+        return fail(c, NUMA_E_NOT_FACTORED, "numa_solve_columns_standard: call numa_factor_columns_standard first");
+    hipError_t e = numa::launch_solve_std(c, y, x);
+    if (e != hipSuccess) return hip_fail(c, e, "numa_solve_columns_standard");
     return NUMA_OK;
 }
 

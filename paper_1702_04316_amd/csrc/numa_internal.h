@@ -72,6 +72,9 @@ struct numa_ctx {
     int rhs_zchunk = 0;            // z elements per RHS workgroup (0 = auto)
     numa::Imex3d *imex = nullptr;  // 3D-IMEX solver (numa_imex3d_setup)
     numa::Learned *learned = nullptr;  // learned correction (numa_learned_setup)
+    double *fac_std = nullptr;     // standard-form column factors [2 nz][4N+3][ncol]
+    int std_factored = 0;
+    double dt_std = 0, lambda_std = 0;
     std::string err;
 };
 
@@ -119,6 +122,11 @@ hipError_t imex3d_solve(numa_ctx *c, const double *y, double *out, const double 
                         double d1, double tol, int *iters, int *converged);
 hipError_t imex3d_step(numa_ctx *c, double *q, double dt, double tol, int *iters, int *converged);
 hipError_t schur_solve_field(numa_ctx *c, const double *r, double *e_out, double tol, int *iters, int *converged);
+
+// colstd.hip: the standard-form column solve (comparison point)
+size_t std_factor_bytes(const numa_ctx *c);
+hipError_t launch_factor_std(numa_ctx *c, double lambda);
+hipError_t launch_solve_std(numa_ctx *c, const double *y, double *x);
 
 // learned.hip: the learned correction of the preconditioner
 bool learned_enabled(const numa_ctx *c);

@@ -97,6 +97,8 @@ def load():
     lib.numa_pbno_apply.argtypes = [vp, vp, vp]
     lib.numa_imex3d_solve.argtypes = [vp, vp, vp, C.c_double, C.POINTER(C.c_int32)]
     lib.numa_imex3d_step.argtypes = [vp, vp, C.c_double, C.c_double, C.POINTER(C.c_int32)]
+    lib.numa_factor_columns_standard.argtypes = [vp, C.c_double, C.POINTER(C.c_int64)]
+    lib.numa_solve_columns_standard.argtypes = [vp, vp, vp]
     lib.numa_learned_setup.argtypes = [vp, C.c_int32, C.c_int64, C.c_uint64]
     lib.numa_learned_info.argtypes = [vp, C.POINTER(C.c_int64)]
     lib.numa_learned_add_samples.argtypes = [vp, vp, C.c_double, C.POINTER(C.c_int32)]
@@ -122,7 +124,8 @@ def load():
                  "numa_imex3d_bounds", "numa_imex3d_set_bounds", "numa_schur_apply", "numa_schur_rhs",
                  "numa_pbno_apply", "numa_imex3d_solve", "numa_learned_setup", "numa_learned_info",
                  "numa_learned_add_samples", "numa_learned_samples", "numa_learned_params", "numa_learned_loss_grad",
-                 "numa_learned_train", "numa_learned_enable", "numa_learned_apply"):
+                 "numa_learned_train", "numa_learned_enable", "numa_learned_apply", "numa_factor_columns_standard",
+                 "numa_solve_columns_standard"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -320,6 +323,16 @@ def imex3d_solve(ctx, y_ptr, x_ptr, tol):
     it = C.c_int32(0)
     _check(load().numa_imex3d_solve(ctx, C.c_void_p(y_ptr), C.c_void_p(x_ptr), float(tol), C.byref(it)), ctx)
     return it.value
+
+
+def factor_columns_standard(ctx, dt):
+    nb = C.c_int64(0)
+    _check(load().numa_factor_columns_standard(ctx, float(dt), C.byref(nb)), ctx)
+    return nb.value
+
+
+def solve_columns_standard(ctx, y_ptr, x_ptr):
+    return _check(load().numa_solve_columns_standard(ctx, C.c_void_p(y_ptr), C.c_void_p(x_ptr)), ctx)
 
 
 def learned_setup(ctx, hidden=64, max_samples=24576, seed=1):
