@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0
 def kernel_bytes(np_, ncol, nz, N):
     """Algorithmic HBM bytes per launch of the five kernels of a step: whole
     unique-node field passes (reads + writes) and the column factor reads."""
-    F = ncol * nz * (4 * N + 1) * 8
+    F = nz * (4 * N + 1) * 8  # one factor set shared by all columns (identical column operators)
     f = 8 * np_
     return [
         ("rhs_stage1", 10 * f),          # reads q^n (5), writes R1 (5)

@@ -107,8 +107,10 @@ int numa_set_stream(numa_ctx *c, void *hip_stream);
  * Eqs. (14)-(17), restricted to the vertical; Sec. 5.4: block-diagonal by
  * column, factored once and stored), at lambda = (1 - 1/sqrt(2)) dt, the
  * diagonal of the ARK2 implicit tableau (Table 1).  Banded LU without
- * pivoting, half-bandwidth 2N (Alg. 9); the factors stay on the device, one
- * set per column.  dt > 0.  Errors: NUMA_E_ARG, NUMA_E_HIP (a zero or
+ * pivoting, half-bandwidth 2N (Alg. 9); the factors stay on the device.
+ * Every column of a context has the same operator (uniform horizontal grid,
+ * one set of vertical faces, horizontally uniform background), so one
+ * factor set serves all columns.  dt > 0.  Errors: NUMA_E_ARG, NUMA_E_HIP (a zero or
  * non-finite pivot is reported by numa_check as NUMA_E_NONFINITE).
  */
 int numa_factor_columns(numa_ctx *c, double dt);

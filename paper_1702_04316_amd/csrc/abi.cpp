@@ -48,9 +48,9 @@ int64_t step_bytes_model(const numa_ctx *c)
 {
     // Field passes per step of the fused schedule (reads + writes of whole
     // unique-node fields): K1 5+5, K2 5+2, K3 12+10, K4 9+2, K5 10+5 = 65,
-    // plus two reads of the column factors.
+    // plus two reads of the (shared) column factors.
     const int64_t fields = 65;
-    const int64_t fac = c->ncol * c->nz * (4 * c->N + 1) * int64_t(sizeof(double));
+    const int64_t fac = c->nz * (4 * c->N + 1) * int64_t(sizeof(double));  // one set shared by all columns
     return fields * c->np * int64_t(sizeof(double)) + 2 * fac;
 }
 
@@ -164,7 +164,9 @@ int numa_setup(const numa_grid *g, int32_t order, const numa_background *bg, voi
     c->lev.D = p; p += (N + 1) * (N + 1);
     c->lev.scf = p;
 
-    const size_t fac_n = size_t(c->ncol) * size_t(nz) * size_t(4 * N + 1);
+    // every column has the same operator (uniform horizontal grid, one set of
+    // vertical faces, horizontally uniform background): one factor set
+    const size_t fac_n = size_t(nz) * size_t(4 * N + 1);
     const size_t work_n = size_t(19) * size_t(c->np);
     e = hipMalloc(&c->fac, fac_n * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&c->work, work_n * sizeof(double));
@@ -210,7 +212,7 @@ int numa_get_info(const numa_ctx *c, numa_info *info)
     info->ny = c->ny;
     info->nz = c->nz;
     info->ncol = c->ncol;
-    info->factor_bytes = c->ncol * c->nz * (4 * c->N + 1) * int64_t(sizeof(double));
+    info->factor_bytes = c->nz * (4 * c->N + 1) * int64_t(sizeof(double));
     info->scratch_bytes = 19 * c->np * int64_t(sizeof(double));
     info->step_bytes = step_bytes_model(c);
     info->order = c->N;

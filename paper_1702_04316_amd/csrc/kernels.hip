@@ -635,8 +635,7 @@ struct SolveGeom {
     static constexpr int HB = 2 * N;   // half-bandwidth of S
     static constexpr int NE = SH::NR + SH::NW + SH::NT;
     static constexpr int depth(int per_level) { return 56 / per_level < 1 ? 1 : (56 / per_level > 8 ? 8 : 56 / per_level); }
-    static constexpr int DF = depth(NE + HB);                   // forward: estimates + L row
-    static constexpr int DB = depth(HB + 1);                    // backward: U row
+    static constexpr int DF = depth(NE);                        // forward: the estimates
     static constexpr int DX = depth(1 + SH::NBW + SH::NBR);     // extraction
     // ring of rho0*w levels (>= 2N+1 for the band window, >= HB for the
     // reads of P below level 0)
@@ -650,7 +649,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     using G = SolveGeom<N, SH>;
     extern __shared__ double smem[];
     constexpr int NS = 2 * N + 1, NB = 4 * N + 1, HB = G::HB, R = G::R, NE = G::NE;
-    constexpr int DF = G::DF, DB = G::DB, DX = G::DX, NXL = 1 + SH::NBW + SH::NBR;
+    constexpr int DF = G::DF, DX = G::DX, NXL = 1 + SH::NBW + SH::NBR;
     const int lane = threadIdx.x;
     const long col = (long)blockIdx.x * 64 + lane;
     const bool act = col < p.ncol;
@@ -668,15 +667,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     for (int k = 0; k < R; ++k) W[k * 64] = 0.0;
     for (int k = 0; k < HB; ++k) P[(M + k) * 64] = 0.0;
     // row d of the factor band of level k
-    auto frow = [&](int k, int d) { return p.fac + ((long)k * NB + d) * p.ncol; };
+    // the factor band, one set shared by all columns: [k][d], read through
+    // the constant address space (scalar loads, cached for every wavefront)
+    cdouble *fac = as_const(p.fac);
 
     // ---- forward.  Step s: P_e and rho0 w_a of level s into LDS (w_a also
     //      parked in p.park for the extraction), then the substitution of
     //      level s - N, whose Dz(rho0 w_a) band is complete:
     //      y_k = P_e,k - lambda G0 Dz(rho0 w_a)_k - sum_d L_kd y_{k-d}
     {
-        double es[DF][NE], ls[DF][HB];
-        auto load = [&](double *e, double *l, int s) {
+        double es[DF][NE];
+        auto load = [&](double *e, int s) {
             const unsigned off = unsigned(min(s, M - 1)) * lbytes + cbyte;
             // (t = 0..2 spelled out: the element type is a template argument)
             if constexpr (SH::NR > 0) e[0] = tload<SolveT<SH, 0>>(p.er[0], off);
@@ -688,12 +689,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
             if constexpr (SH::NT > 0) e[SH::NR + SH::NW + 0] = tload<SolveT<SH, 6>>(p.et[0], off);
             if constexpr (SH::NT > 1) e[SH::NR + SH::NW + 1] = tload<SolveT<SH, 7>>(p.et[1], off);
             if constexpr (SH::NT > 2) e[SH::NR + SH::NW + 2] = tload<SolveT<SH, 8>>(p.et[2], off);
-            const int kl = min(max(s - N, 0), M - 1);
-#pragma unroll
-            for (int d = 0; d < HB; ++d) l[d] = gload(frow(kl, d), cbyte);  // column kl - HB + d
         };
 #pragma unroll
-        for (int b = 0; b < DF; ++b) load(es[b], ls[b], b);
+        for (int b = 0; b < DF; ++b) load(es[b], b);
         for (int s0 = 0; s0 < M + N; s0 += DF) {
 #pragma unroll
             for (int b = 0; b < DF; ++b) {
@@ -721,35 +719,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
                     for (int m = 0; m < NS; ++m) d += bz[m] * W[((k - N + m) & (R - 1)) * 64];
                     double y = P[k * 64] - scf[k * SC_N + SC_LG] * d;
 #pragma unroll
-                    for (int dd = 0; dd < HB; ++dd) y -= ls[b][dd] * P[(k - HB + dd) * 64];
+                    for (int dd = 0; dd < HB; ++dd) y -= fac[k * NB + dd] * P[(k - HB + dd) * 64];  // column k - HB + dd
                     P[k * 64] = y;
                 }
-                load(es[b], ls[b], s + DF);
+                load(es[b], s + DF);
             }
         }
     }
     // ---- backward substitution (U; the reciprocal pivot is stored)
     {
-        double us[DB][HB + 1];
-        auto load = [&](double *u, int s) {
-            const int k = max(M - 1 - s, 0);
+        for (int k = M - 1; k >= 0; --k) {
+            cdouble *u = fac + k * NB + HB;  // U row of level k: reciprocal pivot, then columns k + 1 .. k + HB
+            double x = P[k * 64];
 #pragma unroll
-            for (int d = 0; d <= HB; ++d) u[d] = gload(frow(k, HB + d), cbyte);  // column k + d
-        };
-#pragma unroll
-        for (int b = 0; b < DB; ++b) load(us[b], b);
-        for (int s0 = 0; s0 < M; s0 += DB) {
-#pragma unroll
-            for (int b = 0; b < DB; ++b) {
-                const int k = M - 1 - (s0 + b);
-                if (k >= 0) {
-                    double x = P[k * 64];
-#pragma unroll
-                    for (int dd = 1; dd <= HB; ++dd) x -= us[b][dd] * P[(k + dd) * 64];
-                    P[k * 64] = x * us[b][0];
-                }
-                load(us[b], s0 + b + DB);
-            }
+            for (int dd = 1; dd <= HB; ++dd) x -= u[dd] * P[(k + dd) * 64];
+            P[k * 64] = x * u[0];
         }
     }
     // ---- extraction.  Step s: w~_s = B (w_a - lambda (Dz P / rho0 + g P /
@@ -985,9 +969,9 @@ hipError_t solve_launch(numa_ctx *c, SolveParams p)
 template <int N>
 hipError_t factor_launch(numa_ctx *c, double lambda)
 {
-    dim3 grid(unsigned((c->ncol + 63) / 64));
-    hipLaunchKernelGGL((k_factor<N>), grid, dim3(64), 0, c->stream, c->lev.dzb, c->lev.G0, lambda, c->eos.grav,
-                       int(c->nz), c->ncol, c->fac, c->flag);
+    // one factor set, shared by all columns (their matrices are identical)
+    hipLaunchKernelGGL((k_factor<N>), dim3(1), dim3(64), 0, c->stream, c->lev.dzb, c->lev.G0, lambda, c->eos.grav,
+                       int(c->nz), 1L, c->fac, c->flag);
     return hipGetLastError();
 }
 
