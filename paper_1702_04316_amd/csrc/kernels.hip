@@ -641,9 +641,13 @@ struct SolveGeom {
     // reads of P below level 0)
     static constexpr int R = (2 * N + 1) <= 16 ? 16 : 32;
     static size_t lds_bytes(int M) { return size_t(R + M + HB) * 64 * sizeof(double); }
+    // the shared factor band is staged in LDS too when the total fits a CU
+    static size_t fac_bytes(int M) { return size_t(M) * (4 * N + 1) * sizeof(double); }
+    static bool fac_in_lds(int M) { return lds_bytes(M) + fac_bytes(M) <= kLdsPerCU; }
+    static size_t lds_total(int M) { return lds_bytes(M) + (fac_in_lds(M) ? fac_bytes(M) : 0); }
 };
 
-template <int N, class SH>
+template <int N, class SH, bool FL>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_colsolve(SolveParams p)
 {
     using G = SolveGeom<N, SH>;
@@ -667,9 +671,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     for (int k = 0; k < R; ++k) W[k * 64] = 0.0;
     for (int k = 0; k < HB; ++k) P[(M + k) * 64] = 0.0;
     // row d of the factor band of level k
-    // the factor band, one set shared by all columns: [k][d], read through
-    // the constant address space (scalar loads, cached for every wavefront)
-    cdouble *fac = as_const(p.fac);
+    // the factor band, one set shared by all columns: [k][d].  FL: staged in
+    // LDS after P (broadcast reads); otherwise read through the constant
+    // address space (scalar loads)
+    double *facl = smem + (R + M + HB) * 64;
+    if constexpr (FL) {
+        for (int e = lane; e < M * NB; e += 64) facl[e] = p.fac[e];
+        __syncthreads();
+    }
+    auto fac = [&](int idx) -> double {
+        if constexpr (FL) return facl[idx];
+        else return as_const(p.fac)[idx];
+    };
 
     // ---- forward.  Step s: P_e and rho0 w_a of level s into LDS (w_a also
     //      parked in p.park for the extraction), then the substitution of
@@ -719,7 +732,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
                     for (int m = 0; m < NS; ++m) d += bz[m] * W[((k - N + m) & (R - 1)) * 64];
                     double y = P[k * 64] - scf[k * SC_N + SC_LG] * d;
 #pragma unroll
-                    for (int dd = 0; dd < HB; ++dd) y -= fac[k * NB + dd] * P[(k - HB + dd) * 64];  // column k - HB + dd
+                    for (int dd = 0; dd < HB; ++dd) y -= fac(k * NB + dd) * P[(k - HB + dd) * 64];  // column k - HB + dd
                     P[k * 64] = y;
                 }
                 load(es[b], s + DF);
@@ -729,11 +742,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     // ---- backward substitution (U; the reciprocal pivot is stored)
     {
         for (int k = M - 1; k >= 0; --k) {
-            cdouble *u = fac + k * NB + HB;  // U row of level k: reciprocal pivot, then columns k + 1 .. k + HB
+            const int u = k * NB + HB;  // U row of level k: reciprocal pivot, then columns k + 1 .. k + HB
             double x = P[k * 64];
 #pragma unroll
-            for (int dd = 1; dd <= HB; ++dd) x -= u[dd] * P[(k + dd) * 64];
-            P[k * 64] = x * u[0];
+            for (int dd = 1; dd <= HB; ++dd) x -= fac(u + dd) * P[(k + dd) * 64];
+            P[k * 64] = x * fac(u);
         }
     }
     // ---- extraction.  Step s: w~_s = B (w_a - lambda (Dz P / rho0 + g P /
@@ -908,17 +921,26 @@ hipError_t rhs_prepare(size_t lds)
     return hipSuccess;
 }
 
-template <int N, class SH>
-hipError_t solve_prepare(size_t shm)
+template <int N, class SH, bool FL>
+hipError_t solve_prepare_fl(size_t shm)
 {
     static size_t attr_set = 0;  // tall columns need LDS above 64 KB
     if (shm > 65536 && attr_set < shm) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_colsolve<N, SH>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_colsolve<N, SH, FL>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
         if (e != hipSuccess) return e;
         attr_set = shm;
     }
     return hipSuccess;
+}
+
+// the LDS opt-in of the column-solve variant used for M levels
+template <int N, class SH>
+hipError_t solve_prepare(int M)
+{
+    using G = SolveGeom<N, SH>;
+    return G::fac_in_lds(M) ? solve_prepare_fl<N, SH, true>(G::lds_total(M))
+                            : solve_prepare_fl<N, SH, false>(G::lds_total(M));
 }
 
 template <int N, int EPI, bool HASB, bool MIX = false>
@@ -958,11 +980,16 @@ hipError_t solve_launch(numa_ctx *c, SolveParams p)
     p.lambda = c->lambda;
     p.nz = int(c->nz);
     p.ncol = c->ncol;
-    const size_t shm = SolveGeom<N, SH>::lds_bytes(int(c->nz));
-    hipError_t e = solve_prepare<N, SH>(shm);
+    using G = SolveGeom<N, SH>;
+    const int M = int(c->nz);
+    const size_t shm = G::lds_total(M);
+    hipError_t e = solve_prepare<N, SH>(M);
     if (e != hipSuccess) return e;
     dim3 grid(unsigned((c->ncol + 63) / 64));
-    hipLaunchKernelGGL((k_colsolve<N, SH>), grid, dim3(64), shm, c->stream, p);
+    if (G::fac_in_lds(M))
+        hipLaunchKernelGGL((k_colsolve<N, SH, true>), grid, dim3(64), shm, c->stream, p);
+    else
+        hipLaunchKernelGGL((k_colsolve<N, SH, false>), grid, dim3(64), shm, c->stream, p);
     return hipGetLastError();
 }
 
@@ -1329,15 +1356,15 @@ hipError_t prepare_step(numa_ctx *c, bool mixed)
             if (e == hipSuccess) e = rhs_prepare<NN, EPI_R, false, false>(lds);
             if (e == hipSuccess) e = rhs_prepare<NN, EPI_TWO, true, false>(lds);
             if (e == hipSuccess) e = rhs_prepare<NN, EPI_FINAL, false, false>(lds);
-            if (e == hipSuccess) e = solve_prepare<NN, ShapeStage2>(SolveGeom<NN, ShapeStage2>::lds_bytes(nz));
-            if (e == hipSuccess) e = solve_prepare<NN, ShapeStage3>(SolveGeom<NN, ShapeStage3>::lds_bytes(nz));
+            if (e == hipSuccess) e = solve_prepare<NN, ShapeStage2>(nz);
+            if (e == hipSuccess) e = solve_prepare<NN, ShapeStage3>(nz);
         } else {
             const size_t lds = rhs_lds_bytes<NN, true>(zc, nez);
             if (e == hipSuccess) e = rhs_prepare<NN, EPI_R, false, true>(lds);
             if (e == hipSuccess) e = rhs_prepare<NN, EPI_TWO, true, true>(lds);
             if (e == hipSuccess) e = rhs_prepare<NN, EPI_FINAL, false, true>(lds);
-            if (e == hipSuccess) e = solve_prepare<NN, ShapeStage2Mix>(SolveGeom<NN, ShapeStage2Mix>::lds_bytes(nz));
-            if (e == hipSuccess) e = solve_prepare<NN, ShapeStage3Mix>(SolveGeom<NN, ShapeStage3Mix>::lds_bytes(nz));
+            if (e == hipSuccess) e = solve_prepare<NN, ShapeStage2Mix>(nz);
+            if (e == hipSuccess) e = solve_prepare<NN, ShapeStage3Mix>(nz);
         }
         return e;
     });
