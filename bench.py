@@ -150,8 +150,7 @@ def standard_form_columns(numa, torch, ctx, wl, q, reps=20):
     ctx.check()
     a, b = xs.cpu().numpy(), xk.cpu().numpy()
     diff = {n: float(np.linalg.norm(a[f] - b[f]) / np.linalg.norm(b[f])) for f, n in ((0, "rho'"), (3, "w"))}
-    info = ctx.info()
-    schur_bytes = info["nz"] * (4 * wl.grid.N + 1) * info["ncol"] * 8
+    schur_bytes = ctx.info()["factor_bytes"]
     return {"entry": "numa_solve_columns_standard", "factor_bytes": nbytes, "schur_factor_bytes": schur_bytes,
             "factor_s": t_factor, "ms_per_solve": ms_std, "schur_ms_per_solve": ms_schur,
             "schur_speedup": ms_std / ms_schur, "rel_l2_vs_schur": diff}

@@ -222,8 +222,9 @@ int numa_solve_columns(numa_ctx *c, const double *y, double *x);
  * half-width 2N+1 factored without pivoting.  Its matrix is far worse
  * conditioned than the Schur matrix (about 1e6 against 1e2 at vertical
  * Courant number 15), so it agrees with the Schur solve to about 1e-9, not to
- * rounding.  numa_factor_columns_standard: factors at lambda(dt) (allocated
- * on first use; *bytes_out, nullable host, = their size).  Asynchronous.
+ * rounding.  numa_factor_columns_standard: factors at lambda(dt), one set
+ * shared by the identical columns (allocated on first use; *bytes_out,
+ * nullable host, = their size).  Asynchronous.
  * numa_solve_columns_standard: as numa_solve_columns (y, x state-contract
  * device arrays, not overlapping; u, v, theta' copied through).
  * Asynchronous.  Errors: NUMA_E_ARG, NUMA_E_NOT_FACTORED, NUMA_E_NOMEM,

@@ -9,7 +9,8 @@
 // rho'_1, w_1, ...), so the matrix is a band of half-width 2N+1; it is
 // factored without pivoting (growth stays near 1 because the diagonal
 // blocks are the identity) and solved by band substitution, one column per
-// thread, factors stored [row][band offset][col] like the Schur factors.
+// thread.  As for the Schur form, every column has the same matrix, so one
+// factor set [row][band offset] serves them all.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -86,7 +87,8 @@ __global__ __launch_bounds__(64) void k_solve_std(const double *__restrict__ fac
     const long col = (long)blockIdx.x * 64 + threadIdx.x;
     if (col >= ncol) return;
     const int n = 2 * M;
-    auto F = [&](int r, int d) { return fac[((long)r * NB + d) * ncol + col]; };  // d = c - r + K
+    // the shared factor band (all columns alike), d = c - r + K
+    auto F = [&](int r, int d) { return fac[(long)r * NB + d]; };
     auto at = [&](int k) { return (long)k * ncol + col; };
     // forward (unit lower): z_r = b_r - sum_d L(r, r-d) z_{r-d}; the last K
     // values in a shift register (win[K-1] is z_{r-1})
@@ -151,9 +153,10 @@ hipError_t dispatch_std(int N, F &&f)
 
 }  // namespace
 
+// one factor set shared by all columns (their matrices are identical)
 size_t std_factor_bytes(const numa_ctx *c)
 {
-    return size_t(2 * c->nz) * size_t(2 * (2 * c->N + 1) + 1) * size_t(c->ncol) * sizeof(double);
+    return size_t(2 * c->nz) * size_t(2 * (2 * c->N + 1) + 1) * sizeof(double);
 }
 
 hipError_t launch_factor_std(numa_ctx *c, double lambda)
@@ -167,9 +170,8 @@ hipError_t launch_factor_std(numa_ctx *c, double lambda)
     }
     return dispatch_std(c->N, [&](auto n) {
         constexpr int NN = decltype(n)::value;
-        hipLaunchKernelGGL((k_factor_std<NN>), dim3(unsigned((c->ncol + 63) / 64)), dim3(64), 0, c->stream,
-                           c->lev.dzb, c->lev.rho0, c->lev.G0, lambda, c->eos.grav, int(c->nz), c->ncol, c->fac_std,
-                           c->flag);
+        hipLaunchKernelGGL((k_factor_std<NN>), dim3(1), dim3(64), 0, c->stream, c->lev.dzb, c->lev.rho0, c->lev.G0,
+                           lambda, c->eos.grav, int(c->nz), 1L, c->fac_std, c->flag);
         return hipGetLastError();
     });
 }

@@ -68,7 +68,7 @@ def test_standard_form_solve_parity(torch_cuda, numa_mod, oracle_mod, N, nex, ne
     ref = o.solve(y)
     ctx = numa_mod.Context(g)
     nbytes = numa_mod.factor_columns_standard(ctx.ctx, dt)
-    assert nbytes == 2 * g.nz * (4 * N + 3) * g.nx * g.ny * 8
+    assert nbytes == 2 * g.nz * (4 * N + 3) * 8  # one set shared by the identical columns
     yd = torch_cuda.from_numpy(y).cuda()
     xs = torch_cuda.empty_like(yd)
     numa_mod.solve_columns_standard(ctx.ctx, yd.data_ptr(), xs.data_ptr())
