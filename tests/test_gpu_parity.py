@@ -239,6 +239,76 @@ def test_mass_conservation(torch_cuda, numa_mod, oracle_mod):
         assert abs(np.sum(M * q[0]) - m0) < 1e-13 * np.sum(M * np.abs(q[0]))
 
 
+def test_translation_invariance(torch_cuda, numa_mod):
+    """x, y periodic with identical elements: shifting the state by whole
+    elements shifts the steps' result the same way (the shifted nodes fall
+    into other workgroup tiles, so this also checks the tiling)."""
+    g = _grid(4, 5, 3, 3, 2)
+    dt = W.dt_for_courant(g, 15.0, "z")
+    q0 = W.make_random_state(g, 12)
+    ctx = numa_mod.Context(g)
+    ctx.factor(dt)
+    a = _dev(torch_cuda, q0)
+    ctx.step(a, 3)
+    sx, sy = 2 * g.N, g.N
+    b = _dev(torch_cuda, np.roll(np.roll(q0, sx, axis=3), sy, axis=2))
+    ctx.step(b, 3)
+    ctx.check()
+    ref = np.roll(np.roll(_host(a), sx, axis=3), sy, axis=2)
+    e = _rel(_host(b), ref)
+    assert np.all(e < 1e-13), e
+
+
+def test_mirror_symmetry(torch_cuda, numa_mod):
+    """A state even in x (rho', v, w, theta' even, u odd about x = 0) stays
+    so: the LGL nodes and the DSS line operators are symmetric."""
+    g = _grid(4, 4, 3, 3, None)
+    dt = W.dt_for_courant(g, 15.0, "z")
+    q = W.make_random_state(g, 13)
+    m = lambda f: np.roll(f[..., ::-1], 1, axis=-1)  # node i -> node -i (mod nx)
+    sym = np.empty_like(q)
+    for f in range(5):
+        sgn = -1.0 if f == 1 else 1.0
+        sym[f] = 0.5 * (q[f] + sgn * m(q[f]))
+    ctx = numa_mod.Context(g)
+    ctx.factor(dt)
+    d = _dev(torch_cuda, sym)
+    ctx.step(d, 3)
+    ctx.check()
+    out = _host(d)
+    for f in range(5):
+        sgn = -1.0 if f == 1 else 1.0
+        assert np.linalg.norm(out[f] - sgn * m(out[f])) < 1e-11 * np.linalg.norm(out[f]), f
+
+
+def test_step_cost_does_not_depend_on_courant_number(torch_cuda, numa_mod):
+    """The direct column solve costs the same at any Courant number (Sec. 5.4):
+    one step at vertical Courant number 1, 15 and 150 (factored for each dt)
+    takes the same time within 10 % (the best of five timings each; the
+    state is the rest state, so no value-dependent path is taken)."""
+    wl = W.box_large("R1", nex=32, ney=32)
+    g = wl.grid
+    ctx = numa_mod.Context(g)
+    q = torch_cuda.zeros(ctx.shape, dtype=torch_cuda.float64, device="cuda")
+    times = {}
+    for c in (1.0, 15.0, 150.0):
+        dt = W.dt_for_courant(g, c, "z")
+        ctx.factor(dt)
+        ctx.step(q, 3)
+        best = []
+        for _ in range(5):
+            e0, e1 = torch_cuda.cuda.Event(enable_timing=True), torch_cuda.cuda.Event(enable_timing=True)
+            e0.record()
+            ctx.step(q, 10)
+            e1.record()
+            torch_cuda.cuda.synchronize()
+            best.append(e0.elapsed_time(e1) / 10)
+        times[c] = min(best)
+    ctx.check()
+    t = list(times.values())
+    assert max(t) < 1.10 * min(t), times
+
+
 def test_deterministic_and_resumable(torch_cuda, numa_mod):
     wl = W.box_small("R1")
     q0 = W.make_initial_state(wl)
