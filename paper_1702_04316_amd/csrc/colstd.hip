@@ -28,52 +28,68 @@ struct StdBand {
     static constexpr int NB = 2 * K + 1;  // stored band width
 };
 
+// Assembly and elimination of the one shared band by one workgroup: the
+// threads fill the entries, then for each pivot update the trailing window
+// in parallel and scale the pivot column.  The band is worked on in LDS when
+// it fits (kStdFactorLds bytes), else in place in global memory.
+constexpr int kStdFactorThreads = 256;
+constexpr size_t kStdFactorLds = 64 * 1024;
+
 template <int N>
-__global__ __launch_bounds__(64) void k_factor_std(const double *__restrict__ dzb, const double *__restrict__ rho0,
-                                                   const double *__restrict__ G0, double lambda, double grav, int M,
-                                                   long ncol, double *fac, int *flag)
+__global__ __launch_bounds__(kStdFactorThreads) void k_factor_std(const double *__restrict__ dzb,
+                                                                  const double *__restrict__ rho0,
+                                                                  const double *__restrict__ G0, double lambda,
+                                                                  double grav, int M, int in_lds, double *fac,
+                                                                  int *flag)
 {
+    extern __shared__ double band_lds[];
     constexpr int NS = 2 * N + 1, K = StdBand<N>::K, NB = StdBand<N>::NB;
-    const long col = (long)blockIdx.x * 64 + threadIdx.x;
-    if (col >= ncol) return;
+    const int tid = threadIdx.x;
     const int n = 2 * M;
-    auto A = [&](int r, int c) -> double & { return fac[((long)r * NB + (c - r + K)) * ncol + col]; };
+    double *A = in_lds ? band_lds : fac;  // entry (r, c) at r*NB + (c - r + K)
     auto dz = [&](int k, int m) -> double {
         const int d = m - k + N;
         return (d >= 0 && d < NS) ? dzb[(long)k * NS + d] : 0.0;
     };
-    for (int r = 0; r < n; ++r) {
+    for (int idx = tid; idx < n * NB; idx += kStdFactorThreads) {
+        const int r = idx / NB, c = r + idx % NB - K;
         const int k = r >> 1;
         const bool wrow = r & 1;
         const bool wall = k == 0 || k == M - 1;
-        for (int c = r - K; c <= r + K; ++c) {
-            double v = 0.0;
-            if (c >= 0 && c < n) {
-                const int m = c >> 1;
-                if (c == r) {
-                    v = 1.0;
-                } else if (!wrow && (c & 1)) {  // rho' row, w unknown of level m
-                    if (m >= 1 && m <= M - 2) v = lambda * dz(k, m) * rho0[m];
-                } else if (wrow && !(c & 1) && !wall) {  // w row, rho' unknown of level m
-                    v = lambda * (dz(k, m) * G0[m] + (m == k ? grav : 0.0)) / rho0[k];
-                }
+        double v = 0.0;
+        if (c >= 0 && c < n) {
+            const int m = c >> 1;
+            if (c == r) {
+                v = 1.0;
+            } else if (!wrow && (c & 1)) {  // rho' row, w unknown of level m
+                if (m >= 1 && m <= M - 2) v = lambda * dz(k, m) * rho0[m];
+            } else if (wrow && !(c & 1) && !wall) {  // w row, rho' unknown of level m
+                v = lambda * (dz(k, m) * G0[m] + (m == k ? grav : 0.0)) / rho0[k];
             }
-            fac[((long)r * NB + (c - r + K)) * ncol + col] = v;
         }
+        A[idx] = v;
     }
+    __syncthreads();
     bool bad = false;
     for (int k = 0; k < n; ++k) {
-        const double piv = A(k, k);
-        bad |= !(fabs(piv) > 0.0) || !isfinite(piv);
+        const double piv = A[k * NB + K];
         const double rp = 1.0 / piv;
-        const int e = min(k + K, n - 1);
-        for (int i = k + 1; i <= e; ++i) {
-            const double l = A(i, k) * rp;
-            A(i, k) = l;
-            for (int j = k + 1; j <= e; ++j) A(i, j) -= l * A(k, j);
+        const int w = min(k + K, n - 1) - k;
+        for (int t = tid; t < w * w; t += kStdFactorThreads) {
+            const int i = k + 1 + t / w, j = k + 1 + t % w;
+            const double l = A[i * NB + (k - i + K)] * rp;
+            A[i * NB + (j - i + K)] -= l * A[k * NB + (j - k + K)];
         }
-        A(k, k) = rp;  // the solve multiplies by the reciprocal pivot
+        __syncthreads();  // column k and the pivot are read above, written below
+        for (int t = tid; t < w; t += kStdFactorThreads) A[(k + 1 + t) * NB + (-1 - t + K)] *= rp;
+        if (tid == 0) {
+            bad |= !(fabs(piv) > 0.0) || !isfinite(piv);
+            A[k * NB + K] = rp;  // the solve multiplies by the reciprocal pivot
+        }
+        __syncthreads();
     }
+    if (in_lds)
+        for (int idx = tid; idx < n * NB; idx += kStdFactorThreads) fac[idx] = band_lds[idx];
     if (bad) *flag = 1;
 }
 
@@ -170,8 +186,11 @@ hipError_t launch_factor_std(numa_ctx *c, double lambda)
     }
     return dispatch_std(c->N, [&](auto n) {
         constexpr int NN = decltype(n)::value;
-        hipLaunchKernelGGL((k_factor_std<NN>), dim3(1), dim3(64), 0, c->stream, c->lev.dzb, c->lev.rho0, c->lev.G0,
-                           lambda, c->eos.grav, int(c->nz), 1L, c->fac_std, c->flag);
+        const size_t bytes = std_factor_bytes(c);
+        const bool lds = bytes <= kStdFactorLds;
+        hipLaunchKernelGGL((k_factor_std<NN>), dim3(1), dim3(kStdFactorThreads), lds ? bytes : 0, c->stream,
+                           c->lev.dzb, c->lev.rho0, c->lev.G0, lambda, c->eos.grav, int(c->nz), int(lds), c->fac_std,
+                           c->flag);
         return hipGetLastError();
     });
 }

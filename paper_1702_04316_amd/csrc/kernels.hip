@@ -4,13 +4,13 @@
 //             stage combinations (one pass over the state per evaluation)
 //  k_colsolve Schur-complement column solve with the stored band LU factors,
 //             fused with the stage right-hand side and the extraction
-//  k_factor   assembly and unpivoted band LU of every column's Schur matrix
+//  k_factor   assembly and unpivoted band LU of the column Schur matrix (one
+//             band shared by all columns, factored by one workgroup)
 //  k_background  P0, G0, H0 per level with the device equation of state
 //
 // Layout: fields are FP64 structure of arrays [var][k][j][i], i fastest, on
-// the unique nodes (x, y periodic).  Column factors are [k][m][col] with
-// col = j*nx + i fastest, so a wavefront of 64 columns loads 512 contiguous
-// bytes per factor entry.
+// the unique nodes (x, y periodic).  The column factors are one band
+// [k][m] that every column shares (all columns have the same matrix).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -824,47 +824,63 @@ __global__ void k_solve_coefs(const double *rho0, const double *G0, const double
 // ---------------------------------------------------------------------------
 // Column factorisation: S = I - lambda^2 G0 Dz rho0 B (Dz/rho0 + g/(G0 rho0))
 // = I - lambda^2 G0 Dz B (Dz + g/G0), assembled as a band of half-width 2N,
-// then Doolittle LU without pivoting (Alg. 9), one lane per column.
+// then Doolittle LU without pivoting (Alg. 9).  Every column has the same
+// matrix, so one workgroup factors the single shared band [row][offset]:
+// its threads assemble the entries, then for each pivot k update the
+// (2N x 2N) trailing window in parallel and scale column k.  Each entry sees
+// the same updates in the same order as a sequential elimination.  The band
+// is worked on in LDS when it fits (kFactorLds bytes), else in place in
+// global memory; both through one generic pointer.
 // ---------------------------------------------------------------------------
+constexpr int kFactorThreads = 256;
+constexpr size_t kFactorLds = 64 * 1024;
+
 template <int N>
-__global__ __launch_bounds__(64) void k_factor(const double *__restrict__ dzb, const double *__restrict__ G0,
-                                               double lambda, double grav, int M, long ncol, double *fac,
-                                               int *flag)
+__global__ __launch_bounds__(kFactorThreads) void k_factor(const double *__restrict__ dzb,
+                                                           const double *__restrict__ G0, double lambda, double grav,
+                                                           int M, int in_lds, double *fac, int *flag)
 {
+    extern __shared__ double band_lds[];
     constexpr int NS = 2 * N + 1, NB = 4 * N + 1, HB = 2 * N;
-    const long col = (long)blockIdx.x * 64 + threadIdx.x;
-    if (col >= ncol) return;
-    auto A = [&](int r, int cidx) -> double & { return fac[((long)r * NB + (cidx - r + HB)) * ncol + col]; };
+    const int tid = threadIdx.x;
+    double *A = in_lds ? band_lds : fac;  // entry (r, c) at r*NB + (c - r + HB)
     const double l2 = lambda * lambda;
-    for (int r = 0; r < M; ++r) {
-        for (int cidx = r - HB; cidx <= r + HB; ++cidx) {
-            if (cidx < 0 || cidx >= M) {
-                fac[((long)r * NB + (cidx - r + HB)) * ncol + col] = 0.0;
-                continue;
-            }
+    for (int idx = tid; idx < M * NB; idx += kFactorThreads) {
+        const int r = idx / NB, cidx = r + idx % NB - HB;
+        double v = 0.0;
+        if (cidx >= 0 && cidx < M) {
             double s = 0.0;
-            int mlo = max(max(r, cidx) - N, 1), mhi = min(min(r, cidx) + N, M - 2);
+            const int mlo = max(max(r, cidx) - N, 1), mhi = min(min(r, cidx) + N, M - 2);
             for (int m = mlo; m <= mhi; ++m) {
-                double drm = dzb[(long)r * NS + (m - r + N)];
-                double dmc = dzb[(long)m * NS + (cidx - m + N)];
+                const double drm = dzb[(long)r * NS + (m - r + N)];
+                const double dmc = dzb[(long)m * NS + (cidx - m + N)];
                 s += drm * (dmc + (m == cidx ? grav / G0[m] : 0.0));
             }
-            A(r, cidx) = (r == cidx ? 1.0 : 0.0) - l2 * G0[r] * s;
+            v = (r == cidx ? 1.0 : 0.0) - l2 * G0[r] * s;
         }
+        A[idx] = v;
     }
+    __syncthreads();
     bool bad = false;
     for (int k = 0; k < M; ++k) {
-        const double piv = A(k, k);
-        bad |= !(fabs(piv) > 0.0) || !isfinite(piv);
+        const double piv = A[k * NB + HB];
         const double rp = 1.0 / piv;
-        const int e = min(k + HB, M - 1);
-        for (int i = k + 1; i <= e; ++i) {
-            double l = A(i, k) * rp;
-            A(i, k) = l;
-            for (int jj = k + 1; jj <= e; ++jj) A(i, jj) -= l * A(k, jj);
+        const int w = min(k + HB, M - 1) - k;  // rows below / columns right of the pivot
+        for (int t = tid; t < w * w; t += kFactorThreads) {
+            const int i = k + 1 + t / w, jj = k + 1 + t % w;
+            const double l = A[i * NB + (k - i + HB)] * rp;
+            A[i * NB + (jj - i + HB)] -= l * A[k * NB + (jj - k + HB)];
         }
-        A(k, k) = rp;  // the solve multiplies by the reciprocal pivot
+        __syncthreads();  // column k and the pivot are read above, written below
+        for (int t = tid; t < w; t += kFactorThreads) A[(k + 1 + t) * NB + (-1 - t + HB)] *= rp;
+        if (tid == 0) {
+            bad |= !(fabs(piv) > 0.0) || !isfinite(piv);
+            A[k * NB + HB] = rp;  // the solve multiplies by the reciprocal pivot
+        }
+        __syncthreads();
     }
+    if (in_lds)
+        for (int idx = tid; idx < M * NB; idx += kFactorThreads) fac[idx] = band_lds[idx];
     if (bad) *flag = 1;
 }
 
@@ -997,8 +1013,10 @@ template <int N>
 hipError_t factor_launch(numa_ctx *c, double lambda)
 {
     // one factor set, shared by all columns (their matrices are identical)
-    hipLaunchKernelGGL((k_factor<N>), dim3(1), dim3(64), 0, c->stream, c->lev.dzb, c->lev.G0, lambda, c->eos.grav,
-                       int(c->nz), 1L, c->fac, c->flag);
+    const size_t bytes = size_t(c->nz) * (4 * N + 1) * sizeof(double);
+    const bool lds = bytes <= kFactorLds;
+    hipLaunchKernelGGL((k_factor<N>), dim3(1), dim3(kFactorThreads), lds ? bytes : 0, c->stream, c->lev.dzb,
+                       c->lev.G0, lambda, c->eos.grav, int(c->nz), int(lds), c->fac, c->flag);
     return hipGetLastError();
 }
 
