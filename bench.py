@@ -26,10 +26,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def kernel_bytes(np_, ncol, nz, N):
+def kernel_bytes(np_, ncol, nz, N, table_bytes=None):
     """Algorithmic HBM bytes per launch of the five kernels of a step: whole
-    unique-node field passes (reads + writes) and the column factor reads."""
-    F = nz * (4 * N + 1) * 8  # one factor set shared by all columns (identical column operators)
+    unique-node field passes (reads + writes) and the one table the column
+    solves read (the LU band, or the inverse for the dense solve; all
+    columns share it).  Default: the LU band."""
+    F = nz * (4 * N + 1) * 8 if table_bytes is None else table_bytes
     f = 8 * np_
     return [
         ("rhs_stage1", 10 * f),          # reads q^n (5), writes R1 (5)
@@ -150,10 +152,39 @@ def standard_form_columns(numa, torch, ctx, wl, q, reps=20):
     ctx.check()
     a, b = xs.cpu().numpy(), xk.cpu().numpy()
     diff = {n: float(np.linalg.norm(a[f] - b[f]) / np.linalg.norm(b[f])) for f, n in ((0, "rho'"), (3, "w"))}
-    schur_bytes = ctx.info()["factor_bytes"]
-    return {"entry": "numa_solve_columns_standard", "factor_bytes": nbytes, "schur_factor_bytes": schur_bytes,
-            "factor_s": t_factor, "ms_per_solve": ms_std, "schur_ms_per_solve": ms_schur,
-            "schur_speedup": ms_std / ms_schur, "rel_l2_vs_schur": diff}
+    info = ctx.info()
+    # the Schur form with band substitution, on a context of its own
+    cb = numa.Context(wl.grid, wl.background)
+    cb.set_column_solver(numa.SOLVER_BAND)
+    cb.factor(wl.dt)
+    ms_band = timed(lambda: numa.solve_columns(cb.ctx, y.data_ptr(), xk.data_ptr()))
+    cb.check()
+    band_bytes = cb.info()["factor_bytes"]
+    cb.close()
+    return {"entry": "numa_solve_columns_standard", "factor_bytes": nbytes,
+            "schur_solver": "dense" if info["column_solver"] == numa.SOLVER_DENSE else "band",
+            "schur_factor_bytes": info["factor_bytes"], "factor_s": t_factor, "ms_per_solve": ms_std,
+            "schur_ms_per_solve": ms_schur, "schur_speedup": ms_std / ms_schur, "rel_l2_vs_schur": diff,
+            "schur_band_ms_per_solve": ms_band, "schur_band_factor_bytes": band_bytes}
+
+
+def column_solver_ab(numa, torch, wl, q0, steps=50):
+    """The HEVI step with the band-substitution column solve instead of the
+    default: per-kernel milliseconds (HIP events, launch order) and ms per
+    step, on its own context and a copy of the state."""
+    c = numa.Context(wl.grid, wl.background)
+    c.set_column_solver(numa.SOLVER_BAND)
+    c.factor(wl.dt)
+    q = q0.clone()
+    c.step(q, 5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = numa.profile_steps(c.ctx, q.data_ptr(), wl.dt, steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    c.check()
+    c.close()
+    return {"solver": "band", "ms_per_step": 1e3 * t / steps, "kernels_ms": ms}
 
 
 def batched_ensemble(numa, torch, steps=50):
@@ -396,7 +427,7 @@ def main():
     info = ctx.info()
     dof = 5 * g.n_unique
     value = dof * args.steps / t
-    kb = kernel_bytes(g.n_unique, info["ncol"], info["nz"], g.N)
+    kb = kernel_bytes(g.n_unique, info["ncol"], info["nz"], g.N, info["factor_bytes"])
     per = [{"kernel": n, "ms": m, "GB/s": b / (m * 1e-3) / 1e9} for (n, b), m in zip(kb, ms)]
     dom = max(range(5), key=lambda i: ms[i])
     achieved = kb[dom][1] / (ms[dom] * 1e-3) / 1e9
@@ -443,6 +474,9 @@ def main():
         "step_algorithmic_GBps": step_bytes * args.steps / t / 1e9,
     }
     out["standard_form_columns"] = standard_form_columns(numa, torch, ctx, wl, q)
+    out["column_solver"] = {"in_use": "dense" if info["column_solver"] == numa.SOLVER_DENSE else "band",
+                            "band_substitution": column_solver_ab(numa, torch, wl,
+                                                                  torch.from_numpy(W.make_initial_state(wl)).to("cuda"))}
     if not args.no_precision:
         out["precision_form"] = precision_form(numa, torch, ctx, wl, args, t)
     if not args.no_ensemble:

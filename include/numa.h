@@ -67,12 +67,15 @@ typedef struct {
 typedef struct {
     int64_t nx, ny, nz;           /* unique-node grid                                 */
     int64_t ncol;                 /* vertical columns (nx*ny)                         */
-    int64_t factor_bytes;         /* device bytes of the stored column factors        */
+    int64_t factor_bytes;         /* bytes of the table a column solve reads: the LU
+                                     band, or the inverse for NUMA_SOLVER_DENSE       */
     int64_t scratch_bytes;        /* device bytes of the stage buffers                */
     int64_t step_bytes;           /* algorithmic HBM bytes moved per HEVI step        */
     int32_t order;                /* LGL order N                                      */
     int32_t factored;             /* 1 once numa_factor_columns succeeded             */
     double dt_factored;           /* dt of the stored factors                         */
+    int32_t column_solver;        /* NUMA_SOLVER_BAND or NUMA_SOLVER_DENSE, in use    */
+    int32_t reserved;
 } numa_info;
 
 /*
@@ -114,6 +117,24 @@ int numa_set_stream(numa_ctx *c, void *hip_stream);
  * non-finite pivot is reported by numa_check as NUMA_E_NONFINITE).
  */
 int numa_factor_columns(numa_ctx *c, double dt);
+
+/*
+ * How the column solves apply the factored matrix (the solution is the same
+ * up to rounding).  NUMA_SOLVER_BAND: forward and backward band substitution
+ * with the LU factors (Alg. 9), one lane per column.  NUMA_SOLVER_DENSE:
+ * the inverse of the column matrix, formed once per time-step size from
+ * the same factors, applied as a dense product per column; every column
+ * shares the matrix, so the inverse is one nz x nz table, and the product
+ * has no level-by-level recurrence.  It is available for columns of at most
+ * 64 - 2N levels.  NUMA_SOLVER_AUTO (the default): dense where available.
+ * Takes effect at the next numa_factor_columns; until then the context
+ * counts as not factored.  Errors: NUMA_E_ARG (unknown kind),
+ * NUMA_E_UNSUPPORTED (dense for a taller column).
+ */
+#define NUMA_SOLVER_AUTO 0
+#define NUMA_SOLVER_BAND 1
+#define NUMA_SOLVER_DENSE 2
+int numa_set_column_solver(numa_ctx *c, int32_t kind);
 
 /*
  * Advance state (device, see the state contract) in place by nsteps ARK2

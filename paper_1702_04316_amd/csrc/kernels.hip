@@ -606,6 +606,8 @@ struct SolveParams {
     // large vertical Courant numbers, so w_a must keep FP64 precision
     double *park;
     const double *fac;
+    const double *sinv;  // dense solve: S^-1 transposed, rows of stride ms
+    int ms;
     const double *scf, *dzb;
     double lambda;
     int nz;
@@ -801,6 +803,182 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     }
 }
 
+// ---------------------------------------------------------------------------
+// Column solve with the explicit inverse (short columns).  All columns share
+// S, so its inverse is formed once per dt (k_factor) and the solve becomes a
+// dense product x = S^-1 b per column.  When the band (4N+1 wide) is a large
+// part of the column that is about as many multiply-adds as the two band
+// substitutions, and it has no level-by-level recurrence.  A workgroup of
+// four wavefronts owns 64 columns (one per lane); wavefront g owns the
+// level block [g KL, (g+1) KL), KL = ms/4 <= kDenseKL, and keeps its
+// levels' values in registers.  One LDS array V, [N pad][M levels][N pad] x
+// 64 lanes, exchanges the one field a phase needs from other levels:
+//  1. the estimates: P_e and w_a in registers, V = rho0 w_a;
+//  2. b = P_e - lambda G0 Dz(rho0 w_a), then V = b;
+//  3. x = S^-1 b (the rows of S^-1 a wavefront needs are uniform across it
+//     and come through scalar loads), then V = x;
+//  4. w~ = B (w_a - lambda (Dz x / rho0 + g x / (G0 rho0))), w out, then
+//     V = rho0 w~;
+//  5. rho' = q_e,rho - lambda Dz(rho0 w~).
+// w_a never leaves the registers, so nothing is parked in HBM.  The pads
+// hold zeros and meet only zero band coefficients.
+// ---------------------------------------------------------------------------
+constexpr int kDenseKL = 16;
+
+constexpr int dense_chunk(int per_level) { return per_level >= 6 ? 4 : 8; }
+
+template <int N, class SH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_colsolve_dense(SolveParams p)
+{
+    extern __shared__ double smem[];
+    constexpr int NS = 2 * N + 1, KX = kDenseKL, NE = SolveGeom<N, SH>::NE;
+    constexpr int CF = dense_chunk(NE), CX = dense_chunk(1 + SH::NBW + SH::NBR);
+    const int lane = threadIdx.x & 63;
+    const int g = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const long col = (long)blockIdx.x * 64 + lane;
+    const bool act = col < p.ncol;
+    const unsigned cbyte = unsigned(act ? col : 0) * 8u;
+    const int M = p.nz, KL = p.ms >> 2, k0 = g * KL;
+    const int nk = max(0, min(KL, M - k0));  // levels of this wavefront
+    const unsigned lbytes = unsigned(p.ncol) * 8u;
+    cdouble *scf = as_const(p.scf);
+    cdouble *dzb = as_const(p.dzb);
+    double *V = smem + N * 64 + lane;  // V[k * 64], k in [-N, M + N)
+    for (int t = threadIdx.x; t < N * 64; t += 256) {
+        smem[t] = 0.0;
+        smem[(M + N) * 64 + t] = 0.0;
+    }
+    // Dz of the field in V at level s (band of half-width N)
+    auto dz_of_v = [&](int s) {
+        cdouble *bz = dzb + s * NS;
+        double d = 0.0;
+#pragma unroll
+        for (int m = 0; m < NS; ++m) d += bz[m] * V[(s - N + m) * 64];
+        return d;
+    };
+    double wa[KX], r[KX];  // w_a; then P_e, b, x, rho0 w~ in turn
+    // ---- 1. estimates, CF levels at a time (loads first, then the algebra)
+#pragma unroll
+    for (int i0 = 0; i0 < KX; i0 += CF) {
+        if (i0 < nk) {
+            double e[CF][NE];
+#pragma unroll
+            for (int b = 0; b < CF; ++b) {
+                const unsigned off = unsigned(k0 + min(i0 + b, nk - 1)) * lbytes + cbyte;
+                if constexpr (SH::NR > 0) e[b][0] = tload<SolveT<SH, 0>>(p.er[0], off);
+                if constexpr (SH::NR > 1) e[b][1] = tload<SolveT<SH, 1>>(p.er[1], off);
+                if constexpr (SH::NR > 2) e[b][2] = tload<SolveT<SH, 2>>(p.er[2], off);
+                if constexpr (SH::NW > 0) e[b][SH::NR + 0] = tload<SolveT<SH, 3>>(p.ew[0], off);
+                if constexpr (SH::NW > 1) e[b][SH::NR + 1] = tload<SolveT<SH, 4>>(p.ew[1], off);
+                if constexpr (SH::NW > 2) e[b][SH::NR + 2] = tload<SolveT<SH, 5>>(p.ew[2], off);
+                if constexpr (SH::NT > 0) e[b][SH::NR + SH::NW + 0] = tload<SolveT<SH, 6>>(p.et[0], off);
+                if constexpr (SH::NT > 1) e[b][SH::NR + SH::NW + 1] = tload<SolveT<SH, 7>>(p.et[1], off);
+                if constexpr (SH::NT > 2) e[b][SH::NR + SH::NW + 2] = tload<SolveT<SH, 8>>(p.et[2], off);
+            }
+#pragma unroll
+            for (int b = 0; b < CF; ++b) {
+                const int i = i0 + b, s = k0 + i;
+                if (i < nk) {
+                    double re = 0.0, we = 0.0, te = 0.0;
+#pragma unroll
+                    for (int t = 0; t < SH::NR; ++t) re += p.cr[t] * e[b][t];
+#pragma unroll
+                    for (int t = 0; t < SH::NW; ++t) we += p.cw[t] * e[b][SH::NR + t];
+#pragma unroll
+                    for (int t = 0; t < SH::NT; ++t) te += p.ct[t] * e[b][SH::NR + SH::NW + t];
+                    cdouble *cf = scf + s * SC_N;
+                    // w_a = B (w_e + lambda g H0 theta_e / (G0 rho0))  (Eq. (16), A = I)
+                    wa[i] = (s == 0 || s == M - 1) ? 0.0 : we + cf[SC_WA] * te;
+                    r[i] = cf[SC_G0] * re + cf[SC_H0] * te;
+                    V[s * 64] = cf[SC_RHO0] * wa[i];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // ---- 2. b = P_e - lambda G0 Dz(rho0 w_a)
+#pragma unroll
+    for (int i = 0; i < KX; ++i)
+        if (i < nk) r[i] -= scf[(k0 + i) * SC_N + SC_LG] * dz_of_v(k0 + i);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < KX; ++i)
+        if (i < nk) V[(k0 + i) * 64] = r[i];
+    __syncthreads();
+    // ---- 3. x = S^-1 b: x_k = sum_m (S^-T)[m][k] b_m for the own k
+    {
+#pragma unroll
+        for (int i = 0; i < KX; ++i) r[i] = 0.0;
+        cdouble *row = as_const(p.sinv) + k0;
+        for (int m = 0; m < M; ++m) {
+            const double bm = V[m * 64];
+#pragma unroll
+            for (int i = 0; i < KX; ++i) r[i] += row[i] * bm;
+            row += p.ms;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < KX; ++i)
+        if (i < nk) V[(k0 + i) * 64] = r[i];
+    __syncthreads();
+    // ---- 4. w~ and the w output
+#pragma unroll
+    for (int i0 = 0; i0 < KX; i0 += CX) {
+        if (i0 < nk) {
+            double xb[CX][2];
+#pragma unroll
+            for (int b = 0; b < CX; ++b) {
+                const unsigned off = unsigned(k0 + min(i0 + b, nk - 1)) * lbytes + cbyte;
+                if constexpr (SH::NBW > 0) xb[b][0] = tload<SolveT<SH, 11>>(p.bw[0], off);
+                if constexpr (SH::NBW > 1) xb[b][1] = tload<SolveT<SH, 12>>(p.bw[1], off);
+            }
+#pragma unroll
+            for (int b = 0; b < CX; ++b) {
+                const int i = i0 + b, s = k0 + i;
+                if (i < nk) {
+                    cdouble *cf = scf + s * SC_N;
+                    const double wt =
+                        (s == 0 || s == M - 1) ? 0.0 : wa[i] - (cf[SC_X1] * dz_of_v(s) + cf[SC_X2] * r[i]);
+                    double sh = 0.0;
+#pragma unroll
+                    for (int t = 0; t < SH::NBW; ++t) sh += p.cbw[t] * xb[b][t];
+                    r[i] = cf[SC_RHO0] * wt;
+                    if (act) tstore<SolveT<SH, 13>>(p.out_w, unsigned(s) * lbytes + cbyte, wt + sh);
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < KX; ++i)
+        if (i < nk) V[(k0 + i) * 64] = r[i];
+    __syncthreads();
+    // ---- 5. rho' = q_e,rho - lambda Dz(rho0 w~)
+#pragma unroll
+    for (int i0 = 0; i0 < KX; i0 += CX) {
+        if (i0 < nk) {
+            double xr[CX][2];
+#pragma unroll
+            for (int b = 0; b < CX; ++b) {
+                const unsigned off = unsigned(k0 + min(i0 + b, nk - 1)) * lbytes + cbyte;
+                if constexpr (SH::NBR > 0) xr[b][0] = tload<SolveT<SH, 9>>(p.br[0], off);
+                if constexpr (SH::NBR > 1) xr[b][1] = tload<SolveT<SH, 10>>(p.br[1], off);
+            }
+#pragma unroll
+            for (int b = 0; b < CX; ++b) {
+                const int i = i0 + b, k = k0 + i;
+                if (i < nk) {
+                    double qr = 0.0;
+#pragma unroll
+                    for (int t = 0; t < SH::NBR; ++t) qr += p.cbr[t] * xr[b][t];
+                    if (act) tstore<SolveT<SH, 14>>(p.out_r, unsigned(k) * lbytes + cbyte, qr - p.lambda * dz_of_v(k));
+                }
+            }
+        }
+    }
+}
+
 // Per-level coefficients of the column solve at lambda (Eqs. (16)-(17) in
 // 1D with A = I): G0, H0, rho0, lambda g H0/(G0 rho0), lambda G0,
 // lambda/rho0, lambda g/(G0 rho0).
@@ -838,7 +1016,8 @@ constexpr size_t kFactorLds = 64 * 1024;
 template <int N>
 __global__ __launch_bounds__(kFactorThreads) void k_factor(const double *__restrict__ dzb,
                                                            const double *__restrict__ G0, double lambda, double grav,
-                                                           int M, int in_lds, double *fac, int *flag)
+                                                           int M, int in_lds, double *fac, int *flag,
+                                                           double *sinv, int ms)
 {
     extern __shared__ double band_lds[];
     constexpr int NS = 2 * N + 1, NB = 4 * N + 1, HB = 2 * N;
@@ -881,6 +1060,28 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor(const double *__restr
     }
     if (in_lds)
         for (int idx = tid; idx < M * NB; idx += kFactorThreads) fac[idx] = band_lds[idx];
+    if (sinv) {
+        // the inverse for the dense column solve, from the factors: thread t
+        // solves S x = e_t, so x is column t of S^-1, stored as row t of the
+        // transpose.  The work vectors sit in LDS after the band, [k][t].
+        double *xs = band_lds + M * NB;
+        for (int t = tid; t < M; t += kFactorThreads) {
+            for (int k = 0; k < M; ++k) {  // L z = e_t, L unit lower
+                double z = k == t ? 1.0 : 0.0;
+                for (int dd = max(0, HB - k); dd < HB; ++dd) z -= A[k * NB + dd] * xs[(k - HB + dd) * M + t];
+                xs[k * M + t] = z;
+            }
+            for (int k = M - 1; k >= 0; --k) {  // U x = z; the reciprocal pivot is stored
+                double z = xs[k * M + t];
+                for (int dd = 1; dd <= HB && k + dd < M; ++dd) z -= A[k * NB + HB + dd] * xs[(k + dd) * M + t];
+                xs[k * M + t] = z * A[k * NB + HB];
+            }
+            for (int k = 0; k < M; ++k) sinv[(long)t * ms + k] = xs[k * M + t];
+            for (int k = M; k < ms; ++k) sinv[(long)t * ms + k] = 0.0;
+        }
+        // the solve reads rows 16 wide from any level block start
+        if (tid < 16) sinv[(long)M * ms + tid] = 0.0;
+    }
     if (bad) *flag = 1;
 }
 
@@ -998,6 +1199,15 @@ hipError_t solve_launch(numa_ctx *c, SolveParams p)
     p.ncol = c->ncol;
     using G = SolveGeom<N, SH>;
     const int M = int(c->nz);
+    if (dense_solve_used(c)) {
+        if (!c->sinv || c->sinv_ms > 4 * kDenseKL) return hipErrorInvalidValue;
+        p.sinv = c->sinv;
+        p.ms = int(c->sinv_ms);
+        const size_t lds = size_t(M + 2 * N) * 64 * sizeof(double);
+        hipLaunchKernelGGL((k_colsolve_dense<N, SH>), dim3(unsigned((c->ncol + 63) / 64)), dim3(256), lds, c->stream,
+                           p);
+        return hipGetLastError();
+    }
     const size_t shm = G::lds_total(M);
     hipError_t e = solve_prepare<N, SH>(M);
     if (e != hipSuccess) return e;
@@ -1014,11 +1224,32 @@ hipError_t factor_launch(numa_ctx *c, double lambda)
 {
     // one factor set, shared by all columns (their matrices are identical)
     const size_t bytes = size_t(c->nz) * (4 * N + 1) * sizeof(double);
-    const bool lds = bytes <= kFactorLds;
-    hipLaunchKernelGGL((k_factor<N>), dim3(1), dim3(kFactorThreads), lds ? bytes : 0, c->stream, c->lev.dzb,
-                       c->lev.G0, lambda, c->eos.grav, int(c->nz), int(lds), c->fac, c->flag);
+    const bool dense = dense_solve_used(c);
+    // the dense inverse needs the band and its work vectors in LDS (short
+    // columns: at most about 40 KB together)
+    const size_t shm = bytes + (dense ? size_t(c->nz * c->nz) * sizeof(double) : 0);
+    const bool lds = dense || bytes <= kFactorLds;
+    if (dense && (!c->sinv || shm > kFactorLds)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_factor<N>), dim3(1), dim3(kFactorThreads), lds ? shm : 0, c->stream, c->lev.dzb,
+                       c->lev.G0, lambda, c->eos.grav, int(c->nz), int(lds), c->fac, c->flag,
+                       dense ? c->sinv : nullptr, int(c->sinv_ms));
     return hipGetLastError();
 }
+
+}  // namespace
+
+// the dense solve holds at most 16 levels per wavefront in registers; with
+// nz + 2N <= 64 its LDS array stays within 32 KB and the factor kernel's
+// band plus inverse work vectors within 64 KB
+bool dense_solve_ok(int N, int64_t nz) { return N >= 1 && nz >= 2 && nz + 2 * N <= 64; }
+
+bool dense_solve_used(const numa_ctx *c)
+{
+    if (c->column_solver == NUMA_SOLVER_BAND) return false;
+    return c->column_solver == NUMA_SOLVER_DENSE || dense_solve_ok(c->N, c->nz);
+}
+
+namespace {
 
 // Run f(std::integral_constant<int, N>) for the context's order N.
 template <typename F>

@@ -21,6 +21,7 @@ NUMA_E_NOMEM = -5
 NUMA_E_NONFINITE = -6
 NUMA_E_NOT_CONVERGED = -7
 NUMA_E_UNSUPPORTED = -8
+SOLVER_AUTO, SOLVER_BAND, SOLVER_DENSE = 0, 1, 2
 
 ERROR_NAMES = {
     NUMA_E_ARG: "NUMA_E_ARG",
@@ -48,7 +49,8 @@ class numa_background(C.Structure):
 class numa_info(C.Structure):
     _fields_ = [("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64), ("ncol", C.c_int64),
                 ("factor_bytes", C.c_int64), ("scratch_bytes", C.c_int64), ("step_bytes", C.c_int64),
-                ("order", C.c_int32), ("factored", C.c_int32), ("dt_factored", C.c_double)]
+                ("order", C.c_int32), ("factored", C.c_int32), ("dt_factored", C.c_double),
+                ("column_solver", C.c_int32), ("reserved", C.c_int32)]
 
 
 class NumaError(RuntimeError):
@@ -75,6 +77,7 @@ def load():
     lib.numa_get_info.argtypes = [vp, C.POINTER(numa_info)]
     lib.numa_set_stream.argtypes = [vp, vp]
     lib.numa_factor_columns.argtypes = [vp, C.c_double]
+    lib.numa_set_column_solver.argtypes = [vp, C.c_int32]
     lib.numa_hevi_step.argtypes = [vp, vp, C.c_double, C.c_int32]
     lib.numa_profile_steps.argtypes = [vp, vp, C.c_double, C.c_int32, C.POINTER(C.c_double)]
     lib.numa_hevi_step_mixed.argtypes = [vp, vp, C.c_double, C.c_int32]
@@ -125,7 +128,7 @@ def load():
                  "numa_pbno_apply", "numa_imex3d_solve", "numa_learned_setup", "numa_learned_info",
                  "numa_learned_add_samples", "numa_learned_samples", "numa_learned_params", "numa_learned_loss_grad",
                  "numa_learned_train", "numa_learned_enable", "numa_learned_apply", "numa_factor_columns_standard",
-                 "numa_solve_columns_standard"):
+                 "numa_solve_columns_standard", "numa_set_column_solver"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -186,6 +189,10 @@ def set_stream(ctx, stream):
 
 def factor_columns(ctx, dt):
     return _check(load().numa_factor_columns(ctx, float(dt)), ctx)
+
+
+def set_column_solver(ctx, kind):
+    return _check(load().numa_set_column_solver(ctx, int(kind)), ctx)
 
 
 def hevi_step(ctx, state_ptr, dt, nsteps):
@@ -456,6 +463,11 @@ class Context:
     def factor(self, dt):
         factor_columns(self.ctx, dt)
         self.dt = float(dt)
+
+    def set_column_solver(self, kind):
+        """SOLVER_AUTO, SOLVER_BAND or SOLVER_DENSE; call factor() again after."""
+        set_column_solver(self.ctx, kind)
+        self.dt = None
 
     def _check_state(self, t):
         import torch

@@ -212,6 +212,79 @@ def test_step_parity_box_large_full_size(torch_cuda, numa_mod, oracle_mod):
     print(f"box_large R1 full size: worst per-variable rel L2 over 2 steps {worst}")
 
 
+# Both column solvers on short columns, and the dense solve at its limits:
+# nz + 2N = 64 (N = 7, 50 levels), 16 levels per wavefront (N = 1, 62
+# levels), and a block split with an empty last wavefront (N = 1, 5 levels).
+SOLVER_GRIDS = GRIDS[:6] + [(7, 1, 1, 7, 11, 31), (1, 2, 1, 61, None, 32), (4, 2, 2, 13, 12, 33),
+                            (1, 2, 2, 4, None, 34)]
+
+
+@pytest.mark.parametrize("N,nex,ney,nez,zseed,seed", SOLVER_GRIDS)
+def test_band_and_dense_column_solvers(torch_cuda, numa_mod, oracle_mod, N, nex, ney, nez, zseed, seed):
+    lz = 6000.0 if nez <= 8 else 20000.0
+    zf = None if zseed is None else W.random_zface(nez, lz, zseed)
+    g = W.Grid(9000.0 * nex, 7000.0 * ney, lz, nex, ney, nez, N, zface=zf)
+    assert g.nz + 2 * N <= 64
+    dt = W.dt_for_courant(g, 15.0, "z")
+    o = _oracle(oracle_mod, g)
+    o.factor_dt(dt)
+    y = W.make_random_state(g, seed + 100, smooth=False)
+    ref = o.solve(y)
+    q = W.make_random_state(g, seed, wind=2.0)
+    dtx = min(dt, W.dt_for_courant(g, 0.4, "x"), W.dt_for_courant(g, 0.4, "y"))
+    o.factor_dt(dtx)
+    qref = o.step(q, dtx, 2)
+    ctx = numa_mod.Context(g)
+    outs = {}
+    for kind in (numa_mod.SOLVER_BAND, numa_mod.SOLVER_DENSE):
+        ctx.set_column_solver(kind)
+        ctx.factor(dt)
+        x = _host(ctx.solve(_dev(torch_cuda, y)))
+        ctx.check()
+        e = _rel(x, ref)
+        assert np.all(e < OP_TOL), (kind, e)
+        ctx.factor(dtx)
+        qd = _dev(torch_cuda, q)
+        ctx.step(qd, 2)
+        ctx.check()
+        e = _rel(_host(qd), qref)
+        print(f"solver {kind} N={N} nz={g.nz}: step rel L2 {e}")
+        assert np.all(e < STEP_TOL), (kind, e)
+        outs[kind] = x
+    # the two solvers agree to rounding
+    e = _rel(outs[numa_mod.SOLVER_DENSE], outs[numa_mod.SOLVER_BAND])
+    assert np.all(e < OP_TOL), e
+
+
+def test_column_solver_selection(torch_cuda, numa_mod):
+    numa = numa_mod
+    g = _grid(4, 2, 2, 2, None)
+    ctx = numa.Context(g)
+    ctx.factor(1.0)
+    with pytest.raises(numa.NumaError) as ei:
+        ctx.set_column_solver(7)
+    assert ei.value.code == numa.NUMA_E_ARG
+    ctx.set_column_solver(numa.SOLVER_DENSE)
+    q = torch_cuda.zeros(ctx.shape, dtype=torch_cuda.float64, device="cuda")
+    with pytest.raises(numa.NumaError) as ei:  # a new solver needs a new factorisation
+        numa.hevi_step(ctx.ctx, q.data_ptr(), 1.0, 1)
+    assert ei.value.code == numa.NUMA_E_NOT_FACTORED
+    ctx.factor(1.0)
+    ctx.step(q, 1, dt=1.0)
+    ctx.check()
+    assert float(q.abs().max()) == 0.0
+    ctx.close()
+    # 14 elements of order 4 give 57 levels: above 64 - 2N, dense is refused
+    t = numa.Context(W.Grid(9000.0, 9000.0, 20000.0, 1, 1, 14, 4))
+    with pytest.raises(numa.NumaError) as ei:
+        t.set_column_solver(numa.SOLVER_DENSE)
+    assert ei.value.code == numa.NUMA_E_UNSUPPORTED
+    t.set_column_solver(numa.SOLVER_BAND)
+    t.set_column_solver(numa.SOLVER_AUTO)
+    t.factor(1.0)
+    t.close()
+
+
 def test_rest_state_stays_at_rest(torch_cuda, numa_mod):
     g = _grid(4, 3, 2, 3, 7)
     ctx = numa_mod.Context(g)
