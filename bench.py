@@ -28,9 +28,8 @@ HBM_PEAK_GBS = 8000.0
 
 def kernel_bytes(np_, ncol, nz, N, table_bytes=None):
     """Algorithmic HBM bytes per launch of the five kernels of a step: whole
-    unique-node field passes (reads + writes) and the one table the column
-    solves read (the LU band, or the inverse for the dense solve; all
-    columns share it).  Default: the LU band."""
+    unique-node field passes (reads + writes) and the column factor reads
+    (one LU band shared by all columns)."""
     F = nz * (4 * N + 1) * 8 if table_bytes is None else table_bytes
     f = 8 * np_
     return [
@@ -153,7 +152,7 @@ def standard_form_columns(numa, torch, ctx, wl, q, reps=20):
     a, b = xs.cpu().numpy(), xk.cpu().numpy()
     diff = {n: float(np.linalg.norm(a[f] - b[f]) / np.linalg.norm(b[f])) for f, n in ((0, "rho'"), (3, "w"))}
     info = ctx.info()
-    # the Schur form with band substitution, on a context of its own
+    # the Schur form with one lane per column, on a context of its own
     cb = numa.Context(wl.grid, wl.background)
     cb.set_column_solver(numa.SOLVER_BAND)
     cb.factor(wl.dt)
@@ -162,14 +161,14 @@ def standard_form_columns(numa, torch, ctx, wl, q, reps=20):
     band_bytes = cb.info()["factor_bytes"]
     cb.close()
     return {"entry": "numa_solve_columns_standard", "factor_bytes": nbytes,
-            "schur_solver": "dense" if info["column_solver"] == numa.SOLVER_DENSE else "band",
+            "schur_solver": "blocked" if info["column_solver"] == numa.SOLVER_BLOCKED else "band",
             "schur_factor_bytes": info["factor_bytes"], "factor_s": t_factor, "ms_per_solve": ms_std,
             "schur_ms_per_solve": ms_schur, "schur_speedup": ms_std / ms_schur, "rel_l2_vs_schur": diff,
             "schur_band_ms_per_solve": ms_band, "schur_band_factor_bytes": band_bytes}
 
 
 def column_solver_ab(numa, torch, wl, q0, steps=50):
-    """The HEVI step with the band-substitution column solve instead of the
+    """The HEVI step with the one-lane-per-column solve instead of the
     default: per-kernel milliseconds (HIP events, launch order) and ms per
     step, on its own context and a copy of the state."""
     c = numa.Context(wl.grid, wl.background)
@@ -474,7 +473,7 @@ def main():
         "step_algorithmic_GBps": step_bytes * args.steps / t / 1e9,
     }
     out["standard_form_columns"] = standard_form_columns(numa, torch, ctx, wl, q)
-    out["column_solver"] = {"in_use": "dense" if info["column_solver"] == numa.SOLVER_DENSE else "band",
+    out["column_solver"] = {"in_use": "blocked" if info["column_solver"] == numa.SOLVER_BLOCKED else "band",
                             "band_substitution": column_solver_ab(numa, torch, wl,
                                                                   torch.from_numpy(W.make_initial_state(wl)).to("cuda"))}
     if not args.no_precision:

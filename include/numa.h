@@ -67,14 +67,13 @@ typedef struct {
 typedef struct {
     int64_t nx, ny, nz;           /* unique-node grid                                 */
     int64_t ncol;                 /* vertical columns (nx*ny)                         */
-    int64_t factor_bytes;         /* bytes of the table a column solve reads: the LU
-                                     band, or the inverse for NUMA_SOLVER_DENSE       */
+    int64_t factor_bytes;         /* device bytes of the stored column factors        */
     int64_t scratch_bytes;        /* device bytes of the stage buffers                */
     int64_t step_bytes;           /* algorithmic HBM bytes moved per HEVI step        */
     int32_t order;                /* LGL order N                                      */
     int32_t factored;             /* 1 once numa_factor_columns succeeded             */
     double dt_factored;           /* dt of the stored factors                         */
-    int32_t column_solver;        /* NUMA_SOLVER_BAND or NUMA_SOLVER_DENSE, in use    */
+    int32_t column_solver;        /* NUMA_SOLVER_BAND or NUMA_SOLVER_BLOCKED, in use  */
     int32_t reserved;
 } numa_info;
 
@@ -119,21 +118,21 @@ int numa_set_stream(numa_ctx *c, void *hip_stream);
 int numa_factor_columns(numa_ctx *c, double dt);
 
 /*
- * How the column solves apply the factored matrix (the solution is the same
- * up to rounding).  NUMA_SOLVER_BAND: forward and backward band substitution
- * with the LU factors (Alg. 9), one lane per column.  NUMA_SOLVER_DENSE:
- * the inverse of the column matrix, formed once per time-step size from
- * the same factors, applied as a dense product per column; every column
- * shares the matrix, so the inverse is one nz x nz table, and the product
- * has no level-by-level recurrence.  It is available for columns of at most
- * 64 - 2N levels.  NUMA_SOLVER_AUTO (the default): dense where available.
+ * How the column solves are laid out on the GPU (both run the forward and
+ * backward band substitutions of Alg. 9 with the same stored factors; the
+ * results agree to rounding).  NUMA_SOLVER_BAND: one lane per column, each
+ * lane walking all levels of its column.  NUMA_SOLVER_BLOCKED: four
+ * wavefronts per 64 columns, each holding a block of levels in registers
+ * for the stage right-hand side and the extraction, and one wavefront
+ * running the substitutions from LDS; available for columns of at most
+ * 64 - 2N levels.  NUMA_SOLVER_AUTO (the default): blocked where available.
  * Takes effect at the next numa_factor_columns; until then the context
  * counts as not factored.  Errors: NUMA_E_ARG (unknown kind),
- * NUMA_E_UNSUPPORTED (dense for a taller column).
+ * NUMA_E_UNSUPPORTED (blocked for a taller column).
  */
 #define NUMA_SOLVER_AUTO 0
 #define NUMA_SOLVER_BAND 1
-#define NUMA_SOLVER_DENSE 2
+#define NUMA_SOLVER_BLOCKED 2
 int numa_set_column_solver(numa_ctx *c, int32_t kind);
 
 /*

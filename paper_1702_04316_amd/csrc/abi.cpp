@@ -33,7 +33,6 @@ void free_ctx(numa_ctx *c)
     if (!c) return;
     if (c->lev_block) (void)hipFree(c->lev_block);
     if (c->fac) (void)hipFree(c->fac);
-    if (c->sinv) (void)hipFree(c->sinv);
     if (c->work) (void)hipFree(c->work);
     if (c->work_mix) (void)hipFree(c->work_mix);
     if (c->flag) (void)hipFree(c->flag);
@@ -45,13 +44,8 @@ void free_ctx(numa_ctx *c)
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
-// bytes of the one table every column solve reads: the LU band, or the
-// (padded, transposed) inverse for the dense solve
-int64_t solve_table_bytes(const numa_ctx *c)
-{
-    if (numa::dense_solve_used(c)) return c->nz * 4 * ((c->nz + 3) / 4) * int64_t(sizeof(double));
-    return c->nz * (4 * c->N + 1) * int64_t(sizeof(double));
-}
+// bytes of the one LU band every column solve reads (all columns share it)
+int64_t solve_table_bytes(const numa_ctx *c) { return c->nz * (4 * c->N + 1) * int64_t(sizeof(double)); }
 
 int64_t step_bytes_model(const numa_ctx *c)
 {
@@ -226,7 +220,7 @@ int numa_get_info(const numa_ctx *c, numa_info *info)
     info->order = c->N;
     info->factored = c->factored;
     info->dt_factored = c->dt_factored;
-    info->column_solver = numa::dense_solve_used(c) ? NUMA_SOLVER_DENSE : NUMA_SOLVER_BAND;
+    info->column_solver = numa::blocked_solve_used(c) ? NUMA_SOLVER_BLOCKED : NUMA_SOLVER_BAND;
     info->reserved = 0;
     return NUMA_OK;
 }
@@ -241,10 +235,10 @@ int numa_set_stream(numa_ctx *c, void *hip_stream)
 int numa_set_column_solver(numa_ctx *c, int32_t kind)
 {
     if (!c) return NUMA_E_ARG;
-    if (kind != NUMA_SOLVER_AUTO && kind != NUMA_SOLVER_BAND && kind != NUMA_SOLVER_DENSE)
+    if (kind != NUMA_SOLVER_AUTO && kind != NUMA_SOLVER_BAND && kind != NUMA_SOLVER_BLOCKED)
         return fail(c, NUMA_E_ARG, "numa_set_column_solver: unknown kind");
-    if (kind == NUMA_SOLVER_DENSE && !numa::dense_solve_ok(c->N, c->nz))
-        return fail(c, NUMA_E_UNSUPPORTED, "numa_set_column_solver: the dense solve needs nz <= 64 - 2N");
+    if (kind == NUMA_SOLVER_BLOCKED && !numa::blocked_solve_ok(c->N, c->nz))
+        return fail(c, NUMA_E_UNSUPPORTED, "numa_set_column_solver: the blocked solve needs nz <= 64 - 2N");
     c->column_solver = kind;
     c->factored = 0;
     return NUMA_OK;
@@ -256,16 +250,7 @@ int numa_factor_columns(numa_ctx *c, double dt)
     if (!finite_pos(dt)) return fail(c, NUMA_E_ARG, "numa_factor_columns: dt must be finite and > 0");
     const double lambda = (1.0 - 1.0 / std::sqrt(2.0)) * dt;
     c->factored = 0;
-    hipError_t e = hipSuccess;
-    if (numa::dense_solve_used(c) && !c->sinv) {
-        c->sinv_ms = 4 * ((c->nz + 3) / 4);
-        e = hipMalloc(&c->sinv, size_t(c->nz * c->sinv_ms + 16) * sizeof(double));
-        if (e != hipSuccess) {
-            c->sinv = nullptr;
-            return hip_fail(c, e, "numa_factor_columns: hipMalloc(inverse)");
-        }
-    }
-    e = numa::launch_factor(c, lambda);
+    hipError_t e = numa::launch_factor(c, lambda);
     if (e != hipSuccess) return hip_fail(c, e, "numa_factor_columns");
     c->factored = 1;
     c->dt_factored = dt;

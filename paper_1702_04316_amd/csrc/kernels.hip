@@ -606,8 +606,6 @@ struct SolveParams {
     // large vertical Courant numbers, so w_a must keep FP64 precision
     double *park;
     const double *fac;
-    const double *sinv;  // dense solve: S^-1 transposed, rows of stride ms
-    int ms;
     const double *scf, *dzb;
     double lambda;
     int nz;
@@ -804,50 +802,52 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 }
 
 // ---------------------------------------------------------------------------
-// Column solve with the explicit inverse (short columns).  All columns share
-// S, so its inverse is formed once per dt (k_factor) and the solve becomes a
-// dense product x = S^-1 b per column.  When the band (4N+1 wide) is a large
-// part of the column that is about as many multiply-adds as the two band
-// substitutions, and it has no level-by-level recurrence.  A workgroup of
-// four wavefronts owns 64 columns (one per lane); wavefront g owns the
-// level block [g KL, (g+1) KL), KL = ms/4 <= kDenseKL, and keeps its
-// levels' values in registers.  One LDS array V, [N pad][M levels][N pad] x
-// 64 lanes, exchanges the one field a phase needs from other levels:
+// Level-blocked column solve (columns of at most 64 - 2N levels).  A
+// workgroup of four wavefronts owns 64 columns (one per lane); wavefront g
+// owns the level block [g KL, (g+1) KL), KL = ceil(nz/4) <= kBlockedKL, and
+// keeps its levels' values in registers.  One LDS array V, [N pad][M
+// levels][N pad] x 64 lanes, exchanges the one field a phase needs from
+// other levels, and the shared LU band sits in LDS beside it:
 //  1. the estimates: P_e and w_a in registers, V = rho0 w_a;
 //  2. b = P_e - lambda G0 Dz(rho0 w_a), then V = b;
-//  3. x = S^-1 b (the rows of S^-1 a wavefront needs are uniform across it
-//     and come through scalar loads), then V = x;
+//  3. the forward and backward band substitutions (Alg. 9) in place in V,
+//     by wavefront 0 for all 64 columns: the only level-by-level
+//     recurrence, with every operand in LDS or registers;
 //  4. w~ = B (w_a - lambda (Dz x / rho0 + g x / (G0 rho0))), w out, then
 //     V = rho0 w~;
 //  5. rho' = q_e,rho - lambda Dz(rho0 w~).
-// w_a never leaves the registers, so nothing is parked in HBM.  The pads
-// hold zeros and meet only zero band coefficients.
+// w_a never leaves the registers, so nothing is parked in HBM, and the
+// global loads of phases 1, 4 and 5 come from four wavefronts per 64
+// columns.  The pads hold zeros and meet only zero band coefficients.
 // ---------------------------------------------------------------------------
-constexpr int kDenseKL = 16;
+constexpr int kBlockedKL = 16;
 
-constexpr int dense_chunk(int per_level) { return per_level >= 6 ? 4 : 8; }
+constexpr int blocked_chunk(int per_level) { return per_level >= 6 ? 4 : 8; }
 
 template <int N, class SH>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_colsolve_dense(SolveParams p)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N <= 6 ? 4 : 3))) void k_colsolve_blocked(SolveParams p)
 {
     extern __shared__ double smem[];
-    constexpr int NS = 2 * N + 1, KX = kDenseKL, NE = SolveGeom<N, SH>::NE;
-    constexpr int CF = dense_chunk(NE), CX = dense_chunk(1 + SH::NBW + SH::NBR);
+    constexpr int NS = 2 * N + 1, KX = kBlockedKL, NE = SolveGeom<N, SH>::NE;
+    constexpr int CF = blocked_chunk(NE), CX = blocked_chunk(1 + SH::NBW + SH::NBR);
     const int lane = threadIdx.x & 63;
     const int g = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     const long col = (long)blockIdx.x * 64 + lane;
     const bool act = col < p.ncol;
     const unsigned cbyte = unsigned(act ? col : 0) * 8u;
-    const int M = p.nz, KL = p.ms >> 2, k0 = g * KL;
+    const int M = p.nz, KL = (M + 3) >> 2, k0 = g * KL;
     const int nk = max(0, min(KL, M - k0));  // levels of this wavefront
     const unsigned lbytes = unsigned(p.ncol) * 8u;
     cdouble *scf = as_const(p.scf);
     cdouble *dzb = as_const(p.dzb);
     double *V = smem + N * 64 + lane;  // V[k * 64], k in [-N, M + N)
+    constexpr int HB = 2 * N, NB = 4 * N + 1;
+    double *F = smem + (M + 2 * N) * 64;  // the shared LU band, [k][NB]
     for (int t = threadIdx.x; t < N * 64; t += 256) {
         smem[t] = 0.0;
         smem[(M + N) * 64 + t] = 0.0;
     }
+    for (int e = threadIdx.x; e < M * NB; e += 256) F[e] = p.fac[e];
     // Dz of the field in V at level s (band of half-width N)
     auto dz_of_v = [&](int s) {
         cdouble *bz = dzb + s * NS;
@@ -905,23 +905,75 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     for (int i = 0; i < KX; ++i)
         if (i < nk) V[(k0 + i) * 64] = r[i];
     __syncthreads();
-    // ---- 3. x = S^-1 b: x_k = sum_m (S^-T)[m][k] b_m for the own k
-    {
+    // ---- 3. x = S^-1 b by the band substitutions of the LU factors, one
+    //      wavefront for the 64 columns.  The newest value enters each sum
+    //      last, so the recurrence is one multiply-add per level; b and (for
+    //      N <= 4, where the registers allow) the factor row are read one
+    //      level ahead
+    if (g == 0) {
+        constexpr bool PF = N <= 4;
+        constexpr int PR = PF ? HB + 1 : 1;  // prefetched row entries
+        double win[HB];
 #pragma unroll
-        for (int i = 0; i < KX; ++i) r[i] = 0.0;
-        cdouble *row = as_const(p.sinv) + k0;
-        for (int m = 0; m < M; ++m) {
-            const double bm = V[m * 64];
+        for (int t = 0; t < HB; ++t) win[t] = 0.0;
+        double bn = V[0], ln[PR];
+        if constexpr (PF) {
 #pragma unroll
-            for (int i = 0; i < KX; ++i) r[i] += row[i] * bm;
-            row += p.ms;
+            for (int dd = 0; dd < HB; ++dd) ln[dd] = F[dd];
+        }
+        for (int k = 0; k < M; ++k) {
+            double y = bn, l[PR];
+            if constexpr (PF) {
+#pragma unroll
+                for (int dd = 0; dd < HB; ++dd) l[dd] = ln[dd];
+            }
+            if (k + 1 < M) {
+                bn = V[(k + 1) * 64];
+                if constexpr (PF) {
+#pragma unroll
+                    for (int dd = 0; dd < HB; ++dd) ln[dd] = F[(k + 1) * NB + dd];
+                }
+            }
+#pragma unroll
+            for (int dd = 0; dd < HB; ++dd) y -= (PF ? l[dd] : F[k * NB + dd]) * win[dd];
+#pragma unroll
+            for (int t = 0; t < HB - 1; ++t) win[t] = win[t + 1];
+            win[HB - 1] = y;
+            V[k * 64] = y;
+        }
+#pragma unroll
+        for (int t = 0; t < HB; ++t) win[t] = 0.0;
+        double xn = V[(M - 1) * 64], un[PR];
+        if constexpr (PF) {
+#pragma unroll
+            for (int dd = 0; dd <= HB; ++dd) un[dd] = F[(M - 1) * NB + HB + dd];
+        }
+        for (int k = M - 1; k >= 0; --k) {
+            double x = xn, u[PR];
+            if constexpr (PF) {
+#pragma unroll
+                for (int dd = 0; dd <= HB; ++dd) u[dd] = un[dd];
+            }
+            if (k > 0) {
+                xn = V[(k - 1) * 64];
+                if constexpr (PF) {
+#pragma unroll
+                    for (int dd = 0; dd <= HB; ++dd) un[dd] = F[(k - 1) * NB + HB + dd];
+                }
+            }
+#pragma unroll
+            for (int dd = HB; dd >= 1; --dd) x -= (PF ? u[dd] : F[k * NB + HB + dd]) * win[dd - 1];
+            x *= PF ? u[0] : F[k * NB + HB];
+#pragma unroll
+            for (int t = HB - 1; t > 0; --t) win[t] = win[t - 1];
+            win[0] = x;
+            V[k * 64] = x;
         }
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < KX; ++i)
-        if (i < nk) V[(k0 + i) * 64] = r[i];
-    __syncthreads();
+        if (i < nk) r[i] = V[(k0 + i) * 64];
     // ---- 4. w~ and the w output
 #pragma unroll
     for (int i0 = 0; i0 < KX; i0 += CX) {
@@ -1016,8 +1068,7 @@ constexpr size_t kFactorLds = 64 * 1024;
 template <int N>
 __global__ __launch_bounds__(kFactorThreads) void k_factor(const double *__restrict__ dzb,
                                                            const double *__restrict__ G0, double lambda, double grav,
-                                                           int M, int in_lds, double *fac, int *flag,
-                                                           double *sinv, int ms)
+                                                           int M, int in_lds, double *fac, int *flag)
 {
     extern __shared__ double band_lds[];
     constexpr int NS = 2 * N + 1, NB = 4 * N + 1, HB = 2 * N;
@@ -1060,28 +1111,6 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor(const double *__restr
     }
     if (in_lds)
         for (int idx = tid; idx < M * NB; idx += kFactorThreads) fac[idx] = band_lds[idx];
-    if (sinv) {
-        // the inverse for the dense column solve, from the factors: thread t
-        // solves S x = e_t, so x is column t of S^-1, stored as row t of the
-        // transpose.  The work vectors sit in LDS after the band, [k][t].
-        double *xs = band_lds + M * NB;
-        for (int t = tid; t < M; t += kFactorThreads) {
-            for (int k = 0; k < M; ++k) {  // L z = e_t, L unit lower
-                double z = k == t ? 1.0 : 0.0;
-                for (int dd = max(0, HB - k); dd < HB; ++dd) z -= A[k * NB + dd] * xs[(k - HB + dd) * M + t];
-                xs[k * M + t] = z;
-            }
-            for (int k = M - 1; k >= 0; --k) {  // U x = z; the reciprocal pivot is stored
-                double z = xs[k * M + t];
-                for (int dd = 1; dd <= HB && k + dd < M; ++dd) z -= A[k * NB + HB + dd] * xs[(k + dd) * M + t];
-                xs[k * M + t] = z * A[k * NB + HB];
-            }
-            for (int k = 0; k < M; ++k) sinv[(long)t * ms + k] = xs[k * M + t];
-            for (int k = M; k < ms; ++k) sinv[(long)t * ms + k] = 0.0;
-        }
-        // the solve reads rows 16 wide from any level block start
-        if (tid < 16) sinv[(long)M * ms + tid] = 0.0;
-    }
     if (bad) *flag = 1;
 }
 
@@ -1199,12 +1228,9 @@ hipError_t solve_launch(numa_ctx *c, SolveParams p)
     p.ncol = c->ncol;
     using G = SolveGeom<N, SH>;
     const int M = int(c->nz);
-    if (dense_solve_used(c)) {
-        if (!c->sinv || c->sinv_ms > 4 * kDenseKL) return hipErrorInvalidValue;
-        p.sinv = c->sinv;
-        p.ms = int(c->sinv_ms);
-        const size_t lds = size_t(M + 2 * N) * 64 * sizeof(double);
-        hipLaunchKernelGGL((k_colsolve_dense<N, SH>), dim3(unsigned((c->ncol + 63) / 64)), dim3(256), lds, c->stream,
+    if (blocked_solve_used(c)) {
+        const size_t lds = (size_t(M + 2 * N) * 64 + size_t(M) * (4 * N + 1)) * sizeof(double);
+        hipLaunchKernelGGL((k_colsolve_blocked<N, SH>), dim3(unsigned((c->ncol + 63) / 64)), dim3(256), lds, c->stream,
                            p);
         return hipGetLastError();
     }
@@ -1224,29 +1250,22 @@ hipError_t factor_launch(numa_ctx *c, double lambda)
 {
     // one factor set, shared by all columns (their matrices are identical)
     const size_t bytes = size_t(c->nz) * (4 * N + 1) * sizeof(double);
-    const bool dense = dense_solve_used(c);
-    // the dense inverse needs the band and its work vectors in LDS (short
-    // columns: at most about 40 KB together)
-    const size_t shm = bytes + (dense ? size_t(c->nz * c->nz) * sizeof(double) : 0);
-    const bool lds = dense || bytes <= kFactorLds;
-    if (dense && (!c->sinv || shm > kFactorLds)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_factor<N>), dim3(1), dim3(kFactorThreads), lds ? shm : 0, c->stream, c->lev.dzb,
-                       c->lev.G0, lambda, c->eos.grav, int(c->nz), int(lds), c->fac, c->flag,
-                       dense ? c->sinv : nullptr, int(c->sinv_ms));
+    const bool lds = bytes <= kFactorLds;
+    hipLaunchKernelGGL((k_factor<N>), dim3(1), dim3(kFactorThreads), lds ? bytes : 0, c->stream, c->lev.dzb,
+                       c->lev.G0, lambda, c->eos.grav, int(c->nz), int(lds), c->fac, c->flag);
     return hipGetLastError();
 }
 
 }  // namespace
 
-// the dense solve holds at most 16 levels per wavefront in registers; with
-// nz + 2N <= 64 its LDS array stays within 32 KB and the factor kernel's
-// band plus inverse work vectors within 64 KB
-bool dense_solve_ok(int N, int64_t nz) { return N >= 1 && nz >= 2 && nz + 2 * N <= 64; }
+// the blocked solve holds at most 16 levels per wavefront in registers;
+// with nz + 2N <= 64 its LDS (V and the band) stays below 48 KB
+bool blocked_solve_ok(int N, int64_t nz) { return N >= 1 && nz >= 2 && nz + 2 * N <= 64; }
 
-bool dense_solve_used(const numa_ctx *c)
+bool blocked_solve_used(const numa_ctx *c)
 {
     if (c->column_solver == NUMA_SOLVER_BAND) return false;
-    return c->column_solver == NUMA_SOLVER_DENSE || dense_solve_ok(c->N, c->nz);
+    return c->column_solver == NUMA_SOLVER_BLOCKED || blocked_solve_ok(c->N, c->nz);
 }
 
 namespace {

@@ -64,9 +64,7 @@ struct numa_ctx {
     numa::DevLevels lev;
     void *lev_block = nullptr;     // one allocation holding all of lev
     double *fac = nullptr;         // [nz][4N+1] column LU factors, one set shared by all columns
-    double *sinv = nullptr;        // short columns: S^-1 transposed, [nz][sinv_ms] + 16 zeros
-    int64_t sinv_ms = 0;           // row stride of sinv: 4 ceil(nz / 4)
-    int column_solver = 0;         // NUMA_SOLVER_*: 0 auto, 1 band substitution, 2 dense inverse
+    int column_solver = 0;         // NUMA_SOLVER_*: 0 auto, 1 one lane per column, 2 level-blocked
     double *work = nullptr;        // stage buffers (19 fields)
     char *work_mix = nullptr;      // precision form: R1, E3 (mixed layout), Q2, Q3 rho' (FP64), w (FP32)
     int *flag = nullptr;           // device non-finite flag
@@ -100,10 +98,10 @@ size_t lds_needed(int N, int nez, int nz);
 
 hipError_t launch_background(numa_ctx *c);
 hipError_t launch_factor(numa_ctx *c, double lambda);
-// the dense-inverse column solve: supported for this order and column height
-bool dense_solve_ok(int N, int64_t nz);
+// the level-blocked column solve: supported for this order and column height
+bool blocked_solve_ok(int N, int64_t nz);
 // whether the column solves use it (the context's choice, else by height)
-bool dense_solve_used(const numa_ctx *c);
+bool blocked_solve_used(const numa_ctx *c);
 hipError_t launch_rhs_plain(numa_ctx *c, const double *q, double *R);
 hipError_t launch_solve_plain(numa_ctx *c, const double *y, double *x);
 hipError_t launch_rhs_two(numa_ctx *c, const double *Q, const double *e0, const double *e1, double *out0,

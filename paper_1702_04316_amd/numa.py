@@ -21,7 +21,7 @@ NUMA_E_NOMEM = -5
 NUMA_E_NONFINITE = -6
 NUMA_E_NOT_CONVERGED = -7
 NUMA_E_UNSUPPORTED = -8
-SOLVER_AUTO, SOLVER_BAND, SOLVER_DENSE = 0, 1, 2
+SOLVER_AUTO, SOLVER_BAND, SOLVER_BLOCKED = 0, 1, 2
 
 ERROR_NAMES = {
     NUMA_E_ARG: "NUMA_E_ARG",
@@ -465,7 +465,7 @@ class Context:
         self.dt = float(dt)
 
     def set_column_solver(self, kind):
-        """SOLVER_AUTO, SOLVER_BAND or SOLVER_DENSE; call factor() again after."""
+        """SOLVER_AUTO, SOLVER_BAND or SOLVER_BLOCKED; call factor() again after."""
         set_column_solver(self.ctx, kind)
         self.dt = None
 

@@ -61,7 +61,7 @@ def test_setup_rejects_bad_arguments_before_any_gpu_call():
     assert lib.numa_destroy(None) == numa.NUMA_OK
     assert lib.numa_check(None) == numa.NUMA_E_ARG
     assert lib.numa_hevi_step(None, None, 1.0, 1) == numa.NUMA_E_ARG
-    assert lib.numa_set_column_solver(None, numa.SOLVER_DENSE) == numa.NUMA_E_ARG
+    assert lib.numa_set_column_solver(None, numa.SOLVER_BLOCKED) == numa.NUMA_E_ARG
     assert lib.numa_imex3d_setup(None, 1.0, 30, 1, 30, 100) == numa.NUMA_E_ARG
     assert lib.numa_imex3d_step(None, None, 1.0, 1e-8, None) == numa.NUMA_E_ARG
     assert lib.numa_imex3d_solve(None, None, None, 1e-8, None) == numa.NUMA_E_ARG

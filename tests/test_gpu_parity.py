@@ -212,7 +212,7 @@ def test_step_parity_box_large_full_size(torch_cuda, numa_mod, oracle_mod):
     print(f"box_large R1 full size: worst per-variable rel L2 over 2 steps {worst}")
 
 
-# Both column solvers on short columns, and the dense solve at its limits:
+# Both column solvers on short columns, and the blocked solve at its limits:
 # nz + 2N = 64 (N = 7, 50 levels), 16 levels per wavefront (N = 1, 62
 # levels), and a block split with an empty last wavefront (N = 1, 5 levels).
 SOLVER_GRIDS = GRIDS[:6] + [(7, 1, 1, 7, 11, 31), (1, 2, 1, 61, None, 32), (4, 2, 2, 13, 12, 33),
@@ -220,7 +220,7 @@ SOLVER_GRIDS = GRIDS[:6] + [(7, 1, 1, 7, 11, 31), (1, 2, 1, 61, None, 32), (4, 2
 
 
 @pytest.mark.parametrize("N,nex,ney,nez,zseed,seed", SOLVER_GRIDS)
-def test_band_and_dense_column_solvers(torch_cuda, numa_mod, oracle_mod, N, nex, ney, nez, zseed, seed):
+def test_band_and_blocked_column_solvers(torch_cuda, numa_mod, oracle_mod, N, nex, ney, nez, zseed, seed):
     lz = 6000.0 if nez <= 8 else 20000.0
     zf = None if zseed is None else W.random_zface(nez, lz, zseed)
     g = W.Grid(9000.0 * nex, 7000.0 * ney, lz, nex, ney, nez, N, zface=zf)
@@ -236,7 +236,7 @@ def test_band_and_dense_column_solvers(torch_cuda, numa_mod, oracle_mod, N, nex,
     qref = o.step(q, dtx, 2)
     ctx = numa_mod.Context(g)
     outs = {}
-    for kind in (numa_mod.SOLVER_BAND, numa_mod.SOLVER_DENSE):
+    for kind in (numa_mod.SOLVER_BAND, numa_mod.SOLVER_BLOCKED):
         ctx.set_column_solver(kind)
         ctx.factor(dt)
         x = _host(ctx.solve(_dev(torch_cuda, y)))
@@ -252,7 +252,7 @@ def test_band_and_dense_column_solvers(torch_cuda, numa_mod, oracle_mod, N, nex,
         assert np.all(e < STEP_TOL), (kind, e)
         outs[kind] = x
     # the two solvers agree to rounding
-    e = _rel(outs[numa_mod.SOLVER_DENSE], outs[numa_mod.SOLVER_BAND])
+    e = _rel(outs[numa_mod.SOLVER_BLOCKED], outs[numa_mod.SOLVER_BAND])
     assert np.all(e < OP_TOL), e
 
 
@@ -264,7 +264,7 @@ def test_column_solver_selection(torch_cuda, numa_mod):
     with pytest.raises(numa.NumaError) as ei:
         ctx.set_column_solver(7)
     assert ei.value.code == numa.NUMA_E_ARG
-    ctx.set_column_solver(numa.SOLVER_DENSE)
+    ctx.set_column_solver(numa.SOLVER_BLOCKED)
     q = torch_cuda.zeros(ctx.shape, dtype=torch_cuda.float64, device="cuda")
     with pytest.raises(numa.NumaError) as ei:  # a new solver needs a new factorisation
         numa.hevi_step(ctx.ctx, q.data_ptr(), 1.0, 1)
@@ -274,10 +274,10 @@ def test_column_solver_selection(torch_cuda, numa_mod):
     ctx.check()
     assert float(q.abs().max()) == 0.0
     ctx.close()
-    # 14 elements of order 4 give 57 levels: above 64 - 2N, dense is refused
+    # 14 elements of order 4 give 57 levels: above 64 - 2N, blocked is refused
     t = numa.Context(W.Grid(9000.0, 9000.0, 20000.0, 1, 1, 14, 4))
     with pytest.raises(numa.NumaError) as ei:
-        t.set_column_solver(numa.SOLVER_DENSE)
+        t.set_column_solver(numa.SOLVER_BLOCKED)
     assert ei.value.code == numa.NUMA_E_UNSUPPORTED
     t.set_column_solver(numa.SOLVER_BAND)
     t.set_column_solver(numa.SOLVER_AUTO)
