@@ -109,14 +109,20 @@ __device__ __forceinline__ double pressure_perturbation(double rp, double th, do
 
 // Global access as (uniform 64-bit base) + (32-bit per-lane byte offset):
 // compiles to global_load/store with a scalar base address, so a field needs
-// two scalar registers whatever the number of lanes and levels.
+// two scalar registers whatever the number of lanes and levels.  NT: the
+// FP64 store is non-temporal, chosen for large fields (nontemporal_stores).
+// It is a template argument: a runtime choice between two otherwise equal
+// stores is merged by the compiler, which drops the hint.
 __device__ __forceinline__ double gload(const double *base, unsigned off)
 {
     return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(base) + off);
 }
+template <bool NT = false>
 __device__ __forceinline__ void gstore(double *base, unsigned off, double v)
 {
-    *reinterpret_cast<double *>(reinterpret_cast<char *>(base) + off) = v;
+    double *a = reinterpret_cast<double *>(reinterpret_cast<char *>(base) + off);
+    if constexpr (NT) __builtin_nontemporal_store(v, a);
+    else *a = v;
 }
 
 // The same for a field of element type T, with off the offset an FP64 field
@@ -127,11 +133,11 @@ __device__ __forceinline__ double tload(const void *base, unsigned off)
     if constexpr (sizeof(T) == 8) return gload(static_cast<const double *>(base), off);
     else return double(*reinterpret_cast<const float *>(static_cast<const char *>(base) + (off >> 1)));
 }
-template <class T>
+template <class T, bool NT = false>
 __device__ __forceinline__ void tstore(void *base, unsigned off, double v)
 {
-    if constexpr (sizeof(T) == 8) gstore(static_cast<double *>(base), off, v);
-    else *reinterpret_cast<float *>(static_cast<char *>(base) + (off >> 1)) = float(v);
+    if constexpr (sizeof(T) == 8) gstore<NT>(static_cast<double *>(base), off, v);
+    else *reinterpret_cast<float *>(static_cast<char *>(base) + (off >> 1)) = float(v);  // (non-temporal was slower)
 }
 // field f of a five-field buffer of element type T, field stride fs elements
 template <class T>
@@ -186,11 +192,12 @@ struct FiveField {
     {
         return load1(static_cast<const char *>(buf) + ofs(f, np), f, off);
     }
+    template <bool NT>
     static __device__ __forceinline__ void store(void *buf, int f, long np, unsigned off, double v)
     {
         void *p = static_cast<char *>(buf) + ofs(f, np);
         if (f32(f)) tstore<float>(p, off, v);
-        else tstore<double>(p, off, v);
+        else tstore<double, NT>(p, off, v);
     }
 };
 
@@ -228,7 +235,7 @@ __device__ __forceinline__ double stage_input(const RhsParams &p, int f, unsigne
     return TA::load1(p.a[f], f, off);
 }
 
-template <int N, int EPI, bool HASB, bool MIX>
+template <int N, int EPI, bool HASB, bool MIX, bool NT = false>
 __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 : 8>::MINW)) void k_rhs(RhsParams p)
 {
     using TT = RhsTypes<EPI, MIX>;
@@ -461,13 +468,13 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
         const unsigned off = unsigned(k) * pbytes + own;
         if constexpr (EPI == EPI_R) {
 #pragma unroll
-            for (int f = 0; f < 5; ++f) TO0::store(p.out0, f, p.fs, off, double(R[f]));
+            for (int f = 0; f < 5; ++f) TO0::template store<NT>(p.out0, f, p.fs, off, double(R[f]));
         } else if constexpr (EPI == EPI_TWO) {
 #pragma unroll
             for (int f = 0; f < 5; ++f) {
                 const double e0 = ev[f], e1 = ev[5 + f], r = double(R[f]);
-                TO0::store(p.out0, f, p.fs, off, e0 + p.k01 * e1 + p.k02 * r);
-                FiveField<false>::store(p.out1, f, p.fs, off, e0 + p.k11 * e1 + p.k12 * r);
+                TO0::template store<NT>(p.out0, f, p.fs, off, e0 + p.k01 * e1 + p.k02 * r);
+                FiveField<false>::store<NT>(p.out1, f, p.fs, off, e0 + p.k11 * e1 + p.k12 * r);
             }
         } else {
             bool bad = false;
@@ -475,7 +482,7 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
             for (int f = 0; f < 5; ++f) {
                 const double v2 = ev[f] + p.k02 * double(R[f]);
                 bad |= !isfinite(v2);
-                TO0::store(p.out0, f, p.fs, off, v2);
+                TO0::template store<NT>(p.out0, f, p.fs, off, v2);
             }
             if (bad) *p.flag = 1;
         }
@@ -824,7 +831,7 @@ constexpr int kBlockedKL = 16;
 
 constexpr int blocked_chunk(int per_level) { return per_level >= 6 ? 4 : 8; }
 
-template <int N, class SH>
+template <int N, class SH, bool NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N <= 6 ? 4 : 3))) void k_colsolve_blocked(SolveParams p)
 {
     extern __shared__ double smem[];
@@ -996,7 +1003,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N <= 6 ? 4 
 #pragma unroll
                     for (int t = 0; t < SH::NBW; ++t) sh += p.cbw[t] * xb[b][t];
                     r[i] = cf[SC_RHO0] * wt;
-                    if (act) tstore<SolveT<SH, 13>>(p.out_w, unsigned(s) * lbytes + cbyte, wt + sh);
+                    if (act) tstore<SolveT<SH, 13>, NT>(p.out_w, unsigned(s) * lbytes + cbyte, wt + sh);
                 }
             }
         }
@@ -1024,7 +1031,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N <= 6 ? 4 
                     double qr = 0.0;
 #pragma unroll
                     for (int t = 0; t < SH::NBR; ++t) qr += p.cbr[t] * xr[b][t];
-                    if (act) tstore<SolveT<SH, 14>>(p.out_r, unsigned(k) * lbytes + cbyte, qr - p.lambda * dz_of_v(k));
+                    if (act)
+                        tstore<SolveT<SH, 14>, NT>(p.out_r, unsigned(k) * lbytes + cbyte, qr - p.lambda * dz_of_v(k));
                 }
             }
         }
@@ -1154,12 +1162,12 @@ int rhs_zchunk_auto(const numa_ctx *c)
 
 // Opt the kernel into lds bytes of dynamic LDS (needed above 64 KB); done
 // once per size, before the first launch (and before any stream capture).
-template <int N, int EPI, bool HASB, bool MIX>
+template <int N, int EPI, bool HASB, bool MIX, bool NT = false>
 hipError_t rhs_prepare(size_t lds)
 {
     static size_t attr_set = 0;
     if (attr_set < lds) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rhs<N, EPI, HASB, MIX>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rhs<N, EPI, HASB, MIX, NT>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
         if (e != hipSuccess) return e;
         attr_set = lds;
@@ -1189,6 +1197,20 @@ hipError_t solve_prepare(int M)
                             : solve_prepare_fl<N, SH, false>(G::lds_total(M));
 }
 
+// Non-temporal FP64 stores for fields of at least 12 MB at order N <= 4: the
+// largest kernel of such a step touches about 22 fields, more than the
+// 256 MB last-level cache, so the next kernel reads its inputs from HBM
+// whatever the store does.  Below that size the fields a kernel writes can
+// still be in cache when the next kernel reads them.  Measured: on the
+// 2.7M-node N = 4 benchmark grid they cut the stage-2 right-hand side from
+// 132 to 124 us; on the ensemble, whose large domains are N = 5 and 7, they
+// made the step 5 % slower, so higher orders keep ordinary stores.
+constexpr size_t kNontemporalFieldBytes = size_t(12) << 20;
+bool nontemporal_stores(const numa_ctx *c)
+{
+    return c->N <= 4 && size_t(c->np) * sizeof(double) >= kNontemporalFieldBytes;
+}
+
 template <int N, int EPI, bool HASB, bool MIX = false>
 hipError_t rhs_launch(numa_ctx *c, RhsParams p)
 {
@@ -1209,10 +1231,16 @@ hipError_t rhs_launch(numa_ctx *c, RhsParams p)
     p.nty = int((c->ny + G::TY - 1) / G::TY);
     p.flag = c->flag;
     const size_t lds = rhs_lds_bytes<N, MIX>(p.zchunk, p.nez);
-    hipError_t e = rhs_prepare<N, EPI, HASB, MIX>(lds);
-    if (e != hipSuccess) return e;
     dim3 grid(unsigned(p.ntx * p.nty * p.nchunk));
-    hipLaunchKernelGGL((k_rhs<N, EPI, HASB, MIX>), grid, dim3(G::NT), lds, c->stream, p);
+    if (!MIX && nontemporal_stores(c)) {
+        hipError_t e = rhs_prepare<N, EPI, HASB, MIX, true>(lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_rhs<N, EPI, HASB, MIX, true>), grid, dim3(G::NT), lds, c->stream, p);
+    } else {
+        hipError_t e = rhs_prepare<N, EPI, HASB, MIX>(lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_rhs<N, EPI, HASB, MIX>), grid, dim3(G::NT), lds, c->stream, p);
+    }
     return hipGetLastError();
 }
 
@@ -1230,8 +1258,11 @@ hipError_t solve_launch(numa_ctx *c, SolveParams p)
     const int M = int(c->nz);
     if (blocked_solve_used(c)) {
         const size_t lds = (size_t(M + 2 * N) * 64 + size_t(M) * (4 * N + 1)) * sizeof(double);
-        hipLaunchKernelGGL((k_colsolve_blocked<N, SH>), dim3(unsigned((c->ncol + 63) / 64)), dim3(256), lds, c->stream,
-                           p);
+        const dim3 grid(unsigned((c->ncol + 63) / 64));
+        if (nontemporal_stores(c))
+            hipLaunchKernelGGL((k_colsolve_blocked<N, SH, true>), grid, dim3(256), lds, c->stream, p);
+        else
+            hipLaunchKernelGGL((k_colsolve_blocked<N, SH, false>), grid, dim3(256), lds, c->stream, p);
         return hipGetLastError();
     }
     const size_t shm = G::lds_total(M);
@@ -1621,9 +1652,15 @@ hipError_t prepare_step(numa_ctx *c, bool mixed)
         hipError_t e = hipSuccess;
         if (!mixed) {
             const size_t lds = rhs_lds_bytes<NN, false>(zc, nez);
-            if (e == hipSuccess) e = rhs_prepare<NN, EPI_R, false, false>(lds);
-            if (e == hipSuccess) e = rhs_prepare<NN, EPI_TWO, true, false>(lds);
-            if (e == hipSuccess) e = rhs_prepare<NN, EPI_FINAL, false, false>(lds);
+            if (nontemporal_stores(c)) {
+                if (e == hipSuccess) e = rhs_prepare<NN, EPI_R, false, false, true>(lds);
+                if (e == hipSuccess) e = rhs_prepare<NN, EPI_TWO, true, false, true>(lds);
+                if (e == hipSuccess) e = rhs_prepare<NN, EPI_FINAL, false, false, true>(lds);
+            } else {
+                if (e == hipSuccess) e = rhs_prepare<NN, EPI_R, false, false>(lds);
+                if (e == hipSuccess) e = rhs_prepare<NN, EPI_TWO, true, false>(lds);
+                if (e == hipSuccess) e = rhs_prepare<NN, EPI_FINAL, false, false>(lds);
+            }
             if (e == hipSuccess) e = solve_prepare<NN, ShapeStage2>(nz);
             if (e == hipSuccess) e = solve_prepare<NN, ShapeStage3>(nz);
         } else {
