@@ -2,8 +2,10 @@
 //
 //  k_rhs      explicit Set2NC right-hand side with DSS, fused with the ARK
 //             stage combinations (one pass over the state per evaluation)
-//  k_colsolve Schur-complement column solve with the stored band LU factors,
-//             fused with the stage right-hand side and the extraction
+//  k_colsolve_blocked  Schur-complement column solve with the stored band LU
+//             factors, fused with the stage right-hand side and the
+//             extraction; four wavefronts per 64 columns (short columns)
+//  k_colsolve the same, one lane per column (tall columns)
 //  k_factor   assembly and unpivoted band LU of the column Schur matrix (one
 //             band shared by all columns, factored by one workgroup)
 //  k_background  P0, G0, H0 per level with the device equation of state
