@@ -811,9 +811,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 }
 
 // ---------------------------------------------------------------------------
-// Level-blocked column solve (columns of at most 64 - 2N levels).  A
-// workgroup of four wavefronts owns 64 columns (one per lane); wavefront g
-// owns the level block [g KL, (g+1) KL), KL = ceil(nz/4) <= kBlockedKL, and
+// Level-blocked column solve (columns of at most 128 levels).  A workgroup
+// of W wavefronts owns 64 columns (one per lane): W = 4 for columns of at
+// most 64 - 2N levels, else 8.  Wavefront g owns the level block
+// [g KL, (g+1) KL), KL = ceil(nz/W) <= kBlockedKL, and
 // keeps its levels' values in registers.  One LDS array V, [N pad][M
 // levels][N pad] x 64 lanes, exchanges the one field a phase needs from
 // other levels, and the shared LU band sits in LDS beside it:
@@ -833,8 +834,9 @@ constexpr int kBlockedKL = 16;
 
 constexpr int blocked_chunk(int per_level) { return per_level >= 6 ? 4 : 8; }
 
-template <int N, class SH, bool NT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N <= 6 ? 4 : 3))) void k_colsolve_blocked(SolveParams p)
+template <int N, class SH, bool NT, int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 8 ? 2 : (N <= 6 ? 4 : 3))))
+void k_colsolve_blocked(SolveParams p)
 {
     extern __shared__ double smem[];
     constexpr int NS = 2 * N + 1, KX = kBlockedKL, NE = SolveGeom<N, SH>::NE;
@@ -844,7 +846,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N <= 6 ? 4 
     const long col = (long)blockIdx.x * 64 + lane;
     const bool act = col < p.ncol;
     const unsigned cbyte = unsigned(act ? col : 0) * 8u;
-    const int M = p.nz, KL = (M + 3) >> 2, k0 = g * KL;
+    const int M = p.nz, KL = (M + W - 1) / W, k0 = g * KL;
     const int nk = max(0, min(KL, M - k0));  // levels of this wavefront
     const unsigned lbytes = unsigned(p.ncol) * 8u;
     cdouble *scf = as_const(p.scf);
@@ -852,11 +854,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N <= 6 ? 4 
     double *V = smem + N * 64 + lane;  // V[k * 64], k in [-N, M + N)
     constexpr int HB = 2 * N, NB = 4 * N + 1;
     double *F = smem + (M + 2 * N) * 64;  // the shared LU band, [k][NB]
-    for (int t = threadIdx.x; t < N * 64; t += 256) {
+    for (int t = threadIdx.x; t < N * 64; t += 64 * W) {
         smem[t] = 0.0;
         smem[(M + N) * 64 + t] = 0.0;
     }
-    for (int e = threadIdx.x; e < M * NB; e += 256) F[e] = p.fac[e];
+    for (int e = threadIdx.x; e < M * NB; e += 64 * W) F[e] = p.fac[e];
     // Dz of the field in V at level s (band of half-width N)
     auto dz_of_v = [&](int s) {
         cdouble *bz = dzb + s * NS;
@@ -1246,6 +1248,24 @@ hipError_t rhs_launch(numa_ctx *c, RhsParams p)
     return hipGetLastError();
 }
 
+// The eight-wavefront blocked solve of columns above 64 - 2N levels: its
+// LDS, (nz + 2N) x 64 doubles plus the band, can exceed the default 64 KB
+// (at most 108 KB at 128 levels)
+template <int N, class SH>
+hipError_t blocked8_prepare(size_t lds)
+{
+    static size_t attr_set = 65536;
+    if (lds > attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_colsolve_blocked<N, SH, false, 8>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+        attr_set = lds;
+    }
+    return hipSuccess;
+}
+
+size_t blocked_lds_bytes(int N, int M) { return (size_t(M + 2 * N) * 64 + size_t(M) * (4 * N + 1)) * sizeof(double); }
+
 template <int N, class SH>
 hipError_t solve_launch(numa_ctx *c, SolveParams p)
 {
@@ -1259,12 +1279,17 @@ hipError_t solve_launch(numa_ctx *c, SolveParams p)
     using G = SolveGeom<N, SH>;
     const int M = int(c->nz);
     if (blocked_solve_used(c)) {
-        const size_t lds = (size_t(M + 2 * N) * 64 + size_t(M) * (4 * N + 1)) * sizeof(double);
+        const size_t lds = blocked_lds_bytes(N, M);
         const dim3 grid(unsigned((c->ncol + 63) / 64));
-        if (nontemporal_stores(c))
-            hipLaunchKernelGGL((k_colsolve_blocked<N, SH, true>), grid, dim3(256), lds, c->stream, p);
-        else
-            hipLaunchKernelGGL((k_colsolve_blocked<N, SH, false>), grid, dim3(256), lds, c->stream, p);
+        if (M + 2 * N > 64) {
+            hipError_t e = blocked8_prepare<N, SH>(lds);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((k_colsolve_blocked<N, SH, false, 8>), grid, dim3(512), lds, c->stream, p);
+        } else if (nontemporal_stores(c)) {
+            hipLaunchKernelGGL((k_colsolve_blocked<N, SH, true, 4>), grid, dim3(256), lds, c->stream, p);
+        } else {
+            hipLaunchKernelGGL((k_colsolve_blocked<N, SH, false, 4>), grid, dim3(256), lds, c->stream, p);
+        }
         return hipGetLastError();
     }
     const size_t shm = G::lds_total(M);
@@ -1291,9 +1316,9 @@ hipError_t factor_launch(numa_ctx *c, double lambda)
 
 }  // namespace
 
-// the blocked solve holds at most 16 levels per wavefront in registers;
-// with nz + 2N <= 64 its LDS (V and the band) stays below 48 KB
-bool blocked_solve_ok(int N, int64_t nz) { return N >= 1 && nz >= 2 && nz + 2 * N <= 64; }
+// the blocked solve holds at most 16 levels per wavefront in registers, 8
+// wavefronts per workgroup: up to 128 levels (LDS at most 108 KB)
+bool blocked_solve_ok(int N, int64_t nz) { return N >= 1 && nz >= 2 && nz <= 8 * kBlockedKL; }
 
 bool blocked_solve_used(const numa_ctx *c)
 {
@@ -1665,6 +1690,10 @@ hipError_t prepare_step(numa_ctx *c, bool mixed)
             }
             if (e == hipSuccess) e = solve_prepare<NN, ShapeStage2>(nz);
             if (e == hipSuccess) e = solve_prepare<NN, ShapeStage3>(nz);
+            if (blocked_solve_used(c) && nz + 2 * NN > 64) {
+                if (e == hipSuccess) e = blocked8_prepare<NN, ShapeStage2>(blocked_lds_bytes(NN, nz));
+                if (e == hipSuccess) e = blocked8_prepare<NN, ShapeStage3>(blocked_lds_bytes(NN, nz));
+            }
         } else {
             const size_t lds = rhs_lds_bytes<NN, true>(zc, nez);
             if (e == hipSuccess) e = rhs_prepare<NN, EPI_R, false, true>(lds);
@@ -1672,6 +1701,10 @@ hipError_t prepare_step(numa_ctx *c, bool mixed)
             if (e == hipSuccess) e = rhs_prepare<NN, EPI_FINAL, false, true>(lds);
             if (e == hipSuccess) e = solve_prepare<NN, ShapeStage2Mix>(nz);
             if (e == hipSuccess) e = solve_prepare<NN, ShapeStage3Mix>(nz);
+            if (blocked_solve_used(c) && nz + 2 * NN > 64) {
+                if (e == hipSuccess) e = blocked8_prepare<NN, ShapeStage2Mix>(blocked_lds_bytes(NN, nz));
+                if (e == hipSuccess) e = blocked8_prepare<NN, ShapeStage3Mix>(blocked_lds_bytes(NN, nz));
+            }
         }
         return e;
     });

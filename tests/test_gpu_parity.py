@@ -213,10 +213,13 @@ def test_step_parity_box_large_full_size(torch_cuda, numa_mod, oracle_mod):
 
 
 # Both column solvers on short columns, and the blocked solve at its limits:
-# nz + 2N = 64 (N = 7, 50 levels), 16 levels per wavefront (N = 1, 62
-# levels), and a block split with an empty last wavefront (N = 1, 5 levels).
+# four wavefronts up to nz + 2N = 64 (N = 7, 50 levels), 16 levels per
+# wavefront (N = 1, 62 levels), a block split with an empty last wavefront
+# (N = 1, 5 levels); eight wavefronts above that (N = 4, 57 levels; N = 7,
+# 113 levels, more than 64 KB of LDS; N = 1, 128 levels, the limit).
 SOLVER_GRIDS = GRIDS[:6] + [(7, 1, 1, 7, 11, 31), (1, 2, 1, 61, None, 32), (4, 2, 2, 13, 12, 33),
-                            (1, 2, 2, 4, None, 34)]
+                            (1, 2, 2, 4, None, 34), (4, 2, 2, 14, 13, 35), (7, 1, 1, 16, None, 36),
+                            (1, 2, 1, 127, 14, 37)]
 
 
 @pytest.mark.parametrize("N,nex,ney,nez,zseed,seed", SOLVER_GRIDS)
@@ -224,7 +227,7 @@ def test_band_and_blocked_column_solvers(torch_cuda, numa_mod, oracle_mod, N, ne
     lz = 6000.0 if nez <= 8 else 20000.0
     zf = None if zseed is None else W.random_zface(nez, lz, zseed)
     g = W.Grid(9000.0 * nex, 7000.0 * ney, lz, nex, ney, nez, N, zface=zf)
-    assert g.nz + 2 * N <= 64
+    assert g.nz <= 128
     dt = W.dt_for_courant(g, 15.0, "z")
     o = _oracle(oracle_mod, g)
     o.factor_dt(dt)
@@ -274,8 +277,8 @@ def test_column_solver_selection(torch_cuda, numa_mod):
     ctx.check()
     assert float(q.abs().max()) == 0.0
     ctx.close()
-    # 14 elements of order 4 give 57 levels: above 64 - 2N, blocked is refused
-    t = numa.Context(W.Grid(9000.0, 9000.0, 20000.0, 1, 1, 14, 4))
+    # 33 elements of order 4 give 133 levels: above 128, blocked is refused
+    t = numa.Context(W.Grid(9000.0, 9000.0, 20000.0, 1, 1, 33, 4))
     with pytest.raises(numa.NumaError) as ei:
         t.set_column_solver(numa.SOLVER_BLOCKED)
     assert ei.value.code == numa.NUMA_E_UNSUPPORTED
