@@ -1114,6 +1114,7 @@ int orc_mlp_correction(orc_ctx *c, const orc_mlp *m, const double *r, double *co
 typedef struct {
     pbno_arg *p;
     const orc_mlp *mlp;
+    int net_cycles; /* restart cycles that ran with the network */
 } learned_arg;
 
 /* The polynomial is the fallback: a restart cycle with the network that
@@ -1122,7 +1123,9 @@ typedef struct {
 static void learned_guard(const void *marg, double before, double after)
 {
     learned_arg *a = (learned_arg *)marg;
-    if (a->mlp && after > 0.1 * before) a->mlp = NULL;
+    if (!a->mlp) return;
+    a->net_cycles++;
+    if (after > 0.1 * before) a->mlp = NULL;
 }
 
 static int op_learned(orc_ctx *c, const void *arg, const double *r, double *z)
@@ -1148,7 +1151,7 @@ int orc_learned_apply(orc_ctx *c, const double *r, double *z, double lambda, int
     if (!c || !r || !z || (order >= 0 && !bounds)) return -1;
     schur_arg s = {lambda, (double *)malloc(sizeof(double) * 5 * c->np), (double *)malloc(sizeof(double) * 5 * c->np)};
     pbno_arg pa = {&s, order, bounds ? bounds[0] : 0.0, bounds ? bounds[1] : 0.0};
-    learned_arg la = {&pa, mlp};
+    learned_arg la = {&pa, mlp, 0};
     int rc = (s.s && s.l) ? op_learned(c, &la, r, z) : -5;
     free(s.s); free(s.l);
     return rc;
@@ -1159,7 +1162,7 @@ int orc_learned_apply(orc_ctx *c, const double *r, double *z, double lambda, int
  * polynomial alone, still through flexible GMRES), with the fallback of
  * learned_guard. */
 int orc_solve3d_learned(orc_ctx *c, const double *y, double *x, double lambda, double tol, int restart, int maxit,
-                        int order, const double *bounds, const orc_mlp *mlp, int *iters)
+                        int order, const double *bounds, const orc_mlp *mlp, int *iters, int *net_cycles)
 {
     if (!c || !y || !x || restart < 1 || maxit < 1 || !(tol > 0.0)) return -1;
     if (order >= 0 && (!bounds || !(bounds[1] > bounds[0]) || !(bounds[0] > 0.0))) return -1;
@@ -1169,7 +1172,7 @@ int orc_solve3d_learned(orc_ctx *c, const double *y, double *x, double lambda, d
     double *b = (double *)malloc(sizeof(double) * np), *P = (double *)malloc(sizeof(double) * np);
     int rc = (a.s && a.l && Ua && Up && b && P) ? 0 : -5, it = 0, grc = 0;
     pbno_arg pa = {&a, order, bounds ? bounds[0] : 0.0, bounds ? bounds[1] : 0.0};
-    learned_arg la = {&pa, mlp};
+    learned_arg la = {&pa, mlp, 0};
     if (!rc) rc = schur_rhs(c, &a, y, Ua, b);
     if (!rc) {
         grc = gmres_impl(c, np, op_schur, &a, op_learned, &la, b, P, tol, restart, maxit, 1, learned_guard, &it);
@@ -1186,6 +1189,7 @@ int orc_solve3d_learned(orc_ctx *c, const double *y, double *x, double lambda, d
             x[4 * np + I] = y[4 * np + I];
         }
     if (iters) *iters = it;
+    if (net_cycles) *net_cycles = la.net_cycles;
     free(a.s); free(a.l); free(Ua); free(Up); free(b); free(P);
     return rc ? rc : grc;
 }

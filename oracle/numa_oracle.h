@@ -104,7 +104,8 @@ int orc_solve3d_standard(orc_ctx *c, const double *y, double *x, double lambda, 
  * s_e MLP(r_e/s_e).  orc_learned_apply: z = PBNO(r) + that correction.
  * orc_solve3d_learned: orc_solve3d through flexible GMRES with it; a
  * restart cycle that does not reduce the residual norm tenfold switches the
- * network off for the rest of the solve (the polynomial is the fallback). */
+ * network off for the rest of the solve (the polynomial is the fallback);
+ * *net_cycles (nullable): the restart cycles that ran with the network. */
 typedef struct {
     int nin, nh;
     const double *W1, *b1, *W2, *b2;
@@ -117,7 +118,7 @@ int orc_mlp_correction(orc_ctx *c, const orc_mlp *m, const double *r, double *co
 int orc_learned_apply(orc_ctx *c, const double *r, double *z, double lambda, int order, const double *bounds,
                       const orc_mlp *mlp);
 int orc_solve3d_learned(orc_ctx *c, const double *y, double *x, double lambda, double tol, int restart, int maxit,
-                        int order, const double *bounds, const orc_mlp *mlp, int *iters);
+                        int order, const double *bounds, const orc_mlp *mlp, int *iters, int *net_cycles);
 /* nsteps 3D-IMEX ARK2 steps (orc_step with L in place of L_V and the Schur
  * GMRES solve to tol; linear as in orc_step).  *iters: GMRES iterations in
  * total. */

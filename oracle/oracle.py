@@ -69,7 +69,7 @@ def _load():
     lib.orc_mlp_correction.argtypes = [C.c_void_p, C.POINTER(OrcMlp), _dp, _dp]
     lib.orc_learned_apply.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_int, _dp, C.POINTER(OrcMlp)]
     lib.orc_solve3d_learned.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
-                                        _dp, C.POINTER(OrcMlp), C.POINTER(C.c_int)]
+                                        _dp, C.POINTER(OrcMlp), C.POINTER(C.c_int), C.POINTER(C.c_int)]
     for name in ("orc_schur_apply", "orc_schur_rhs", "orc_pbno_apply", "orc_schur_bounds", "orc_solve3d",
                  "orc_solve3d_standard", "orc_step3d", "orc_element_features", "orc_mlp_correction",
                  "orc_learned_apply", "orc_solve3d_learned"):
@@ -315,12 +315,18 @@ class Oracle:
                                       C.byref(mlp.s) if mlp is not None else None), "orc_learned_apply")
         return out
 
-    def solve3d_learned(self, y, lam, mlp, tol=1e-12, restart=30, maxit=100000, order=-1, bounds=None):
+    def solve3d_learned(self, y, lam, mlp, tol=1e-12, restart=30, maxit=100000, order=-1, bounds=None,
+                        with_cycles=False):
+        """Flexible GMRES with PBNO + the network; returns (x, iterations), and
+        with with_cycles also the number of restart cycles that ran with the
+        network (the fallback switches it off after a cycle that does not cut
+        the residual tenfold)."""
         y = np.ascontiguousarray(y, dtype=np.float64)
         x = np.zeros(self.shape)
         it = C.c_int(0)
+        nc = C.c_int(0)
         bd = np.ascontiguousarray(bounds if bounds is not None else (1.0, 2.0), dtype=np.float64)
         _check(_lib.orc_solve3d_learned(self.h, y.reshape(-1), x.reshape(-1), float(lam), float(tol), int(restart),
                                         int(maxit), int(order), bd, C.byref(mlp.s) if mlp is not None else None,
-                                        C.byref(it)), "orc_solve3d_learned")
-        return x, it.value
+                                        C.byref(it), C.byref(nc)), "orc_solve3d_learned")
+        return (x, it.value, nc.value) if with_cycles else (x, it.value)

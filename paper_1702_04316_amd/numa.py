@@ -9,8 +9,7 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# NUMA_HEVI_LIB may name another build of the same library (tile experiments)
-LIB_PATH = os.environ.get("NUMA_HEVI_LIB") or os.path.join(_HERE, "libnuma_hevi.so")
+LIB_PATH = os.path.join(_HERE, "libnuma_hevi.so")
 
 NUMA_OK = 0
 NUMA_E_ARG = -1

@@ -254,6 +254,92 @@ def test_rhs_advection_and_buoyancy(oracle_mod):
     assert R[3][1:-1][th[1:-1] > 0.1].min() > 0
 
 
+def _set2nc_manufactured(lx, ly, lz, bg):
+    """A smooth state with every field nonzero and varying in x, y and z
+    (periodic in x and y, w = 0 on the walls), and the Set2NC tendencies
+    of Sec. 3.1 (continuity in divergence form) differentiated analytically
+    by sympy, P' by the chain rule through the equation of state, Eq. (10)."""
+    import sympy as sp
+    x, y, z = sp.symbols("x y z", real=True)
+    kx, ky = 2 * sp.pi / lx, 2 * sp.pi / ly
+    cp, R, g, th0, p00 = bg.cp, bg.rgas, bg.grav, bg.theta0, bg.p00
+    cv = cp - R
+    gam = cp / cv
+    pi0 = 1 - g * z / (cp * th0)
+    rho0 = p00 * pi0 ** (cv / R) / (R * th0)
+    P0 = p00 * (rho0 * R * th0 / p00) ** gam
+    rp = sp.Rational(4, 100) * (1 + sp.sin(kx * x + 0.7) * sp.cos(ky * y - 0.4) / 2) * (1 + z / (5 * lz))
+    th = 3 * sp.cos(kx * x - 0.3) * sp.sin(ky * y + 1.1) * (sp.Rational(1, 2) + z / lz) + 1
+    u = 12 + 8 * sp.sin(kx * x + 0.3) * sp.cos(ky * y + 0.8) * (1 + z / lz) + 3 * sp.sin(ky * y)
+    v = -7 + 6 * sp.cos(kx * x - 0.5) * sp.sin(ky * y) * sp.exp(-z / lz)
+    w = 5 * sp.sin(sp.pi * z / lz) * (1 + sp.Rational(3, 5) * sp.cos(kx * x + 0.2) * sp.sin(ky * y + 0.9))
+    rho, the = rho0 + rp, th0 + th
+    Pp = p00 * (rho * R * the / p00) ** gam - P0
+    d = sp.diff
+    tend = (
+        -(d(rho * u, x) + d(rho * v, y) + d(rho * w, z)),
+        -(u * d(u, x) + v * d(u, y) + w * d(u, z) + d(Pp, x) / rho),
+        -(u * d(v, x) + v * d(v, y) + w * d(v, z) + d(Pp, y) / rho),
+        -(u * d(w, x) + v * d(w, y) + w * d(w, z) + d(Pp, z) / rho + g * rp / rho),
+        -(u * d(th, x) + v * d(th, y) + w * d(th, z)),
+    )
+    f = lambda e: sp.lambdify((x, y, z), e, "numpy")
+    return [f(e) for e in (rp, u, v, w, th)], [f(e) for e in tend]
+
+
+@pytest.mark.parametrize("N,nex,nez,zface", [
+    (10, 8, 4, None),
+    (10, 8, 4, (0.0, 380.0, 1010.0, 1420.0, 2000.0)),
+    (12, 6, 3, (0.0, 610.0, 1350.0, 2000.0)),
+])
+def test_rhs_manufactured_solution(oracle_mod, N, nex, nez, zface):
+    """Every nonlinear Set2NC term, pinned by a manufactured solution: the
+    oracle's element-local collocation + DSS of a smooth state equals the
+    analytic tendencies to spectral accuracy (observed <= 7e-13 at these
+    orders; a swapped derivative axis, a flipped sign, the mass flux
+    rho0 u in place of rho u, or 1/rho0 in place of 1/rho in the pressure
+    gradient or the buoyancy each moves one tendency by >= 1e-2)."""
+    lx, ly, lz = 4000.0, 3000.0, 2000.0
+    bg = W.Background()
+    g = W.Grid(lx, ly, lz, nex, nex, nez, N, zface=None if zface is None else np.array(zface))
+    o = _oracle(oracle_mod, g)
+    qf, rf = _set2nc_manufactured(lx, ly, lz, bg)
+    xs, ys, zs = o.coords()
+    Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+    q = np.stack([np.broadcast_to(fn(X, Y, Z), X.shape) for fn in qf])
+    ref = np.stack([np.broadcast_to(fn(X, Y, Z), X.shape) for fn in rf])
+    R = o.rhs(q)
+    # w is imposed, not evolved, on the bottom and top nodes
+    assert np.all(R[3, 0] == 0.0) and np.all(R[3, -1] == 0.0)
+    ref[3, 0] = 0.0
+    ref[3, -1] = 0.0
+    for f in range(5):
+        e = np.linalg.norm(R[f] - ref[f]) / np.linalg.norm(ref[f])
+        assert e < 1e-10, (f, e)
+
+
+def test_rhs_manufactured_solution_converges_spectrally(oracle_mod):
+    """The same manufactured state at N = 6, 8, 10 on the same elements: the
+    error falls by orders of magnitude per step in N (spectral convergence of
+    the collocation derivative), so the agreement above is not a tolerance
+    wide enough to hide a wrong term."""
+    lx, ly, lz = 4000.0, 3000.0, 2000.0
+    bg = W.Background()
+    qf, rf = _set2nc_manufactured(lx, ly, lz, bg)
+    errs = []
+    for N in (6, 8, 10):
+        g = W.Grid(lx, ly, lz, 6, 6, 3, N)
+        o = _oracle(oracle_mod, g)
+        xs, ys, zs = o.coords()
+        Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+        q = np.stack([np.broadcast_to(fn(X, Y, Z), X.shape) for fn in qf])
+        ref = np.stack([np.broadcast_to(fn(X, Y, Z), X.shape) for fn in rf])
+        ref[3, 0] = ref[3, -1] = 0.0
+        R = o.rhs(q)
+        errs.append(max(np.linalg.norm(R[f] - ref[f]) / np.linalg.norm(ref[f]) for f in range(5)))
+    assert errs[0] > 30 * errs[1] > 30 * 30 * errs[2], errs
+
+
 def test_acoustic_phase_speed(oracle_mod):
     """With g = 0 the background is uniform and the full linear operator is
     linear acoustics: the x-mode of wavenumber k has frequency c0 k, with c0
@@ -800,3 +886,33 @@ def test_flexible_gmres_with_and_without_network(oracle_mod):
     assert it2 < 2 * it0
     res = x2 - lam * o.lfull(x2) - y
     assert np.linalg.norm(res) < 1e-9 * np.linalg.norm(y)
+
+
+def test_learned_guard_drops_a_failing_network_after_one_cycle(oracle_mod):
+    """The fallback rule of the learned preconditioner: a restart cycle with
+    the network that does not cut the true residual tenfold switches it off.
+    A network of large random weights proposes directions unrelated to S^-1,
+    so a short flexible cycle cannot cut the residual tenfold: it runs for
+    exactly one cycle, after which the polynomial alone finishes the solve
+    to the tolerance.  A network whose output is zero leaves PBNO's own
+    cycles, which at order 4 and restart 6 do cut the residual tenfold, so it
+    stays on for several cycles, and its iterations equal those of the
+    polynomial alone (switching it off changes nothing else)."""
+    g = _G3
+    o = _oracle(oracle_mod, g)
+    lam = (1.0 - 1.0 / math.sqrt(2.0)) * W.dt_for_courant(g, 15.0, "x")
+    bd = o.schur_bounds(lam, 30)
+    y = W.make_random_state(g, 3, smooth=False)
+    nin = (g.N + 1) ** 3
+    bad = _random_mlp(oracle_mod, nin, 8, 5, scale=30.0)
+    zero = oracle_mod.Mlp(np.zeros((8, nin)), np.zeros(8), np.zeros((nin, 8)), np.zeros(nin))
+    for order, m in ((1, 3), (2, 4), (4, 6)):
+        x, it, cyc = o.solve3d_learned(y, lam, bad, tol=1e-12, order=order, bounds=bd, restart=m, maxit=5000,
+                                       with_cycles=True)
+        assert cyc == 1, (order, m, cyc)
+        res = x - lam * o.lfull(x) - y
+        assert np.linalg.norm(res) < 1e-9 * np.linalg.norm(y)
+    x0, it0 = o.solve3d_learned(y, lam, None, tol=1e-12, order=4, bounds=bd, restart=6)
+    x1, it1, cyc1 = o.solve3d_learned(y, lam, zero, tol=1e-12, order=4, bounds=bd, restart=6, with_cycles=True)
+    assert cyc1 > 2 and it1 == it0
+    assert np.max(np.abs(x1 - x0)) < 1e-12 * np.max(np.abs(x0))
