@@ -122,6 +122,50 @@ def precision_form(numa, torch, ctx, wl, args, t_fp64):
     }
 
 
+def precision_form_n7(numa, torch, steps=20, err_steps=100):
+    """The precision-form workload at N=7: 28x28x28 elements of a stretched
+    1 km cube (196x196x197 = 7,567,952 unique nodes), vertical Courant
+    number 15.  FP64 and precision-form steps on the same GPU (per-kernel
+    HIP events), simulated seconds per wall second of each, and the
+    relative L2 difference per variable after err_steps steps (the FP64 step
+    equals the oracle to 1e-11; the tests check the precision form against
+    the oracle at N=7 on 4x4x4 elements)."""
+    import numpy as np
+    from paper_1702_04316_amd import workloads as W
+    wl = W.box_precision("large")
+    g = wl.grid
+    ctx = numa.Context(g, wl.background)
+    ctx.factor(wl.dt)
+    q0 = torch.from_numpy(W.make_initial_state(wl)).to("cuda")
+    names = ["rhs_stage1", "colsolve_stage2", "rhs_stage2", "colsolve_stage3", "rhs_stage3"]
+    out = {"workload": f"{wl.name}: 28x28x28 elements, LGL N=7, {g.nx}x{g.ny}x{g.nz} unique nodes, "
+                       "vertical Courant 15", "unique_nodes": g.n_unique, "dt_s": wl.dt}
+    for name, prof, mixed in (("fp64", numa.profile_steps, False), ("mixed", numa.profile_steps_mixed, True)):
+        q = q0.clone()
+        ctx.step(q, 3, mixed=mixed)
+        ctx.check()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ms = prof(ctx.ctx, q.data_ptr(), wl.dt, steps)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        ctx.check()
+        out[name] = {"ms_per_step": 1e3 * t, "value": 5 * g.n_unique / t, "sim_s_per_wall_s": wl.dt / t,
+                     "kernels": [{"kernel": n, "ms": m} for n, m in zip(names, ms)]}
+    out["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"]
+    a, b = q0.clone(), q0.clone()
+    ctx.step(a, err_steps)
+    ctx.step(b, err_steps, mixed=True)
+    ctx.check()
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    out["rel_l2_vs_fp64_after_%d_steps" % err_steps] = {
+        n: float(np.linalg.norm(b[f] - a[f]) / np.linalg.norm(a[f]))
+        for f, n in enumerate(("rho'", "u", "v", "w", "theta'"))}
+    out["unit"] = "DOF-steps/s"
+    ctx.close()
+    return out
+
+
 def standard_form_columns(numa, torch, ctx, wl, q, reps=20):
     """The column solve in its standard (rho', w) form against the Schur
     form on the benchmark grid: factor bytes, milliseconds per solve (HIP
@@ -478,6 +522,7 @@ def main():
                                                                   torch.from_numpy(W.make_initial_state(wl)).to("cuda"))}
     if not args.no_precision:
         out["precision_form"] = precision_form(numa, torch, ctx, wl, args, t)
+        out["precision_form_n7"] = precision_form_n7(numa, torch)
     if not args.no_ensemble:
         out["batched_ensemble"] = batched_ensemble(numa, torch)
     if not args.no_imex3d:

@@ -163,16 +163,19 @@ int numa_profile_steps(numa_ctx *c, double *state, double dt, int32_t nsteps, do
  * Precision form of numa_hevi_step.  Not a method of the paper (whose
  * kernels are FP64 and, by its own roofline measurements in Sec. 6.1,
  * mostly memory-bound): a project addition on top of the ARK2 HEVI step of
- * Sec. 2.2 that halves the bytes of most stage buffers.  The same five
- * kernels and stage algebra, with the right-hand
- * sides evaluated in FP32 (LDS planes, line and column derivatives,
- * tendencies) on FP32 stage buffers R1, E3, Q2, Q3, while the state, the
- * accumulator of the final combination, the pressure perturbation
- * P' = EOS(rho, theta) - P0 and the column solves (FP64 factors) stay in
- * FP64.  state: the FP64 device array of the state contract, advanced in
- * place.  Needs the factors of numa_factor_columns(dt) like the FP64 step.
- * The first call allocates 14 FP32 fields of stage buffers for the context
- * (freed by numa_destroy).  Asynchronous.  Errors: as numa_hevi_step, and
+ * Sec. 2.2 that halves the bytes of the horizontal velocities in the stage
+ * buffers and the right-hand sides' LDS traffic.  The same five kernels and
+ * stage algebra, with the right-hand sides evaluated in FP32 (LDS planes,
+ * line and column derivatives, tendencies) and u, v of the stage buffers
+ * R1, E3 in FP32, while the state, the accumulator of the final
+ * combination, rho', w and theta' of every stage buffer, the pressure
+ * perturbation P' = EOS(rho, theta) - P0 with its derivatives, the tendency
+ * of w (which holds the stiff vertical pressure gradient and buoyancy) and
+ * the column solves (FP64 factors) stay in FP64.  state: the FP64 device
+ * array of the state contract, advanced in place.  Needs the factors of
+ * numa_factor_columns(dt) like the FP64 step.  The first call allocates
+ * 96 bytes per unique node of stage buffers for the context (freed by
+ * numa_destroy).  Asynchronous.  Errors: as numa_hevi_step, and
  * NUMA_E_NOMEM.
  */
 int numa_hevi_step_mixed(numa_ctx *c, double *state, double dt, int32_t nsteps);

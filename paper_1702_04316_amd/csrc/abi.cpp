@@ -69,14 +69,14 @@ int step_preconditions(numa_ctx *c, double dt, const char *who)
     return NUMA_OK;
 }
 
-// The precision form's FP32 stage buffers, allocated on first use.
+// The precision form's stage buffers, allocated on first use.
 int ensure_mixed_buffers(numa_ctx *c, const char *who)
 {
     if (c->work_mix) return NUMA_OK;
-    hipError_t e = hipMalloc(&c->work_mix, size_t(80) * size_t(c->np));  // bytes per node
+    hipError_t e = hipMalloc(&c->work_mix, numa::kMixedBytesPerNode * size_t(c->np));
     if (e != hipSuccess) {
         c->work_mix = nullptr;
-        return hip_fail(c, e, (std::string(who) + ": hipMalloc(FP32 stage buffers)").c_str());
+        return hip_fail(c, e, (std::string(who) + ": hipMalloc(precision-form stage buffers)").c_str());
     }
     return NUMA_OK;
 }

@@ -66,7 +66,7 @@ struct numa_ctx {
     double *fac = nullptr;         // [nz][4N+1] column LU factors, one set shared by all columns
     int column_solver = 0;         // NUMA_SOLVER_*: 0 auto, 1 one lane per column, 2 level-blocked
     double *work = nullptr;        // stage buffers (19 fields)
-    char *work_mix = nullptr;      // precision form: R1, E3 (mixed layout), Q2, Q3 rho' (FP64), w (FP32)
+    char *work_mix = nullptr;      // precision form: R1, E3 (mixed layout), Q2, Q3 rho' and w (FP64)
     int *flag = nullptr;           // device non-finite flag
     int factored = 0;
     double dt_factored = 0, lambda = 0;
@@ -108,7 +108,11 @@ hipError_t launch_rhs_two(numa_ctx *c, const double *Q, const double *e0, const 
                           double *out1, double k01, double k02, double k11, double k12);
 hipError_t launch_rhs_final(numa_ctx *c, const double *Q, const double *e0, double *out, double k);
 hipError_t launch_hevi_step(numa_ctx *c, double *q, double dt, hipEvent_t *ev = nullptr);
+// the precision form's stage buffers: bytes per unique node
+constexpr size_t kMixedBytesPerNode = 96;
 hipError_t launch_hevi_step_mixed(numa_ctx *c, double *q, double dt, hipEvent_t *ev = nullptr);
+// the same with the stage buffers at mb (kMixedBytesPerNode * np bytes)
+hipError_t launch_hevi_step_mixed_in(numa_ctx *c, double *q, double dt, char *mb, hipEvent_t *ev = nullptr);
 hipError_t prepare_step(numa_ctx *c, bool mixed);
 hipError_t autotune_rhs_zchunk(numa_ctx *c, const double *state, int reps, int *chosen);
 // abi.cpp: NUMA_OK or the error code (message recorded in the context)

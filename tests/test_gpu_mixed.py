@@ -1,13 +1,11 @@
 """GPU tests of the precision form (numa_hevi_step_mixed): FP32 right-hand
-sides and u, v, w stage buffers; FP64 state, accumulator, rho'/theta' stage
-values, pressure perturbation and column solves.
+sides and u, v stage values; FP64 state, accumulator, rho'/w/theta' stage
+values, pressure perturbation, w tendency and column solves.
 
-The bar is the relative L2 error per variable against the FP64 oracle after
-100 steps that FP32 arithmetic allows: 1e-6, except w at N = 7, where the
-FP32 tendencies leave 2.4e-6 (checked at 5e-6 here; stated with the
-measured values in the design notes).  The form's FP64 parts are checked
-exactly: a rest state stays at rest, and its errors stay far below the
-FP32 rounding of its stage values.
+The bar is a relative L2 error per variable of at most 1e-6 against the
+FP64 oracle after 100 steps, at N = 4 and N = 7, and against the FP64 step
+(which equals the oracle to 1e-11) on the benchmarked grid after 100 steps.
+The form's FP64 parts are checked exactly: a rest state stays at rest.
 """
 import numpy as np
 import pytest
@@ -42,8 +40,8 @@ def _oracle(O, g, bg):
                     rgas=bg.rgas, grav=bg.grav, zface=g.zface)
 
 
-@pytest.mark.parametrize("name,wbar", [("box_small", BAR), ("box_precision", 5e-6)])
-def test_mixed_error_against_oracle(torch_cuda, numa_mod, oracle_mod, name, wbar):
+@pytest.mark.parametrize("name", ["box_small", "box_precision"])
+def test_mixed_error_against_oracle(torch_cuda, numa_mod, oracle_mod, name):
     wl = W.box_small("R1") if name == "box_small" else W.box_precision("small")
     g = wl.grid
     q0 = W.make_initial_state(wl)
@@ -57,24 +55,23 @@ def test_mixed_error_against_oracle(torch_cuda, numa_mod, oracle_mod, name, wbar
     ctx.check()
     e = _rel(q.cpu().numpy(), ref)
     print(f"{wl.name} mixed, 100 steps, rel L2 per variable (rho', u, v, w, theta'): {e}")
-    assert np.all(e[[0, 1, 2, 4]] < BAR), e
-    assert e[3] < wbar, e
+    assert np.all(e < BAR), e
     ctx.close()
 
 
 def test_mixed_full_size_against_fp64(torch_cuda, numa_mod):
-    """The benchmarked grid: 20 precision-form steps against 20 FP64 steps
+    """The benchmarked grid: 100 precision-form steps against 100 FP64 steps
     (the FP64 path equals the oracle to 1e-11)."""
     wl = W.box_large("R1")
     ctx = numa_mod.Context(wl.grid, wl.background)
     ctx.factor(wl.dt)
     q0 = torch_cuda.from_numpy(W.make_initial_state(wl)).cuda()
     a, b = q0.clone(), q0.clone()
-    ctx.step(a, 20)
-    ctx.step(b, 20, mixed=True)
+    ctx.step(a, 100)
+    ctx.step(b, 100, mixed=True)
     ctx.check()
     e = _rel(b.cpu().numpy(), a.cpu().numpy())
-    print(f"box_large mixed vs FP64, 20 steps: {e}")
+    print(f"box_large mixed vs FP64, 100 steps: {e}")
     assert np.all(e < BAR), e
     ctx.close()
 
