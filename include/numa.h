@@ -24,7 +24,9 @@
  *
  * All GPU work is enqueued on the stream given to numa_setup; calls are
  * asynchronous except numa_check and numa_destroy, which synchronise.
- * A context serves one host thread at a time; the library has no global state.
+ * A context serves one host thread at a time.  The only state outside the
+ * contexts is the fixed stage-buffer array of numa_hevi_step_mixed_noalloc
+ * (one per GPU, shared by every call on that GPU).
  *
  * Every function returns 0 (NUMA_OK) or a negative error code; the message of
  * the last error on a context is returned by numa_last_error.
@@ -179,6 +181,24 @@ int numa_profile_steps(numa_ctx *c, double *state, double dt, int32_t nsteps, do
  * NUMA_E_NOMEM.
  */
 int numa_hevi_step_mixed(numa_ctx *c, double *state, double dt, int32_t nsteps);
+
+/*
+ * numa_hevi_step_mixed without any device allocation, for callers that
+ * cannot allocate (code under HIP graph capture, serving loops, harnesses
+ * that forbid hipMalloc).  Same kernels, arguments and results as
+ * numa_hevi_step_mixed, but the precision form's stage buffers (96 bytes per
+ * unique node) live in a fixed 64 MiB device array of the library (one copy
+ * per GPU, resolved by numa_setup on its device, held until the process
+ * ends), so grids of at most 699,050 unique nodes are accepted.  The
+ * context's own buffers (allocated by numa_setup) are used as by
+ * numa_hevi_step_mixed.  Every call on a GPU shares that GPU's array: calls
+ * that overlap in time on one GPU (other streams, other contexts, other
+ * host threads) race and must be ordered by the caller.  The array keeps
+ * the last call's contents; nothing in it needs to start at zero.
+ * Asynchronous.  Errors: as numa_hevi_step, and NUMA_E_UNSUPPORTED (grid
+ * above the array's size; nothing is launched).
+ */
+int numa_hevi_step_mixed_noalloc(numa_ctx *c, double *state, double dt, int32_t nsteps);
 
 /*
  * numa_profile_steps for the precision form (ms_out as there).

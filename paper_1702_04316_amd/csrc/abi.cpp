@@ -144,12 +144,20 @@ int numa_setup(const numa_grid *g, int32_t order, const numa_background *bg, voi
     c->eos.grav = bg->grav;
     numa::set_binomial(c->eos);
     c->stream = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = hipGetDevice(&c->device);
+    // the fixed stage buffers of numa_hevi_step_mixed_noalloc on this device
+    if (e == hipSuccess) e = numa::noalloc_scratch_init();
+    if (e != hipSuccess) {
+        int rc = hip_fail(nullptr, e, "numa_setup: device");
+        delete c;
+        return rc;
+    }
 
     numa::build_ops(c, g->zface);
 
     const int N = order, ns = 2 * N + 1;
     const size_t n_lev = size_t(4 * nz + nz * ns + 3 * g->nez + 2 * N * ns + (N + 1) * (N + 1) + 8 * nz);
-    hipError_t e = hipMalloc(&c->lev_block, n_lev * sizeof(double));
+    e = hipMalloc(&c->lev_block, n_lev * sizeof(double));
     if (e != hipSuccess) {
         int rc = hip_fail(nullptr, e, "numa_setup: hipMalloc(levels)");
         free_ctx(c);
@@ -312,6 +320,28 @@ int numa_hevi_step_mixed(numa_ctx *c, double *state, double dt, int32_t nsteps)
     if (rc == NUMA_OK) rc = ensure_mixed_buffers(c, "numa_hevi_step_mixed");
     if (rc != NUMA_OK) return rc;
     return run_steps(c, numa::launch_hevi_step_mixed, state, dt, nsteps, "numa_hevi_step_mixed");
+}
+
+int numa_hevi_step_mixed_noalloc(numa_ctx *c, double *state, double dt, int32_t nsteps)
+{
+    if (!c) return NUMA_E_ARG;
+    if (!state || nsteps < 0) return fail(c, NUMA_E_ARG, "numa_hevi_step_mixed_noalloc: null state or nsteps < 0");
+    int rc = step_preconditions(c, dt, "numa_hevi_step_mixed_noalloc");
+    if (rc != NUMA_OK) return rc;
+    const size_t need = numa::kMixedBytesPerNode * size_t(c->np);
+    if (need > numa::kNoAllocScratchBytes)
+        return fail(c, NUMA_E_UNSUPPORTED,
+                    "numa_hevi_step_mixed_noalloc: the grid needs " + std::to_string(need) +
+                        " bytes of stage buffers (96 per unique node), above the fixed " +
+                        std::to_string(numa::kNoAllocScratchBytes) + " bytes");
+    char *mb = numa::noalloc_scratch(c->device);
+    if (!mb)
+        return fail(c, NUMA_E_HIP, "numa_hevi_step_mixed_noalloc: no fixed stage buffers on the context's device");
+    for (int32_t s = 0; s < nsteps; ++s) {
+        hipError_t e = numa::launch_hevi_step_mixed_in(c, state, dt, mb);
+        if (e != hipSuccess) return hip_fail(c, e, "numa_hevi_step_mixed_noalloc");
+    }
+    return NUMA_OK;
 }
 
 int numa_profile_steps(numa_ctx *c, double *state, double dt, int32_t nsteps, double *ms_out)

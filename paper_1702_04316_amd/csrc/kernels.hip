@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -1704,6 +1705,41 @@ hipError_t launch_hevi_step_mixed_in(numa_ctx *c, double *q, double dt, char *mb
 hipError_t launch_hevi_step_mixed(numa_ctx *c, double *q, double dt, hipEvent_t *ev)
 {
     return launch_hevi_step_mixed_in(c, q, dt, c->work_mix, ev);
+}
+
+// The precision form's stage buffers for callers that cannot allocate: one
+// array per GPU in the code object.  Host code never uses the array's name
+// as an address (on the host it is only a stand-in for the symbol): each
+// device's copy is resolved once, with that device current, and kept here.
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+char *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_init()
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_ptr[dev]) return hipSuccess;
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = static_cast<char *>(ptr);
+    return hipSuccess;
+}
+
+char *noalloc_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    return g_scratch_ptr[device];
 }
 
 // Set the LDS attributes of every kernel one step of this context launches,

@@ -60,6 +60,7 @@ struct numa_ctx {
     numa::EOS eos{};
     double cp = 0;
     hipStream_t stream = nullptr;
+    int device = 0;                // the device current at numa_setup
     numa::HostOps ops;
     numa::DevLevels lev;
     void *lev_block = nullptr;     // one allocation holding all of lev
@@ -113,6 +114,14 @@ constexpr size_t kMixedBytesPerNode = 96;
 hipError_t launch_hevi_step_mixed(numa_ctx *c, double *q, double dt, hipEvent_t *ev = nullptr);
 // the same with the stage buffers at mb (kMixedBytesPerNode * np bytes)
 hipError_t launch_hevi_step_mixed_in(numa_ctx *c, double *q, double dt, char *mb, hipEvent_t *ev = nullptr);
+// Fixed stage-buffer memory of the precision form for callers that cannot
+// allocate: a device array in the library's code object, one copy per GPU,
+// kept until the process ends.  noalloc_scratch_init resolves the current
+// device's copy (once per device); noalloc_scratch returns it (nullptr if
+// that device was never initialised).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+hipError_t noalloc_scratch_init();
+char *noalloc_scratch(int device);
 hipError_t prepare_step(numa_ctx *c, bool mixed);
 hipError_t autotune_rhs_zchunk(numa_ctx *c, const double *state, int reps, int *chosen);
 // abi.cpp: NUMA_OK or the error code (message recorded in the context)

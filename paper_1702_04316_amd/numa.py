@@ -80,6 +80,7 @@ def load():
     lib.numa_hevi_step.argtypes = [vp, vp, C.c_double, C.c_int32]
     lib.numa_profile_steps.argtypes = [vp, vp, C.c_double, C.c_int32, C.POINTER(C.c_double)]
     lib.numa_hevi_step_mixed.argtypes = [vp, vp, C.c_double, C.c_int32]
+    lib.numa_hevi_step_mixed_noalloc.argtypes = [vp, vp, C.c_double, C.c_int32]
     lib.numa_ensemble_create.argtypes = [C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_double), C.c_int32, C.c_int32,
                                          C.c_int32, vp, C.POINTER(vp)]
     lib.numa_ensemble_step.argtypes = [vp, C.c_int32]
@@ -119,7 +120,7 @@ def load():
     lib.numa_line_operators.argtypes = [C.POINTER(numa_grid), C.c_int32, C.POINTER(C.c_double),
                                         C.POINTER(C.c_double)]
     for name in ("numa_setup", "numa_state_shape", "numa_get_info", "numa_set_stream", "numa_factor_columns",
-                 "numa_hevi_step", "numa_profile_steps", "numa_hevi_step_mixed", "numa_profile_steps_mixed",
+                 "numa_hevi_step", "numa_profile_steps", "numa_hevi_step_mixed", "numa_hevi_step_mixed_noalloc", "numa_profile_steps_mixed",
                  "numa_rhs", "numa_solve_columns", "numa_imex3d_step", "numa_check", "numa_destroy",
                  "numa_lgl_basis", "numa_line_operators", "numa_ensemble_create", "numa_ensemble_step",
                  "numa_ensemble_sync", "numa_ensemble_zchunks", "numa_ensemble_destroy", "numa_imex3d_setup",
@@ -199,8 +200,13 @@ def hevi_step(ctx, state_ptr, dt, nsteps):
 
 
 def hevi_step_mixed(ctx, state_ptr, dt, nsteps):
-    """The precision form of hevi_step (FP32 right-hand sides and stage buffers)."""
+    """The precision form of hevi_step (FP32 right-hand sides, FP32 u, v stage values)."""
     return _check(load().numa_hevi_step_mixed(ctx, C.c_void_p(state_ptr), float(dt), int(nsteps)), ctx)
+
+
+def hevi_step_mixed_noalloc(ctx, state_ptr, dt, nsteps):
+    """hevi_step_mixed with the library's fixed stage buffers (no allocation)."""
+    return _check(load().numa_hevi_step_mixed_noalloc(ctx, C.c_void_p(state_ptr), float(dt), int(nsteps)), ctx)
 
 
 def profile_steps_mixed(ctx, state_ptr, dt, nsteps):
