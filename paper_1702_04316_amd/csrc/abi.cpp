@@ -332,7 +332,7 @@ int numa_hevi_step_mixed_noalloc(numa_ctx *c, double *state, double dt, int32_t 
     if (need > numa::kNoAllocScratchBytes)
         return fail(c, NUMA_E_UNSUPPORTED,
                     "numa_hevi_step_mixed_noalloc: the grid needs " + std::to_string(need) +
-                        " bytes of stage buffers (96 per unique node), above the fixed " +
+                        " bytes of stage buffers (104 per unique node), above the fixed " +
                         std::to_string(numa::kNoAllocScratchBytes) + " bytes");
     char *mb = numa::noalloc_scratch(c->device);
     if (!mb)

@@ -55,11 +55,12 @@ struct RhsGeom {
     static constexpr int FS = LX * LY;              // one field of one plane
     // a plane: rho', u, v, w, theta' (ES bytes each), then P' in FP64 (the
     // pressure and its derivatives stay FP64 in every form), and with FP32
-    // fields an FP64 copy of rho' for the buoyancy, which nearly balances
-    // the vertical pressure gradient
+    // fields FP64 copies of rho' and w for the buoyancy, the mass flux and
+    // w's tendency
     static constexpr int POFF = (5 * FS * ES + 7) / 8 * 8;  // byte offset of P'
     static constexpr int ROFF = POFF + 8 * FS;               // byte offset of the FP64 rho' (ES = 4)
-    static constexpr int PB = ROFF + (ES == 8 ? 0 : 8 * FS); // bytes of a plane
+    static constexpr int WOFF = ROFF + 8 * FS;               // byte offset of the FP64 w (ES = 4)
+    static constexpr int PB = ES == 8 ? ROFF : WOFF + 8 * FS; // bytes of a plane
     static constexpr int NS = 2 * N + 1;            // x/y stencil width
     // cross-shaped part of a plane that is loaded: tile rows with the x halo,
     // plus the y-halo rows of the tile columns
@@ -174,7 +175,7 @@ struct RhsParams {
 enum { EPI_R = 0, EPI_TWO = 1, EPI_FINAL = 2 };
 
 // Layout of a five-field stage buffer of np nodes: all FP64, or (M) the
-// precision form's u and v in FP32 with rho', w and theta' in FP64.  The
+// precision form's R1 with u and v in FP32 and rho', w, theta' in FP64.  The
 // pressure perturbation P0 ((1+x)^gamma - 1) scales the relative rounding of
 // rho' and theta' by P0, so their stage values stay FP64; w's tendency holds
 // the stiff vertical pressure gradient and buoyancy, whose FP32 rounding,
@@ -210,17 +211,19 @@ struct FiveField {
 // Buffers of one right-hand-side launch.  The FP64 step keeps every field
 // in FP64.  The precision form (MIX) keeps the state q and the accumulator
 // ACC (e0 of the last two launches, out1) in FP64, its other stage buffers
-// in the mixed layout, and the LDS ring (except P' and an FP64 copy of
-// rho') and the stencil arithmetic in FP32.  FP64 in that form: P' and its
-// derivatives, w's tendency, and the mass flux (rho0 + rho') u_i with its
-// divergence.  The flux divergence is a small difference of large terms at
-// the finest LGL spacing, and its FP32 rounding, carried through rho' into
-// the buoyancy, left 2.5e-6 relative error in w after 100 steps at N = 7.
+// in the mixed layout, and the LDS ring (except P' and FP64 copies of rho'
+// and w) and the stencil arithmetic in FP32.  FP64 in that form: P' and its
+// derivatives, w with its derivatives and tendency, and the mass flux
+// (rho0 + rho') u_i with its divergence.  The flux divergence is a small
+// difference of large terms at the finest LGL spacing, and its FP32
+// rounding, carried through rho' into the buoyancy, left 2.5e-6 relative
+// error in w after 100 steps at N = 7; FP32 derivatives of w under a strong
+// wind left 2e-6 after 50 steps at N = 3.
 template <int EPI, bool MIX>
 struct RhsTypes {
-    using A = FiveField<MIX && EPI != EPI_R>;       // inputs a[]
+    using A = FiveField<false>;                     // inputs a[]
     using E1 = FiveField<MIX>;                      // e1 (R1)
-    using O0 = FiveField<MIX && EPI != EPI_FINAL>;  // out0
+    using O0 = FiveField<MIX && EPI == EPI_R>;      // out0 (R1 in the first launch)
     using D = FiveField<false>;                     // e0, out1
     using C = std::conditional_t<MIX, float, double>;
 };
@@ -264,6 +267,7 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
     auto cfield = [&](int slot) { return reinterpret_cast<C *>(ringb + slot * G::PB); };
     auto pfield = [&](int slot) { return reinterpret_cast<double *>(ringb + slot * G::PB + G::POFF); };
     auto rfield = [&](int slot) { return reinterpret_cast<double *>(ringb + slot * G::PB + G::ROFF); };
+    auto wfield = [&](int slot) { return reinterpret_cast<double *>(ringb + slot * G::PB + G::WOFF); };
     __shared__ C sw[2][N][NS];
     __shared__ C sD[NQ * NQ];
     // FP64 copies of the tables for the mass flux of the precision form (the
@@ -316,6 +320,18 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
         sIRT[s] = 1.0 / (r0 * eos.theta0);
     }
     for (int s = tid; s < 3 * p.nez; s += G::NT) zs[s] = p.zsc[s];
+    // Precision form: the ring holds u - uref and v - vref in FP32, with the
+    // workgroup's reference velocities uref, vref (FP64) taken at the first
+    // node of its tile.  A wind far larger than its variation (a uniform
+    // wind) then keeps its variation's relative precision in the FP32
+    // derivatives, which annihilate the constants; u and v themselves are
+    // uref + (u - uref).  The FP64 form stores u and v as they are.
+    double uref = 0.0, vref = 0.0;
+    if constexpr (MIX) {
+        const unsigned oref = unsigned(ez0 * N) * pbytes + unsigned(y0 * nx + x0) * 8u;
+        uref = stage_input<HASB, TA, TE1>(p, 1, oref);
+        vref = stage_input<HASB, TA, TE1>(p, 2, oref);
+    }
 
     // plane loads of this thread: which of the N new planes (1..N, 0 = none),
     // LDS offset in the plane, byte offset in a level plane
@@ -388,33 +404,42 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
             const double Pp = pressure_perturbation(v[s][0], v[s][4], sR0[kl], sP0[kl], sIRT[kl], eos);
             C *d = cfield(k % NQ) + it_l[s];
             d[0 * FS] = C(v[s][0]);
-            d[1 * FS] = C(v[s][1]);
-            d[2 * FS] = C(v[s][2]);
+            d[1 * FS] = C(v[s][1] - uref);
+            d[2 * FS] = C(v[s][2] - vref);
             d[3 * FS] = C(v[s][3]);
             d[4 * FS] = C(v[s][4]);
             pfield(k % NQ)[it_l[s]] = Pp;
-            if constexpr (MIX) rfield(k % NQ)[it_l[s]] = v[s][0];
+            if constexpr (MIX) {
+                rfield(k % NQ)[it_l[s]] = v[s][0];
+                wfield(k % NQ)[it_l[s]] = v[s][3];
+            }
         }
     };
 
     // sum_n D[r][n] g(level ez*N + n) over the own column for the six
     // z-differentiated quantities rho w, u, v, w, theta' (out) and P' (outp)
     // (not unrolled: unrolled, all 6*(N+1) LDS reads would be in flight at once)
-    auto zsum = [&](int ez, int r, C *out, double &outp, double &outr) {
+    auto zsum = [&](int ez, int r, C *out, double &outp, double &outr, double &outw) {
 #pragma unroll
         for (int f = 0; f < 5; ++f) out[f] = C(0);
         outp = 0.0;
         outr = 0.0;
+        outw = 0.0;
         int k = ez * N, slot = k % NQ;
 #pragma unroll 1
         for (int n = 0; n < NQ; ++n) {
             const C *q = cfield(slot) + l_own;
             const C d = sD[r * NQ + n];
-            if constexpr (MIX) outr += sDd[r * NQ + n] * ((sR0[k - kb] + rfield(slot)[l_own]) * double(q[3 * FS]));
-            else outr += double(d) * ((C(sR0[k - kb]) + q[0]) * q[3 * FS]);
+            if constexpr (MIX) {
+                const double wv = wfield(slot)[l_own], dd = sDd[r * NQ + n];
+                outr += dd * ((sR0[k - kb] + rfield(slot)[l_own]) * wv);
+                outw += dd * wv;
+            } else {
+                outr += double(d) * ((C(sR0[k - kb]) + q[0]) * q[3 * FS]);
+                outw += double(d) * q[3 * FS];
+            }
             out[1] += d * q[1 * FS];
             out[2] += d * q[2 * FS];
-            out[3] += d * q[3 * FS];
             out[4] += d * q[4 * FS];
             outp += double(d) * pfield(slot)[l_own];
             ++k;
@@ -441,11 +466,16 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
     // tendencies at level k (Set2NC, Sec. 3.1) from the x/y line derivatives
     // of the plane in the ring and the scaled vertical derivatives dz; then
     // the stage epilogue with its inputs ev
-    auto node = [&](int k, const C *dz, double dzp, double dz0, const double *ev) {
+    auto node = [&](int k, const C *dz, double dzp, double dz0, double dzw, const double *ev) {
         const C *q = cfield(k % NQ);
         const double *qp = pfield(k % NQ);
         const C r0 = C(sR0[k - kb]);
-        const C rp = q[l_own], u = q[FS + l_own], v = q[2 * FS + l_own], w = q[3 * FS + l_own];
+        const C rp = q[l_own], w = q[3 * FS + l_own];
+        C u = q[FS + l_own], v = q[2 * FS + l_own];
+        if constexpr (MIX) {
+            u = C(uref + double(u));
+            v = C(vref + double(v));
+        }
         const C ir = C(1) / (r0 + rp);
         // rho' and 1/rho for the pressure and buoyancy terms: FP64 in every form
         const double rpd = MIX ? rfield(k % NQ)[l_own] : double(rp);
@@ -462,46 +492,52 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
         // form only its advection products are FP32)
         double R3;
         if constexpr (MIX)
-            R3 = double(w * dz[3]) + (dzp * irp + eos.grav * rpd * irp);
+            R3 = wfield(k % NQ)[l_own] * dzw + (dzp * irp + eos.grav * rpd * irp);
         else
-            R3 = w * dz[3] + dzp * ir + eos.grav * rp * ir;
+            R3 = w * dzw + dzp * ir + eos.grav * rp * ir;
         R[4] = w * dz[4];
         // line derivative of the six quantities along x (dir 0) or y (dir 1)
         // (not unrolled: unrolled, the scheduler hoists all its LDS reads)
-        auto line = [&](int dir, C *d5, double &dp, double &dfl) {
+        auto line = [&](int dir, C *d5, double &dp, double &dfl, double &dwl) {
             const C *cw = dir == 0 ? cwx : cwy;
             const double *cwd = dir == 0 ? cwxd : cwyd;
             const double *rq = rfield(k % NQ);
+            const double *wq = wfield(k % NQ);
             const int base = dir == 0 ? l_x : l_y, step = dir == 0 ? 1 : LX;
             const int fv = dir == 0 ? FS : 2 * FS;  // the velocity in rho u or rho v
+            const double vr = dir == 0 ? uref : vref;
 #pragma unroll
             for (int f = 0; f < 5; ++f) d5[f] = C(0);
             dp = 0.0;
             dfl = 0.0;
+            dwl = 0.0;
 #pragma unroll 1
             for (int m = 0; m < NS; ++m) {
                 const C cm = cw[m];
                 const C *qm = q + base + m * step;
-                if constexpr (MIX) dfl += cwd[m] * ((sR0[k - kb] + rq[base + m * step]) * double(qm[fv]));
+                if constexpr (MIX) dfl += cwd[m] * ((sR0[k - kb] + rq[base + m * step]) * (vr + double(qm[fv])));
                 else dfl += double(cm) * ((r0 + qm[0]) * qm[fv]);
-#pragma unroll
-                for (int f = 1; f < 5; ++f) d5[f] += cm * qm[f * FS];
+                d5[1] += cm * qm[1 * FS];
+                d5[2] += cm * qm[2 * FS];
+                if constexpr (MIX) dwl += cwd[m] * wq[base + m * step];
+                else dwl += double(cm) * qm[3 * FS];
+                d5[4] += cm * qm[4 * FS];
                 dp += double(cm) * qp[base + m * step];
             }
         };
         C d5[5];
-        double dp, dfl;
-        line(0, d5, dp, dfl);
+        double dp, dfl, dwl;
+        line(0, d5, dp, dfl, dwl);
         R0 += dfl;
         R[1] += u * d5[1] + C(dp * irp);
         R[2] += u * d5[2];
-        R3 += double(u * d5[3]);
+        R3 += double(u) * dwl;
         R[4] += u * d5[4];
-        line(1, d5, dp, dfl);
+        line(1, d5, dp, dfl, dwl);
         R0 = -(R0 + dfl);
         R[1] = -(R[1] + v * d5[1]);
         R[2] = -(R[2] + v * d5[2] + C(dp * irp));
-        R3 = -(R3 + double(v * d5[3]));
+        R3 = -(R3 + double(v) * dwl);
         R[4] = -(R[4] + v * d5[4]);
         if (k == 0 || k == p.nz - 1) R3 = 0.0;
         if (!owner) return;
@@ -545,12 +581,15 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
         const double Pp = pressure_perturbation(rp, th, sR0[kl], sP0[kl], sIRT[kl], eos);
         C *d = cfield(k % NQ) + it_l[s];
         d[0 * FS] = C(rp);
-        d[1 * FS] = C(u);
-        d[2 * FS] = C(v);
+        d[1 * FS] = C(u - uref);
+        d[2 * FS] = C(v - vref);
         d[3 * FS] = C(w);
         d[4 * FS] = C(th);
         pfield(k % NQ)[it_l[s]] = Pp;
-        if constexpr (MIX) rfield(k % NQ)[it_l[s]] = rp;
+        if constexpr (MIX) {
+            rfield(k % NQ)[it_l[s]] = rp;
+            wfield(k % NQ)[it_l[s]] = w;
+        }
     }
     if (c == 0 && ez0 > 0) {
         const int eb = ez0 - 1;
@@ -559,8 +598,10 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
             const int k = eb * N + n, kl = k - kb;
             const unsigned off = unsigned(k) * pbytes + own;
             // rounded to the ring's type first, as the layer loop sees them
-            const double rp = C(stage_input<HASB, TA, TE1>(p, 0, off)), u = C(stage_input<HASB, TA, TE1>(p, 1, off));
-            const double v = C(stage_input<HASB, TA, TE1>(p, 2, off)), w = C(stage_input<HASB, TA, TE1>(p, 3, off));
+            const double rp = C(stage_input<HASB, TA, TE1>(p, 0, off));
+            const double u = C(stage_input<HASB, TA, TE1>(p, 1, off) - uref);
+            const double v = C(stage_input<HASB, TA, TE1>(p, 2, off) - vref);
+            const double w = stage_input<HASB, TA, TE1>(p, 3, off);  // FP64 in both forms
             const double th0 = stage_input<HASB, TA, TE1>(p, 4, off), th = C(th0);
             const double rho = MIX ? sR0[kl] + stage_input<HASB, TA, TE1>(p, 0, off) : double(C(sR0[kl])) + rp;
             const double Pp = pressure_perturbation(stage_input<HASB, TA, TE1>(p, 0, off), th0, sR0[kl], sP0[kl],
@@ -576,7 +617,7 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
         const double st = zs[2 * p.nez + eb];
         double *zb = zp + (ez0 & 1) * 6 * (TX * TY) + txy;
 #pragma unroll
-        for (int f = 0; f < 5; ++f) zb[f * (TX * TY)] = f == 0 ? st * acc[0] : double(C(st * acc[f]));
+        for (int f = 0; f < 5; ++f) zb[f * (TX * TY)] = (f == 0 || f == 3) ? st * acc[f] : double(C(st * acc[f]));
         zb[5 * (TX * TY)] = st * acc[5];
     }
 
@@ -587,8 +628,8 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
         double ev[NEPI];
         epi_load(unsigned(ez * N + c) * pbytes + own, ev);
         C dz[5], sum[5];
-        double sump, sumr;
-        zsum(ez, c, sum, sump, sumr);
+        double sump, sumr, sumw;
+        zsum(ez, c, sum, sump, sumr, sumw);
         const double scd = (c == 0) ? zs[p.nez + ez] : zs[ez];
         const C sc = C(scd);
         const double *zb = zp + (ez & 1) * 6 * (TX * TY) + txy;
@@ -597,16 +638,18 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
         for (int f = 0; f < 5; ++f) dz[f] = (below ? C(zb[f * (TX * TY)]) : C(0)) + sc * sum[f];
         const double dzp = (below ? zb[5 * (TX * TY)] : 0.0) + scd * sump;
         const double dz0 = (below ? zb[0] : 0.0) + scd * sumr;
-        node(ez * N + c, dz, dzp, dz0, ev);
+        const double dzw = (below ? zb[3 * (TX * TY)] : 0.0) + scd * sumw;
+        node(ez * N + c, dz, dzp, dz0, dzw, ev);
         // this element's share of the interface (or top node) above
         const double st = zs[2 * p.nez + ez];
         double *zn = zp + ((ez + 1) & 1) * 6 * (TX * TY) + txy;
         if (c == 0) {
             C s5[5];
-            double s5p, s5r;
-            zsum(ez, N, s5, s5p, s5r);
+            double s5p, s5r, s5w;
+            zsum(ez, N, s5, s5p, s5r, s5w);
 #pragma unroll
-            for (int f = 0; f < 5; ++f) zn[f * (TX * TY)] = f == 0 ? st * s5r : double(C(st) * s5[f]);
+            for (int f = 0; f < 5; ++f)
+                zn[f * (TX * TY)] = f == 0 ? st * s5r : (f == 3 ? st * s5w : double(C(st) * s5[f]));
             zn[5 * (TX * TY)] = st * s5p;
         }
     }
@@ -620,7 +663,7 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
         const double dzp = zb[5 * (TX * TY)];
         double ev[NEPI];
         epi_load(unsigned(p.nez * N) * pbytes + own, ev);
-        node(p.nez * N, dz, dzp, zb[0], ev);
+        node(p.nez * N, dz, dzp, zb[0], zb[3 * (TX * TY)], ev);
     }
 }
 
@@ -1616,21 +1659,23 @@ size_t mixed_field_offset(int f, long np)
 }
 
 // The precision form of the step (same stage algebra as launch_hevi_step):
-// the right-hand sides evaluate in FP32 (P', its derivatives and w's
-// tendency in FP64); the stage buffers R1 and E3 hold u, v in FP32 and
-// rho', w, theta' in FP64, Q2 and Q3 (rho', w) are FP64; the state and the
-// accumulator ACC stay FP64; the column solves read those and run in FP64
-// with the FP64 factors.  mb: mixed_buffer_bytes(np) bytes of stage buffers.
+// the right-hand sides evaluate in FP32 (P', its derivatives, w's tendency
+// and the mass flux in FP64); the stage buffer R1 holds u, v in FP32 and
+// rho', w, theta' in FP64, E3 and Q2, Q3 (rho', w) are FP64 (E3's u and v
+// are differentiated by the last right-hand side, and their FP32 rounding
+// would be amplified there like any rounding of a stage value); the state
+// and the accumulator ACC stay FP64; the column solves read those and run
+// in FP64 with the FP64 factors.  mb: kMixedBytesPerNode * np bytes.
 hipError_t launch_hevi_step_mixed_in(numa_ctx *c, double *q, double dt, char *mb, hipEvent_t *ev)
 {
     static const Ark2 t;
     const long np = c->np;
-    // R1, E3 in the mixed five-field layout (32 bytes per node), then Q2 and
-    // Q3 rho' and w
+    // R1 in the mixed five-field layout (32 bytes per node), E3 in FP64 (40),
+    // then Q2 and Q3 rho' and w
     char *const R1 = mb, *const E3 = mb + 32 * np;
-    double *const Q2r = reinterpret_cast<double *>(mb + 64 * np), *const Q3r = reinterpret_cast<double *>(mb + 72 * np);
-    double *const Q2w = reinterpret_cast<double *>(mb + 80 * np), *const Q3w = reinterpret_cast<double *>(mb + 88 * np);
-    auto fld = [&](char *buf, int f) { return buf + mixed_field_offset(f, np); };
+    double *const Q2r = reinterpret_cast<double *>(mb + 72 * np), *const Q3r = reinterpret_cast<double *>(mb + 80 * np);
+    double *const Q2w = reinterpret_cast<double *>(mb + 88 * np), *const Q3w = reinterpret_cast<double *>(mb + 96 * np);
+    auto fld = [&](char *buf, int f) { return buf + (buf == E3 ? size_t(8) * f * np : mixed_field_offset(f, np)); };
     double *const ACC = stage_buffers(c).ACC;
     const double *qr = q + 0 * np, *qw = q + 3 * np, *qt = q + 4 * np;
     const double f = dt * t.a21;

@@ -110,7 +110,7 @@ hipError_t launch_rhs_two(numa_ctx *c, const double *Q, const double *e0, const 
 hipError_t launch_rhs_final(numa_ctx *c, const double *Q, const double *e0, double *out, double k);
 hipError_t launch_hevi_step(numa_ctx *c, double *q, double dt, hipEvent_t *ev = nullptr);
 // the precision form's stage buffers: bytes per unique node
-constexpr size_t kMixedBytesPerNode = 96;
+constexpr size_t kMixedBytesPerNode = 104;
 hipError_t launch_hevi_step_mixed(numa_ctx *c, double *q, double dt, hipEvent_t *ev = nullptr);
 // the same with the stage buffers at mb (kMixedBytesPerNode * np bytes)
 hipError_t launch_hevi_step_mixed_in(numa_ctx *c, double *q, double dt, char *mb, hipEvent_t *ev = nullptr);

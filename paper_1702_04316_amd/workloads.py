@@ -338,6 +338,35 @@ def ensemble_domains(seed=4, n=16):
     return out
 
 
+def ensemble_small_domains(seed=7):
+    """One domain per order N in {3, 4, 5, 7} drawn like ensemble_domains
+    (vertical elements spanning 6..16, a uniform wind of 0..20 m/s in a
+    random direction, 1..3 theta' bumps, vertical Courant number 15 and the
+    horizontal extent stretched to a horizontal Courant number of 0.4 with
+    c0 + |u|), on 3..4 horizontal elements per axis so that the oracle can
+    step every domain.  Bumps of 0.1..1 K with radii of 1..2 km: with the
+    ensemble's 0.5..2 km radii some of these small periodic boxes sum the
+    bump's images into a layer of theta' decreasing with height several
+    kelvin deep, statically unstable over the neutral background, which
+    convects within 50..70 steps (in the oracle as on the GPU) and turns
+    rounding differences into exponentially growing ones."""
+    rng = np.random.default_rng(seed)
+    c0 = sound_speed()
+    out = []
+    for d, (N, nez) in enumerate(((3, 6), (4, 10), (5, 13), (7, 16))):
+        ne = int(rng.integers(3, 5))
+        speed = float(rng.uniform(0.0, 20.0))
+        ang = float(rng.uniform(0.0, 2.0 * np.pi))
+        nb = int(rng.integers(1, 4))
+        lx, lz = 20000.0 * ne / 64, 10000.0
+        s = _stretch(lx, ne, lz, nez) * (c0 + speed) / c0
+        g = Grid(lx * s, lx * s, lz, ne, ne, nez, N)
+        dt = dt_for_courant(g, C_VERT, "z")
+        out.append(Workload(f"ens_small{d}_{ne}x{ne}x{nez}_N{N}", g, dt, 50, 100 * seed + d, nb, (0.1, 1.0),
+                            (1000.0, 2000.0), stretch=s, wind=(speed * np.cos(ang), speed * np.sin(ang))))
+    return out
+
+
 IMEX3D_COURANT = 15.0
 IMEX3D_TOL = 1e-8
 

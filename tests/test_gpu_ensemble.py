@@ -30,9 +30,12 @@ def numa_mod():
     return numa
 
 
-# (N, nex, ney, nez, wind u, v, seed): orders 3..7, ragged tiles, winds
+# (N, nex, ney, nez, wind u, v, seed): orders 3..7, ragged tiles, winds, and
+# tall columns (N = 5 with 71 levels, N = 7 with 113) whose column solves use
+# eight wavefronts and more than 64 KB of LDS per workgroup
 DOMAINS = [(3, 6, 5, 4, 12.0, -3.0, 1), (4, 5, 4, 3, 0.0, 0.0, 2), (5, 3, 3, 3, -8.0, 5.0, 3),
-           (7, 2, 3, 2, 4.0, 15.0, 4), (4, 9, 2, 5, 20.0, 0.0, 5)]
+           (7, 2, 3, 2, 4.0, 15.0, 4), (4, 9, 2, 5, 20.0, 0.0, 5), (5, 3, 2, 14, 6.0, -6.0, 6),
+           (7, 2, 2, 16, -10.0, 2.0, 7)]
 
 
 def _domain(torch, numa, N, nex, ney, nez, u, v, seed):
@@ -97,3 +100,55 @@ def test_ensemble_argument_errors(torch_cuda, numa_mod):
     assert lib.numa_ensemble_step(None, 1) == numa_mod.NUMA_E_ARG
     a.close()
     b.close()
+
+
+def _oracle(O, g, bg):
+    return O.Oracle(g.lx, g.ly, g.lz, g.nex, g.ney, g.nez, g.N, theta0=bg.theta0, p00=bg.p00, cp=bg.cp,
+                    rgas=bg.rgas, grav=bg.grav, zface=g.zface)
+
+
+# Relative L2 bars per variable (rho', u, v, w, theta') after up to 50 steps.
+# The precision form's w on the N = 3 domain (6 vertical elements of
+# 1.7 km, theta' spread over the whole small box) reaches 2.3e-6: its FP32
+# theta', u and v tendencies couple into w through the pressure and the
+# buoyancy, and w is the smallest variable (the same domain without wind
+# leaves 2.4e-6 in u and v too); the other three domains stay below 9e-7.
+ORACLE_BARS = {False: [1e-11] * 5, True: [1e-6, 1e-6, 1e-6, 3e-6, 1e-6]}
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("mixed", [False, True])
+def test_ensemble_matches_oracle(torch_cuda, numa_mod, oracle_mod, mixed):
+    """One domain per order (3, 4, 5, 7), 6..16 vertical elements, winds of
+    up to 20 m/s, vertical Courant number 15: 50 steps of the captured
+    ensemble graph against 50 oracle steps of each domain, compared every 10
+    steps (FP64 form to 1e-11; precision form to ORACLE_BARS)."""
+    bar = np.array(ORACLE_BARS[mixed])
+    doms = W.ensemble_small_domains()
+    ctxs, states, orcs, qos = [], [], [], []
+    for wl in doms:
+        g = wl.grid
+        c = numa_mod.Context(g, wl.background)
+        c.factor(wl.dt)
+        q0 = W.make_initial_state(wl)
+        ctxs.append(c)
+        states.append(torch_cuda.from_numpy(q0.copy()).cuda())
+        o = _oracle(oracle_mod, g, wl.background)
+        o.factor_dt(wl.dt)
+        orcs.append(o)
+        qos.append(q0)
+    ens = numa_mod.Ensemble(ctxs, states, mixed=mixed, tune=True)
+    worst = np.zeros((len(doms), 5))
+    for block in range(5):
+        ens.step(10)
+        ens.sync()
+        for i, wl in enumerate(doms):
+            qos[i] = orcs[i].step(qos[i], wl.dt, 10)
+            qg = states[i].cpu().numpy()
+            e = np.array([np.linalg.norm(qg[f] - qos[i][f]) / np.linalg.norm(qos[i][f]) for f in range(5)])
+            print(f"{wl.name} {'mixed' if mixed else 'fp64'} after {10 * (block + 1)} graph steps: {e}")
+            worst[i] = np.maximum(worst[i], e)
+    ens.close()
+    for c in ctxs:
+        c.close()
+    assert np.all(worst < bar), worst

@@ -160,7 +160,12 @@ def test_tall_column_solve_and_step_parity(torch_cuda, numa_mod, oracle_mod, N, 
     assert np.all(e < STEP_TOL), e
 
 
-def _run_steps(torch, numa, O, wl, q0, nsteps, tol=STEP_TOL):
+def _run_steps(torch, numa, O, wl, q0, nsteps, tol=STEP_TOL, velocity_vector=False):
+    """GPU and oracle trajectories from q0, compared after every step.
+    velocity_vector: the errors of u, v and w are taken relative to the L2
+    norm of the whole velocity field (for states that start at rest with a
+    zero horizontal pressure gradient, whose u and v stay far smaller than
+    w for the first steps)."""
     g = wl.grid
     o = _oracle(O, g, wl.background)
     o.factor_dt(wl.dt)
@@ -173,7 +178,11 @@ def _run_steps(torch, numa, O, wl, q0, nsteps, tol=STEP_TOL):
         qo = o.step(qo, wl.dt, 1)
         ctx.step(qd, 1)
         qg = _host(qd)
-        table.append(_rel(qg, qo))
+        e = _rel(qg, qo)
+        if velocity_vector:
+            vn = np.linalg.norm(qo[1:4])
+            e[1:4] = [np.linalg.norm(qg[f] - qo[f]) / vn for f in (1, 2, 3)]
+        table.append(e)
     ctx.check()
     table = np.array(table)
     print(f"{wl.name}: per-step relative L2 (rho', u, v, w, theta'):")
@@ -203,13 +212,21 @@ def test_step_parity_random(torch_cuda, numa_mod, oracle_mod, N, nex, ney, nez, 
 
 
 @pytest.mark.timeout(900)
-def test_step_parity_box_large_full_size(torch_cuda, numa_mod, oracle_mod):
+@pytest.mark.parametrize("reading,nsteps", [("R1", 100), ("R2", 10)])
+def test_step_parity_box_large_full_size(torch_cuda, numa_mod, oracle_mod, reading, nsteps):
     """The benchmarked workload at full size (64x64x10 elements, N = 4, 2.7M
-    unique nodes), with the launch configuration the benchmark uses."""
-    wl = W.box_large("R1")
+    unique nodes), with the launch configuration the benchmark uses: the
+    GPU trajectory against the oracle's after every step, for all 100 steps
+    of the workload under R1 and 10 steps under R2.  The initial state has
+    P' = 0, so the horizontal pressure gradient starts as rounding noise;
+    under R2 (dt = 0.062 s) u and v are still 1e-4 of w after ten steps and
+    their own relative L2 measures that noise (7.6e-10 after the first
+    step, falling as they grow), so there the velocity errors are taken
+    relative to the whole velocity field."""
+    wl = W.box_large(reading)
     q0 = W.make_initial_state(wl)
-    worst = _run_steps(torch_cuda, numa_mod, oracle_mod, wl, q0, 2)
-    print(f"box_large R1 full size: worst per-variable rel L2 over 2 steps {worst}")
+    worst = _run_steps(torch_cuda, numa_mod, oracle_mod, wl, q0, nsteps, velocity_vector=reading == "R2")
+    print(f"box_large {reading} full size: worst per-variable rel L2 over {nsteps} steps {worst}")
 
 
 # Both column solvers on short columns, and the blocked solve at its limits:
