@@ -124,14 +124,16 @@ int numa_factor_columns(numa_ctx *c, double dt);
  * backward band substitutions of Alg. 9 with the same stored factors; the
  * results agree to rounding).  NUMA_SOLVER_BAND: one lane per column, each
  * lane walking all levels of its column.  NUMA_SOLVER_BLOCKED: four
- * wavefronts per 64 columns (eight above 64 - 2N levels), each holding a
- * block of levels in registers for the stage right-hand side and the
- * extraction, and one wavefront running the substitutions from LDS;
- * available for columns of at most 128 levels.  NUMA_SOLVER_AUTO (the
- * default): blocked where available.
+ * wavefronts per 64 columns (eight above 64 - 2N levels, sixteen above 128
+ * levels), each holding a block of levels in registers for the stage
+ * right-hand side and the extraction, and one wavefront running the
+ * substitutions from LDS; available for columns of at most 128 levels, and
+ * of at most 224 levels where (nz + 2N) * 64 + nz * (4N + 1) doubles of LDS
+ * fit one CU's 160 KB.  NUMA_SOLVER_AUTO (the default): blocked where
+ * available.
  * Takes effect at the next numa_factor_columns; until then the context
  * counts as not factored.  Errors: NUMA_E_ARG (unknown kind),
- * NUMA_E_UNSUPPORTED (blocked for a taller column).
+ * NUMA_E_UNSUPPORTED (blocked for a column it does not support).
  */
 #define NUMA_SOLVER_AUTO 0
 #define NUMA_SOLVER_BAND 1

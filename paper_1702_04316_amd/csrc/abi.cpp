@@ -246,7 +246,7 @@ int numa_set_column_solver(numa_ctx *c, int32_t kind)
     if (kind != NUMA_SOLVER_AUTO && kind != NUMA_SOLVER_BAND && kind != NUMA_SOLVER_BLOCKED)
         return fail(c, NUMA_E_ARG, "numa_set_column_solver: unknown kind");
     if (kind == NUMA_SOLVER_BLOCKED && !numa::blocked_solve_ok(c->N, c->nz))
-        return fail(c, NUMA_E_UNSUPPORTED, "numa_set_column_solver: the blocked solve needs nz <= 128");
+        return fail(c, NUMA_E_UNSUPPORTED, "numa_set_column_solver: the blocked solve needs nz <= 128, or nz <= 224 where its LDS fits one CU");
     c->column_solver = kind;
     c->factored = 0;
     return NUMA_OK;

@@ -891,10 +891,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 }
 
 // ---------------------------------------------------------------------------
-// Level-blocked column solve (columns of at most 128 levels).  A workgroup
+// Level-blocked column solve (columns of at most 224 levels).  A workgroup
 // of W wavefronts owns 64 columns (one per lane): W = 4 for columns of at
-// most 64 - 2N levels, else 8.  Wavefront g owns the level block
-// [g KL, (g+1) KL), KL = ceil(nz/W) <= kBlockedKL, and
+// most 64 - 2N levels, 8 up to 128 levels, 16 (the largest workgroup) up to
+// 224 levels where the LDS below fits one CU.  Wavefront g owns the level
+// block [g KL, (g+1) KL), KL = ceil(nz/W) <= blocked_kl(W), and
 // keeps its levels' values in registers.  One LDS array V, [N pad][M
 // levels][N pad] x 64 lanes, exchanges the one field a phase needs from
 // other levels, and the shared LU band sits in LDS beside it:
@@ -911,16 +912,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 // columns.  The pads hold zeros and meet only zero band coefficients.
 // ---------------------------------------------------------------------------
 constexpr int kBlockedKL = 16;
+// levels per wavefront: 16 with 4 or 8 wavefronts; 14 with 16 wavefronts,
+// whose four wavefronts per SIMD leave 128 registers per lane
+constexpr int blocked_kl(int W) { return W == 16 ? 14 : kBlockedKL; }
+constexpr int kBlockedMaxLevels = 16 * 14;
 
-constexpr int blocked_chunk(int per_level) { return per_level >= 6 ? 4 : 8; }
+// levels whose global loads are issued together
+constexpr int blocked_chunk(int per_level, int W) { return W == 16 ? (per_level >= 6 ? 2 : 4) : (per_level >= 6 ? 4 : 8); }
 
 template <int N, class SH, bool NT, int W>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 8 ? 2 : (N <= 6 ? 4 : 3))))
+__global__ __launch_bounds__(64 * W)
+__attribute__((amdgpu_waves_per_eu(W == 16 ? 4 : (W == 8 ? 2 : (N <= 6 ? 4 : 3)))))
 void k_colsolve_blocked(SolveParams p)
 {
     extern __shared__ double smem[];
-    constexpr int NS = 2 * N + 1, KX = kBlockedKL, NE = SolveGeom<N, SH>::NE;
-    constexpr int CF = blocked_chunk(NE), CX = blocked_chunk(1 + SH::NBW + SH::NBR);
+    constexpr int NS = 2 * N + 1, KX = blocked_kl(W), NE = SolveGeom<N, SH>::NE;
+    constexpr int CF = blocked_chunk(NE, W), CX = blocked_chunk(1 + SH::NBW + SH::NBR, W);
     const int lane = threadIdx.x & 63;
     const int g = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     const long col = (long)blockIdx.x * 64 + lane;
@@ -1328,15 +1335,15 @@ hipError_t rhs_launch(numa_ctx *c, RhsParams p)
     return hipGetLastError();
 }
 
-// The eight-wavefront blocked solve of columns above 64 - 2N levels: its
-// LDS, (nz + 2N) x 64 doubles plus the band, can exceed the default 64 KB
-// (at most 108 KB at 128 levels)
-template <int N, class SH>
-hipError_t blocked8_prepare(size_t lds)
+// The eight- and sixteen-wavefront blocked solves of columns above 64 - 2N
+// levels: their LDS, (nz + 2N) x 64 doubles plus the band, can exceed the
+// default 64 KB (at most 108 KB at 128 levels, 160 KB above)
+template <int N, class SH, int W>
+hipError_t blocked_prepare(size_t lds)
 {
     static size_t attr_set = 65536;
     if (lds > attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_colsolve_blocked<N, SH, false, 8>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_colsolve_blocked<N, SH, false, W>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
         if (e != hipSuccess) return e;
         attr_set = lds;
@@ -1361,8 +1368,12 @@ hipError_t solve_launch(numa_ctx *c, SolveParams p)
     if (blocked_solve_used(c)) {
         const size_t lds = blocked_lds_bytes(N, M);
         const dim3 grid(unsigned((c->ncol + 63) / 64));
-        if (M + 2 * N > 64) {
-            hipError_t e = blocked8_prepare<N, SH>(lds);
+        if (M > 8 * kBlockedKL) {
+            hipError_t e = blocked_prepare<N, SH, 16>(lds);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((k_colsolve_blocked<N, SH, false, 16>), grid, dim3(1024), lds, c->stream, p);
+        } else if (M + 2 * N > 64) {
+            hipError_t e = blocked_prepare<N, SH, 8>(lds);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL((k_colsolve_blocked<N, SH, false, 8>), grid, dim3(512), lds, c->stream, p);
         } else if (nontemporal_stores(c)) {
@@ -1396,9 +1407,15 @@ hipError_t factor_launch(numa_ctx *c, double lambda)
 
 }  // namespace
 
-// the blocked solve holds at most 16 levels per wavefront in registers, 8
-// wavefronts per workgroup: up to 128 levels (LDS at most 108 KB)
-bool blocked_solve_ok(int N, int64_t nz) { return N >= 1 && nz >= 2 && nz <= 8 * kBlockedKL; }
+// the blocked solve holds at most 16 levels per wavefront in registers with
+// up to 8 wavefronts (128 levels, LDS at most 108 KB), 14 with 16 (224
+// levels, where its LDS fits one CU)
+bool blocked_solve_ok(int N, int64_t nz)
+{
+    if (N < 1 || nz < 2) return false;
+    if (nz <= 8 * kBlockedKL) return true;
+    return nz <= kBlockedMaxLevels && blocked_lds_bytes(N, int(nz)) <= kLdsPerCU;
+}
 
 bool blocked_solve_used(const numa_ctx *c)
 {
@@ -1816,9 +1833,12 @@ hipError_t prepare_step(numa_ctx *c, bool mixed)
         // the column solves of both forms are the FP64 ones
         if (e == hipSuccess) e = solve_prepare<NN, ShapeStage2>(nz);
         if (e == hipSuccess) e = solve_prepare<NN, ShapeStage3>(nz);
-        if (blocked_solve_used(c) && nz + 2 * NN > 64) {
-            if (e == hipSuccess) e = blocked8_prepare<NN, ShapeStage2>(blocked_lds_bytes(NN, nz));
-            if (e == hipSuccess) e = blocked8_prepare<NN, ShapeStage3>(blocked_lds_bytes(NN, nz));
+        if (blocked_solve_used(c) && nz > 8 * kBlockedKL) {
+            if (e == hipSuccess) e = blocked_prepare<NN, ShapeStage2, 16>(blocked_lds_bytes(NN, nz));
+            if (e == hipSuccess) e = blocked_prepare<NN, ShapeStage3, 16>(blocked_lds_bytes(NN, nz));
+        } else if (blocked_solve_used(c) && nz + 2 * NN > 64) {
+            if (e == hipSuccess) e = blocked_prepare<NN, ShapeStage2, 8>(blocked_lds_bytes(NN, nz));
+            if (e == hipSuccess) e = blocked_prepare<NN, ShapeStage3, 8>(blocked_lds_bytes(NN, nz));
         }
         return e;
     });

@@ -128,13 +128,16 @@ def test_solve_parity(torch_cuda, numa_mod, oracle_mod, N, nex, ney, nez, zseed,
     assert np.array_equal(out[1], y[1]) and np.array_equal(out[2], y[2]) and np.array_equal(out[4], y[4])
 
 
-# Tall columns: the column solve's LDS exceeds 64 KB per wavefront, so fewer
-# wavefronts share a CU (161 and 197 levels).
-TALL = [(4, 2, 2, 40, None, 21), (7, 1, 2, 28, 8, 22)]
+# Tall columns (161, 197 and 224 levels): the one-lane-per-column solve's LDS
+# exceeds 64 KB per wavefront, and the blocked solve runs sixteen wavefronts
+# per 64 columns (224 = 16 x 14 levels, its limit).
+TALL = [(4, 2, 2, 40, None, 21), (7, 1, 2, 28, 8, 22), (1, 2, 1, 223, None, 23)]
 
 
 @pytest.mark.parametrize("N,nex,ney,nez,zseed,seed", TALL)
-def test_tall_column_solve_and_step_parity(torch_cuda, numa_mod, oracle_mod, N, nex, ney, nez, zseed, seed):
+@pytest.mark.parametrize("solver", ["band", "blocked"])
+def test_tall_column_solve_and_step_parity(torch_cuda, numa_mod, oracle_mod, N, nex, ney, nez, zseed, seed,
+                                           solver):
     lz = 20000.0
     zf = None if zseed is None else W.random_zface(nez, lz, zseed)
     g = W.Grid(9000.0 * nex, 7000.0 * ney, lz, nex, ney, nez, N, zface=zf)
@@ -142,7 +145,10 @@ def test_tall_column_solve_and_step_parity(torch_cuda, numa_mod, oracle_mod, N, 
     o = _oracle(oracle_mod, g)
     o.factor_dt(dt)
     ctx = numa_mod.Context(g)
+    kind = numa_mod.SOLVER_BAND if solver == "band" else numa_mod.SOLVER_BLOCKED
+    ctx.set_column_solver(kind)
     ctx.factor(dt)
+    assert ctx.info()["column_solver"] == kind
     y = W.make_random_state(g, seed, smooth=False)
     e = _rel(_host(ctx.solve(_dev(torch_cuda, y))), o.solve(y))
     ctx.check()
@@ -156,7 +162,7 @@ def test_tall_column_solve_and_step_parity(torch_cuda, numa_mod, oracle_mod, N, 
     ctx.step(qd, 2)
     ctx.check()
     e = _rel(_host(qd), o.step(q, dtx, 2))
-    print(f"tall N={N} nz={g.nz}: step rel L2 {e}")
+    print(f"tall {solver} N={N} nz={g.nz}: step rel L2 {e}")
     assert np.all(e < STEP_TOL), e
 
 
@@ -294,8 +300,8 @@ def test_column_solver_selection(torch_cuda, numa_mod):
     ctx.check()
     assert float(q.abs().max()) == 0.0
     ctx.close()
-    # 33 elements of order 4 give 133 levels: above 128, blocked is refused
-    t = numa.Context(W.Grid(9000.0, 9000.0, 20000.0, 1, 1, 33, 4))
+    # 60 elements of order 4 give 241 levels: above 224, blocked is refused
+    t = numa.Context(W.Grid(9000.0, 9000.0, 20000.0, 1, 1, 60, 4))
     with pytest.raises(numa.NumaError) as ei:
         t.set_column_solver(numa.SOLVER_BLOCKED)
     assert ei.value.code == numa.NUMA_E_UNSUPPORTED
