@@ -12,8 +12,12 @@
  *  - continuity in divergence form, d rho'/dt = -div((rho0 + rho') u);
  *  - DSS = mass-weighted average of element-local strong-form values;
  *  - x, y periodic; w = 0 imposed strongly at the bottom and top nodes;
- *  - isentropic background: theta0 constant, pi0 = 1 - g z/(cp theta0),
- *    rho0 = p00 pi0^(cv/R)/(R theta0), P0 = EOS(rho0, theta0);
+ *  - background in hydrostatic balance: isentropic (theta0 constant,
+ *    pi0 = 1 - g z/(cp theta0)) or, with a Brunt-Vaisala frequency Nb > 0,
+ *    stratified: theta0(z) = theta0 exp(S z), S = Nb^2/g, and the Exner
+ *    function integrated in closed form, pi0 = 1 + g (exp(-S z) - 1)/(cp
+ *    theta0 S); in both rho0 = p00 pi0^(cv/R)/(R theta0(z)), P0 =
+ *    EOS(rho0, theta0(z));
  *  - ARK2 tableau with the signs restored by the order conditions.
  */
 #include "numa_oracle.h"
@@ -38,12 +42,16 @@ struct orc_ctx {
     double *mloc;  /* element-local mass weight m_e */
     double *mass;  /* assembled mass M_I */
     double theta0, p00, cp, R, cv, gamma, g;
+    double nbv;                       /* Brunt-Vaisala frequency (0: isentropic) */
     double *zk, *rho0, *P0, *G0, *H0; /* per level */
-    /* column factors of I - lambda L_V */
+    double *th0, *th0z;               /* theta0(z) and d theta0/dz per level */
+    /* column factors of I - lambda L_V; unknowns per level: rho', w, and
+     * theta' when the background is stratified (nvar = 3) */
+    int nvar;
     int factored;
     double lambda;
-    double *A; /* per column (2M)^2, LU in place */
-    int *piv;  /* per column 2M */
+    double *A; /* per column (nvar M)^2, LU in place */
+    int *piv;  /* per column nvar M */
 };
 
 /* ------------------------------------------------------------------------ */
@@ -116,10 +124,11 @@ static long lidx(const orc_ctx *c, int a, int b, int cc) { return a + c->nq * (b
 
 orc_ctx *orc_setup(double lx, double ly, double lz, int nex, int ney, int nez,
                    const double *zface, int N, double theta0, double p00,
-                   double cp, double rgas, double grav)
+                   double cp, double rgas, double grav, double nbv)
 {
     if (N < 1 || N > 15 || nex < 1 || ney < 1 || nez < 1) return NULL;
     if (!(lx > 0) || !(ly > 0) || !(lz > 0)) return NULL;
+    if (!(nbv >= 0.0) || (nbv > 0.0 && !(grav > 0.0))) return NULL;
     if (zface) {
         if (zface[0] != 0.0 || zface[nez] != lz) return NULL;
         for (int e = 0; e < nez; ++e) if (!(zface[e + 1] > zface[e])) return NULL;
@@ -135,6 +144,8 @@ orc_ctx *orc_setup(double lx, double ly, double lz, int nex, int ney, int nez,
     c->hx = lx / nex; c->hy = ly / ney;
     c->theta0 = theta0; c->p00 = p00; c->cp = cp; c->R = rgas;
     c->cv = cp - rgas; c->gamma = cp / c->cv; c->g = grav;
+    c->nbv = nbv;
+    c->nvar = nbv > 0.0 ? 3 : 2;
 
     c->zf = (double *)malloc(sizeof(double) * (nez + 1));
     c->hz = (double *)malloc(sizeof(double) * nez);
@@ -175,18 +186,33 @@ orc_ctx *orc_setup(double lx, double ly, double lz, int nex, int ney, int nez,
     c->P0 = (double *)malloc(sizeof(double) * c->nz);
     c->G0 = (double *)malloc(sizeof(double) * c->nz);
     c->H0 = (double *)malloc(sizeof(double) * c->nz);
+    c->th0 = (double *)malloc(sizeof(double) * c->nz);
+    c->th0z = (double *)malloc(sizeof(double) * c->nz);
     for (int ez = 0; ez < nez; ++ez)
         for (int cc = 0; cc <= N; ++cc)
             c->zk[ez * N + cc] = c->zf[ez] + (c->xi[cc] + 1.0) * c->hz[ez] / 2.0;
     for (int k = 0; k < c->nz; ++k) {
-        /* hydrostatic, neutral background with constant theta0 */
-        double pi0 = 1.0 - grav * c->zk[k] / (cp * theta0);
-        double rho0 = p00 * pow(pi0, c->cv / rgas) / (rgas * theta0);
-        double P0 = p00 * pow(rho0 * rgas * theta0 / p00, c->gamma); /* EOS, Eq. (10) */
+        /* hydrostatic background: d pi0/dz = -g/(cp theta0(z)), pi0(0) = 1 */
+        double z = c->zk[k], th, thz, pi0;
+        if (nbv > 0.0) { /* constant Brunt-Vaisala frequency: (g/theta0) d theta0/dz = Nb^2 */
+            double S = nbv * nbv / grav;
+            th = theta0 * exp(S * z);
+            thz = S * th;
+            pi0 = 1.0 + grav * (exp(-S * z) - 1.0) / (cp * theta0 * S);
+        } else { /* neutral: theta0 constant */
+            th = theta0;
+            thz = 0.0;
+            pi0 = 1.0 - grav * z / (cp * theta0);
+        }
+        if (!(pi0 > 0.0)) { orc_free(c); return NULL; }
+        double rho0 = p00 * pow(pi0, c->cv / rgas) / (rgas * th);
+        double P0 = p00 * pow(rho0 * rgas * th / p00, c->gamma); /* EOS, Eq. (10) */
+        c->th0[k] = th;
+        c->th0z[k] = thz;
         c->rho0[k] = rho0;
         c->P0[k] = P0;
         c->G0[k] = c->gamma * P0 / rho0;   /* Eq. (13) */
-        c->H0[k] = c->gamma * P0 / theta0;
+        c->H0[k] = c->gamma * P0 / th;
     }
     return c;
 }
@@ -197,6 +223,7 @@ void orc_free(orc_ctx *c)
     free(c->zf); free(c->hz); free(c->xi); free(c->wq); free(c->D);
     free(c->gmap); free(c->mloc); free(c->mass);
     free(c->zk); free(c->rho0); free(c->P0); free(c->G0); free(c->H0);
+    free(c->th0); free(c->th0z);
     free(c->A); free(c->piv);
     free(c);
 }
@@ -243,6 +270,12 @@ void orc_background(const orc_ctx *c, double *rho0, double *P0, double *G0, doub
         if (G0) G0[k] = c->G0[k];
         if (H0) H0[k] = c->H0[k];
     }
+}
+
+void orc_background_theta(const orc_ctx *c, double *th0, double *th0z)
+{
+    memcpy(th0, c->th0, sizeof(double) * c->nz);
+    memcpy(th0z, c->th0z, sizeof(double) * c->nz);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -294,7 +327,7 @@ static void dss(const orc_ctx *c, const double *r, double *R)
  * Pa, the whole of P' in a balanced state).  Accuracy: a few ulp of P'. */
 static double pressure_perturbation(const orc_ctx *c, int k, double rp, double th)
 {
-    double r0 = c->rho0[k], t0 = c->theta0;
+    double r0 = c->rho0[k], t0 = c->th0[k];
     /* rho0 theta', theta0 rho' and rho' theta' nearly cancel in a
      * hydrostatically balanced state; the rounding error of each product is
      * recovered exactly with fma, so that their small sum keeps its relative
@@ -331,6 +364,7 @@ int orc_rhs(orc_ctx *c, const double *q, double *R)
             double *rp = buf, *u = buf + nq3, *v = buf + 2 * nq3, *w = buf + 3 * nq3;
             double *th = buf + 4 * nq3, *rho = buf + 5 * nq3, *Pp = buf + 6 * nq3;
             double *Fx = buf + 7 * nq3, *Fy = buf + 8 * nq3, *Fz = buf + 9 * nq3;
+            double *tz0 = buf + 10 * nq3; /* d theta0/dz at the node */
 #pragma omp for schedule(static)
             for (long e = 0; e < c->nelem; ++e) {
                 int ez = (int)(e / ((long)c->nex * c->ney));
@@ -343,6 +377,7 @@ int orc_rhs(orc_ctx *c, const double *q, double *R)
                     rho[l] = c->rho0[k] + rp[l];
                     Pp[l] = pressure_perturbation(c, k, rp[l], th[l]);
                     Fx[l] = rho[l] * u[l]; Fy[l] = rho[l] * v[l]; Fz[l] = rho[l] * w[l];
+                    tz0[l] = c->th0z[k];
                 }
                 for (int cc = 0; cc < c->nq; ++cc)
                     for (int b = 0; b < c->nq; ++b)
@@ -362,7 +397,8 @@ int orc_rhs(orc_ctx *c, const double *q, double *R)
                             r[1 * nl + o] = -(U * ux + V * uy + W * uz + px / rh);
                             r[2 * nl + o] = -(U * vx + V * vy + W * vz + py / rh);
                             r[3 * nl + o] = -(U * wx + V * wy + W * wz + pz / rh + c->g * rp[l] / rh);
-                            r[4 * nl + o] = -(U * tx + V * ty + W * tz); /* u . grad theta0 = 0 */
+                            /* u . grad theta0 = w d theta0/dz (theta0 depends on z only) */
+                            r[4 * nl + o] = -(U * tx + V * ty + W * tz + W * tz0[l]);
                         }
             }
             free(buf);
@@ -388,11 +424,11 @@ static int linop(orc_ctx *c, const double *q, double *L, int full)
     int ok = 1;
 #pragma omp parallel
     {
-        double *buf = (double *)malloc(sizeof(double) * 6 * nq3);
+        double *buf = (double *)malloc(sizeof(double) * 7 * nq3);
         if (!buf) ok = 0;
         if (buf) {
             double *rp = buf, *mu = buf + nq3, *mv = buf + 2 * nq3, *mw = buf + 3 * nq3;
-            double *pl = buf + 4 * nq3, *r0 = buf + 5 * nq3;
+            double *pl = buf + 4 * nq3, *r0 = buf + 5 * nq3, *wt = buf + 6 * nq3;
 #pragma omp for schedule(static)
             for (long e = 0; e < c->nelem; ++e) {
                 int ez = (int)(e / ((long)c->nex * c->ney));
@@ -406,6 +442,7 @@ static int linop(orc_ctx *c, const double *q, double *L, int full)
                     mv[l] = c->rho0[k] * q[2 * np + I];
                     mw[l] = c->rho0[k] * q[3 * np + I];
                     pl[l] = c->G0[k] * q[0 * np + I] + c->H0[k] * q[4 * np + I];
+                    wt[l] = q[3 * np + I] * c->th0z[k];
                 }
                 for (int cc = 0; cc < c->nq; ++cc)
                     for (int b = 0; b < c->nq; ++b)
@@ -417,7 +454,7 @@ static int linop(orc_ctx *c, const double *q, double *L, int full)
                             r[1 * nl + o] = full ? -(sx * dref(c, pl, a, b, cc, 0) / r0[l]) : 0.0;
                             r[2 * nl + o] = full ? -(sy * dref(c, pl, a, b, cc, 1) / r0[l]) : 0.0;
                             r[3 * nl + o] = -(sz * dref(c, pl, a, b, cc, 2) / r0[l] + c->g * rp[l] / r0[l]);
-                            r[4 * nl + o] = 0.0; /* -u . grad theta0 = 0 for constant theta0 */
+                            r[4 * nl + o] = -wt[l]; /* -u . grad theta0 = -w d theta0/dz */
                         }
             }
             free(buf);
@@ -434,20 +471,24 @@ int orc_lfull(orc_ctx *c, const double *q, double *L) { return linop(c, q, L, 1)
 
 /* ------------------------------------------------------------------------ */
 /* Column matrices of I - lambda L_V (Sec. 5.4): built by probing (Alg. 7),  */
-/* unknowns (rho'_k, w_k) per column, solved by Gaussian elimination with    */
-/* partial pivoting.  u, v, theta' pass through unchanged because L_V has no */
-/* rows for them.                                                           */
+/* unknowns (rho'_k, w_k) per column, and theta'_k when the background is    */
+/* stratified, solved by Gaussian elimination with partial pivoting.  u, v  */
+/* pass through unchanged because L_V has no rows for them; so does theta'  */
+/* over a neutral background, where its row -w d theta0/dz vanishes.       */
 /* ------------------------------------------------------------------------ */
+
+/* field of column unknown block gv: rho', w, theta' */
+static int unknown_field(int gv) { return gv == 0 ? 0 : (gv == 1 ? 3 : 4); }
 
 static int build_columns(orc_ctx *c, double lambda, double *A)
 {
-    int M = c->nz, n2 = 2 * M;
+    int M = c->nz, nv = c->nvar, n2 = nv * M;
     long plane = (long)c->nx * c->ny, np = c->np;
     double *P = (double *)calloc(5 * np, sizeof(double));
     double *L = (double *)malloc(sizeof(double) * 5 * np);
     if (!P || !L) { free(P); free(L); return -5; }
-    for (int gvar = 0; gvar < 2; ++gvar) {
-        int f = gvar == 0 ? 0 : 3; /* rho' or w */
+    for (int gvar = 0; gvar < nv; ++gvar) {
+        int f = unknown_field(gvar);
         for (int m = 0; m < M; ++m) {
             /* unit value of dof (gvar, m) in every column at once */
             for (long I = 0; I < plane; ++I) P[f * np + (long)m * plane + I] = 1.0;
@@ -457,10 +498,12 @@ static int build_columns(orc_ctx *c, double lambda, double *A)
             int col = gvar * M + m;
             for (long I = 0; I < plane; ++I) {
                 double *Ac = A + I * (long)n2 * n2;
-                for (int k = 0; k < M; ++k) {
-                    Ac[(0 * M + k) * n2 + col] = (col == 0 * M + k ? 1.0 : 0.0) - lambda * L[0 * np + (long)k * plane + I];
-                    Ac[(1 * M + k) * n2 + col] = (col == 1 * M + k ? 1.0 : 0.0) - lambda * L[3 * np + (long)k * plane + I];
-                }
+                for (int rv = 0; rv < nv; ++rv)
+                    for (int k = 0; k < M; ++k) {
+                        int row = rv * M + k;
+                        Ac[(long)row * n2 + col] =
+                            (col == row ? 1.0 : 0.0) - lambda * L[unknown_field(rv) * np + (long)k * plane + I];
+                    }
             }
         }
     }
@@ -482,7 +525,7 @@ static int build_columns(orc_ctx *c, double lambda, double *A)
 int orc_column_matrix(orc_ctx *c, double lambda, int i, int j, double *Aout)
 {
     if (!c || !Aout || i < 0 || j < 0 || i >= c->nx || j >= c->ny) return -1;
-    int n2 = 2 * c->nz;
+    int n2 = c->nvar * c->nz;
     long plane = (long)c->nx * c->ny;
     double *A = (double *)malloc(sizeof(double) * plane * n2 * n2);
     if (!A) return -5;
@@ -528,7 +571,7 @@ static void lu_solve(const double *A, const int *piv, int n, double *x)
 int orc_factor(orc_ctx *c, double lambda)
 {
     if (!c) return -1;
-    int n2 = 2 * c->nz;
+    int n2 = c->nvar * c->nz;
     long plane = (long)c->nx * c->ny;
     free(c->A); free(c->piv);
     c->factored = 0;
@@ -551,35 +594,35 @@ int orc_solve(orc_ctx *c, const double *y, double *x)
 {
     if (!c || !y || !x) return -1;
     if (!c->factored) return -2;
-    int M = c->nz, n2 = 2 * M;
+    int M = c->nz, nv = c->nvar, n2 = nv * M;
     long plane = (long)c->nx * c->ny, np = c->np;
     for (long I = 0; I < plane; ++I)
         if (y[3 * np + I] != 0.0 || y[3 * np + (long)(M - 1) * plane + I] != 0.0) return -3;
-    /* theta' is known (x_theta = y_theta): move its L_V contribution to the
-     * right-hand side, then solve the (rho', w) system column by column. */
+    /* Over a neutral background theta' is known (x_theta = y_theta): its L_V
+     * contribution moves to the right-hand side and the (rho', w) system is
+     * solved column by column; over a stratified one theta' is an unknown. */
     double *t = (double *)calloc(5 * np, sizeof(double));
-    double *Lt = (double *)malloc(sizeof(double) * 5 * np);
+    double *Lt = (double *)calloc(5 * np, sizeof(double));
     if (!t || !Lt) { free(t); free(Lt); return -5; }
-    memcpy(t + 4 * np, y + 4 * np, sizeof(double) * np);
-    int rc = orc_lv(c, t, Lt);
-    if (rc) { free(t); free(Lt); return rc; }
+    if (nv == 2) {
+        memcpy(t + 4 * np, y + 4 * np, sizeof(double) * np);
+        int rc = orc_lv(c, t, Lt);
+        if (rc) { free(t); free(Lt); return rc; }
+    }
     double lam = c->lambda;
 #pragma omp parallel
     {
         double *b = (double *)malloc(sizeof(double) * n2);
 #pragma omp for schedule(static)
         for (long I = 0; I < plane; ++I) {
-            for (int k = 0; k < M; ++k) {
-                long o = (long)k * plane + I;
-                b[k] = y[0 * np + o] + lam * Lt[0 * np + o];
-                b[M + k] = y[3 * np + o] + lam * Lt[3 * np + o];
-            }
+            for (int gv = 0; gv < nv; ++gv)
+                for (int k = 0; k < M; ++k) {
+                    long o = unknown_field(gv) * np + (long)k * plane + I;
+                    b[gv * M + k] = y[o] + lam * Lt[o];
+                }
             lu_solve(c->A + I * (long)n2 * n2, c->piv + I * n2, n2, b);
-            for (int k = 0; k < M; ++k) {
-                long o = (long)k * plane + I;
-                t[0 * np + o] = b[k];
-                t[3 * np + o] = b[M + k];
-            }
+            for (int gv = 0; gv < nv; ++gv)
+                for (int k = 0; k < M; ++k) t[unknown_field(gv) * np + (long)k * plane + I] = b[gv * M + k];
         }
         free(b);
     }
@@ -588,7 +631,7 @@ int orc_solve(orc_ctx *c, const double *y, double *x)
         x[1 * np + I] = y[1 * np + I];
         x[2 * np + I] = y[2 * np + I];
         x[3 * np + I] = t[3 * np + I];
-        x[4 * np + I] = y[4 * np + I];
+        x[4 * np + I] = nv == 3 ? t[4 * np + I] : y[4 * np + I];
     }
     free(t); free(Lt);
     return 0;
@@ -870,6 +913,7 @@ static int schur_rhs(orc_ctx *c, const schur_arg *a, const double *y, double *Ua
 int orc_schur_apply(orc_ctx *c, const double *P, double *out, double lambda)
 {
     if (!c || !P || !out) return -1;
+    if (c->nbv > 0.0) return -7;
     schur_arg a = {lambda, (double *)malloc(sizeof(double) * 5 * c->np), (double *)malloc(sizeof(double) * 5 * c->np)};
     int rc = (a.s && a.l) ? op_schur(c, &a, P, out) : -5;
     free(a.s); free(a.l);
@@ -879,6 +923,7 @@ int orc_schur_apply(orc_ctx *c, const double *P, double *out, double lambda)
 int orc_schur_rhs(orc_ctx *c, const double *y, double *b, double lambda)
 {
     if (!c || !y || !b) return -1;
+    if (c->nbv > 0.0) return -7;
     long np = c->np;
     schur_arg a = {lambda, (double *)malloc(sizeof(double) * 5 * np), (double *)malloc(sizeof(double) * 5 * np)};
     double *Ua = (double *)malloc(sizeof(double) * 3 * np);
@@ -935,6 +980,7 @@ static int op_pbno(orc_ctx *c, const void *arg, const double *r, double *z)
 int orc_pbno_apply(orc_ctx *c, const double *r, double *z, double lambda, int order, double lmin, double lmax)
 {
     if (!c || !r || !z || order < 0 || !(lmax > lmin) || !(lmin > 0.0)) return -1;
+    if (c->nbv > 0.0) return -7;
     schur_arg s = {lambda, (double *)malloc(sizeof(double) * 5 * c->np), (double *)malloc(sizeof(double) * 5 * c->np)};
     pbno_arg a = {&s, order, lmin, lmax};
     int rc = (s.s && s.l) ? op_pbno(c, &a, r, z) : -5;
@@ -951,6 +997,7 @@ int orc_pbno_apply(orc_ctx *c, const double *r, double *z, double lambda, int or
 int orc_schur_bounds(orc_ctx *c, double lambda, int k, double *out)
 {
     if (!c || !out || k < 1) return -1;
+    if (c->nbv > 0.0) return -7;
     long n = c->np;
     double *v = (double *)malloc(sizeof(double) * n), *w = (double *)malloc(sizeof(double) * n);
     schur_arg a = {lambda, (double *)malloc(sizeof(double) * 5 * n), (double *)malloc(sizeof(double) * 5 * n)};
@@ -983,6 +1030,7 @@ int orc_solve3d(orc_ctx *c, const double *y, double *x, double lambda, double to
                 int order, const double *bounds, int *iters)
 {
     if (!c || !y || !x || restart < 1 || maxit < 1 || !(tol > 0.0)) return -1;
+    if (c->nbv > 0.0) return -7;
     if (order >= 0 && (!bounds || !(bounds[1] > bounds[0]) || !(bounds[0] > 0.0))) return -1;
     long np = c->np;
     schur_arg a = {lambda, (double *)malloc(sizeof(double) * 5 * np), (double *)malloc(sizeof(double) * 5 * np)};
@@ -1149,6 +1197,7 @@ int orc_learned_apply(orc_ctx *c, const double *r, double *z, double lambda, int
                       const orc_mlp *mlp)
 {
     if (!c || !r || !z || (order >= 0 && !bounds)) return -1;
+    if (c->nbv > 0.0) return -7;
     schur_arg s = {lambda, (double *)malloc(sizeof(double) * 5 * c->np), (double *)malloc(sizeof(double) * 5 * c->np)};
     pbno_arg pa = {&s, order, bounds ? bounds[0] : 0.0, bounds ? bounds[1] : 0.0};
     learned_arg la = {&pa, mlp, 0};
@@ -1165,6 +1214,7 @@ int orc_solve3d_learned(orc_ctx *c, const double *y, double *x, double lambda, d
                         int order, const double *bounds, const orc_mlp *mlp, int *iters, int *net_cycles)
 {
     if (!c || !y || !x || restart < 1 || maxit < 1 || !(tol > 0.0)) return -1;
+    if (c->nbv > 0.0) return -7;
     if (order >= 0 && (!bounds || !(bounds[1] > bounds[0]) || !(bounds[0] > 0.0))) return -1;
     long np = c->np;
     schur_arg a = {lambda, (double *)malloc(sizeof(double) * 5 * np), (double *)malloc(sizeof(double) * 5 * np)};
@@ -1201,6 +1251,7 @@ int orc_step3d(orc_ctx *c, double *q, double dt, int nsteps, int linear, double 
                const double *bounds, int *iters)
 {
     if (!c || !q || nsteps < 0 || !(dt > 0.0)) return -1;
+    if (c->nbv > 0.0) return -7;
     double a[9], at[9], b[3];
     orc_ark2_tableau(a, at, b);
     double lam = at[1 * 3 + 1] * dt;

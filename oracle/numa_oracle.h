@@ -22,7 +22,9 @@
  *
  * Return codes: 0 ok, -1 bad argument, -2 not factored / lambda mismatch,
  * -3 precondition violated (w != 0 on a wall), -4 singular column matrix,
- * -5 out of memory, -6 iterative solve did not converge.
+ * -5 out of memory, -6 iterative solve did not converge, -7 not available
+ * over a stratified background (the 3D-IMEX Schur form assumes theta0
+ * constant).
  */
 #ifndef NUMA_ORACLE_H
 #define NUMA_ORACLE_H
@@ -38,10 +40,13 @@ void orc_lgl(int N, double *xi, double *w);
 /* LGL differentiation matrix D[i*(N+1)+j] = d l_j / d xi at xi_i. */
 void orc_dmat(int N, const double *xi, double *D);
 
-/* zface: NULL (uniform) or nez+1 increasing heights from 0 to lz. */
+/* zface: NULL (uniform) or nez+1 increasing heights from 0 to lz.  nbv: the
+ * background's Brunt-Vaisala frequency [1/s]; 0 gives the isentropic
+ * background (theta0 constant), nbv > 0 theta0(z) = theta0 exp(nbv^2 z / g)
+ * (Sec. 3.1: background in hydrostatic balance). */
 orc_ctx *orc_setup(double lx, double ly, double lz, int nex, int ney, int nez,
                    const double *zface, int N, double theta0, double p00,
-                   double cp, double rgas, double grav);
+                   double cp, double rgas, double grav, double nbv);
 void orc_free(orc_ctx *c);
 void orc_set_threads(int n);
 int orc_get_threads(void);
@@ -54,6 +59,8 @@ void orc_coords(const orc_ctx *c, double *x, double *y, double *z);
 void orc_mass(const orc_ctx *c, double *M);
 /* Background per level k: rho0, P0, G0 = gamma P0/rho0, H0 = gamma P0/theta0. */
 void orc_background(const orc_ctx *c, double *rho0, double *P0, double *G0, double *H0);
+/* theta0(z) and its vertical derivative per level. */
+void orc_background_theta(const orc_ctx *c, double *th0, double *th0z);
 
 /* Perturbation pressure P' = EOS(rho, theta) - P0 at every unique node
  * (evaluated without cancelling the background pressure). */
@@ -68,8 +75,9 @@ int orc_lfull(orc_ctx *c, const double *q, double *L);
 int orc_factor(orc_ctx *c, double lambda);
 /* x = (I - lambda L_V)^{-1} y using the stored factors.  y and x may alias. */
 int orc_solve(orc_ctx *c, const double *y, double *x);
-/* The dense column matrix (2M x 2M, row-major, unknowns (rho'_0..M-1, w_0..M-1))
- * of I - lambda L_V for column (i, j), before factorisation. */
+/* The dense column matrix (nv M x nv M, row-major, unknowns (rho'_0..M-1,
+ * w_0..M-1) and, over a stratified background (nv = 3), theta'_0..M-1) of
+ * I - lambda L_V for column (i, j), before factorisation. */
 int orc_column_matrix(orc_ctx *c, double lambda, int i, int j, double *A);
 /* nsteps ARK2 steps of size dt, in place.  linear != 0 replaces R by the full
  * linear operator L (used by the time-order test).  The factors must have been

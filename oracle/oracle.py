@@ -32,7 +32,7 @@ def _load():
     lib.orc_setup.restype = C.c_void_p
     lib.orc_setup.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
                               C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_double,
-                              C.c_double, C.c_double]
+                              C.c_double, C.c_double, C.c_double]
     lib.orc_free.argtypes = [C.c_void_p]
     lib.orc_set_threads.argtypes = [C.c_int]
     lib.orc_get_threads.restype = C.c_int
@@ -40,6 +40,7 @@ def _load():
     lib.orc_coords.argtypes = [C.c_void_p, _dp, _dp, _dp]
     lib.orc_mass.argtypes = [C.c_void_p, _dp]
     lib.orc_background.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
+    lib.orc_background_theta.argtypes = [C.c_void_p, _dp, _dp]
     for name in ("orc_rhs", "orc_lv", "orc_lfull", "orc_solve"):
         f = getattr(lib, name)
         f.argtypes = [C.c_void_p, _dp, _dp]
@@ -152,11 +153,12 @@ class Oracle:
     """One grid + background; mirrors the GPU library's set-up contract."""
 
     def __init__(self, lx, ly, lz, nex, ney, nez, N, theta0=300.0, p00=1.0e5,
-                 cp=1004.67, rgas=287.17, grav=9.80616, zface=None):
+                 cp=1004.67, rgas=287.17, grav=9.80616, zface=None, nbv=0.0):
         lib = _load()
         self._zf = None if zface is None else np.ascontiguousarray(zface, dtype=np.float64)
         zp = None if self._zf is None else self._zf.ctypes.data_as(C.c_void_p)
-        self.h = lib.orc_setup(lx, ly, lz, nex, ney, nez, zp, N, theta0, p00, cp, rgas, grav)
+        self.h = lib.orc_setup(lx, ly, lz, nex, ney, nez, zp, N, theta0, p00, cp, rgas, grav, nbv)
+        self.nvar = 3 if nbv > 0.0 else 2
         if not self.h:
             raise OracleError("orc_setup rejected its arguments")
         sz = np.zeros(4, dtype=np.int64)
@@ -187,7 +189,9 @@ class Oracle:
     def background(self):
         out = [np.zeros(self.nz) for _ in range(4)]
         _lib.orc_background(self.h, *out)
-        return dict(zip(("rho0", "P0", "G0", "H0"), out))
+        th = [np.zeros(self.nz) for _ in range(2)]
+        _lib.orc_background_theta(self.h, *th)
+        return dict(zip(("rho0", "P0", "G0", "H0", "theta0", "dtheta0dz"), out + th))
 
     def _op(self, name, q):
         q = np.ascontiguousarray(q, dtype=np.float64)
@@ -222,7 +226,7 @@ class Oracle:
         return self._op("orc_solve", y)
 
     def column_matrix(self, lam, i, j):
-        n2 = 2 * self.nz
+        n2 = self.nvar * self.nz
         A = np.zeros(n2 * n2)
         _check(_lib.orc_column_matrix(self.h, float(lam), i, j, A), "orc_column_matrix")
         return A.reshape(n2, n2)

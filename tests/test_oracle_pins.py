@@ -28,12 +28,16 @@ def _golden(name):
     return rows
 
 
-def _oracle(O, grid, bg=None, grav=None):
+def _oracle(O, grid, bg=None, grav=None, nbv=0.0):
     bg = bg or W.Background()
     g = bg.grav if grav is None else grav
     return O.Oracle(grid.lx, grid.ly, grid.lz, grid.nex, grid.ney, grid.nez, grid.N,
                     theta0=bg.theta0, p00=bg.p00, cp=bg.cp, rgas=bg.rgas, grav=g,
-                    zface=grid.zface)
+                    zface=grid.zface, nbv=nbv)
+
+
+# Brunt-Vaisala frequency of the stratified background used by the pins
+NBV = 0.012
 
 
 # ---------------------------------------------------------------------------
@@ -106,6 +110,96 @@ def test_background_pins(oracle_mod):
     # hydrostatic: the continuum d P0/dz = -rho0 g holds (central differences, interior)
     dP = np.gradient(bg["P0"], z)
     assert np.max(np.abs(dP[1:-1] / (-bg["rho0"][1:-1] * grav) - 1.0)) < 1e-4
+
+
+def _element_derivative(z, f, nez, N):
+    """d f/dz at the LGL levels z by differentiating, element by element, the
+    degree-N polynomial through the element's N+1 levels (numpy fit in a
+    centred, scaled variable; independent of the oracle's operators)."""
+    out = np.zeros_like(f)
+    for e in range(nez):
+        sl = slice(e * N, e * N + N + 1)
+        zc, h = 0.5 * (z[sl][0] + z[sl][-1]), 0.5 * (z[sl][-1] - z[sl][0])
+        p = np.polynomial.Polynomial.fit((z[sl] - zc) / h, f[sl], N, domain=[-1, 1], window=[-1, 1])
+        d = p.deriv()((z[sl] - zc) / h) / h
+        out[sl] = d  # shared levels: the upper element's value (both are the continuum's to ~1e-12)
+    return out
+
+
+def test_stratified_background_hydrostatic_with_buoyancy_frequency(oracle_mod):
+    """The stratified background (Sec. 3.1: hydrostatically balanced
+    reference state) against the continuum: d P0/dz = -rho0 g, the buoyancy
+    frequency (g/theta0) d theta0/dz equals the prescribed Nb^2 at every
+    level, theta0 = gamma P0/H0 and G0 = gamma P0/rho0 (Eq. (13)), and the
+    surface values are those of the neutral background."""
+    N, nez, lz = 8, 6, 12000.0
+    g = W.Grid(5000.0, 5000.0, lz, 1, 1, nez, N)
+    o = _oracle(oracle_mod, g, nbv=NBV)
+    bg = o.background()
+    _, _, z = o.coords()
+    grav, cp, R = W.GRAV, W.CP, W.RGAS
+    gamma = cp / (cp - R)
+    dP = _element_derivative(z, bg["P0"], nez, N)
+    assert np.max(np.abs(dP / (-bg["rho0"] * grav) - 1.0)) < 1e-9
+    th = gamma * bg["P0"] / bg["H0"]
+    assert np.max(np.abs(th / bg["theta0"] - 1.0)) < 1e-14
+    dth = _element_derivative(z, th, nez, N)
+    assert np.max(np.abs(grav * dth / th / NBV ** 2 - 1.0)) < 1e-9
+    assert np.max(np.abs(bg["dtheta0dz"] * grav / (bg["theta0"] * NBV ** 2) - 1.0)) < 1e-14
+    assert np.max(np.abs(bg["G0"] / (gamma * bg["P0"] / bg["rho0"]) - 1.0)) < 1e-14
+    assert abs(bg["theta0"][0] - W.THETA0) < 1e-12 and abs(bg["P0"][0] / W.P00 - 1.0) < 1e-14
+    # stable stratification: theta0 grows, and more slowly than the neutral density falls
+    assert np.all(np.diff(bg["theta0"]) > 0)
+    neutral = _oracle(oracle_mod, g).background()
+    assert np.all(bg["rho0"][1:] < neutral["rho0"][1:])
+
+
+def test_stratified_rest_state_stays_at_rest(oracle_mod):
+    """Over the stratified background the rest state (rho' = u = theta' = 0)
+    has a zero right-hand side, exactly, and stays at rest under steps."""
+    zf = W.random_zface(4, 6000.0, 5)
+    g = W.Grid(60000.0, 50000.0, 6000.0, 3, 2, 4, 5, zface=zf)
+    o = _oracle(oracle_mod, g, nbv=NBV)
+    q = np.zeros(g.shape)
+    assert np.all(o.rhs(q) == 0.0)
+    dt = W.dt_for_courant(g, 15.0, "z")
+    o.factor_dt(dt)
+    assert np.all(o.step(q, dt, 3) == 0.0)
+
+
+def test_stratified_linearisation_and_column_solve(oracle_mod):
+    """Over the stratified background: R(eps q) about rest is eps L(q) with L
+    carrying -w d theta0/dz in the theta' row; the column solve satisfies
+    x - lambda L_V(x) = y, now changing theta'; and the probed 3M x 3M
+    column matrix solved by LAPACK gives the same x."""
+    g = W.Grid(6000.0, 5000.0, 3000.0, 2, 2, 2, 4)
+    o = _oracle(oracle_mod, g, nbv=NBV)
+    q = W.make_random_state(g, seed=3)
+    L = o.lfull(q)
+    dR = (o.rhs(0.25 * q) - o.rhs(-0.25 * q)) / 0.5
+    assert np.max(np.abs(dR - L)) < 1e-6 * np.max(np.abs(L))
+    th = o.background()["dtheta0dz"]
+    assert np.max(np.abs(L[4] + q[3] * th[:, None, None])) < 1e-12 * np.max(np.abs(q[3] * th[:, None, None]))
+    lz = 5000.0
+    g = W.Grid(3000.0, 2000.0, lz, 2, 2, 3, 4, zface=W.random_zface(3, lz, 6))
+    o = _oracle(oracle_mod, g, nbv=NBV)
+    dt = W.dt_for_courant(g, 15.0, "z")
+    lam = (1 - 1 / np.sqrt(2)) * dt
+    o.factor(lam)
+    y = W.make_random_state(g, 8, smooth=False)
+    x = o.solve(y)
+    res = x - lam * o.lv(x) - y
+    for f in range(5):
+        assert np.max(np.abs(res[f])) < 1e-11 * max(1.0, np.max(np.abs(y[f]))), f
+    assert np.max(np.abs(x[4] - y[4])) > 1e-3 * np.max(np.abs(y[4]))  # theta' is solved for
+    assert np.array_equal(x[1], y[1]) and np.array_equal(x[2], y[2])
+    A = o.column_matrix(lam, 3, 5)
+    M = g.nz
+    assert A.shape == (3 * M, 3 * M)
+    b = np.concatenate((y[0, :, 5, 3], y[3, :, 5, 3], y[4, :, 5, 3]))
+    sol = scipy.linalg.solve(A, b)
+    for blk, f in enumerate((0, 3, 4)):
+        assert np.max(np.abs(sol[blk * M:(blk + 1) * M] - x[f, :, 5, 3])) < 1e-12 * np.max(np.abs(x[f]))
 
 
 def test_sound_speed_printed_value():
@@ -254,18 +348,28 @@ def test_rhs_advection_and_buoyancy(oracle_mod):
     assert R[3][1:-1][th[1:-1] > 0.1].min() > 0
 
 
-def _set2nc_manufactured(lx, ly, lz, bg):
+def _set2nc_manufactured(lx, ly, lz, bg, nbv=0.0):
     """A smooth state with every field nonzero and varying in x, y and z
     (periodic in x and y, w = 0 on the walls), and the Set2NC tendencies
     of Sec. 3.1 (continuity in divergence form) differentiated analytically
-    by sympy, P' by the chain rule through the equation of state, Eq. (10)."""
+    by sympy, P' by the chain rule through the equation of state, Eq. (10).
+    nbv > 0: over the stratified background theta0(z) = theta0 exp(nbv^2 z/g)
+    with its hydrostatic Exner function, integrated here by sympy; the
+    theta' tendency then carries -w d theta0/dz."""
     import sympy as sp
     x, y, z = sp.symbols("x y z", real=True)
     kx, ky = 2 * sp.pi / lx, 2 * sp.pi / ly
-    cp, R, g, th0, p00 = bg.cp, bg.rgas, bg.grav, bg.theta0, bg.p00
+    cp, R, g, th00, p00 = bg.cp, bg.rgas, bg.grav, bg.theta0, bg.p00
     cv = cp - R
     gam = cp / cv
-    pi0 = 1 - g * z / (cp * th0)
+    if nbv > 0.0:
+        zz = sp.symbols("zz", real=True)
+        th0 = th00 * sp.exp(sp.Float(nbv) ** 2 * z / g)
+        # hydrostatic balance d pi0/dz = -g/(cp theta0), pi0(0) = 1
+        pi0 = 1 - sp.integrate(g / (cp * th0.subs(z, zz)), (zz, 0, z))
+    else:
+        th0 = th00
+        pi0 = 1 - g * z / (cp * th0)
     rho0 = p00 * pi0 ** (cv / R) / (R * th0)
     P0 = p00 * (rho0 * R * th0 / p00) ** gam
     rp = sp.Rational(4, 100) * (1 + sp.sin(kx * x + 0.7) * sp.cos(ky * y - 0.4) / 2) * (1 + z / (5 * lz))
@@ -281,7 +385,7 @@ def _set2nc_manufactured(lx, ly, lz, bg):
         -(u * d(u, x) + v * d(u, y) + w * d(u, z) + d(Pp, x) / rho),
         -(u * d(v, x) + v * d(v, y) + w * d(v, z) + d(Pp, y) / rho),
         -(u * d(w, x) + v * d(w, y) + w * d(w, z) + d(Pp, z) / rho + g * rp / rho),
-        -(u * d(th, x) + v * d(th, y) + w * d(th, z)),
+        -(u * d(th, x) + v * d(th, y) + w * d(th, z) + w * d(th0, z)),
     )
     f = lambda e: sp.lambdify((x, y, z), e, "numpy")
     return [f(e) for e in (rp, u, v, w, th)], [f(e) for e in tend]
@@ -311,6 +415,33 @@ def test_rhs_manufactured_solution(oracle_mod, N, nex, nez, zface):
     R = o.rhs(q)
     # w is imposed, not evolved, on the bottom and top nodes
     assert np.all(R[3, 0] == 0.0) and np.all(R[3, -1] == 0.0)
+    ref[3, 0] = 0.0
+    ref[3, -1] = 0.0
+    for f in range(5):
+        e = np.linalg.norm(R[f] - ref[f]) / np.linalg.norm(ref[f])
+        assert e < 1e-10, (f, e)
+
+
+@pytest.mark.parametrize("N,nex,nez,zface", [
+    (10, 8, 4, None),
+    (12, 6, 3, (0.0, 610.0, 1350.0, 2000.0)),
+])
+def test_rhs_manufactured_solution_stratified(oracle_mod, N, nex, nez, zface):
+    """The manufactured-solution pin over the stratified background: theta0(z)
+    enters P' = EOS(rho0 + rho', theta0 + theta') - P0 and the theta'
+    tendency gets -w d theta0/dz (Sec. 3.1, u . grad theta0).  A constant
+    theta0 in P', a flipped or missing w d theta0/dz, or the isentropic
+    Exner function move a tendency by far more than the tolerance."""
+    lx, ly, lz = 4000.0, 3000.0, 2000.0
+    bg = W.Background()
+    g = W.Grid(lx, ly, lz, nex, nex, nez, N, zface=None if zface is None else np.array(zface))
+    o = _oracle(oracle_mod, g, nbv=NBV)
+    qf, rf = _set2nc_manufactured(lx, ly, lz, bg, nbv=NBV)
+    xs, ys, zs = o.coords()
+    Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+    q = np.stack([np.broadcast_to(fn(X, Y, Z), X.shape) for fn in qf])
+    ref = np.stack([np.broadcast_to(fn(X, Y, Z), X.shape) for fn in rf])
+    R = o.rhs(q)
     ref[3, 0] = 0.0
     ref[3, -1] = 0.0
     for f in range(5):
