@@ -11,7 +11,8 @@
  *
  * Domain: an axis-aligned box, x and y periodic, rigid bottom and top
  * (w = 0 imposed strongly on the bottom and top nodes).  Background:
- * hydrostatic and neutral with constant theta0 (isentropic).
+ * hydrostatic, either neutral with constant theta0 (isentropic) or stably
+ * stratified with a constant Brunt-Vaisala frequency.
  *
  * State contract (every entry point that takes a state):
  *   - a DEVICE pointer owned by the caller (e.g. a torch tensor on cuda:0),
@@ -60,10 +61,12 @@ typedef struct {
 } numa_grid;
 
 typedef struct {
-    double theta0;                /* background potential temperature [K] (constant)  */
+    double theta0;                /* background potential temperature [K] at z = 0    */
     double p00;                   /* reference pressure of the equation of state [Pa] */
     double cp, rgas;              /* specific heat at constant pressure, gas constant */
     double grav;                  /* gravitational acceleration [m/s^2]               */
+    double nbv;                   /* Brunt-Vaisala frequency Nb [1/s] (>= 0): theta0(z)
+                                     = theta0 exp(Nb^2 z / g); 0 = isentropic          */
 } numa_background;
 
 typedef struct {
@@ -82,10 +85,12 @@ typedef struct {
 /*
  * Set up a context: LGL nodes and differentiation matrix of order N
  * (the sD operator of Alg. 1-2), the direct-stiffness-summed 1D derivative
- * operators along x, y and z (Sec. 5.3), and the background profiles rho0,
- * P0 = EOS(rho0, theta0), G0 = gamma P0/rho0, H0 = gamma P0/theta0
- * (Sec. 3.1, background split and linearised pressure, Eq. (13)); reference
- * fields are computed once at start-up as in Sec. 5.1.
+ * operators along x, y and z (Sec. 5.3), and the background profiles
+ * theta0(z), rho0 from the hydrostatic Exner function (d pi0/dz =
+ * -g/(cp theta0), pi0(0) = 1, integrated in closed form), P0 = EOS(rho0,
+ * theta0), G0 = gamma P0/rho0, H0 = gamma P0/theta0 (Sec. 3.1, background
+ * split and linearised pressure, Eq. (13)); reference fields are computed
+ * once at start-up as in Sec. 5.1.
  * g, bg: host pointers, read during the call only.  order: N in 1..8.
  * hip_stream: a hipStream_t (NULL = the null stream).  *out receives the
  * context.  Errors: NUMA_E_ARG, NUMA_E_UNSUPPORTED (order 9..15; columns

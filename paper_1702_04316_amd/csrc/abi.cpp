@@ -51,8 +51,10 @@ int64_t step_bytes_model(const numa_ctx *c)
 {
     // Field passes per step of the fused schedule (reads + writes of whole
     // unique-node fields): K1 5+5, K2 5+2, K3 12+10, K4 9+2, K5 10+5 = 65,
-    // plus two reads of the (shared) column factors.
-    const int64_t fields = 65;
+    // plus two reads of the (shared) column factors.  Over a stratified
+    // background the solves also write theta' (K2 reads q^n and R1 theta'
+    // for it, K3 reads it, K4 reads E3 theta' for it): 6 more.
+    const int64_t fields = numa::stratified(c) ? 71 : 65;
     return fields * c->np * int64_t(sizeof(double)) + 2 * solve_table_bytes(c);
 }
 
@@ -73,7 +75,7 @@ int step_preconditions(numa_ctx *c, double dt, const char *who)
 int ensure_mixed_buffers(numa_ctx *c, const char *who)
 {
     if (c->work_mix) return NUMA_OK;
-    hipError_t e = hipMalloc(&c->work_mix, numa::kMixedBytesPerNode * size_t(c->np));
+    hipError_t e = hipMalloc(&c->work_mix, numa::mixed_bytes_per_node(c) * size_t(c->np));
     if (e != hipSuccess) {
         c->work_mix = nullptr;
         return hip_fail(c, e, (std::string(who) + ": hipMalloc(precision-form stage buffers)").c_str());
@@ -112,10 +114,11 @@ int numa_setup(const numa_grid *g, int32_t order, const numa_background *bg, voi
                 return fail(nullptr, NUMA_E_ARG, "numa_setup: zface must be strictly increasing");
     }
     if (!finite_pos(bg->theta0) || !finite_pos(bg->p00) || !finite_pos(bg->rgas) || !finite_pos(bg->cp) ||
-        !(bg->cp > bg->rgas) || !std::isfinite(bg->grav) || bg->grav < 0.0)
+        !(bg->cp > bg->rgas) || !std::isfinite(bg->grav) || bg->grav < 0.0 || !std::isfinite(bg->nbv) ||
+        bg->nbv < 0.0 || (bg->nbv > 0.0 && !(bg->grav > 0.0)))
         return fail(nullptr, NUMA_E_ARG, "numa_setup: invalid background constants");
-    if (!(1.0 - bg->grav * g->lz / (bg->cp * bg->theta0) > 0.0))
-        return fail(nullptr, NUMA_E_ARG, "numa_setup: box top above the isentropic atmosphere's top");
+    if (!(numa::exner_at(bg->theta0, bg->cp, bg->grav, bg->nbv, g->lz) > 0.0))
+        return fail(nullptr, NUMA_E_ARG, "numa_setup: box top above the background atmosphere's top");
     if (numa::lds_needed(order, g->nez, int(nz)) > numa::kLdsPerCU)
         return fail(nullptr, NUMA_E_UNSUPPORTED, "numa_setup: columns too tall for one CU's LDS");
     if (nx * ny * nz * int64_t(sizeof(double)) >= (int64_t(1) << 32))
@@ -142,6 +145,7 @@ int numa_setup(const numa_grid *g, int32_t order, const numa_background *bg, voi
     c->eos.rgas = bg->rgas;
     c->eos.gamma = bg->cp / (bg->cp - bg->rgas);
     c->eos.grav = bg->grav;
+    c->nbv = bg->nbv;
     numa::set_binomial(c->eos);
     c->stream = static_cast<hipStream_t>(hip_stream);
     hipError_t e = hipGetDevice(&c->device);
@@ -156,7 +160,8 @@ int numa_setup(const numa_grid *g, int32_t order, const numa_background *bg, voi
     numa::build_ops(c, g->zface);
 
     const int N = order, ns = 2 * N + 1;
-    const size_t n_lev = size_t(4 * nz + nz * ns + 3 * g->nez + 2 * N * ns + (N + 1) * (N + 1) + 8 * nz);
+    const size_t n_lev =
+        size_t(4 * nz + nz * ns + 3 * g->nez + 2 * N * ns + (N + 1) * (N + 1) + numa::SC_N * nz + 2 * nz);
     e = hipMalloc(&c->lev_block, n_lev * sizeof(double));
     if (e != hipSuccess) {
         int rc = hip_fail(nullptr, e, "numa_setup: hipMalloc(levels)");
@@ -172,12 +177,14 @@ int numa_setup(const numa_grid *g, int32_t order, const numa_background *bg, voi
     c->lev.zsc = p; p += 3 * g->nez;
     c->lev.wxy = p; p += 2 * N * ns;
     c->lev.D = p; p += (N + 1) * (N + 1);
-    c->lev.scf = p;
+    c->lev.scf = p; p += numa::SC_N * nz;
+    c->lev.th0 = p; p += nz;
+    c->lev.th0z = p;
 
     // every column has the same operator (uniform horizontal grid, one set of
     // vertical faces, horizontally uniform background): one factor set
     const size_t fac_n = size_t(nz) * size_t(4 * N + 1);
-    const size_t work_n = size_t(19) * size_t(c->np);
+    const size_t work_n = size_t(numa::kStageFields) * size_t(c->np);
     e = hipMalloc(&c->fac, fac_n * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&c->work, work_n * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&c->flag, sizeof(int));
@@ -188,7 +195,8 @@ int numa_setup(const numa_grid *g, int32_t order, const numa_background *bg, voi
     }
     struct Up { double *dst; const std::vector<double> *src; };
     const Up ups[] = {{c->lev.rho0, &c->ops.rho0}, {c->lev.dzb, &c->ops.dzb}, {c->lev.zsc, &c->ops.zsc},
-                      {c->lev.wxy, &c->ops.wxy}, {c->lev.D, &c->ops.D}};
+                      {c->lev.wxy, &c->ops.wxy}, {c->lev.D, &c->ops.D}, {c->lev.th0, &c->ops.th0},
+                      {c->lev.th0z, &c->ops.th0z}};
     for (const Up &u : ups) {
         e = hipMemcpyAsync(u.dst, u.src->data(), u.src->size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
         if (e != hipSuccess) break;
@@ -223,7 +231,7 @@ int numa_get_info(const numa_ctx *c, numa_info *info)
     info->nz = c->nz;
     info->ncol = c->ncol;
     info->factor_bytes = solve_table_bytes(c);
-    info->scratch_bytes = 19 * c->np * int64_t(sizeof(double));
+    info->scratch_bytes = numa::kStageFields * c->np * int64_t(sizeof(double));
     info->step_bytes = step_bytes_model(c);
     info->order = c->N;
     info->factored = c->factored;
@@ -328,11 +336,11 @@ int numa_hevi_step_mixed_noalloc(numa_ctx *c, double *state, double dt, int32_t 
     if (!state || nsteps < 0) return fail(c, NUMA_E_ARG, "numa_hevi_step_mixed_noalloc: null state or nsteps < 0");
     int rc = step_preconditions(c, dt, "numa_hevi_step_mixed_noalloc");
     if (rc != NUMA_OK) return rc;
-    const size_t need = numa::kMixedBytesPerNode * size_t(c->np);
+    const size_t per = numa::mixed_bytes_per_node(c), need = per * size_t(c->np);
     if (need > numa::kNoAllocScratchBytes)
         return fail(c, NUMA_E_UNSUPPORTED,
-                    "numa_hevi_step_mixed_noalloc: the grid needs " + std::to_string(need) +
-                        " bytes of stage buffers (104 per unique node), above the fixed " +
+                    "numa_hevi_step_mixed_noalloc: the grid needs " + std::to_string(need) + " bytes of stage buffers (" +
+                        std::to_string(per) + " per unique node), above the fixed " +
                         std::to_string(numa::kNoAllocScratchBytes) + " bytes");
     char *mb = numa::noalloc_scratch(c->device);
     if (!mb)
@@ -388,6 +396,8 @@ int numa_factor_columns_standard(numa_ctx *c, double dt, int64_t *bytes_out)
 {
     if (!c) return NUMA_E_ARG;
     if (!finite_pos(dt)) return fail(c, NUMA_E_ARG, "numa_factor_columns_standard: dt must be finite and > 0");
+    if (numa::stratified(c))
+        return fail(c, NUMA_E_UNSUPPORTED, "numa_factor_columns_standard: built for the isentropic background only");
     const double lambda = (1.0 - 1.0 / std::sqrt(2.0)) * dt;
     c->std_factored = 0;
     hipError_t e = numa::launch_factor_std(c, lambda);
@@ -414,6 +424,8 @@ int numa_imex3d_setup(numa_ctx *c, double dt, int32_t restart, int32_t pbno_orde
                       int32_t maxit)
 {
     if (!c) return NUMA_E_ARG;
+    if (numa::stratified(c))
+        return fail(c, NUMA_E_UNSUPPORTED, "numa_imex3d_setup: the 3D Schur form is built for theta0 constant");
     if (!finite_pos(dt) || restart < 1 || restart > 63 || pbno_order < -1 || pbno_order > 16 || power_steps < 0 ||
         power_steps > 1000 || maxit < 1)
         return fail(c, NUMA_E_ARG, "numa_imex3d_setup: bad arguments");

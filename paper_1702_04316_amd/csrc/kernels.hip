@@ -93,12 +93,11 @@ __device__ __forceinline__ double eos_pressure(double rho, double theta, const E
 // across the stencil loops, for a path that weather states do not take.
 __device__ __noinline__ double binom_power_m1(double x, double gamma) { return expm1(gamma * log1p(x)); }
 
-// irt = 1/(rho0 theta0) of the level.
+// r0, t0, P0: rho0, theta0, P0 of the level; irt = 1/(rho0 theta0).
 __device__ __forceinline__ double pressure_perturbation(double rp, double th, double r0, double P0, double irt,
-                                                        const EOS &e)
+                                                        double t0, const EOS &e)
 {
 #pragma clang fp contract(off)
-    const double t0 = e.theta0;
     const double p1 = r0 * th, p2 = t0 * rp, p3 = rp * th;
     const double e1 = __builtin_fma(r0, th, -p1), e2 = __builtin_fma(t0, rp, -p2), e3 = __builtin_fma(rp, th, -p3);
     const double d = ((p1 + p2) + p3) + ((e1 + e2) + e3);
@@ -157,9 +156,12 @@ __device__ __forceinline__ void *field(void *base, int f, long fs)
 
 struct RhsParams {
     // input fields (rho', u, v, w, theta'); with HASB, u, v, theta' of the
-    // input are e0 + cb * e1 (a[1], a[2], a[4] unused)
+    // input are e0 + cb * e1 (a[1], a[2], a[4] unused), except theta' when
+    // theta_in is set (a[4]: the stage value the column solve wrote over a
+    // stratified background)
     const void *a[5];
     double cb;
+    int theta_in;
     // five-field buffers (field f at + f * fs): out0 = e0 + k01 e1 + k02 R,
     // out1 = e0 + k11 e1 + k12 R
     void *out0, *out1;
@@ -167,6 +169,7 @@ struct RhsParams {
     long fs;
     double k01, k02, k11, k12;
     const double *rho0, *P0, *zsc, *wxy, *D;
+    const double *th0, *th0z;  // theta0 and d theta0/dz per level
     EOS eos;
     int nx, ny, nz, nez, zchunk, nchunk, ntx, nty;
     int *flag;
@@ -243,7 +246,8 @@ template <bool HASB, class TA, class TE1>
 __device__ __forceinline__ double stage_input(const RhsParams &p, int f, unsigned off)
 {
     if constexpr (HASB) {
-        if (f == 1 || f == 2 || f == 4) return FiveField<false>::load(p.e0, f, p.fs, off) + p.cb * TE1::load(p.e1, f, p.fs, off);
+        if (f == 1 || f == 2 || (f == 4 && !p.theta_in))
+            return FiveField<false>::load(p.e0, f, p.fs, off) + p.cb * TE1::load(p.e1, f, p.fs, off);
     }
     return TA::load1(p.a[f], f, off);
 }
@@ -259,7 +263,8 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
     using G = RhsGeom<N, sizeof(C)>;
     constexpr int NQ = N + 1, NS = G::NS, TX = G::TX, TY = G::TY, LX = G::LX, FS = G::FS;
     // dynamic LDS: ring of N+1 planes [rho', u, v, w, theta' (C)][P' (FP64)]
-    // of [LY][LX], then per-level tables rho0, P0, 1/(rho0 theta0) for the
+    // of [LY][LX], then per-level tables rho0, P0, 1/(rho0 theta0), theta0,
+    // d theta0/dz for the
     // levels this chunk touches, zsc [3][nez], and the interface shares
     // [2][6][TX*TY] (FP64)
     extern __shared__ double lds_block[];
@@ -299,7 +304,9 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
     double *sR0 = lds_block + G::LDS / sizeof(double);
     double *sP0 = sR0 + nlev;
     double *sIRT = sP0 + nlev;
-    double *zs = sIRT + nlev;  // [0,nez): 2/h ; [nez,2nez): bottom factor ; [2nez,3nez): top factor
+    double *sT0 = sIRT + nlev;
+    double *sTZ = sT0 + nlev;
+    double *zs = sTZ + nlev;  // [0,nez): 2/h ; [nez,2nez): bottom factor ; [2nez,3nez): top factor
     // the lower element's share of the six z-derivatives at the interface
     // node of each column, double-buffered by element parity: [2][6][TX*TY]
     double *zp = zs + 3 * p.nez;
@@ -315,9 +322,12 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
     }
     for (int s = tid; s < nlev; s += G::NT) {
         const double r0 = p.rho0[kb + s];
+        const double t0 = p.th0[kb + s];
         sR0[s] = r0;
         sP0[s] = p.P0[kb + s];
-        sIRT[s] = 1.0 / (r0 * eos.theta0);
+        sIRT[s] = 1.0 / (r0 * t0);
+        sT0[s] = t0;
+        sTZ[s] = p.th0z[kb + s];
     }
     for (int s = tid; s < 3 * p.nez; s += G::NT) zs[s] = p.zsc[s];
     // Precision form: the ring holds u - uref and v - vref in FP32, with the
@@ -385,9 +395,10 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
         for (int s = 0; s < G::NITEM; ++s) {
             const unsigned off = unsigned(kbase + it_p[s]) * pbytes + it_o[s];
 #pragma unroll
-            for (int f = 0; f < 5; ++f)
-                v[s][f] = HASB && (f == 1 || f == 2 || f == 4) ? FiveField<false>::load(p.e0, f, p.fs, off)
-                                                             : TA::load1(p.a[f], f, off);
+            for (int f = 0; f < 4; ++f)
+                v[s][f] = HASB && (f == 1 || f == 2) ? FiveField<false>::load(p.e0, f, p.fs, off)
+                                                     : TA::load1(p.a[f], f, off);
+            v[s][4] = HASB && !p.theta_in ? FiveField<false>::load(p.e0, 4, p.fs, off) : TA::load1(p.a[4], 4, off);
         }
         if constexpr (HASB) {
 #pragma unroll
@@ -395,13 +406,13 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
                 const unsigned off = unsigned(kbase + it_p[s]) * pbytes + it_o[s];
                 v[s][1] += p.cb * TE1::load(p.e1, 1, p.fs, off);
                 v[s][2] += p.cb * TE1::load(p.e1, 2, p.fs, off);
-                v[s][4] += p.cb * TE1::load(p.e1, 4, p.fs, off);
+                if (!p.theta_in) v[s][4] += p.cb * TE1::load(p.e1, 4, p.fs, off);
             }
         }
 #pragma unroll
         for (int s = 0; s < G::NITEM; ++s) {
             const int k = kbase + it_p[s], kl = k - kb;
-            const double Pp = pressure_perturbation(v[s][0], v[s][4], sR0[kl], sP0[kl], sIRT[kl], eos);
+            const double Pp = pressure_perturbation(v[s][0], v[s][4], sR0[kl], sP0[kl], sIRT[kl], sT0[kl], eos);
             C *d = cfield(k % NQ) + it_l[s];
             d[0 * FS] = C(v[s][0]);
             d[1 * FS] = C(v[s][1] - uref);
@@ -495,7 +506,8 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
             R3 = wfield(k % NQ)[l_own] * dzw + (dzp * irp + eos.grav * rpd * irp);
         else
             R3 = w * dzw + dzp * ir + eos.grav * rp * ir;
-        R[4] = w * dz[4];
+        // theta': advection of theta' and of the background, w d theta0/dz
+        R[4] = w * dz[4] + w * C(sTZ[k - kb]);
         // line derivative of the six quantities along x (dir 0) or y (dir 1)
         // (not unrolled: unrolled, the scheduler hoists all its LDS reads)
         auto line = [&](int dir, C *d5, double &dp, double &dfl, double &dwl) {
@@ -578,7 +590,7 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
         const double rp = stage_input<HASB, TA, TE1>(p, 0, off), u = stage_input<HASB, TA, TE1>(p, 1, off);
         const double v = stage_input<HASB, TA, TE1>(p, 2, off), w = stage_input<HASB, TA, TE1>(p, 3, off);
         const double th = stage_input<HASB, TA, TE1>(p, 4, off);
-        const double Pp = pressure_perturbation(rp, th, sR0[kl], sP0[kl], sIRT[kl], eos);
+        const double Pp = pressure_perturbation(rp, th, sR0[kl], sP0[kl], sIRT[kl], sT0[kl], eos);
         C *d = cfield(k % NQ) + it_l[s];
         d[0 * FS] = C(rp);
         d[1 * FS] = C(u - uref);
@@ -605,7 +617,7 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
             const double th0 = stage_input<HASB, TA, TE1>(p, 4, off), th = C(th0);
             const double rho = MIX ? sR0[kl] + stage_input<HASB, TA, TE1>(p, 0, off) : double(C(sR0[kl])) + rp;
             const double Pp = pressure_perturbation(stage_input<HASB, TA, TE1>(p, 0, off), th0, sR0[kl], sP0[kl],
-                                                    sIRT[kl], eos);
+                                                    sIRT[kl], sT0[kl], eos);
             const double d = double(sD[N * NQ + n]);
             acc[0] += d * (rho * w);
             acc[1] += d * u;
@@ -682,17 +694,16 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
 typedef const __attribute__((address_space(4))) double cdouble;
 __device__ __forceinline__ cdouble *as_const(const double *p) { return (cdouble *)(p); }
 
-// per-level coefficients of the column solve, [nz][8]
-enum { SC_G0 = 0, SC_H0, SC_RHO0, SC_WA, SC_LG, SC_X1, SC_X2, SC_N = 8 };
 
 struct SolveParams {
     // q~_e for rho', w, theta': sum_t c_t * ptr_t
     const void *er[3], *ew[3], *et[3];
     double cr[3], cw[3], ct[3];
-    // outputs: rho' = sum_t cbr_t br_t - lambda Dz(rho0 w~);  w = w~ + sum_t cbw_t bw_t
-    const void *br[2], *bw[2];
-    double cbr[2], cbw[2];
-    void *out_r, *out_w;
+    // outputs: rho' = sum_t cbr_t br_t - lambda Dz(rho0 w~);  w = w~ + sum_t cbw_t bw_t;
+    // over a stratified background (out_t set) also theta' = sum_t cbt_t bt_t - TZ w~
+    const void *br[2], *bw[2], *bt[2];
+    double cbr[2], cbw[2], cbt[2];
+    void *out_r, *out_w, *out_t;
     // FP64 field where the forward pass parks w_a for the extraction (out_w
     // itself when that is FP64): w~ = w_a - lambda (...) cancels strongly at
     // large vertical Courant numbers, so w_a must keep FP64 precision
@@ -707,14 +718,14 @@ struct SolveParams {
 // term counts of the stage variants: (NR, NW, NT) explicit-estimate terms,
 // (NBR, NBW) output terms; F32: which fields are FP32 (bit 0+t er[t], 3+t
 // ew[t], 6+t et[t], 9+t br[t], 11+t bw[t], 13 out_w, 14 out_r), the rest FP64
-template <int NR_, int NW_, int NT_, int NBR_, int NBW_, unsigned F32_ = 0>
+template <int NR_, int NW_, int NT_, int NBR_, int NBW_, int NBT_, unsigned F32_ = 0>
 struct SolveShape {
-    static constexpr int NR = NR_, NW = NW_, NT = NT_, NBR = NBR_, NBW = NBW_;
+    static constexpr int NR = NR_, NW = NW_, NT = NT_, NBR = NBR_, NBW = NBW_, NBT = NBT_;
     static constexpr unsigned F32 = F32_;
 };
-using ShapePlain = SolveShape<1, 1, 1, 1, 0>;
-using ShapeStage2 = SolveShape<1, 1, 1, 2, 1>;
-using ShapeStage3 = SolveShape<3, 3, 3, 1, 2>;
+using ShapePlain = SolveShape<1, 1, 1, 1, 0, 1>;
+using ShapeStage2 = SolveShape<1, 1, 1, 2, 1, 2>;
+using ShapeStage3 = SolveShape<3, 3, 3, 1, 2, 1>;
 // element type of field bit b of a shape
 template <class SH, int B>
 using SolveT = std::conditional_t<((SH::F32 >> B) & 1u) != 0, float, double>;
@@ -807,8 +818,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 #pragma unroll
                     for (int t = 0; t < SH::NT; ++t) te += p.ct[t] * es[b][SH::NR + SH::NW + t];
                     cdouble *cf = scf + s * SC_N;
-                    // w_a = B (w_e + lambda g H0 theta_e / (G0 rho0))  (Eq. (16), A = I)
-                    const double wa = (s == 0 || s == M - 1) ? 0.0 : we + cf[SC_WA] * te;
+                    // w_a = B A^-1 (w_e + lambda g H0 theta_e / (G0 rho0))  (Eq. (16))
+                    const double wa = (s == 0 || s == M - 1) ? 0.0 : cf[SC_AI] * we + cf[SC_WA] * te;
                     P[s * 64] = cf[SC_G0] * re + cf[SC_H0] * te;
                     W[(s & (R - 1)) * 64] = cf[SC_RHO0] * wa;
                     if (act) gstore(p.park, unsigned(s) * lbytes + cbyte, wa);
@@ -819,7 +830,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
                     double d = 0.0;
 #pragma unroll
                     for (int m = 0; m < NS; ++m) d += bz[m] * W[((k - N + m) & (R - 1)) * 64];
-                    double y = P[k * 64] - scf[k * SC_N + SC_LG] * d;
+                    cdouble *ck = scf + k * SC_N;
+                    double y = P[k * 64] - ck[SC_LG] * d - ck[SC_HZ] * (W[(k & (R - 1)) * 64] / ck[SC_RHO0]);
 #pragma unroll
                     for (int dd = 0; dd < HB; ++dd) y -= fac(k * NB + dd) * P[(k - HB + dd) * 64];  // column k - HB + dd
                     P[k * 64] = y;
@@ -872,6 +884,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
                     for (int t = 0; t < SH::NBW; ++t) sh += p.cbw[t] * xs[b][1 + t];
                     W[(s & (R - 1)) * 64] = cf[SC_RHO0] * wt;
                     if (act) tstore<SolveT<SH, 13>>(p.out_w, unsigned(s) * lbytes + cbyte, wt + sh);
+                    if (p.out_t && act) {  // theta' over a stratified background
+                        const unsigned off = unsigned(s) * lbytes + cbyte;
+                        double th = 0.0;
+#pragma unroll
+                        for (int t = 0; t < SH::NBT; ++t) th += p.cbt[t] * gload(static_cast<const double *>(p.bt[t]), off);
+                        gstore(static_cast<double *>(p.out_t), off, th - cf[SC_TZ] * wt);
+                    }
                 }
                 const int k = s - N;
                 if (k >= 0 && k < M) {
@@ -985,8 +1004,8 @@ void k_colsolve_blocked(SolveParams p)
 #pragma unroll
                     for (int t = 0; t < SH::NT; ++t) te += p.ct[t] * e[b][SH::NR + SH::NW + t];
                     cdouble *cf = scf + s * SC_N;
-                    // w_a = B (w_e + lambda g H0 theta_e / (G0 rho0))  (Eq. (16), A = I)
-                    wa[i] = (s == 0 || s == M - 1) ? 0.0 : we + cf[SC_WA] * te;
+                    // w_a = B A^-1 (w_e + lambda g H0 theta_e / (G0 rho0))  (Eq. (16))
+                    wa[i] = (s == 0 || s == M - 1) ? 0.0 : cf[SC_AI] * we + cf[SC_WA] * te;
                     r[i] = cf[SC_G0] * re + cf[SC_H0] * te;
                     V[s * 64] = cf[SC_RHO0] * wa[i];
                 }
@@ -994,10 +1013,10 @@ void k_colsolve_blocked(SolveParams p)
         }
     }
     __syncthreads();
-    // ---- 2. b = P_e - lambda G0 Dz(rho0 w_a)
+    // ---- 2. b = P_e - lambda G0 Dz(rho0 w_a) - lambda H0 (d theta0/dz) w_a
 #pragma unroll
     for (int i = 0; i < KX; ++i)
-        if (i < nk) r[i] -= scf[(k0 + i) * SC_N + SC_LG] * dz_of_v(k0 + i);
+        if (i < nk) r[i] -= scf[(k0 + i) * SC_N + SC_LG] * dz_of_v(k0 + i) + scf[(k0 + i) * SC_N + SC_HZ] * wa[i];
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < KX; ++i)
@@ -1072,16 +1091,21 @@ void k_colsolve_blocked(SolveParams p)
 #pragma unroll
     for (int i = 0; i < KX; ++i)
         if (i < nk) r[i] = V[(k0 + i) * 64];
-    // ---- 4. w~ and the w output
+    // ---- 4. w~ and the w output (and theta' over a stratified background)
+    const bool strat = p.out_t != nullptr;
 #pragma unroll
     for (int i0 = 0; i0 < KX; i0 += CX) {
         if (i0 < nk) {
-            double xb[CX][2];
+            double xb[CX][2], xt[CX][2];
 #pragma unroll
             for (int b = 0; b < CX; ++b) {
                 const unsigned off = unsigned(k0 + min(i0 + b, nk - 1)) * lbytes + cbyte;
                 if constexpr (SH::NBW > 0) xb[b][0] = tload<SolveT<SH, 11>>(p.bw[0], off);
                 if constexpr (SH::NBW > 1) xb[b][1] = tload<SolveT<SH, 12>>(p.bw[1], off);
+                if (strat) {
+#pragma unroll
+                    for (int t = 0; t < SH::NBT; ++t) xt[b][t] = gload(static_cast<const double *>(p.bt[t]), off);
+                }
             }
 #pragma unroll
             for (int b = 0; b < CX; ++b) {
@@ -1095,6 +1119,12 @@ void k_colsolve_blocked(SolveParams p)
                     for (int t = 0; t < SH::NBW; ++t) sh += p.cbw[t] * xb[b][t];
                     r[i] = cf[SC_RHO0] * wt;
                     if (act) tstore<SolveT<SH, 13>, NT>(p.out_w, unsigned(s) * lbytes + cbyte, wt + sh);
+                    if (strat && act) {
+                        double th = 0.0;
+#pragma unroll
+                        for (int t = 0; t < SH::NBT; ++t) th += p.cbt[t] * xt[b][t];
+                        gstore<NT>(static_cast<double *>(p.out_t), unsigned(s) * lbytes + cbyte, th - cf[SC_TZ] * wt);
+                    }
                 }
             }
         }
@@ -1130,29 +1160,40 @@ void k_colsolve_blocked(SolveParams p)
     }
 }
 
-// Per-level coefficients of the column solve at lambda (Eqs. (16)-(17) in
-// 1D with A = I): G0, H0, rho0, lambda g H0/(G0 rho0), lambda G0,
-// lambda/rho0, lambda g/(G0 rho0).
-__global__ void k_solve_coefs(const double *rho0, const double *G0, const double *H0, double lambda, double grav,
-                              int nz, double *scf)
+// Per-level coefficients of the column solve at lambda (Eqs. (14)-(17) in
+// 1D): with the vertical part of A = I + lambda^2 (g/theta0) grad(theta0)^T,
+// a = 1 + lambda^2 g (d theta0/dz)/theta0 (1 over a neutral background), and
+// F0 . u = G0 w d rho0/dz + H0 w d theta0/dz, whose G0 part the divergence
+// form G0 Dz(rho0 w) holds:
+//   w_a = B (w_e + lambda g H0 theta_e/(G0 rho0)) / a = AI w_e + WA theta_e,
+//   w_p = B (X1 Dz P + X2 P), X1 = lambda/(a rho0), X2 = lambda g/(a G0 rho0),
+//   S P = P - LG Dz(rho0 w_p) - HZ w_p, LG = lambda G0, HZ = lambda H0 d theta0/dz,
+//   theta' = theta_e - TZ w~, TZ = lambda d theta0/dz.
+__global__ void k_solve_coefs(const double *rho0, const double *G0, const double *H0, const double *th0,
+                              const double *th0z, double lambda, double grav, int nz, double *scf)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nz) return;
-    const double r0 = rho0[k], g0 = G0[k], h0 = H0[k];
+    const double r0 = rho0[k], g0 = G0[k], h0 = H0[k], tz = th0z[k];
+    const double ai = 1.0 / (1.0 + lambda * lambda * grav * tz / th0[k]);
     double *o = scf + SC_N * k;
     o[SC_G0] = g0;
     o[SC_H0] = h0;
     o[SC_RHO0] = r0;
-    o[SC_WA] = lambda * grav * h0 / (g0 * r0);
+    o[SC_WA] = ai * (lambda * grav * h0 / (g0 * r0));
     o[SC_LG] = lambda * g0;
-    o[SC_X1] = lambda / r0;
-    o[SC_X2] = lambda * grav / (g0 * r0);
-    o[7] = 0.0;
+    o[SC_X1] = (lambda * ai) / r0;
+    o[SC_X2] = (lambda * ai) * grav / (g0 * r0);
+    o[SC_AI] = ai;
+    o[SC_HZ] = lambda * h0 * tz;
+    o[SC_TZ] = lambda * tz;
+    for (int t = SC_TZ + 1; t < SC_N; ++t) o[t] = 0.0;
 }
 
 // ---------------------------------------------------------------------------
-// Column factorisation: S = I - lambda^2 G0 Dz rho0 B (Dz/rho0 + g/(G0 rho0))
-// = I - lambda^2 G0 Dz B (Dz + g/G0), assembled as a band of half-width 2N,
+// Column factorisation: S = I - LG Dz rho0 B (X1 Dz + X2) - HZ B (X1 Dz + X2)
+// (the Schur matrix of the coefficients above; over a neutral background
+// I - lambda^2 G0 Dz B (Dz + g/G0)), assembled as a band of half-width 2N,
 // then Doolittle LU without pivoting (Alg. 9).  Every column has the same
 // matrix, so one workgroup factors the single shared band [row][offset]:
 // its threads assemble the entries, then for each pivot k update the
@@ -1166,26 +1207,30 @@ constexpr size_t kFactorLds = 64 * 1024;
 
 template <int N>
 __global__ __launch_bounds__(kFactorThreads) void k_factor(const double *__restrict__ dzb,
-                                                           const double *__restrict__ G0, double lambda, double grav,
-                                                           int M, int in_lds, double *fac, int *flag)
+                                                           const double *__restrict__ scf, int M, int in_lds,
+                                                           double *fac, int *flag)
 {
     extern __shared__ double band_lds[];
     constexpr int NS = 2 * N + 1, NB = 4 * N + 1, HB = 2 * N;
     const int tid = threadIdx.x;
     double *A = in_lds ? band_lds : fac;  // entry (r, c) at r*NB + (c - r + HB)
-    const double l2 = lambda * lambda;
     for (int idx = tid; idx < M * NB; idx += kFactorThreads) {
         const int r = idx / NB, cidx = r + idx % NB - HB;
         double v = 0.0;
         if (cidx >= 0 && cidx < M) {
+            // rows of the interior levels m (B zeroes the walls)
             double s = 0.0;
             const int mlo = max(max(r, cidx) - N, 1), mhi = min(min(r, cidx) + N, M - 2);
             for (int m = mlo; m <= mhi; ++m) {
                 const double drm = dzb[(long)r * NS + (m - r + N)];
                 const double dmc = dzb[(long)m * NS + (cidx - m + N)];
-                s += drm * (dmc + (m == cidx ? grav / G0[m] : 0.0));
+                const double *cm = scf + (long)m * SC_N;
+                s += drm * cm[SC_RHO0] * (cm[SC_X1] * dmc + (m == cidx ? cm[SC_X2] : 0.0));
             }
-            v = (r == cidx ? 1.0 : 0.0) - l2 * G0[r] * s;
+            const double *cr = scf + (long)r * SC_N;
+            v = (r == cidx ? 1.0 : 0.0) - cr[SC_LG] * s;
+            if (r >= 1 && r <= M - 2 && cidx >= r - N && cidx <= r + N)
+                v -= cr[SC_HZ] * (cr[SC_X1] * dzb[(long)r * NS + (cidx - r + N)] + (r == cidx ? cr[SC_X2] : 0.0));
         }
         A[idx] = v;
     }
@@ -1213,15 +1258,16 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor(const double *__restr
     if (bad) *flag = 1;
 }
 
-// P0 = EOS(rho0, theta0), G0 = gamma P0 / rho0, H0 = gamma P0 / theta0
-__global__ void k_background(const double *rho0, double *P0, double *G0, double *H0, int nz, EOS e)
+// P0 = EOS(rho0, theta0), G0 = gamma P0 / rho0, H0 = gamma P0 / theta0 per level
+__global__ void k_background(const double *rho0, const double *th0, double *P0, double *G0, double *H0, int nz,
+                             EOS e)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nz) return;
-    double P = eos_pressure(rho0[k], e.theta0, e);
+    double P = eos_pressure(rho0[k], th0[k], e);
     P0[k] = P;
     G0[k] = e.gamma * P / rho0[k];
-    H0[k] = e.gamma * P / e.theta0;
+    H0[k] = e.gamma * P / th0[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -1236,7 +1282,7 @@ size_t rhs_lds_bytes(int zchunk, int nez)
 {
     constexpr int ES = MIX ? 4 : 8;
     return RhsGeom<N, ES>::LDS +
-           sizeof(double) * (3 * ((zchunk + 1) * N + 1) + 3 * nez + 2 * 6 * RhsGeom<N>::TX * RhsGeom<N>::TY);
+           sizeof(double) * (5 * ((zchunk + 1) * N + 1) + 3 * nez + 2 * 6 * RhsGeom<N>::TX * RhsGeom<N>::TY);
 }
 
 template <int N>
@@ -1311,6 +1357,8 @@ hipError_t rhs_launch(numa_ctx *c, RhsParams p)
     p.zsc = c->lev.zsc;
     p.wxy = c->lev.wxy;
     p.D = c->lev.D;
+    p.th0 = c->lev.th0;
+    p.th0z = c->lev.th0z;
     p.eos = c->eos;
     p.nx = int(c->nx);
     p.ny = int(c->ny);
@@ -1401,7 +1449,7 @@ hipError_t factor_launch(numa_ctx *c, double lambda)
     const size_t bytes = size_t(c->nz) * (4 * N + 1) * sizeof(double);
     const bool lds = bytes <= kFactorLds;
     hipLaunchKernelGGL((k_factor<N>), dim3(1), dim3(kFactorThreads), lds ? bytes : 0, c->stream, c->lev.dzb,
-                       c->lev.G0, lambda, c->eos.grav, int(c->nz), int(lds), c->fac, c->flag);
+                       c->lev.scf, int(c->nz), int(lds), c->fac, c->flag);
     return hipGetLastError();
 }
 
@@ -1494,20 +1542,22 @@ StageBuffers stage_buffers(numa_ctx *c)
     s.Q2w = c->work + 16 * np;
     s.Q3r = c->work + 17 * np;
     s.Q3w = c->work + 18 * np;
+    s.Q2t = c->work + 19 * np;
+    s.Q3t = c->work + 20 * np;
     return s;
 }
 
 hipError_t launch_background(numa_ctx *c)
 {
     hipLaunchKernelGGL(k_background, dim3(unsigned((c->nz + 63) / 64)), dim3(64), 0, c->stream, c->lev.rho0,
-                       c->lev.P0, c->lev.G0, c->lev.H0, int(c->nz), c->eos);
+                       c->lev.th0, c->lev.P0, c->lev.G0, c->lev.H0, int(c->nz), c->eos);
     return hipGetLastError();
 }
 
 hipError_t launch_factor(numa_ctx *c, double lambda)
 {
     hipLaunchKernelGGL(k_solve_coefs, dim3(unsigned((c->nz + 63) / 64)), dim3(64), 0, c->stream, c->lev.rho0,
-                       c->lev.G0, c->lev.H0, lambda, c->eos.grav, int(c->nz), c->lev.scf);
+                       c->lev.G0, c->lev.H0, c->lev.th0, c->lev.th0z, lambda, c->eos.grav, int(c->nz), c->lev.scf);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return dispatch(c->N, [&](auto n) { return factor_launch<decltype(n)::value>(c, lambda); });
@@ -1561,8 +1611,13 @@ hipError_t launch_solve_plain(numa_ctx *c, const double *y, double *x)
     p.br[0] = y + 0 * np; p.cbr[0] = 1.0;
     p.out_r = x + 0 * np;
     p.out_w = x + 3 * np;
+    if (stratified(c)) {  // theta' = y_theta - lambda (d theta0/dz) w
+        p.bt[0] = y + 4 * np; p.cbt[0] = 1.0;
+        p.out_t = x + 4 * np;
+    }
     hipError_t e;
     for (int f : {1, 2, 4}) {
+        if (f == 4 && stratified(c)) continue;
         e = hipMemcpyAsync(x + f * np, y + f * np, sizeof(double) * np, hipMemcpyDeviceToDevice, c->stream);
         if (e != hipSuccess) return e;
     }
@@ -1586,6 +1641,7 @@ hipError_t launch_hevi_step(numa_ctx *c, double *q, double dt, hipEvent_t *ev)
     StageBuffers s = stage_buffers(c);
     const double *qr = q + 0 * np, *qw = q + 3 * np, *qt = q + 4 * np;
     const double *R1 = s.R1;
+    const bool strat = stratified(c);
     hipError_t e;
 
     // ev (optional): events ev[0..5] recorded around the 5 kernels
@@ -1608,6 +1664,10 @@ hipError_t launch_hevi_step(numa_ctx *c, double *q, double dt, hipEvent_t *ev)
         p.bw[0] = qw; p.cbw[0] = 1.0;
         p.out_r = s.Q2r;
         p.out_w = s.Q2w;
+        if (strat) {  // Q2 theta' = q^n + dt a21 R1 - lambda (d theta0/dz) w~
+            p.bt[0] = qt; p.cbt[0] = 1.0; p.bt[1] = R1 + 4 * np; p.cbt[1] = f;
+            p.out_t = s.Q2t;
+        }
         e = dispatch(c->N, [&](auto n) { return solve_launch<decltype(n)::value, ShapeStage2>(c, p); });
         if (e != hipSuccess) return e;
         if ((e = mark(2)) != hipSuccess) return e;
@@ -1620,6 +1680,10 @@ hipError_t launch_hevi_step(numa_ctx *c, double *q, double dt, hipEvent_t *ev)
         p.a[0] = s.Q2r;
         p.a[3] = s.Q2w;
         p.cb = f;  // u, v, theta' = e0 + f e1 = q^n + f R1
+        if (strat) {  // theta' from the solve
+            p.theta_in = 1;
+            p.a[4] = s.Q2t;
+        }
         p.out0 = s.E3;
         p.out1 = s.ACC;
         p.e0 = q;
@@ -1644,6 +1708,11 @@ hipError_t launch_hevi_step(numa_ctx *c, double *q, double dt, hipEvent_t *ev)
         p.bw[0] = qw; p.cbw[0] = -t.c31; p.bw[1] = s.Q2w; p.cbw[1] = -t.c32;
         p.out_r = s.Q3r;
         p.out_w = s.Q3w;
+        if (strat) {  // Q2 theta' is the solve's; Q3 theta' = E3 - lambda (d theta0/dz) w~
+            p.ct[1] = t.c31; p.et[2] = s.Q2t; p.ct[2] = t.c32;
+            p.bt[0] = s.E3 + 4 * np; p.cbt[0] = 1.0;
+            p.out_t = s.Q3t;
+        }
         e = dispatch(c->N, [&](auto n) { return solve_launch<decltype(n)::value, ShapeStage3>(c, p); });
         if (e != hipSuccess) return e;
         if ((e = mark(4)) != hipSuccess) return e;
@@ -1656,7 +1725,7 @@ hipError_t launch_hevi_step(numa_ctx *c, double *q, double dt, hipEvent_t *ev)
         p.a[1] = s.E3 + 1 * np;
         p.a[2] = s.E3 + 2 * np;
         p.a[3] = s.Q3w;
-        p.a[4] = s.E3 + 4 * np;
+        p.a[4] = strat ? s.Q3t : s.E3 + 4 * np;
         p.out0 = q;
         p.e0 = s.ACC;
         p.fs = np;
@@ -1682,16 +1751,19 @@ size_t mixed_field_offset(int f, long np)
 // are differentiated by the last right-hand side, and their FP32 rounding
 // would be amplified there like any rounding of a stage value); the state
 // and the accumulator ACC stay FP64; the column solves read those and run
-// in FP64 with the FP64 factors.  mb: kMixedBytesPerNode * np bytes.
+// in FP64 with the FP64 factors.  mb: mixed_bytes_per_node(c) * np bytes.
 hipError_t launch_hevi_step_mixed_in(numa_ctx *c, double *q, double dt, char *mb, hipEvent_t *ev)
 {
     static const Ark2 t;
     const long np = c->np;
     // R1 in the mixed five-field layout (32 bytes per node), E3 in FP64 (40),
-    // then Q2 and Q3 rho' and w
+    // then Q2 and Q3 rho' and w, and over a stratified background theta'
     char *const R1 = mb, *const E3 = mb + 32 * np;
     double *const Q2r = reinterpret_cast<double *>(mb + 72 * np), *const Q3r = reinterpret_cast<double *>(mb + 80 * np);
     double *const Q2w = reinterpret_cast<double *>(mb + 88 * np), *const Q3w = reinterpret_cast<double *>(mb + 96 * np);
+    const bool strat = stratified(c);
+    double *const Q2t = strat ? reinterpret_cast<double *>(mb + 104 * np) : nullptr;
+    double *const Q3t = strat ? reinterpret_cast<double *>(mb + 112 * np) : nullptr;
     auto fld = [&](char *buf, int f) { return buf + (buf == E3 ? size_t(8) * f * np : mixed_field_offset(f, np)); };
     double *const ACC = stage_buffers(c).ACC;
     const double *qr = q + 0 * np, *qw = q + 3 * np, *qt = q + 4 * np;
@@ -1716,6 +1788,10 @@ hipError_t launch_hevi_step_mixed_in(numa_ctx *c, double *q, double dt, char *mb
         p.bw[0] = qw; p.cbw[0] = 1.0;
         p.out_r = Q2r;
         p.out_w = Q2w;
+        if (strat) {
+            p.bt[0] = qt; p.cbt[0] = 1.0; p.bt[1] = fld(R1, 4); p.cbt[1] = f;
+            p.out_t = Q2t;
+        }
         e = dispatch(c->N, [&](auto n) { return solve_launch<decltype(n)::value, ShapeStage2>(c, p); });
         if (e != hipSuccess || (e = mark(2)) != hipSuccess) return e;
     }
@@ -1724,6 +1800,10 @@ hipError_t launch_hevi_step_mixed_in(numa_ctx *c, double *q, double dt, char *mb
         p.a[0] = Q2r;
         p.a[3] = Q2w;
         p.cb = f;
+        if (strat) {
+            p.theta_in = 1;
+            p.a[4] = Q2t;
+        }
         p.out0 = E3;
         p.out1 = ACC;
         p.e0 = q;
@@ -1744,6 +1824,11 @@ hipError_t launch_hevi_step_mixed_in(numa_ctx *c, double *q, double dt, char *mb
         p.bw[0] = qw; p.cbw[0] = -t.c31; p.bw[1] = Q2w; p.cbw[1] = -t.c32;
         p.out_r = Q3r;
         p.out_w = Q3w;
+        if (strat) {
+            p.ct[1] = t.c31; p.et[2] = Q2t; p.ct[2] = t.c32;
+            p.bt[0] = fld(E3, 4); p.cbt[0] = 1.0;
+            p.out_t = Q3t;
+        }
         e = dispatch(c->N, [&](auto n) { return solve_launch<decltype(n)::value, ShapeStage3>(c, p); });
         if (e != hipSuccess || (e = mark(4)) != hipSuccess) return e;
     }
@@ -1753,7 +1838,7 @@ hipError_t launch_hevi_step_mixed_in(numa_ctx *c, double *q, double dt, char *mb
         p.a[1] = fld(E3, 1);
         p.a[2] = fld(E3, 2);
         p.a[3] = Q3w;
-        p.a[4] = fld(E3, 4);
+        p.a[4] = strat ? static_cast<const void *>(Q3t) : fld(E3, 4);
         p.out0 = q;
         p.e0 = ACC;
         p.fs = np;

@@ -24,7 +24,20 @@ struct HostOps {
     std::vector<double> dzb;    // [nz][2N+1] column DSS derivative band (offsets -N..N)
     std::vector<double> zk;     // level heights, nz
     std::vector<double> rho0;   // nz
+    std::vector<double> th0;    // theta0 per level, nz
+    std::vector<double> th0z;   // d theta0/dz per level, nz
 };
+
+// Exner function of the hydrostatic background at height z: d pi0/dz =
+// -g/(cp theta0(z)), pi0(0) = 1, with theta0(z) = theta0 exp(nbv^2 z/g)
+// (theta0 constant for nbv = 0), in closed form.
+double exner_at(double theta0, double cp, double grav, double nbv, double z);
+
+// per-level coefficients of the column solve, [nz][SC_N]: G0, H0, rho0;
+// w_a = AI w_e + WA theta_e; LG = lambda G0; w~ = w_a - (X1 Dz P + X2 P);
+// the stratified terms HZ = lambda H0 d theta0/dz (Schur right-hand side and
+// matrix) and TZ = lambda d theta0/dz (theta' extraction)
+enum { SC_G0 = 0, SC_H0, SC_RHO0, SC_WA, SC_LG, SC_X1, SC_X2, SC_AI, SC_HZ, SC_TZ, SC_N = 12 };
 
 // Per-level background on the device (P0, G0, H0 are evaluated on the device
 // with the same equation-of-state code as the right-hand side, so that the
@@ -32,7 +45,8 @@ struct HostOps {
 struct DevLevels {
     double *rho0 = nullptr, *P0 = nullptr, *G0 = nullptr, *H0 = nullptr;
     double *dzb = nullptr, *zsc = nullptr, *wxy = nullptr, *D = nullptr;
-    double *scf = nullptr;  // [nz][8] column-solve coefficients at the factored lambda
+    double *scf = nullptr;  // [nz][SC_N] column-solve coefficients at the factored lambda
+    double *th0 = nullptr, *th0z = nullptr;  // theta0 and d theta0/dz per level
 };
 
 // Binomial series (1 + x)^gamma - 1 = sum_k C(gamma, k) x^k, used for the
@@ -59,6 +73,7 @@ struct numa_ctx {
     double lx = 0, ly = 0, lz = 0;
     numa::EOS eos{};
     double cp = 0;
+    double nbv = 0;                // background Brunt-Vaisala frequency (0: isentropic)
     hipStream_t stream = nullptr;
     int device = 0;                // the device current at numa_setup
     numa::HostOps ops;
@@ -90,7 +105,12 @@ void build_ops(numa_ctx *c, const double *zface);
 // kernels.hip: launchers return hipSuccess or the launch error.
 struct StageBuffers {
     double *R1, *Q2r, *Q2w, *E3, *ACC, *Q3r, *Q3w;  // R1/E3/ACC: 5 fields each
+    double *Q2t, *Q3t;                              // theta' of Q2, Q3 (stratified background)
 };
+constexpr int kStageFields = 21;  // fields of the stage buffers (c->work)
+
+// a background with a buoyancy frequency: the column solves change theta'
+inline bool stratified(const numa_ctx *c) { return c->nbv > 0.0; }
 StageBuffers stage_buffers(numa_ctx *c);
 
 // LDS per CU on gfx950, and what one workgroup of the kernels needs
@@ -109,8 +129,10 @@ hipError_t launch_rhs_two(numa_ctx *c, const double *Q, const double *e0, const 
                           double *out1, double k01, double k02, double k11, double k12);
 hipError_t launch_rhs_final(numa_ctx *c, const double *Q, const double *e0, double *out, double k);
 hipError_t launch_hevi_step(numa_ctx *c, double *q, double dt, hipEvent_t *ev = nullptr);
-// the precision form's stage buffers: bytes per unique node
+// the precision form's stage buffers: bytes per unique node (16 more over a
+// stratified background, for theta' of Q2 and Q3)
 constexpr size_t kMixedBytesPerNode = 104;
+inline size_t mixed_bytes_per_node(const numa_ctx *c) { return kMixedBytesPerNode + (stratified(c) ? 16 : 0); }
 hipError_t launch_hevi_step_mixed(numa_ctx *c, double *q, double dt, hipEvent_t *ev = nullptr);
 // the same with the stage buffers at mb (kMixedBytesPerNode * np bytes)
 hipError_t launch_hevi_step_mixed_in(numa_ctx *c, double *q, double dt, char *mb, hipEvent_t *ev = nullptr);

@@ -164,16 +164,33 @@ void build_ops(numa_ctx *c, const double *zface)
         }
     }
 
-    // level heights and background density (isentropic, hydrostatic)
+    // level heights and the hydrostatic background: theta0(z), its vertical
+    // derivative, and rho0 = p00 pi0^(cv/R) / (R theta0) from the Exner
+    // function (P0 = EOS(rho0, theta0) follows on the device)
     o.zk.assign(nz, 0.0);
     for (int e = 0; e < c->nez; ++e)
         for (int cc = 0; cc <= N; ++cc) o.zk[e * N + cc] = zf[e] + 0.5 * (o.xi[cc] + 1.0) * hz[e];
     o.rho0.assign(nz, 0.0);
+    o.th0.assign(nz, 0.0);
+    o.th0z.assign(nz, 0.0);
     const double cv = c->cp - c->eos.rgas;
+    const double S = c->nbv > 0.0 ? c->nbv * c->nbv / c->eos.grav : 0.0;  // (1/theta0) d theta0/dz
     for (int k = 0; k < nz; ++k) {
-        double exner = 1.0 - c->eos.grav * o.zk[k] / (c->cp * c->eos.theta0);
-        o.rho0[k] = c->eos.p00 * std::pow(exner, cv / c->eos.rgas) / (c->eos.rgas * c->eos.theta0);
+        const double z = o.zk[k];
+        const double th = S > 0.0 ? c->eos.theta0 * std::exp(S * z) : c->eos.theta0;
+        const double exner = exner_at(c->eos.theta0, c->cp, c->eos.grav, c->nbv, z);
+        o.th0[k] = th;
+        o.th0z[k] = S * th;
+        o.rho0[k] = c->eos.p00 * std::pow(exner, cv / c->eos.rgas) / (c->eos.rgas * th);
     }
+}
+
+double exner_at(double theta0, double cp, double grav, double nbv, double z)
+{
+    if (!(nbv > 0.0)) return 1.0 - grav * z / (cp * theta0);
+    // theta0(z) = theta0 exp(S z): pi0 = 1 - g (1 - exp(-S z)) / (cp theta0 S)
+    const double S = nbv * nbv / grav;
+    return 1.0 + grav * std::expm1(-S * z) / (cp * theta0 * S);
 }
 
 }  // namespace numa

@@ -42,7 +42,7 @@ class numa_grid(C.Structure):
 
 class numa_background(C.Structure):
     _fields_ = [("theta0", C.c_double), ("p00", C.c_double), ("cp", C.c_double),
-                ("rgas", C.c_double), ("grav", C.c_double)]
+                ("rgas", C.c_double), ("grav", C.c_double), ("nbv", C.c_double)]
 
 
 class numa_info(C.Structure):
@@ -444,7 +444,7 @@ class Context:
         self.grid = grid
         self._g, self._zkeep = make_grid(grid.lx, grid.ly, grid.lz, grid.nex, grid.ney, grid.nez,
                                          grid.zface)
-        self._bg = numa_background(bg.theta0, bg.p00, bg.cp, bg.rgas, bg.grav)
+        self._bg = numa_background(bg.theta0, bg.p00, bg.cp, bg.rgas, bg.grav, getattr(bg, "nbv", 0.0))
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self.ctx = setup(self._g, grid.N, self._bg, stream)

@@ -79,6 +79,7 @@ class Background:
     cp: float = CP
     rgas: float = RGAS
     grav: float = GRAV
+    nbv: float = 0.0  # Brunt-Vaisala frequency [1/s]; 0: isentropic
 
 
 @dataclass
@@ -168,6 +169,24 @@ def _theta_bumps(grid, bumps, stretch):
     return th
 
 
+def hydrostatic_profile(z, bg=None):
+    """theta0(z) and the hydrostatic density at heights z of the background
+    the initial states are built on: theta0 constant (bg.nbv = 0) or
+    theta0 exp(nbv^2 z/g), with d pi/dz = -g/(cp theta0) integrated in
+    closed form and rho = p00 pi^(cv/R)/(R theta0)."""
+    bg = bg or Background()
+    z = np.asarray(z, dtype=np.float64)
+    cv = bg.cp - bg.rgas
+    if bg.nbv > 0.0:
+        S = bg.nbv ** 2 / bg.grav
+        th = bg.theta0 * np.exp(S * z)
+        pi = 1.0 + bg.grav * np.expm1(-S * z) / (bg.cp * bg.theta0 * S)
+    else:
+        th = np.full_like(z, bg.theta0)
+        pi = 1.0 - bg.grav * z / (bg.cp * bg.theta0)
+    return th, bg.p00 * pi ** (cv / bg.rgas) / (bg.rgas * th)
+
+
 def balanced_density(grid, theta_p, bg=None):
     """rho' that keeps the hydrostatic pressure unperturbed for a given theta'.
 
@@ -176,10 +195,8 @@ def balanced_density(grid, theta_p, bg=None):
     """
     bg = bg or Background()
     _, _, z = node_coords(grid)
-    cv = bg.cp - bg.rgas
-    pi = 1.0 - bg.grav * z / (bg.cp * bg.theta0)
-    rho_h = bg.p00 * pi ** (cv / bg.rgas) / (bg.rgas * bg.theta0)
-    return -rho_h[:, None, None] * theta_p / (bg.theta0 + theta_p)
+    th, rho_h = hydrostatic_profile(z, bg)
+    return -rho_h[:, None, None] * theta_p / (th[:, None, None] + theta_p)
 
 
 def make_initial_state(wl: Workload):
@@ -310,6 +327,21 @@ def box_precision(size="small", reading="R1"):
     if size == "small":
         return Workload(f"box4x4x4_N7_{reading}", g, dt, 100, 1, 1, (0.5, 0.5), (250.0, 250.0), stretch=s)
     return Workload(f"box28x28x28_N7_{reading}", g, dt, 100, 3, 8, (0.1, 2.0), (50.0, 200.0), stretch=s)
+
+
+NBV = 0.01  # Brunt-Vaisala frequency of the stratified workloads [1/s]
+
+
+def box_stratified(size="small"):
+    """The stratified-background workloads: the 4x4x4, N=4 box of
+    box_small('R1') ('small') or the 64x64x10, N=4 box of box_large('R1')
+    ('large') over theta0(z) = 300 K exp(Nb^2 z/g) with Nb = 0.01/s (a
+    typical tropospheric stratification), same bumps, dt and steps."""
+    wl = box_small("R1") if size == "small" else box_large("R1")
+    bg = Background(nbv=NBV)
+    name = wl.name.replace("_R1", "_strat")
+    return Workload(name, wl.grid, wl.dt, wl.nsteps, wl.seed, wl.nbumps, wl.amp, wl.radius,
+                    stretch=wl.stretch, background=bg, wind=wl.wind)
 
 
 def ensemble_domains(seed=4, n=16):
