@@ -387,10 +387,11 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
     const double *cwxd = swd + ax * NS;
     const double *cwyd = swd + (N + ay) * NS;
 
-    // the N new planes above level kbase into their ring slots: every load of
-    // every item is issued before the first is used (no item branches)
-    auto load_planes = [&](int kbase) {
-        double v[G::NITEM][5];
+    // the N new planes above level kbase into their ring slots, in two parts:
+    // issue (every global load of every item, into registers, no item
+    // branches) and commit (P' and the LDS stores)
+    constexpr int NV = HASB ? 8 : 5;
+    auto issue_planes = [&](int kbase, double (*v)[NV]) {
 #pragma unroll
         for (int s = 0; s < G::NITEM; ++s) {
             const unsigned off = unsigned(kbase + it_p[s]) * pbytes + it_o[s];
@@ -399,14 +400,20 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
                 v[s][f] = HASB && (f == 1 || f == 2) ? FiveField<false>::load(p.e0, f, p.fs, off)
                                                      : TA::load1(p.a[f], f, off);
             v[s][4] = HASB && !p.theta_in ? FiveField<false>::load(p.e0, 4, p.fs, off) : TA::load1(p.a[4], 4, off);
+            if constexpr (HASB) {
+                v[s][5 % NV] = TE1::load(p.e1, 1, p.fs, off);
+                v[s][6 % NV] = TE1::load(p.e1, 2, p.fs, off);
+                v[s][7 % NV] = p.theta_in ? 0.0 : TE1::load(p.e1, 4, p.fs, off);
+            }
         }
+    };
+    auto commit_planes = [&](int kbase, double (*v)[NV]) {
         if constexpr (HASB) {
 #pragma unroll
             for (int s = 0; s < G::NITEM; ++s) {
-                const unsigned off = unsigned(kbase + it_p[s]) * pbytes + it_o[s];
-                v[s][1] += p.cb * TE1::load(p.e1, 1, p.fs, off);
-                v[s][2] += p.cb * TE1::load(p.e1, 2, p.fs, off);
-                if (!p.theta_in) v[s][4] += p.cb * TE1::load(p.e1, 4, p.fs, off);
+                v[s][1] += p.cb * v[s][5 % NV];
+                v[s][2] += p.cb * v[s][6 % NV];
+                if (!p.theta_in) v[s][4] += p.cb * v[s][7 % NV];
             }
         }
 #pragma unroll
@@ -426,6 +433,11 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
             }
         }
     };
+    // The first right-hand side (no epilogue inputs, fewest live registers)
+    // issues the next element's plane loads before computing the current
+    // element, so that they are in flight during its stencils; the others
+    // would spill the registers that needs.
+    constexpr bool PREFETCH = EPI == EPI_R;
 
     // sum_n D[r][n] g(level ez*N + n) over the own column for the six
     // z-differentiated quantities rho w, u, v, w, theta' (out) and P' (outp)
@@ -633,10 +645,21 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 
         zb[5 * (TX * TY)] = st * acc[5];
     }
 
+    double vpre[G::NITEM][NV];
+    if constexpr (PREFETCH) issue_planes(ez0 * N, vpre);
     for (int ez = ez0; ez < ez1; ++ez) {
         __syncthreads();  // the slots about to be overwritten are no longer read
-        load_planes(ez * N);
+        if constexpr (PREFETCH) {
+            commit_planes(ez * N, vpre);
+        } else {
+            double v[G::NITEM][NV];
+            issue_planes(ez * N, v);
+            commit_planes(ez * N, v);
+        }
         __syncthreads();
+        if constexpr (PREFETCH) {
+            if (ez + 1 < ez1) issue_planes((ez + 1) * N, vpre);
+        }
         double ev[NEPI];
         epi_load(unsigned(ez * N + c) * pbytes + own, ev);
         C dz[5], sum[5];
