@@ -111,6 +111,29 @@ int numa_get_info(const numa_ctx *c, numa_info *info);
 int numa_set_stream(numa_ctx *c, void *hip_stream);
 
 /*
+ * Launch configuration of the right-hand sides (Sec. 5.1: the volume kernel
+ * over element tiles), a project autotuner on top of the paper's method.
+ * The right-hand-side kernel is compiled for two tile shapes per order (TX x
+ * TY columns per workgroup, element aligned; one shape at N = 8) and runs
+ * over a vertical chunk of zchunk elements per workgroup.
+ * numa_autotune: times the three right-hand sides of a step on state
+ * (device, state contract; read only, outputs into the context's stage
+ * buffers) for every tile that fits one CU's LDS and every chunk nez,
+ * nez/2, nez/3, ..., 1, `reps` launches each, and keeps the fastest pair for
+ * the context; config_out (host, nullable, 4 ints) as numa_get_rhs_config.
+ * Synchronous.  The step's results do not depend on the configuration.  The
+ * precision form uses the chosen chunk with the first tile.
+ * numa_set_rhs_config: tile 0 (the default shape) or 1, zchunk 0 (automatic:
+ * the largest chunk that still gives two workgroups per CU) or 1..nez.
+ * numa_get_rhs_config: out[4] (host) = {tile, TX, TY, zchunk in use}.
+ * Errors: NUMA_E_ARG, NUMA_E_UNSUPPORTED (tile 1 where the order has one
+ * shape or its LDS does not fit), NUMA_E_HIP.
+ */
+int numa_autotune(numa_ctx *c, const double *state, int32_t reps, int32_t *config_out);
+int numa_set_rhs_config(numa_ctx *c, int32_t tile, int32_t zchunk);
+int numa_get_rhs_config(const numa_ctx *c, int32_t *out);
+
+/*
  * Build and LU-factor, once per time-step size, the matrix of every vertical
  * column of the Schur-complement system of the implicit stages (Sec. 3.1,
  * Eqs. (14)-(17), restricted to the vertical; Sec. 5.4: block-diagonal by
@@ -222,10 +245,9 @@ int numa_profile_steps_mixed(numa_ctx *c, double *state, double dt, int32_t nste
  * its own branch, so that domains too small to fill the GPU run side by
  * side and a step costs one graph launch.  mixed != 0 captures the
  * precision form (numa_hevi_step_mixed) instead of the FP64 step.
- * tune != 0 runs the autotuner first: for every domain it times the
- * right-hand side for each vertical chunk (elements per workgroup in the z
- * march: nez, nez/2, ..., 1) on the domain's state (read only) and keeps
- * the fastest for that context.  States and dts are fixed at creation (the
+ * tune != 0 runs the autotuner of numa_autotune on every domain's state
+ * first (tile shape and vertical chunk per context; numa_get_rhs_config
+ * reports them).  States and dts are fixed at creation (the
  * graph holds them); the contexts must not be destroyed or refactored while
  * the ensemble lives.  hip_stream: the stream the graph is launched on
  * (NULL: the ensemble creates one).  Creation synchronises the contexts'

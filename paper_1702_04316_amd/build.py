@@ -14,7 +14,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnuma_hevi.so")
-SOURCES = ["abi.cpp", "setup.cpp", "ensemble.cpp", "kernels.hip", "imex3d.hip", "learned.hip", "colstd.hip"]
+SOURCES = ["abi.cpp", "setup.cpp", "ensemble.cpp", "kernels.hip", "rhs_alt.hip", "imex3d.hip", "learned.hip",
+           "colstd.hip"]
 ARCH = "gfx950"
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -260,6 +260,43 @@ int numa_set_column_solver(numa_ctx *c, int32_t kind)
     return NUMA_OK;
 }
 
+int numa_autotune(numa_ctx *c, const double *state, int32_t reps, int32_t *config_out)
+{
+    if (!c) return NUMA_E_ARG;
+    if (!state || reps < 1 || reps > 1000) return fail(c, NUMA_E_ARG, "numa_autotune: null state or reps outside 1..1000");
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = numa::autotune_rhs(c, state, reps, nullptr, nullptr);
+    if (e != hipSuccess) return hip_fail(c, e, "numa_autotune");
+    return config_out ? numa_get_rhs_config(c, config_out) : NUMA_OK;
+}
+
+int numa_set_rhs_config(numa_ctx *c, int32_t tile, int32_t zchunk)
+{
+    if (!c) return NUMA_E_ARG;
+    if (tile < 0 || tile > 1 || zchunk < 0 || zchunk > c->nez)
+        return fail(c, NUMA_E_ARG, "numa_set_rhs_config: tile must be 0 or 1 and zchunk in 0..nez");
+    if (tile == 1) {
+        const int zc = zchunk > 0 ? zchunk : 1;
+        if (!numa::rhs_alt_differs(c->N) || numa::rhs_lds_alt(c->N, zc, c->nez) > numa::kLdsPerCU)
+            return fail(c, NUMA_E_UNSUPPORTED, "numa_set_rhs_config: no second tile for this order or column");
+    }
+    c->rhs_tile = tile;
+    c->rhs_zchunk = zchunk;
+    return NUMA_OK;
+}
+
+int numa_get_rhs_config(const numa_ctx *c, int32_t *out)
+{
+    if (!c || !out) return NUMA_E_ARG;
+    int tx = 0;
+    const int ty = numa::rhs_tile_shape(c->N, c->rhs_tile, &tx);
+    out[0] = c->rhs_tile;
+    out[1] = tx;
+    out[2] = ty;
+    out[3] = numa::rhs_zchunk_in_use(c);
+    return NUMA_OK;
+}
+
 int numa_factor_columns(numa_ctx *c, double dt)
 {
     if (!c) return NUMA_E_ARG;

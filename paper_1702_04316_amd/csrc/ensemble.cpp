@@ -127,7 +127,7 @@ int numa_ensemble_create(numa_ctx *const *ctxs, double *const *states, const dou
     // every domain's pending work (set-up, factors) done before tuning and capture
     for (int32_t i = 0; i < n && h == hipSuccess; ++i) h = hipStreamSynchronize(ctxs[i]->stream);
     for (int32_t i = 0; i < n && h == hipSuccess; ++i) {
-        if (tune) h = numa::autotune_rhs_zchunk(ctxs[i], states[i], 3, &e->zchunk[i]);
+        if (tune) h = numa::autotune_rhs(ctxs[i], states[i], 3, &e->zchunk[i], nullptr);
         if (h == hipSuccess) h = numa::prepare_step(ctxs[i], e->mixed != 0);
         if (h == hipSuccess) h = hipStreamSynchronize(ctxs[i]->stream);
         if (!tune) e->zchunk[i] = ctxs[i]->rhs_zchunk;

@@ -22,685 +22,9 @@
 #include <vector>
 
 #include "numa_internal.h"
+#include "rhs_kernel.h"
 
 namespace numa {
-
-// ---------------------------------------------------------------------------
-// Right-hand-side kernel.  A workgroup owns a TX x TY tile of columns
-// (element aligned) and marches upwards through a chunk of vertical
-// elements.  For element ez its TX*TY*N threads compute the N owned levels
-// ez*N + c (c = 0..N-1, c slowest in the thread index, so a wavefront shares
-// c).  The N+1 levels of the element sit in an LDS ring of planes (level k in
-// slot k mod (N+1)); each plane holds the tile plus the halo the DSS line
-// operators need (N nodes below, 1 node above, in x and in y).
-// ---------------------------------------------------------------------------
-template <int N>
-struct Tile;
-//                     TX  TY      threads   LDS (ring of N+1 planes, 6 fields)
-template <> struct Tile<1> { static constexpr int TX = 32, TY = 16; };
-template <> struct Tile<2> { static constexpr int TX = 32, TY = 8; };
-template <> struct Tile<3> { static constexpr int TX = 24, TY = 6; };
-template <> struct Tile<4> { static constexpr int TX = 16, TY = 8; };
-template <> struct Tile<5> { static constexpr int TX = 15, TY = 5; };
-template <> struct Tile<6> { static constexpr int TX = 12, TY = 6; };
-template <> struct Tile<7> { static constexpr int TX = 14, TY = 7; };
-template <> struct Tile<8> { static constexpr int TX = 8, TY = 8; };
-
-template <int N, int ES = 8>  // ES: bytes of an LDS ring element (8 FP64, 4 FP32)
-struct RhsGeom {
-    static constexpr int TX = Tile<N>::TX, TY = Tile<N>::TY;
-    static constexpr int NT = TX * TY * N;          // threads
-    static constexpr int LX = TX + N + 1;           // plane incl. halo
-    static constexpr int LY = TY + N + 1;
-    static constexpr int FS = LX * LY;              // one field of one plane
-    // a plane: rho', u, v, w, theta' (ES bytes each), then P' in FP64 (the
-    // pressure and its derivatives stay FP64 in every form), and with FP32
-    // fields FP64 copies of rho' and w for the buoyancy, the mass flux and
-    // w's tendency
-    static constexpr int POFF = (5 * FS * ES + 7) / 8 * 8;  // byte offset of P'
-    static constexpr int ROFF = POFF + 8 * FS;               // byte offset of the FP64 rho' (ES = 4)
-    static constexpr int WOFF = ROFF + 8 * FS;               // byte offset of the FP64 w (ES = 4)
-    static constexpr int PB = ES == 8 ? ROFF : WOFF + 8 * FS; // bytes of a plane
-    static constexpr int NS = 2 * N + 1;            // x/y stencil width
-    // cross-shaped part of a plane that is loaded: tile rows with the x halo,
-    // plus the y-halo rows of the tile columns
-    static constexpr int NCROSS = TY * LX + TX * (N + 1);
-    static constexpr int NITEM = (N * NCROSS + NT - 1) / NT;  // plane loads per thread
-    static constexpr size_t LDS = size_t(N + 1) * PB;
-    // waves per SIMD to compile for: two workgroups per CU where LDS allows
-    static constexpr int MINW = (NT <= 512 && 2 * LDS <= 150 * 1024) ? 2 * (NT / 256) : 1;
-};
-
-// device equation of state: P = p00 (rho R theta / p00)^gamma (Eq. (10))
-__device__ __forceinline__ double eos_pressure(double rho, double theta, const EOS &e)
-{
-    return e.p00 * pow(rho * e.rgas * theta / e.p00, e.gamma);
-}
-
-// P' = EOS(rho0 + rho', theta0 + theta') - P0 evaluated as
-// P0 [((rho theta)/(rho0 theta0))^gamma - 1]: with rho theta - rho0 theta0 =
-// rho0 theta' + theta0 rho' + rho' theta' no two ~1e5 Pa numbers are
-// subtracted, so P' keeps its own relative precision.
-// rho0 theta', theta0 rho' and rho' theta' nearly cancel in a balanced state:
-// each product is split into rounded value + exact error (fma), so their
-// small sum keeps its relative precision (no contraction may touch this).
-// With x = (rho theta - rho0 theta0)/(rho0 theta0), P' = P0 ((1 + x)^gamma - 1):
-// a 10-term binomial series for |x| <= 1/32 (every state of a weather
-// perturbation; the first omitted term is below 1e-18 relative), log1p/expm1
-// beyond.
-// (1 + x)^gamma - 1 for |x| beyond the series range.  Out of line: inlined,
-// the compiler keeps the constants of log1p and expm1 in vector registers
-// across the stencil loops, for a path that weather states do not take.
-__device__ __noinline__ double binom_power_m1(double x, double gamma) { return expm1(gamma * log1p(x)); }
-
-// r0, t0, P0: rho0, theta0, P0 of the level; irt = 1/(rho0 theta0).
-__device__ __forceinline__ double pressure_perturbation(double rp, double th, double r0, double P0, double irt,
-                                                        double t0, const EOS &e)
-{
-#pragma clang fp contract(off)
-    const double p1 = r0 * th, p2 = t0 * rp, p3 = rp * th;
-    const double e1 = __builtin_fma(r0, th, -p1), e2 = __builtin_fma(t0, rp, -p2), e3 = __builtin_fma(rp, th, -p3);
-    const double d = ((p1 + p2) + p3) + ((e1 + e2) + e3);
-    const double x = d * irt;
-    if (fabs(x) > kBinomMaxX) return P0 * binom_power_m1(x, e.gamma);
-    // (1 + x)^gamma - 1 by its binomial series, Horner form
-    double s = e.binom[kBinomTerms - 1];
-#pragma unroll
-    for (int k = kBinomTerms - 2; k >= 0; --k) s = __builtin_fma(s, x, e.binom[k]);
-    return P0 * (s * x);
-}
-
-// Global access as (uniform 64-bit base) + (32-bit per-lane byte offset):
-// compiles to global_load/store with a scalar base address, so a field needs
-// two scalar registers whatever the number of lanes and levels.  NT: the
-// FP64 store is non-temporal, chosen for large fields (nontemporal_stores).
-// It is a template argument: a runtime choice between two otherwise equal
-// stores is merged by the compiler, which drops the hint.
-__device__ __forceinline__ double gload(const double *base, unsigned off)
-{
-    return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(base) + off);
-}
-template <bool NT = false>
-__device__ __forceinline__ void gstore(double *base, unsigned off, double v)
-{
-    double *a = reinterpret_cast<double *>(reinterpret_cast<char *>(base) + off);
-    if constexpr (NT) __builtin_nontemporal_store(v, a);
-    else *a = v;
-}
-
-// The same for a field of element type T, with off the offset an FP64 field
-// would have (an FP32 field is addressed at off / 2).
-template <class T>
-__device__ __forceinline__ double tload(const void *base, unsigned off)
-{
-    if constexpr (sizeof(T) == 8) return gload(static_cast<const double *>(base), off);
-    else return double(*reinterpret_cast<const float *>(static_cast<const char *>(base) + (off >> 1)));
-}
-template <class T, bool NT = false>
-__device__ __forceinline__ void tstore(void *base, unsigned off, double v)
-{
-    if constexpr (sizeof(T) == 8) gstore<NT>(static_cast<double *>(base), off, v);
-    else *reinterpret_cast<float *>(static_cast<char *>(base) + (off >> 1)) = float(v);  // (non-temporal was slower)
-}
-// field f of a five-field buffer of element type T, field stride fs elements
-template <class T>
-__device__ __forceinline__ const void *field(const void *base, int f, long fs)
-{
-    return static_cast<const T *>(base) + f * fs;
-}
-template <class T>
-__device__ __forceinline__ void *field(void *base, int f, long fs)
-{
-    return static_cast<T *>(base) + f * fs;
-}
-
-struct RhsParams {
-    // input fields (rho', u, v, w, theta'); with HASB, u, v, theta' of the
-    // input are e0 + cb * e1 (a[1], a[2], a[4] unused), except theta' when
-    // theta_in is set (a[4]: the stage value the column solve wrote over a
-    // stratified background)
-    const void *a[5];
-    double cb;
-    int theta_in;
-    // five-field buffers (field f at + f * fs): out0 = e0 + k01 e1 + k02 R,
-    // out1 = e0 + k11 e1 + k12 R
-    void *out0, *out1;
-    const void *e0, *e1;
-    long fs;
-    double k01, k02, k11, k12;
-    const double *rho0, *P0, *zsc, *wxy, *D;
-    const double *th0, *th0z;  // theta0 and d theta0/dz per level
-    EOS eos;
-    int nx, ny, nz, nez, zchunk, nchunk, ntx, nty;
-    int *flag;
-};
-
-enum { EPI_R = 0, EPI_TWO = 1, EPI_FINAL = 2 };
-
-// Layout of a five-field stage buffer of np nodes: all FP64, or (M) the
-// precision form's R1 with u and v in FP32 and rho', w, theta' in FP64.  The
-// pressure perturbation P0 ((1+x)^gamma - 1) scales the relative rounding of
-// rho' and theta' by P0, so their stage values stay FP64; w's tendency holds
-// the stiff vertical pressure gradient and buoyancy, whose FP32 rounding,
-// multiplied by the vertical Courant number, reached 2e-6 relative in w
-// after 100 steps, so w stays FP64 too.  Byte offsets of the fields per
-// node: 0, 8, 16, 24, 32 (FP64) or 0, 8, 12, 16, 24 (M).
-// Offsets passed in are those an FP64 field would have.
-template <bool M>
-struct FiveField {
-    static __device__ __forceinline__ bool f32(int f) { return M && (f == 1 || f == 2); }
-    static __device__ __forceinline__ size_t ofs(int f, long np)
-    {
-        return M ? size_t(np) * size_t(f == 0 ? 0 : (f == 1 ? 8 : (f == 2 ? 12 : 8 * f - 8))) : size_t(np) * 8 * size_t(f);
-    }
-    // field f stored alone at p
-    static __device__ __forceinline__ double load1(const void *p, int f, unsigned off)
-    {
-        return f32(f) ? tload<float>(p, off) : tload<double>(p, off);
-    }
-    static __device__ __forceinline__ double load(const void *buf, int f, long np, unsigned off)
-    {
-        return load1(static_cast<const char *>(buf) + ofs(f, np), f, off);
-    }
-    template <bool NT>
-    static __device__ __forceinline__ void store(void *buf, int f, long np, unsigned off, double v)
-    {
-        void *p = static_cast<char *>(buf) + ofs(f, np);
-        if (f32(f)) tstore<float>(p, off, v);
-        else tstore<double, NT>(p, off, v);
-    }
-};
-
-// Buffers of one right-hand-side launch.  The FP64 step keeps every field
-// in FP64.  The precision form (MIX) keeps the state q and the accumulator
-// ACC (e0 of the last two launches, out1) in FP64, its other stage buffers
-// in the mixed layout, and the LDS ring (except P' and FP64 copies of rho'
-// and w) and the stencil arithmetic in FP32.  FP64 in that form: P' and its
-// derivatives, w with its derivatives and tendency, and the mass flux
-// (rho0 + rho') u_i with its divergence.  The flux divergence is a small
-// difference of large terms at the finest LGL spacing, and its FP32
-// rounding, carried through rho' into the buoyancy, left 2.5e-6 relative
-// error in w after 100 steps at N = 7; FP32 derivatives of w under a strong
-// wind left 2e-6 after 50 steps at N = 3.
-template <int EPI, bool MIX>
-struct RhsTypes {
-    using A = FiveField<false>;                     // inputs a[]
-    using E1 = FiveField<MIX>;                      // e1 (R1)
-    using O0 = FiveField<MIX && EPI == EPI_R>;      // out0 (R1 in the first launch)
-    using D = FiveField<false>;                     // e0, out1
-    using C = std::conditional_t<MIX, float, double>;
-};
-
-// Map the launch index to a tile so that each of the 8 XCDs (which receive
-// workgroups round-robin) works on a contiguous band of tiles and shares the
-// halo rows in its own L2.
-__device__ __forceinline__ int xcd_remap(int b, int nb)
-{
-    int q = nb >> 3, r = nb & 7;
-    int x = b & 7, s = b >> 3;
-    return x < r ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
-}
-
-// Stage input of field f at offset off.
-template <bool HASB, class TA, class TE1>
-__device__ __forceinline__ double stage_input(const RhsParams &p, int f, unsigned off)
-{
-    if constexpr (HASB) {
-        if (f == 1 || f == 2 || (f == 4 && !p.theta_in))
-            return FiveField<false>::load(p.e0, f, p.fs, off) + p.cb * TE1::load(p.e1, f, p.fs, off);
-    }
-    return TA::load1(p.a[f], f, off);
-}
-
-template <int N, int EPI, bool HASB, bool MIX, bool NT = false>
-__global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8>::NT), (RhsGeom<N, MIX ? 4 : 8>::MINW)) void k_rhs(RhsParams p)
-{
-    using TT = RhsTypes<EPI, MIX>;
-    using TA = typename TT::A;
-    using TE1 = typename TT::E1;
-    using TO0 = typename TT::O0;
-    using C = typename TT::C;
-    using G = RhsGeom<N, sizeof(C)>;
-    constexpr int NQ = N + 1, NS = G::NS, TX = G::TX, TY = G::TY, LX = G::LX, FS = G::FS;
-    // dynamic LDS: ring of N+1 planes [rho', u, v, w, theta' (C)][P' (FP64)]
-    // of [LY][LX], then per-level tables rho0, P0, 1/(rho0 theta0), theta0,
-    // d theta0/dz for the
-    // levels this chunk touches, zsc [3][nez], and the interface shares
-    // [2][6][TX*TY] (FP64)
-    extern __shared__ double lds_block[];
-    char *const ringb = reinterpret_cast<char *>(lds_block);
-    auto cfield = [&](int slot) { return reinterpret_cast<C *>(ringb + slot * G::PB); };
-    auto pfield = [&](int slot) { return reinterpret_cast<double *>(ringb + slot * G::PB + G::POFF); };
-    auto rfield = [&](int slot) { return reinterpret_cast<double *>(ringb + slot * G::PB + G::ROFF); };
-    auto wfield = [&](int slot) { return reinterpret_cast<double *>(ringb + slot * G::PB + G::WOFF); };
-    __shared__ C sw[2][N][NS];
-    __shared__ C sD[NQ * NQ];
-    // FP64 copies of the tables for the mass flux of the precision form (the
-    // FP64 form reads sw and sD themselves)
-    __shared__ double swd_m[MIX ? 2 * N * NS : 1];
-    __shared__ double sDd_m[MIX ? NQ * NQ : 1];
-    const double *const swd = [&]() -> const double * {
-        if constexpr (MIX) return swd_m;
-        else return &sw[0][0][0];
-    }();
-    const double *const sDd = [&]() -> const double * {
-        if constexpr (MIX) return sDd_m;
-        else return sD;
-    }();
-
-    const int tid = threadIdx.x;
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int ntile = p.ntx * p.nty;
-    const int chunk = lb / ntile;
-    const int tt = lb - chunk * ntile;
-    const int tyb = tt / p.ntx, txb = tt - tyb * p.ntx;
-    const int x0 = txb * TX, y0 = tyb * TY;
-    const int nx = p.nx, ny = p.ny;
-    const unsigned pbytes = unsigned(nx) * unsigned(ny) * 8u;
-    const int ez0 = chunk * p.zchunk;
-    const int ez1 = min(p.nez, ez0 + p.zchunk);
-    const int kb = max(ez0 - 1, 0) * N;          // lowest level in the tables
-    const int nlev = ez1 * N + 1 - kb;
-    double *sR0 = lds_block + G::LDS / sizeof(double);
-    double *sP0 = sR0 + nlev;
-    double *sIRT = sP0 + nlev;
-    double *sT0 = sIRT + nlev;
-    double *sTZ = sT0 + nlev;
-    double *zs = sTZ + nlev;  // [0,nez): 2/h ; [nez,2nez): bottom factor ; [2nez,3nez): top factor
-    // the lower element's share of the six z-derivatives at the interface
-    // node of each column, double-buffered by element parity: [2][6][TX*TY]
-    double *zp = zs + 3 * p.nez;
-    const EOS eos = p.eos;
-
-    for (int s = tid; s < 2 * N * NS; s += G::NT) {
-        (&sw[0][0][0])[s] = C(p.wxy[s]);
-        if constexpr (MIX) swd_m[s] = p.wxy[s];
-    }
-    for (int s = tid; s < NQ * NQ; s += G::NT) {
-        sD[s] = C(p.D[s]);
-        if constexpr (MIX) sDd_m[s] = p.D[s];
-    }
-    for (int s = tid; s < nlev; s += G::NT) {
-        const double r0 = p.rho0[kb + s];
-        const double t0 = p.th0[kb + s];
-        sR0[s] = r0;
-        sP0[s] = p.P0[kb + s];
-        sIRT[s] = 1.0 / (r0 * t0);
-        sT0[s] = t0;
-        sTZ[s] = p.th0z[kb + s];
-    }
-    for (int s = tid; s < 3 * p.nez; s += G::NT) zs[s] = p.zsc[s];
-    // Precision form: the ring holds u - uref and v - vref in FP32, with the
-    // workgroup's reference velocities uref, vref (FP64) taken at the first
-    // node of its tile.  A wind far larger than its variation (a uniform
-    // wind) then keeps its variation's relative precision in the FP32
-    // derivatives, which annihilate the constants; u and v themselves are
-    // uref + (u - uref).  The FP64 form stores u and v as they are.
-    double uref = 0.0, vref = 0.0;
-    if constexpr (MIX) {
-        const unsigned oref = unsigned(ez0 * N) * pbytes + unsigned(y0 * nx + x0) * 8u;
-        uref = stage_input<HASB, TA, TE1>(p, 1, oref);
-        vref = stage_input<HASB, TA, TE1>(p, 2, oref);
-    }
-
-    // plane loads of this thread: which of the N new planes (1..N, 0 = none),
-    // LDS offset in the plane, byte offset in a level plane
-    int it_p[G::NITEM], it_l[G::NITEM];
-    unsigned it_o[G::NITEM];
-#pragma unroll
-    for (int s = 0; s < G::NITEM; ++s) {
-        const int item = tid + s * G::NT;
-        const int pl = item / G::NCROSS, q = item - pl * G::NCROSS;
-        int lx, ly;
-        if (q < TY * LX) {
-            ly = N + q / LX;
-            lx = q % LX;
-        } else {
-            const int r = q - TY * LX, hy = r / TX;
-            lx = N + r % TX;
-            ly = hy < N ? hy : TY + N;
-        }
-        int gi = (x0 - N + lx) % nx;
-        if (gi < 0) gi += nx;
-        int gj = (y0 - N + ly) % ny;
-        if (gj < 0) gj += ny;
-        // an item past the N planes reads level + 0 and writes a plane corner
-        // (lx, ly < N), which no stencil reads
-        const bool valid = item < N * G::NCROSS;
-        it_p[s] = valid ? pl + 1 : 0;
-        it_l[s] = valid ? ly * LX + lx : 0;
-        it_o[s] = unsigned(gj * nx + gi) * 8u;
-    }
-
-    const int c = tid / (TX * TY);
-    const int txy = tid - c * (TX * TY);
-    const int ty = txy / TX, tx = txy - ty * TX;
-    const int i = x0 + tx, j = y0 + ty;
-    const bool owner = (i < nx) && (j < ny);
-    const unsigned own = unsigned((j % ny) * nx + (i % nx)) * 8u;
-    const int ax = tx % N, ay = ty % N;
-    const int l_own = (ty + N) * LX + (tx + N);
-    const int l_x = (ty + N) * LX + (tx - ax);
-    const int l_y = (ty - ay) * LX + (tx + N);
-    const C *cwx = &sw[0][0][0] + ax * NS;
-    const C *cwy = &sw[1][0][0] + ay * NS;
-    const double *cwxd = swd + ax * NS;
-    const double *cwyd = swd + (N + ay) * NS;
-
-    // the N new planes above level kbase into their ring slots, in two parts:
-    // issue (every global load of every item, into registers, no item
-    // branches) and commit (P' and the LDS stores)
-    constexpr int NV = HASB ? 8 : 5;
-    auto issue_planes = [&](int kbase, double (*v)[NV]) {
-#pragma unroll
-        for (int s = 0; s < G::NITEM; ++s) {
-            const unsigned off = unsigned(kbase + it_p[s]) * pbytes + it_o[s];
-#pragma unroll
-            for (int f = 0; f < 4; ++f)
-                v[s][f] = HASB && (f == 1 || f == 2) ? FiveField<false>::load(p.e0, f, p.fs, off)
-                                                     : TA::load1(p.a[f], f, off);
-            v[s][4] = HASB && !p.theta_in ? FiveField<false>::load(p.e0, 4, p.fs, off) : TA::load1(p.a[4], 4, off);
-            if constexpr (HASB) {
-                v[s][5 % NV] = TE1::load(p.e1, 1, p.fs, off);
-                v[s][6 % NV] = TE1::load(p.e1, 2, p.fs, off);
-                v[s][7 % NV] = p.theta_in ? 0.0 : TE1::load(p.e1, 4, p.fs, off);
-            }
-        }
-    };
-    auto commit_planes = [&](int kbase, double (*v)[NV]) {
-        if constexpr (HASB) {
-#pragma unroll
-            for (int s = 0; s < G::NITEM; ++s) {
-                v[s][1] += p.cb * v[s][5 % NV];
-                v[s][2] += p.cb * v[s][6 % NV];
-                if (!p.theta_in) v[s][4] += p.cb * v[s][7 % NV];
-            }
-        }
-#pragma unroll
-        for (int s = 0; s < G::NITEM; ++s) {
-            const int k = kbase + it_p[s], kl = k - kb;
-            const double Pp = pressure_perturbation(v[s][0], v[s][4], sR0[kl], sP0[kl], sIRT[kl], sT0[kl], eos);
-            C *d = cfield(k % NQ) + it_l[s];
-            d[0 * FS] = C(v[s][0]);
-            d[1 * FS] = C(v[s][1] - uref);
-            d[2 * FS] = C(v[s][2] - vref);
-            d[3 * FS] = C(v[s][3]);
-            d[4 * FS] = C(v[s][4]);
-            pfield(k % NQ)[it_l[s]] = Pp;
-            if constexpr (MIX) {
-                rfield(k % NQ)[it_l[s]] = v[s][0];
-                wfield(k % NQ)[it_l[s]] = v[s][3];
-            }
-        }
-    };
-    // The first right-hand side (no epilogue inputs, fewest live registers)
-    // issues the next element's plane loads before computing the current
-    // element, so that they are in flight during its stencils; the others
-    // would spill the registers that needs.
-    constexpr bool PREFETCH = EPI == EPI_R;
-
-    // sum_n D[r][n] g(level ez*N + n) over the own column for the six
-    // z-differentiated quantities rho w, u, v, w, theta' (out) and P' (outp)
-    // (not unrolled: unrolled, all 6*(N+1) LDS reads would be in flight at once)
-    auto zsum = [&](int ez, int r, C *out, double &outp, double &outr, double &outw) {
-#pragma unroll
-        for (int f = 0; f < 5; ++f) out[f] = C(0);
-        outp = 0.0;
-        outr = 0.0;
-        outw = 0.0;
-        int k = ez * N, slot = k % NQ;
-#pragma unroll 1
-        for (int n = 0; n < NQ; ++n) {
-            const C *q = cfield(slot) + l_own;
-            const C d = sD[r * NQ + n];
-            if constexpr (MIX) {
-                const double wv = wfield(slot)[l_own], dd = sDd[r * NQ + n];
-                outr += dd * ((sR0[k - kb] + rfield(slot)[l_own]) * wv);
-                outw += dd * wv;
-            } else {
-                outr += double(d) * ((C(sR0[k - kb]) + q[0]) * q[3 * FS]);
-                outw += double(d) * q[3 * FS];
-            }
-            out[1] += d * q[1 * FS];
-            out[2] += d * q[2 * FS];
-            out[4] += d * q[4 * FS];
-            outp += double(d) * pfield(slot)[l_own];
-            ++k;
-            slot = (slot + 1 == NQ) ? 0 : slot + 1;
-        }
-    };
-
-    // epilogue inputs of a node at byte offset off (issued before the node's
-    // z sums and stencils, so that they arrive while those run)
-    constexpr int NEPI = EPI == EPI_TWO ? 10 : (EPI == EPI_FINAL ? 5 : 1);
-    auto epi_load = [&](unsigned off, double *ev) {
-        if constexpr (EPI == EPI_TWO) {
-#pragma unroll
-            for (int f = 0; f < 5; ++f) {
-                ev[f] = FiveField<false>::load(p.e0, f, p.fs, off);
-                ev[5 + f] = TE1::load(p.e1, f, p.fs, off);
-            }
-        } else if constexpr (EPI == EPI_FINAL) {
-#pragma unroll
-            for (int f = 0; f < 5; ++f) ev[f] = FiveField<false>::load(p.e0, f, p.fs, off);
-        }
-    };
-
-    // tendencies at level k (Set2NC, Sec. 3.1) from the x/y line derivatives
-    // of the plane in the ring and the scaled vertical derivatives dz; then
-    // the stage epilogue with its inputs ev
-    auto node = [&](int k, const C *dz, double dzp, double dz0, double dzw, const double *ev) {
-        const C *q = cfield(k % NQ);
-        const double *qp = pfield(k % NQ);
-        const C r0 = C(sR0[k - kb]);
-        const C rp = q[l_own], w = q[3 * FS + l_own];
-        C u = q[FS + l_own], v = q[2 * FS + l_own];
-        if constexpr (MIX) {
-            u = C(uref + double(u));
-            v = C(vref + double(v));
-        }
-        const C ir = C(1) / (r0 + rp);
-        // rho' and 1/rho for the pressure and buoyancy terms: FP64 in every form
-        const double rpd = MIX ? rfield(k % NQ)[l_own] : double(rp);
-        const double irp = MIX ? 1.0 / (sR0[k - kb] + rpd) : double(ir);
-        // the vertical terms first, so that only the tendencies stay live
-        // across the x and y stencils (with few live registers the stencil
-        // loads can be in flight together)
-        C R[5];
-        double R0 = dz0;
-        R[1] = w * dz[1];
-        R[2] = w * dz[2];
-        // w's tendency accumulates in FP64 in every form: it holds the nearly
-        // balanced vertical pressure gradient and buoyancy (in the precision
-        // form only its advection products are FP32)
-        double R3;
-        if constexpr (MIX)
-            R3 = wfield(k % NQ)[l_own] * dzw + (dzp * irp + eos.grav * rpd * irp);
-        else
-            R3 = w * dzw + dzp * ir + eos.grav * rp * ir;
-        // theta': advection of theta' and of the background, w d theta0/dz
-        R[4] = w * dz[4] + w * C(sTZ[k - kb]);
-        // line derivative of the six quantities along x (dir 0) or y (dir 1)
-        // (not unrolled: unrolled, the scheduler hoists all its LDS reads)
-        auto line = [&](int dir, C *d5, double &dp, double &dfl, double &dwl) {
-            const C *cw = dir == 0 ? cwx : cwy;
-            const double *cwd = dir == 0 ? cwxd : cwyd;
-            const double *rq = rfield(k % NQ);
-            const double *wq = wfield(k % NQ);
-            const int base = dir == 0 ? l_x : l_y, step = dir == 0 ? 1 : LX;
-            const int fv = dir == 0 ? FS : 2 * FS;  // the velocity in rho u or rho v
-            const double vr = dir == 0 ? uref : vref;
-#pragma unroll
-            for (int f = 0; f < 5; ++f) d5[f] = C(0);
-            dp = 0.0;
-            dfl = 0.0;
-            dwl = 0.0;
-#pragma unroll 1
-            for (int m = 0; m < NS; ++m) {
-                const C cm = cw[m];
-                const C *qm = q + base + m * step;
-                if constexpr (MIX) dfl += cwd[m] * ((sR0[k - kb] + rq[base + m * step]) * (vr + double(qm[fv])));
-                else dfl += double(cm) * ((r0 + qm[0]) * qm[fv]);
-                d5[1] += cm * qm[1 * FS];
-                d5[2] += cm * qm[2 * FS];
-                if constexpr (MIX) dwl += cwd[m] * wq[base + m * step];
-                else dwl += double(cm) * qm[3 * FS];
-                d5[4] += cm * qm[4 * FS];
-                dp += double(cm) * qp[base + m * step];
-            }
-        };
-        C d5[5];
-        double dp, dfl, dwl;
-        line(0, d5, dp, dfl, dwl);
-        R0 += dfl;
-        R[1] += u * d5[1] + C(dp * irp);
-        R[2] += u * d5[2];
-        R3 += double(u) * dwl;
-        R[4] += u * d5[4];
-        line(1, d5, dp, dfl, dwl);
-        R0 = -(R0 + dfl);
-        R[1] = -(R[1] + v * d5[1]);
-        R[2] = -(R[2] + v * d5[2] + C(dp * irp));
-        R3 = -(R3 + double(v) * dwl);
-        R[4] = -(R[4] + v * d5[4]);
-        if (k == 0 || k == p.nz - 1) R3 = 0.0;
-        if (!owner) return;
-        auto Rv = [&](int f) -> double { return f == 3 ? R3 : (f == 0 ? R0 : double(R[f])); };
-        const unsigned off = unsigned(k) * pbytes + own;
-        if constexpr (EPI == EPI_R) {
-#pragma unroll
-            for (int f = 0; f < 5; ++f) TO0::template store<NT>(p.out0, f, p.fs, off, Rv(f));
-        } else if constexpr (EPI == EPI_TWO) {
-#pragma unroll
-            for (int f = 0; f < 5; ++f) {
-                const double e0 = ev[f], e1 = ev[5 + f], r = Rv(f);
-                TO0::template store<NT>(p.out0, f, p.fs, off, e0 + p.k01 * e1 + p.k02 * r);
-                FiveField<false>::store<NT>(p.out1, f, p.fs, off, e0 + p.k11 * e1 + p.k12 * r);
-            }
-        } else {
-            bool bad = false;
-#pragma unroll
-            for (int f = 0; f < 5; ++f) {
-                const double v2 = ev[f] + p.k02 * Rv(f);
-                bad |= !isfinite(v2);
-                TO0::template store<NT>(p.out0, f, p.fs, off, v2);
-            }
-            if (bad) *p.flag = 1;
-        }
-    };
-
-    __syncthreads();  // tables are in LDS
-
-    // prologue: level ez0*N into the ring (the items of the first new plane
-    // cover one whole plane); the c = 0 threads take the contribution of the
-    // element below to the interface at ez0*N from their own column
-#pragma unroll
-    for (int s = 0; s < G::NITEM; ++s) {
-        if (it_p[s] != 1) continue;
-        const int k = ez0 * N, kl = k - kb;
-        const unsigned off = unsigned(k) * pbytes + it_o[s];
-        const double rp = stage_input<HASB, TA, TE1>(p, 0, off), u = stage_input<HASB, TA, TE1>(p, 1, off);
-        const double v = stage_input<HASB, TA, TE1>(p, 2, off), w = stage_input<HASB, TA, TE1>(p, 3, off);
-        const double th = stage_input<HASB, TA, TE1>(p, 4, off);
-        const double Pp = pressure_perturbation(rp, th, sR0[kl], sP0[kl], sIRT[kl], sT0[kl], eos);
-        C *d = cfield(k % NQ) + it_l[s];
-        d[0 * FS] = C(rp);
-        d[1 * FS] = C(u - uref);
-        d[2 * FS] = C(v - vref);
-        d[3 * FS] = C(w);
-        d[4 * FS] = C(th);
-        pfield(k % NQ)[it_l[s]] = Pp;
-        if constexpr (MIX) {
-            rfield(k % NQ)[it_l[s]] = rp;
-            wfield(k % NQ)[it_l[s]] = w;
-        }
-    }
-    if (c == 0 && ez0 > 0) {
-        const int eb = ez0 - 1;
-        double acc[6] = {0, 0, 0, 0, 0, 0};
-        for (int n = 0; n < NQ; ++n) {
-            const int k = eb * N + n, kl = k - kb;
-            const unsigned off = unsigned(k) * pbytes + own;
-            // rounded to the ring's type first, as the layer loop sees them
-            const double rp = C(stage_input<HASB, TA, TE1>(p, 0, off));
-            const double u = C(stage_input<HASB, TA, TE1>(p, 1, off) - uref);
-            const double v = C(stage_input<HASB, TA, TE1>(p, 2, off) - vref);
-            const double w = stage_input<HASB, TA, TE1>(p, 3, off);  // FP64 in both forms
-            const double th0 = stage_input<HASB, TA, TE1>(p, 4, off), th = C(th0);
-            const double rho = MIX ? sR0[kl] + stage_input<HASB, TA, TE1>(p, 0, off) : double(C(sR0[kl])) + rp;
-            const double Pp = pressure_perturbation(stage_input<HASB, TA, TE1>(p, 0, off), th0, sR0[kl], sP0[kl],
-                                                    sIRT[kl], sT0[kl], eos);
-            const double d = double(sD[N * NQ + n]);
-            acc[0] += d * (rho * w);
-            acc[1] += d * u;
-            acc[2] += d * v;
-            acc[3] += d * w;
-            acc[4] += d * th;
-            acc[5] += d * Pp;
-        }
-        const double st = zs[2 * p.nez + eb];
-        double *zb = zp + (ez0 & 1) * 6 * (TX * TY) + txy;
-#pragma unroll
-        for (int f = 0; f < 5; ++f) zb[f * (TX * TY)] = (f == 0 || f == 3) ? st * acc[f] : double(C(st * acc[f]));
-        zb[5 * (TX * TY)] = st * acc[5];
-    }
-
-    double vpre[G::NITEM][NV];
-    if constexpr (PREFETCH) issue_planes(ez0 * N, vpre);
-    for (int ez = ez0; ez < ez1; ++ez) {
-        __syncthreads();  // the slots about to be overwritten are no longer read
-        if constexpr (PREFETCH) {
-            commit_planes(ez * N, vpre);
-        } else {
-            double v[G::NITEM][NV];
-            issue_planes(ez * N, v);
-            commit_planes(ez * N, v);
-        }
-        __syncthreads();
-        if constexpr (PREFETCH) {
-            if (ez + 1 < ez1) issue_planes((ez + 1) * N, vpre);
-        }
-        double ev[NEPI];
-        epi_load(unsigned(ez * N + c) * pbytes + own, ev);
-        C dz[5], sum[5];
-        double sump, sumr, sumw;
-        zsum(ez, c, sum, sump, sumr, sumw);
-        const double scd = (c == 0) ? zs[p.nez + ez] : zs[ez];
-        const C sc = C(scd);
-        const double *zb = zp + (ez & 1) * 6 * (TX * TY) + txy;
-        const bool below = c == 0 && ez > 0;  // a lower element shares the node
-#pragma unroll
-        for (int f = 0; f < 5; ++f) dz[f] = (below ? C(zb[f * (TX * TY)]) : C(0)) + sc * sum[f];
-        const double dzp = (below ? zb[5 * (TX * TY)] : 0.0) + scd * sump;
-        const double dz0 = (below ? zb[0] : 0.0) + scd * sumr;
-        const double dzw = (below ? zb[3 * (TX * TY)] : 0.0) + scd * sumw;
-        node(ez * N + c, dz, dzp, dz0, dzw, ev);
-        // this element's share of the interface (or top node) above
-        const double st = zs[2 * p.nez + ez];
-        double *zn = zp + ((ez + 1) & 1) * 6 * (TX * TY) + txy;
-        if (c == 0) {
-            C s5[5];
-            double s5p, s5r, s5w;
-            zsum(ez, N, s5, s5p, s5r, s5w);
-#pragma unroll
-            for (int f = 0; f < 5; ++f)
-                zn[f * (TX * TY)] = f == 0 ? st * s5r : (f == 3 ? st * s5w : double(C(st) * s5[f]));
-            zn[5 * (TX * TY)] = st * s5p;
-        }
-    }
-    // top node of the column: one-sided from the top element
-    __syncthreads();  // the shares of the top element are in LDS
-    if (ez1 == p.nez && c == 0) {
-        const double *zb = zp + (ez1 & 1) * 6 * (TX * TY) + txy;
-        C dz[5];
-#pragma unroll
-        for (int f = 0; f < 5; ++f) dz[f] = C(zb[f * (TX * TY)]);
-        const double dzp = zb[5 * (TX * TY)];
-        double ev[NEPI];
-        epi_load(unsigned(p.nez * N) * pbytes + own, ev);
-        node(p.nez * N, dz, dzp, zb[0], zb[3 * (TX * TY)], ev);
-    }
-}
 
 // ---------------------------------------------------------------------------
 // Column solve.  One lane per column, 64 columns per workgroup (one
@@ -1298,43 +622,6 @@ __global__ void k_background(const double *rho0, const double *th0, double *P0, 
 // ---------------------------------------------------------------------------
 namespace {
 
-// dynamic LDS of k_rhs: the ring, three per-level tables of the chunk's
-// levels (zchunk + 1 elements), the element factors, the interface shares
-template <int N, bool MIX = false>
-size_t rhs_lds_bytes(int zchunk, int nez)
-{
-    constexpr int ES = MIX ? 4 : 8;
-    return RhsGeom<N, ES>::LDS +
-           sizeof(double) * (5 * ((zchunk + 1) * N + 1) + 3 * nez + 2 * 6 * RhsGeom<N>::TX * RhsGeom<N>::TY);
-}
-
-template <int N>
-int rhs_zchunk_auto(const numa_ctx *c)
-{
-    if (c->rhs_zchunk > 0) return c->rhs_zchunk;
-    using G = RhsGeom<N>;
-    long tiles = ((c->nx + G::TX - 1) / G::TX) * ((c->ny + G::TY - 1) / G::TY);
-    // enough workgroups for every CU (256) to hold two
-    int zc = c->nez;
-    while (zc > 1 && tiles * ((c->nez + zc - 1) / zc) < 512) zc = (zc + 1) / 2;
-    return zc;
-}
-
-// Opt the kernel into lds bytes of dynamic LDS (needed above 64 KB); done
-// once per size, before the first launch (and before any stream capture).
-template <int N, int EPI, bool HASB, bool MIX, bool NT = false>
-hipError_t rhs_prepare(size_t lds)
-{
-    static size_t attr_set = 0;
-    if (attr_set < lds) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rhs<N, EPI, HASB, MIX, NT>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-        if (e != hipSuccess) return e;
-        attr_set = lds;
-    }
-    return hipSuccess;
-}
-
 template <int N, class SH, bool FL>
 hipError_t solve_prepare_fl(size_t shm)
 {
@@ -1357,53 +644,15 @@ hipError_t solve_prepare(int M)
                             : solve_prepare_fl<N, SH, false>(G::lds_total(M));
 }
 
-// Non-temporal FP64 stores for fields of at least 12 MB at order N <= 4: the
-// largest kernel of such a step touches about 22 fields, more than the
-// 256 MB last-level cache, so the next kernel reads its inputs from HBM
-// whatever the store does.  Below that size the fields a kernel writes can
-// still be in cache when the next kernel reads them.  Measured: on the
-// 2.7M-node N = 4 benchmark grid they cut the stage-2 right-hand side from
-// 132 to 124 us; on the ensemble, whose large domains are N = 5 and 7, they
-// made the step 5 % slower, so higher orders keep ordinary stores.
-constexpr size_t kNontemporalFieldBytes = size_t(12) << 20;
-bool nontemporal_stores(const numa_ctx *c)
-{
-    return c->N <= 4 && size_t(c->np) * sizeof(double) >= kNontemporalFieldBytes;
-}
-
+// k_rhs with the context's tile variant: the second variant serves the FP64
+// step's three right-hand sides; other launches, and the precision form,
+// use the first.
 template <int N, int EPI, bool HASB, bool MIX = false>
 hipError_t rhs_launch(numa_ctx *c, RhsParams p)
 {
-    using G = RhsGeom<N>;
-    p.rho0 = c->lev.rho0;
-    p.P0 = c->lev.P0;
-    p.zsc = c->lev.zsc;
-    p.wxy = c->lev.wxy;
-    p.D = c->lev.D;
-    p.th0 = c->lev.th0;
-    p.th0z = c->lev.th0z;
-    p.eos = c->eos;
-    p.nx = int(c->nx);
-    p.ny = int(c->ny);
-    p.nz = int(c->nz);
-    p.nez = c->nez;
-    p.zchunk = rhs_zchunk_auto<N>(c);
-    p.nchunk = (c->nez + p.zchunk - 1) / p.zchunk;
-    p.ntx = int((c->nx + G::TX - 1) / G::TX);
-    p.nty = int((c->ny + G::TY - 1) / G::TY);
-    p.flag = c->flag;
-    const size_t lds = rhs_lds_bytes<N, MIX>(p.zchunk, p.nez);
-    dim3 grid(unsigned(p.ntx * p.nty * p.nchunk));
-    if (!MIX && nontemporal_stores(c)) {
-        hipError_t e = rhs_prepare<N, EPI, HASB, MIX, true>(lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_rhs<N, EPI, HASB, MIX, true>), grid, dim3(G::NT), lds, c->stream, p);
-    } else {
-        hipError_t e = rhs_prepare<N, EPI, HASB, MIX>(lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_rhs<N, EPI, HASB, MIX>), grid, dim3(G::NT), lds, c->stream, p);
-    }
-    return hipGetLastError();
+    const bool step_kernel = (EPI == EPI_TWO) == HASB;
+    if (!MIX && c->rhs_tile == 1 && step_kernel) return rhs_launch_alt(c, p, EPI);
+    return rhs_launch_t<N, 0, EPI, HASB, MIX>(c, p);
 }
 
 // The eight- and sixteen-wavefront blocked solves of columns above 64 - 2N
@@ -1918,25 +1167,14 @@ hipError_t prepare_step(numa_ctx *c, bool mixed)
 {
     return dispatch(c->N, [&](auto n) -> hipError_t {
         constexpr int NN = decltype(n)::value;
-        const int zc = c->rhs_zchunk > 0 ? c->rhs_zchunk : rhs_zchunk_auto<NN>(c);
-        const int nez = c->nez, nz = int(c->nz);
-        hipError_t e = hipSuccess;
-        if (!mixed) {
-            const size_t lds = rhs_lds_bytes<NN, false>(zc, nez);
-            if (nontemporal_stores(c)) {
-                if (e == hipSuccess) e = rhs_prepare<NN, EPI_R, false, false, true>(lds);
-                if (e == hipSuccess) e = rhs_prepare<NN, EPI_TWO, true, false, true>(lds);
-                if (e == hipSuccess) e = rhs_prepare<NN, EPI_FINAL, false, false, true>(lds);
-            } else {
-                if (e == hipSuccess) e = rhs_prepare<NN, EPI_R, false, false>(lds);
-                if (e == hipSuccess) e = rhs_prepare<NN, EPI_TWO, true, false>(lds);
-                if (e == hipSuccess) e = rhs_prepare<NN, EPI_FINAL, false, false>(lds);
-            }
+        const int nz = int(c->nz);
+        hipError_t e;
+        if (c->rhs_tile == 1 && !mixed) {
+            const int zc = c->rhs_zchunk > 0 ? c->rhs_zchunk : rhs_zchunk_auto<NN, 1>(c);
+            e = rhs_prepare_alt(c, zc);
         } else {
-            const size_t lds = rhs_lds_bytes<NN, true>(zc, nez);
-            if (e == hipSuccess) e = rhs_prepare<NN, EPI_R, false, true>(lds);
-            if (e == hipSuccess) e = rhs_prepare<NN, EPI_TWO, true, true>(lds);
-            if (e == hipSuccess) e = rhs_prepare<NN, EPI_FINAL, false, true>(lds);
+            const int zc = c->rhs_zchunk > 0 ? c->rhs_zchunk : rhs_zchunk_auto<NN, 0>(c);
+            e = rhs_prepare_step<NN, 0>(c, mixed, zc);
         }
         // the column solves of both forms are the FP64 ones
         if (e == hipSuccess) e = solve_prepare<NN, ShapeStage2>(nz);
@@ -1952,41 +1190,101 @@ hipError_t prepare_step(numa_ctx *c, bool mixed)
     });
 }
 
-// Autotuner of the right-hand side's vertical chunk (elements per workgroup,
-// i.e. the workgroup's height in the z march): times the plain right-hand
-// side of state (written to the context's stage buffer R1; state is only
-// read) for chunks nez, nez/2, nez/3, ... 1 and keeps the fastest in
-// c->rhs_zchunk.  Synchronises the context's stream.
-hipError_t autotune_rhs_zchunk(numa_ctx *c, const double *state, int reps, int *chosen)
+int rhs_zchunk_in_use(const numa_ctx *c, bool mixed)
 {
-    std::vector<int> cand;
+    int zc = 0;
+    (void)dispatch(c->N, [&](auto n) -> hipError_t {
+        constexpr int NN = decltype(n)::value;
+        zc = c->rhs_tile == 1 && !mixed ? rhs_zchunk_auto<NN, 1>(c) : rhs_zchunk_auto<NN, 0>(c);
+        return hipSuccess;
+    });
+    return zc;
+}
+
+int rhs_tile_shape(int N, int variant, int *tx)
+{
+    int ty = 0;
+    (void)dispatch(N, [&](auto n) -> hipError_t {
+        constexpr int NN = decltype(n)::value;
+        *tx = variant == 1 ? Tile<NN, 1>::TX : Tile<NN, 0>::TX;
+        ty = variant == 1 ? Tile<NN, 1>::TY : Tile<NN, 0>::TY;
+        return hipSuccess;
+    });
+    return ty;
+}
+
+// The three right-hand sides of a step, timed on state without changing it:
+// R(state) into R1; the stage-2 form reading state and R1 into E3 and ACC;
+// the final form reading state and ACC into E3 (outputs are scratch).
+static hipError_t launch_rhs_set(numa_ctx *c, const double *state)
+{
+    StageBuffers s = stage_buffers(c);
+    const long np = c->np;
+    hipError_t e = launch_rhs_plain(c, state, s.R1);
+    if (e != hipSuccess) return e;
+    e = dispatch(c->N, [&](auto n) {
+        RhsParams p{};
+        p.a[0] = state;
+        p.a[3] = state + 3 * np;
+        p.cb = 0.5;
+        p.out0 = s.E3;
+        p.out1 = s.ACC;
+        p.e0 = state;
+        p.e1 = s.R1;
+        p.fs = np;
+        p.k01 = p.k02 = p.k11 = p.k12 = 0.5;
+        return rhs_launch<decltype(n)::value, EPI_TWO, true>(c, p);
+    });
+    if (e != hipSuccess) return e;
+    return launch_rhs_final(c, state, s.ACC, s.E3, 0.5);
+}
+
+// Autotuner of the right-hand sides: for each tile variant that differs
+// from the first and fits one CU's LDS, and each vertical chunk (elements
+// per workgroup in the z march: nez, nez/2, nez/3, ... 1), times the three
+// right-hand sides of a step on state (read only; outputs into the stage
+// buffers) and keeps the fastest pair in c->rhs_tile and c->rhs_zchunk.
+// Synchronises the context's stream.
+hipError_t autotune_rhs(numa_ctx *c, const double *state, int reps, int *zchunk_out, int *tile_out)
+{
+    std::vector<int> chunks;
     for (int d = 1; d <= c->nez; ++d) {
         const int zc = (c->nez + d - 1) / d;
-        if (cand.empty() || cand.back() != zc) cand.push_back(zc);
+        if (chunks.empty() || chunks.back() != zc) chunks.push_back(zc);
     }
+    std::vector<int> tiles = {0};
+    if (rhs_alt_differs(c->N)) tiles.push_back(1);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    const int keep = c->rhs_zchunk;
+    const int keep_zc = c->rhs_zchunk, keep_tile = c->rhs_tile;
     float best = 0.f;
-    int best_zc = keep;
-    double *R = stage_buffers(c).R1;
-    for (size_t i = 0; i < cand.size() && e == hipSuccess; ++i) {
-        c->rhs_zchunk = cand[i];
-        e = launch_rhs_plain(c, state, R);  // warm-up (and LDS attribute)
-        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
-        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_rhs_plain(c, state, R);
-        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e == hipSuccess && (i == 0 || ms < best)) {
-            best = ms;
-            best_zc = cand[i];
+    int best_zc = keep_zc, best_tile = keep_tile;
+    bool any = false;
+    for (int tile : tiles) {
+        for (size_t i = 0; i < chunks.size() && e == hipSuccess; ++i) {
+            if (tile == 1 && rhs_lds_alt(c->N, chunks[i], c->nez) > kLdsPerCU) continue;
+            c->rhs_tile = tile;
+            c->rhs_zchunk = chunks[i];
+            e = launch_rhs_set(c, state);  // warm-up (and LDS attributes)
+            if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+            for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_rhs_set(c, state);
+            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && (!any || ms < best)) {
+                any = true;
+                best = ms;
+                best_zc = chunks[i];
+                best_tile = tile;
+            }
         }
     }
-    c->rhs_zchunk = e == hipSuccess ? best_zc : keep;
-    if (chosen) *chosen = c->rhs_zchunk;
+    c->rhs_zchunk = e == hipSuccess ? best_zc : keep_zc;
+    c->rhs_tile = e == hipSuccess ? best_tile : keep_tile;
+    if (zchunk_out) *zchunk_out = c->rhs_zchunk;
+    if (tile_out) *tile_out = c->rhs_tile;
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     return e;

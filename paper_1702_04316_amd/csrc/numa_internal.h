@@ -87,6 +87,7 @@ struct numa_ctx {
     int factored = 0;
     double dt_factored = 0, lambda = 0;
     int rhs_zchunk = 0;            // z elements per RHS workgroup (0 = auto)
+    int rhs_tile = 0;              // RHS tile variant (0 default, 1 the alternative)
     numa::Imex3d *imex = nullptr;  // 3D-IMEX solver (numa_imex3d_setup)
     numa::Learned *learned = nullptr;  // learned correction (numa_learned_setup)
     double *fac_std = nullptr;     // standard-form column factors [2 nz][4N+3], shared by all columns
@@ -145,7 +146,17 @@ constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
 hipError_t noalloc_scratch_init();
 char *noalloc_scratch(int device);
 hipError_t prepare_step(numa_ctx *c, bool mixed);
-hipError_t autotune_rhs_zchunk(numa_ctx *c, const double *state, int reps, int *chosen);
+// times the step's right-hand sides for every tile variant and vertical
+// chunk on state (read only) and keeps the fastest; synchronises
+hipError_t autotune_rhs(numa_ctx *c, const double *state, int reps, int *zchunk_out, int *tile_out);
+// TX of tile variant (0, 1) of order N into *tx; returns TY
+int rhs_tile_shape(int N, int variant, int *tx);
+// the vertical chunk the right-hand sides of the FP64 step (or, mixed, of the
+// precision form) use: the set one, else the automatic
+int rhs_zchunk_in_use(const numa_ctx *c, bool mixed = false);
+// whether tile variant 1 differs from 0 for order N, and its LDS (FP64 form)
+bool rhs_alt_differs(int N);
+size_t rhs_lds_alt(int N, int zc, int nez);
 // abi.cpp: NUMA_OK or the error code (message recorded in the context)
 int ensure_mixed_buffers(numa_ctx *c, const char *who);
 int step_preconditions(numa_ctx *c, double dt, const char *who);

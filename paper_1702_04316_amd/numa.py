@@ -77,6 +77,9 @@ def load():
     lib.numa_set_stream.argtypes = [vp, vp]
     lib.numa_factor_columns.argtypes = [vp, C.c_double]
     lib.numa_set_column_solver.argtypes = [vp, C.c_int32]
+    lib.numa_autotune.argtypes = [vp, vp, C.c_int32, C.POINTER(C.c_int32)]
+    lib.numa_set_rhs_config.argtypes = [vp, C.c_int32, C.c_int32]
+    lib.numa_get_rhs_config.argtypes = [vp, C.POINTER(C.c_int32)]
     lib.numa_hevi_step.argtypes = [vp, vp, C.c_double, C.c_int32]
     lib.numa_profile_steps.argtypes = [vp, vp, C.c_double, C.c_int32, C.POINTER(C.c_double)]
     lib.numa_hevi_step_mixed.argtypes = [vp, vp, C.c_double, C.c_int32]
@@ -128,7 +131,8 @@ def load():
                  "numa_pbno_apply", "numa_imex3d_solve", "numa_learned_setup", "numa_learned_info",
                  "numa_learned_add_samples", "numa_learned_samples", "numa_learned_params", "numa_learned_loss_grad",
                  "numa_learned_train", "numa_learned_enable", "numa_learned_apply", "numa_factor_columns_standard",
-                 "numa_solve_columns_standard", "numa_set_column_solver"):
+                 "numa_solve_columns_standard", "numa_set_column_solver", "numa_autotune",
+                 "numa_set_rhs_config", "numa_get_rhs_config"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -193,6 +197,23 @@ def factor_columns(ctx, dt):
 
 def set_column_solver(ctx, kind):
     return _check(load().numa_set_column_solver(ctx, int(kind)), ctx)
+
+
+def autotune(ctx, state_ptr, reps=3):
+    """Autotune the right-hand sides on the state; returns {tile, TX, TY, zchunk}."""
+    out = (C.c_int32 * 4)()
+    _check(load().numa_autotune(ctx, C.c_void_p(state_ptr), int(reps), out), ctx)
+    return dict(zip(("tile", "TX", "TY", "zchunk"), (int(v) for v in out)))
+
+
+def set_rhs_config(ctx, tile, zchunk=0):
+    return _check(load().numa_set_rhs_config(ctx, int(tile), int(zchunk)), ctx)
+
+
+def get_rhs_config(ctx):
+    out = (C.c_int32 * 4)()
+    _check(load().numa_get_rhs_config(ctx, out), ctx)
+    return dict(zip(("tile", "TX", "TY", "zchunk"), (int(v) for v in out)))
 
 
 def hevi_step(ctx, state_ptr, dt, nsteps):
