@@ -78,7 +78,7 @@ typedef struct {
     int32_t order;                /* LGL order N                                      */
     int32_t factored;             /* 1 once numa_factor_columns succeeded             */
     double dt_factored;           /* dt of the stored factors                         */
-    int32_t column_solver;        /* NUMA_SOLVER_BAND or NUMA_SOLVER_BLOCKED, in use  */
+    int32_t column_solver;        /* NUMA_SOLVER_BAND, _BLOCKED or _PER_COLUMN, in use */
     int32_t reserved;
 } numa_info;
 
@@ -142,8 +142,10 @@ int numa_get_rhs_config(const numa_ctx *c, int32_t *out);
  * pivoting, half-bandwidth 2N (Alg. 9); the factors stay on the device.
  * Every column of a context has the same operator (uniform horizontal grid,
  * one set of vertical faces, horizontally uniform background), so one
- * factor set serves all columns.  dt > 0.  Errors: NUMA_E_ARG, NUMA_E_HIP (a zero or
- * non-finite pivot is reported by numa_check as NUMA_E_NONFINITE).
+ * factor set serves all columns, unless NUMA_SOLVER_PER_COLUMN asks for
+ * each column's own.  dt > 0.  Errors: NUMA_E_ARG, NUMA_E_NOMEM (per-column
+ * factors), NUMA_E_HIP (a zero or non-finite pivot is reported by
+ * numa_check as NUMA_E_NONFINITE).
  */
 int numa_factor_columns(numa_ctx *c, double dt);
 
@@ -157,15 +159,23 @@ int numa_factor_columns(numa_ctx *c, double dt);
  * right-hand side and the extraction, and one wavefront running the
  * substitutions from LDS; available for columns of at most 128 levels, and
  * of at most 224 levels where (nz + 2N) * 64 + nz * (4N + 1) doubles of LDS
- * fit one CU's 160 KB.  NUMA_SOLVER_AUTO (the default): blocked where
- * available.
+ * fit one CU's 160 KB.  NUMA_SOLVER_PER_COLUMN: one lane per column with
+ * every column's own factors, assembled and factored by its own lane and
+ * stored [level][diagonal][column] in device memory (Sec. 5.4: the LU of
+ * each column computed once and stored; nz (4N+1) ncol doubles, below
+ * 4 GiB, allocated by numa_factor_columns), for columns whose matrices may
+ * differ; here they are equal, so it reads the same numbers as the shared
+ * band from a layout of ncol times its size.  NUMA_SOLVER_AUTO (the
+ * default): blocked where available.
  * Takes effect at the next numa_factor_columns; until then the context
  * counts as not factored.  Errors: NUMA_E_ARG (unknown kind),
- * NUMA_E_UNSUPPORTED (blocked for a column it does not support).
+ * NUMA_E_UNSUPPORTED (blocked for a column it does not support, per-column
+ * factors above 4 GiB).
  */
 #define NUMA_SOLVER_AUTO 0
 #define NUMA_SOLVER_BAND 1
 #define NUMA_SOLVER_BLOCKED 2
+#define NUMA_SOLVER_PER_COLUMN 3
 int numa_set_column_solver(numa_ctx *c, int32_t kind);
 
 /*

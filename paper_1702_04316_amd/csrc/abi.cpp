@@ -33,6 +33,7 @@ void free_ctx(numa_ctx *c)
     if (!c) return;
     if (c->lev_block) (void)hipFree(c->lev_block);
     if (c->fac) (void)hipFree(c->fac);
+    if (c->fac_cols) (void)hipFree(c->fac_cols);
     if (c->work) (void)hipFree(c->work);
     if (c->work_mix) (void)hipFree(c->work_mix);
     if (c->flag) (void)hipFree(c->flag);
@@ -44,8 +45,6 @@ void free_ctx(numa_ctx *c)
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
-// bytes of the one LU band every column solve reads (all columns share it)
-int64_t solve_table_bytes(const numa_ctx *c) { return c->nz * (4 * c->N + 1) * int64_t(sizeof(double)); }
 
 int64_t step_bytes_model(const numa_ctx *c)
 {
@@ -55,7 +54,7 @@ int64_t step_bytes_model(const numa_ctx *c)
     // background the solves also write theta' (K2 reads q^n and R1 theta'
     // for it, K3 reads it, K4 reads E3 theta' for it): 6 more.
     const int64_t fields = numa::stratified(c) ? 71 : 65;
-    return fields * c->np * int64_t(sizeof(double)) + 2 * solve_table_bytes(c);
+    return fields * c->np * int64_t(sizeof(double)) + 2 * numa::factor_bytes(c);
 }
 
 }  // namespace
@@ -230,13 +229,15 @@ int numa_get_info(const numa_ctx *c, numa_info *info)
     info->ny = c->ny;
     info->nz = c->nz;
     info->ncol = c->ncol;
-    info->factor_bytes = solve_table_bytes(c);
+    info->factor_bytes = numa::factor_bytes(c);
     info->scratch_bytes = numa::kStageFields * c->np * int64_t(sizeof(double));
     info->step_bytes = step_bytes_model(c);
     info->order = c->N;
     info->factored = c->factored;
     info->dt_factored = c->dt_factored;
-    info->column_solver = numa::blocked_solve_used(c) ? NUMA_SOLVER_BLOCKED : NUMA_SOLVER_BAND;
+    info->column_solver = numa::per_column_factors(c) ? NUMA_SOLVER_PER_COLUMN
+                          : numa::blocked_solve_used(c) ? NUMA_SOLVER_BLOCKED
+                                                        : NUMA_SOLVER_BAND;
     info->reserved = 0;
     return NUMA_OK;
 }
@@ -251,8 +252,12 @@ int numa_set_stream(numa_ctx *c, void *hip_stream)
 int numa_set_column_solver(numa_ctx *c, int32_t kind)
 {
     if (!c) return NUMA_E_ARG;
-    if (kind != NUMA_SOLVER_AUTO && kind != NUMA_SOLVER_BAND && kind != NUMA_SOLVER_BLOCKED)
+    if (kind != NUMA_SOLVER_AUTO && kind != NUMA_SOLVER_BAND && kind != NUMA_SOLVER_BLOCKED &&
+        kind != NUMA_SOLVER_PER_COLUMN)
         return fail(c, NUMA_E_ARG, "numa_set_column_solver: unknown kind");
+    if (kind == NUMA_SOLVER_PER_COLUMN &&
+        c->nz * (4 * c->N + 1) * c->ncol * int64_t(sizeof(double)) >= (int64_t(1) << 32))
+        return fail(c, NUMA_E_UNSUPPORTED, "numa_set_column_solver: per-column factors above 4 GiB");
     if (kind == NUMA_SOLVER_BLOCKED && !numa::blocked_solve_ok(c->N, c->nz))
         return fail(c, NUMA_E_UNSUPPORTED, "numa_set_column_solver: the blocked solve needs nz <= 128, or nz <= 224 where its LDS fits one CU");
     c->column_solver = kind;
@@ -303,7 +308,15 @@ int numa_factor_columns(numa_ctx *c, double dt)
     if (!finite_pos(dt)) return fail(c, NUMA_E_ARG, "numa_factor_columns: dt must be finite and > 0");
     const double lambda = (1.0 - 1.0 / std::sqrt(2.0)) * dt;
     c->factored = 0;
-    hipError_t e = numa::launch_factor(c, lambda);
+    hipError_t e = hipSuccess;
+    if (numa::per_column_factors(c) && !c->fac_cols) {
+        e = hipMalloc(&c->fac_cols, size_t(numa::factor_bytes(c)));
+        if (e != hipSuccess) {
+            c->fac_cols = nullptr;
+            return hip_fail(c, e, "numa_factor_columns: hipMalloc(per-column factors)");
+        }
+    }
+    e = numa::launch_factor(c, lambda);
     if (e != hipSuccess) return hip_fail(c, e, "numa_factor_columns");
     c->factored = 1;
     c->dt_factored = dt;

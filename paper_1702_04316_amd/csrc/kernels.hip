@@ -94,7 +94,11 @@ struct SolveGeom {
     static size_t lds_total(int M) { return lds_bytes(M) + (fac_in_lds(M) ? fac_bytes(M) : 0); }
 };
 
-template <int N, class SH, bool FL>
+// FL: where the factor band comes from: 0, the band shared by all columns
+// through scalar loads; 1, the shared band staged in LDS; 2, each column's
+// own band, [level][diagonal][column] in global memory (the per-column
+// layout)
+template <int N, class SH, int FL>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_colsolve(SolveParams p)
 {
     using G = SolveGeom<N, SH>;
@@ -122,12 +126,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     // LDS after P (broadcast reads); otherwise read through the constant
     // address space (scalar loads)
     double *facl = smem + (R + M + HB) * 64;
-    if constexpr (FL) {
+    if constexpr (FL == 1) {
         for (int e = lane; e < M * NB; e += 64) facl[e] = p.fac[e];
         __syncthreads();
     }
     auto fac = [&](int idx) -> double {
-        if constexpr (FL) return facl[idx];
+        if constexpr (FL == 1) return facl[idx];
+        else if constexpr (FL == 2) return gload(p.fac, unsigned(idx) * lbytes + cbyte);
         else return as_const(p.fac)[idx];
     };
 
@@ -605,6 +610,55 @@ __global__ __launch_bounds__(kFactorThreads) void k_factor(const double *__restr
     if (bad) *flag = 1;
 }
 
+// The per-column layout of the factors (Sec. 5.4: every column's LU stored
+// for reuse): each lane assembles and factors its own column's band, the
+// same matrix and the same elimination as k_factor, in place in
+// F[(row * NB + offset) * ncol + col] (consecutive lanes, consecutive
+// columns).
+template <int N>
+__global__ __launch_bounds__(64) void k_factor_cols(const double *__restrict__ dzb, const double *__restrict__ scf,
+                                                    int M, long ncol, double *F, int *flag)
+{
+    constexpr int NS = 2 * N + 1, NB = 4 * N + 1, HB = 2 * N;
+    const long col = (long)blockIdx.x * 64 + threadIdx.x;
+    if (col >= ncol) return;
+    auto A = [&](int r, int cidx) -> double & { return F[(size_t(r) * NB + size_t(cidx - r + HB)) * size_t(ncol) + col]; };
+    for (int r = 0; r < M; ++r)
+        for (int j = 0; j < NB; ++j) {
+            const int cidx = r + j - HB;
+            double v = 0.0;
+            if (cidx >= 0 && cidx < M) {
+                double s = 0.0;
+                const int mlo = max(max(r, cidx) - N, 1), mhi = min(min(r, cidx) + N, M - 2);
+                for (int m = mlo; m <= mhi; ++m) {
+                    const double drm = dzb[(long)r * NS + (m - r + N)];
+                    const double dmc = dzb[(long)m * NS + (cidx - m + N)];
+                    const double *cm = scf + (long)m * SC_N;
+                    s += drm * cm[SC_RHO0] * (cm[SC_X1] * dmc + (m == cidx ? cm[SC_X2] : 0.0));
+                }
+                const double *cr = scf + (long)r * SC_N;
+                v = (r == cidx ? 1.0 : 0.0) - cr[SC_LG] * s;
+                if (r >= 1 && r <= M - 2 && cidx >= r - N && cidx <= r + N)
+                    v -= cr[SC_HZ] * (cr[SC_X1] * dzb[(long)r * NS + (cidx - r + N)] + (r == cidx ? cr[SC_X2] : 0.0));
+            }
+            F[(size_t(r) * NB + j) * size_t(ncol) + col] = v;
+        }
+    bool bad = false;
+    for (int k = 0; k < M; ++k) {
+        const double piv = A(k, k);
+        const double rp = 1.0 / piv;
+        const int last = min(k + HB, M - 1);
+        for (int i = k + 1; i <= last; ++i) {
+            const double l = A(i, k) * rp;
+            for (int jj = k + 1; jj <= last; ++jj) A(i, jj) -= l * A(k, jj);
+            A(i, k) = l;
+        }
+        bad |= !(fabs(piv) > 0.0) || !isfinite(piv);
+        A(k, k) = rp;  // the solve multiplies by the reciprocal pivot
+    }
+    if (bad) *flag = 1;
+}
+
 // P0 = EOS(rho0, theta0), G0 = gamma P0 / rho0, H0 = gamma P0 / theta0 per level
 __global__ void k_background(const double *rho0, const double *th0, double *P0, double *G0, double *H0, int nz,
                              EOS e)
@@ -622,7 +676,7 @@ __global__ void k_background(const double *rho0, const double *th0, double *P0, 
 // ---------------------------------------------------------------------------
 namespace {
 
-template <int N, class SH, bool FL>
+template <int N, class SH, int FL>
 hipError_t solve_prepare_fl(size_t shm)
 {
     static size_t attr_set = 0;  // tall columns need LDS above 64 KB
@@ -640,8 +694,8 @@ template <int N, class SH>
 hipError_t solve_prepare(int M)
 {
     using G = SolveGeom<N, SH>;
-    return G::fac_in_lds(M) ? solve_prepare_fl<N, SH, true>(G::lds_total(M))
-                            : solve_prepare_fl<N, SH, false>(G::lds_total(M));
+    return G::fac_in_lds(M) ? solve_prepare_fl<N, SH, 1>(G::lds_total(M))
+                            : solve_prepare_fl<N, SH, 0>(G::lds_total(M));
 }
 
 // k_rhs with the context's tile variant: the second variant serves the FP64
@@ -703,20 +757,33 @@ hipError_t solve_launch(numa_ctx *c, SolveParams p)
         }
         return hipGetLastError();
     }
+    dim3 grid(unsigned((c->ncol + 63) / 64));
+    if (per_column_factors(c)) {  // each column's own band from global memory
+        p.fac = c->fac_cols;
+        const size_t shm = G::lds_bytes(M);
+        hipError_t e = solve_prepare_fl<N, SH, 2>(shm);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_colsolve<N, SH, 2>), grid, dim3(64), shm, c->stream, p);
+        return hipGetLastError();
+    }
     const size_t shm = G::lds_total(M);
     hipError_t e = solve_prepare<N, SH>(M);
     if (e != hipSuccess) return e;
-    dim3 grid(unsigned((c->ncol + 63) / 64));
     if (G::fac_in_lds(M))
-        hipLaunchKernelGGL((k_colsolve<N, SH, true>), grid, dim3(64), shm, c->stream, p);
+        hipLaunchKernelGGL((k_colsolve<N, SH, 1>), grid, dim3(64), shm, c->stream, p);
     else
-        hipLaunchKernelGGL((k_colsolve<N, SH, false>), grid, dim3(64), shm, c->stream, p);
+        hipLaunchKernelGGL((k_colsolve<N, SH, 0>), grid, dim3(64), shm, c->stream, p);
     return hipGetLastError();
 }
 
 template <int N>
 hipError_t factor_launch(numa_ctx *c, double lambda)
 {
+    if (per_column_factors(c)) {
+        hipLaunchKernelGGL((k_factor_cols<N>), dim3(unsigned((c->ncol + 63) / 64)), dim3(64), 0, c->stream,
+                           c->lev.dzb, c->lev.scf, int(c->nz), c->ncol, c->fac_cols, c->flag);
+        return hipGetLastError();
+    }
     // one factor set, shared by all columns (their matrices are identical)
     const size_t bytes = size_t(c->nz) * (4 * N + 1) * sizeof(double);
     const bool lds = bytes <= kFactorLds;
@@ -739,7 +806,7 @@ bool blocked_solve_ok(int N, int64_t nz)
 
 bool blocked_solve_used(const numa_ctx *c)
 {
-    if (c->column_solver == NUMA_SOLVER_BAND) return false;
+    if (c->column_solver == NUMA_SOLVER_BAND || c->column_solver == NUMA_SOLVER_PER_COLUMN) return false;
     return c->column_solver == NUMA_SOLVER_BLOCKED || blocked_solve_ok(c->N, c->nz);
 }
 
@@ -1179,6 +1246,10 @@ hipError_t prepare_step(numa_ctx *c, bool mixed)
         // the column solves of both forms are the FP64 ones
         if (e == hipSuccess) e = solve_prepare<NN, ShapeStage2>(nz);
         if (e == hipSuccess) e = solve_prepare<NN, ShapeStage3>(nz);
+        if (per_column_factors(c)) {
+            if (e == hipSuccess) e = solve_prepare_fl<NN, ShapeStage2, 2>(SolveGeom<NN, ShapeStage2>::lds_bytes(nz));
+            if (e == hipSuccess) e = solve_prepare_fl<NN, ShapeStage3, 2>(SolveGeom<NN, ShapeStage3>::lds_bytes(nz));
+        }
         if (blocked_solve_used(c) && nz > 8 * kBlockedKL) {
             if (e == hipSuccess) e = blocked_prepare<NN, ShapeStage2, 16>(blocked_lds_bytes(NN, nz));
             if (e == hipSuccess) e = blocked_prepare<NN, ShapeStage3, 16>(blocked_lds_bytes(NN, nz));

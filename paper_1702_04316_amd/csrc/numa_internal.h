@@ -80,7 +80,9 @@ struct numa_ctx {
     numa::DevLevels lev;
     void *lev_block = nullptr;     // one allocation holding all of lev
     double *fac = nullptr;         // [nz][4N+1] column LU factors, one set shared by all columns
-    int column_solver = 0;         // NUMA_SOLVER_*: 0 auto, 1 one lane per column, 2 level-blocked
+    double *fac_cols = nullptr;    // per-column layout [nz][4N+1][ncol] (NUMA_SOLVER_PER_COLUMN)
+    int column_solver = 0;         // NUMA_SOLVER_*: 0 auto, 1 one lane per column, 2 level-blocked,
+                                   // 3 one lane per column with per-column factors
     double *work = nullptr;        // stage buffers (19 fields)
     char *work_mix = nullptr;      // precision form: R1, E3 (mixed layout), Q2, Q3 rho' and w (FP64)
     int *flag = nullptr;           // device non-finite flag
@@ -112,6 +114,14 @@ constexpr int kStageFields = 21;  // fields of the stage buffers (c->work)
 
 // a background with a buoyancy frequency: the column solves change theta'
 inline bool stratified(const numa_ctx *c) { return c->nbv > 0.0; }
+// the column solves read every column's own factors (per-column layout)
+inline bool per_column_factors(const numa_ctx *c) { return c->column_solver == NUMA_SOLVER_PER_COLUMN; }
+// device bytes of the factors the column solves read
+inline int64_t factor_bytes(const numa_ctx *c)
+{
+    const int64_t band = c->nz * (4 * c->N + 1) * int64_t(sizeof(double));
+    return per_column_factors(c) ? band * c->ncol : band;
+}
 StageBuffers stage_buffers(numa_ctx *c);
 
 // LDS per CU on gfx950, and what one workgroup of the kernels needs

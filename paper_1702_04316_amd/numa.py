@@ -20,7 +20,7 @@ NUMA_E_NOMEM = -5
 NUMA_E_NONFINITE = -6
 NUMA_E_NOT_CONVERGED = -7
 NUMA_E_UNSUPPORTED = -8
-SOLVER_AUTO, SOLVER_BAND, SOLVER_BLOCKED = 0, 1, 2
+SOLVER_AUTO, SOLVER_BAND, SOLVER_BLOCKED, SOLVER_PER_COLUMN = 0, 1, 2, 3
 
 ERROR_NAMES = {
     NUMA_E_ARG: "NUMA_E_ARG",

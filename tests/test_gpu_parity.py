@@ -135,7 +135,7 @@ TALL = [(4, 2, 2, 40, None, 21), (7, 1, 2, 28, 8, 22), (1, 2, 1, 223, None, 23)]
 
 
 @pytest.mark.parametrize("N,nex,ney,nez,zseed,seed", TALL)
-@pytest.mark.parametrize("solver", ["band", "blocked"])
+@pytest.mark.parametrize("solver", ["band", "blocked", "per_column"])
 def test_tall_column_solve_and_step_parity(torch_cuda, numa_mod, oracle_mod, N, nex, ney, nez, zseed, seed,
                                            solver):
     lz = 20000.0
@@ -145,7 +145,8 @@ def test_tall_column_solve_and_step_parity(torch_cuda, numa_mod, oracle_mod, N, 
     o = _oracle(oracle_mod, g)
     o.factor_dt(dt)
     ctx = numa_mod.Context(g)
-    kind = numa_mod.SOLVER_BAND if solver == "band" else numa_mod.SOLVER_BLOCKED
+    kind = {"band": numa_mod.SOLVER_BAND, "blocked": numa_mod.SOLVER_BLOCKED,
+            "per_column": numa_mod.SOLVER_PER_COLUMN}[solver]
     ctx.set_column_solver(kind)
     ctx.factor(dt)
     assert ctx.info()["column_solver"] == kind
@@ -262,7 +263,7 @@ def test_band_and_blocked_column_solvers(torch_cuda, numa_mod, oracle_mod, N, ne
     qref = o.step(q, dtx, 2)
     ctx = numa_mod.Context(g)
     outs = {}
-    for kind in (numa_mod.SOLVER_BAND, numa_mod.SOLVER_BLOCKED):
+    for kind in (numa_mod.SOLVER_BAND, numa_mod.SOLVER_BLOCKED, numa_mod.SOLVER_PER_COLUMN):
         ctx.set_column_solver(kind)
         ctx.factor(dt)
         x = _host(ctx.solve(_dev(torch_cuda, y)))
@@ -277,9 +278,12 @@ def test_band_and_blocked_column_solvers(torch_cuda, numa_mod, oracle_mod, N, ne
         print(f"solver {kind} N={N} nz={g.nz}: step rel L2 {e}")
         assert np.all(e < STEP_TOL), (kind, e)
         outs[kind] = x
-    # the two solvers agree to rounding
+    # the solvers agree to rounding; the per-column factors are the shared
+    # band's numbers, so that solve equals the band solve
     e = _rel(outs[numa_mod.SOLVER_BLOCKED], outs[numa_mod.SOLVER_BAND])
     assert np.all(e < OP_TOL), e
+    e = _rel(outs[numa_mod.SOLVER_PER_COLUMN], outs[numa_mod.SOLVER_BAND])
+    assert np.all(e < 1e-15), e
 
 
 def test_column_solver_selection(torch_cuda, numa_mod):

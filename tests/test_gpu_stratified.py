@@ -69,7 +69,7 @@ def test_rhs_and_solve_parity(torch_cuda, numa_mod, oracle_mod, N, nex, ney, nez
     y = W.make_random_state(g, seed + 50, smooth=False)
     ref = o.solve(y)
     assert np.linalg.norm(ref[4] - y[4]) > 1e-3 * np.linalg.norm(y[4])  # theta' is solved for
-    for kind in (numa_mod.SOLVER_BAND, numa_mod.SOLVER_BLOCKED):
+    for kind in (numa_mod.SOLVER_BAND, numa_mod.SOLVER_BLOCKED, numa_mod.SOLVER_PER_COLUMN):
         ctx.set_column_solver(kind)
         ctx.factor(dt)
         x = ctx.solve(torch_cuda.from_numpy(y).cuda()).cpu().numpy()
