@@ -9,9 +9,10 @@ potential-temperature bumps in hydrostatic pressure balance.
 Prints ONE JSON line.  value = DOF-steps/s = 5 * unique nodes * steps / s,
 with the state already resident in HBM.  The timed steps record a HIP event
 around every kernel on the library's stream; the roofline object uses the
-average duration of the dominant kernel and its algorithmic bytes.  The CPU
-baseline times the plain FP64 oracle on a bounded sub-box of the same
-workload (same element shape, order and dt).
+average duration of the dominant kernel and its algorithmic bytes.  The
+right-hand sides' tile shape and vertical chunk come from the library's
+autotuner, run before the warm-up steps.  The CPU baseline times the plain
+FP64 oracle on the same workload for a few steps.
 """
 import argparse
 import hashlib
@@ -41,13 +42,17 @@ def kernel_bytes(np_, ncol, nz, N, table_bytes=None):
     ]
 
 
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1702_04316_amd", "csrc", "kernels.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1702_04316_amd", "csrc", f)
+                  for f in ("kernels.hip", "rhs_kernel.h", "rhs_alt.hip", "numa_internal.h")]
 
 
 def kernel_source_hash():
-    import hashlib
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    """SHA-256 over the sources of the step's kernels, in a fixed order."""
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def load_traffic():
@@ -64,23 +69,54 @@ def load_traffic():
     return t
 
 
-def cpu_baseline(sample_nex=32, steps=60):
-    import numpy as np
+def cpu_model():
+    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(steps=5, single_steps=1):
+    """The plain FP64 oracle on the benchmarked workload itself (64x64x10,
+    N=4, R1): factorisation untimed, then `steps` steps with every host
+    thread and `single_steps` with one thread, timed."""
     from oracle import oracle as O
     from paper_1702_04316_amd import workloads as W
-    wl = W.box_large("R1", nex=sample_nex, ney=sample_nex)
+    wl = W.box_large("R1")
     g = wl.grid
     o = O.Oracle(g.lx, g.ly, g.lz, g.nex, g.ney, g.nez, g.N)
     q0 = W.make_initial_state(wl)
     o.factor_dt(wl.dt)
+    threads = O.get_threads()
     t0 = time.perf_counter()
-    o.step(q0, wl.dt, steps)
+    q = o.step(q0, wl.dt, steps)
     t = time.perf_counter() - t0
-    return {"value": 5.0 * g.n_unique * steps / t, "unit": "DOF-steps/s", "cores": O.get_threads(),
+    O.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        o.step(q, wl.dt, single_steps)
+        t1 = time.perf_counter() - t0
+    finally:
+        O.set_threads(threads)
+    return {"value": 5.0 * g.n_unique * steps / t, "unit": "DOF-steps/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{sample_nex}x{sample_nex}x10 elements N=4 sub-box of the benchmarked workload "
-                      f"(same element shape, order and dt), {steps} steps, factorisation not timed",
-            "seconds": t}
+            "sample": (f"the benchmarked workload itself (64x64x10 elements, N=4, 256x256x41 unique nodes), "
+                       f"{steps} steps on {threads} threads, factorisation not timed"),
+            "seconds": t, "cpu_model": cpu_model(),
+            "single_thread": {"value": 5.0 * g.n_unique * single_steps / t1, "steps": single_steps,
+                              "seconds": t1}}
 
 
 def precision_form(numa, torch, ctx, wl, args, t_fp64):
@@ -139,7 +175,8 @@ def precision_form_n7(numa, torch, steps=20, err_steps=100):
     q0 = torch.from_numpy(W.make_initial_state(wl)).to("cuda")
     names = ["rhs_stage1", "colsolve_stage2", "rhs_stage2", "colsolve_stage3", "rhs_stage3"]
     out = {"workload": f"{wl.name}: 28x28x28 elements, LGL N=7, {g.nx}x{g.ny}x{g.nz} unique nodes, "
-                       "vertical Courant 15", "unique_nodes": g.n_unique, "dt_s": wl.dt}
+                       "vertical Courant 15", "unique_nodes": g.n_unique, "dt_s": wl.dt,
+           "rhs_config": numa.autotune(ctx.ctx, q0.data_ptr(), reps=3)}
     for name, prof, mixed in (("fp64", numa.profile_steps, False), ("mixed", numa.profile_steps_mixed, True)):
         q = q0.clone()
         ctx.step(q, 3, mixed=mixed)
@@ -163,6 +200,59 @@ def precision_form_n7(numa, torch, steps=20, err_steps=100):
         for f, n in enumerate(("rho'", "u", "v", "w", "theta'"))}
     out["unit"] = "DOF-steps/s"
     ctx.close()
+    return out
+
+
+def step_leg(numa, torch, wl, solver=None, steps=20, tune=True):
+    """FP64 steps of workload wl on its own context (optionally with a
+    column-solver kind), after the autotuner: ms per step, per-kernel
+    milliseconds (HIP events, launch order) and the step's algorithmic bytes
+    and GB/s (the library's byte model, numa_get_info)."""
+    from paper_1702_04316_amd import workloads as W
+    ctx = numa.Context(wl.grid, wl.background)
+    if solver is not None:
+        ctx.set_column_solver(solver)
+    t0 = time.perf_counter()
+    ctx.factor(wl.dt)
+    torch.cuda.synchronize()
+    t_factor = time.perf_counter() - t0
+    q = torch.from_numpy(W.make_initial_state(wl)).to("cuda")
+    cfg = numa.autotune(ctx.ctx, q.data_ptr(), reps=5) if tune else numa.get_rhs_config(ctx.ctx)
+    ctx.step(q, 3)
+    ctx.check()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = numa.profile_steps(ctx.ctx, q.data_ptr(), wl.dt, steps)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    ctx.check()
+    info = ctx.info()
+    ctx.close()
+    names = ["rhs_stage1", "colsolve_stage2", "rhs_stage2", "colsolve_stage3", "rhs_stage3"]
+    gbs = info["step_bytes"] / t / 1e9
+    return {"ms_per_step": 1e3 * t, "value": 5 * wl.grid.n_unique / t, "unit": "DOF-steps/s",
+            "factor_s": t_factor, "factor_bytes": info["factor_bytes"], "step_bytes": info["step_bytes"],
+            "step_GBps": gbs, "step_frac_of_8TBps": gbs / HBM_PEAK_GBS, "rhs_config": cfg,
+            "kernels": [{"kernel": n, "ms": m} for n, m in zip(names, ms)]}
+
+
+def per_column_factors(numa, torch, steps=20):
+    """The benchmarked workload with every column's own factors
+    (NUMA_SOLVER_PER_COLUMN, 365 MB read twice per step): the byte model of
+    65 field passes plus 2F, F = 41 x 17 x 65,536 doubles."""
+    from paper_1702_04316_amd import workloads as W
+    out = step_leg(numa, torch, W.box_large("R1"), solver=numa.SOLVER_PER_COLUMN, steps=steps)
+    out["entry"] = "numa_set_column_solver(NUMA_SOLVER_PER_COLUMN)"
+    return out
+
+
+def stratified_leg(numa, torch, steps=20):
+    """The benchmarked grid over the stratified background (Nb = 0.01/s):
+    the solves also write theta' (71 field passes)."""
+    from paper_1702_04316_amd import workloads as W
+    out = step_leg(numa, torch, W.box_stratified("large"), steps=steps)
+    out["workload"] = ("box64x64x10_N4_strat: the 64x64x10, N=4 grid over theta0(z) = 300 K exp(Nb^2 z/g), "
+                       "Nb = 0.01/s")
     return out
 
 
@@ -272,11 +362,26 @@ def batched_ensemble(numa, torch, steps=50):
         ens.sync()
         out[name] = {"value": dof * steps / t, "ms_per_step": 1e3 * t / steps, "speedup_vs_sequential": t_seq / t}
         out["tuned_zchunks"] = ens.zchunks()
+        out["tuned_tiles"] = [numa.get_rhs_config(c.ctx)["tile"] for c in ctxs]
         ens.close()
+        if mixed:
+            out[name]["rel_l2_vs_fp64_after_%d_steps" % (steps + 2)] = ensemble_rel_l2(torch, qs, fp64_states)
+        else:
+            fp64_states = [q.clone() for q in qs]
     out["unit"] = "DOF-steps/s"
     for c in ctxs:
         c.close()
     return out
+
+
+def ensemble_rel_l2(torch, qs, refs):
+    """Largest relative L2 difference per variable over the domains."""
+    worst = [0.0] * 5
+    for q, r in zip(qs, refs):
+        for f in range(5):
+            d = float(torch.linalg.vector_norm(q[f] - r[f]) / torch.linalg.vector_norm(r[f]))
+            worst[f] = max(worst[f], d)
+    return dict(zip(("rho'", "u", "v", "w", "theta'"), worst))
 
 
 def imex3d(numa, torch, steps=10, order=6, restart=30, learned=True):
@@ -457,6 +562,7 @@ def main():
     torch.cuda.synchronize()
     t_factor = time.perf_counter() - t0
     q = torch.from_numpy(W.make_initial_state(wl)).to("cuda")
+    rhs_config = numa.autotune(ctx.ctx, q.data_ptr(), reps=5)
 
     ctx.step(q, args.warmup)
     ctx.check()
@@ -501,6 +607,7 @@ def main():
             "dt_s": wl.dt,
             "element_local_dof_steps_per_s": 5 * g.n_local * args.steps / t,
             "factor_s": t_factor,
+            "rhs_config": rhs_config,
         },
         "roofline": {
             "bound": "hbm",
@@ -520,6 +627,8 @@ def main():
     out["column_solver"] = {"in_use": "blocked" if info["column_solver"] == numa.SOLVER_BLOCKED else "band",
                             "band_substitution": column_solver_ab(numa, torch, wl,
                                                                   torch.from_numpy(W.make_initial_state(wl)).to("cuda"))}
+    out["per_column_factors"] = per_column_factors(numa, torch)
+    out["stratified"] = stratified_leg(numa, torch)
     if not args.no_precision:
         out["precision_form"] = precision_form(numa, torch, ctx, wl, args, t)
         out["precision_form_n7"] = precision_form_n7(numa, torch)
@@ -527,6 +636,9 @@ def main():
         out["batched_ensemble"] = batched_ensemble(numa, torch)
     if not args.no_imex3d:
         out["imex3d"] = imex3d(numa, torch, learned=not args.no_learned)
+    cp = copy_probe()
+    out["copy_probe"] = cp
+    out["roofline"]["frac_of_copy"] = achieved / cp["copy_GBps"]
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline()
