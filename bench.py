@@ -429,12 +429,11 @@ def imex3d(numa, torch, steps=10, order=6, restart=30, learned=True):
 def imex3d_learned(numa, torch, ctx, wl, q0, order, restart, runs):
     """The learned correction: trained on 3 fields' element patches (24,576
     samples: one Schur right-hand side of a stage-like state, two seeded
-    random fields), then the same steps with it enabled."""
+    random fields), judged by PBNO on a stage-like system (kept only if it
+    needs fewer GMRES iterations), then the same steps with the judged
+    configuration."""
     from paper_1702_04316_amd import workloads as W
     g = wl.grid
-    # learned correction: trained on 3 fields' element patches (24,576
-    # samples: one Schur right-hand side of a stage-like state, two seeded
-    # random fields), then the same steps with it enabled
     ctx.imex3d_setup(wl.dt, restart=restart, pbno_order=order, power_steps=30, maxit=5000)
     ne = g.nex * g.ney * g.nez
     t0 = time.perf_counter()
@@ -459,7 +458,14 @@ def imex3d_learned(numa, torch, ctx, wl, q0, order, restart, runs):
     t_train = time.perf_counter() - t0
     loss_after = numa.learned_loss_grad(ctx.ctx, Xs.data_ptr(), Ts.data_ptr(), 3 * ne, gr.data_ptr())
     del Xs, Ts, gr
-    numa.learned_enable(ctx.ctx, True)
+    # PBNO judges the network on a stage-like system; the steps below run
+    # with it only if it was accepted
+    y = q0 + 0.5 * wl.dt * R1
+    xj = torch.empty_like(y)
+    t0 = time.perf_counter()
+    judge = numa.learned_judge(ctx.ctx, y.data_ptr(), xj.data_ptr(), W.IMEX3D_TOL)
+    judge["s"] = time.perf_counter() - t0
+    del xj
     q = q0.clone()
     ctx.imex3d_step(q, W.IMEX3D_TOL)
     torch.cuda.synchronize()
@@ -475,7 +481,8 @@ def imex3d_learned(numa, torch, ctx, wl, q0, order, restart, runs):
         "network": "per-element perceptron %d-16-%d, tanh, FP32" % ((g.N + 1) ** 3, (g.N + 1) ** 3),
         "samples": 3 * ne, "sample_solve_iters": sample_iters, "sample_s": t_samples,
         "train_steps": 2000, "batch": 1024, "train_s": t_train, "loss_all_samples_before": loss_before,
-        "loss_all_samples_after": loss_after,
+        "loss_all_samples_after": loss_after, "judge": judge,
+        "network_in_timed_steps": judge["accepted"],
         "gain_vs_polynomial": runs["pbno%d" % order]["ms_per_step"] / (1e3 * t)}
 
 

@@ -403,7 +403,16 @@ int numa_imex3d_step(numa_ctx *c, double *state, double dt, double tol, int32_t 
  * numa_learned_train: `steps` Adam steps (lr; betas 0.9, 0.999) on batches of
  * `batch` consecutive samples at seeded offsets; losses of the first and
  * last batch to the host pointers (nullable).  Synchronous.
- * numa_learned_enable: on != 0 uses the correction in the 3D-IMEX solves.
+ * numa_learned_enable: on != 0 uses the correction in the 3D-IMEX solves
+ * (unconditionally: numa_learned_judge is the checked way to switch it on).
+ * numa_learned_judge: PBNO as the judge of the network.  Solves
+ * (I - lambda L) x = y (y, x device 5-field states, distinct, the lambda of
+ * numa_imex3d_setup) to tol twice: flexible GMRES with the network, then
+ * the polynomial alone; x receives the second solution.  The network is
+ * accepted, and left switched on, only if its solve converged in fewer
+ * GMRES iterations than the polynomial's; otherwise it is switched off.
+ * out[3] (host) = {polynomial iterations, network iterations, accepted}.
+ * NUMA_E_NOT_CONVERGED if the polynomial solve does not converge.
  * numa_learned_apply: z = s(S) r + corr(r) (device fields, distinct).
  * Errors: NUMA_E_ARG, NUMA_E_NOT_FACTORED (no numa_imex3d_setup /
  * numa_learned_setup), NUMA_E_NOT_CONVERGED (a sample solve), NUMA_E_HIP.
@@ -417,6 +426,7 @@ int numa_learned_loss_grad(numa_ctx *c, const float *X, const float *T, int64_t 
 int numa_learned_train(numa_ctx *c, int32_t steps, int32_t batch, double lr, uint64_t seed, double *loss_first,
                        double *loss_last);
 int numa_learned_enable(numa_ctx *c, int32_t on);
+int numa_learned_judge(numa_ctx *c, const double *y, double *x, double tol, int32_t *out);
 int numa_learned_apply(numa_ctx *c, const double *r, double *z);
 
 /*

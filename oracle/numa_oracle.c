@@ -1244,6 +1244,28 @@ int orc_solve3d_learned(orc_ctx *c, const double *y, double *x, double lambda, d
     return rc ? rc : grc;
 }
 
+/* The polynomial judges the network: the same system solved to tol with
+ * the network (flexible GMRES, its fallback included) and with the
+ * polynomial alone; the network is accepted only if its solve converged in
+ * fewer GMRES iterations.  out = {polynomial iterations, network
+ * iterations, accepted}.  -6 if the polynomial solve does not converge. */
+int orc_learned_judge(orc_ctx *c, const double *y, double lambda, double tol, int restart, int maxit, int order,
+                      const double *bounds, const orc_mlp *mlp, int *out)
+{
+    if (!c || !y || !mlp || !out) return -1;
+    double *x = (double *)malloc(sizeof(double) * 5 * c->np);
+    if (!x) return -5;
+    int it_net = 0, it_pb = 0;
+    int rn = orc_solve3d_learned(c, y, x, lambda, tol, restart, maxit, order, bounds, mlp, &it_net, NULL);
+    int rp = (rn == 0 || rn == -6) ? orc_solve3d(c, y, x, lambda, tol, restart, maxit, order, bounds, &it_pb) : rn;
+    free(x);
+    if (rp) return rp;
+    out[0] = it_pb;
+    out[1] = it_net;
+    out[2] = rn == 0 && it_net < it_pb;
+    return 0;
+}
+
 /* nsteps 3D-IMEX ARK2 steps: orc_step with L in place of L_V and the Schur
  * GMRES solve (PBNO order and interval as orc_solve3d; restart 30); linear
  * != 0: R := L.  *iters: GMRES iterations of all solves. */

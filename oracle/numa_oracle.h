@@ -127,6 +127,13 @@ int orc_learned_apply(orc_ctx *c, const double *r, double *z, double lambda, int
                       const orc_mlp *mlp);
 int orc_solve3d_learned(orc_ctx *c, const double *y, double *x, double lambda, double tol, int restart, int maxit,
                         int order, const double *bounds, const orc_mlp *mlp, int *iters, int *net_cycles);
+/* orc_learned_judge: the polynomial as the judge of the network: solves
+ * the same system to tol with the network (orc_solve3d_learned) and with
+ * the polynomial alone (orc_solve3d); out[3] = {polynomial iterations,
+ * network iterations, accepted}, accepted only if the network's solve
+ * converged in fewer iterations.  -6 if the polynomial solve does not. */
+int orc_learned_judge(orc_ctx *c, const double *y, double lambda, double tol, int restart, int maxit, int order,
+                      const double *bounds, const orc_mlp *mlp, int *out);
 /* nsteps 3D-IMEX ARK2 steps (orc_step with L in place of L_V and the Schur
  * GMRES solve to tol; linear as in orc_step).  *iters: GMRES iterations in
  * total. */

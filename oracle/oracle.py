@@ -71,9 +71,11 @@ def _load():
     lib.orc_learned_apply.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_int, _dp, C.POINTER(OrcMlp)]
     lib.orc_solve3d_learned.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
                                         _dp, C.POINTER(OrcMlp), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    lib.orc_learned_judge.argtypes = [C.c_void_p, _dp, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, _dp,
+                                      C.POINTER(OrcMlp), C.POINTER(C.c_int)]
     for name in ("orc_schur_apply", "orc_schur_rhs", "orc_pbno_apply", "orc_schur_bounds", "orc_solve3d",
                  "orc_solve3d_standard", "orc_step3d", "orc_element_features", "orc_mlp_correction",
-                 "orc_learned_apply", "orc_solve3d_learned"):
+                 "orc_learned_apply", "orc_solve3d_learned", "orc_learned_judge"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -334,3 +336,14 @@ class Oracle:
                                         int(maxit), int(order), bd, C.byref(mlp.s) if mlp is not None else None,
                                         C.byref(it), C.byref(nc)), "orc_solve3d_learned")
         return (x, it.value, nc.value) if with_cycles else (x, it.value)
+
+    def learned_judge(self, y, lam, mlp, tol=1e-12, restart=30, maxit=100000, order=-1, bounds=None):
+        """The polynomial judges the network on (I - lam L) x = y: returns
+        (polynomial iterations, network iterations, accepted)."""
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        assert y.shape == self.shape
+        out = (C.c_int * 3)()
+        bd = np.ascontiguousarray(bounds if bounds is not None else (1.0, 2.0), dtype=np.float64)
+        _check(_lib.orc_learned_judge(self.h, y.reshape(-1), float(lam), float(tol), int(restart), int(maxit),
+                                      int(order), bd, C.byref(mlp.s), out), "orc_learned_judge")
+        return int(out[0]), int(out[1]), bool(out[2])

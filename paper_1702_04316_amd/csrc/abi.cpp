@@ -706,6 +706,33 @@ int numa_learned_enable(numa_ctx *c, int32_t on)
     return NUMA_OK;
 }
 
+// PBNO judges the network: the flexible solve with it must reach tol in
+// fewer GMRES iterations than the polynomial alone on the same system.
+int numa_learned_judge(numa_ctx *c, const double *y, double *x, double tol, int32_t *out)
+{
+    if (!c) return NUMA_E_ARG;
+    if (!y || !x || !out || y == x || !(tol > 0.0) || !std::isfinite(tol))
+        return fail(c, NUMA_E_ARG, "numa_learned_judge: bad arguments");
+    int rc = imex3d_ready(c, "numa_learned_judge");
+    if (rc != NUMA_OK) return rc;
+    if ((rc = learned_ready(c, "numa_learned_judge")) != NUMA_OK) return rc;
+    out[0] = out[1] = out[2] = 0;
+    int it_net = 0, conv_net = 0, it_pb = 0, conv_pb = 0;
+    numa::learned_set_enabled(c, 1);
+    hipError_t e = numa::imex3d_solve(c, y, x, nullptr, 0.0, nullptr, 0.0, tol, &it_net, &conv_net);
+    numa::learned_set_enabled(c, 0);
+    if (e == hipSuccess) e = numa::imex3d_solve(c, y, x, nullptr, 0.0, nullptr, 0.0, tol, &it_pb, &conv_pb);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "numa_learned_judge");
+    if (!conv_pb) return fail(c, NUMA_E_NOT_CONVERGED, "numa_learned_judge: the polynomial solve did not converge");
+    const int accepted = conv_net && it_net < it_pb;
+    numa::learned_set_enabled(c, accepted);
+    out[0] = it_pb;
+    out[1] = it_net;
+    out[2] = accepted;
+    return NUMA_OK;
+}
+
 int numa_learned_apply(numa_ctx *c, const double *r, double *z)
 {
     if (!c) return NUMA_E_ARG;

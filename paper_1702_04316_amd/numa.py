@@ -115,6 +115,7 @@ def load():
                                        C.POINTER(C.c_double)]
     lib.numa_learned_enable.argtypes = [vp, C.c_int32]
     lib.numa_learned_apply.argtypes = [vp, vp, vp]
+    lib.numa_learned_judge.argtypes = [vp, vp, vp, C.c_double, C.POINTER(C.c_int32)]
     lib.numa_check.argtypes = [vp]
     lib.numa_destroy.argtypes = [vp]
     lib.numa_last_error.argtypes = [vp]
@@ -130,7 +131,7 @@ def load():
                  "numa_imex3d_bounds", "numa_imex3d_set_bounds", "numa_schur_apply", "numa_schur_rhs",
                  "numa_pbno_apply", "numa_imex3d_solve", "numa_learned_setup", "numa_learned_info",
                  "numa_learned_add_samples", "numa_learned_samples", "numa_learned_params", "numa_learned_loss_grad",
-                 "numa_learned_train", "numa_learned_enable", "numa_learned_apply", "numa_factor_columns_standard",
+                 "numa_learned_train", "numa_learned_enable", "numa_learned_apply", "numa_learned_judge", "numa_factor_columns_standard",
                  "numa_solve_columns_standard", "numa_set_column_solver", "numa_autotune",
                  "numa_set_rhs_config", "numa_get_rhs_config"):
         getattr(lib, name).restype = C.c_int
@@ -411,6 +412,14 @@ def learned_train(ctx, steps, batch=1024, lr=1e-3, seed=7):
 
 def learned_enable(ctx, on):
     return _check(load().numa_learned_enable(ctx, 1 if on else 0), ctx)
+
+
+def learned_judge(ctx, y_ptr, x_ptr, tol):
+    """PBNO judges the network on (I - lambda L) x = y; returns
+    {pbno_iters, net_iters, accepted} (the network stays on if accepted)."""
+    out = (C.c_int32 * 3)()
+    _check(load().numa_learned_judge(ctx, C.c_void_p(y_ptr), C.c_void_p(x_ptr), float(tol), out), ctx)
+    return {"pbno_iters": int(out[0]), "net_iters": int(out[1]), "accepted": bool(out[2])}
 
 
 def learned_apply(ctx, r_ptr, z_ptr):

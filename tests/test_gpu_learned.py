@@ -42,10 +42,15 @@ def _dt(g):
     return min(W.dt_for_courant(g, 15.0, "x"), W.dt_for_courant(g, 15.0, "y"), W.dt_for_courant(g, 15.0, "z"))
 
 
-def _setup(numa, g, order=2, hidden=16, cap=None, seed=3):
+def _setup(numa, g, o=None, order=2, hidden=16, cap=None, seed=3):
+    """Context, dt and PBNO interval: the oracle's interval (o given), set on
+    the GPU solver too, so that both sides use the same polynomial."""
     ctx = numa.Context(g)
     dt = _dt(g)
     bd = ctx.imex3d_setup(dt, restart=30, pbno_order=order, power_steps=30, maxit=5000)
+    if o is not None:
+        bd = o.schur_bounds((1.0 - 1.0 / np.sqrt(2.0)) * dt, 30)
+        numa.imex3d_set_bounds(ctx.ctx, *bd)
     nelem = g.nex * g.ney * g.nez
     numa.learned_setup(ctx.ctx, hidden=hidden, max_samples=cap or 4 * nelem, seed=seed)
     return ctx, dt, bd
@@ -73,7 +78,7 @@ def _dense_schur(o, lam, shape):
 def test_samples_parity(torch_cuda, numa_mod, oracle_mod):
     g = _grid()
     o = _oracle(oracle_mod, g)
-    ctx, dt, bd = _setup(numa_mod, g)
+    ctx, dt, bd = _setup(numa_mod, g, o)
     lam = (1.0 - 1.0 / np.sqrt(2.0)) * dt
     rng = np.random.default_rng(5)
     r = rng.standard_normal(g.shape[1:]) * 100.0
@@ -126,7 +131,7 @@ def test_loss_gradient_parity(torch_cuda, numa_mod, oracle_mod):
 def test_learned_apply_parity(torch_cuda, numa_mod, oracle_mod):
     g = _grid(N=3, nex=1, ney=3, nez=2)  # a single element along x: the node gather wraps onto itself
     o = _oracle(oracle_mod, g)
-    ctx, dt, bd = _setup(numa_mod, g, order=1, hidden=10)
+    ctx, dt, bd = _setup(numa_mod, g, o, order=1, hidden=10)
     lam = (1.0 - 1.0 / np.sqrt(2.0)) * dt
     info = numa_mod.learned_info(ctx.ctx)
     theta = np.zeros(info["nparam"], dtype=np.float32)
@@ -156,8 +161,9 @@ def test_training_and_flexible_solve(torch_cuda, numa_mod, oracle_mod):
     ne = g.nex * g.ney * g.nez
     ctx = numa_mod.Context(g)
     ctx.imex3d_setup(wl.dt, restart=30, pbno_order=2, power_steps=30, maxit=5000)
-    bd = numa_mod.imex3d_bounds(ctx.ctx)
     lam = (1.0 - 1.0 / np.sqrt(2.0)) * wl.dt
+    bd = o.schur_bounds(lam, 30)
+    numa_mod.imex3d_set_bounds(ctx.ctx, *bd)
     nfields = 72
     numa_mod.learned_setup(ctx.ctx, hidden=16, max_samples=nfields * ne, seed=3)
     q0 = W.make_initial_state(wl)
@@ -187,6 +193,99 @@ def test_training_and_flexible_solve(torch_cuda, numa_mod, oracle_mod):
     xp, itp = o.solve3d(y, lam, tol=1e-10, order=2, bounds=bd)
     assert abs(it_pb - itp) <= 1
     print(f"\nGMRES iterations to 1e-10: PBNO(2) {it_pb}, PBNO(2) + network {it_net} (oracle {ito})")
+    # PBNO judges the trained network on the same system, as the oracle does
+    xj = torch_cuda.empty_like(yd)
+    jd = numa_mod.learned_judge(ctx.ctx, yd.data_ptr(), xj.data_ptr(), 1e-10)
+    po, qo, acc_o = o.learned_judge(y, lam, m, tol=1e-10, order=2, bounds=bd)
+    print(f"judge: {jd} (oracle {po}, {qo}, {acc_o})")
+    assert jd["pbno_iters"] == it_pb and jd["net_iters"] == it_net
+    assert jd["accepted"] == (it_net < it_pb)
+    if abs(qo - po) > 3:
+        assert jd["accepted"] == acc_o
+    assert numa_mod.learned_info(ctx.ctx)["enabled"] == int(jd["accepted"])
+    assert np.linalg.norm(xj.cpu().numpy() - x_pb.cpu().numpy()) <= 1e-12 * np.linalg.norm(x_pb.cpu().numpy())
+    # what the judged configuration then costs: at most PBNO's iterations
+    # (the network kept only where it took fewer)
+    _, it_after = ctx.imex3d_solve(yd, 1e-10)
+    assert it_after <= it_pb, (it_after, it_pb)
+    ctx.close()
+
+
+def _diagonal_mlp(O, o, g, lam, scale, eps=1e-3):
+    """A network in its linear regime (tanh(eps t) = eps t to 1e-7) whose
+    output is D x, D the mean over the elements of 1/diag(S) at each local
+    node: a Jacobi-like correction added to the polynomial."""
+    shape = g.shape[1:]
+    n = int(np.prod(shape))
+    diag = np.empty(n)
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        diag[j] = o.schur_apply(e.reshape(shape), lam).reshape(-1)[j]
+    diag = diag.reshape(shape)
+    nq = g.N + 1
+    nin = nq ** 3
+    acc = np.zeros(nin)
+    for ez in range(g.nez):
+        for ey in range(g.ney):
+            for ex in range(g.nex):
+                for c in range(nq):
+                    for b in range(nq):
+                        for a in range(nq):
+                            k, j, i = ez * g.N + c, (ey * g.N + b) % shape[1], (ex * g.N + a) % shape[2]
+                            acc[a + nq * (b + nq * c)] += 1.0 / diag[k, j, i]
+    d = scale * acc / (g.nex * g.ney * g.nez)
+    return O.Mlp(eps * np.eye(nin), np.zeros(nin), np.diag(d) / eps, np.zeros(nin))
+
+
+def _theta_of(m):
+    return np.concatenate([m.W1.reshape(-1), m.b1, m.W2.reshape(-1), m.b2]).astype(np.float32)
+
+
+@pytest.mark.parametrize("kind", ["diagonal", "zero", "random"])
+def test_judge_matches_oracle(torch_cuda, numa_mod, oracle_mod, kind):
+    """PBNO as the judge: the GPU's decision and both iteration counts agree
+    with the oracle's judge on the same weights.  A diagonal correction
+    (mean 1/diag(S) per local node) takes fewer iterations than PBNO(2) and
+    is accepted; a zero network ties and large random weights lose: both are
+    rejected and the solver is back on the polynomial alone."""
+    g = W.Grid(3000.0, 2500.0, 2000.0, 2, 2, 2, 3)
+    o = _oracle(oracle_mod, g)
+    nin = (g.N + 1) ** 3
+    ctx = numa_mod.Context(g)
+    dt = W.dt_for_courant(g, 15.0, "x")
+    lam = (1.0 - 1.0 / np.sqrt(2.0)) * dt
+    ctx.imex3d_setup(dt, restart=30, pbno_order=2, power_steps=30, maxit=5000)
+    bd = o.schur_bounds(lam, 30)
+    numa_mod.imex3d_set_bounds(ctx.ctx, *bd)
+    numa_mod.learned_setup(ctx.ctx, hidden=nin, max_samples=8, seed=1)
+    if kind == "diagonal":
+        m = _diagonal_mlp(oracle_mod, o, g, lam, 0.5)
+    elif kind == "zero":
+        m = oracle_mod.Mlp(np.zeros((nin, nin)), np.zeros(nin), np.zeros((nin, nin)), np.zeros(nin))
+    else:
+        rng = np.random.default_rng(5)
+        m = oracle_mod.Mlp(30.0 * rng.standard_normal((nin, nin)), 30.0 * rng.standard_normal(nin),
+                           30.0 * rng.standard_normal((nin, nin)), 30.0 * rng.standard_normal(nin))
+    theta = _theta_of(m)
+    numa_mod.learned_params(ctx.ctx, theta_in=theta)
+    m = _mlp_from_theta(oracle_mod, theta, nin, nin)  # the FP32 weights the GPU runs
+    y = W.make_random_state(g, 3, smooth=False)
+    yd = torch_cuda.from_numpy(y).cuda()
+    x = torch_cuda.empty_like(yd)
+    jd = numa_mod.learned_judge(ctx.ctx, yd.data_ptr(), x.data_ptr(), 1e-10)
+    po, qo, acc_o = o.learned_judge(y, lam, m, tol=1e-10, order=2, bounds=bd)
+    print(f"{kind}: GPU {jd}, oracle ({po}, {qo}, {acc_o})")
+    assert abs(jd["pbno_iters"] - po) <= 1
+    assert abs(jd["net_iters"] - qo) <= max(3, 0.15 * qo)
+    assert jd["accepted"] == acc_o == (kind == "diagonal")
+    assert numa_mod.learned_info(ctx.ctx)["enabled"] == int(acc_o)
+    xo, _ = o.solve3d(y, lam, tol=1e-10, order=2, bounds=bd)
+    xh = x.cpu().numpy()
+    for f in range(5):
+        assert np.linalg.norm(xh[f] - xo[f]) <= 1e-7 * np.linalg.norm(xo[f]) + 1e-300, f
+    _, it_after = ctx.imex3d_solve(yd, 1e-10)
+    assert it_after <= jd["pbno_iters"] + 1, (it_after, jd)
     ctx.close()
 
 
@@ -195,7 +294,7 @@ def test_fallback_keeps_a_bad_network_harmless(torch_cuda, numa_mod, oracle_mod)
     residual tenfold, the network is switched off and the solve converges."""
     g = _grid(N=3, nex=3, ney=3, nez=2)
     o = _oracle(oracle_mod, g)
-    ctx, dt, bd = _setup(numa_mod, g, order=2, hidden=8)
+    ctx, dt, bd = _setup(numa_mod, g, o, order=2, hidden=8)
     lam = (1.0 - 1.0 / np.sqrt(2.0)) * dt
     info = numa_mod.learned_info(ctx.ctx)
     theta = (3.0 * np.random.default_rng(9).standard_normal(info["nparam"])).astype(np.float32)

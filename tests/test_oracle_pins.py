@@ -1019,6 +1019,60 @@ def test_flexible_gmres_with_and_without_network(oracle_mod):
     assert np.linalg.norm(res) < 1e-9 * np.linalg.norm(y)
 
 
+def _diagonal_mlp(oracle_mod, o, g, lam, scale, eps=1e-3):
+    """A network in its linear regime (tanh(eps t) = eps t to 1e-7) whose
+    output is D x, D the mean over the elements of 1/diag(S) at each local
+    node: the correction is then a diagonal (Jacobi-like) preconditioner
+    added to the polynomial."""
+    shape = g.shape[1:]
+    n = int(np.prod(shape))
+    diag = np.empty(n)
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        diag[j] = o.schur_apply(e.reshape(shape), lam).reshape(-1)[j]
+    diag = diag.reshape(shape)
+    nq = g.N + 1
+    nin = nq ** 3
+    acc = np.zeros(nin)
+    for ez in range(g.nez):
+        for ey in range(g.ney):
+            for ex in range(g.nex):
+                for c in range(nq):
+                    for b in range(nq):
+                        for a in range(nq):
+                            k, j, i = ez * g.N + c, (ey * g.N + b) % shape[1], (ex * g.N + a) % shape[2]
+                            acc[a + nq * (b + nq * c)] += 1.0 / diag[k, j, i]
+    d = scale * acc / (g.nex * g.ney * g.nez)
+    return oracle_mod.Mlp(eps * np.eye(nin), np.zeros(nin), np.diag(d) / eps, np.zeros(nin))
+
+
+def test_learned_judge_accepts_only_fewer_iterations(oracle_mod):
+    """The polynomial judges the network on the same system: accepted only
+    if the flexible solve with it converges in fewer GMRES iterations.  A
+    diagonal correction of the mean 1/diag(S) helps PBNO of order 2 on this
+    grid (accepted), a zero network reproduces the polynomial's iterations
+    exactly (a tie: rejected) and large random weights need more iterations
+    (rejected).  Each count is checked against the plain solves."""
+    g = _G3
+    o = _oracle(oracle_mod, g)
+    lam = (1.0 - 1.0 / math.sqrt(2.0)) * W.dt_for_courant(g, 15.0, "x")
+    bd = o.schur_bounds(lam, 30)
+    y = W.make_random_state(g, 3, smooth=False)
+    nin = (g.N + 1) ** 3
+    _, it_pb = o.solve3d(y, lam, tol=1e-10, order=2, bounds=bd)
+    diag = _diagonal_mlp(oracle_mod, o, g, lam, 0.5)
+    zero = oracle_mod.Mlp(np.zeros((8, nin)), np.zeros(8), np.zeros((nin, 8)), np.zeros(nin))
+    bad = _random_mlp(oracle_mod, nin, 8, 5, scale=30.0)
+    for m, accept in ((diag, True), (zero, False), (bad, False)):
+        p, q, acc = o.learned_judge(y, lam, m, tol=1e-10, order=2, bounds=bd)
+        _, it_net = o.solve3d_learned(y, lam, m, tol=1e-10, order=2, bounds=bd)
+        assert (p, q) == (it_pb, it_net)
+        assert acc == accept and acc == (q < p), (p, q, acc)
+    assert o.learned_judge(y, lam, diag, tol=1e-10, order=2, bounds=bd)[1] < 0.8 * it_pb
+    assert o.learned_judge(y, lam, zero, tol=1e-10, order=2, bounds=bd)[1] == it_pb
+
+
 def test_learned_guard_drops_a_failing_network_after_one_cycle(oracle_mod):
     """The fallback rule of the learned preconditioner: a restart cycle with
     the network that does not cut the true residual tenfold switches it off.
