@@ -272,16 +272,13 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8, V>::NT), (RhsGeom<N, MIX ?
     auto pfield = [&](int slot) { return reinterpret_cast<double *>(ringb + slot * G::PB + G::POFF); };
     auto rfield = [&](int slot) { return reinterpret_cast<double *>(ringb + slot * G::PB + G::ROFF); };
     auto wfield = [&](int slot) { return reinterpret_cast<double *>(ringb + slot * G::PB + G::WOFF); };
-    __shared__ C sw[2][N][NS];
+    // line stencils (FP64 in both forms: the line sums round them for their
+    // FP32 products) and the differentiation matrix (FP32 in the precision
+    // form, with an FP64 copy for its FP64 column sums)
+    __shared__ double sw[2][N][NS];
     __shared__ C sD[NQ * NQ];
-    // FP64 copies of the tables for the mass flux of the precision form (the
-    // FP64 form reads sw and sD themselves)
-    __shared__ double swd_m[MIX ? 2 * N * NS : 1];
     __shared__ double sDd_m[MIX ? NQ * NQ : 1];
-    const double *const swd = [&]() -> const double * {
-        if constexpr (MIX) return swd_m;
-        else return &sw[0][0][0];
-    }();
+    const double *const swd = &sw[0][0][0];
     const double *const sDd = [&]() -> const double * {
         if constexpr (MIX) return sDd_m;
         else return sD;
@@ -312,8 +309,7 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8, V>::NT), (RhsGeom<N, MIX ?
     const EOS eos = p.eos;
 
     for (int s = tid; s < 2 * N * NS; s += G::NT) {
-        (&sw[0][0][0])[s] = C(p.wxy[s]);
-        if constexpr (MIX) swd_m[s] = p.wxy[s];
+        (&sw[0][0][0])[s] = p.wxy[s];
     }
     for (int s = tid; s < NQ * NQ; s += G::NT) {
         sD[s] = C(p.D[s]);
@@ -381,8 +377,6 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8, V>::NT), (RhsGeom<N, MIX ?
     const int l_own = (ty + N) * LX + (tx + N);
     const int l_x = (ty + N) * LX + (tx - ax);
     const int l_y = (ty - ay) * LX + (tx + N);
-    const C *cwx = &sw[0][0][0] + ax * NS;
-    const C *cwy = &sw[1][0][0] + ay * NS;
     const double *cwxd = swd + ax * NS;
     const double *cwyd = swd + (N + ay) * NS;
 
@@ -522,7 +516,6 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8, V>::NT), (RhsGeom<N, MIX ?
         // line derivative of the six quantities along x (dir 0) or y (dir 1)
         // (not unrolled: unrolled, the scheduler hoists all its LDS reads)
         auto line = [&](int dir, C *d5, double &dp, double &dfl, double &dwl) {
-            const C *cw = dir == 0 ? cwx : cwy;
             const double *cwd = dir == 0 ? cwxd : cwyd;
             const double *rq = rfield(k % NQ);
             const double *wq = wfield(k % NQ);
@@ -536,16 +529,19 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8, V>::NT), (RhsGeom<N, MIX ?
             dwl = 0.0;
 #pragma unroll 1
             for (int m = 0; m < NS; ++m) {
-                const C cm = cw[m];
+                // one coefficient read: the FP64 table (the only one in the
+                // FP64 form), rounded for the FP32 products
+                const double cmd = cwd[m];
+                const C cm = C(cmd);
                 const C *qm = q + base + m * step;
-                if constexpr (MIX) dfl += cwd[m] * ((sR0[k - kb] + rq[base + m * step]) * (vr + double(qm[fv])));
-                else dfl += double(cm) * ((r0 + qm[0]) * qm[fv]);
+                if constexpr (MIX) dfl += cmd * ((sR0[k - kb] + rq[base + m * step]) * (vr + double(qm[fv])));
+                else dfl += cmd * ((r0 + qm[0]) * qm[fv]);
                 d5[1] += cm * qm[1 * FS];
                 d5[2] += cm * qm[2 * FS];
-                if constexpr (MIX) dwl += cwd[m] * wq[base + m * step];
-                else dwl += double(cm) * qm[3 * FS];
+                if constexpr (MIX) dwl += cmd * wq[base + m * step];
+                else dwl += cmd * qm[3 * FS];
                 d5[4] += cm * qm[4 * FS];
-                dp += double(cm) * qp[base + m * step];
+                dp += cmd * qp[base + m * step];
             }
         };
         C d5[5];
