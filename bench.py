@@ -391,8 +391,9 @@ def imex3d(numa, torch, steps=10, order=6, restart=30, learned=True):
     """The 3D-IMEX step (all acoustics implicit, Schur-complement GMRES with
     PBNO) on 32x32x8 elements, N=5, at acoustic Courant number 15 in every
     direction, tol 1e-8: throughput, simulated seconds per wall second,
-    GMRES iterations per step, the same with PBNO order 1 and without a
-    preconditioner, and the Schur operator kernel against the HBM roofline
+    GMRES iterations per step, the same with the FP32 polynomial (flexible
+    GMRES), with PBNO order 1 and without a preconditioner, and the Schur
+    operator kernel against the HBM roofline
     (HIP events on the context's stream around 50 launches)."""
     from paper_1702_04316_amd import workloads as W
     wl = W.box_imex3d("full")
@@ -403,9 +404,11 @@ def imex3d(numa, torch, steps=10, order=6, restart=30, learned=True):
            f"{g.nx}x{g.ny}x{g.nz} unique nodes, acoustic Courant 15 on the finest spacing, tol {W.IMEX3D_TOL}",
            "dt_s": wl.dt, "unique_nodes": g.n_unique}
     runs = {}
-    for name, p, n in (("pbno%d" % order, order, steps), ("pbno1", 1, 3), ("none", -1, 3)):
+    for name, p, n, f32 in (("pbno%d" % order, order, steps, False), ("pbno%d_fp32" % order, order, steps, True),
+                            ("pbno1", 1, 3, False), ("none", -1, 3, False)):
         t0 = time.perf_counter()
         bd = ctx.imex3d_setup(wl.dt, restart=restart, pbno_order=p, power_steps=30, maxit=5000)
+        numa.imex3d_set_precision(ctx.ctx, f32)
         torch.cuda.synchronize()
         t_setup = time.perf_counter() - t0
         q = q0.clone()
@@ -416,7 +419,7 @@ def imex3d(numa, torch, steps=10, order=6, restart=30, learned=True):
         torch.cuda.synchronize()
         t = (time.perf_counter() - t0) / n
         ctx.check()
-        runs[name] = {"pbno_order": p, "restart": restart, "ms_per_step": 1e3 * t,
+        runs[name] = {"pbno_order": p, "pbno_fp32": f32, "restart": restart, "ms_per_step": 1e3 * t,
                       "value": 5 * g.n_unique / t, "sim_s_per_wall_s": wl.dt / t,
                       "gmres_iters_per_step": sum(its) / n, "setup_s": t_setup, "interval": list(bd)}
     if learned:
@@ -425,7 +428,8 @@ def imex3d(numa, torch, steps=10, order=6, restart=30, learned=True):
     best = runs["pbno%d" % order]
     out.update({"value": best["value"], "unit": "DOF-steps/s", "ms_per_step": best["ms_per_step"],
                 "sim_s_per_wall_s": best["sim_s_per_wall_s"],
-                "pbno_speedup_vs_none": runs["none"]["ms_per_step"] / best["ms_per_step"]})
+                "pbno_speedup_vs_none": runs["none"]["ms_per_step"] / best["ms_per_step"],
+                "fp32_pbno_speedup": best["ms_per_step"] / runs["pbno%d_fp32" % order]["ms_per_step"]})
     return imex3d_roofline(numa, torch, ctx, g, out)
 
 

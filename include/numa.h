@@ -345,6 +345,16 @@ int numa_solve_columns_standard(numa_ctx *c, const double *y, double *x);
  * Errors: NUMA_E_ARG, NUMA_E_NOMEM, NUMA_E_HIP.
  * numa_imex3d_bounds: out[2] (host) = {lmin, lmax}.  numa_imex3d_set_bounds:
  * overrides them (0 < lmin < lmax).
+ * numa_imex3d_set_precision: pbno_fp32 = 1 runs the PBNO recurrence (orders
+ * >= 1) in FP32: the residual is rounded to FP32, the p applications of S
+ * use FP32 fields, tables and sums, and the result is widened to FP64 (a
+ * preconditioner only has to approximate S^-1; the Krylov vectors, S in the
+ * Arnoldi step and the stopping test stay FP64).  Rounding makes the
+ * polynomial differ slightly between applications, so the solves then run
+ * flexible GMRES (the Z basis), which converges to the same true-residual
+ * tolerance.  0 (the default after numa_imex3d_setup) is the FP64
+ * polynomial.  Also applies to numa_pbno_apply.  Errors: NUMA_E_ARG,
+ * NUMA_E_NOT_FACTORED (no numa_imex3d_setup).
  *
  * numa_schur_apply (out = S P), numa_schur_rhs (b from y) and
  * numa_pbno_apply (z = s(S) r): single device fields of nz*ny*nx doubles
@@ -364,6 +374,7 @@ int numa_imex3d_setup(numa_ctx *c, double dt, int32_t restart, int32_t pbno_orde
                       int32_t maxit);
 int numa_imex3d_bounds(const numa_ctx *c, double *out);
 int numa_imex3d_set_bounds(numa_ctx *c, double lmin, double lmax);
+int numa_imex3d_set_precision(numa_ctx *c, int32_t pbno_fp32);
 int numa_schur_apply(numa_ctx *c, const double *P, double *out);
 int numa_schur_rhs(numa_ctx *c, const double *y, double *b);
 int numa_pbno_apply(numa_ctx *c, const double *r, double *z);

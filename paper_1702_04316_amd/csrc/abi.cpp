@@ -506,6 +506,15 @@ int numa_imex3d_set_bounds(numa_ctx *c, double lmin, double lmax)
     return NUMA_OK;
 }
 
+int numa_imex3d_set_precision(numa_ctx *c, int32_t pbno_fp32)
+{
+    if (!c) return NUMA_E_ARG;
+    if (!c->imex) return fail(c, NUMA_E_NOT_FACTORED, "numa_imex3d_set_precision: call numa_imex3d_setup first");
+    if (pbno_fp32 != 0 && pbno_fp32 != 1) return fail(c, NUMA_E_ARG, "numa_imex3d_set_precision: pbno_fp32 must be 0 or 1");
+    numa::imex3d_set_pbno32(c, pbno_fp32);
+    return NUMA_OK;
+}
+
 namespace {
 
 int imex3d_ready(numa_ctx *c, const char *who)

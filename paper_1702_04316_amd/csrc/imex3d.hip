@@ -34,6 +34,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <type_traits>
 #include <vector>
@@ -249,6 +250,89 @@ __global__ __launch_bounds__(kTB) void k_schur_apply(OpTables t, ApplyArgs a)
         for (int u = 0; u < 8; ++u) q[u] = (ok && v0 + u < a.nv) ? val * a.V[long(v0 + u) * t.np + I] : 0.0;
         block_sums<8>(q, min(8, a.nv - v0), sh + 4 * 8 * ((v0 / 8) & 7), a.part + long(v0) * a.nblk + blk, a.nblk);
     }
+}
+
+// One step of the Chebyshev recurrence of the polynomial preconditioner in
+// FP32 (the mixed-precision preconditioner): the same one-pass operator and
+// tiling as k_schur_apply's AP_CHEB mode, with FP32 fields, slab, tables and
+// sums.  res = res_in - S d, d' = c1 d + c2 res, z = z_in + d' with
+// d = scale * in (null res_in: res_in = in; null z_in: z_in = d).
+struct ChebArgs32 {
+    const float *in, *res_in, *z_in;
+    float *res_out, *d_out, *z_out;
+    float scale, c1, c2, lam2;
+    const int *stop;
+};
+
+struct OpTables32 {
+    const float *wxx, *wyy, *vb, *G0;
+    int nx, ny, nz;
+};
+
+template <int N, bool ONE>
+__global__ __launch_bounds__(kTB) void k_schur_cheb32(OpTables32 t, ChebArgs32 a)
+{
+    using G = ApplyTile<N>;
+    constexpr int W = G::W;
+    __shared__ float slab[G::R * G::C];
+    __shared__ float cx[N * W], cz[kAK * W];
+    if (a.stop && *a.stop) return;
+    const int nx = t.nx, ny = t.ny, nz = t.nz;
+    const int tx = threadIdx.x, tk = threadIdx.y, tid = tk * kAX + tx;
+    // XCD-aware block order, as k_schur_apply
+    const int gx = (nx + kAX - 1) / kAX, gk = (nz + kAK - 1) / kAK;
+    const long nb = long(gx) * gk * ny, w = blockIdx.x;
+    const long per = nb / 8, rem = nb % 8, xcd = w % 8;
+    const long L = xcd * per + min(xcd, rem) + w / 8;
+    const int bx = int(L % gx), bk = int((L / gx) % gk), j = int(L / (long(gx) * gk));
+    const int i0 = bx * kAX, k0 = bk * kAK;
+    const long plane = long(nx) * ny;
+    const float *in = a.in;
+    for (int e = tid; e < G::R * G::C; e += kTB) {
+        const int r = e / G::C, cc = e - r * G::C;
+        const int k = k0 - 2 * N + r, i = wrap(i0 - 2 * N + cc, nx);
+        slab[e] = (k >= 0 && k < nz) ? in[long(k) * plane + long(j) * nx + i] : 0.0f;
+    }
+    for (int e = tid; e < N * W; e += kTB) cx[e] = t.wxx[e];
+    for (int e = tid; e < kAK * W; e += kTB) {
+        const int k = k0 + e / W;
+        cz[e] = k < nz ? t.vb[long(k) * W + e % W] : 0.0f;
+    }
+    __syncthreads();
+    const int i = i0 + tx, k = k0 + tk;
+    if (!(i < nx && k < nz)) return;
+    const long I = long(k) * plane + long(j) * nx + i;
+    const float *wx = cx + (i % N) * W, *wz = cz + tk * W, *wy = t.wyy + (j % N) * W;
+    float sx = 0.0f, sy = 0.0f, sv = 0.0f;
+#pragma unroll
+    for (int m = 0; m < W; ++m) sx += wx[m] * slab[(tk + 2 * N) * G::C + tx + m];
+#pragma unroll
+    for (int m = 0; m < W; ++m) sv += wz[m] * slab[(tk + m) * G::C + tx + 2 * N];
+    const float *rowk = in + long(k) * plane + i;
+#pragma unroll
+    for (int m = 0; m < W; ++m) sy += wy[m] * rowk[long(wrapx<ONE>(j - 2 * N + m, ny)) * nx];
+    const float center = slab[(tk + 2 * N) * G::C + tx + 2 * N];
+    const float Sx = a.scale * (center - a.lam2 * (sv + t.G0[k] * (sx + sy)));
+    const float x = a.scale * center;
+    const float res = (a.res_in ? a.res_in[I] : center) - Sx;
+    const float dn = a.c1 * x + a.c2 * res;
+    a.z_out[I] = (a.z_in ? a.z_in[I] : x) + dn;
+    if (a.res_out) a.res_out[I] = res;
+    if (a.d_out) a.d_out[I] = dn;
+}
+
+__global__ __launch_bounds__(kTB) void k_to_f32(float *out, const double *in, long n, const int *stop)
+{
+    if (stop && *stop) return;
+    const long i = long(blockIdx.x) * kTB + threadIdx.x;
+    if (i < n) out[i] = float(in[i]);
+}
+
+__global__ __launch_bounds__(kTB) void k_to_f64(double *out, const float *in, long n, const int *stop)
+{
+    if (stop && *stop) return;
+    const long i = long(blockIdx.x) * kTB + threadIdx.x;
+    if (i < n) out[i] = double(in[i]);
 }
 
 // first derivatives along x, y (line stencils) and z (column band) of f at I
@@ -522,6 +606,10 @@ struct Imex3d {
     double *part = nullptr;                                // (restart+1) nblk
     double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *hb = nullptr, *yc = nullptr;
     double *R1 = nullptr, *Q2 = nullptr, *E3 = nullptr, *ACC = nullptr;  // 5 np each
+    // the FP32 preconditioner: tables and its five work fields
+    int pbno32 = 0;
+    float *wxx32 = nullptr, *wyy32 = nullptr, *vb32 = nullptr, *G032 = nullptr;
+    float *r32 = nullptr, *cres32 = nullptr, *d032 = nullptr, *d132 = nullptr, *z32 = nullptr;
     int *stop = nullptr;
     std::vector<double> hH, hg, hy;
 };
@@ -685,11 +773,59 @@ hipError_t norm_host(numa_ctx *c, const double *v, double *out)
     return e;
 }
 
-// dst = s(S) src, the PBNO polynomial (order < 0: dst = src)
+template <int N>
+hipError_t cheb32_launch(numa_ctx *c, const ChebArgs32 &a)
+{
+    const Imex3d &s = *c->imex;
+    OpTables32 t{s.wxx32, s.wyy32, s.vb32, s.G032, int(c->nx), int(c->ny), int(c->nz)};
+    if (one_wrap(c))
+        hipLaunchKernelGGL((k_schur_cheb32<N, true>), apply_grid(c), dim3(kAX, kAK), 0, c->stream, t, a);
+    else
+        hipLaunchKernelGGL((k_schur_cheb32<N, false>), apply_grid(c), dim3(kAX, kAK), 0, c->stream, t, a);
+    return hipGetLastError();
+}
+
+// dst = s(S) src with the recurrence in FP32 (order >= 1): src rounded to
+// FP32, p FP32 steps, the result widened to FP64
+hipError_t precondition32(numa_ctx *c, const double *src, double *dst)
+{
+    Imex3d &s = *c->imex;
+    const double theta = 0.5 * (s.lmax + s.lmin), delta = 0.5 * (s.lmax - s.lmin);
+    const double sigma = theta / delta;
+    const unsigned nb = unsigned(nblocks(s.np));
+    hipLaunchKernelGGL(k_to_f32, dim3(nb), dim3(kTB), 0, c->stream, s.r32, src, s.np, nullptr);
+    double rho = 1.0 / sigma;
+    const float *din = s.r32;
+    float *dbuf[2] = {s.d032, s.d132};
+    for (int k = 1; k <= s.order; ++k) {
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        ChebArgs32 a{};
+        a.in = din;
+        a.scale = float(k == 1 ? 1.0 / theta : 1.0);
+        a.res_in = k == 1 ? nullptr : s.cres32;
+        a.z_in = k == 1 ? nullptr : s.z32;
+        a.z_out = s.z32;
+        a.res_out = k < s.order ? s.cres32 : nullptr;
+        a.d_out = k < s.order ? dbuf[k & 1] : nullptr;
+        a.c1 = float(rn * rho);
+        a.c2 = float(2.0 * rn / delta);
+        a.lam2 = float(s.lambda * s.lambda);
+        hipError_t e = dispatch3(c->N, [&](auto n) { return cheb32_launch<decltype(n)::value>(c, a); });
+        if (e != hipSuccess) return e;
+        din = dbuf[k & 1];
+        rho = rn;
+    }
+    hipLaunchKernelGGL(k_to_f64, dim3(nb), dim3(kTB), 0, c->stream, dst, s.z32, s.np, nullptr);
+    return hipGetLastError();
+}
+
+// dst = s(S) src, the PBNO polynomial (order < 0: dst = src); in FP32 when
+// the mixed-precision preconditioner is on
 hipError_t precondition(numa_ctx *c, const double *src, double *dst)
 {
     Imex3d &s = *c->imex;
     if (s.order < 0) return hipMemcpyAsync(dst, src, sizeof(double) * s.np, hipMemcpyDeviceToDevice, c->stream);
+    if (s.pbno32 && s.order >= 1) return precondition32(c, src, dst);
     const double theta = 0.5 * (s.lmax + s.lmin), delta = 0.5 * (s.lmax - s.lmin);
     const double sigma = theta / delta;
     if (s.order == 0) {
@@ -801,8 +937,10 @@ hipError_t imex3d_setup(numa_ctx *c, double dt, int restart, int order, int powe
     // sizes in doubles
     const size_t n_tab = size_t(2 * N * W + nz * W);
     const size_t n_vec = size_t(2 * m + 1) * np + 8 * size_t(np) + 20 * size_t(np);
+    // FP32 tables and five FP32 work fields, in doubles
+    const size_t n_f32 = (size_t(2 * N * W + nz * W + nz) + 5 * size_t(np) + 8) / 2 + 8;
     const size_t n_small = size_t(m + 1) * npart + size_t(m + 1) * m + 4 * size_t(m + 2) + size_t(m + 2);
-    const size_t total = n_tab + n_vec + n_small + 64;
+    const size_t total = n_tab + n_vec + n_small + n_f32 + 64;
     hipError_t e = hipMalloc(&s->block, total * sizeof(double) + 64);
     if (e != hipSuccess) {
         s->block = nullptr;
@@ -833,6 +971,20 @@ hipError_t imex3d_setup(numa_ctx *c, double dt, int restart, int order, int powe
     s->g = p; p += m + 2;
     s->hb = p; p += m + 2;
     s->yc = p; p += m + 2;
+    {
+        float *f = reinterpret_cast<float *>(p);
+        s->wxx32 = f; f += N * W;
+        s->wyy32 = f; f += N * W;
+        s->vb32 = f; f += nz * W;
+        s->G032 = f; f += nz;
+        f += (reinterpret_cast<uintptr_t>(f) / sizeof(float)) & 1;  // 8-byte alignment of the fields
+        s->r32 = f; f += np;
+        s->cres32 = f; f += np;
+        s->d032 = f; f += np;
+        s->d132 = f; f += np;
+        s->z32 = f; f += np;
+        p = reinterpret_cast<double *>(f + ((reinterpret_cast<uintptr_t>(f) / sizeof(float)) & 1));
+    }
     s->stop = reinterpret_cast<int *>(p);
 
     // host tables: composed line stencils and the vertical band
@@ -846,6 +998,17 @@ hipError_t imex3d_setup(numa_ctx *c, double dt, int restart, int order, int powe
     if ((e = hipMemcpy(s->wxx, wxx.data(), sizeof(double) * N * W, hipMemcpyHostToDevice)) != hipSuccess) return e;
     if ((e = hipMemcpy(s->wyy, wyy.data(), sizeof(double) * N * W, hipMemcpyHostToDevice)) != hipSuccess) return e;
     if ((e = hipMemcpy(s->vb, vb.data(), sizeof(double) * nz * W, hipMemcpyHostToDevice)) != hipSuccess) return e;
+    {
+        std::vector<float> f32;
+        auto put = [&](float *dst, const std::vector<double> &v, size_t n) {
+            f32.assign(v.begin(), v.begin() + long(n));
+            return hipMemcpy(dst, f32.data(), sizeof(float) * n, hipMemcpyHostToDevice);
+        };
+        if ((e = put(s->wxx32, wxx, size_t(N) * W)) != hipSuccess) return e;
+        if ((e = put(s->wyy32, wyy, size_t(N) * W)) != hipSuccess) return e;
+        if ((e = put(s->vb32, vb, size_t(nz) * W)) != hipSuccess) return e;
+        if ((e = put(s->G032, G0, size_t(nz))) != hipSuccess) return e;
+    }
     if ((e = hipMemset(s->stop, 0, 2 * sizeof(int))) != hipSuccess) return e;
     s->hH.assign(size_t(m + 1) * m, 0.0);
     s->hg.assign(size_t(m + 1), 0.0);
@@ -871,6 +1034,8 @@ hipError_t imex3d_setup(numa_ctx *c, double dt, int restart, int order, int powe
     }
     return hipGetLastError();
 }
+
+void imex3d_set_pbno32(numa_ctx *c, int on) { c->imex->pbno32 = on ? 1 : 0; }
 
 void imex3d_set_bounds(numa_ctx *c, double lmin, double lmax)
 {
@@ -899,8 +1064,12 @@ hipError_t schur_gmres(numa_ctx *c, const double *bvec, int *iters, int *converg
     const long np = s.np;
     const int m = s.restart;
     // the learned correction (flexible GMRES) until a restart cycle with it
-    // fails to reduce the residual norm tenfold; then the polynomial alone
-    bool flex = learned_enabled(c);
+    // fails to reduce the residual norm tenfold; then the polynomial alone.
+    // The FP32 polynomial is not exactly the same linear map at every
+    // application, so it always runs in flexible GMRES.
+    bool net = learned_enabled(c);
+    const bool flex32 = s.pbno32 && s.order >= 1;
+    bool flex = net || flex32;
     hipError_t e;
     *iters = 0;
     *converged = 0;
@@ -930,7 +1099,7 @@ hipError_t schur_gmres(numa_ctx *c, const double *bvec, int *iters, int *converg
                 if (flex) {
                     double *zj = s.Z + size_t(j) * np;
                     if ((e = precondition(c, vj, zj)) != hipSuccess) return e;
-                    if ((e = learned_correction_add(c, vj, zj, s.stop)) != hipSuccess) return e;
+                    if (net && (e = learned_correction_add(c, vj, zj, s.stop)) != hipSuccess) return e;
                     zin = zj;
                 } else if (s.order >= 0) {
                     if ((e = precondition(c, vj, s.z)) != hipSuccess) return e;
@@ -990,7 +1159,10 @@ hipError_t schur_gmres(numa_ctx *c, const double *bvec, int *iters, int *converg
         if ((e = apply(c, axpy_args(s.x, s.r, 0.0, -1.0, 1.0, bvec))) != hipSuccess) return e;
         const double before = beta;
         if ((e = norm_host(c, s.r, &beta)) != hipSuccess) return e;
-        if (flex && beta > 0.1 * before) flex = false;
+        if (net && beta > 0.1 * before) {
+            net = false;
+            flex = flex32;
+        }
         rvec = s.r;
     }
     *iters = total;

@@ -175,6 +175,7 @@ int step_preconditions(numa_ctx *c, double dt, const char *who);
 hipError_t imex3d_setup(numa_ctx *c, double dt, int restart, int order, int power_steps, int maxit);
 void imex3d_free(numa_ctx *c);
 void imex3d_set_bounds(numa_ctx *c, double lmin, double lmax);
+void imex3d_set_pbno32(numa_ctx *c, int on);
 void imex3d_info(const numa_ctx *c, double *dt, double *lmin, double *lmax);
 hipError_t schur_apply(numa_ctx *c, const double *P, double *out);
 hipError_t schur_rhs(numa_ctx *c, const double *y, double *b);

@@ -98,6 +98,7 @@ def load():
     lib.numa_imex3d_setup.argtypes = [vp, C.c_double, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
     lib.numa_imex3d_bounds.argtypes = [vp, C.POINTER(C.c_double)]
     lib.numa_imex3d_set_bounds.argtypes = [vp, C.c_double, C.c_double]
+    lib.numa_imex3d_set_precision.argtypes = [vp, C.c_int32]
     lib.numa_schur_apply.argtypes = [vp, vp, vp]
     lib.numa_schur_rhs.argtypes = [vp, vp, vp]
     lib.numa_pbno_apply.argtypes = [vp, vp, vp]
@@ -131,7 +132,8 @@ def load():
                  "numa_imex3d_bounds", "numa_imex3d_set_bounds", "numa_schur_apply", "numa_schur_rhs",
                  "numa_pbno_apply", "numa_imex3d_solve", "numa_learned_setup", "numa_learned_info",
                  "numa_learned_add_samples", "numa_learned_samples", "numa_learned_params", "numa_learned_loss_grad",
-                 "numa_learned_train", "numa_learned_enable", "numa_learned_apply", "numa_learned_judge", "numa_factor_columns_standard",
+                 "numa_learned_train", "numa_learned_enable", "numa_learned_apply", "numa_learned_judge",
+                 "numa_imex3d_set_precision", "numa_factor_columns_standard",
                  "numa_solve_columns_standard", "numa_set_column_solver", "numa_autotune",
                  "numa_set_rhs_config", "numa_get_rhs_config"):
         getattr(lib, name).restype = C.c_int
@@ -339,6 +341,11 @@ def imex3d_bounds(ctx):
 
 def imex3d_set_bounds(ctx, lmin, lmax):
     return _check(load().numa_imex3d_set_bounds(ctx, float(lmin), float(lmax)), ctx)
+
+
+def imex3d_set_precision(ctx, pbno_fp32):
+    """pbno_fp32=True: the PBNO recurrence in FP32 (flexible GMRES)."""
+    return _check(load().numa_imex3d_set_precision(ctx, 1 if pbno_fp32 else 0), ctx)
 
 
 def schur_apply(ctx, p_ptr, out_ptr):

@@ -146,6 +146,62 @@ def test_solve_parity(torch_cuda, numa_mod, oracle_mod, N, nex, ney, nez, zseed,
     ctx.close()
 
 
+@pytest.mark.parametrize("order", [1, 2, 6])
+@pytest.mark.parametrize("N,nex,ney,nez,zseed,seed", GRIDS)
+def test_fp32_preconditioner(torch_cuda, numa_mod, oracle_mod, N, nex, ney, nez, zseed, seed, order):
+    """The mixed-precision preconditioner: the FP32 PBNO polynomial equals the
+    oracle's FP64 one to FP32 accuracy (1e-5 after up to six applications of
+    S); the flexible GMRES solve with it meets the same 1e-10 bar against the
+    oracle's FP64 solve at tol 1e-13 in at most two more iterations than the
+    oracle's flexible solve with the FP64 polynomial; switching it off restores
+    the FP64 polynomial exactly."""
+    g = _grid(N, nex, ney, nez, zseed)
+    o = _oracle(oracle_mod, g)
+    dt = _dt(g)
+    lam = (1.0 - 1.0 / np.sqrt(2.0)) * dt
+    ctx = _ctx(numa_mod, g, dt, order=order, restart=20)
+    bd = _oracle_bounds(numa_mod, ctx, o, lam)
+    numa_mod.imex3d_set_precision(ctx.ctx, True)
+    rng = np.random.default_rng(seed + 40)
+    r = rng.standard_normal(g.shape[1:])
+    z = _host(ctx.pbno_apply(_dev(torch_cuda, r)))
+    zo = o.pbno_apply(r, lam, order, bd)
+    e = _r1(z, zo)
+    print(f"N={N} order {order}: FP32 PBNO rel L2 {e:.2e}")
+    assert 1e-12 < e < 1e-5, e  # FP32 indeed, and accurate to FP32
+    y = W.make_random_state(g, seed, smooth=False)
+    x, it = ctx.imex3d_solve(_dev(torch_cuda, y), GMRES_TOL)
+    x = _host(x)
+    xo, _ = o.solve3d(y, lam, tol=GMRES_TOL, restart=20, order=order, bounds=bd)
+    _, itf = o.solve3d_learned(y, lam, None, tol=GMRES_TOL, restart=20, order=order, bounds=bd)
+    print(f"N={N} order {order}: iterations FP32 {it}, oracle flexible FP64 {itf}")
+    assert np.all(_rel(x, xo) < SOLVE_TOL), _rel(x, xo)
+    assert itf - 1 <= it <= itf + 2, (it, itf)
+    numa_mod.imex3d_set_precision(ctx.ctx, False)
+    assert _r1(_host(ctx.pbno_apply(_dev(torch_cuda, r))), zo) < OP_TOL
+    ctx.close()
+
+
+def test_fp32_preconditioner_steps(torch_cuda, numa_mod, oracle_mod):
+    """Three steps of the small 3D workload with the FP32 PBNO of order 6,
+    against the oracle's FP64 steps."""
+    wl = W.box_imex3d("small")
+    g = wl.grid
+    o = _oracle(oracle_mod, g)
+    ctx = _ctx(numa_mod, g, wl.dt, order=6)
+    bd = _oracle_bounds(numa_mod, ctx, o, (1.0 - 1.0 / np.sqrt(2.0)) * wl.dt)
+    numa_mod.imex3d_set_precision(ctx.ctx, True)
+    q0 = W.make_initial_state(wl)
+    qd = _dev(torch_cuda, q0)
+    ctx.imex3d_step(qd, GMRES_TOL, nsteps=3)
+    qo, _ = o.step3d(q0, wl.dt, 3, tol=GMRES_TOL, order=6, bounds=bd)
+    err = _rel(_host(qd) - q0, qo - q0)
+    print(f"FP32 PBNO(6), 3 steps: {err}")
+    assert np.all(err < SOLVE_TOL), err
+    ctx.check()
+    ctx.close()
+
+
 def test_solve_in_place_and_zero_rhs(torch_cuda, numa_mod, oracle_mod):
     g = _grid(3, 2, 3, 2, None)
     o = _oracle(oracle_mod, g)
