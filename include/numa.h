@@ -423,7 +423,8 @@ int numa_imex3d_step(numa_ctx *c, double *state, double dt, double tol, int32_t 
  * accepted, and left switched on, only if its solve converged in fewer
  * GMRES iterations than the polynomial's; otherwise it is switched off.
  * out[3] (host) = {polynomial iterations, network iterations, accepted}.
- * NUMA_E_NOT_CONVERGED if the polynomial solve does not converge.
+ * NUMA_E_NOT_CONVERGED if the polynomial solve does not converge; on that
+ * or any other error the network is left switched off.  Synchronous.
  * numa_learned_apply: z = s(S) r + corr(r) (device fields, distinct).
  * Errors: NUMA_E_ARG, NUMA_E_NOT_FACTORED (no numa_imex3d_setup /
  * numa_learned_setup), NUMA_E_NOT_CONVERGED (a sample solve), NUMA_E_HIP.
