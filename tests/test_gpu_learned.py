@@ -289,6 +289,48 @@ def test_judge_matches_oracle(torch_cuda, numa_mod, oracle_mod, kind):
     ctx.close()
 
 
+@pytest.mark.parametrize("kind", ["diagonal", "random"])
+def test_judge_with_fp32_polynomial(torch_cuda, numa_mod, oracle_mod, kind):
+    """The judge and the network on top of the FP32 polynomial (flexible
+    GMRES either way): the decision and both iteration counts agree with the
+    oracle's FP64 judge within two iterations, and the accepted network's
+    solution meets the solve bar."""
+    g = W.Grid(3000.0, 2500.0, 2000.0, 2, 2, 2, 3)
+    o = _oracle(oracle_mod, g)
+    nin = (g.N + 1) ** 3
+    ctx = numa_mod.Context(g)
+    dt = W.dt_for_courant(g, 15.0, "x")
+    lam = (1.0 - 1.0 / np.sqrt(2.0)) * dt
+    ctx.imex3d_setup(dt, restart=30, pbno_order=2, power_steps=30, maxit=5000)
+    bd = o.schur_bounds(lam, 30)
+    numa_mod.imex3d_set_bounds(ctx.ctx, *bd)
+    numa_mod.imex3d_set_precision(ctx.ctx, True)
+    numa_mod.learned_setup(ctx.ctx, hidden=nin, max_samples=8, seed=1)
+    if kind == "diagonal":
+        m = _diagonal_mlp(oracle_mod, o, g, lam, 0.5)
+    else:
+        rng = np.random.default_rng(5)
+        m = oracle_mod.Mlp(30.0 * rng.standard_normal((nin, nin)), 30.0 * rng.standard_normal(nin),
+                           30.0 * rng.standard_normal((nin, nin)), 30.0 * rng.standard_normal(nin))
+    theta = _theta_of(m)
+    numa_mod.learned_params(ctx.ctx, theta_in=theta)
+    m = _mlp_from_theta(oracle_mod, theta, nin, nin)
+    y = W.make_random_state(g, 3, smooth=False)
+    yd = torch_cuda.from_numpy(y).cuda()
+    x = torch_cuda.empty_like(yd)
+    jd = numa_mod.learned_judge(ctx.ctx, yd.data_ptr(), x.data_ptr(), 1e-10)
+    po, qo, acc_o = o.learned_judge(y, lam, m, tol=1e-10, order=2, bounds=bd)
+    print(f"{kind} over the FP32 polynomial: GPU {jd}, oracle FP64 ({po}, {qo}, {acc_o})")
+    assert abs(jd["pbno_iters"] - po) <= 2 and abs(jd["net_iters"] - qo) <= max(3, 0.15 * qo)
+    assert jd["accepted"] == acc_o == (kind == "diagonal")
+    xn, _ = ctx.imex3d_solve(yd, 1e-10)
+    xo, _ = o.solve3d(y, lam, tol=1e-10, order=2, bounds=bd)
+    xh = xn.cpu().numpy()
+    for f in range(5):
+        assert np.linalg.norm(xh[f] - xo[f]) <= 1e-7 * np.linalg.norm(xo[f]) + 1e-300, f
+    ctx.close()
+
+
 def test_fallback_keeps_a_bad_network_harmless(torch_cuda, numa_mod, oracle_mod):
     """Large random weights: the first flexible cycle fails to reduce the
     residual tenfold, the network is switched off and the solve converges."""
