@@ -456,9 +456,19 @@ __global__ __launch_bounds__(kTB) void k_finish(const double *part, long nblk, d
     __shared__ double sh[4];
     if (stop && *stop) return;
     const int v = blockIdx.x;
-    double s = 0.0;
-    for (long b = threadIdx.x; b < nblk; b += kTB) s += part[long(v) * nblk + b];
-    s = block_sum(s, sh);
+    // four independent partial sums per thread, so that four loads are in
+    // flight at a time; combined in a fixed order (reproducible)
+    const double *pv = part + long(v) * nblk;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    long b = threadIdx.x;
+    for (; b + 3 * kTB < nblk; b += 4 * kTB) {
+        s0 += pv[b];
+        s1 += pv[b + kTB];
+        s2 += pv[b + 2 * kTB];
+        s3 += pv[b + 3 * kTB];
+    }
+    for (; b < nblk; b += kTB) s0 += pv[b];
+    double s = block_sum((s0 + s1) + (s2 + s3), sh);
     if (threadIdx.x == 0) {
         if (root) s = std::sqrt(s);
         h[v] = s;
