@@ -535,21 +535,38 @@ __global__ __launch_bounds__(kTB) void k_scale(double *out, const double *in, do
 // Givens step of column j of the Hessenberg matrix (row stride m): the
 // earlier rotations, a new one that zeroes H[j+1][j], the rotated residual
 // vector g; stop[0] = 1 once |g[j+1]| <= tolb; stop[1] counts iterations.
-__global__ void k_givens(double *H, double *cs, double *sn, double *g, int j, int m, double tolb, int *stop)
+// One wavefront: its lanes load column j of H and the previous rotations
+// into LDS together, then lane 0 applies the rotations in order (the same
+// arithmetic as a sequential loop over global memory, without its chain of
+// dependent global loads).  m <= 63.
+__global__ __launch_bounds__(64) void k_givens(double *H, double *cs, double *sn, double *g, int j, int m,
+                                               double tolb, int *stop)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0 || stop[0]) return;
-    for (int i = 0; i < j; ++i) {
-        const double a = H[i * m + j], b = H[(i + 1) * m + j];
-        H[i * m + j] = cs[i] * a + sn[i] * b;
-        H[(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+    __shared__ double col[65], cc[64], ss[64];
+    if (stop[0]) return;
+    const int t = threadIdx.x;
+    for (int i = t; i <= j + 1; i += 64) col[i] = H[i * m + j];
+    for (int i = t; i < j; i += 64) {
+        cc[i] = cs[i];
+        ss[i] = sn[i];
     }
-    const double a = H[j * m + j], b = H[(j + 1) * m + j], r = std::hypot(a, b);
-    cs[j] = r > 0.0 ? a / r : 1.0;
-    sn[j] = r > 0.0 ? b / r : 0.0;
+    __syncthreads();
+    if (t != 0) return;
+    double a = col[0];
+    for (int i = 0; i < j; ++i) {
+        const double b = col[i + 1];
+        H[i * m + j] = cc[i] * a + ss[i] * b;
+        a = -ss[i] * a + cc[i] * b;  // the new H[i+1][j]
+    }
+    const double b = col[j + 1], r = std::hypot(a, b);
+    const double c = r > 0.0 ? a / r : 1.0, sv = r > 0.0 ? b / r : 0.0;
+    cs[j] = c;
+    sn[j] = sv;
     H[j * m + j] = r;
     H[(j + 1) * m + j] = 0.0;
-    g[j + 1] = -sn[j] * g[j];
-    g[j] = cs[j] * g[j];
+    const double gj = g[j];
+    g[j + 1] = -sv * gj;
+    g[j] = c * gj;
     stop[1] += 1;
     if (std::fabs(g[j + 1]) <= tolb) stop[0] = 1;
 }
@@ -1133,7 +1150,7 @@ hipError_t schur_gmres(numa_ctx *c, const double *bvec, int *iters, int *converg
                                    s.H + size_t(j + 1) * m, m, j, 0, s.stop);
                 hipLaunchKernelGGL(k_normalize, dim3(unsigned(s.nblk)), dim3(kTB), 0, c->stream, vn, s.w,
                                    s.H + size_t(j + 1) * m + j, np, s.stop);
-                hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, c->stream, s.H, s.cs, s.sn, s.g, j, m, tolb, s.stop);
+                hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, c->stream, s.H, s.cs, s.sn, s.g, j, m, tolb, s.stop);
                 if ((e = hipGetLastError()) != hipSuccess) return e;
             }
             int flags[2] = {0, 0};
