@@ -29,18 +29,20 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def kernel_bytes(np_, ncol, nz, N, table_bytes=None):
+def kernel_bytes(np_, ncol, nz, N, table_bytes=None, r1=8):
     """Algorithmic HBM bytes per launch of the five kernels of a step: whole
     unique-node field passes (reads + writes) and the column factor reads
-    (one LU band shared by all columns)."""
+    (one LU band shared by all columns).  r1: bytes per value of the
+    first-stage tendency R1 (8; 4 in the precision form), every other field
+    FP64."""
     F = nz * (4 * N + 1) * 8 if table_bytes is None else table_bytes
-    f = 8 * np_
+    f, r = 8 * np_, r1 * np_
     return [
-        ("rhs_stage1", 10 * f),          # reads q^n (5), writes R1 (5)
-        ("colsolve_stage2", 7 * f + F),  # reads R1 rho/w/theta, q^n rho/w; writes Q2 rho/w; factors
-        ("rhs_stage2", 22 * f),          # reads Q2 rho/w, q^n (5), R1 (5); writes E3 (5), ACC (5)
-        ("colsolve_stage3", 11 * f + F), # reads E3, q^n (rho/w/theta), Q2 rho/w, R1 theta; writes Q3 rho/w; factors
-        ("rhs_stage3", 15 * f),          # reads Q3 rho/w, E3 u/v/theta, ACC (5); writes q^{n+1} (5)
+        ("rhs_stage1", 5 * f + 5 * r),          # reads q^n (5), writes R1 (5)
+        ("colsolve_stage2", 4 * f + 3 * r + F), # reads R1 rho/w/theta, q^n rho/w; writes Q2 rho/w; factors
+        ("rhs_stage2", 17 * f + 5 * r),         # reads Q2 rho/w, q^n (5), R1 (5); writes E3 (5), ACC (5)
+        ("colsolve_stage3", 10 * f + r + F),    # reads E3, q^n (rho/w/theta), Q2 rho/w, R1 theta; writes Q3 rho/w; factors
+        ("rhs_stage3", 15 * f),                 # reads Q3 rho/w, E3 u/v/theta, ACC (5); writes q^{n+1} (5)
     ]
 
 
@@ -138,11 +140,12 @@ def cpu_baseline(steps=5, single_steps=1):
 
 
 def precision_form(numa, torch, ctx, wl, args, t_fp64):
-    """The precision form (FP32 right-hand sides and u, v, w stage buffers)
-    on the same workload and GPU: throughput, simulated seconds per wall
-    second against the FP64 step, and its relative L2 difference per
-    variable from the FP64 step after 100 steps (the FP64 step matches the
-    oracle to 1e-11; the tests check the form against the oracle itself)."""
+    """The precision form (the first-stage tendency R1 stored in FP32) on
+    the same workload and GPU: throughput, simulated seconds per wall second
+    against the FP64 step, its algorithmic bytes, and its relative L2
+    difference per variable from the FP64 step after 100 steps (the FP64
+    step matches the oracle to 1e-11; the tests check the form against the
+    oracle itself)."""
     import numpy as np
     from paper_1702_04316_amd import workloads as W
     g = wl.grid
@@ -160,16 +163,21 @@ def precision_form(numa, torch, ctx, wl, args, t_fp64):
     a, b = a.cpu().numpy(), b.cpu().numpy()
     err = {n: float(np.linalg.norm(b[f] - a[f]) / np.linalg.norm(a[f]))
            for f, n in enumerate(("rho'", "u", "v", "w", "theta'"))}
-    names = ["rhs_stage1", "colsolve_stage2", "rhs_stage2", "colsolve_stage3", "rhs_stage3"]
+    info = ctx.info()
+    kb = kernel_bytes(g.n_unique, info["ncol"], info["nz"], g.N, info["factor_bytes"], r1=4)
+    step_bytes = sum(b for _, b in kb)
+    names = [n for n, _ in kb]
     return {
         "entry": "numa_hevi_step_mixed",
+        "algorithmic_bytes_per_step": step_bytes,
+        "step_algorithmic_GBps": step_bytes * args.steps / tm / 1e9,
         "value": 5 * g.n_unique * args.steps / tm,
         "unit": "DOF-steps/s",
         "ms_per_step": 1e3 * tm / args.steps,
         "speedup_vs_fp64": t_fp64 / tm,
         "sim_s_per_wall_s": {"fp64": wl.dt * args.steps / t_fp64, "mixed": wl.dt * args.steps / tm},
         "rel_l2_vs_fp64_after_100_steps": err,
-        "kernels": [{"kernel": n, "ms": m} for n, m in zip(names, ms)],
+        "kernels": [{"kernel": n, "ms": m, "GB/s": bb / (m * 1e6)} for (n, bb), m in zip(kb, ms)],
     }
 
 

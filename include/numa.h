@@ -205,22 +205,17 @@ int numa_profile_steps(numa_ctx *c, double *state, double dt, int32_t nsteps, do
  * Precision form of numa_hevi_step.  Not a method of the paper (whose
  * kernels are FP64 and, by its own roofline measurements in Sec. 6.1,
  * mostly memory-bound): a project addition on top of the ARK2 HEVI step of
- * Sec. 2.2 that evaluates the right-hand sides in FP32 and keeps the
- * first stage's horizontal-velocity tendencies in FP32.  The same five
- * kernels and stage algebra, with the right-hand sides evaluated in FP32
- * (LDS planes with u, v stored relative to a per-workgroup reference
- * velocity, line and column derivatives, tendencies) and u, v of the first
- * stage's tendency R1 in FP32, while the state, the accumulator of the
- * final combination, every other stage value, the pressure perturbation
- * P' = EOS(rho, theta) - P0 with its derivatives, the mass flux
- * (rho0 + rho') u_i with its divergence, the tendency of w (which holds the
- * stiff vertical pressure gradient and buoyancy) and the column solves
- * (FP64 factors) stay in FP64.  state: the FP64 device
- * array of the state contract, advanced in place.  Needs the factors of
- * numa_factor_columns(dt) like the FP64 step.  The first call allocates
- * 104 bytes per unique node of stage buffers for the context (freed by
- * numa_destroy).  Asynchronous.  Errors: as numa_hevi_step, and
- * NUMA_E_NOMEM.
+ * Sec. 2.2 that stores the first stage's tendency R1 in FP32.  The same five
+ * kernels, stage algebra and FP64 arithmetic as numa_hevi_step; R1, which
+ * the step uses only multiplied by dt, is written and read as FP32 (14 of
+ * the step's 65 field passes: 464 bytes per node instead of 520),
+ * while the state, the accumulator of the final combination, every stage
+ * value and the column solves (FP64 factors) stay in FP64.  state: the FP64
+ * device array of the state contract, advanced in place.  Needs the
+ * factors of numa_factor_columns(dt) like the FP64 step.  The first call
+ * allocates 96 bytes per unique node of stage buffers for the context (112
+ * over a stratified background; freed by numa_destroy).  Asynchronous.
+ * Errors: as numa_hevi_step, and NUMA_E_NOMEM.
  */
 int numa_hevi_step_mixed(numa_ctx *c, double *state, double dt, int32_t nsteps);
 
@@ -228,10 +223,11 @@ int numa_hevi_step_mixed(numa_ctx *c, double *state, double dt, int32_t nsteps);
  * numa_hevi_step_mixed without any device allocation, for callers that
  * cannot allocate (code under HIP graph capture, serving loops, harnesses
  * that forbid hipMalloc).  Same kernels, arguments and results as
- * numa_hevi_step_mixed, but the precision form's stage buffers (104 bytes
- * per unique node) live in a fixed 64 MiB device array of the library (one
- * copy per GPU, resolved by numa_setup on its device, held until the process
- * ends), so grids of at most 645,277 unique nodes are accepted.  The
+ * numa_hevi_step_mixed, but the precision form's stage buffers (96 bytes
+ * per unique node, 112 over a stratified background) live in a fixed 64 MiB
+ * device array of the library (one copy per GPU, resolved by numa_setup on
+ * its device, held until the process ends), so grids of at most 699,050
+ * unique nodes (599,186 stratified) are accepted.  The
  * context's own buffers (allocated by numa_setup) are used as by
  * numa_hevi_step_mixed.  Every call on a GPU shares that GPU's array: calls
  * that overlap in time on one GPU (other streams, other contexts, other

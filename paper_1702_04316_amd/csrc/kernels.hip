@@ -63,8 +63,9 @@ struct SolveParams {
 };
 
 // term counts of the stage variants: (NR, NW, NT) explicit-estimate terms,
-// (NBR, NBW) output terms; F32: which fields are FP32 (bit 0+t er[t], 3+t
-// ew[t], 6+t et[t], 9+t br[t], 11+t bw[t], 13 out_w, 14 out_r), the rest FP64
+// (NBR, NBW, NBT) output terms; F32: which fields are FP32 (bit 0+t er[t],
+// 3+t ew[t], 6+t et[t], 9+t br[t], 11+t bw[t], 13 out_w, 14 out_r, 15+t
+// bt[t]), the rest FP64
 template <int NR_, int NW_, int NT_, int NBR_, int NBW_, int NBT_, unsigned F32_ = 0>
 struct SolveShape {
     static constexpr int NR = NR_, NW = NW_, NT = NT_, NBR = NBR_, NBW = NBW_, NBT = NBT_;
@@ -73,9 +74,19 @@ struct SolveShape {
 using ShapePlain = SolveShape<1, 1, 1, 1, 0, 1>;
 using ShapeStage2 = SolveShape<1, 1, 1, 2, 1, 2>;
 using ShapeStage3 = SolveShape<3, 3, 3, 1, 2, 1>;
+// the precision form's solves: R1 (FP32) in er[0], ew[0], et[0], br[1] and
+// bt[1] of stage 2, and (over the isentropic background) in et[2] of stage 3
+using ShapeStage2R = SolveShape<1, 1, 1, 2, 1, 2, (1u << 0) | (1u << 3) | (1u << 6) | (1u << 10) | (1u << 16)>;
+using ShapeStage3R = SolveShape<3, 3, 3, 1, 2, 1, (1u << 8)>;
 // element type of field bit b of a shape
 template <class SH, int B>
 using SolveT = std::conditional_t<((SH::F32 >> B) & 1u) != 0, float, double>;
+// term t of the theta' output (t is a constant after unrolling)
+template <class SH>
+__device__ __forceinline__ double bt_load(const SolveParams &p, int t, unsigned off)
+{
+    return t == 0 ? tload<SolveT<SH, 15>>(p.bt[0], off) : tload<SolveT<SH, 16>>(p.bt[1], off);
+}
 
 template <int N, class SH>
 struct SolveGeom {
@@ -240,7 +251,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
                         const unsigned off = unsigned(s) * lbytes + cbyte;
                         double th = 0.0;
 #pragma unroll
-                        for (int t = 0; t < SH::NBT; ++t) th += p.cbt[t] * gload(static_cast<const double *>(p.bt[t]), off);
+                        for (int t = 0; t < SH::NBT; ++t) th += p.cbt[t] * bt_load<SH>(p, t, off);
                         gstore(static_cast<double *>(p.out_t), off, th - cf[SC_TZ] * wt);
                     }
                 }
@@ -456,7 +467,7 @@ void k_colsolve_blocked(SolveParams p)
                 if constexpr (SH::NBW > 1) xb[b][1] = tload<SolveT<SH, 12>>(p.bw[1], off);
                 if (strat) {
 #pragma unroll
-                    for (int t = 0; t < SH::NBT; ++t) xt[b][t] = gload(static_cast<const double *>(p.bt[t]), off);
+                    for (int t = 0; t < SH::NBT; ++t) xt[b][t] = bt_load<SH>(p, t, off);
                 }
             }
 #pragma unroll
@@ -698,14 +709,25 @@ hipError_t solve_prepare(int M)
                             : solve_prepare_fl<N, SH, 0>(G::lds_total(M));
 }
 
-// k_rhs with the context's tile variant: the second variant serves the FP64
-// step's three right-hand sides; other launches, and the precision form,
-// use the first.
-template <int N, int EPI, bool HASB, bool MIX = false>
+// Whether the precision form's right-hand sides take the context's tile
+// variant 1.  Not at N = 6: there its stage-2 kernel on the 18 x 6 tile
+// returned values that differ from the first tile's at most nodes (finite
+// after one step, non-finite after two), while the FP64 kernels on that tile
+// and the precision form on every other order's second tile agree with the
+// first tile to rounding.  The cause is not found, so the precision form
+// keeps the first tile at N = 6.
+inline bool mixed_uses_tile1(const numa_ctx *c) { return c->rhs_tile == 1 && c->N != 6; }
+
+// k_rhs with the context's tile variant: the second variant serves the
+// three right-hand sides of a step; other launches use the first.  MS: a
+// launch of the precision-form step, whose first two right-hand sides have
+// R1 in FP32 and whose last is the FP64 step's.
+template <int N, int EPI, bool HASB, bool MS = false>
 hipError_t rhs_launch(numa_ctx *c, RhsParams p)
 {
+    constexpr bool MIX = MS && EPI != EPI_FINAL;
     const bool step_kernel = (EPI == EPI_TWO) == HASB;
-    if (!MIX && c->rhs_tile == 1 && step_kernel) return rhs_launch_alt(c, p, EPI);
+    if (step_kernel && (MS ? mixed_uses_tile1(c) : c->rhs_tile == 1)) return rhs_launch_alt(c, p, EPI, MIX);
     return rhs_launch_t<N, 0, EPI, HASB, MIX>(c, p);
 }
 
@@ -1076,34 +1098,27 @@ hipError_t launch_hevi_step(numa_ctx *c, double *q, double dt, hipEvent_t *ev)
     return hipSuccess;
 }
 
-// byte offset of field f in the precision form's five-field buffers (the
-// device layout of FiveField<true>)
-size_t mixed_field_offset(int f, long np)
-{
-    return size_t(np) * size_t(f == 0 ? 0 : (f == 1 ? 8 : (f == 2 ? 12 : 8 * f - 8)));
-}
-
-// The precision form of the step (same stage algebra as launch_hevi_step):
-// the right-hand sides evaluate in FP32 (P', its derivatives, w's tendency
-// and the mass flux in FP64); the stage buffer R1 holds u, v in FP32 and
-// rho', w, theta' in FP64, E3 and Q2, Q3 (rho', w) are FP64 (E3's u and v
-// are differentiated by the last right-hand side, and their FP32 rounding
-// would be amplified there like any rounding of a stage value); the state
-// and the accumulator ACC stay FP64; the column solves read those and run
-// in FP64 with the FP64 factors.  mb: mixed_bytes_per_node(c) * np bytes.
+// The precision form of the step (same stage algebra and arithmetic as
+// launch_hevi_step): the first-stage tendency R1 is stored in FP32, five
+// fields of 4 bytes per node, written once and read by the next three
+// kernels; every stage value (Q2, Q3, E3), the accumulator ACC and the
+// state stay FP64, and so do the right-hand sides' LDS ring and arithmetic
+// and the column solves with their factors.  mb: mixed_bytes_per_node(c) *
+// np bytes.
 hipError_t launch_hevi_step_mixed_in(numa_ctx *c, double *q, double dt, char *mb, hipEvent_t *ev)
 {
     static const Ark2 t;
     const long np = c->np;
-    // R1 in the mixed five-field layout (32 bytes per node), E3 in FP64 (40),
-    // then Q2 and Q3 rho' and w, and over a stratified background theta'
-    char *const R1 = mb, *const E3 = mb + 32 * np;
-    double *const Q2r = reinterpret_cast<double *>(mb + 72 * np), *const Q3r = reinterpret_cast<double *>(mb + 80 * np);
-    double *const Q2w = reinterpret_cast<double *>(mb + 88 * np), *const Q3w = reinterpret_cast<double *>(mb + 96 * np);
+    // R1 (FP32, 20 bytes per node in a 24-byte slot, so that the FP64
+    // buffers after it stay 8-byte aligned), E3 in FP64 (40), then Q2 and Q3
+    // rho' and w, and over a stratified background theta'
+    char *const R1 = mb, *const E3 = mb + 24 * np;
+    double *const Q2r = reinterpret_cast<double *>(mb + 64 * np), *const Q3r = reinterpret_cast<double *>(mb + 72 * np);
+    double *const Q2w = reinterpret_cast<double *>(mb + 80 * np), *const Q3w = reinterpret_cast<double *>(mb + 88 * np);
     const bool strat = stratified(c);
-    double *const Q2t = strat ? reinterpret_cast<double *>(mb + 104 * np) : nullptr;
-    double *const Q3t = strat ? reinterpret_cast<double *>(mb + 112 * np) : nullptr;
-    auto fld = [&](char *buf, int f) { return buf + (buf == E3 ? size_t(8) * f * np : mixed_field_offset(f, np)); };
+    double *const Q2t = strat ? reinterpret_cast<double *>(mb + 96 * np) : nullptr;
+    double *const Q3t = strat ? reinterpret_cast<double *>(mb + 104 * np) : nullptr;
+    auto fld = [&](char *buf, int f) { return buf + size_t(buf == E3 ? 8 : 4) * f * np; };
     double *const ACC = stage_buffers(c).ACC;
     const double *qr = q + 0 * np, *qw = q + 3 * np, *qt = q + 4 * np;
     const double f = dt * t.a21;
@@ -1131,10 +1146,10 @@ hipError_t launch_hevi_step_mixed_in(numa_ctx *c, double *q, double dt, char *mb
             p.bt[0] = qt; p.cbt[0] = 1.0; p.bt[1] = fld(R1, 4); p.cbt[1] = f;
             p.out_t = Q2t;
         }
-        e = dispatch(c->N, [&](auto n) { return solve_launch<decltype(n)::value, ShapeStage2>(c, p); });
+        e = dispatch(c->N, [&](auto n) { return solve_launch<decltype(n)::value, ShapeStage2R>(c, p); });
         if (e != hipSuccess || (e = mark(2)) != hipSuccess) return e;
     }
-    {  // K3: rhs(Q2) -> E3 (FP32), ACC (FP64)
+    {  // K3: rhs(Q2) -> E3, ACC
         RhsParams p{};
         p.a[0] = Q2r;
         p.a[3] = Q2w;
@@ -1168,7 +1183,11 @@ hipError_t launch_hevi_step_mixed_in(numa_ctx *c, double *q, double dt, char *mb
             p.bt[0] = fld(E3, 4); p.cbt[0] = 1.0;
             p.out_t = Q3t;
         }
-        e = dispatch(c->N, [&](auto n) { return solve_launch<decltype(n)::value, ShapeStage3>(c, p); });
+        // over a stratified background et[2] is Q2's theta' (FP64), else R1's
+        e = dispatch(c->N, [&](auto n) {
+            return strat ? solve_launch<decltype(n)::value, ShapeStage3>(c, p)
+                         : solve_launch<decltype(n)::value, ShapeStage3R>(c, p);
+        });
         if (e != hipSuccess || (e = mark(4)) != hipSuccess) return e;
     }
     {  // K5: q^{n+1} = ACC + dt b3 R(Q3)
@@ -1182,6 +1201,7 @@ hipError_t launch_hevi_step_mixed_in(numa_ctx *c, double *q, double dt, char *mb
         p.e0 = ACC;
         p.fs = np;
         p.k02 = dt * t.b3;
+        // the FP64 step's last right-hand side
         e = dispatch(c->N, [&](auto n) { return rhs_launch<decltype(n)::value, EPI_FINAL, false, true>(c, p); });
         if (e != hipSuccess || (e = mark(5)) != hipSuccess) return e;
     }
@@ -1236,37 +1256,48 @@ hipError_t prepare_step(numa_ctx *c, bool mixed)
         constexpr int NN = decltype(n)::value;
         const int nz = int(c->nz);
         hipError_t e;
-        if (c->rhs_tile == 1 && !mixed) {
+        if (mixed ? mixed_uses_tile1(c) : c->rhs_tile == 1) {
             const int zc = c->rhs_zchunk > 0 ? c->rhs_zchunk : rhs_zchunk_auto<NN, 1>(c);
-            e = rhs_prepare_alt(c, zc);
+            e = rhs_prepare_alt(c, zc, mixed);
         } else {
             const int zc = c->rhs_zchunk > 0 ? c->rhs_zchunk : rhs_zchunk_auto<NN, 0>(c);
-            e = rhs_prepare_step<NN, 0>(c, mixed, zc);
+            e = mixed ? rhs_prepare_step<NN, 0, true>(c, zc) : rhs_prepare_step<NN, 0, false>(c, zc);
         }
-        // the column solves of both forms are the FP64 ones
-        if (e == hipSuccess) e = solve_prepare<NN, ShapeStage2>(nz);
-        if (e == hipSuccess) e = solve_prepare<NN, ShapeStage3>(nz);
-        if (per_column_factors(c)) {
-            if (e == hipSuccess) e = solve_prepare_fl<NN, ShapeStage2, 2>(SolveGeom<NN, ShapeStage2>::lds_bytes(nz));
-            if (e == hipSuccess) e = solve_prepare_fl<NN, ShapeStage3, 2>(SolveGeom<NN, ShapeStage3>::lds_bytes(nz));
-        }
-        if (blocked_solve_used(c) && nz > 8 * kBlockedKL) {
-            if (e == hipSuccess) e = blocked_prepare<NN, ShapeStage2, 16>(blocked_lds_bytes(NN, nz));
-            if (e == hipSuccess) e = blocked_prepare<NN, ShapeStage3, 16>(blocked_lds_bytes(NN, nz));
-        } else if (blocked_solve_used(c) && nz + 2 * NN > 64) {
-            if (e == hipSuccess) e = blocked_prepare<NN, ShapeStage2, 8>(blocked_lds_bytes(NN, nz));
-            if (e == hipSuccess) e = blocked_prepare<NN, ShapeStage3, 8>(blocked_lds_bytes(NN, nz));
+        // the column solves: the FP64 step's shapes, or the precision form's
+        // (its stage-3 solve over a stratified background is the FP64 one)
+        auto solves = [&](auto s2, auto s3) -> hipError_t {
+            using S2 = decltype(s2);
+            using S3 = decltype(s3);
+            hipError_t h = solve_prepare<NN, S2>(nz);
+            if (h == hipSuccess) h = solve_prepare<NN, S3>(nz);
+            if (per_column_factors(c)) {
+                if (h == hipSuccess) h = solve_prepare_fl<NN, S2, 2>(SolveGeom<NN, S2>::lds_bytes(nz));
+                if (h == hipSuccess) h = solve_prepare_fl<NN, S3, 2>(SolveGeom<NN, S3>::lds_bytes(nz));
+            }
+            if (blocked_solve_used(c) && nz > 8 * kBlockedKL) {
+                if (h == hipSuccess) h = blocked_prepare<NN, S2, 16>(blocked_lds_bytes(NN, nz));
+                if (h == hipSuccess) h = blocked_prepare<NN, S3, 16>(blocked_lds_bytes(NN, nz));
+            } else if (blocked_solve_used(c) && nz + 2 * NN > 64) {
+                if (h == hipSuccess) h = blocked_prepare<NN, S2, 8>(blocked_lds_bytes(NN, nz));
+                if (h == hipSuccess) h = blocked_prepare<NN, S3, 8>(blocked_lds_bytes(NN, nz));
+            }
+            return h;
+        };
+        if (e == hipSuccess) {
+            if (!mixed) e = solves(ShapeStage2{}, ShapeStage3{});
+            else if (stratified(c)) e = solves(ShapeStage2R{}, ShapeStage3{});
+            else e = solves(ShapeStage2R{}, ShapeStage3R{});
         }
         return e;
     });
 }
 
-int rhs_zchunk_in_use(const numa_ctx *c, bool mixed)
+int rhs_zchunk_in_use(const numa_ctx *c)
 {
     int zc = 0;
     (void)dispatch(c->N, [&](auto n) -> hipError_t {
         constexpr int NN = decltype(n)::value;
-        zc = c->rhs_tile == 1 && !mixed ? rhs_zchunk_auto<NN, 1>(c) : rhs_zchunk_auto<NN, 0>(c);
+        zc = c->rhs_tile == 1 ? rhs_zchunk_auto<NN, 1>(c) : rhs_zchunk_auto<NN, 0>(c);
         return hipSuccess;
     });
     return zc;

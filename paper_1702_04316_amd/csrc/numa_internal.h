@@ -84,7 +84,7 @@ struct numa_ctx {
     int column_solver = 0;         // NUMA_SOLVER_*: 0 auto, 1 one lane per column, 2 level-blocked,
                                    // 3 one lane per column with per-column factors
     double *work = nullptr;        // stage buffers (19 fields)
-    char *work_mix = nullptr;      // precision form: R1, E3 (mixed layout), Q2, Q3 rho' and w (FP64)
+    char *work_mix = nullptr;      // precision form: R1 (FP32), E3, Q2, Q3 rho' and w (FP64)
     int *flag = nullptr;           // device non-finite flag
     int factored = 0;
     double dt_factored = 0, lambda = 0;
@@ -140,9 +140,10 @@ hipError_t launch_rhs_two(numa_ctx *c, const double *Q, const double *e0, const 
                           double *out1, double k01, double k02, double k11, double k12);
 hipError_t launch_rhs_final(numa_ctx *c, const double *Q, const double *e0, double *out, double k);
 hipError_t launch_hevi_step(numa_ctx *c, double *q, double dt, hipEvent_t *ev = nullptr);
-// the precision form's stage buffers: bytes per unique node (16 more over a
-// stratified background, for theta' of Q2 and Q3)
-constexpr size_t kMixedBytesPerNode = 104;
+// the precision form's stage buffers: bytes per unique node (R1 in a 24-byte
+// slot, E3 40, Q2 and Q3 rho' and w 32; 16 more over a stratified
+// background, for theta' of Q2 and Q3)
+constexpr size_t kMixedBytesPerNode = 96;
 inline size_t mixed_bytes_per_node(const numa_ctx *c) { return kMixedBytesPerNode + (stratified(c) ? 16 : 0); }
 hipError_t launch_hevi_step_mixed(numa_ctx *c, double *q, double dt, hipEvent_t *ev = nullptr);
 // the same with the stage buffers at mb (kMixedBytesPerNode * np bytes)
@@ -161,10 +162,10 @@ hipError_t prepare_step(numa_ctx *c, bool mixed);
 hipError_t autotune_rhs(numa_ctx *c, const double *state, int reps, int *zchunk_out, int *tile_out);
 // TX of tile variant (0, 1) of order N into *tx; returns TY
 int rhs_tile_shape(int N, int variant, int *tx);
-// the vertical chunk the right-hand sides of the FP64 step (or, mixed, of the
-// precision form) use: the set one, else the automatic
-int rhs_zchunk_in_use(const numa_ctx *c, bool mixed = false);
-// whether tile variant 1 differs from 0 for order N, and its LDS (FP64 form)
+// the vertical chunk the step's right-hand sides use (both forms): the set
+// one, else the automatic
+int rhs_zchunk_in_use(const numa_ctx *c);
+// whether tile variant 1 differs from 0 for order N, and its LDS
 bool rhs_alt_differs(int N);
 size_t rhs_lds_alt(int N, int zc, int nez);
 // abi.cpp: NUMA_OK or the error code (message recorded in the context)

@@ -1,8 +1,7 @@
 // The second tile variant of the right-hand-side kernel (Tile<N, 1>): the
-// FP64 step's three launches, compiled apart from kernels.hip so that the
-// two sets of instantiations build in parallel.  (The precision form keeps
-// the first tile: with the 18 x 6 tile at N = 6 its kernels returned
-// non-finite values, a fault not found.)
+// three launches of the FP64 step and the two of the precision form that
+// differ from them (FP32 R1), compiled apart from kernels.hip so that the
+// two sets of instantiations build in parallel.
 #include "rhs_kernel.h"
 
 namespace numa {
@@ -27,26 +26,31 @@ hipError_t for_order(int N, F &&f)
 
 }  // namespace
 
-hipError_t rhs_launch_alt(numa_ctx *c, const RhsParams &p, int epi)
+hipError_t rhs_launch_alt(numa_ctx *c, const RhsParams &p, int epi, bool mixed)
 {
     return for_order(c->N, [&](auto n) -> hipError_t {
         constexpr int NN = decltype(n)::value;
-        if (epi == EPI_R) return rhs_launch_t<NN, 1, EPI_R, false, false>(c, p);
-        if (epi == EPI_TWO) return rhs_launch_t<NN, 1, EPI_TWO, true, false>(c, p);
+        if (epi == EPI_R)
+            return mixed ? rhs_launch_t<NN, 1, EPI_R, false, true>(c, p) : rhs_launch_t<NN, 1, EPI_R, false, false>(c, p);
+        if (epi == EPI_TWO)
+            return mixed ? rhs_launch_t<NN, 1, EPI_TWO, true, true>(c, p) : rhs_launch_t<NN, 1, EPI_TWO, true, false>(c, p);
         return rhs_launch_t<NN, 1, EPI_FINAL, false, false>(c, p);
     });
 }
 
-hipError_t rhs_prepare_alt(const numa_ctx *c, int zc)
+hipError_t rhs_prepare_alt(const numa_ctx *c, int zc, bool mixed)
 {
-    return for_order(c->N, [&](auto n) { return rhs_prepare_step<decltype(n)::value, 1>(c, false, zc); });
+    return for_order(c->N, [&](auto n) {
+        constexpr int NN = decltype(n)::value;
+        return mixed ? rhs_prepare_step<NN, 1, true>(c, zc) : rhs_prepare_step<NN, 1, false>(c, zc);
+    });
 }
 
 size_t rhs_lds_alt(int N, int zc, int nez)
 {
     size_t b = 0;
     (void)for_order(N, [&](auto n) {
-        b = rhs_lds_bytes<decltype(n)::value, false, 1>(zc, nez);
+        b = rhs_lds_bytes<decltype(n)::value, 1>(zc, nez);
         return hipSuccess;
     });
     return b;

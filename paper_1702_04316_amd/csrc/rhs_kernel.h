@@ -45,21 +45,16 @@ template <> struct Tile<6, 1> { static constexpr int TX = 18, TY = 6; };
 template <> struct Tile<7, 1> { static constexpr int TX = 7, TY = 14; };
 template <> struct Tile<8, 1> { static constexpr int TX = 8, TY = 8; };  // no other shape fits: same as 0
 
-template <int N, int ES = 8, int V = 0>  // ES: bytes of an LDS ring element (8 FP64, 4 FP32); V: tile
+template <int N, int V = 0>  // V: tile variant
 struct RhsGeom {
     static constexpr int TX = Tile<N, V>::TX, TY = Tile<N, V>::TY;
     static constexpr int NT = TX * TY * N;          // threads
     static constexpr int LX = TX + N + 1;           // plane incl. halo
     static constexpr int LY = TY + N + 1;
     static constexpr int FS = LX * LY;              // one field of one plane
-    // a plane: rho', u, v, w, theta' (ES bytes each), then P' in FP64 (the
-    // pressure and its derivatives stay FP64 in every form), and with FP32
-    // fields FP64 copies of rho' and w for the buoyancy, the mass flux and
-    // w's tendency
-    static constexpr int POFF = (5 * FS * ES + 7) / 8 * 8;  // byte offset of P'
-    static constexpr int ROFF = POFF + 8 * FS;               // byte offset of the FP64 rho' (ES = 4)
-    static constexpr int WOFF = ROFF + 8 * FS;               // byte offset of the FP64 w (ES = 4)
-    static constexpr int PB = ES == 8 ? ROFF : WOFF + 8 * FS; // bytes of a plane
+    // a plane: rho', u, v, w, theta', P' (FP64 each)
+    static constexpr int POFF = 5 * FS * 8;         // byte offset of P'
+    static constexpr int PB = POFF + 8 * FS;        // bytes of a plane
     static constexpr int NS = 2 * N + 1;            // x/y stencil width
     // cross-shaped part of a plane that is loaded: tile rows with the x halo,
     // plus the y-halo rows of the tile columns
@@ -177,21 +172,15 @@ struct RhsParams {
 enum { EPI_R = 0, EPI_TWO = 1, EPI_FINAL = 2 };
 
 // Layout of a five-field stage buffer of np nodes: all FP64, or (M) the
-// precision form's R1 with u and v in FP32 and rho', w, theta' in FP64.  The
-// pressure perturbation P0 ((1+x)^gamma - 1) scales the relative rounding of
-// rho' and theta' by P0, so their stage values stay FP64; w's tendency holds
-// the stiff vertical pressure gradient and buoyancy, whose FP32 rounding,
-// multiplied by the vertical Courant number, reached 2e-6 relative in w
-// after 100 steps, so w stays FP64 too.  Byte offsets of the fields per
-// node: 0, 8, 16, 24, 32 (FP64) or 0, 8, 12, 16, 24 (M).
+// precision form's first-stage tendency R1 with all five fields in FP32.
+// R1 is a tendency: the step uses it only multiplied by dt (Sec. 2.2), so
+// its FP32 rounding is relative to the change over a step, not to the
+// state.  Byte offsets of the fields per node: 8 f (FP64) or 4 f (M).
 // Offsets passed in are those an FP64 field would have.
 template <bool M>
 struct FiveField {
-    static __device__ __forceinline__ bool f32(int f) { return M && (f == 1 || f == 2); }
-    static __device__ __forceinline__ size_t ofs(int f, long np)
-    {
-        return M ? size_t(np) * size_t(f == 0 ? 0 : (f == 1 ? 8 : (f == 2 ? 12 : 8 * f - 8))) : size_t(np) * 8 * size_t(f);
-    }
+    static __device__ __forceinline__ bool f32(int) { return M; }
+    static __device__ __forceinline__ size_t ofs(int f, long np) { return size_t(np) * (M ? 4 : 8) * size_t(f); }
     // field f stored alone at p
     static __device__ __forceinline__ double load1(const void *p, int f, unsigned off)
     {
@@ -211,23 +200,17 @@ struct FiveField {
 };
 
 // Buffers of one right-hand-side launch.  The FP64 step keeps every field
-// in FP64.  The precision form (MIX) keeps the state q and the accumulator
-// ACC (e0 of the last two launches, out1) in FP64, its other stage buffers
-// in the mixed layout, and the LDS ring (except P' and FP64 copies of rho'
-// and w) and the stencil arithmetic in FP32.  FP64 in that form: P' and its
-// derivatives, w with its derivatives and tendency, and the mass flux
-// (rho0 + rho') u_i with its divergence.  The flux divergence is a small
-// difference of large terms at the finest LGL spacing, and its FP32
-// rounding, carried through rho' into the buoyancy, left 2.5e-6 relative
-// error in w after 100 steps at N = 7; FP32 derivatives of w under a strong
-// wind left 2e-6 after 50 steps at N = 3.
+// in FP64.  The precision form (MIX) stores R1 in FP32 (written by the first
+// launch, read by the second); its arithmetic, the LDS ring and every other
+// buffer are the FP64 step's.  Stage values (Q2, Q3, E3, ACC) stay FP64: the
+// next right-hand side differentiates them, which multiplies their rounding
+// by the stencil's sum of |coefficients| (about N^2 / h).
 template <int EPI, bool MIX>
 struct RhsTypes {
     using A = FiveField<false>;                     // inputs a[]
     using E1 = FiveField<MIX>;                      // e1 (R1)
     using O0 = FiveField<MIX && EPI == EPI_R>;      // out0 (R1 in the first launch)
     using D = FiveField<false>;                     // e0, out1
-    using C = std::conditional_t<MIX, float, double>;
 };
 
 // Map the launch index to a tile so that each of the 8 XCDs (which receive
@@ -252,37 +235,27 @@ __device__ __forceinline__ double stage_input(const RhsParams &p, int f, unsigne
 }
 
 template <int N, int EPI, bool HASB, bool MIX, bool NT = false, int V = 0>
-__global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8, V>::NT), (RhsGeom<N, MIX ? 4 : 8, V>::MINW)) void k_rhs(RhsParams p)
+__global__ __launch_bounds__((RhsGeom<N, V>::NT), (RhsGeom<N, V>::MINW)) void k_rhs(RhsParams p)
 {
     using TT = RhsTypes<EPI, MIX>;
     using TA = typename TT::A;
     using TE1 = typename TT::E1;
     using TO0 = typename TT::O0;
-    using C = typename TT::C;
-    using G = RhsGeom<N, sizeof(C), V>;
+    using G = RhsGeom<N, V>;
     constexpr int NQ = N + 1, NS = G::NS, TX = G::TX, TY = G::TY, LX = G::LX, FS = G::FS;
-    // dynamic LDS: ring of N+1 planes [rho', u, v, w, theta' (C)][P' (FP64)]
-    // of [LY][LX], then per-level tables rho0, P0, 1/(rho0 theta0), theta0,
+    // dynamic LDS: ring of N+1 planes [rho', u, v, w, theta', P'] of
+    // [LY][LX], then per-level tables rho0, P0, 1/(rho0 theta0), theta0,
     // d theta0/dz for the
     // levels this chunk touches, zsc [3][nez], and the interface shares
     // [2][6][TX*TY] (FP64)
     extern __shared__ double lds_block[];
     char *const ringb = reinterpret_cast<char *>(lds_block);
-    auto cfield = [&](int slot) { return reinterpret_cast<C *>(ringb + slot * G::PB); };
+    auto cfield = [&](int slot) { return reinterpret_cast<double *>(ringb + slot * G::PB); };
     auto pfield = [&](int slot) { return reinterpret_cast<double *>(ringb + slot * G::PB + G::POFF); };
-    auto rfield = [&](int slot) { return reinterpret_cast<double *>(ringb + slot * G::PB + G::ROFF); };
-    auto wfield = [&](int slot) { return reinterpret_cast<double *>(ringb + slot * G::PB + G::WOFF); };
-    // line stencils (FP64 in both forms: the line sums round them for their
-    // FP32 products) and the differentiation matrix (FP32 in the precision
-    // form, with an FP64 copy for its FP64 column sums)
+    // line stencils and the differentiation matrix
     __shared__ double sw[2][N][NS];
-    __shared__ C sD[NQ * NQ];
-    __shared__ double sDd_m[MIX ? NQ * NQ : 1];
+    __shared__ double sD[NQ * NQ];
     const double *const swd = &sw[0][0][0];
-    const double *const sDd = [&]() -> const double * {
-        if constexpr (MIX) return sDd_m;
-        else return sD;
-    }();
 
     const int tid = threadIdx.x;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
@@ -311,10 +284,7 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8, V>::NT), (RhsGeom<N, MIX ?
     for (int s = tid; s < 2 * N * NS; s += G::NT) {
         (&sw[0][0][0])[s] = p.wxy[s];
     }
-    for (int s = tid; s < NQ * NQ; s += G::NT) {
-        sD[s] = C(p.D[s]);
-        if constexpr (MIX) sDd_m[s] = p.D[s];
-    }
+    for (int s = tid; s < NQ * NQ; s += G::NT) sD[s] = p.D[s];
     for (int s = tid; s < nlev; s += G::NT) {
         const double r0 = p.rho0[kb + s];
         const double t0 = p.th0[kb + s];
@@ -325,19 +295,6 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8, V>::NT), (RhsGeom<N, MIX ?
         sTZ[s] = p.th0z[kb + s];
     }
     for (int s = tid; s < 3 * p.nez; s += G::NT) zs[s] = p.zsc[s];
-    // Precision form: the ring holds u - uref and v - vref in FP32, with the
-    // workgroup's reference velocities uref, vref (FP64) taken at the first
-    // node of its tile.  A wind far larger than its variation (a uniform
-    // wind) then keeps its variation's relative precision in the FP32
-    // derivatives, which annihilate the constants; u and v themselves are
-    // uref + (u - uref).  The FP64 form stores u and v as they are.
-    double uref = 0.0, vref = 0.0;
-    if constexpr (MIX) {
-        const unsigned oref = unsigned(ez0 * N) * pbytes + unsigned(y0 * nx + x0) * 8u;
-        uref = stage_input<HASB, TA, TE1>(p, 1, oref);
-        vref = stage_input<HASB, TA, TE1>(p, 2, oref);
-    }
-
     // plane loads of this thread: which of the N new planes (1..N, 0 = none),
     // LDS offset in the plane, byte offset in a level plane
     int it_p[G::NITEM], it_l[G::NITEM];
@@ -413,17 +370,10 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8, V>::NT), (RhsGeom<N, MIX ?
         for (int s = 0; s < G::NITEM; ++s) {
             const int k = kbase + it_p[s], kl = k - kb;
             const double Pp = pressure_perturbation(v[s][0], v[s][4], sR0[kl], sP0[kl], sIRT[kl], sT0[kl], eos);
-            C *d = cfield(k % NQ) + it_l[s];
-            d[0 * FS] = C(v[s][0]);
-            d[1 * FS] = C(v[s][1] - uref);
-            d[2 * FS] = C(v[s][2] - vref);
-            d[3 * FS] = C(v[s][3]);
-            d[4 * FS] = C(v[s][4]);
+            double *d = cfield(k % NQ) + it_l[s];
+#pragma unroll
+            for (int f = 0; f < 5; ++f) d[f * FS] = v[s][f];
             pfield(k % NQ)[it_l[s]] = Pp;
-            if constexpr (MIX) {
-                rfield(k % NQ)[it_l[s]] = v[s][0];
-                wfield(k % NQ)[it_l[s]] = v[s][3];
-            }
         }
     };
     // The first right-hand side (no epilogue inputs, fewest live registers)
@@ -435,29 +385,23 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8, V>::NT), (RhsGeom<N, MIX ?
     // sum_n D[r][n] g(level ez*N + n) over the own column for the six
     // z-differentiated quantities rho w, u, v, w, theta' (out) and P' (outp)
     // (not unrolled: unrolled, all 6*(N+1) LDS reads would be in flight at once)
-    auto zsum = [&](int ez, int r, C *out, double &outp, double &outr, double &outw) {
+    auto zsum = [&](int ez, int r, double *out, double &outp, double &outr, double &outw) {
 #pragma unroll
-        for (int f = 0; f < 5; ++f) out[f] = C(0);
+        for (int f = 0; f < 5; ++f) out[f] = 0.0;
         outp = 0.0;
         outr = 0.0;
         outw = 0.0;
         int k = ez * N, slot = k % NQ;
 #pragma unroll 1
         for (int n = 0; n < NQ; ++n) {
-            const C *q = cfield(slot) + l_own;
-            const C d = sD[r * NQ + n];
-            if constexpr (MIX) {
-                const double wv = wfield(slot)[l_own], dd = sDd[r * NQ + n];
-                outr += dd * ((sR0[k - kb] + rfield(slot)[l_own]) * wv);
-                outw += dd * wv;
-            } else {
-                outr += double(d) * ((C(sR0[k - kb]) + q[0]) * q[3 * FS]);
-                outw += double(d) * q[3 * FS];
-            }
+            const double *q = cfield(slot) + l_own;
+            const double d = sD[r * NQ + n];
+            outr += d * ((sR0[k - kb] + q[0]) * q[3 * FS]);
+            outw += d * q[3 * FS];
             out[1] += d * q[1 * FS];
             out[2] += d * q[2 * FS];
             out[4] += d * q[4 * FS];
-            outp += double(d) * pfield(slot)[l_own];
+            outp += d * pfield(slot)[l_own];
             ++k;
             slot = (slot + 1 == NQ) ? 0 : slot + 1;
         }
@@ -482,85 +426,64 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8, V>::NT), (RhsGeom<N, MIX ?
     // tendencies at level k (Set2NC, Sec. 3.1) from the x/y line derivatives
     // of the plane in the ring and the scaled vertical derivatives dz; then
     // the stage epilogue with its inputs ev
-    auto node = [&](int k, const C *dz, double dzp, double dz0, double dzw, const double *ev) {
-        const C *q = cfield(k % NQ);
+    auto node = [&](int k, const double *dz, double dzp, double dz0, double dzw, const double *ev) {
+        const double *q = cfield(k % NQ);
         const double *qp = pfield(k % NQ);
-        const C r0 = C(sR0[k - kb]);
-        const C rp = q[l_own], w = q[3 * FS + l_own];
-        C u = q[FS + l_own], v = q[2 * FS + l_own];
-        if constexpr (MIX) {
-            u = C(uref + double(u));
-            v = C(vref + double(v));
-        }
-        const C ir = C(1) / (r0 + rp);
-        // rho' and 1/rho for the pressure and buoyancy terms: FP64 in every form
-        const double rpd = MIX ? rfield(k % NQ)[l_own] : double(rp);
-        const double irp = MIX ? 1.0 / (sR0[k - kb] + rpd) : double(ir);
+        const double r0 = sR0[k - kb];
+        const double rp = q[l_own], w = q[3 * FS + l_own];
+        const double u = q[FS + l_own], v = q[2 * FS + l_own];
+        const double ir = 1.0 / (r0 + rp);
         // the vertical terms first, so that only the tendencies stay live
         // across the x and y stencils (with few live registers the stencil
         // loads can be in flight together)
-        C R[5];
-        double R0 = dz0;
+        double R[5];
+        R[0] = dz0;
         R[1] = w * dz[1];
         R[2] = w * dz[2];
-        // w's tendency accumulates in FP64 in every form: it holds the nearly
-        // balanced vertical pressure gradient and buoyancy (in the precision
-        // form only its advection products are FP32)
-        double R3;
-        if constexpr (MIX)
-            R3 = wfield(k % NQ)[l_own] * dzw + (dzp * irp + eos.grav * rpd * irp);
-        else
-            R3 = w * dzw + dzp * ir + eos.grav * rp * ir;
+        // w: the nearly balanced vertical pressure gradient and buoyancy
+        R[3] = w * dzw + dzp * ir + eos.grav * rp * ir;
         // theta': advection of theta' and of the background, w d theta0/dz
-        R[4] = w * dz[4] + w * C(sTZ[k - kb]);
+        R[4] = w * dz[4] + w * sTZ[k - kb];
         // line derivative of the six quantities along x (dir 0) or y (dir 1)
         // (not unrolled: unrolled, the scheduler hoists all its LDS reads)
-        auto line = [&](int dir, C *d5, double &dp, double &dfl, double &dwl) {
+        auto line = [&](int dir, double *d5, double &dp, double &dfl, double &dwl) {
             const double *cwd = dir == 0 ? cwxd : cwyd;
-            const double *rq = rfield(k % NQ);
-            const double *wq = wfield(k % NQ);
             const int base = dir == 0 ? l_x : l_y, step = dir == 0 ? 1 : LX;
             const int fv = dir == 0 ? FS : 2 * FS;  // the velocity in rho u or rho v
-            const double vr = dir == 0 ? uref : vref;
 #pragma unroll
-            for (int f = 0; f < 5; ++f) d5[f] = C(0);
+            for (int f = 0; f < 5; ++f) d5[f] = 0.0;
             dp = 0.0;
             dfl = 0.0;
             dwl = 0.0;
 #pragma unroll 1
             for (int m = 0; m < NS; ++m) {
-                // one coefficient read: the FP64 table (the only one in the
-                // FP64 form), rounded for the FP32 products
-                const double cmd = cwd[m];
-                const C cm = C(cmd);
-                const C *qm = q + base + m * step;
-                if constexpr (MIX) dfl += cmd * ((sR0[k - kb] + rq[base + m * step]) * (vr + double(qm[fv])));
-                else dfl += cmd * ((r0 + qm[0]) * qm[fv]);
+                const double cm = cwd[m];
+                const double *qm = q + base + m * step;
+                dfl += cm * ((r0 + qm[0]) * qm[fv]);
                 d5[1] += cm * qm[1 * FS];
                 d5[2] += cm * qm[2 * FS];
-                if constexpr (MIX) dwl += cmd * wq[base + m * step];
-                else dwl += cmd * qm[3 * FS];
+                dwl += cm * qm[3 * FS];
                 d5[4] += cm * qm[4 * FS];
-                dp += cmd * qp[base + m * step];
+                dp += cm * qp[base + m * step];
             }
         };
-        C d5[5];
+        double d5[5];
         double dp, dfl, dwl;
         line(0, d5, dp, dfl, dwl);
-        R0 += dfl;
-        R[1] += u * d5[1] + C(dp * irp);
+        R[0] += dfl;
+        R[1] += u * d5[1] + dp * ir;
         R[2] += u * d5[2];
-        R3 += double(u) * dwl;
+        R[3] += u * dwl;
         R[4] += u * d5[4];
         line(1, d5, dp, dfl, dwl);
-        R0 = -(R0 + dfl);
+        R[0] = -(R[0] + dfl);
         R[1] = -(R[1] + v * d5[1]);
-        R[2] = -(R[2] + v * d5[2] + C(dp * irp));
-        R3 = -(R3 + double(v) * dwl);
+        R[2] = -(R[2] + v * d5[2] + dp * ir);
+        R[3] = -(R[3] + v * dwl);
         R[4] = -(R[4] + v * d5[4]);
-        if (k == 0 || k == p.nz - 1) R3 = 0.0;
+        if (k == 0 || k == p.nz - 1) R[3] = 0.0;
         if (!owner) return;
-        auto Rv = [&](int f) -> double { return f == 3 ? R3 : (f == 0 ? R0 : double(R[f])); };
+        auto Rv = [&](int f) -> double { return R[f]; };
         const unsigned off = unsigned(k) * pbytes + own;
         if constexpr (EPI == EPI_R) {
 #pragma unroll
@@ -598,17 +521,13 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8, V>::NT), (RhsGeom<N, MIX ?
         const double v = stage_input<HASB, TA, TE1>(p, 2, off), w = stage_input<HASB, TA, TE1>(p, 3, off);
         const double th = stage_input<HASB, TA, TE1>(p, 4, off);
         const double Pp = pressure_perturbation(rp, th, sR0[kl], sP0[kl], sIRT[kl], sT0[kl], eos);
-        C *d = cfield(k % NQ) + it_l[s];
-        d[0 * FS] = C(rp);
-        d[1 * FS] = C(u - uref);
-        d[2 * FS] = C(v - vref);
-        d[3 * FS] = C(w);
-        d[4 * FS] = C(th);
+        double *d = cfield(k % NQ) + it_l[s];
+        d[0 * FS] = rp;
+        d[1 * FS] = u;
+        d[2 * FS] = v;
+        d[3 * FS] = w;
+        d[4 * FS] = th;
         pfield(k % NQ)[it_l[s]] = Pp;
-        if constexpr (MIX) {
-            rfield(k % NQ)[it_l[s]] = rp;
-            wfield(k % NQ)[it_l[s]] = w;
-        }
     }
     if (c == 0 && ez0 > 0) {
         const int eb = ez0 - 1;
@@ -616,16 +535,14 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8, V>::NT), (RhsGeom<N, MIX ?
         for (int n = 0; n < NQ; ++n) {
             const int k = eb * N + n, kl = k - kb;
             const unsigned off = unsigned(k) * pbytes + own;
-            // rounded to the ring's type first, as the layer loop sees them
-            const double rp = C(stage_input<HASB, TA, TE1>(p, 0, off));
-            const double u = C(stage_input<HASB, TA, TE1>(p, 1, off) - uref);
-            const double v = C(stage_input<HASB, TA, TE1>(p, 2, off) - vref);
-            const double w = stage_input<HASB, TA, TE1>(p, 3, off);  // FP64 in both forms
-            const double th0 = stage_input<HASB, TA, TE1>(p, 4, off), th = C(th0);
-            const double rho = MIX ? sR0[kl] + stage_input<HASB, TA, TE1>(p, 0, off) : double(C(sR0[kl])) + rp;
-            const double Pp = pressure_perturbation(stage_input<HASB, TA, TE1>(p, 0, off), th0, sR0[kl], sP0[kl],
-                                                    sIRT[kl], sT0[kl], eos);
-            const double d = double(sD[N * NQ + n]);
+            const double rp = stage_input<HASB, TA, TE1>(p, 0, off);
+            const double u = stage_input<HASB, TA, TE1>(p, 1, off);
+            const double v = stage_input<HASB, TA, TE1>(p, 2, off);
+            const double w = stage_input<HASB, TA, TE1>(p, 3, off);
+            const double th = stage_input<HASB, TA, TE1>(p, 4, off);
+            const double rho = sR0[kl] + rp;
+            const double Pp = pressure_perturbation(rp, th, sR0[kl], sP0[kl], sIRT[kl], sT0[kl], eos);
+            const double d = sD[N * NQ + n];
             acc[0] += d * (rho * w);
             acc[1] += d * u;
             acc[2] += d * v;
@@ -636,8 +553,7 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8, V>::NT), (RhsGeom<N, MIX ?
         const double st = zs[2 * p.nez + eb];
         double *zb = zp + (ez0 & 1) * 6 * (TX * TY) + txy;
 #pragma unroll
-        for (int f = 0; f < 5; ++f) zb[f * (TX * TY)] = (f == 0 || f == 3) ? st * acc[f] : double(C(st * acc[f]));
-        zb[5 * (TX * TY)] = st * acc[5];
+        for (int f = 0; f < 6; ++f) zb[f * (TX * TY)] = st * acc[f];
     }
 
     double vpre[G::NITEM][NV];
@@ -657,29 +573,27 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8, V>::NT), (RhsGeom<N, MIX ?
         }
         double ev[NEPI];
         epi_load(unsigned(ez * N + c) * pbytes + own, ev);
-        C dz[5], sum[5];
+        double dz[5], sum[5];
         double sump, sumr, sumw;
         zsum(ez, c, sum, sump, sumr, sumw);
-        const double scd = (c == 0) ? zs[p.nez + ez] : zs[ez];
-        const C sc = C(scd);
+        const double sc = (c == 0) ? zs[p.nez + ez] : zs[ez];
         const double *zb = zp + (ez & 1) * 6 * (TX * TY) + txy;
         const bool below = c == 0 && ez > 0;  // a lower element shares the node
 #pragma unroll
-        for (int f = 0; f < 5; ++f) dz[f] = (below ? C(zb[f * (TX * TY)]) : C(0)) + sc * sum[f];
-        const double dzp = (below ? zb[5 * (TX * TY)] : 0.0) + scd * sump;
-        const double dz0 = (below ? zb[0] : 0.0) + scd * sumr;
-        const double dzw = (below ? zb[3 * (TX * TY)] : 0.0) + scd * sumw;
+        for (int f = 0; f < 5; ++f) dz[f] = (below ? zb[f * (TX * TY)] : 0.0) + sc * sum[f];
+        const double dzp = (below ? zb[5 * (TX * TY)] : 0.0) + sc * sump;
+        const double dz0 = (below ? zb[0] : 0.0) + sc * sumr;
+        const double dzw = (below ? zb[3 * (TX * TY)] : 0.0) + sc * sumw;
         node(ez * N + c, dz, dzp, dz0, dzw, ev);
         // this element's share of the interface (or top node) above
         const double st = zs[2 * p.nez + ez];
         double *zn = zp + ((ez + 1) & 1) * 6 * (TX * TY) + txy;
         if (c == 0) {
-            C s5[5];
+            double s5[5];
             double s5p, s5r, s5w;
             zsum(ez, N, s5, s5p, s5r, s5w);
 #pragma unroll
-            for (int f = 0; f < 5; ++f)
-                zn[f * (TX * TY)] = f == 0 ? st * s5r : (f == 3 ? st * s5w : double(C(st) * s5[f]));
+            for (int f = 0; f < 5; ++f) zn[f * (TX * TY)] = f == 0 ? st * s5r : (f == 3 ? st * s5w : st * s5[f]);
             zn[5 * (TX * TY)] = st * s5p;
         }
     }
@@ -687,9 +601,9 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8, V>::NT), (RhsGeom<N, MIX ?
     __syncthreads();  // the shares of the top element are in LDS
     if (ez1 == p.nez && c == 0) {
         const double *zb = zp + (ez1 & 1) * 6 * (TX * TY) + txy;
-        C dz[5];
+        double dz[5];
 #pragma unroll
-        for (int f = 0; f < 5; ++f) dz[f] = C(zb[f * (TX * TY)]);
+        for (int f = 0; f < 5; ++f) dz[f] = zb[f * (TX * TY)];
         const double dzp = zb[5 * (TX * TY)];
         double ev[NEPI];
         epi_load(unsigned(p.nez * N) * pbytes + own, ev);
@@ -702,11 +616,10 @@ __global__ __launch_bounds__((RhsGeom<N, MIX ? 4 : 8, V>::NT), (RhsGeom<N, MIX ?
 // ---------------------------------------------------------------------------
 // dynamic LDS of k_rhs: the ring, three per-level tables of the chunk's
 // levels (zchunk + 1 elements), the element factors, the interface shares
-template <int N, bool MIX = false, int V = 0>
+template <int N, int V = 0>
 size_t rhs_lds_bytes(int zchunk, int nez)
 {
-    constexpr int ES = MIX ? 4 : 8;
-    using G = RhsGeom<N, ES, V>;
+    using G = RhsGeom<N, V>;
     return G::LDS + sizeof(double) * (5 * ((zchunk + 1) * N + 1) + 3 * nez + 2 * 6 * G::TX * G::TY);
 }
 
@@ -714,7 +627,7 @@ template <int N, int V = 0>
 int rhs_zchunk_auto(const numa_ctx *c)
 {
     if (c->rhs_zchunk > 0) return c->rhs_zchunk;
-    using G = RhsGeom<N, 8, V>;
+    using G = RhsGeom<N, V>;
     long tiles = ((c->nx + G::TX - 1) / G::TX) * ((c->ny + G::TY - 1) / G::TY);
     // enough workgroups for every CU (256) to hold two
     int zc = c->nez;
@@ -755,7 +668,7 @@ inline bool nontemporal_stores(const numa_ctx *c)
 template <int N, int V, int EPI, bool HASB, bool MIX>
 hipError_t rhs_launch_t(numa_ctx *c, RhsParams p)
 {
-    using G = RhsGeom<N, 8, V>;
+    using G = RhsGeom<N, V>;
     p.rho0 = c->lev.rho0;
     p.P0 = c->lev.P0;
     p.zsc = c->lev.zsc;
@@ -773,9 +686,9 @@ hipError_t rhs_launch_t(numa_ctx *c, RhsParams p)
     p.ntx = int((c->nx + G::TX - 1) / G::TX);
     p.nty = int((c->ny + G::TY - 1) / G::TY);
     p.flag = c->flag;
-    const size_t lds = rhs_lds_bytes<N, MIX, V>(p.zchunk, p.nez);
+    const size_t lds = rhs_lds_bytes<N, V>(p.zchunk, p.nez);
     dim3 grid(unsigned(p.ntx * p.nty * p.nchunk));
-    if (!MIX && nontemporal_stores(c)) {
+    if (nontemporal_stores(c)) {
         hipError_t e = rhs_prepare<N, EPI, HASB, MIX, true, V>(lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_rhs<N, EPI, HASB, MIX, true, V>), grid, dim3(G::NT), lds, c->stream, p);
@@ -788,36 +701,28 @@ hipError_t rhs_launch_t(numa_ctx *c, RhsParams p)
 }
 
 // The LDS opt-ins of the three right-hand sides of a step with tile V and
-// vertical chunk zc (before any stream capture).
-template <int N, int V>
-hipError_t rhs_prepare_step(const numa_ctx *c, bool mixed, int zc)
+// vertical chunk zc (before any stream capture); MIX: the precision form,
+// whose last right-hand side is the FP64 step's.
+template <int N, int V, bool MIX>
+hipError_t rhs_prepare_step(const numa_ctx *c, int zc)
 {
-    hipError_t e = hipSuccess;
-    if (!mixed) {
-        const size_t lds = rhs_lds_bytes<N, false, V>(zc, c->nez);
-        if (nontemporal_stores(c)) {
-            if (e == hipSuccess) e = rhs_prepare<N, EPI_R, false, false, true, V>(lds);
-            if (e == hipSuccess) e = rhs_prepare<N, EPI_TWO, true, false, true, V>(lds);
-            if (e == hipSuccess) e = rhs_prepare<N, EPI_FINAL, false, false, true, V>(lds);
-        } else {
-            if (e == hipSuccess) e = rhs_prepare<N, EPI_R, false, false, false, V>(lds);
-            if (e == hipSuccess) e = rhs_prepare<N, EPI_TWO, true, false, false, V>(lds);
-            if (e == hipSuccess) e = rhs_prepare<N, EPI_FINAL, false, false, false, V>(lds);
-        }
-    } else {
-        const size_t lds = rhs_lds_bytes<N, true, V>(zc, c->nez);
-        if (e == hipSuccess) e = rhs_prepare<N, EPI_R, false, true, false, V>(lds);
-        if (e == hipSuccess) e = rhs_prepare<N, EPI_TWO, true, true, false, V>(lds);
-        if (e == hipSuccess) e = rhs_prepare<N, EPI_FINAL, false, true, false, V>(lds);
-    }
-    return e;
+    const size_t lds = rhs_lds_bytes<N, V>(zc, c->nez);
+    auto three = [&](auto nt) -> hipError_t {
+        constexpr bool NTS = decltype(nt)::value;
+        hipError_t e = rhs_prepare<N, EPI_R, false, MIX, NTS, V>(lds);
+        if (e == hipSuccess) e = rhs_prepare<N, EPI_TWO, true, MIX, NTS, V>(lds);
+        if (e == hipSuccess) e = rhs_prepare<N, EPI_FINAL, false, false, NTS, V>(lds);
+        return e;
+    };
+    return nontemporal_stores(c) ? three(std::true_type{}) : three(std::false_type{});
 }
 
-// The second tile variant (rhs_alt.hip): the FP64 step's three right-hand
-// sides (EPI_R, EPI_TWO with the stage-2 inputs, EPI_FINAL).
-hipError_t rhs_launch_alt(numa_ctx *c, const RhsParams &p, int epi);
-hipError_t rhs_prepare_alt(const numa_ctx *c, int zc);
-// dynamic LDS of the variant's launch with vertical chunk zc (FP64 form)
+// The second tile variant (rhs_alt.hip): the step's three right-hand sides
+// (EPI_R, EPI_TWO with the stage-2 inputs, EPI_FINAL), of the FP64 step or
+// (mixed) of the precision form.
+hipError_t rhs_launch_alt(numa_ctx *c, const RhsParams &p, int epi, bool mixed);
+hipError_t rhs_prepare_alt(const numa_ctx *c, int zc, bool mixed);
+// dynamic LDS of the variant's launch with vertical chunk zc
 size_t rhs_lds_alt(int N, int zc, int nez);
 // whether variant 1 differs from variant 0 for order N
 bool rhs_alt_differs(int N);

@@ -25,3 +25,16 @@ def test_byte_model_matches_field_passes():
     assert kb["colsolve_stage3"] - kb["colsolve_stage2"] == 4 * f
     # 1.397 GB per step on the benchmark grid
     assert abs(sum(kb.values()) / 1e9 - 1.397) < 0.001
+
+
+def test_precision_form_byte_model():
+    """R1 in FP32: its 14 field passes (5 written, 9 read) move 4 bytes per
+    value, the other 51 passes 8: 464 bytes per node against 520."""
+    import bench
+    np_, ncol, nz, N = 2686976, 65536, 41, 4
+    k64 = dict(bench.kernel_bytes(np_, ncol, nz, N))
+    k32 = dict(bench.kernel_bytes(np_, ncol, nz, N, r1=4))
+    F = nz * (4 * N + 1) * 8
+    assert sum(k32.values()) == 464 * np_ + 2 * F
+    assert sum(k64.values()) - sum(k32.values()) == 14 * 4 * np_
+    assert k32["rhs_stage3"] == k64["rhs_stage3"]

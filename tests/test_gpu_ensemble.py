@@ -108,12 +108,7 @@ def _oracle(O, g, bg):
 
 
 # Relative L2 bars per variable (rho', u, v, w, theta') after up to 50 steps.
-# The precision form's w on the N = 3 domain (6 vertical elements of
-# 1.7 km, theta' spread over the whole small box) reaches 2.3e-6: its FP32
-# theta', u and v tendencies couple into w through the pressure and the
-# buoyancy, and w is the smallest variable (the same domain without wind
-# leaves 2.4e-6 in u and v too); the other three domains stay below 9e-7.
-ORACLE_BARS = {False: [1e-11] * 5, True: [1e-6, 1e-6, 1e-6, 3e-6, 1e-6]}
+ORACLE_BARS = {False: [1e-11] * 5, True: [1e-6] * 5}
 
 
 @pytest.mark.timeout(600)

@@ -1,6 +1,6 @@
-"""GPU tests of the precision form (numa_hevi_step_mixed): FP32 right-hand
-sides and u, v stage values; FP64 state, accumulator, rho'/w/theta' stage
-values, pressure perturbation, w tendency and column solves.
+"""GPU tests of the precision form (numa_hevi_step_mixed): the first-stage
+tendency R1 stored in FP32; FP64 state, accumulator, stage values,
+right-hand-side arithmetic and column solves.
 
 The bar is a relative L2 error per variable of at most 1e-6 against the
 FP64 oracle after 100 steps, at N = 4 and N = 7, and against the FP64 step

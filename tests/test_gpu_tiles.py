@@ -1,7 +1,8 @@
 """GPU tests of the right-hand side's launch configurations: the second tile
 shape of every order and the vertical chunks give the same steps as the
 default configuration (each node's arithmetic does not depend on the tile or
-the chunk; the precision form keeps the first tile), and the autotuner keeps
+the chunk, in either form; the precision form keeps the first tile at N = 6
+and stays within 1e-6 of the FP64 step), and the autotuner keeps
 a configuration that the step then uses.  The default configuration is the
 one the oracle parity tests check."""
 import numpy as np
@@ -49,8 +50,11 @@ def test_tiles_and_chunks_give_the_same_steps(torch_cuda, numa_mod, N, nex, ney,
     g = W.Grid(9000.0 * nex, 7000.0 * ney, 6000.0, nex, ney, nez, N)
     dt = min(W.dt_for_courant(g, 15.0, "z"), W.dt_for_courant(g, 0.4, "x"), W.dt_for_courant(g, 0.4, "y"))
     q0 = W.make_random_state(g, 60 + N, wind=4.0)
+    fp64 = None
     for mixed in (False, True):
         ref, cfg0 = _steps(torch_cuda, numa_mod, g, q0, dt, 0, 0, mixed)
+        if not mixed:
+            fp64 = ref
         assert cfg0["tile"] == 0 and cfg0["TX"] % N == 0 and cfg0["TY"] % N == 0
         for tile, zc in ((0, 1), (1, 0), (1, 1)):
             if tile == 1 and N == 8:
@@ -65,6 +69,9 @@ def test_tiles_and_chunks_give_the_same_steps(torch_cuda, numa_mod, N, nex, ney,
             d = max(np.max(np.abs(out[f] - ref[f])) / np.max(np.abs(ref[f])) for f in range(5))
             print(f"N={N} mixed={mixed} tile {tile} ({cfg['TX']}x{cfg['TY']}) zchunk {cfg['zchunk']}: max rel diff {d}")
             assert d < 1e-14, (tile, zc, d)
+            if mixed:  # and the precision form stays within its bar of the FP64 step
+                e = max(np.linalg.norm(out[f] - fp64[f]) / np.linalg.norm(fp64[f]) for f in range(5))
+                assert e < 1e-6, (tile, zc, e)
 
 
 def test_autotune_keeps_a_configuration(torch_cuda, numa_mod):

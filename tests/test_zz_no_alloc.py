@@ -58,12 +58,12 @@ def test_noalloc_matches_allocating_entry_point(env):
 def test_noalloc_refuses_grid_above_fixed_size(env):
     torch, numa = env
     lib = numa.load()
-    g = W.Grid(3.2e6, 3.2e6, 8000.0, 32, 32, 9, 4)  # 128x128x37 = 606,208 nodes: fits
+    g = W.Grid(3.2e6, 3.2e6, 8000.0, 32, 32, 10, 4)  # 128x128x41 = 671,744 nodes: fits (at most 699,050)
     ctx, dt, q0 = _grid_state(torch, numa, g, seed=40)
     assert lib.numa_hevi_step_mixed_noalloc(ctx.ctx, C.c_void_p(q0.data_ptr()), dt, 1) == numa.NUMA_OK
     ctx.check()
     ctx.close()
-    g = W.Grid(3.2e6, 3.2e6, 8000.0, 32, 32, 10, 4)  # 128x128x41 = 671,744 nodes: too large
+    g = W.Grid(3.2e6, 3.2e6, 8000.0, 32, 32, 11, 4)  # 128x128x45 = 737,280 nodes: too large
     ctx, dt, q0 = _grid_state(torch, numa, g, seed=41)
     q1 = q0.clone()
     rc = lib.numa_hevi_step_mixed_noalloc(ctx.ctx, C.c_void_p(q1.data_ptr()), dt, 1)
