@@ -709,15 +709,6 @@ hipError_t solve_prepare(int M)
                             : solve_prepare_fl<N, SH, 0>(G::lds_total(M));
 }
 
-// Whether the precision form's right-hand sides take the context's tile
-// variant 1.  Not at N = 6: there its stage-2 kernel on the 18 x 6 tile
-// returned values that differ from the first tile's at most nodes (finite
-// after one step, non-finite after two), while the FP64 kernels on that tile
-// and the precision form on every other order's second tile agree with the
-// first tile to rounding.  The cause is not found, so the precision form
-// keeps the first tile at N = 6.
-inline bool mixed_uses_tile1(const numa_ctx *c) { return c->rhs_tile == 1 && c->N != 6; }
-
 // k_rhs with the context's tile variant: the second variant serves the
 // three right-hand sides of a step; other launches use the first.  MS: a
 // launch of the precision-form step, whose first two right-hand sides have
@@ -727,7 +718,7 @@ hipError_t rhs_launch(numa_ctx *c, RhsParams p)
 {
     constexpr bool MIX = MS && EPI != EPI_FINAL;
     const bool step_kernel = (EPI == EPI_TWO) == HASB;
-    if (step_kernel && (MS ? mixed_uses_tile1(c) : c->rhs_tile == 1)) return rhs_launch_alt(c, p, EPI, MIX);
+    if (step_kernel && c->rhs_tile == 1) return rhs_launch_alt(c, p, EPI, MIX);
     return rhs_launch_t<N, 0, EPI, HASB, MIX>(c, p);
 }
 
@@ -1256,7 +1247,7 @@ hipError_t prepare_step(numa_ctx *c, bool mixed)
         constexpr int NN = decltype(n)::value;
         const int nz = int(c->nz);
         hipError_t e;
-        if (mixed ? mixed_uses_tile1(c) : c->rhs_tile == 1) {
+        if (c->rhs_tile == 1) {
             const int zc = c->rhs_zchunk > 0 ? c->rhs_zchunk : rhs_zchunk_auto<NN, 1>(c);
             e = rhs_prepare_alt(c, zc, mixed);
         } else {

@@ -41,7 +41,11 @@ template <> struct Tile<2, 1> { static constexpr int TX = 16, TY = 8; };
 template <> struct Tile<3, 1> { static constexpr int TX = 12, TY = 6; };
 template <> struct Tile<4, 1> { static constexpr int TX = 16, TY = 4; };
 template <> struct Tile<5, 1> { static constexpr int TX = 20, TY = 5; };
-template <> struct Tile<6, 1> { static constexpr int TX = 18, TY = 6; };
+// N = 6 has one shape: the 18 x 6 tile (648 threads) returned wrong values
+// in its stage-2 kernel, in the precision form with this ring layout and in
+// the FP64 step with a per-node interleaved one, while 12 x 6 and every
+// other order's shapes agree; the cause was not found
+template <> struct Tile<6, 1> { static constexpr int TX = 12, TY = 6; };
 template <> struct Tile<7, 1> { static constexpr int TX = 7, TY = 14; };
 template <> struct Tile<8, 1> { static constexpr int TX = 8, TY = 8; };  // no other shape fits: same as 0
 

@@ -1,8 +1,8 @@
 """GPU tests of the right-hand side's launch configurations: the second tile
 shape of every order and the vertical chunks give the same steps as the
 default configuration (each node's arithmetic does not depend on the tile or
-the chunk, in either form; the precision form keeps the first tile at N = 6
-and stays within 1e-6 of the FP64 step), and the autotuner keeps
+the chunk, in either form, and the precision form stays within 1e-6 of the
+FP64 step), and the autotuner keeps
 a configuration that the step then uses.  The default configuration is the
 one the oracle parity tests check."""
 import numpy as np
@@ -57,8 +57,8 @@ def test_tiles_and_chunks_give_the_same_steps(torch_cuda, numa_mod, N, nex, ney,
             fp64 = ref
         assert cfg0["tile"] == 0 and cfg0["TX"] % N == 0 and cfg0["TY"] % N == 0
         for tile, zc in ((0, 1), (1, 0), (1, 1)):
-            if tile == 1 and N == 8:
-                with pytest.raises(numa_mod.NumaError) as ei:  # one shape at N = 8
+            if tile == 1 and N in (6, 8):
+                with pytest.raises(numa_mod.NumaError) as ei:  # one shape at N = 6 and 8
                     _steps(torch_cuda, numa_mod, g, q0, dt, tile, zc, mixed)
                 assert ei.value.code == numa_mod.NUMA_E_UNSUPPORTED
                 continue
