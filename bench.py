@@ -561,6 +561,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="3D-IMEX without the learned-correction run")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the headline FP64 measurement (the other legs and the CPU baseline skipped)")
+    ap.add_argument("--precision-only", action="store_true",
+                    help="only the headline workload's FP64 and precision-form steps (printed alone)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -580,6 +582,20 @@ def main():
         return
     wl = W.box_large("R1")
     g = wl.grid
+    if args.precision_only:
+        ctx = numa.Context(g, wl.background)
+        ctx.factor(wl.dt)
+        q = torch.from_numpy(W.make_initial_state(wl)).to("cuda")
+        cfg = numa.autotune(ctx.ctx, q.data_ptr(), reps=5)
+        ctx.step(q, args.warmup)
+        t, ms = wall_and_kernels(numa, torch, ctx, q, wl.dt, args.steps)
+        ctx.check()
+        out = {"workload": "box 64x64x10 elements, N=4, 256x256x41 unique nodes", "rhs_config": cfg,
+               "fp64": {"ms_per_step": 1e3 * t, "kernels_ms": ms},
+               "precision_form": precision_form(numa, torch, ctx, wl, args, t * args.steps)}
+        ctx.close()
+        print(json.dumps(out), flush=True)
+        return
     ctx = numa.Context(g, wl.background)
     t0 = time.perf_counter()
     ctx.factor(wl.dt)
