@@ -101,3 +101,40 @@ def test_mixed_error_codes(torch_cuda, numa_mod):
     ms = (C.c_double * 5)()
     assert lib.numa_profile_steps_mixed(ctx.ctx, C.c_void_p(q.data_ptr()), 1.0, 0, ms) == numa_mod.NUMA_E_ARG
     ctx.close()
+
+
+# (N, nex, ney, nez, Nb): the blocked solve with four and eight wavefronts,
+# the one-lane solve of a 161-level column, and a stratified background
+# (whose solves also read R1's theta' as FP32)
+SOLVE_GRIDS = [(3, 3, 2, 5, 0.0), (5, 2, 2, 13, 0.0), (4, 2, 2, 40, 0.0), (4, 3, 2, 6, 0.012)]
+
+
+@pytest.mark.parametrize("N,nex,ney,nez,nbv", SOLVE_GRIDS)
+def test_mixed_with_every_column_solver(torch_cuda, numa_mod, N, nex, ney, nez, nbv):
+    """The precision form's solve shapes (R1 read as FP32) in every column
+    solver: two steps within the 1e-6 bar of the FP64 step with the same
+    solver, and the solvers' precision-form results equal to rounding."""
+    lz = 6000.0 if nez <= 8 else 20000.0
+    g = W.Grid(9000.0 * nex, 7000.0 * ney, lz, nex, ney, nez, N)
+    bg = W.Background(nbv=nbv) if nbv else None
+    dt = min(W.dt_for_courant(g, 15.0, "z"), W.dt_for_courant(g, 0.4, "x"), W.dt_for_courant(g, 0.4, "y"))
+    q0 = W.make_random_state(g, 70 + N, wind=3.0)
+    outs = {}
+    for kind in (numa_mod.SOLVER_BAND, numa_mod.SOLVER_BLOCKED, numa_mod.SOLVER_PER_COLUMN):
+        ctx = numa_mod.Context(g, bg)
+        ctx.set_column_solver(kind)
+        ctx.factor(dt)
+        a = torch_cuda.from_numpy(q0.copy()).cuda()
+        b = a.clone()
+        ctx.step(a, 2)
+        ctx.step(b, 2, mixed=True)
+        ctx.check()
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        e = _rel(b, a)
+        print(f"N={N} nz={g.nz} Nb={nbv} solver {ctx.info()['column_solver']}: mixed vs FP64 {e}")
+        assert np.all(e < BAR), (kind, e)
+        outs[kind] = b
+        ctx.close()
+    for kind in (numa_mod.SOLVER_BLOCKED, numa_mod.SOLVER_PER_COLUMN):
+        e = _rel(outs[kind], outs[numa_mod.SOLVER_BAND])
+        assert np.all(e < 1e-12), (kind, e)
