@@ -224,7 +224,7 @@ def hevi_step(ctx, state_ptr, dt, nsteps):
 
 
 def hevi_step_mixed(ctx, state_ptr, dt, nsteps):
-    """The precision form of hevi_step (FP32 right-hand sides, FP32 u, v stage values)."""
+    """The precision form of hevi_step (the first-stage tendency R1 stored in FP32)."""
     return _check(load().numa_hevi_step_mixed(ctx, C.c_void_p(state_ptr), float(dt), int(nsteps)), ctx)
 
 
