@@ -138,3 +138,28 @@ def test_mixed_with_every_column_solver(torch_cuda, numa_mod, N, nex, ney, nez, 
     for kind in (numa_mod.SOLVER_BLOCKED, numa_mod.SOLVER_PER_COLUMN):
         e = _rel(outs[kind], outs[numa_mod.SOLVER_BAND])
         assert np.all(e < 1e-12), (kind, e)
+
+
+@pytest.mark.timeout(600)
+def test_mixed_full_size_against_oracle(torch_cuda, numa_mod, oracle_mod):
+    """The benchmarked grid (64x64x10 elements, N = 4, 2.7M unique nodes):
+    the precision form against the oracle after each of 10 steps, every
+    variable within the 1e-6 bar."""
+    wl = W.box_large("R1")
+    g = wl.grid
+    q0 = W.make_initial_state(wl)
+    o = _oracle(oracle_mod, g, wl.background)
+    o.factor_dt(wl.dt)
+    ctx = numa_mod.Context(g, wl.background)
+    ctx.factor(wl.dt)
+    q = torch_cuda.from_numpy(q0.copy()).cuda()
+    qo = q0.copy()
+    worst = np.zeros(5)
+    for n in range(10):
+        qo = o.step(qo, wl.dt, 1)
+        ctx.step(q, 1, mixed=True)
+        worst = np.maximum(worst, _rel(q.cpu().numpy(), qo))
+    ctx.check()
+    print(f"box_large mixed vs oracle, worst over 10 steps: {worst}")
+    assert np.all(worst < BAR), worst
+    ctx.close()
