@@ -1,8 +1,9 @@
 """GPU test of numa_hevi_step_mixed_noalloc: the precision-form step with the
-library's fixed stage buffers instead of allocated ones.  Two calls in a row
-on two contexts, the second grid smaller than the first, each compared with
-numa_hevi_step_mixed on the same input (same kernels and arithmetic, so the
-results agree bit for bit); a grid above the fixed size is refused."""
+library's fixed stage buffers instead of allocated ones.  Three calls in a
+row on three contexts, the second grid smaller than the first, the third
+over a stratified background, each compared with numa_hevi_step_mixed on the
+same input (same kernels and arithmetic, so the results agree bit for bit);
+a grid above the fixed size is refused."""
 import ctypes as C
 
 import numpy as np
@@ -22,8 +23,8 @@ def env():
     return torch, numa
 
 
-def _grid_state(torch, numa, g, seed):
-    ctx = numa.Context(g)
+def _grid_state(torch, numa, g, seed, bg=None):
+    ctx = numa.Context(g, bg)
     dt = W.dt_for_courant(g, 15.0, "z")
     ctx.factor(dt)
     q0 = torch.from_numpy(W.make_random_state(g, seed)).cuda()
@@ -34,11 +35,15 @@ def test_noalloc_matches_allocating_entry_point(env):
     torch, numa = env
     lib = numa.load()
     # first a grid of 96x96x33 = 304,128 nodes (29 MB of the 64 MiB array),
-    # then 16x16x17 = 4,352 nodes; 100 km elements keep the horizontal
-    # Courant number small at vertical Courant number 15
-    grids = [W.Grid(2.4e6, 2.4e6, 8000.0, 24, 24, 8, 4), W.Grid(4.0e5, 4.0e5, 4000.0, 4, 4, 4, 4)]
-    for n, g in enumerate(grids):
-        ctx, dt, q0 = _grid_state(torch, numa, g, seed=30 + n)
+    # then 16x16x17 = 4,352 nodes, then 12x12x25 over a stratified
+    # background (whose stage buffers also hold theta' of Q2 and Q3); 100 km
+    # elements keep the horizontal Courant number small at vertical Courant
+    # number 15
+    grids = [(W.Grid(2.4e6, 2.4e6, 8000.0, 24, 24, 8, 4), None),
+             (W.Grid(4.0e5, 4.0e5, 4000.0, 4, 4, 4, 4), None),
+             (W.Grid(3.0e5, 3.0e5, 8000.0, 3, 3, 6, 4), W.Background(nbv=0.01))]
+    for n, (g, bg) in enumerate(grids):
+        ctx, dt, q0 = _grid_state(torch, numa, g, seed=30 + n, bg=bg)
         print(f"noalloc case {n}: grid {g.nx}x{g.ny}x{g.nz}, N={g.N}, dt={dt}", flush=True)
         a, b = q0.clone(), q0.clone()
         rc = lib.numa_hevi_step_mixed_noalloc(ctx.ctx, C.c_void_p(b.data_ptr()), dt, 3)
