@@ -114,7 +114,7 @@ int numa_set_stream(numa_ctx *c, void *hip_stream);
  * Launch configuration of the right-hand sides (Sec. 5.1: the volume kernel
  * over element tiles), a project autotuner on top of the paper's method.
  * The right-hand-side kernel is compiled for two tile shapes per order (TX x
- * TY columns per workgroup, element aligned; one shape at N = 8) and runs
+ * TY columns per workgroup, element aligned; one shape at N = 6 and 8) and runs
  * over a vertical chunk of zchunk elements per workgroup.
  * numa_autotune: times the three right-hand sides of a step on state
  * (device, state contract; read only, outputs into the context's stage
@@ -122,7 +122,7 @@ int numa_set_stream(numa_ctx *c, void *hip_stream);
  * nez/2, nez/3, ..., 1, `reps` launches each, and keeps the fastest pair for
  * the context; config_out (host, nullable, 4 ints) as numa_get_rhs_config.
  * Synchronous.  The step's results do not depend on the configuration.  The
- * precision form uses the chosen chunk with the first tile.
+ * precision form uses the same configuration.
  * numa_set_rhs_config: tile 0 (the default shape) or 1, zchunk 0 (automatic:
  * the largest chunk that still gives two workgroups per CU) or 1..nez.
  * numa_get_rhs_config: out[4] (host) = {tile, TX, TY, zchunk in use}.
