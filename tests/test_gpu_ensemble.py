@@ -147,3 +147,29 @@ def test_ensemble_matches_oracle(torch_cuda, numa_mod, oracle_mod, mixed):
     for c in ctxs:
         c.close()
     assert np.all(worst < bar), worst
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_ensemble_with_second_tiles_replays_match_eager_steps(torch_cuda, numa_mod, mixed):
+    """Every domain on its second tile shape (set by hand, no autotuner):
+    the captured graph's replays equal eager steps of the same contexts."""
+    doms = [_domain(torch_cuda, numa_mod, *d) for d in DOMAINS]
+    ctxs = [c for c, _ in doms]
+    for c in ctxs:
+        numa_mod.set_rhs_config(c.ctx, 1, 0)
+        assert numa_mod.get_rhs_config(c.ctx)["tile"] == 1
+    states = [q for _, q in doms]
+    refs = [q.clone() for q in states]
+    ens = numa_mod.Ensemble(ctxs, states, mixed=mixed, tune=False)
+    for replay in range(2):
+        ens.step(1)
+        ens.sync()
+        for c, r in zip(ctxs, refs):
+            c.step(r, 1, mixed=mixed)
+            c.check()
+        for i, (q, r) in enumerate(zip(states, refs)):
+            assert torch_cuda.equal(q, r), f"domain {i}, replay {replay}"
+    assert [numa_mod.get_rhs_config(c.ctx)["tile"] for c in ctxs] == [1] * len(ctxs)
+    ens.close()
+    for c in ctxs:
+        c.close()
