@@ -563,6 +563,8 @@ def main():
                     help="only the headline FP64 measurement (the other legs and the CPU baseline skipped)")
     ap.add_argument("--precision-only", action="store_true",
                     help="only the headline workload's FP64 and precision-form steps (printed alone)")
+    ap.add_argument("--ensemble-only", action="store_true",
+                    help="only the batched-ensemble measurement (printed alone)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -579,6 +581,9 @@ def main():
     torch.cuda.set_device(0)
     if args.imex3d_only:
         print(json.dumps(imex3d(numa, torch, learned=not args.no_learned)), flush=True)
+        return
+    if args.ensemble_only:
+        print(json.dumps(batched_ensemble(numa, torch, steps=args.steps)), flush=True)
         return
     wl = W.box_large("R1")
     g = wl.grid
